@@ -1,0 +1,468 @@
+"""Pins for the CPU oracle: each test checks the oracle against something other
+than itself -- a published test vector, a brute-force definition at tiny N, an
+exact big-integer identity, a library routine, or a value the paper prints.
+
+Paper passages pinned here: the Newton step for 1/sqrt (§2.2), the Chebyshev
+initial value (§2.3) and the statement in §5.3 that a degree-14 initial value
+needs at least 12 Newton iterations to converge in plaintext.
+"""
+import hashlib
+import math
+
+import mpmath
+import numpy as np
+import pytest
+import sympy
+
+from paper_2606_10477_amd import inputs
+
+
+# --------------------------------------------------------------------------
+# helpers written from the definitions (Python big integers, tiny N)
+# --------------------------------------------------------------------------
+def bitrev(x, bits):
+    r = 0
+    for _ in range(bits):
+        r = (r << 1) | (x & 1)
+        x >>= 1
+    return r
+
+
+def ntt_def(a, q, psi, logN):
+    """NTT(a)[j] = sum_i a_i psi^((2 br(j) + 1) i) mod q."""
+    N = 1 << logN
+    return [sum(int(a[i]) * pow(psi, (2 * bitrev(j, logN) + 1) * i, q) for i in range(N)) % q
+            for j in range(N)]
+
+
+def intt_def(A, q, psi, logN):
+    N = 1 << logN
+    ninv = pow(N, -1, q)
+    ipsi = pow(psi, -1, q)
+    return [ninv * sum(int(A[j]) * pow(ipsi, (2 * bitrev(j, logN) + 1) * i, q) for j in range(N)) % q
+            for i in range(N)]
+
+
+def negacyclic_mul(a, b, q):
+    N = len(a)
+    out = [0] * N
+    for i in range(N):
+        for j in range(N):
+            k = i + j
+            if k < N:
+                out[k] += int(a[i]) * int(b[j])
+            else:
+                out[k - N] -= int(a[i]) * int(b[j])
+    return [v % q for v in out]
+
+
+def centred(v, q):
+    v %= q
+    return v - q if v > q // 2 else v
+
+
+def crt(residues, primes):
+    Q = 1
+    for p in primes:
+        Q *= int(p)
+    x = 0
+    for r, p in zip(residues, primes):
+        p = int(p)
+        Qi = Q // p
+        x += int(r) * Qi * pow(Qi, -1, p)
+    return x % Q, Q
+
+
+@pytest.fixture(scope="module")
+def tiny(oracle_mod):
+    """N = 16, three 40-bit-ish scaling primes, one special prime."""
+    ctx = oracle_mod.Context(4, 3, 1, 1, h=0)
+    ctx.keygen(7, [ctx.galois_rot(1), ctx.galois_rot(3), 2 * ctx.N - 1])
+    return ctx
+
+
+@pytest.fixture(scope="module")
+def p12(oracle_mod):
+    """The N = 2^12 parameter set: q0 60-bit + 13 scaling primes, one 60-bit special prime."""
+    ctx = oracle_mod.Context(12, 13, 1, 1, h=0)
+    ctx.keygen(2, [ctx.galois_rot(1), ctx.galois_rot(-3), 2 * ctx.N - 1])
+    return ctx
+
+
+# --------------------------------------------------------------------------
+# SHAKE-256: byte equality with hashlib (FIPS 202 reference available here)
+# --------------------------------------------------------------------------
+@pytest.mark.parametrize("n", [0, 1, 16, 135, 136, 137, 271, 272, 500])
+def test_shake256_matches_hashlib(oracle_mod, n):
+    data = bytes((i * 37 + 11) & 0xFF for i in range(n))
+    assert oracle_mod.shake256(data, 700) == hashlib.shake_256(data).digest(700)
+
+
+# --------------------------------------------------------------------------
+# primes, psi, the scale ladder
+# --------------------------------------------------------------------------
+def test_is_prime_against_sympy(oracle_mod):
+    rng = np.random.default_rng(5)
+    for n in list(range(0, 2000)) + [int(v) for v in rng.integers(2 ** 40, 2 ** 61, 300, dtype=np.int64)]:
+        assert oracle_mod.is_prime(n) == sympy.isprime(n), n
+    # strong pseudoprimes to several small bases
+    for n in [3215031751, 2152302898747, 3474749660383, 341550071728321, 3825123056546413051]:
+        assert not oracle_mod.is_prime(n)
+
+
+@pytest.mark.parametrize("logN,L,K", [(12, 13, 1), (16, 27, 7)])
+def test_prime_chain(oracle_mod, logN, L, K):
+    ctx = oracle_mod.Context(logN, L, K, 1 if logN == 12 else 10, h=0 if logN == 12 else 192)
+    N = 1 << logN
+    P = [int(p) for p in ctx.primes]
+    assert len(set(P)) == len(P)
+    for p in P:
+        assert p % (2 * N) == 1 and sympy.isprime(p)
+    assert P[0].bit_length() == 60 and P[0] < 2 ** 60
+    # q0 is the largest such prime below 2^60
+    for c in range(P[0] + 2 * N, 2 ** 60, 2 * N):
+        assert not sympy.isprime(c)
+    for p in P[L + 1:]:
+        assert p.bit_length() == 60
+    # canonical scale ladder: S_L = 2^40, S_{l-1} = S_l^2 / q_l, all close to 2^40
+    S = ctx.ladder
+    assert S[L] == 2.0 ** 40
+    for l in range(L, 0, -1):
+        assert S[l - 1] == (S[l] * S[l]) / float(P[l])
+        assert abs(S[l - 1] / 2 ** 40 - 1) < 6e-5
+    for l in range(1, L + 1):
+        assert abs(P[l] / 2 ** 40 - 1) < 1e-4
+    if logN == 16:
+        logQP = sum(math.log2(p) for p in P)
+        assert 1550 < logQP < 1565
+
+
+def test_psi_order(oracle_mod, tiny):
+    N = tiny.N
+    for q in tiny.primes:
+        q = int(q)
+        psi = oracle_mod.psi(q, N)
+        assert pow(psi, N, q) == q - 1 and pow(psi, 2 * N, q) == 1
+        # the rule: smallest g >= 2 whose (q-1)/2N power has order 2N
+        g = 2
+        while pow(pow(g, (q - 1) // (2 * N), q), N, q) != q - 1:
+            g += 1
+        assert psi == pow(g, (q - 1) // (2 * N), q)
+
+
+# --------------------------------------------------------------------------
+# NTT: definition, negacyclic convolution, round trip
+# --------------------------------------------------------------------------
+def test_ntt_matches_definition(oracle_mod, tiny):
+    rng = np.random.default_rng(11)
+    for pi, q in enumerate(tiny.primes):
+        q = int(q)
+        a = rng.integers(0, q, tiny.N, dtype=np.uint64)
+        psi = oracle_mod.psi(q, tiny.N)
+        assert [int(v) for v in tiny.ntt(pi, a)] == ntt_def(a, q, psi, tiny.logN)
+        A = rng.integers(0, q, tiny.N, dtype=np.uint64)
+        assert [int(v) for v in tiny.intt(pi, A)] == intt_def(A, q, psi, tiny.logN)
+
+
+def test_ntt_negacyclic_convolution(oracle_mod, p12):
+    rng = np.random.default_rng(12)
+    q = int(p12.primes[3])
+    N = 64
+    ctx = oracle_mod.Context(6, 2, 1, 1)
+    for pi in range(ctx.np_):
+        q = int(ctx.primes[pi])
+        a = rng.integers(0, q, N, dtype=np.uint64)
+        b = rng.integers(0, q, N, dtype=np.uint64)
+        A, B = ctx.ntt(pi, a), ctx.ntt(pi, b)
+        prod = np.array([(int(x) * int(y)) % q for x, y in zip(A, B)], dtype=np.uint64)
+        assert [int(v) for v in ctx.intt(pi, prod)] == negacyclic_mul(a, b, q)
+
+
+def test_ntt_roundtrip_full_size(oracle_mod, p12):
+    rng = np.random.default_rng(13)
+    for pi in [0, 5, p12.np_ - 1]:
+        q = int(p12.primes[pi])
+        a = rng.integers(0, q, p12.N, dtype=np.uint64)
+        assert np.array_equal(p12.intt(pi, p12.ntt(pi, a)), a)
+
+
+# --------------------------------------------------------------------------
+# canonical embedding (encode / decode)
+# --------------------------------------------------------------------------
+def test_dft_fast_matches_direct(oracle_mod):
+    rng = np.random.default_rng(14)
+    x = rng.normal(size=64) + 1j * rng.normal(size=64)
+    for s in (1, -1):
+        ref = np.fft.ifft(x) * 64 if s == 1 else np.fft.fft(x)
+        assert np.allclose(oracle_mod.dft_direct(x, s), ref, atol=1e-11)
+        assert np.allclose(oracle_mod.dft_fast(x, s), ref, atol=1e-11)
+
+
+def test_decode_matches_brute_force_embedding(oracle_mod, tiny):
+    m = inputs.small_ints(tiny.N, 1000, 15)
+    z_fast = tiny.decode_coeffs(m, 1.0)
+    N = tiny.N
+    z_ref = []
+    for j in range(tiny.n):
+        e = pow(5, j, 2 * N)
+        z_ref.append(sum(int(m[k]) * np.exp(1j * np.pi * e * k / N) for k in range(N)))
+    assert np.allclose(z_fast, np.array(z_ref), atol=1e-9)
+    assert np.allclose(tiny.embed_direct(m), np.array(z_ref), atol=1e-9)
+
+
+def test_encode_is_rounded_exact_inverse(oracle_mod, tiny):
+    """encode(z) = rint(scale * tau^-1(z)) with tau^-1 evaluated exactly (mpmath, 60 digits)."""
+    mpmath.mp.dps = 60
+    rng = np.random.default_rng(16)
+    N, n = tiny.N, tiny.n
+    re = rng.uniform(-1, 1, n)
+    im = rng.uniform(-1, 1, n)
+    scale = 2.0 ** 45
+    got = tiny.encode(re, im, scale)
+    for k in range(N):
+        s = mpmath.mpf(0)
+        for j in range(n):
+            e = pow(5, j, 2 * N)
+            zj = mpmath.mpc(re[j], im[j])
+            s += (zj * mpmath.expj(-mpmath.pi * e * k / N)).real
+        exact = 2 * s / N * scale
+        assert int(got[k]) == int(mpmath.nint(exact)), k
+
+
+def test_encode_decode_roundtrip(oracle_mod, p12):
+    x = inputs.log_uniform(p12.n, 2 ** -8, 1.0, 1)
+    m = p12.encode(x, None, 2.0 ** 50)
+    z = p12.decode_coeffs(m, 2.0 ** 50)
+    # rounding error bound: |z - x| <= (N/2) * 0.5 / scale per slot (triangle inequality)
+    assert np.max(np.abs(z - x)) < p12.N / 2 ** 51
+    assert np.max(np.abs(z - x)) < 1e-12
+
+
+# --------------------------------------------------------------------------
+# sampler
+# --------------------------------------------------------------------------
+def test_gaussian_cdt_against_exact(oracle_mod, p12):
+    mpmath.mp.dps = 40
+    T = p12.cdt()
+    sigma = mpmath.mpf("3.2")
+    J = len(T) - 1
+    assert J == math.ceil(6.25 * 3.2)
+    rho = [mpmath.e ** (-(mpmath.mpf(j) ** 2) / (2 * sigma ** 2)) for j in range(J + 1)]
+    Z = rho[0] + 2 * sum(rho[1:])
+    for k in range(J):
+        F = (rho[0] + 2 * sum(rho[1:k + 1])) / Z
+        assert abs(int(T[k]) - int(mpmath.floor(F * 2 ** 53))) <= 2
+    assert int(T[J]) == 2 ** 53
+
+
+def test_secret_distributions(oracle_mod):
+    ctx = oracle_mod.Context(12, 3, 1, 1, h=64)
+    ctx.keygen(3)
+    s = ctx.secret()
+    assert np.count_nonzero(s) == 64 and set(np.unique(s[s != 0])) <= {-1, 1}
+    ctx2 = oracle_mod.Context(12, 3, 1, 1, h=0)
+    ctx2.keygen(3)
+    s2 = ctx2.secret()
+    counts = [np.sum(s2 == v) for v in (-1, 0, 1)]
+    assert all(abs(c - ctx2.N / 3) < 5 * math.sqrt(ctx2.N) for c in counts)
+
+
+def test_public_key_error_is_gaussian(oracle_mod, p12):
+    """pk0 + pk1*s = e with e ~ D(3.2): recover e at prime q_0 and check its moments."""
+    pk = p12.pk()
+    s = p12.secret()
+    q = int(p12.primes[0])
+    e_ntt = (pk[0, 0].astype(object) + pk[1, 0].astype(object) * np.array(
+        [int(v) for v in p12.ntt(0, np.array([v % q for v in s.astype(np.int64)], dtype=np.uint64))],
+        dtype=object)) % q
+    e = np.array([centred(int(v), q) for v in p12.intt(0, np.array(e_ntt, dtype=np.uint64))])
+    assert np.max(np.abs(e)) <= 20
+    assert abs(np.mean(e)) < 0.3
+    assert abs(np.std(e) - 3.2) < 0.15
+
+
+# --------------------------------------------------------------------------
+# encryption / operations within noise; exact identities
+# --------------------------------------------------------------------------
+def test_encrypt_decrypt(oracle_mod, p12):
+    x = inputs.log_uniform(p12.n, 2 ** -8, 1.0, 1)
+    for lvl, sc in [(13, 2.0 ** 40), (5, 2.0 ** 50), (0, 2.0 ** 40)]:
+        ct = p12.encrypt(x, lvl, sc, 3)
+        assert ct.level == lvl and ct.scale == sc
+        z = p12.decrypt(ct)
+        assert np.max(np.abs(z - x)) < 2e4 / sc * 64
+
+
+def test_rescale_is_exact_rounding(oracle_mod, tiny):
+    """rescale = round(c / q_l) coefficient-wise, checked with exact CRT."""
+    rng = np.random.default_rng(21)
+    lvl = 3
+    primes = [int(p) for p in tiny.primes[:lvl + 1]]
+    words = inputs.uniform_words((2, lvl + 1, tiny.N), primes, 22)
+    ct = tiny.ct_import(words, lvl, 2.0 ** 40)
+    out = tiny.rescale(ct).words()
+    psis = [oracle_mod.psi(q, tiny.N) for q in primes]
+    for p in range(2):
+        coef = [intt_def(words[p, i], primes[i], psis[i], tiny.logN) for i in range(lvl + 1)]
+        got = [intt_def(out[p, i], primes[i], psis[i], tiny.logN) for i in range(lvl)]
+        for k in range(tiny.N):
+            C, Q = crt([coef[i][k] for i in range(lvl + 1)], primes)
+            r = C % primes[lvl]
+            if r > primes[lvl] // 2:
+                r -= primes[lvl]
+            rounded = (C - r) // primes[lvl]
+            assert abs(C / primes[lvl] - rounded) <= 0.5
+            for i in range(lvl):
+                assert got[i][k] == rounded % primes[i]
+    del rng
+
+
+def test_keyswitch_identity(oracle_mod, tiny):
+    """o0 + o1*s = d*s^2 + small, at every level (relinearisation key)."""
+    s = tiny.secret()
+    for lvl in (3, 1):
+        primes = [int(p) for p in tiny.primes[:lvl + 1]]
+        d = inputs.uniform_words((lvl + 1, tiny.N), primes, 30 + lvl)
+        o0, o1 = tiny.keyswitch(-1, lvl, d)
+        for i, q in enumerate(primes):
+            psi = oracle_mod.psi(q, tiny.N)
+            s_i = [v % q for v in s.astype(np.int64)]
+            dc = intt_def(d[i], q, psi, tiny.logN)
+            want = negacyclic_mul(negacyclic_mul(dc, s_i, q), s_i, q)
+            o0c = intt_def(o0[i], q, psi, tiny.logN)
+            o1c = intt_def(o1[i], q, psi, tiny.logN)
+            got = [(a + b) % q for a, b in zip(o0c, negacyclic_mul(o1c, s_i, q))]
+            err = [centred(g - w, q) for g, w in zip(got, want)]
+            assert max(abs(e) for e in err) < 2 ** 12
+
+
+def test_automorphism_permutation(oracle_mod, tiny):
+    """NTT(a(X^g)) = NTT(a)[perm_g]: brute-force substitution in the coefficient domain."""
+    rng = np.random.default_rng(23)
+    N = tiny.N
+    q = int(tiny.primes[1])
+    a = rng.integers(0, q, N, dtype=np.uint64)
+    for g in [tiny.galois_rot(1), tiny.galois_rot(3), 2 * N - 1, 3]:
+        b = [0] * N
+        for i in range(N):
+            e = (i * g) % (2 * N)
+            if e < N:
+                b[e] = (b[e] + int(a[i])) % q
+            else:
+                b[e - N] = (b[e - N] - int(a[i])) % q
+        perm = tiny.automorph_perm(g)
+        A = tiny.ntt(1, a)
+        assert [int(v) for v in tiny.ntt(1, np.array(b, dtype=np.uint64))] == [int(A[p]) for p in perm]
+
+
+def test_hmult_rotate_conjugate_decrypt(oracle_mod, p12):
+    x = inputs.log_uniform(p12.n, 2 ** -8, 1.0, 1)
+    x2 = inputs.log_uniform(p12.n, 2 ** -8, 1.0, 2)
+    a = p12.encrypt(x, 13, 2.0 ** 40, 3)
+    b = p12.encrypt(x2, 13, 2.0 ** 40, 4)
+    m = p12.rescale(p12.hmult(a, b))
+    assert m.level == 12 and abs(m.scale / p12.ladder[12] - 1) < 1e-15
+    assert np.max(np.abs(p12.decrypt(m) - x * x2)) < 1e-6
+    r = p12.rotate(a, 1)
+    assert np.max(np.abs(p12.decrypt(r) - np.roll(x, -1))) < 1e-6
+    r = p12.rotate(a, -3)
+    assert np.max(np.abs(p12.decrypt(r) - np.roll(x, 3))) < 1e-6
+    cj = p12.conjugate(p12.mul_int(a, 1))
+    assert np.max(np.abs(p12.decrypt(cj) - x)) < 1e-6
+    with pytest.raises(oracle_mod.OracleError):
+        p12.rotate(a, 2)            # no key for 2
+    with pytest.raises(oracle_mod.OracleError):
+        p12.add(a, m)               # level mismatch
+
+
+def test_constants_and_level_to(oracle_mod, p12):
+    x = inputs.log_uniform(p12.n, 2 ** -8, 1.0, 1)
+    a = p12.encrypt(x, 13, 2.0 ** 50, 3)
+    h = p12.mul_const_down(a, 0.5)
+    assert h.level == 12 and h.scale == (p12.ladder[12] * float(p12.primes[13])) / 2.0 ** 50 * 2.0 ** 50 / float(p12.primes[13])
+    assert np.max(np.abs(p12.decrypt(h) - 0.5 * x)) < 1e-8
+    t = p12.add_const(h, -0.25)
+    assert np.max(np.abs(p12.decrypt(t) - (0.5 * x - 0.25))) < 1e-8
+    d = p12.level_to(h, 7)
+    assert d.level == 7 and abs(d.scale / p12.ladder[7] - 1) < 1e-14
+    assert np.max(np.abs(p12.decrypt(d) - 0.5 * x)) < 1e-8
+    k = p12.mul_int(d, -3)
+    assert np.max(np.abs(p12.decrypt(k) + 1.5 * x)) < 1e-7
+
+
+# --------------------------------------------------------------------------
+# Chebyshev initial value and Newton (paper §2.2, §2.3, §5.3)
+# --------------------------------------------------------------------------
+@pytest.mark.parametrize("d,a,b", [(15, 2 ** -8, 1.0), (31, 2 ** -10, 1.0), (14, 1e-5, 1.0), (127, 2 ** -10, 1.0)])
+def test_cheb_coeffs_match_numpy_interpolation(oracle_mod, d, a, b):
+    ours = oracle_mod.cheb_coeffs_invsqrt(d, a, b)
+    ref = np.polynomial.chebyshev.chebinterpolate(lambda t: 1 / np.sqrt((a + b) / 2 + (b - a) / 2 * t), d)
+    assert np.max(np.abs(ours - ref)) < 1e-12 * np.max(np.abs(ref))
+    # interpolation property at the first-kind nodes
+    nodes = np.cos(np.pi * (np.arange(d + 1) + 0.5) / (d + 1))
+    vals = np.polynomial.chebyshev.chebval(nodes, ours)
+    assert np.max(np.abs(vals - 1 / np.sqrt((a + b) / 2 + (b - a) / 2 * nodes)) / vals) < 1e-10
+
+
+def test_newton_error_recurrence():
+    """y = (1 + e)/sqrt(x) -> y' = y (3 - x y^2) / 2 = (1 + e')/sqrt(x), e' = -1.5 e^2 - 0.5 e^3."""
+    e, x = sympy.symbols("e x", positive=True)
+    y = (1 + e) / sympy.sqrt(x)
+    yn = y * (3 - x * y ** 2) / 2
+    assert sympy.simplify(yn * sympy.sqrt(x) - 1 - (-sympy.Rational(3, 2) * e ** 2 - e ** 3 / 2)) == 0
+
+
+def _plain_chain(x, coeffs, a, b, iters):
+    t = (2 * x - a - b) / (b - a)
+    y = np.polynomial.chebyshev.chebval(t, coeffs)
+    out = [y]
+    for _ in range(iters):
+        y = 0.5 * y * (3 - x * y * y)
+        out.append(y)
+    return out
+
+
+def test_paper_degree14_needs_12_iterations(oracle_mod):
+    """§5.3: with the degree 2^4-2 initial value, at least 12 Newton iterations
+    are needed to converge in plaintext (input range [0.001, 100], B = 100)."""
+    A, B, Bn = 0.001, 100.0, 100.0
+    x = inputs.linspace_input(2 ** 15, A, B) / Bn
+    cf = oracle_mod.cheb_coeffs_invsqrt(14, A / Bn, B / Bn)
+    ys = _plain_chain(x, cf, A / Bn, B / Bn, 15)
+    ref = 1 / np.sqrt(x)
+    first = next(i for i, y in enumerate(ys) if np.max(np.abs(y - ref) / ref) < 1e-14)
+    assert first == 12
+
+
+def test_cheb_eval_encrypted(oracle_mod, p12):
+    x = inputs.log_uniform(p12.n, 2 ** -8, 1.0, 1)
+    ct = p12.encrypt(x, 13, 2.0 ** 50, 3)
+    for d in (7, 15):
+        cf = oracle_mod.cheb_coeffs_invsqrt(d, 2 ** -8, 1.0)
+        y = p12.cheb_eval(ct, cf, 2 ** -8, 1.0)
+        m = d.bit_length()
+        assert y.level == 13 - 1 - (m + 1)
+        ref = _plain_chain(x, cf, 2 ** -8, 1.0, 0)[0]
+        assert np.max(np.abs(p12.decrypt(y).real - ref)) < 1e-5
+    # a [-1, 1] polynomial with a zero coefficient block skips the affine step
+    cf = np.array([0.25, 0.0, -0.5, 0.0, 0.125])
+    t = p12.encrypt(np.linspace(-1, 1, p12.n), 13, 2.0 ** 40, 5)
+    y = p12.cheb_eval(t, cf, -1.0, 1.0)
+    assert np.max(np.abs(p12.decrypt(y).real - np.polynomial.chebyshev.chebval(np.linspace(-1, 1, p12.n), cf))) < 1e-6
+
+
+def test_invsqrt_small_ring_matches_plain_chain(oracle_mod, p12):
+    """Alg. 1 on the N = 2^12 parameter set: degree 15, 2 Newton steps on [2^-8, 1]."""
+    x = inputs.log_uniform(p12.n, 2 ** -8, 1.0, 1)
+    ct = p12.encrypt(x, 13, 2.0 ** 50, 3)
+    y = p12.invsqrt(ct, 15, 2, 2 ** -8, 1.0)
+    assert y.level == 13 - 1 - 5 - 2 - 2
+    z = p12.decrypt(y).real
+    cf = oracle_mod.cheb_coeffs_invsqrt(15, 2 ** -8, 1.0)
+    plain = _plain_chain(x, cf, 2 ** -8, 1.0, 2)[-1]
+    ref = 1 / np.sqrt(x)
+    mre_plain = np.mean(np.abs(plain - ref) / ref)
+    mre = np.mean(np.abs(z - ref) / ref)
+    assert abs(mre_plain - 2.7e-5) < 0.1e-5
+    assert abs(mre - mre_plain) < 0.02 * mre_plain
+    assert np.max(np.abs(z - plain) / ref) < 1e-6
