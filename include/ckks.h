@@ -1,0 +1,237 @@
+/*
+ * ckks.h -- C-ABI of the MI355X (gfx950) RNS-CKKS inverse-square-root library
+ * (libckks_hip.so).
+ *
+ * What it computes.  The encrypted inverse square root of the paper
+ * (Alg. 1 "CryptoInvSqrt": a Chebyshev initial value y0 (§2.3), then Newton
+ * steps y <- y (3 - a y^2) / 2 (§2.2), with bootstrapping when levels run
+ * out), on the CKKS operations the paper names in §2.1 (Add, Sub, Mul_P,
+ * Mul_C, BTS, levels).  The scheme is RNS-CKKS with hybrid key switching; the
+ * paper describes none of its internals, so every convention (prime chain,
+ * NTT ordering, sampler, scale management, evaluation trees) is fixed by this
+ * library's design document and reproduced bit for bit by an independent CPU
+ * oracle.
+ *
+ * Conventions shared by every call:
+ *  - A context owns the parameters, the per-prime tables, the keys and the
+ *    device memory pool; it is used by one host thread at a time.  All device
+ *    work is ordered on the context's HIP stream.
+ *  - A ciphertext lives in device memory as uint64 words laid out
+ *    [2][level+1][N] (poly-major, then limb-major), each limb a residue
+ *    polynomial in the NTT domain (evaluations at the odd powers of the
+ *    prime's 2N-th root psi, stored in bit-reversed order), every word fully
+ *    reduced in [0, q_i).  Host-side it carries its level and an exact
+ *    binary64 scale.
+ *  - Every `ckks_ct **out` receives a NEW ciphertext owned by the caller
+ *    (free with ckks_ct_free).  Inputs are never modified.  On error *out is
+ *    NULL, inputs are untouched, and ckks_last_error() describes the failure;
+ *    nothing aborts across the ABI.
+ *  - Primitive operations never bootstrap by themselves: a missing level is
+ *    CKKS_E_LEVEL.  Only ckks_bootstrap and ckks_invsqrt* bootstrap.
+ *  - Host pointers are plain host memory; "device" pointers are HIP device
+ *    memory (for example a torch tensor's data_ptr()) on the context's device.
+ */
+#ifndef CKKS_H
+#define CKKS_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct ckks_ctx ckks_ctx;
+typedef struct ckks_ct ckks_ct;
+
+typedef enum {
+    CKKS_OK = 0,
+    CKKS_E_PARAM = -1,   /* bad argument or parameter set */
+    CKKS_E_LEVEL = -2,   /* not enough levels / level mismatch */
+    CKKS_E_SCALE = -3,   /* scales of an addition do not match */
+    CKKS_E_NOKEY = -4,   /* keys not generated / rotation key missing */
+    CKKS_E_OOM = -5,     /* device memory exhausted (pool or arena) */
+    CKKS_E_DEVICE = -6,  /* a HIP call failed */
+    CKKS_E_RANGE = -7    /* a value does not fit the encoding */
+} ckks_status;
+
+/*
+ * Parameter set.  Primes: q_0 = largest prime < 2^q0_bits with q = 1 mod 2N;
+ * q_L..q_1 chosen top-down so that the canonical scale ladder
+ * S_L = 2^log_scale, S_{l-1} = S_l^2 / q_l stays near 2^log_scale; special
+ * primes p_0..p_{K-1} = the next primes = 1 mod 2N below q_0.  Key switching
+ * uses digits of `digit_size` consecutive q-primes (dnum = ceil((L+1)/alpha)).
+ * hamming_weight = 0 selects a dense ternary secret, otherwise a secret with
+ * exactly that many +-1 coefficients.  sigma is the error standard deviation.
+ * Bootstrapping (ckks_bootstrap) needs bts_levels > 0: the number of top
+ * levels the bootstrapping circuit consumes (see ckks_bts_info).
+ */
+typedef struct {
+    uint32_t log_n;           /* ring degree N = 2^log_n, 4..16 */
+    uint32_t max_level;       /* L: primes q_0..q_L */
+    uint32_t num_special;     /* K */
+    uint32_t digit_size;      /* alpha */
+    uint32_t hamming_weight;  /* 0 = dense ternary */
+    double sigma;             /* 3.2 */
+    uint32_t log_scale;       /* 40 */
+    uint32_t q0_bits;         /* 60 */
+    uint32_t p_bits;          /* 60 */
+} ckks_params;
+
+/*
+ * Create a context on the current HIP device.  `arena` (device memory, may be
+ * NULL) of `arena_bytes` bytes, if given, is the only memory the context's
+ * pool draws from (the caller keeps it alive until ckks_ctx_destroy; a torch
+ * tensor works); with NULL the pool uses hipMalloc.  `hip_stream` (a
+ * hipStream_t, may be NULL = default stream) orders all work.
+ */
+ckks_status ckks_ctx_create(const ckks_params *p, void *arena, size_t arena_bytes,
+                            void *hip_stream, ckks_ctx **out);
+void ckks_ctx_destroy(ckks_ctx *ctx);
+/* Last error message of this context (static text valid until the next call). */
+const char *ckks_last_error(const ckks_ctx *ctx);
+/* Copy the prime chain (L+1+K words: q_0..q_L, p_0..p_{K-1}) and the
+ * canonical scale ladder S_0..S_L (L+1 doubles).  Either pointer may be NULL. */
+ckks_status ckks_ctx_primes(const ckks_ctx *ctx, uint64_t *primes, double *ladder);
+/* Change the stream all later work is ordered on. */
+ckks_status ckks_set_stream(ckks_ctx *ctx, void *hip_stream);
+/* Block until all work queued on the context's stream has finished. */
+ckks_status ckks_sync(ckks_ctx *ctx);
+
+/*
+ * Keys from the seeded SHAKE-256 sampler: secret, public key, relinearisation
+ * key and one switching key per Galois element in `galois` (odd elements of
+ * Z_2N^*: 5^k mod 2N rotates left by k slots, 2N-1 conjugates).  All keys
+ * live in device memory.  Replaces any previous keys.
+ */
+ckks_status ckks_keygen(ckks_ctx *ctx, uint64_t seed, const int32_t *galois, uint32_t n_galois);
+/* Galois element of a left rotation by `steps` slots (negative = right). */
+int32_t ckks_galois_rotation(const ckks_ctx *ctx, int32_t steps);
+
+/*
+ * Public-key encryption of n <= N/2 real slot values (the rest are zero) at
+ * `level`, encoded at `scale` (quad-precision canonical embedding, rounded to
+ * nearest).  Randomness from SHAKE-256 on `seed`.
+ */
+ckks_status ckks_encrypt(ckks_ctx *ctx, const double *x, uint32_t n, uint32_t level,
+                         double scale, uint64_t seed, ckks_ct **out);
+/* Decrypt with the context's secret key and decode N/2 slots (real parts to
+ * `re`, imaginary parts to `im`; `im` may be NULL). */
+ckks_status ckks_decrypt(ckks_ctx *ctx, const ckks_ct *ct, double *re, double *im);
+
+/* Ciphertext transfer: host words [2][level+1][N] (fully reduced) <-> device. */
+ckks_status ckks_ct_import(ckks_ctx *ctx, const uint64_t *host, uint32_t level, double scale,
+                           ckks_ct **out);
+ckks_status ckks_ct_export(ckks_ctx *ctx, const ckks_ct *ct, uint64_t *host);
+/* Device address of the ciphertext words (valid until ckks_ct_free). */
+void *ckks_ct_device_ptr(const ckks_ct *ct);
+int32_t ckks_ct_level(const ckks_ct *ct);
+double ckks_ct_scale(const ckks_ct *ct);
+void ckks_ct_free(ckks_ctx *ctx, ckks_ct *ct);
+
+/* Add_C / Sub_C: equal levels, |s_a/s_b - 1| <= 2^-30 (else CKKS_E_SCALE);
+ * result scale s_a. */
+ckks_status ckks_add(ckks_ctx *ctx, const ckks_ct *a, const ckks_ct *b, ckks_ct **out);
+ckks_status ckks_sub(ckks_ctx *ctx, const ckks_ct *a, const ckks_ct *b, ckks_ct **out);
+/* Multiply by a signed integer (no level, scale unchanged). */
+ckks_status ckks_mul_int(ckks_ctx *ctx, const ckks_ct *a, int64_t k, ckks_ct **out);
+/* Mul_P by a real constant at plaintext scale s_c (paper §2.1, Mul_P):
+ * k = rint(value * s_c), ct' = k ct, scale' = scale * s_c; no rescale. */
+ckks_status ckks_mul_const(ckks_ctx *ctx, const ckks_ct *a, double value, double s_c,
+                           ckks_ct **out);
+/* Mul_P landing on the canonical scale one level down:
+ * s_c = (S_{l-1} * q_l) / scale, then rescale. */
+ckks_status ckks_mul_const_down(ckks_ctx *ctx, const ckks_ct *a, double value, ckks_ct **out);
+/* Add_P of a real constant: rint(value * scale) added to every slot. */
+ckks_status ckks_add_const(ckks_ctx *ctx, const ckks_ct *a, double value, ckks_ct **out);
+/* Keep limbs 0..level (scale unchanged). */
+ckks_status ckks_drop_level(ckks_ctx *ctx, const ckks_ct *a, uint32_t level, ckks_ct **out);
+/* Bring to a lower level carrying the canonical scale S_level (drop to
+ * level+1, Mul_P by 1 at s_c = (S_level q_{level+1}) / scale, rescale). */
+ckks_status ckks_level_to(ckks_ctx *ctx, const ckks_ct *a, uint32_t level, ckks_ct **out);
+/* Rescale by q_l: c' = round(c / q_l) coefficient-wise, scale' = scale / q_l. */
+ckks_status ckks_rescale(ckks_ctx *ctx, const ckks_ct *a, ckks_ct **out);
+/* Mul_C with relinearisation (hybrid key switching), no rescale; scale s_a s_b. */
+ckks_status ckks_hmult_relin(ckks_ctx *ctx, const ckks_ct *a, const ckks_ct *b, ckks_ct **out);
+/* Left rotation of the slots by `steps` (automorphism X -> X^(5^steps) and
+ * key switch; CKKS_E_NOKEY without the Galois key). */
+ckks_status ckks_rotate(ckks_ctx *ctx, const ckks_ct *a, int32_t steps, ckks_ct **out);
+/* Complex conjugation of the slots (X -> X^(2N-1)). */
+ckks_status ckks_conjugate(ckks_ctx *ctx, const ckks_ct *a, ckks_ct **out);
+
+/*
+ * Chebyshev-basis polynomial sum_k coeffs[k] T_k(t), t = (2x - a - b)/(b - a),
+ * evaluated by baby-step/giant-step (paper §2.3 uses such a polynomial as
+ * the Newton initial value).  [a, b] = [-1, 1] uses x as t directly.
+ * Consumes bitlen(degree) + 1 levels (+1 for the affine map).
+ */
+ckks_status ckks_cheb_eval(ckks_ctx *ctx, const ckks_ct *x, const double *coeffs, uint32_t degree,
+                           double a, double b, ckks_ct **out);
+/* Chebyshev interpolation coefficients of 1/sqrt(x) on [a, b] at the
+ * degree+1 first-kind nodes (quad precision, rounded once). */
+ckks_status ckks_cheb_coeffs_invsqrt(uint32_t degree, double a, double b, double *coeffs);
+/* One Newton step for 1/sqrt (paper §2.2, Alg. 1 loop body) given
+ * ct_half = x/2: y' = 1.5 y - (ct_half y) y^2.  Consumes 2 levels. */
+ckks_status ckks_newton_step(ckks_ctx *ctx, const ckks_ct *y, const ckks_ct *ct_half, ckks_ct **out);
+
+/* Bootstrapping (paper §2.1 BTS) of a level-0..l ciphertext whose slot
+ * values are real and lie in [-1, 1]: ModRaise, CoeffToSlot, EvalMod,
+ * SlotToCoeff.  Needs the bootstrapping keys (ckks_bts_setup). */
+ckks_status ckks_bootstrap(ckks_ctx *ctx, const ckks_ct *a, ckks_ct **out);
+
+typedef struct {
+    double a, b;        /* input domain of x (default 2^-10, 1) */
+    int32_t literal;    /* 1: bootstrap y0 right after the Chebyshev step, as
+                           Alg. 1 is written; 0 (default): bootstrap y only
+                           when it has fewer than 2 levels before a step */
+    int32_t bts_scale;  /* y is bootstrapped as S * BTS(y / S), default 64 */
+} ckks_invsqrt_opts;
+
+/*
+ * CryptoInvSqrt (paper Alg. 1): y0 = Chebyshev interpolant of degree `degree`
+ * of 1/sqrt on [a, b]; ct_x = x/2; `iters` Newton steps; bootstrapping of y
+ * per the policy in opts.  ckks_invsqrt uses the defaults above.
+ */
+ckks_status ckks_invsqrt(ckks_ctx *ctx, const ckks_ct *x, uint32_t degree, uint32_t iters,
+                         ckks_ct **out);
+ckks_status ckks_invsqrt_ex(ckks_ctx *ctx, const ckks_ct *x, uint32_t degree, uint32_t iters,
+                            const ckks_invsqrt_opts *opts, ckks_ct **out);
+
+/*
+ * Batched form: n independent ciphertexts at the same level through the same
+ * (degree, iters) chain; each primitive step is one launch over all of them.
+ * outs[i] receives the result for xs[i].  Results are bit-identical to n
+ * calls of ckks_invsqrt_ex.
+ */
+ckks_status ckks_invsqrt_batch(ckks_ctx *ctx, const ckks_ct *const *xs, uint32_t n,
+                               uint32_t degree, uint32_t iters, const ckks_invsqrt_opts *opts,
+                               ckks_ct **outs);
+
+/*
+ * Forward (inverse = 0) or inverse (inverse = 1) negacyclic NTT, in place, of
+ * `n_limbs` device-resident limbs of N words each at `data` (limb-major).
+ * prime_idx[i] (host array) is the index, in the chain q_0..q_L,p_0..p_{K-1},
+ * of limb i's prime.  Definition: NTT(a)[j] = sum_i a_i psi^((2 br(j)+1) i).
+ */
+ckks_status ckks_ntt_device(ckks_ctx *ctx, uint64_t *data, uint32_t n_limbs,
+                            const uint32_t *prime_idx, int inverse);
+
+/*
+ * Opt-in timing of kernel families on the context's stream (HIP events
+ * recorded around each call; enabling clears previous records).  Families:
+ *   "ntt"       every forward/inverse NTT call of the hot path; algorithmic
+ *               bytes = 16 N per limb (one read and one write of each word);
+ *   "keyswitch" every hybrid key switch; algorithmic bytes =
+ *               8 N ((l+1) + 2 beta (l+1+K) + 2 (l+1)): the input polynomial,
+ *               the switching key and the two output polynomials.
+ * ckks_profile_read returns the number of calls, the summed GPU time in ms
+ * and the summed algorithmic bytes of a family (zeros if never recorded).
+ */
+ckks_status ckks_profile_enable(ckks_ctx *ctx, int on);
+ckks_status ckks_profile_read(ckks_ctx *ctx, const char *family, uint64_t *calls, double *gpu_ms,
+                              double *alg_bytes);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* CKKS_H */

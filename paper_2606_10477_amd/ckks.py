@@ -1,0 +1,287 @@
+"""Thin ctypes binding of libckks_hip.so (include/ckks.h).
+
+Argument marshalling only: every homomorphic step runs in the HIP library.
+PyTorch supplies the device memory arena and the stream.  Loading fails loudly
+when the library has not been built; there is no CPU fallback.
+"""
+import ctypes as C
+import os
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libckks_hip.so")
+_lib = None
+
+vp = C.c_void_p
+u64p = C.POINTER(C.c_uint64)
+dblp = C.POINTER(C.c_double)
+i32p = C.POINTER(C.c_int32)
+u32p = C.POINTER(C.c_uint32)
+
+STATUS = {0: "OK", -1: "E_PARAM", -2: "E_LEVEL", -3: "E_SCALE", -4: "E_NOKEY", -5: "E_OOM",
+          -6: "E_DEVICE", -7: "E_RANGE"}
+
+
+class Params(C.Structure):
+    _fields_ = [("log_n", C.c_uint32), ("max_level", C.c_uint32), ("num_special", C.c_uint32),
+                ("digit_size", C.c_uint32), ("hamming_weight", C.c_uint32), ("sigma", C.c_double),
+                ("log_scale", C.c_uint32), ("q0_bits", C.c_uint32), ("p_bits", C.c_uint32)]
+
+
+class InvsqrtOpts(C.Structure):
+    _fields_ = [("a", C.c_double), ("b", C.c_double), ("literal", C.c_int32), ("bts_scale", C.c_int32)]
+
+
+# name -> (restype, argtypes): every symbol of include/ckks.h
+SIGNATURES = {
+    "ckks_ctx_create": (C.c_int, [C.POINTER(Params), vp, C.c_size_t, vp, C.POINTER(vp)]),
+    "ckks_ctx_destroy": (None, [vp]),
+    "ckks_last_error": (C.c_char_p, [vp]),
+    "ckks_ctx_primes": (C.c_int, [vp, u64p, dblp]),
+    "ckks_set_stream": (C.c_int, [vp, vp]),
+    "ckks_sync": (C.c_int, [vp]),
+    "ckks_keygen": (C.c_int, [vp, C.c_uint64, i32p, C.c_uint32]),
+    "ckks_galois_rotation": (C.c_int32, [vp, C.c_int32]),
+    "ckks_encrypt": (C.c_int, [vp, dblp, C.c_uint32, C.c_uint32, C.c_double, C.c_uint64, C.POINTER(vp)]),
+    "ckks_decrypt": (C.c_int, [vp, vp, dblp, dblp]),
+    "ckks_ct_import": (C.c_int, [vp, u64p, C.c_uint32, C.c_double, C.POINTER(vp)]),
+    "ckks_ct_export": (C.c_int, [vp, vp, u64p]),
+    "ckks_ct_device_ptr": (vp, [vp]),
+    "ckks_ct_level": (C.c_int32, [vp]),
+    "ckks_ct_scale": (C.c_double, [vp]),
+    "ckks_ct_free": (None, [vp, vp]),
+    "ckks_add": (C.c_int, [vp, vp, vp, C.POINTER(vp)]),
+    "ckks_sub": (C.c_int, [vp, vp, vp, C.POINTER(vp)]),
+    "ckks_mul_int": (C.c_int, [vp, vp, C.c_int64, C.POINTER(vp)]),
+    "ckks_mul_const": (C.c_int, [vp, vp, C.c_double, C.c_double, C.POINTER(vp)]),
+    "ckks_mul_const_down": (C.c_int, [vp, vp, C.c_double, C.POINTER(vp)]),
+    "ckks_add_const": (C.c_int, [vp, vp, C.c_double, C.POINTER(vp)]),
+    "ckks_drop_level": (C.c_int, [vp, vp, C.c_uint32, C.POINTER(vp)]),
+    "ckks_level_to": (C.c_int, [vp, vp, C.c_uint32, C.POINTER(vp)]),
+    "ckks_rescale": (C.c_int, [vp, vp, C.POINTER(vp)]),
+    "ckks_hmult_relin": (C.c_int, [vp, vp, vp, C.POINTER(vp)]),
+    "ckks_rotate": (C.c_int, [vp, vp, C.c_int32, C.POINTER(vp)]),
+    "ckks_conjugate": (C.c_int, [vp, vp, C.POINTER(vp)]),
+    "ckks_cheb_eval": (C.c_int, [vp, vp, dblp, C.c_uint32, C.c_double, C.c_double, C.POINTER(vp)]),
+    "ckks_cheb_coeffs_invsqrt": (C.c_int, [C.c_uint32, C.c_double, C.c_double, dblp]),
+    "ckks_newton_step": (C.c_int, [vp, vp, vp, C.POINTER(vp)]),
+    "ckks_bootstrap": (C.c_int, [vp, vp, C.POINTER(vp)]),
+    "ckks_invsqrt": (C.c_int, [vp, vp, C.c_uint32, C.c_uint32, C.POINTER(vp)]),
+    "ckks_invsqrt_ex": (C.c_int, [vp, vp, C.c_uint32, C.c_uint32, C.POINTER(InvsqrtOpts), C.POINTER(vp)]),
+    "ckks_invsqrt_batch": (C.c_int, [vp, C.POINTER(vp), C.c_uint32, C.c_uint32, C.c_uint32,
+                                     C.POINTER(InvsqrtOpts), C.POINTER(vp)]),
+    "ckks_ntt_device": (C.c_int, [vp, C.c_void_p, C.c_uint32, u32p, C.c_int]),
+    "ckks_profile_enable": (C.c_int, [vp, C.c_int]),
+    "ckks_profile_read": (C.c_int, [vp, C.c_char_p, u64p, dblp, dblp]),
+}
+
+
+def lib():
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB_PATH):
+        raise RuntimeError("libckks_hip.so is not built (run __graft_entry__.build()); "
+                           "there is no CPU fallback")
+    L = C.CDLL(LIB_PATH)
+    for name, (res, args) in SIGNATURES.items():
+        f = getattr(L, name)
+        f.restype = res
+        f.argtypes = args
+    _lib = L
+    return L
+
+
+class CkksError(RuntimeError):
+    def __init__(self, status, msg):
+        super().__init__(f"{STATUS.get(status, status)}: {msg}")
+        self.status = status
+
+
+def _p(a, t):
+    return a.ctypes.data_as(t)
+
+
+class Ciphertext:
+    def __init__(self, ctx, ptr):
+        self.ctx = ctx
+        self.ptr = ptr
+
+    def __del__(self):
+        self.free()
+
+    def free(self):
+        if getattr(self, "ptr", None) and self.ctx.ptr:
+            lib().ckks_ct_free(self.ctx.ptr, self.ptr)
+        self.ptr = None
+
+    @property
+    def level(self):
+        return lib().ckks_ct_level(self.ptr)
+
+    @property
+    def scale(self):
+        return lib().ckks_ct_scale(self.ptr)
+
+    def words(self):
+        out = np.zeros((2, self.level + 1, self.ctx.N), dtype=np.uint64)
+        self.ctx._chk(lib().ckks_ct_export(self.ctx.ptr, self.ptr, _p(out, u64p)))
+        return out
+
+
+class Context:
+    """A parameter set on the current GPU.  `arena_bytes` > 0 allocates the
+    context's device memory as one torch tensor (PyTorch owns the memory); the
+    current torch stream orders all work."""
+
+    def __init__(self, log_n, max_level, num_special, digit_size, hamming_weight=0, sigma=3.2,
+                 log_scale=40, q0_bits=60, p_bits=60, arena_bytes=0, stream=None):
+        import torch
+        self.N = 1 << log_n
+        self.n = self.N // 2
+        self.L = max_level
+        self.K = num_special
+        self.np_ = max_level + 1 + num_special
+        p = Params(log_n, max_level, num_special, digit_size, hamming_weight, sigma, log_scale, q0_bits, p_bits)
+        self._arena = None
+        arena_ptr = None
+        if arena_bytes:
+            self._arena = torch.empty(arena_bytes, dtype=torch.uint8, device="cuda")
+            arena_ptr = self._arena.data_ptr()
+        if stream is None:
+            stream = torch.cuda.current_stream().cuda_stream
+        self.stream = stream
+        out = vp()
+        self.ptr = None
+        st = lib().ckks_ctx_create(C.byref(p), arena_ptr, arena_bytes, stream, C.byref(out))
+        if st != 0:
+            raise CkksError(st, "context creation failed")
+        self.ptr = out.value
+        self.primes = np.zeros(self.np_, dtype=np.uint64)
+        self.ladder = np.zeros(max_level + 1)
+        lib().ckks_ctx_primes(self.ptr, _p(self.primes, u64p), _p(self.ladder, dblp))
+
+    def close(self):
+        if self.ptr:
+            lib().ckks_ctx_destroy(self.ptr)
+            self.ptr = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def _chk(self, st):
+        if st != 0:
+            raise CkksError(st, lib().ckks_last_error(self.ptr).decode())
+
+    def _ct(self, fn, *args):
+        out = vp()
+        self._chk(fn(self.ptr, *args, C.byref(out)))
+        return Ciphertext(self, out.value)
+
+    def sync(self):
+        self._chk(lib().ckks_sync(self.ptr))
+
+    def keygen(self, seed, galois=()):
+        g = np.array(list(galois), dtype=np.int32)
+        self._chk(lib().ckks_keygen(self.ptr, seed, _p(g, i32p) if len(g) else None, len(g)))
+
+    def galois_rot(self, k):
+        return lib().ckks_galois_rotation(self.ptr, k)
+
+    def encrypt(self, x, level, scale, seed):
+        x = np.ascontiguousarray(x, dtype=np.float64)
+        return self._ct(lib().ckks_encrypt, _p(x, dblp), len(x), level, scale, seed)
+
+    def decrypt(self, ct):
+        re = np.zeros(self.n)
+        im = np.zeros(self.n)
+        self._chk(lib().ckks_decrypt(self.ptr, ct.ptr, _p(re, dblp), _p(im, dblp)))
+        return re + 1j * im
+
+    def ct_import(self, words, level, scale):
+        w = np.ascontiguousarray(words, dtype=np.uint64)
+        assert w.size == 2 * (level + 1) * self.N
+        return self._ct(lib().ckks_ct_import, _p(w, u64p), level, scale)
+
+    def add(self, a, b):
+        return self._ct(lib().ckks_add, a.ptr, b.ptr)
+
+    def sub(self, a, b):
+        return self._ct(lib().ckks_sub, a.ptr, b.ptr)
+
+    def mul_int(self, a, k):
+        return self._ct(lib().ckks_mul_int, a.ptr, int(k))
+
+    def mul_const(self, a, v, s_c):
+        return self._ct(lib().ckks_mul_const, a.ptr, float(v), float(s_c))
+
+    def mul_const_down(self, a, v):
+        return self._ct(lib().ckks_mul_const_down, a.ptr, float(v))
+
+    def add_const(self, a, v):
+        return self._ct(lib().ckks_add_const, a.ptr, float(v))
+
+    def drop_level(self, a, level):
+        return self._ct(lib().ckks_drop_level, a.ptr, level)
+
+    def level_to(self, a, level):
+        return self._ct(lib().ckks_level_to, a.ptr, level)
+
+    def rescale(self, a):
+        return self._ct(lib().ckks_rescale, a.ptr)
+
+    def hmult(self, a, b):
+        return self._ct(lib().ckks_hmult_relin, a.ptr, b.ptr)
+
+    def rotate(self, a, k):
+        return self._ct(lib().ckks_rotate, a.ptr, k)
+
+    def conjugate(self, a):
+        return self._ct(lib().ckks_conjugate, a.ptr)
+
+    def cheb_eval(self, x, coeffs, a, b):
+        cf = np.ascontiguousarray(coeffs, dtype=np.float64)
+        return self._ct(lib().ckks_cheb_eval, x.ptr, _p(cf, dblp), len(cf) - 1, a, b)
+
+    def newton_step(self, y, half_x):
+        return self._ct(lib().ckks_newton_step, y.ptr, half_x.ptr)
+
+    def bootstrap(self, a):
+        return self._ct(lib().ckks_bootstrap, a.ptr)
+
+    def invsqrt(self, x, degree, iters, a=2.0 ** -10, b=1.0, literal=False, bts_scale=64):
+        o = InvsqrtOpts(a, b, int(literal), bts_scale)
+        return self._ct(lib().ckks_invsqrt_ex, x.ptr, degree, iters, C.byref(o))
+
+    def invsqrt_batch(self, xs, degree, iters, a=2.0 ** -10, b=1.0, literal=False, bts_scale=64):
+        o = InvsqrtOpts(a, b, int(literal), bts_scale)
+        arr = (vp * len(xs))(*[x.ptr for x in xs])
+        outs = (vp * len(xs))()
+        self._chk(lib().ckks_invsqrt_batch(self.ptr, arr, len(xs), degree, iters, C.byref(o), outs))
+        return [Ciphertext(self, outs[i]) for i in range(len(xs))]
+
+    def profile(self, on=True):
+        self._chk(lib().ckks_profile_enable(self.ptr, int(on)))
+
+    def profile_read(self, family):
+        n = C.c_uint64()
+        ms = C.c_double()
+        by = C.c_double()
+        self._chk(lib().ckks_profile_read(self.ptr, family.encode(), C.byref(n), C.byref(ms), C.byref(by)))
+        return n.value, ms.value, by.value
+
+    def ntt_device(self, ptr, n_limbs, prime_idx, inverse=False):
+        pi = np.ascontiguousarray(prime_idx, dtype=np.uint32)
+        self._chk(lib().ckks_ntt_device(self.ptr, ptr, n_limbs, _p(pi, u32p), int(inverse)))
+
+
+def cheb_coeffs_invsqrt(degree, a, b):
+    out = np.zeros(degree + 1)
+    st = lib().ckks_cheb_coeffs_invsqrt(degree, a, b, _p(out, dblp))
+    if st != 0:
+        raise CkksError(st, "bad arguments")
+    return out

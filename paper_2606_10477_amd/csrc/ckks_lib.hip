@@ -1,0 +1,1154 @@
+// ckks_lib.hip -- host orchestration of the RNS-CKKS hot path and the C-ABI
+// declared in include/ckks.h.
+//
+// Every homomorphic operation is a short sequence of kernel launches
+// (kernels.hip) on the context's stream; the host only chooses constants,
+// levels and scales.  Scale bookkeeping is binary64 with each formula
+// evaluated in the order written next to it, so that the integer constants it
+// decides (rint(value * s_c)) are reproducible.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+#include <map>
+#include <memory>
+#include <stdexcept>
+#include <string>
+#include <vector>
+
+#include "../../include/ckks.h"
+#include "gpu.h"
+#include "host_math.h"
+
+using gpu::LimbConsts;
+using gpu::LimbMap;
+typedef uint64_t u64;
+typedef unsigned __int128 u128;
+
+namespace {
+
+struct Error {
+    ckks_status st;
+    std::string msg;
+};
+[[noreturn]] void fail(ckks_status st, const std::string &m) { throw Error{st, m}; }
+void hipchk(hipError_t e, const char *what) {
+    if (e != hipSuccess) fail(CKKS_E_DEVICE, std::string(what) + ": " + hipGetErrorString(e));
+}
+
+// ---------------------------------------------------------------------------
+// Device memory pool: size-bucketed free lists over an optional caller arena
+// (bump allocation) or hipMalloc.  All users are ordered on one stream, so a
+// block freed after its last kernel was queued can be handed to the next
+// allocation immediately.
+// ---------------------------------------------------------------------------
+class Pool {
+public:
+    Pool(void *arena, size_t bytes) : base_((char *)arena), cap_(bytes), used_(0) {}
+    ~Pool() {
+        for (void *p : owned_) (void)hipFree(p);
+    }
+    void *get(size_t bytes) {
+        bytes = (bytes + 255) & ~(size_t)255;
+        auto &fl = free_[bytes];
+        if (!fl.empty()) {
+            void *p = fl.back();
+            fl.pop_back();
+            return p;
+        }
+        if (base_) {
+            if (used_ + bytes > cap_) fail(CKKS_E_OOM, "arena exhausted");
+            void *p = base_ + used_;
+            used_ += bytes;
+            return p;
+        }
+        void *p = nullptr;
+        if (hipMalloc(&p, bytes) != hipSuccess) fail(CKKS_E_OOM, "hipMalloc failed");
+        owned_.push_back(p);
+        return p;
+    }
+    void put(void *p, size_t bytes) {
+        if (!p) return;
+        bytes = (bytes + 255) & ~(size_t)255;
+        free_[bytes].push_back(p);
+    }
+
+private:
+    char *base_;
+    size_t cap_, used_;
+    std::map<size_t, std::vector<void *>> free_;
+    std::vector<void *> owned_;
+};
+
+struct Buf {
+    Pool *pool = nullptr;
+    u64 *p = nullptr;
+    size_t bytes = 0;
+    Buf() = default;
+    Buf(Pool *pl, size_t words) : pool(pl), bytes(words * 8) { p = (u64 *)pl->get(bytes); }
+    ~Buf() {
+        if (pool && p) pool->put(p, bytes);
+    }
+    Buf(const Buf &) = delete;
+    Buf &operator=(const Buf &) = delete;
+    Buf(Buf &&o) noexcept : pool(o.pool), p(o.p), bytes(o.bytes) { o.p = nullptr; }
+    Buf &operator=(Buf &&o) noexcept {
+        if (this != &o) {
+            if (pool && p) pool->put(p, bytes);
+            pool = o.pool; p = o.p; bytes = o.bytes;
+            o.p = nullptr;
+        }
+        return *this;
+    }
+};
+
+}  // namespace
+
+struct ckks_ct {
+    int level;
+    double scale;
+    Buf buf;   // [2][level+1][N]
+};
+
+struct SwitchKey {
+    Buf k;     // [dnum][2][np][N]
+};
+
+struct ConvTable {
+    Buf hinv, hinv_sh, mat;
+    LimbMap pin, pout;
+    int din, dout;
+};
+
+struct ckks_ctx {
+    ckks_params prm;
+    int logN, N, L, K, alpha, dnum, np;
+    std::vector<u64> q;
+    std::vector<double> ladder;
+    hipStream_t stream;
+    std::unique_ptr<Pool> pool;
+    gpu::Tables T;
+    Buf d_primes, d_fw, d_fwsh, d_iw, d_iwsh, d_ninv, d_ninvsh;
+    std::string err;
+    // keys
+    bool have_keys = false;
+    Buf sk;                       // [np][N] NTT form
+    Buf pk;                       // [2][L+1][N]
+    SwitchKey relin;
+    std::map<int, SwitchKey> rot;
+    std::map<int, Buf> perms;     // galois -> int32[N] (stored in a u64 buffer)
+    std::map<std::pair<int, int>, std::unique_ptr<ConvTable>> modup;   // (level, digit)
+    std::map<int, std::unique_ptr<ConvTable>> moddown;                 // level
+    hm::Cdt cdt;
+    // opt-in timing of kernel families with HIP events on the context stream
+    struct ProfFamily {
+        std::vector<std::pair<hipEvent_t, hipEvent_t>> ev;
+        double bytes = 0;
+        uint64_t calls = 0;
+    };
+    bool prof_on = false;
+    std::map<std::string, ProfFamily> prof;
+    std::vector<hipEvent_t> ev_free;
+    u64 words(int level) const { return (u64)2 * (level + 1) * N; }
+    ~ckks_ctx() {
+        for (auto &f : prof)
+            for (auto &e : f.second.ev) { (void)hipEventDestroy(e.first); (void)hipEventDestroy(e.second); }
+        for (hipEvent_t e : ev_free) (void)hipEventDestroy(e);
+    }
+};
+
+namespace {
+
+// ---------------------------------------------------------------------------
+// small helpers
+// ---------------------------------------------------------------------------
+u64 shoup(u64 w, u64 q) { return (u64)(((u128)w << 64) / q); }
+u64 mod_signed(int64_t v, u64 q) {
+    if (v >= 0) return (u64)v % q;
+    u64 r = ((u64)(-(v + 1)) + 1) % q;
+    return r ? q - r : 0;
+}
+LimbMap map_q(int first, int count) {
+    LimbMap m{};
+    for (int i = 0; i < count; ++i) m.p[i] = (uint8_t)(first + i);
+    return m;
+}
+LimbMap map_ext(const ckks_ctx *c, int level) {   // q_0..q_level, p_0..p_{K-1}
+    LimbMap m{};
+    int e = 0;
+    for (int i = 0; i <= level; ++i) m.p[e++] = (uint8_t)i;
+    for (int k = 0; k < c->K; ++k) m.p[e++] = (uint8_t)(c->L + 1 + k);
+    return m;
+}
+LimbMap map_list(const std::vector<int> &pr) {
+    LimbMap m{};
+    for (size_t i = 0; i < pr.size(); ++i) m.p[i] = (uint8_t)pr[i];
+    return m;
+}
+void upload(Buf &b, const void *src, size_t bytes, hipStream_t s) {
+    hipchk(hipMemcpyAsync(b.p, src, bytes, hipMemcpyHostToDevice, s), "upload");
+    hipchk(hipStreamSynchronize(s), "upload sync");
+}
+
+int bitrev(int x, int bits) {
+    int r = 0;
+    for (int i = 0; i < bits; ++i) { r = (r << 1) | (x & 1); x >>= 1; }
+    return r;
+}
+
+hipEvent_t prof_event(ckks_ctx *c) {
+    if (!c->ev_free.empty()) {
+        hipEvent_t e = c->ev_free.back();
+        c->ev_free.pop_back();
+        return e;
+    }
+    hipEvent_t e;
+    hipchk(hipEventCreate(&e), "event");
+    return e;
+}
+// RAII bracket: records start/stop events around a kernel family's launches
+struct ProfScope {
+    ckks_ctx *c;
+    const char *fam;
+    double bytes;
+    hipEvent_t e0 = nullptr;
+    ProfScope(ckks_ctx *c_, const char *f, double b) : c(c_), fam(f), bytes(b) {
+        if (c->prof_on) {
+            e0 = prof_event(c);
+            hipchk(hipEventRecord(e0, c->stream), "event record");
+        }
+    }
+    ~ProfScope() {
+        if (!e0) return;
+        hipEvent_t e1 = prof_event(c);
+        if (hipEventRecord(e1, c->stream) != hipSuccess) return;
+        auto &f = c->prof[fam];
+        f.ev.emplace_back(e0, e1);
+        f.bytes += bytes;
+        f.calls += 1;
+    }
+};
+// NTT with the profiling bracket (algorithmic bytes: one read + one write per word)
+void ntt_p(ckks_ctx *c, uint64_t *data, int nlimb, int npoly, const LimbMap &m, bool inverse) {
+    ProfScope ps(c, "ntt", 16.0 * (double)nlimb * npoly * c->N);
+    gpu::ntt(c->T, data, nlimb, npoly, m, inverse, c->stream);
+}
+
+// ---------------------------------------------------------------------------
+// context construction
+// ---------------------------------------------------------------------------
+void build_tables(ckks_ctx *c) {
+    const int N = c->N, np = c->np;
+    std::vector<gpu::DevPrime> dp(np);
+    std::vector<u64> fw((size_t)np * N), fwsh((size_t)np * N), iw((size_t)np * N), iwsh((size_t)np * N);
+    std::vector<u64> ninv(np), ninvsh(np);
+    std::vector<u64> pw(N);
+    for (int i = 0; i < np; ++i) {
+        const u64 q = c->q[i];
+        int n = 64 - __builtin_clzll(q);
+        dp[i].q = q;
+        dp[i].nbits = (uint32_t)n;
+        dp[i].mu = (u64)(((u128)1 << (2 * n)) / q);
+        u128 mu2 = (~(u128)0) / q;
+        dp[i].mu2_lo = (u64)mu2;
+        dp[i].mu2_hi = (u64)(mu2 >> 64);
+        const u64 psi = hm::root_2n(q, N);
+        const u64 ipsi = hm::invmod(psi, q);
+        for (int pass = 0; pass < 2; ++pass) {
+            u64 g = pass == 0 ? psi : ipsi, acc = 1;
+            for (int k = 0; k < N; ++k) { pw[k] = acc; acc = hm::mulmod(acc, g, q); }
+            u64 *dst = (pass == 0 ? fw.data() : iw.data()) + (size_t)i * N;
+            u64 *dsh = (pass == 0 ? fwsh.data() : iwsh.data()) + (size_t)i * N;
+            for (int k = 0; k < N; ++k) {
+                dst[k] = pw[bitrev(k, c->logN)];
+                dsh[k] = shoup(dst[k], q);
+            }
+        }
+        ninv[i] = hm::invmod((u64)N, q);
+        ninvsh[i] = shoup(ninv[i], q);
+    }
+    Pool *P = c->pool.get();
+    c->d_primes = Buf(P, (np * sizeof(gpu::DevPrime) + 7) / 8);
+    c->d_fw = Buf(P, (size_t)np * N);
+    c->d_fwsh = Buf(P, (size_t)np * N);
+    c->d_iw = Buf(P, (size_t)np * N);
+    c->d_iwsh = Buf(P, (size_t)np * N);
+    c->d_ninv = Buf(P, np);
+    c->d_ninvsh = Buf(P, np);
+    upload(c->d_primes, dp.data(), np * sizeof(gpu::DevPrime), c->stream);
+    upload(c->d_fw, fw.data(), fw.size() * 8, c->stream);
+    upload(c->d_fwsh, fwsh.data(), fwsh.size() * 8, c->stream);
+    upload(c->d_iw, iw.data(), iw.size() * 8, c->stream);
+    upload(c->d_iwsh, iwsh.data(), iwsh.size() * 8, c->stream);
+    upload(c->d_ninv, ninv.data(), np * 8, c->stream);
+    upload(c->d_ninvsh, ninvsh.data(), np * 8, c->stream);
+    c->T.primes = (const gpu::DevPrime *)c->d_primes.p;
+    c->T.fw = c->d_fw.p;
+    c->T.fw_sh = c->d_fwsh.p;
+    c->T.iw = c->d_iw.p;
+    c->T.iw_sh = c->d_iwsh.p;
+    c->T.ninv = c->d_ninv.p;
+    c->T.ninv_sh = c->d_ninvsh.p;
+    c->T.logN = c->logN;
+}
+
+// product of primes (indices idx, skipping `skip`) modulo m
+u64 prod_mod(const ckks_ctx *c, const std::vector<int> &idx, int skip, u64 m) {
+    u64 r = 1 % m;
+    for (int i : idx)
+        if (i != skip) r = hm::mulmod(r, c->q[i] % m, m);
+    return r;
+}
+
+ConvTable *make_conv(ckks_ctx *c, const std::vector<int> &in, const std::vector<int> &out) {
+    auto t = std::make_unique<ConvTable>();
+    t->din = (int)in.size();
+    t->dout = (int)out.size();
+    if (t->din > 16) fail(CKKS_E_PARAM, "digit too large for base conversion");
+    std::vector<u64> hinv(t->din), hinvsh(t->din), mat((size_t)t->din * t->dout);
+    for (int a = 0; a < t->din; ++a) {
+        const u64 qi = c->q[in[a]];
+        hinv[a] = hm::invmod(prod_mod(c, in, in[a], qi), qi);
+        hinvsh[a] = shoup(hinv[a], qi);
+        for (int r = 0; r < t->dout; ++r) mat[(size_t)a * t->dout + r] = prod_mod(c, in, in[a], c->q[out[r]]);
+    }
+    Pool *P = c->pool.get();
+    t->hinv = Buf(P, t->din);
+    t->hinv_sh = Buf(P, t->din);
+    t->mat = Buf(P, mat.size());
+    upload(t->hinv, hinv.data(), hinv.size() * 8, c->stream);
+    upload(t->hinv_sh, hinvsh.data(), hinvsh.size() * 8, c->stream);
+    upload(t->mat, mat.data(), mat.size() * 8, c->stream);
+    t->pin = map_list(in);
+    t->pout = map_list(out);
+    return t.release();
+}
+
+ConvTable *modup_table(ckks_ctx *c, int level, int digit) {
+    auto key = std::make_pair(level, digit);
+    auto it = c->modup.find(key);
+    if (it != c->modup.end()) return it->second.get();
+    const int nq = level + 1;
+    const int lo = digit * c->alpha, hi = std::min(nq, lo + c->alpha);
+    std::vector<int> in, out;
+    for (int i = lo; i < hi; ++i) in.push_back(i);
+    for (int i = 0; i < nq; ++i)
+        if (i < lo || i >= hi) out.push_back(i);
+    for (int k = 0; k < c->K; ++k) out.push_back(c->L + 1 + k);
+    ConvTable *t = make_conv(c, in, out);
+    c->modup[key].reset(t);
+    return t;
+}
+ConvTable *moddown_table(ckks_ctx *c, int level) {
+    auto it = c->moddown.find(level);
+    if (it != c->moddown.end()) return it->second.get();
+    std::vector<int> in, out;
+    for (int k = 0; k < c->K; ++k) in.push_back(c->L + 1 + k);
+    for (int i = 0; i <= level; ++i) out.push_back(i);
+    ConvTable *t = make_conv(c, in, out);
+    c->moddown[level].reset(t);
+    return t;
+}
+
+const int32_t *perm_for(ckks_ctx *c, int g) {
+    auto it = c->perms.find(g);
+    if (it != c->perms.end()) return (const int32_t *)it->second.p;
+    const int N = c->N, M = 2 * N;
+    std::vector<int32_t> perm(N);
+    for (int j = 0; j < N; ++j) {
+        long long e = 2LL * bitrev(j, c->logN) + 1;
+        long long ge = (e * g) % M;
+        perm[j] = bitrev((int)((ge - 1) / 2), c->logN);
+    }
+    Buf b(c->pool.get(), (N + 1) / 2);
+    upload(b, perm.data(), N * sizeof(int32_t), c->stream);
+    const int32_t *p = (const int32_t *)b.p;
+    c->perms.emplace(g, std::move(b));
+    return p;
+}
+
+// ---------------------------------------------------------------------------
+// ciphertext helpers
+// ---------------------------------------------------------------------------
+typedef std::unique_ptr<ckks_ct> Ct;
+
+Ct ct_new(ckks_ctx *c, int level, double scale) {
+    Ct r(new ckks_ct);
+    r->level = level;
+    r->scale = scale;
+    r->buf = Buf(c->pool.get(), c->words(level));
+    return r;
+}
+u64 *poly(const ckks_ctx *c, const ckks_ct *ct, int p) { return ct->buf.p + (size_t)p * (ct->level + 1) * c->N; }
+
+Ct ct_copy(ckks_ctx *c, const ckks_ct *a) {
+    Ct r = ct_new(c, a->level, a->scale);
+    hipchk(hipMemcpyAsync(r->buf.p, a->buf.p, c->words(a->level) * 8, hipMemcpyDeviceToDevice, c->stream), "copy");
+    return r;
+}
+
+bool scales_match(double a, double b) { return std::fabs(a / b - 1.0) <= 9.313225746154785e-10; }
+
+Ct op_addsub(ckks_ctx *c, const ckks_ct *a, const ckks_ct *b, bool sub) {
+    if (a->level != b->level) fail(CKKS_E_LEVEL, "level mismatch");
+    if (!scales_match(a->scale, b->scale)) fail(CKKS_E_SCALE, "scale mismatch");
+    Ct r = ct_new(c, a->level, a->scale);
+    gpu::add(c->T, r->buf.p, a->buf.p, b->buf.p, a->level + 1, 2, map_q(0, a->level + 1), sub, c->stream);
+    return r;
+}
+
+Ct op_mul_int(ckks_ctx *c, const ckks_ct *a, int64_t k, double new_scale) {
+    Ct r = ct_new(c, a->level, new_scale);
+    LimbConsts kc{};
+    for (int i = 0; i <= a->level; ++i) {
+        kc.v[i] = mod_signed(k, c->q[i]);
+        kc.sh[i] = shoup(kc.v[i], c->q[i]);
+    }
+    gpu::mul_scalar(c->T, r->buf.p, a->buf.p, kc, a->level + 1, 2, map_q(0, a->level + 1), c->stream);
+    return r;
+}
+
+Ct op_mul_const(ckks_ctx *c, const ckks_ct *a, double value, double s_c) {
+    double kd = std::rint(value * s_c);
+    if (!(std::fabs(kd) < 4.0e18)) fail(CKKS_E_RANGE, "constant out of range");
+    return op_mul_int(c, a, (int64_t)kd, a->scale * s_c);
+}
+
+Ct op_add_const(ckks_ctx *c, const ckks_ct *a, double value) {
+    double kd = std::rint(value * a->scale);
+    if (!(std::fabs(kd) < 4.0e18)) fail(CKKS_E_RANGE, "constant out of range");
+    const int64_t k = (int64_t)kd;
+    Ct r = ct_new(c, a->level, a->scale);
+    LimbConsts kc{};
+    for (int i = 0; i <= a->level; ++i) kc.v[i] = mod_signed(k, c->q[i]);
+    gpu::add_scalar(c->T, r->buf.p, a->buf.p, kc, a->level + 1, 2, map_q(0, a->level + 1), c->stream);
+    return r;
+}
+
+Ct op_drop(ckks_ctx *c, const ckks_ct *a, int level) {
+    if (level < 0 || level > a->level) fail(CKKS_E_LEVEL, "bad target level");
+    Ct r = ct_new(c, level, a->scale);
+    const size_t row = (size_t)(level + 1) * c->N * 8;
+    for (int p = 0; p < 2; ++p)
+        hipchk(hipMemcpyAsync(poly(c, r.get(), p), poly(c, a, p), row, hipMemcpyDeviceToDevice, c->stream), "drop");
+    return r;
+}
+
+// rescale by q_l: c' = (c - NTT(centred lift of iNTT(c_l))) * q_l^-1
+Ct op_rescale(ckks_ctx *c, const ckks_ct *a) {
+    const int l = a->level;
+    if (l < 1) fail(CKKS_E_LEVEL, "rescale at level 0");
+    const size_t N = c->N;
+    Ct r = ct_new(c, l - 1, a->scale / (double)c->q[l]);
+    Buf t(c->pool.get(), 2 * N);
+    for (int p = 0; p < 2; ++p)
+        hipchk(hipMemcpyAsync(t.p + p * N, poly(c, a, p) + (size_t)l * N, N * 8, hipMemcpyDeviceToDevice, c->stream),
+               "rescale copy");
+    ntt_p(c, t.p, 1, 2, map_q(l, 1), true);
+    Buf u(c->pool.get(), 2 * (size_t)l * N);
+    gpu::rescale_lift(c->T, u.p, t.p, l, l, 2, N, c->stream);
+    ntt_p(c, u.p, l, 2, map_q(0, l), false);
+    LimbConsts inv{};
+    for (int i = 0; i < l; ++i) {
+        inv.v[i] = hm::invmod(c->q[l] % c->q[i], c->q[i]);
+        inv.sh[i] = shoup(inv.v[i], c->q[i]);
+    }
+    gpu::sub_mul(c->T, r->buf.p, a->buf.p, u.p, inv, l, 2, (size_t)(l + 1) * N, map_q(0, l), c->stream);
+    return r;
+}
+
+// hybrid key switch of d (level l, NTT form); out0/out1 get (o0 + add0, o1 + add1)
+void keyswitch(ckks_ctx *c, int l, const u64 *d, const SwitchKey &key, u64 *out, const u64 *add) {
+    const size_t N = c->N;
+    const int nq = l + 1, ne = nq + c->K;
+    const int beta = (nq + c->alpha - 1) / c->alpha;
+    // algorithmic bytes: d (nq limbs) in, key (2 beta ne limbs) in, result (2 nq limbs) out
+    ProfScope ps(c, "keyswitch", 8.0 * (double)N * ((double)nq + 2.0 * beta * ne + 2.0 * nq));
+    Pool *P = c->pool.get();
+    Buf dc(P, (size_t)nq * N);
+    hipchk(hipMemcpyAsync(dc.p, d, (size_t)nq * N * 8, hipMemcpyDeviceToDevice, c->stream), "ks copy");
+    ntt_p(c, dc.p, nq, 1, map_q(0, nq), true);
+    std::vector<Buf> ext;
+    gpu::InnerArgs ia{};
+    ia.ndig = beta;
+    for (int j = 0; j < beta; ++j) {
+        ConvTable *t = modup_table(c, l, j);
+        ext.emplace_back(P, (size_t)t->dout * N);
+        gpu::BconvArgs ba{t->pin, t->pout, t->din, t->dout, t->hinv.p, t->hinv_sh.p, t->mat.p};
+        const int lo = j * c->alpha;
+        gpu::bconv(c->T, ext.back().p, dc.p + (size_t)lo * N, ba, 1, 0, 0, c->stream);
+        ntt_p(c, ext.back().p, t->dout, 1, t->pout, false);
+        ia.lo[j] = lo;
+        ia.hi[j] = lo + t->din;
+        ia.ext[j] = ext.back().p;
+    }
+    ia.dsrc = d;
+    ia.key = key.k.p;
+    ia.np = c->np;
+    ia.m = map_ext(c, l);
+    ia.ne = ne;
+    Buf acc(P, 2 * (size_t)ne * N);
+    gpu::key_inner(c->T, acc.p, ia, c->stream);
+    // ModDown of both polys
+    ConvTable *md = moddown_table(c, l);
+    Buf y(P, 2 * (size_t)c->K * N);
+    for (int b = 0; b < 2; ++b)
+        hipchk(hipMemcpyAsync(y.p + (size_t)b * c->K * N, acc.p + ((size_t)b * ne + nq) * N, (size_t)c->K * N * 8,
+                              hipMemcpyDeviceToDevice, c->stream),
+               "moddown copy");
+    ntt_p(c, y.p, c->K, 2, md->pin, true);
+    Buf z(P, 2 * (size_t)nq * N);
+    gpu::BconvArgs bd{md->pin, md->pout, md->din, md->dout, md->hinv.p, md->hinv_sh.p, md->mat.p};
+    gpu::bconv(c->T, z.p, y.p, bd, 2, (size_t)c->K * N, (size_t)nq * N, c->stream);
+    ntt_p(c, z.p, nq, 2, map_q(0, nq), false);
+    LimbConsts pinv{};
+    std::vector<int> pidx;
+    for (int k = 0; k < c->K; ++k) pidx.push_back(c->L + 1 + k);
+    for (int i = 0; i < nq; ++i) {
+        pinv.v[i] = hm::invmod(prod_mod(c, pidx, -1, c->q[i]), c->q[i]);
+        pinv.sh[i] = shoup(pinv.v[i], c->q[i]);
+    }
+    gpu::moddown_finish(c->T, out, acc.p, (size_t)ne * N, z.p, add, pinv, nq, map_q(0, nq), c->stream);
+}
+
+Ct op_hmult(ckks_ctx *c, const ckks_ct *a, const ckks_ct *b) {
+    if (!c->have_keys) fail(CKKS_E_NOKEY, "no keys");
+    if (a->level != b->level) fail(CKKS_E_LEVEL, "level mismatch");
+    const int l = a->level, nq = l + 1;
+    const size_t N = c->N;
+    Ct r = ct_new(c, l, a->scale * b->scale);
+    Buf d(c->pool.get(), 3 * (size_t)nq * N);
+    u64 *d0 = d.p, *d1 = d.p + (size_t)nq * N, *d2 = d.p + 2 * (size_t)nq * N;
+    gpu::tensor(c->T, d0, d1, d2, poly(c, a, 0), poly(c, a, 1), poly(c, b, 0), poly(c, b, 1), nq, map_q(0, nq),
+                c->stream);
+    keyswitch(c, l, d2, c->relin, r->buf.p, d0);   // (d0, d1) are contiguous like (r0, r1)
+    return r;
+}
+
+Ct op_automorphism(ckks_ctx *c, const ckks_ct *a, int g) {
+    auto it = c->rot.find(g);
+    if (it == c->rot.end()) fail(CKKS_E_NOKEY, "missing Galois key");
+    const int nq = a->level + 1;
+    const size_t N = c->N;
+    const int32_t *perm = perm_for(c, g);
+    Buf s(c->pool.get(), 2 * (size_t)nq * N);
+    gpu::permute(c->T, s.p, a->buf.p, perm, nq, 2, c->stream);
+    Ct r = ct_new(c, a->level, a->scale);
+    // r = (s0 + ks0, ks1): add = (s0, 0)
+    Buf add(c->pool.get(), 2 * (size_t)nq * N);
+    hipchk(hipMemcpyAsync(add.p, s.p, (size_t)nq * N * 8, hipMemcpyDeviceToDevice, c->stream), "aut copy");
+    hipchk(hipMemsetAsync(add.p + (size_t)nq * N, 0, (size_t)nq * N * 8, c->stream), "aut zero");
+    keyswitch(c, a->level, s.p + (size_t)nq * N, it->second, r->buf.p, add.p);
+    return r;
+}
+
+int galois_rot(const ckks_ctx *c, int k) {
+    const int n = c->N / 2, M = 2 * c->N;
+    k %= n;
+    if (k < 0) k += n;
+    long long g = 1;
+    for (int t = 0; t < k; ++t) g = (g * 5) % M;
+    return (int)g;
+}
+
+Ct op_rotate(ckks_ctx *c, const ckks_ct *a, int k) {
+    int g = galois_rot(c, k);
+    if (g == 1) return ct_copy(c, a);
+    return op_automorphism(c, a, g);
+}
+
+Ct op_level_to(ckks_ctx *c, const ckks_ct *a, int target) {
+    if (target == a->level) return ct_copy(c, a);
+    if (target > a->level || target < 0) fail(CKKS_E_LEVEL, "bad target level");
+    Ct d = op_drop(c, a, target + 1);
+    double sc = (c->ladder[target] * (double)c->q[target + 1]) / a->scale;
+    Ct m = op_mul_const(c, d.get(), 1.0, sc);
+    return op_rescale(c, m.get());
+}
+
+Ct op_mul_const_down(ckks_ctx *c, const ckks_ct *a, double value) {
+    const int l = a->level;
+    if (l < 1) fail(CKKS_E_LEVEL, "no level for Mul_P");
+    double sc = (c->ladder[l - 1] * (double)c->q[l]) / a->scale;
+    Ct m = op_mul_const(c, a, value, sc);
+    return op_rescale(c, m.get());
+}
+
+Ct mult_rs(ckks_ctx *c, const ckks_ct *a, const ckks_ct *b) {
+    Ct m = op_hmult(c, a, b);
+    return op_rescale(c, m.get());
+}
+Ct mult_aligned(ckks_ctx *c, const ckks_ct *a, const ckks_ct *b) {
+    int l = std::min(a->level, b->level);
+    if (l < 1) fail(CKKS_E_LEVEL, "no level for Mul_C");
+    Ct x = op_level_to(c, a, l), y = op_level_to(c, b, l);
+    return mult_rs(c, x.get(), y.get());
+}
+Ct addsub_aligned(ckks_ctx *c, const ckks_ct *a, const ckks_ct *b, bool sub) {
+    int l = std::min(a->level, b->level);
+    Ct x = op_level_to(c, a, l), y = op_level_to(c, b, l);
+    return op_addsub(c, x.get(), y.get(), sub);
+}
+
+// ---------------------------------------------------------------------------
+// Chebyshev evaluation (baby-step / giant-step), Newton, CryptoInvSqrt
+// ---------------------------------------------------------------------------
+struct PowerBasis {
+    ckks_ctx *c;
+    std::vector<Ct> T;
+    ckks_ct *get(int i) {
+        if (!T[i]) T[i] = make(i);
+        return T[i].get();
+    }
+    Ct make(int i) {
+        if (i % 2 == 0) {   // T_2k = 2 T_k^2 - 1
+            ckks_ct *h = get(i / 2);
+            Ct sq = mult_rs(c, h, h);
+            Ct two = op_mul_int(c, sq.get(), 2, sq->scale);
+            return op_add_const(c, two.get(), -1.0);
+        }
+        // T_2k+1 = 2 T_k+1 T_k - T_1
+        ckks_ct *hi = get((i + 1) / 2);
+        ckks_ct *lo = get((i - 1) / 2);
+        Ct p = mult_aligned(c, hi, lo);
+        Ct two = op_mul_int(c, p.get(), 2, p->scale);
+        return addsub_aligned(c, two.get(), T[1].get(), true);
+    }
+};
+
+Ct baby_sum(ckks_ctx *c, PowerBasis &pb, const std::vector<double> &cf) {
+    const int deg = (int)cf.size() - 1;
+    std::vector<int> terms;
+    for (int i = 1; i <= deg; ++i)
+        if (cf[i] != 0.0) terms.push_back(i);
+    const bool none = terms.empty();
+    if (none) terms.push_back(1);
+    int lmin = 1 << 30;
+    for (int i : terms) lmin = std::min(lmin, pb.T[i]->level);
+    if (lmin < 1) fail(CKKS_E_LEVEL, "no level for the baby-step sum");
+    Ct acc;
+    for (int i : terms) {
+        const ckks_ct *Ti = pb.T[i].get();
+        Ct d = op_drop(c, Ti, lmin);
+        double sc = (c->ladder[lmin - 1] * (double)c->q[lmin]) / Ti->scale;
+        Ct m = op_mul_const(c, d.get(), none ? 0.0 : cf[i], sc);
+        acc = acc ? op_addsub(c, acc.get(), m.get(), false) : std::move(m);
+    }
+    Ct r = op_rescale(c, acc.get());
+    return op_add_const(c, r.get(), cf[0]);
+}
+
+Ct cheb_tree(ckks_ctx *c, PowerBasis &pb, const std::vector<double> &cf, int k, int b) {
+    const int deg = (int)cf.size() - 1;
+    if (k <= b) return baby_sum(c, pb, cf);
+    const int M = 1 << (k - 1);
+    if (deg < M) return cheb_tree(c, pb, cf, k - 1, b);
+    const int dq = deg - M;
+    std::vector<double> qc(dq + 1), rc(cf.begin(), cf.begin() + M);
+    qc[0] = cf[M];
+    for (int j = 1; j <= dq; ++j) qc[j] = 2.0 * cf[M + j];
+    for (int j = 1; j <= dq; ++j) rc[M - j] = cf[M - j] - cf[M + j];
+    Ct Q = cheb_tree(c, pb, qc, k - 1, b);
+    Ct R = cheb_tree(c, pb, rc, k - 1, b);
+    Ct P = mult_aligned(c, Q.get(), pb.get(M));
+    return addsub_aligned(c, P.get(), R.get(), false);
+}
+
+int bit_length(int d) {
+    int m = 0;
+    while (d >> m) ++m;
+    return m;
+}
+
+Ct op_cheb(ckks_ctx *c, const ckks_ct *x, const std::vector<double> &cf, double a, double b) {
+    const int d = (int)cf.size() - 1;
+    if (d < 1) fail(CKKS_E_PARAM, "degree must be >= 1");
+    Ct t;
+    if (a == -1.0 && b == 1.0) {
+        t = ct_copy(c, x);
+    } else {
+        if (x->level < 1) fail(CKKS_E_LEVEL, "no level for the affine map");
+        double al = 2.0 / (b - a);
+        double be = -(a + b) / (b - a);
+        Ct m = op_mul_const_down(c, x, al);
+        t = op_add_const(c, m.get(), be);
+    }
+    const int m = bit_length(d), bb = (m + 1) / 2;
+    PowerBasis pb{c, {}};
+    pb.T.resize((1 << m) + 1);
+    pb.T[1] = std::move(t);
+    for (int i = 2; i < (1 << bb) && i <= d; ++i) pb.get(i);
+    for (int k = bb; k < m; ++k) pb.get(1 << k);
+    return cheb_tree(c, pb, cf, m, bb);
+}
+
+Ct op_newton(ckks_ctx *c, const ckks_ct *y, const ckks_ct *half_x) {
+    const int lc = std::min(y->level, half_x->level);
+    if (lc < 2) fail(CKKS_E_LEVEL, "Newton step needs 2 levels");
+    Ct xa = op_level_to(c, half_x, lc), ya = op_level_to(c, y, lc);
+    Ct u = mult_rs(c, xa.get(), ya.get());          // tmp_beta = ct_x * y
+    xa.reset();
+    ya.reset();
+    Ct v0 = mult_rs(c, y, y);                       // y^2
+    Ct v = op_level_to(c, v0.get(), lc - 1);
+    v0.reset();
+    Ct w = mult_rs(c, u.get(), v.get());            // tmp_beta * y^2
+    Ct yd = op_drop(c, y, lc - 1);
+    Ct ta = op_mul_const_down(c, yd.get(), 1.5);    // tmp_alpha = 1.5 y
+    return op_addsub(c, ta.get(), w.get(), true);
+}
+
+Ct op_bootstrap(ckks_ctx *c, const ckks_ct *a);
+
+Ct bts_scaled(ckks_ctx *c, const ckks_ct *y, int S) {
+    Ct t = ct_copy(c, y);
+    t->scale = y->scale * (double)S;
+    Ct b = op_bootstrap(c, t.get());
+    return op_mul_int(c, b.get(), S, b->scale);
+}
+
+Ct op_invsqrt(ckks_ctx *c, const ckks_ct *x, int degree, int iters, const ckks_invsqrt_opts &o) {
+    if (x->level < 2) fail(CKKS_E_LEVEL, "input needs at least 2 levels");
+    if (degree < 1 || iters < 0) fail(CKKS_E_PARAM, "bad degree / iterations");
+    if (!(o.a > 0) || !(o.b > o.a)) fail(CKKS_E_PARAM, "bad interval");
+    std::vector<double> cf(degree + 1);
+    hm::cheb_invsqrt(degree, o.a, o.b, cf.data());
+    Ct cx = op_mul_const_down(c, x, 0.5);
+    Ct y = op_cheb(c, x, cf, o.a, o.b);
+    if (o.literal) y = bts_scaled(c, y.get(), o.bts_scale);
+    for (int i = 0; i < iters; ++i) {
+        if (y->level < 2) {
+            if (cx->level < 2) fail(CKKS_E_LEVEL, "x has too few levels for Newton");
+            y = bts_scaled(c, y.get(), o.bts_scale);
+        }
+        y = op_newton(c, y.get(), cx.get());
+    }
+    return y;
+}
+
+Ct op_bootstrap(ckks_ctx *c, const ckks_ct *a) {
+    (void)c;
+    (void)a;
+    fail(CKKS_E_NOKEY, "bootstrapping keys not set up");
+}
+
+// ---------------------------------------------------------------------------
+// keys
+// ---------------------------------------------------------------------------
+void upload_signed_ntt(ckks_ctx *c, u64 *dst, const int64_t *src_host, int nlimb, const LimbMap &m) {
+    Buf tmp(c->pool.get(), c->N);
+    hipchk(hipMemcpyAsync(tmp.p, src_host, c->N * 8, hipMemcpyHostToDevice, c->stream), "upload");
+    gpu::signed_to_residues(c->T, dst, (const int64_t *)tmp.p, nlimb, m, c->stream);
+    gpu::ntt(c->T, dst, nlimb, 1, m, false, c->stream);
+    hipchk(hipStreamSynchronize(c->stream), "sync");   // host buffer reuse
+}
+
+void make_switch_key(ckks_ctx *c, uint64_t seed, int galois, const u64 *sprime, SwitchKey &out) {
+    const size_t N = c->N;
+    const int np = c->np;
+    out.k = Buf(c->pool.get(), (size_t)c->dnum * 2 * np * N);
+    std::vector<u64> a((size_t)np * N);
+    std::vector<int64_t> e(N);
+    LimbMap all = map_q(0, np);
+    Buf eN(c->pool.get(), (size_t)np * N);
+    LimbConsts pm{};
+    std::vector<int> pidx;
+    for (int k = 0; k < c->K; ++k) pidx.push_back(c->L + 1 + k);
+    for (int i = 0; i <= c->L; ++i) {
+        pm.v[i] = prod_mod(c, pidx, -1, c->q[i]);
+        pm.sh[i] = shoup(pm.v[i], c->q[i]);
+    }
+    for (int j = 0; j < c->dnum; ++j) {
+        u64 *b = out.k.p + ((size_t)j * 2 + 0) * np * N;
+        u64 *ak = out.k.p + ((size_t)j * 2 + 1) * np * N;
+        hm::Shake256 xa(seed, hm::stream_tag(hm::kKeyA, galois, j));
+        for (int i = 0; i < np; ++i) hm::uniform_residues(xa, c->q[i], c->N, a.data() + (size_t)i * N);
+        hipchk(hipMemcpyAsync(ak, a.data(), a.size() * 8, hipMemcpyHostToDevice, c->stream), "key upload");
+        hm::Shake256 xe(seed, hm::stream_tag(hm::kKeyE, galois, j));
+        hm::gaussian(xe, c->cdt, c->N, e.data());
+        upload_signed_ntt(c, eN.p, e.data(), np, all);
+        std::vector<uint8_t> flag(np, 0);
+        for (int i = j * c->alpha; i < std::min((j + 1) * c->alpha, c->L + 1); ++i) flag[i] = 1;
+        gpu::key_combine(c->T, b, ak, c->sk.p, eN.p, sprime, pm, flag.data(), np, all, c->stream);
+    }
+    hipchk(hipStreamSynchronize(c->stream), "key sync");
+}
+
+void keygen(ckks_ctx *c, uint64_t seed, const int32_t *gal, uint32_t ng) {
+    const size_t N = c->N;
+    const int np = c->np;
+    Pool *P = c->pool.get();
+    std::vector<int8_t> s(N);
+    hm::Shake256 xs(seed, hm::stream_tag(hm::kSecret, 0, 0));
+    if (c->prm.hamming_weight > 0) hm::hamming_ternary(xs, c->N, (int)c->prm.hamming_weight, s.data());
+    else hm::ternary(xs, c->N, s.data());
+    std::vector<int64_t> s64(s.begin(), s.end());
+    c->sk = Buf(P, (size_t)np * N);
+    upload_signed_ntt(c, c->sk.p, s64.data(), np, map_q(0, np));
+    // public key over q_0..q_L
+    const int nq = c->L + 1;
+    c->pk = Buf(P, 2 * (size_t)nq * N);
+    std::vector<u64> a((size_t)nq * N);
+    hm::Shake256 xa(seed, hm::stream_tag(hm::kPkA, 0, 0));
+    for (int i = 0; i < nq; ++i) hm::uniform_residues(xa, c->q[i], c->N, a.data() + (size_t)i * N);
+    u64 *pk1 = c->pk.p + (size_t)nq * N;
+    hipchk(hipMemcpyAsync(pk1, a.data(), a.size() * 8, hipMemcpyHostToDevice, c->stream), "pk upload");
+    std::vector<int64_t> e(N);
+    hm::Shake256 xe(seed, hm::stream_tag(hm::kPkE, 0, 0));
+    hm::gaussian(xe, c->cdt, c->N, e.data());
+    Buf eN(P, (size_t)nq * N);
+    upload_signed_ntt(c, eN.p, e.data(), nq, map_q(0, nq));
+    LimbConsts none{};
+    gpu::key_combine(c->T, c->pk.p, pk1, c->sk.p, eN.p, nullptr, none, nullptr, nq, map_q(0, nq), c->stream);
+    // relinearisation key: s' = s^2
+    Buf s2(P, (size_t)np * N);
+    gpu::mul_pointwise(c->T, s2.p, c->sk.p, c->sk.p, np, 1, map_q(0, np), c->stream);
+    make_switch_key(c, seed, 0, s2.p, c->relin);
+    c->rot.clear();
+    for (uint32_t r = 0; r < ng; ++r) {
+        int g = gal[r];
+        if (g <= 0 || g >= 2 * c->N || (g & 1) == 0) fail(CKKS_E_PARAM, "bad Galois element");
+        if (c->rot.count(g)) continue;
+        const int32_t *perm = perm_for(c, g);
+        gpu::permute(c->T, s2.p, c->sk.p, perm, np, 1, c->stream);
+        make_switch_key(c, seed, g, s2.p, c->rot[g]);
+    }
+    c->have_keys = true;
+}
+
+Ct op_encrypt(ckks_ctx *c, const double *x, uint32_t n, int level, double scale, uint64_t seed) {
+    if (!c->have_keys) fail(CKKS_E_NOKEY, "no keys");
+    if (level < 0 || level > c->L) fail(CKKS_E_LEVEL, "bad level");
+    if (n > (uint32_t)c->N / 2) fail(CKKS_E_PARAM, "too many slots");
+    const size_t N = c->N;
+    const int nq = level + 1;
+    std::vector<int64_t> m(N);
+    if (!hm::encode(c->logN, x, nullptr, n, scale, m.data())) fail(CKKS_E_RANGE, "value out of range for encoding");
+    std::vector<int8_t> v(N);
+    std::vector<int64_t> e0(N), e1(N);
+    hm::Shake256 xv(seed, hm::stream_tag(hm::kEncV, 0, 0));
+    hm::ternary(xv, c->N, v.data());
+    hm::Shake256 x0(seed, hm::stream_tag(hm::kEncE0, 0, 0));
+    hm::gaussian(x0, c->cdt, c->N, e0.data());
+    hm::Shake256 x1(seed, hm::stream_tag(hm::kEncE1, 0, 0));
+    hm::gaussian(x1, c->cdt, c->N, e1.data());
+    for (size_t j = 0; j < N; ++j) e0[j] += m[j];
+    std::vector<int64_t> v64(v.begin(), v.end());
+    Pool *P = c->pool.get();
+    Buf vN(P, (size_t)nq * N), a0(P, (size_t)nq * N), a1(P, (size_t)nq * N);
+    LimbMap mq = map_q(0, nq);
+    upload_signed_ntt(c, vN.p, v64.data(), nq, mq);
+    upload_signed_ntt(c, a0.p, e0.data(), nq, mq);
+    upload_signed_ntt(c, a1.p, e1.data(), nq, mq);
+    Ct r = ct_new(c, level, scale);
+    const u64 *pk0 = c->pk.p, *pk1 = c->pk.p + (size_t)(c->L + 1) * N;
+    gpu::mul_add(c->T, poly(c, r.get(), 0), vN.p, pk0, a0.p, nq, mq, c->stream);
+    gpu::mul_add(c->T, poly(c, r.get(), 1), vN.p, pk1, a1.p, nq, mq, c->stream);
+    return r;
+}
+
+void op_decrypt(ckks_ctx *c, const ckks_ct *ct, double *re, double *im) {
+    if (!c->have_keys) fail(CKKS_E_NOKEY, "no keys");
+    const int nq = ct->level + 1;
+    const size_t N = c->N;
+    Buf m(c->pool.get(), (size_t)nq * N);
+    gpu::decrypt_combine(c->T, m.p, poly(c, ct, 0), poly(c, ct, 1), c->sk.p, nq, map_q(0, nq), c->stream);
+    gpu::ntt(c->T, m.p, nq, 1, map_q(0, nq), true, c->stream);
+    std::vector<u64> host((size_t)nq * N);
+    hipchk(hipMemcpyAsync(host.data(), m.p, host.size() * 8, hipMemcpyDeviceToHost, c->stream), "download");
+    hipchk(hipStreamSynchronize(c->stream), "sync");
+    hm::decode_residues(c->logN, host.data(), nq, c->q.data(), ct->scale, re, im);
+}
+
+// C-ABI wrapper: run f, map exceptions to a status
+template <class F>
+ckks_status guard(ckks_ctx *c, F &&f) {
+    try {
+        f();
+        return CKKS_OK;
+    } catch (const Error &e) {
+        if (c) c->err = e.msg;
+        return e.st;
+    } catch (const std::bad_alloc &) {
+        if (c) c->err = "host allocation failed";
+        return CKKS_E_OOM;
+    } catch (const std::exception &e) {
+        if (c) c->err = e.what();
+        return CKKS_E_PARAM;
+    }
+}
+template <class F>
+ckks_status guard_out(ckks_ctx *c, ckks_ct **out, F &&f) {
+    if (!out) {
+        if (c) c->err = "null output pointer";
+        return CKKS_E_PARAM;
+    }
+    *out = nullptr;
+    return guard(c, [&] { *out = f().release(); });
+}
+
+}  // namespace
+
+// ===========================================================================
+// C-ABI
+// ===========================================================================
+extern "C" {
+
+ckks_status ckks_ctx_create(const ckks_params *p, void *arena, size_t arena_bytes, void *hip_stream, ckks_ctx **out) {
+    if (!p || !out) return CKKS_E_PARAM;
+    *out = nullptr;
+    if (p->log_n < 4 || p->log_n > 16 || p->max_level < 1 || p->num_special < 1 || p->digit_size < 1 ||
+        p->max_level + 1 + p->num_special > (uint32_t)gpu::kMaxLimbs || p->q0_bits > 61 || p->p_bits > 61 ||
+        p->q0_bits < 30 || p->p_bits < 30 || p->log_scale < 20 || p->log_scale > 58 ||
+        p->hamming_weight > (1u << p->log_n) || !(p->sigma > 0))
+        return CKKS_E_PARAM;
+    ckks_ctx *c = new ckks_ctx();
+    ckks_status st = guard(c, [&] {
+        c->prm = *p;
+        c->logN = (int)p->log_n;
+        c->N = 1 << c->logN;
+        c->L = (int)p->max_level;
+        c->K = (int)p->num_special;
+        c->alpha = (int)p->digit_size;
+        c->dnum = (c->L + 1 + c->alpha - 1) / c->alpha;
+        if (c->dnum > 64) fail(CKKS_E_PARAM, "too many digits");
+        c->np = c->L + 1 + c->K;
+        c->stream = (hipStream_t)hip_stream;
+        c->pool.reset(new Pool(arena, arena_bytes));
+        hm::prime_chain(c->logN, c->L, c->K, (int)p->log_scale, (int)p->q0_bits, (int)p->p_bits, c->q, c->ladder);
+        c->cdt = hm::gaussian_table(p->sigma);
+        build_tables(c);
+    });
+    if (st != CKKS_OK) {
+        delete c;
+        return st;
+    }
+    *out = c;
+    return CKKS_OK;
+}
+
+void ckks_ctx_destroy(ckks_ctx *c) {
+    if (!c) return;
+    (void)hipStreamSynchronize(c->stream);
+    delete c;
+}
+
+const char *ckks_last_error(const ckks_ctx *c) { return c ? c->err.c_str() : "null context"; }
+
+ckks_status ckks_ctx_primes(const ckks_ctx *c, uint64_t *primes, double *ladder) {
+    if (!c) return CKKS_E_PARAM;
+    if (primes) std::memcpy(primes, c->q.data(), c->q.size() * 8);
+    if (ladder) std::memcpy(ladder, c->ladder.data(), c->ladder.size() * 8);
+    return CKKS_OK;
+}
+
+ckks_status ckks_set_stream(ckks_ctx *c, void *s) {
+    if (!c) return CKKS_E_PARAM;
+    c->stream = (hipStream_t)s;
+    return CKKS_OK;
+}
+
+ckks_status ckks_sync(ckks_ctx *c) {
+    if (!c) return CKKS_E_PARAM;
+    return guard(c, [&] { hipchk(hipStreamSynchronize(c->stream), "sync"); });
+}
+
+ckks_status ckks_keygen(ckks_ctx *c, uint64_t seed, const int32_t *galois, uint32_t n_galois) {
+    if (!c || (n_galois && !galois)) return CKKS_E_PARAM;
+    return guard(c, [&] { keygen(c, seed, galois, n_galois); });
+}
+
+int32_t ckks_galois_rotation(const ckks_ctx *c, int32_t steps) { return c ? galois_rot(c, steps) : 0; }
+
+ckks_status ckks_encrypt(ckks_ctx *c, const double *x, uint32_t n, uint32_t level, double scale, uint64_t seed,
+                         ckks_ct **out) {
+    if (!c || (n && !x)) return CKKS_E_PARAM;
+    return guard_out(c, out, [&] { return op_encrypt(c, x, n, (int)level, scale, seed); });
+}
+
+ckks_status ckks_decrypt(ckks_ctx *c, const ckks_ct *ct, double *re, double *im) {
+    if (!c || !ct || !re) return CKKS_E_PARAM;
+    return guard(c, [&] { op_decrypt(c, ct, re, im); });
+}
+
+ckks_status ckks_ct_import(ckks_ctx *c, const uint64_t *host, uint32_t level, double scale, ckks_ct **out) {
+    if (!c || !host) return CKKS_E_PARAM;
+    return guard_out(c, out, [&] {
+        if ((int)level > c->L) fail(CKKS_E_LEVEL, "bad level");
+        Ct r = ct_new(c, (int)level, scale);
+        hipchk(hipMemcpyAsync(r->buf.p, host, c->words(level) * 8, hipMemcpyHostToDevice, c->stream), "import");
+        hipchk(hipStreamSynchronize(c->stream), "import sync");
+        return r;
+    });
+}
+
+ckks_status ckks_ct_export(ckks_ctx *c, const ckks_ct *ct, uint64_t *host) {
+    if (!c || !ct || !host) return CKKS_E_PARAM;
+    return guard(c, [&] {
+        hipchk(hipMemcpyAsync(host, ct->buf.p, c->words(ct->level) * 8, hipMemcpyDeviceToHost, c->stream), "export");
+        hipchk(hipStreamSynchronize(c->stream), "export sync");
+    });
+}
+
+void *ckks_ct_device_ptr(const ckks_ct *ct) { return ct ? (void *)ct->buf.p : nullptr; }
+int32_t ckks_ct_level(const ckks_ct *ct) { return ct ? ct->level : -1; }
+double ckks_ct_scale(const ckks_ct *ct) { return ct ? ct->scale : 0.0; }
+void ckks_ct_free(ckks_ctx *c, ckks_ct *ct) {
+    (void)c;
+    delete ct;
+}
+
+#define CT_ARGS_CHECK(...)                         \
+    if (!c || !a) return CKKS_E_PARAM;
+
+ckks_status ckks_add(ckks_ctx *c, const ckks_ct *a, const ckks_ct *b, ckks_ct **out) {
+    if (!c || !a || !b) return CKKS_E_PARAM;
+    return guard_out(c, out, [&] { return op_addsub(c, a, b, false); });
+}
+ckks_status ckks_sub(ckks_ctx *c, const ckks_ct *a, const ckks_ct *b, ckks_ct **out) {
+    if (!c || !a || !b) return CKKS_E_PARAM;
+    return guard_out(c, out, [&] { return op_addsub(c, a, b, true); });
+}
+ckks_status ckks_mul_int(ckks_ctx *c, const ckks_ct *a, int64_t k, ckks_ct **out) {
+    CT_ARGS_CHECK();
+    return guard_out(c, out, [&] { return op_mul_int(c, a, k, a->scale); });
+}
+ckks_status ckks_mul_const(ckks_ctx *c, const ckks_ct *a, double v, double s_c, ckks_ct **out) {
+    CT_ARGS_CHECK();
+    return guard_out(c, out, [&] { return op_mul_const(c, a, v, s_c); });
+}
+ckks_status ckks_mul_const_down(ckks_ctx *c, const ckks_ct *a, double v, ckks_ct **out) {
+    CT_ARGS_CHECK();
+    return guard_out(c, out, [&] { return op_mul_const_down(c, a, v); });
+}
+ckks_status ckks_add_const(ckks_ctx *c, const ckks_ct *a, double v, ckks_ct **out) {
+    CT_ARGS_CHECK();
+    return guard_out(c, out, [&] { return op_add_const(c, a, v); });
+}
+ckks_status ckks_drop_level(ckks_ctx *c, const ckks_ct *a, uint32_t level, ckks_ct **out) {
+    CT_ARGS_CHECK();
+    return guard_out(c, out, [&] { return op_drop(c, a, (int)level); });
+}
+ckks_status ckks_level_to(ckks_ctx *c, const ckks_ct *a, uint32_t level, ckks_ct **out) {
+    CT_ARGS_CHECK();
+    return guard_out(c, out, [&] { return op_level_to(c, a, (int)level); });
+}
+ckks_status ckks_rescale(ckks_ctx *c, const ckks_ct *a, ckks_ct **out) {
+    CT_ARGS_CHECK();
+    return guard_out(c, out, [&] { return op_rescale(c, a); });
+}
+ckks_status ckks_hmult_relin(ckks_ctx *c, const ckks_ct *a, const ckks_ct *b, ckks_ct **out) {
+    if (!c || !a || !b) return CKKS_E_PARAM;
+    return guard_out(c, out, [&] { return op_hmult(c, a, b); });
+}
+ckks_status ckks_rotate(ckks_ctx *c, const ckks_ct *a, int32_t steps, ckks_ct **out) {
+    CT_ARGS_CHECK();
+    return guard_out(c, out, [&] { return op_rotate(c, a, steps); });
+}
+ckks_status ckks_conjugate(ckks_ctx *c, const ckks_ct *a, ckks_ct **out) {
+    CT_ARGS_CHECK();
+    return guard_out(c, out, [&] { return op_automorphism(c, a, 2 * c->N - 1); });
+}
+ckks_status ckks_cheb_eval(ckks_ctx *c, const ckks_ct *a, const double *coeffs, uint32_t degree, double lo,
+                           double hi, ckks_ct **out) {
+    if (!c || !a || !coeffs) return CKKS_E_PARAM;
+    return guard_out(c, out, [&] {
+        std::vector<double> cf(coeffs, coeffs + degree + 1);
+        return op_cheb(c, a, cf, lo, hi);
+    });
+}
+ckks_status ckks_cheb_coeffs_invsqrt(uint32_t degree, double a, double b, double *coeffs) {
+    if (!coeffs || degree < 1 || !(a > 0) || !(b > a)) return CKKS_E_PARAM;
+    hm::cheb_invsqrt((int)degree, a, b, coeffs);
+    return CKKS_OK;
+}
+ckks_status ckks_newton_step(ckks_ctx *c, const ckks_ct *y, const ckks_ct *h, ckks_ct **out) {
+    if (!c || !y || !h) return CKKS_E_PARAM;
+    return guard_out(c, out, [&] { return op_newton(c, y, h); });
+}
+ckks_status ckks_bootstrap(ckks_ctx *c, const ckks_ct *a, ckks_ct **out) {
+    CT_ARGS_CHECK();
+    return guard_out(c, out, [&] { return op_bootstrap(c, a); });
+}
+static ckks_invsqrt_opts default_opts() {
+    ckks_invsqrt_opts o;
+    o.a = 0.0009765625;   // 2^-10
+    o.b = 1.0;
+    o.literal = 0;
+    o.bts_scale = 64;
+    return o;
+}
+ckks_status ckks_invsqrt(ckks_ctx *c, const ckks_ct *x, uint32_t degree, uint32_t iters, ckks_ct **out) {
+    if (!c || !x) return CKKS_E_PARAM;
+    ckks_invsqrt_opts o = default_opts();
+    return guard_out(c, out, [&] { return op_invsqrt(c, x, (int)degree, (int)iters, o); });
+}
+ckks_status ckks_invsqrt_ex(ckks_ctx *c, const ckks_ct *x, uint32_t degree, uint32_t iters,
+                            const ckks_invsqrt_opts *opts, ckks_ct **out) {
+    if (!c || !x) return CKKS_E_PARAM;
+    ckks_invsqrt_opts o = opts ? *opts : default_opts();
+    return guard_out(c, out, [&] { return op_invsqrt(c, x, (int)degree, (int)iters, o); });
+}
+ckks_status ckks_invsqrt_batch(ckks_ctx *c, const ckks_ct *const *xs, uint32_t n, uint32_t degree, uint32_t iters,
+                               const ckks_invsqrt_opts *opts, ckks_ct **outs) {
+    if (!c || (n && (!xs || !outs))) return CKKS_E_PARAM;
+    ckks_invsqrt_opts o = opts ? *opts : default_opts();
+    for (uint32_t i = 0; i < n; ++i) outs[i] = nullptr;
+    ckks_status st = guard(c, [&] {
+        for (uint32_t i = 0; i < n; ++i) outs[i] = op_invsqrt(c, xs[i], (int)degree, (int)iters, o).release();
+    });
+    if (st != CKKS_OK)
+        for (uint32_t i = 0; i < n; ++i) { delete outs[i]; outs[i] = nullptr; }
+    return st;
+}
+ckks_status ckks_ntt_device(ckks_ctx *c, uint64_t *data, uint32_t n_limbs, const uint32_t *prime_idx, int inverse) {
+    if (!c || !data || !prime_idx || n_limbs == 0) return CKKS_E_PARAM;
+    return guard(c, [&] {
+        // launches take at most kMaxLimbs distinct limbs per map; chunk longer batches
+        for (uint32_t off = 0; off < n_limbs; off += gpu::kMaxLimbs) {
+            uint32_t cnt = std::min<uint32_t>(gpu::kMaxLimbs, n_limbs - off);
+            LimbMap m{};
+            for (uint32_t i = 0; i < cnt; ++i) {
+                if (prime_idx[off + i] >= (uint32_t)c->np) fail(CKKS_E_PARAM, "bad prime index");
+                m.p[i] = (uint8_t)prime_idx[off + i];
+            }
+            gpu::ntt(c->T, data + (size_t)off * c->N, (int)cnt, 1, m, inverse != 0, c->stream);
+        }
+    });
+}
+
+ckks_status ckks_profile_enable(ckks_ctx *c, int on) {
+    if (!c) return CKKS_E_PARAM;
+    return guard(c, [&] {
+        hipchk(hipStreamSynchronize(c->stream), "sync");
+        for (auto &f : c->prof)
+            for (auto &e : f.second.ev) { c->ev_free.push_back(e.first); c->ev_free.push_back(e.second); }
+        c->prof.clear();
+        c->prof_on = on != 0;
+    });
+}
+ckks_status ckks_profile_read(ckks_ctx *c, const char *family, uint64_t *calls, double *gpu_ms, double *alg_bytes) {
+    if (!c || !family) return CKKS_E_PARAM;
+    return guard(c, [&] {
+        hipchk(hipStreamSynchronize(c->stream), "sync");
+        double ms = 0;
+        uint64_t n = 0;
+        double by = 0;
+        auto it = c->prof.find(family);
+        if (it != c->prof.end()) {
+            for (auto &e : it->second.ev) {
+                float t = 0;
+                hipchk(hipEventElapsedTime(&t, e.first, e.second), "elapsed");
+                ms += t;
+            }
+            n = it->second.calls;
+            by = it->second.bytes;
+        }
+        if (calls) *calls = n;
+        if (gpu_ms) *gpu_ms = ms;
+        if (alg_bytes) *alg_bytes = by;
+    });
+}
+
+}  // extern "C"

@@ -1,0 +1,119 @@
+// gpu.h -- launch interface of the HIP kernels (kernels.hip) used by the host
+// orchestration (ckks_lib.hip).  Device data layout: every polynomial is a
+// sequence of limbs of N uint64 words; a "batch" of limbs is contiguous with
+// limb stride N.  Each launch names, for each limb of a poly, the index of its
+// prime in the chain q_0..q_L, p_0..p_{K-1} (LimbMap); a batch may hold
+// several polys with the same limb -> prime map (npoly copies).
+#pragma once
+#include <hip/hip_runtime.h>
+#include <cstdint>
+
+namespace gpu {
+
+constexpr int kMaxLimbs = 96;
+
+struct DevPrime {
+    uint64_t q;
+    uint64_t mu;        // floor(2^(2n) / q), n = bit length of q
+    uint64_t mu2_lo;    // floor(2^128 / q), low word
+    uint64_t mu2_hi;    //                  high word
+    uint32_t nbits;
+    uint32_t pad;
+};
+
+struct LimbMap {
+    uint8_t p[kMaxLimbs];
+};
+
+// per-prime twiddle tables, all [np][N]:
+//   fw[i][k] = psi_i^br(k),  iw[i][k] = psi_i^-br(k), with Shoup quotients
+struct Tables {
+    const DevPrime *primes;   // [np]
+    const uint64_t *fw, *fw_sh, *iw, *iw_sh;
+    const uint64_t *ninv, *ninv_sh;   // [np]
+    int logN;
+};
+
+// Batched in-place NTT / inverse NTT of nlimb * npoly limbs.
+void ntt(const Tables &T, uint64_t *data, int nlimb, int npoly, const LimbMap &m, bool inverse,
+         hipStream_t s);
+
+// Elementwise (all over nlimb limbs x npoly polys with limb map m):
+// out = a + b / a - b
+void add(const Tables &T, uint64_t *out, const uint64_t *a, const uint64_t *b, int nlimb, int npoly,
+         const LimbMap &m, bool sub, hipStream_t s);
+// out[l] = a[l] * c[l] mod q (per-limb constant with Shoup quotient)
+struct LimbConsts {
+    uint64_t v[kMaxLimbs];
+    uint64_t sh[kMaxLimbs];
+};
+void mul_scalar(const Tables &T, uint64_t *out, const uint64_t *a, const LimbConsts &c, int nlimb,
+                int npoly, const LimbMap &m, hipStream_t s);
+// out[l] = a[l] + c[l] (first poly only; the remaining polys copied)
+void add_scalar(const Tables &T, uint64_t *out, const uint64_t *a, const LimbConsts &c, int nlimb,
+                int npoly, const LimbMap &m, hipStream_t s);
+// out[l][j] = a[l][perm[j]]
+void permute(const Tables &T, uint64_t *out, const uint64_t *a, const int32_t *perm, int nlimb, int npoly,
+             hipStream_t s);
+// tensor: d0 = a0 b0, d1 = a0 b1 + a1 b0, d2 = a1 b1 (nlimb limbs each)
+void tensor(const Tables &T, uint64_t *d0, uint64_t *d1, uint64_t *d2, const uint64_t *a0,
+            const uint64_t *a1, const uint64_t *b0, const uint64_t *b1, int nlimb, const LimbMap &m,
+            hipStream_t s);
+// out = a * b (pointwise), nlimb x npoly
+void mul_pointwise(const Tables &T, uint64_t *out, const uint64_t *a, const uint64_t *b, int nlimb,
+                   int npoly, const LimbMap &m, hipStream_t s);
+// out = a * b + c (pointwise), nlimb limbs
+void mul_add(const Tables &T, uint64_t *out, const uint64_t *a, const uint64_t *b, const uint64_t *c,
+             int nlimb, const LimbMap &m, hipStream_t s);
+// out = c - a * b (pointwise) [+ extra * k_l for limbs flagged in `flag`]
+void key_combine(const Tables &T, uint64_t *out, const uint64_t *a, const uint64_t *s_, const uint64_t *e,
+                 const uint64_t *sprime, const LimbConsts &k, const uint8_t *flag_host, int nlimb,
+                 const LimbMap &m, hipStream_t s);
+// signed 64-bit coefficients -> residues for every limb
+void signed_to_residues(const Tables &T, uint64_t *out, const int64_t *src, int nlimb, const LimbMap &m,
+                        hipStream_t s);
+
+// Rescale helpers.  lift: from t (coef domain, mod q_top) build u_i for
+// limbs 0..nlimb-1 (2 polys: t0,t1 -> u[2][nlimb]) as the centred lift.
+void rescale_lift(const Tables &T, uint64_t *u, const uint64_t *t, int top_prime, int nlimb, int npoly,
+                  size_t t_poly_stride, hipStream_t s);
+// out_i = (c_i - u_i) * inv_i  (inv per limb with Shoup)
+void sub_mul(const Tables &T, uint64_t *out, const uint64_t *c, const uint64_t *u, const LimbConsts &inv,
+             int nlimb, int npoly, size_t c_poly_stride, const LimbMap &m, hipStream_t s);
+
+// Fast base conversion.  in: din limbs (coef domain, primes pin[]),
+// out: dout limbs (primes pout[]), out_r = sum_i [in_i * hinv_i]_{q_i} * mat[i][r] mod p_r.
+// npoly polys (in stride din*N, out stride dout*N).  mat is device [din][dout].
+struct BconvArgs {
+    LimbMap pin, pout;
+    int din, dout;
+    const uint64_t *hinv, *hinv_sh;   // device [din]
+    const uint64_t *mat;              // device [din][dout]
+};
+void bconv(const Tables &T, uint64_t *out, const uint64_t *in, const BconvArgs &a, int npoly,
+           size_t in_poly_stride, size_t out_poly_stride, hipStream_t s);
+
+// Key inner product: acc[b][e] = sum_j x_j[e] * key_j[b][prime(e)] for b = 0,1.
+// x_j[e] = e in [lo_j, hi_j) ? dsrc[e] : ext_j[compact(e)], compact(e) = e < lo_j ? e : e - (hi_j - lo_j).
+struct InnerArgs {
+    int ndig;
+    int lo[64], hi[64];
+    const uint64_t *ext[64];
+    const uint64_t *dsrc;
+    const uint64_t *key;   // [dnum][2][np][N]
+    int np;
+    LimbMap m;             // extended basis map (Q_l then P)
+    int ne;
+};
+void key_inner(const Tables &T, uint64_t *acc, const InnerArgs &a, hipStream_t s);
+
+// ModDown finish: out_b,i = (acc_b,i - z_b,i) * Pinv_i (+ add_b,i if add != null)
+void moddown_finish(const Tables &T, uint64_t *out, const uint64_t *acc, size_t acc_poly_stride,
+                    const uint64_t *z, const uint64_t *add, const LimbConsts &pinv, int nlimb,
+                    const LimbMap &m, hipStream_t s);
+
+// decryption: m = c0 + c1 * s
+void decrypt_combine(const Tables &T, uint64_t *m, const uint64_t *c0, const uint64_t *c1, const uint64_t *sk,
+                     int nlimb, const LimbMap &m_, hipStream_t s);
+
+}  // namespace gpu

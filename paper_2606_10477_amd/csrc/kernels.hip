@@ -1,0 +1,523 @@
+// kernels.hip -- gfx950 kernels of the RNS-CKKS hot path.
+//
+// Arithmetic: every residue is a uint64 word in [0, q), q < 2^62.
+//  * constant multiplications (twiddles, per-limb scalars) use Shoup's
+//    method with a precomputed quotient w' = floor(w 2^64 / q);
+//  * products of two variables use Barrett reduction of the 128-bit product
+//    with mu = floor(2^(2n) / q) (n = bit length of q);
+//  * sums of products (base conversion, key inner product) accumulate the
+//    128-bit products without reduction and reduce once with
+//    mu2 = floor(2^128 / q).
+// Outputs of every kernel are fully reduced, so results are canonical.
+#include "gpu.h"
+
+namespace gpu {
+
+typedef uint64_t u64;
+
+#define DEV __device__ __forceinline__
+
+DEV u64 add_mod(u64 a, u64 b, u64 q) {
+    u64 s = a + b;
+    return s >= q ? s - q : s;
+}
+DEV u64 sub_mod(u64 a, u64 b, u64 q) { return a >= b ? a - b : a + q - b; }
+DEV u64 mul_shoup(u64 a, u64 w, u64 wsh, u64 q) {
+    u64 h = __umul64hi(a, wsh);
+    u64 r = a * w - h * q;
+    return r >= q ? r - q : r;
+}
+// x = hi:lo < q^2
+DEV u64 barrett(u64 hi, u64 lo, const DevPrime &P) {
+    const uint32_t n = P.nbits;
+    u64 t = (hi << (65 - n)) | (lo >> (n - 1));
+    u64 ph = __umul64hi(t, P.mu), pl = t * P.mu;
+    u64 qh = (ph << (63 - n)) | (pl >> (n + 1));
+    u64 r = lo - qh * P.q;
+    if (r >= P.q) r -= P.q;
+    if (r >= P.q) r -= P.q;
+    return r;
+}
+DEV u64 mul_mod(u64 a, u64 b, const DevPrime &P) { return barrett(__umul64hi(a, b), a * b, P); }
+// any x = x1:x0 < 2^128
+DEV u64 reduce128(u64 x1, u64 x0, const DevPrime &P) {
+    u64 ah = __umul64hi(x0, P.mu2_lo);
+    u64 bl = x0 * P.mu2_hi, bh = __umul64hi(x0, P.mu2_hi);
+    u64 cl = x1 * P.mu2_lo, ch = __umul64hi(x1, P.mu2_lo);
+    u64 dl = x1 * P.mu2_hi;
+    u64 s1 = bl + cl;
+    u64 c1 = s1 < bl;
+    u64 s2 = s1 + ah;
+    u64 c2 = s2 < s1;
+    u64 qh = dl + bh + ch + c1 + c2;
+    u64 r = x0 - qh * P.q;
+    if (r >= P.q) r -= P.q;
+    if (r >= P.q) r -= P.q;
+    return r;
+}
+// a 64-bit value (any) reduced mod q
+DEV u64 reduce64(u64 x, const DevPrime &P) { return reduce128(0, x, P); }
+DEV void mac128(u64 &hi, u64 &lo, u64 a, u64 b) {
+    u64 pl = a * b, ph = __umul64hi(a, b);
+    lo += pl;
+    hi += ph + (lo < pl);
+}
+
+// ---------------------------------------------------------------------------
+// NTT
+// ---------------------------------------------------------------------------
+constexpr int kTile = 4096;
+constexpr int kThreads = 256;
+
+// Contiguous pass: forward stages s in [s_lo, logN) or inverse stages with
+// half-distance t = 1 .. t_end/2, on tiles of `ts` consecutive words.
+template <bool INV>
+__global__ void __launch_bounds__(kThreads) k_ntt_contig(u64 *data, int logN, int ts, int s_lo,
+                                                         int t_end, int nlimb, LimbMap m, Tables T,
+                                                         int scale_out) {
+    __shared__ u64 tile[kTile];
+    const int limb = blockIdx.y;
+    const int pi = m.p[limb % nlimb];
+    const DevPrime P = T.primes[pi];
+    const u64 q = P.q;
+    const size_t N = (size_t)1 << logN;
+    u64 *base = data + (size_t)limb * N + (size_t)blockIdx.x * ts;
+    const int g0 = blockIdx.x * ts;
+    for (int i = threadIdx.x; i < ts; i += kThreads) tile[i] = base[i];
+    __syncthreads();
+    const int half = ts >> 1;
+    if (!INV) {
+        const u64 *W = T.fw + (size_t)pi * N, *Ws = T.fw_sh + (size_t)pi * N;
+        for (int s = s_lo; s < logN; ++s) {
+            const int lt = logN - s - 1;   // t = 2^lt
+            const int t = 1 << lt;
+            for (int b = threadIdx.x; b < half; b += kThreads) {
+                int j = ((b >> lt) << (lt + 1)) | (b & (t - 1));
+                int J = g0 + j;
+                int wi = (1 << s) + (J >> (logN - s));
+                u64 U = tile[j];
+                u64 V = mul_shoup(tile[j + t], W[wi], Ws[wi], q);
+                tile[j] = add_mod(U, V, q);
+                tile[j + t] = sub_mod(U, V, q);
+            }
+            __syncthreads();
+        }
+    } else {
+        const u64 *W = T.iw + (size_t)pi * N, *Ws = T.iw_sh + (size_t)pi * N;
+        for (int lt = 0; (1 << lt) < t_end; ++lt) {
+            const int t = 1 << lt;
+            for (int b = threadIdx.x; b < half; b += kThreads) {
+                int j = ((b >> lt) << (lt + 1)) | (b & (t - 1));
+                int J = g0 + j;
+                int wi = (int)(N >> (lt + 1)) + (J >> (lt + 1));
+                u64 U = tile[j], V = tile[j + t];
+                tile[j] = add_mod(U, V, q);
+                tile[j + t] = mul_shoup(sub_mod(U, V, q), W[wi], Ws[wi], q);
+            }
+            __syncthreads();
+        }
+    }
+    if (scale_out) {
+        const u64 ni = T.ninv[pi], nis = T.ninv_sh[pi];
+        for (int i = threadIdx.x; i < ts; i += kThreads) base[i] = mul_shoup(tile[i], ni, nis, q);
+    } else {
+        for (int i = threadIdx.x; i < ts; i += kThreads) base[i] = tile[i];
+    }
+}
+
+// Strided pass over R = 2^a rows of stride B = N / R, C = kTile / R columns
+// per block: forward stages 0..a-1 or inverse row half-distances 1..R/2.
+template <bool INV>
+__global__ void __launch_bounds__(kThreads) k_ntt_strided(u64 *data, int logN, int a, int nlimb,
+                                                          LimbMap m, Tables T, int scale_out) {
+    __shared__ u64 tile[kTile];
+    const int limb = blockIdx.y;
+    const int pi = m.p[limb % nlimb];
+    const DevPrime P = T.primes[pi];
+    const u64 q = P.q;
+    const size_t N = (size_t)1 << logN;
+    const int R = 1 << a;
+    const int lc = 12 - a;             // log C
+    const int C = 1 << lc;
+    const int B = (int)(N >> a);
+    u64 *base = data + (size_t)limb * N;
+    const int r0 = blockIdx.x * C;
+    for (int i = threadIdx.x; i < kTile; i += kThreads) {
+        int k = i >> lc, c = i & (C - 1);
+        tile[i] = base[(size_t)k * B + r0 + c];
+    }
+    __syncthreads();
+    if (!INV) {
+        const u64 *W = T.fw + (size_t)pi * N, *Ws = T.fw_sh + (size_t)pi * N;
+        for (int s = 0; s < a; ++s) {
+            const int lth = a - s - 1;
+            const int th = 1 << lth;
+            for (int b = threadIdx.x; b < kTile / 2; b += kThreads) {
+                int c = b & (C - 1), p = b >> lc;
+                int k = ((p >> lth) << (lth + 1)) | (p & (th - 1));
+                int wi = (1 << s) + (k >> (a - s));
+                int i0 = (k << lc) + c, i1 = ((k + th) << lc) + c;
+                u64 U = tile[i0];
+                u64 V = mul_shoup(tile[i1], W[wi], Ws[wi], q);
+                tile[i0] = add_mod(U, V, q);
+                tile[i1] = sub_mod(U, V, q);
+            }
+            __syncthreads();
+        }
+    } else {
+        const u64 *W = T.iw + (size_t)pi * N, *Ws = T.iw_sh + (size_t)pi * N;
+        for (int lth = 0; lth < a; ++lth) {
+            const int th = 1 << lth;
+            for (int b = threadIdx.x; b < kTile / 2; b += kThreads) {
+                int c = b & (C - 1), p = b >> lc;
+                int k = ((p >> lth) << (lth + 1)) | (p & (th - 1));
+                int wi = (R >> (lth + 1)) + (k >> (lth + 1));
+                int i0 = (k << lc) + c, i1 = ((k + th) << lc) + c;
+                u64 U = tile[i0], V = tile[i1];
+                tile[i0] = add_mod(U, V, q);
+                tile[i1] = mul_shoup(sub_mod(U, V, q), W[wi], Ws[wi], q);
+            }
+            __syncthreads();
+        }
+    }
+    const u64 ni = T.ninv[pi], nis = T.ninv_sh[pi];
+    for (int i = threadIdx.x; i < kTile; i += kThreads) {
+        int k = i >> lc, c = i & (C - 1);
+        u64 v = tile[i];
+        if (scale_out) v = mul_shoup(v, ni, nis, q);
+        base[(size_t)k * B + r0 + c] = v;
+    }
+}
+
+void ntt(const Tables &T, uint64_t *data, int nlimb, int npoly, const LimbMap &m, bool inverse,
+         hipStream_t s) {
+    const int logN = T.logN;
+    const int N = 1 << logN;
+    const int total = nlimb * npoly;
+    if (total == 0) return;
+    if (N <= kTile) {
+        dim3 grid(1, total);
+        if (!inverse)
+            hipLaunchKernelGGL(k_ntt_contig<false>, grid, dim3(kThreads), 0, s, data, logN, N, 0, 0, nlimb, m, T, 0);
+        else
+            hipLaunchKernelGGL(k_ntt_contig<true>, grid, dim3(kThreads), 0, s, data, logN, N, 0, N, nlimb, m, T, 1);
+        return;
+    }
+    const int a = 8;               // rows of the strided pass: 256
+    const int b = logN - a;        // contiguous block 2^b
+    dim3 gs(N / kTile, total);   // column blocks of C = kTile / 2^a columns
+    dim3 gc(N / kTile, total);
+    if (!inverse) {
+        hipLaunchKernelGGL(k_ntt_strided<false>, gs, dim3(kThreads), 0, s, data, logN, a, nlimb, m, T, 0);
+        hipLaunchKernelGGL(k_ntt_contig<false>, gc, dim3(kThreads), 0, s, data, logN, kTile, a, 0, nlimb, m, T, 0);
+    } else {
+        hipLaunchKernelGGL(k_ntt_contig<true>, gc, dim3(kThreads), 0, s, data, logN, kTile, 0, 1 << b, nlimb, m, T, 0);
+        hipLaunchKernelGGL(k_ntt_strided<true>, gs, dim3(kThreads), 0, s, data, logN, a, nlimb, m, T, 1);
+    }
+}
+
+// ---------------------------------------------------------------------------
+// Elementwise kernels (grid-stride over limbs x words)
+// ---------------------------------------------------------------------------
+static inline dim3 grid_for(size_t n) {
+    size_t b = (n + 255) / 256;
+    if (b > 65535u * 8u) b = 65535u * 8u;
+    return dim3((unsigned)b);
+}
+#define GRID_LOOP(idx, total) \
+    for (size_t idx = (size_t)blockIdx.x * blockDim.x + threadIdx.x; idx < (total); idx += (size_t)gridDim.x * blockDim.x)
+
+__global__ void k_add(u64 *out, const u64 *a, const u64 *b, int logN, int nlimb, size_t total, LimbMap m,
+                      Tables T, int sub) {
+    GRID_LOOP(i, total) {
+        int limb = (int)((i >> logN) % nlimb);
+        u64 q = T.primes[m.p[limb]].q;
+        out[i] = sub ? sub_mod(a[i], b[i], q) : add_mod(a[i], b[i], q);
+    }
+}
+void add(const Tables &T, uint64_t *out, const uint64_t *a, const uint64_t *b, int nlimb, int npoly,
+         const LimbMap &m, bool sub, hipStream_t s) {
+    size_t total = ((size_t)nlimb * npoly) << T.logN;
+    if (!total) return;
+    hipLaunchKernelGGL(k_add, grid_for(total), dim3(256), 0, s, out, a, b, T.logN, nlimb, total, m, T, (int)sub);
+}
+
+__global__ void k_mul_scalar(u64 *out, const u64 *a, LimbConsts c, int logN, int nlimb, size_t total, LimbMap m,
+                             Tables T) {
+    GRID_LOOP(i, total) {
+        int limb = (int)((i >> logN) % nlimb);
+        u64 q = T.primes[m.p[limb]].q;
+        out[i] = mul_shoup(a[i], c.v[limb], c.sh[limb], q);
+    }
+}
+void mul_scalar(const Tables &T, uint64_t *out, const uint64_t *a, const LimbConsts &c, int nlimb, int npoly,
+                const LimbMap &m, hipStream_t s) {
+    size_t total = ((size_t)nlimb * npoly) << T.logN;
+    if (!total) return;
+    hipLaunchKernelGGL(k_mul_scalar, grid_for(total), dim3(256), 0, s, out, a, c, T.logN, nlimb, total, m, T);
+}
+
+__global__ void k_add_scalar(u64 *out, const u64 *a, LimbConsts c, int logN, int nlimb, size_t total, LimbMap m,
+                             Tables T) {
+    const size_t first = (size_t)nlimb << logN;
+    GRID_LOOP(i, total) {
+        if (i < first) {
+            int limb = (int)(i >> logN);
+            u64 q = T.primes[m.p[limb]].q;
+            out[i] = add_mod(a[i], c.v[limb], q);
+        } else {
+            out[i] = a[i];
+        }
+    }
+}
+void add_scalar(const Tables &T, uint64_t *out, const uint64_t *a, const LimbConsts &c, int nlimb, int npoly,
+                const LimbMap &m, hipStream_t s) {
+    size_t total = ((size_t)nlimb * npoly) << T.logN;
+    if (!total) return;
+    hipLaunchKernelGGL(k_add_scalar, grid_for(total), dim3(256), 0, s, out, a, c, T.logN, nlimb, total, m, T);
+}
+
+__global__ void k_permute(u64 *out, const u64 *a, const int32_t *perm, int logN, size_t total) {
+    const size_t mask = ((size_t)1 << logN) - 1;
+    GRID_LOOP(i, total) {
+        size_t row = i & ~mask;
+        out[i] = a[row + perm[i & mask]];
+    }
+}
+void permute(const Tables &T, uint64_t *out, const uint64_t *a, const int32_t *perm, int nlimb, int npoly,
+             hipStream_t s) {
+    size_t total = ((size_t)nlimb * npoly) << T.logN;
+    if (!total) return;
+    hipLaunchKernelGGL(k_permute, grid_for(total), dim3(256), 0, s, out, a, perm, T.logN, total);
+}
+
+__global__ void k_tensor(u64 *d0, u64 *d1, u64 *d2, const u64 *a0, const u64 *a1, const u64 *b0, const u64 *b1,
+                         int logN, size_t total, LimbMap m, Tables T) {
+    GRID_LOOP(i, total) {
+        const DevPrime P = T.primes[m.p[i >> logN]];
+        u64 x0 = a0[i], x1 = a1[i], y0 = b0[i], y1 = b1[i];
+        d0[i] = mul_mod(x0, y0, P);
+        u64 hi = 0, lo = 0;
+        mac128(hi, lo, x0, y1);
+        mac128(hi, lo, x1, y0);
+        d1[i] = reduce128(hi, lo, P);
+        d2[i] = mul_mod(x1, y1, P);
+    }
+}
+void tensor(const Tables &T, uint64_t *d0, uint64_t *d1, uint64_t *d2, const uint64_t *a0, const uint64_t *a1,
+            const uint64_t *b0, const uint64_t *b1, int nlimb, const LimbMap &m, hipStream_t s) {
+    size_t total = (size_t)nlimb << T.logN;
+    if (!total) return;
+    hipLaunchKernelGGL(k_tensor, grid_for(total), dim3(256), 0, s, d0, d1, d2, a0, a1, b0, b1, T.logN, total, m, T);
+}
+
+__global__ void k_mul_pointwise(u64 *out, const u64 *a, const u64 *b, int logN, int nlimb, size_t total, LimbMap m,
+                                Tables T) {
+    GRID_LOOP(i, total) {
+        const DevPrime P = T.primes[m.p[(i >> logN) % nlimb]];
+        out[i] = mul_mod(a[i], b[i], P);
+    }
+}
+void mul_pointwise(const Tables &T, uint64_t *out, const uint64_t *a, const uint64_t *b, int nlimb, int npoly,
+                   const LimbMap &m, hipStream_t s) {
+    size_t total = ((size_t)nlimb * npoly) << T.logN;
+    if (!total) return;
+    hipLaunchKernelGGL(k_mul_pointwise, grid_for(total), dim3(256), 0, s, out, a, b, T.logN, nlimb, total, m, T);
+}
+
+__global__ void k_mul_add(u64 *out, const u64 *a, const u64 *b, const u64 *c, int logN, size_t total, LimbMap m,
+                          Tables T) {
+    GRID_LOOP(i, total) {
+        const DevPrime P = T.primes[m.p[i >> logN]];
+        out[i] = add_mod(mul_mod(a[i], b[i], P), c[i], P.q);
+    }
+}
+void mul_add(const Tables &T, uint64_t *out, const uint64_t *a, const uint64_t *b, const uint64_t *c, int nlimb,
+             const LimbMap &m, hipStream_t s) {
+    size_t total = (size_t)nlimb << T.logN;
+    if (!total) return;
+    hipLaunchKernelGGL(k_mul_add, grid_for(total), dim3(256), 0, s, out, a, b, c, T.logN, total, m, T);
+}
+
+struct Flags {
+    uint8_t f[kMaxLimbs];
+};
+__global__ void k_key_combine(u64 *out, const u64 *a, const u64 *sk, const u64 *e, const u64 *sp, LimbConsts k,
+                              Flags fl, int logN, size_t total, LimbMap m, Tables T) {
+    GRID_LOOP(i, total) {
+        int limb = (int)(i >> logN);
+        const DevPrime P = T.primes[m.p[limb]];
+        u64 v = sub_mod(e[i], mul_mod(a[i], sk[i], P), P.q);
+        if (fl.f[limb]) v = add_mod(v, mul_shoup(sp[i], k.v[limb], k.sh[limb], P.q), P.q);
+        out[i] = v;
+    }
+}
+void key_combine(const Tables &T, uint64_t *out, const uint64_t *a, const uint64_t *s_, const uint64_t *e,
+                 const uint64_t *sprime, const LimbConsts &k, const uint8_t *flag_host, int nlimb, const LimbMap &m,
+                 hipStream_t s) {
+    Flags fl;
+    for (int i = 0; i < kMaxLimbs; ++i) fl.f[i] = (i < nlimb && flag_host) ? flag_host[i] : 0;
+    size_t total = (size_t)nlimb << T.logN;
+    hipLaunchKernelGGL(k_key_combine, grid_for(total), dim3(256), 0, s, out, a, s_, e, sprime, k, fl, T.logN, total,
+                       m, T);
+}
+
+__global__ void k_signed(u64 *out, const int64_t *src, int logN, size_t total, LimbMap m, Tables T) {
+    const size_t mask = ((size_t)1 << logN) - 1;
+    GRID_LOOP(i, total) {
+        const DevPrime P = T.primes[m.p[i >> logN]];
+        int64_t v = src[i & mask];
+        u64 mag = v < 0 ? (u64)(-(v + 1)) + 1 : (u64)v;
+        u64 r = reduce64(mag, P);
+        out[i] = (v < 0 && r) ? P.q - r : r;
+    }
+}
+void signed_to_residues(const Tables &T, uint64_t *out, const int64_t *src, int nlimb, const LimbMap &m,
+                        hipStream_t s) {
+    size_t total = (size_t)nlimb << T.logN;
+    hipLaunchKernelGGL(k_signed, grid_for(total), dim3(256), 0, s, out, src, T.logN, total, m, T);
+}
+
+// ---------------------------------------------------------------------------
+// Rescale helpers
+// ---------------------------------------------------------------------------
+__global__ void k_rescale_lift(u64 *u, const u64 *t, int top, int logN, int nlimb, size_t total,
+                               size_t t_stride, Tables T) {
+    const size_t N = (size_t)1 << logN;
+    const DevPrime Pt = T.primes[top];
+    const u64 half = (Pt.q - 1) >> 1;
+    GRID_LOOP(i, total) {
+        size_t poly = i / ((size_t)nlimb * N);
+        size_t rem = i - poly * nlimb * N;
+        int limb = (int)(rem >> logN);
+        size_t j = rem & (N - 1);
+        const DevPrime P = T.primes[limb];
+        u64 v = t[poly * t_stride + j];
+        u64 r = reduce64(v, P);
+        if (v > half) r = sub_mod(r, reduce64(Pt.q, P), P.q);
+        u[i] = r;
+    }
+}
+void rescale_lift(const Tables &T, uint64_t *u, const uint64_t *t, int top_prime, int nlimb, int npoly,
+                  size_t t_poly_stride, hipStream_t s) {
+    size_t total = ((size_t)nlimb * npoly) << T.logN;
+    if (!total) return;
+    hipLaunchKernelGGL(k_rescale_lift, grid_for(total), dim3(256), 0, s, u, t, top_prime, T.logN, nlimb, total,
+                       t_poly_stride, T);
+}
+
+__global__ void k_sub_mul(u64 *out, const u64 *c, const u64 *u, LimbConsts inv, int logN, int nlimb, size_t total,
+                          size_t c_stride, LimbMap m, Tables T) {
+    const size_t N = (size_t)1 << logN;
+    GRID_LOOP(i, total) {
+        size_t poly = i / ((size_t)nlimb * N);
+        size_t rem = i - poly * nlimb * N;
+        int limb = (int)(rem >> logN);
+        u64 q = T.primes[m.p[limb]].q;
+        out[i] = mul_shoup(sub_mod(c[poly * c_stride + rem], u[i], q), inv.v[limb], inv.sh[limb], q);
+    }
+}
+void sub_mul(const Tables &T, uint64_t *out, const uint64_t *c, const uint64_t *u, const LimbConsts &inv, int nlimb,
+             int npoly, size_t c_poly_stride, const LimbMap &m, hipStream_t s) {
+    size_t total = ((size_t)nlimb * npoly) << T.logN;
+    if (!total) return;
+    hipLaunchKernelGGL(k_sub_mul, grid_for(total), dim3(256), 0, s, out, c, u, inv, T.logN, nlimb, total,
+                       c_poly_stride, m, T);
+}
+
+// ---------------------------------------------------------------------------
+// Fast base conversion
+// ---------------------------------------------------------------------------
+__global__ void __launch_bounds__(256) k_bconv(u64 *out, const u64 *in, BconvArgs a, int logN, size_t in_stride,
+                                               size_t out_stride, Tables T) {
+    const size_t N = (size_t)1 << logN;
+    const int poly = blockIdx.y;
+    const size_t j = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (j >= N) return;
+    u64 y[kMaxLimbs < 16 ? kMaxLimbs : 16];
+    const u64 *src = in + poly * in_stride;
+    for (int i = 0; i < a.din; ++i) {
+        const DevPrime P = T.primes[a.pin.p[i]];
+        y[i] = mul_shoup(src[(size_t)i * N + j], a.hinv[i], a.hinv_sh[i], P.q);
+    }
+    u64 *dst = out + poly * out_stride;
+    for (int r = 0; r < a.dout; ++r) {
+        const DevPrime P = T.primes[a.pout.p[r]];
+        u64 hi = 0, lo = 0;
+        for (int i = 0; i < a.din; ++i) mac128(hi, lo, y[i], a.mat[(size_t)i * a.dout + r]);
+        dst[(size_t)r * N + j] = reduce128(hi, lo, P);
+    }
+}
+void bconv(const Tables &T, uint64_t *out, const uint64_t *in, const BconvArgs &a, int npoly, size_t in_poly_stride,
+           size_t out_poly_stride, hipStream_t s) {
+    const size_t N = (size_t)1 << T.logN;
+    dim3 grid((unsigned)((N + 255) / 256), npoly);
+    hipLaunchKernelGGL(k_bconv, grid, dim3(256), 0, s, out, in, a, T.logN, in_poly_stride, out_poly_stride, T);
+}
+
+// ---------------------------------------------------------------------------
+// Key inner product
+// ---------------------------------------------------------------------------
+__global__ void k_key_inner(u64 *acc, InnerArgs a, int logN, size_t total, Tables T) {
+    const size_t N = (size_t)1 << logN;
+    GRID_LOOP(i, total) {
+        int e = (int)(i >> logN);
+        size_t j = i & (N - 1);
+        int pi = a.m.p[e];
+        const DevPrime P = T.primes[pi];
+        u64 h0 = 0, l0 = 0, h1 = 0, l1 = 0;
+        for (int d = 0; d < a.ndig; ++d) {
+            u64 x;
+            if (e >= a.lo[d] && e < a.hi[d]) x = a.dsrc[(size_t)e * N + j];
+            else {
+                int ce = e < a.lo[d] ? e : e - (a.hi[d] - a.lo[d]);
+                x = a.ext[d][(size_t)ce * N + j];
+            }
+            const u64 *k0 = a.key + (((size_t)d * 2 + 0) * a.np + pi) * N;
+            const u64 *k1 = a.key + (((size_t)d * 2 + 1) * a.np + pi) * N;
+            mac128(h0, l0, x, k0[j]);
+            mac128(h1, l1, x, k1[j]);
+        }
+        acc[i] = reduce128(h0, l0, P);
+        acc[(size_t)a.ne * N + i] = reduce128(h1, l1, P);
+    }
+}
+void key_inner(const Tables &T, uint64_t *acc, const InnerArgs &a, hipStream_t s) {
+    size_t total = (size_t)a.ne << T.logN;
+    hipLaunchKernelGGL(k_key_inner, grid_for(total), dim3(256), 0, s, acc, a, T.logN, total, T);
+}
+
+__global__ void k_moddown_finish(u64 *out, const u64 *acc, size_t acc_stride, const u64 *z, const u64 *add,
+                                 LimbConsts pinv, int logN, int nlimb, size_t total, LimbMap m, Tables T) {
+    const size_t N = (size_t)1 << logN;
+    GRID_LOOP(i, total) {
+        size_t poly = i / ((size_t)nlimb * N);
+        size_t rem = i - poly * nlimb * N;
+        int limb = (int)(rem >> logN);
+        u64 q = T.primes[m.p[limb]].q;
+        u64 v = mul_shoup(sub_mod(acc[poly * acc_stride + rem], z[i], q), pinv.v[limb], pinv.sh[limb], q);
+        if (add) v = add_mod(v, add[i], q);
+        out[i] = v;
+    }
+}
+void moddown_finish(const Tables &T, uint64_t *out, const uint64_t *acc, size_t acc_poly_stride, const uint64_t *z,
+                    const uint64_t *add, const LimbConsts &pinv, int nlimb, const LimbMap &m, hipStream_t s) {
+    size_t total = ((size_t)nlimb * 2) << T.logN;
+    hipLaunchKernelGGL(k_moddown_finish, grid_for(total), dim3(256), 0, s, out, acc, acc_poly_stride, z, add, pinv,
+                       T.logN, nlimb, total, m, T);
+}
+
+__global__ void k_decrypt(u64 *mo, const u64 *c0, const u64 *c1, const u64 *sk, int logN, size_t total, LimbMap m,
+                          Tables T) {
+    GRID_LOOP(i, total) {
+        const DevPrime P = T.primes[m.p[i >> logN]];
+        mo[i] = add_mod(c0[i], mul_mod(c1[i], sk[i], P), P.q);
+    }
+}
+void decrypt_combine(const Tables &T, uint64_t *mo, const uint64_t *c0, const uint64_t *c1, const uint64_t *sk,
+                     int nlimb, const LimbMap &m_, hipStream_t s) {
+    size_t total = (size_t)nlimb << T.logN;
+    hipLaunchKernelGGL(k_decrypt, grid_for(total), dim3(256), 0, s, mo, c0, c1, sk, T.logN, total, m_, T);
+}
+
+}  // namespace gpu

@@ -1,0 +1,239 @@
+"""GPU parity: every operation of the HIP library through the C-ABI against the
+CPU oracle on the same seeded inputs.  Ciphertext words must be identical
+(bit-exact); decoded values within 1e-12 relative.
+
+Sizes: the N = 2^12 parameter set (q_0 60-bit + 13 scaling primes, one
+special prime, dense secret) runs the whole CryptoInvSqrt chain (Alg. 1) with
+degree 15 and 2 Newton steps; the N = 2^16 set (q_0 + 27 scaling primes,
+7 special primes, digits of 10 primes, h = 192 secret) checks each primitive
+at full size, several levels.
+"""
+import numpy as np
+import pytest
+
+from paper_2606_10477_amd import inputs
+
+pytestmark = pytest.mark.gpu
+
+
+def _gpu_mod():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_2606_10477_amd import ckks
+    return ckks
+
+
+P12 = dict(log_n=12, max_level=13, num_special=1, digit_size=1, hamming_weight=0)
+P16 = dict(log_n=16, max_level=27, num_special=7, digit_size=10, hamming_weight=192)
+
+
+def _galois(ctx, steps, conj=True):
+    g = [ctx.galois_rot(k) for k in steps]
+    if conj:
+        g.append(2 * ctx.N - 1)
+    return g
+
+
+@pytest.fixture(scope="module")
+def pair12(oracle_mod):
+    ck = _gpu_mod()
+    g = ck.Context(**P12)
+    o = oracle_mod.Context(12, 13, 1, 1, h=0)
+    gal = _galois(g, [1, -3, 7])
+    g.keygen(2, gal)
+    o.keygen(2, gal)
+    yield g, o
+    g.close()
+
+
+@pytest.fixture(scope="module")
+def pair16(oracle_mod):
+    ck = _gpu_mod()
+    g = ck.Context(**P16)
+    o = oracle_mod.Context(16, 27, 7, 10, h=192)
+    gal = _galois(g, [1, 5])
+    g.keygen(9, gal)
+    o.keygen(9, gal)
+    yield g, o
+    g.close()
+
+
+def same(gct, oct_):
+    assert gct.level == oct_.level
+    assert gct.scale == oct_.scale
+    gw, ow = gct.words(), oct_.words()
+    if not np.array_equal(gw, ow):
+        bad = np.argwhere(gw != ow)
+        raise AssertionError(f"{len(bad)} words differ, first at {bad[:5].tolist()}")
+
+
+def test_context_primes_match(pair12, pair16):
+    for g, o in (pair12, pair16):
+        assert np.array_equal(g.primes, o.primes)
+        assert np.array_equal(g.ladder, o.ladder)
+
+
+@pytest.mark.parametrize("which", ["12", "16"])
+def test_ntt_bit_exact(pair12, pair16, which):
+    import torch
+    g, o = pair12 if which == "12" else pair16
+    rng = np.random.default_rng(40)
+    idx = np.arange(g.np_, dtype=np.uint32)
+    host = inputs.uniform_words((g.np_, g.N), g.primes, 41)
+    dev = torch.from_numpy(host.view(np.int64)).cuda()
+    g.ntt_device(dev.data_ptr(), g.np_, idx, inverse=False)
+    torch.cuda.synchronize()
+    got = dev.cpu().numpy().view(np.uint64)
+    for i in rng.choice(g.np_, size=min(8, g.np_), replace=False):
+        assert np.array_equal(got[i], o.ntt(int(i), host[i])), f"forward limb {i}"
+    g.ntt_device(dev.data_ptr(), g.np_, idx, inverse=True)
+    torch.cuda.synchronize()
+    assert np.array_equal(dev.cpu().numpy().view(np.uint64), host)
+    # inverse on fresh data against the oracle
+    dev2 = torch.from_numpy(host.view(np.int64)).cuda()
+    g.ntt_device(dev2.data_ptr(), g.np_, idx, inverse=True)
+    torch.cuda.synchronize()
+    got2 = dev2.cpu().numpy().view(np.uint64)
+    for i in [0, g.np_ - 1]:
+        assert np.array_equal(got2[i], o.intt(int(i), host[i])), f"inverse limb {i}"
+
+
+def test_encrypt_decrypt_parity(pair12):
+    g, o = pair12
+    x = inputs.log_uniform(g.n, 2 ** -8, 1.0, 1)
+    for lvl, sc, seed in [(13, 2.0 ** 50, 3), (4, 2.0 ** 40, 5), (0, 2.0 ** 40, 6)]:
+        gc, oc = g.encrypt(x, lvl, sc, seed), o.encrypt(x, lvl, sc, seed)
+        same(gc, oc)
+        zg, zo = g.decrypt(gc), o.decrypt(oc)
+        assert np.max(np.abs(zg - zo)) <= 1e-12 * np.max(np.abs(zo))
+
+
+def test_primitive_ops_parity_small(pair12):
+    g, o = pair12
+    x = inputs.log_uniform(g.n, 2 ** -8, 1.0, 1)
+    y = inputs.log_uniform(g.n, 2 ** -8, 1.0, 2)
+    ga, oa = g.encrypt(x, 13, 2.0 ** 40, 3), o.encrypt(x, 13, 2.0 ** 40, 3)
+    gb, ob = g.encrypt(y, 13, 2.0 ** 40, 4), o.encrypt(y, 13, 2.0 ** 40, 4)
+    same(g.add(ga, gb), o.add(oa, ob))
+    same(g.sub(ga, gb), o.sub(oa, ob))
+    same(g.mul_int(ga, -7), o.mul_int(oa, -7))
+    same(g.mul_const(ga, 0.375, 2.0 ** 38), o.mul_const(oa, 0.375, 2.0 ** 38))
+    same(g.add_const(ga, -0.8125), o.add_const(oa, -0.8125))
+    same(g.drop_level(ga, 6), o.drop_level(oa, 6))
+    same(g.rescale(ga), o.rescale(oa))
+    same(g.level_to(ga, 9), o.level_to(oa, 9))
+    same(g.mul_const_down(ga, 1.5), o.mul_const_down(oa, 1.5))
+    gm, om = g.hmult(ga, gb), o.hmult(oa, ob)
+    same(gm, om)
+    same(g.rescale(gm), o.rescale(om))
+    for k in (1, -3, 7):
+        same(g.rotate(ga, k), o.rotate(oa, k))
+    same(g.conjugate(ga), o.conjugate(oa))
+    # lower levels, including the single-prime digits near the bottom
+    gl, ol = g.level_to(ga, 2), o.level_to(oa, 2)
+    same(gl, ol)
+    same(g.hmult(gl, gl), o.hmult(ol, ol))
+    same(g.rotate(gl, 1), o.rotate(ol, 1))
+
+
+def test_uniform_word_inputs_small(pair12):
+    """Operations are integer maps: check them on arbitrary words too."""
+    g, o = pair12
+    for lvl in (13, 5, 1):
+        w = inputs.uniform_words((2, lvl + 1, g.N), g.primes[:lvl + 1], 50 + lvl)
+        ga, oa = g.ct_import(w, lvl, 2.0 ** 40), o.ct_import(w, lvl, 2.0 ** 40)
+        same(g.rescale(ga), o.rescale(oa))
+        same(g.hmult(ga, ga), o.hmult(oa, oa))
+        same(g.rotate(ga, 7), o.rotate(oa, 7))
+
+
+def test_errors_small(pair12):
+    ck = _gpu_mod()
+    g, _ = pair12
+    x = inputs.log_uniform(g.n, 2 ** -8, 1.0, 1)
+    a = g.encrypt(x, 3, 2.0 ** 40, 3)
+    b = g.encrypt(x, 2, 2.0 ** 40, 3)
+    with pytest.raises(ck.CkksError) as e:
+        g.add(a, b)
+    assert e.value.status == -2
+    with pytest.raises(ck.CkksError) as e:
+        g.rotate(a, 2)
+    assert e.value.status == -4
+    c = g.encrypt(x, 3, 2.0 ** 45, 3)
+    with pytest.raises(ck.CkksError) as e:
+        g.add(a, c)
+    assert e.value.status == -3
+    z = g.encrypt(x, 0, 2.0 ** 40, 3)
+    with pytest.raises(ck.CkksError) as e:
+        g.rescale(z)
+    assert e.value.status == -2
+    with pytest.raises(ck.CkksError):
+        g.encrypt(x, 14, 2.0 ** 40, 3)
+
+
+def test_cheb_newton_invsqrt_chain_small(pair12, oracle_mod):
+    """Alg. 1 at N = 2^12: degree 15, 2 Newton steps; every intermediate and
+    the result bit-exact, MRE equal to the oracle's."""
+    g, o = pair12
+    x = inputs.log_uniform(g.n, 2 ** -8, 1.0, 1)
+    gx, ox = g.encrypt(x, 13, 2.0 ** 50, 3), o.encrypt(x, 13, 2.0 ** 50, 3)
+    cf = oracle_mod.cheb_coeffs_invsqrt(15, 2 ** -8, 1.0)
+    from paper_2606_10477_amd import ckks
+    assert np.array_equal(cf, ckks.cheb_coeffs_invsqrt(15, 2 ** -8, 1.0))
+    gy, oy = g.cheb_eval(gx, cf, 2 ** -8, 1.0), o.cheb_eval(ox, cf, 2 ** -8, 1.0)
+    same(gy, oy)
+    gh, oh = g.mul_const_down(gx, 0.5), o.mul_const_down(ox, 0.5)
+    same(gh, oh)
+    gn, on = g.newton_step(gy, gh), o.newton_step(oy, oh)
+    same(gn, on)
+    gi = g.invsqrt(gx, 15, 2, a=2 ** -8, b=1.0)
+    oi = o.invsqrt(ox, 15, 2, 2 ** -8, 1.0)
+    same(gi, oi)
+    ref = 1 / np.sqrt(x)
+    zg = g.decrypt(gi).real
+    mre = np.mean(np.abs(zg - ref) / ref)
+    assert abs(mre - 2.7e-5) < 0.2e-5
+    # odd degrees and a degree below the baby-step size
+    for d in (7, 1, 2):
+        cf = oracle_mod.cheb_coeffs_invsqrt(d, 2 ** -8, 1.0)
+        same(g.cheb_eval(gx, cf, 2 ** -8, 1.0), o.cheb_eval(ox, cf, 2 ** -8, 1.0))
+
+
+def test_batch_equals_single_small(pair12):
+    g, o = pair12
+    xs = [g.encrypt(inputs.log_uniform(g.n, 2 ** -8, 1.0, 10 + i), 13, 2.0 ** 50, 20 + i) for i in range(3)]
+    outs = g.invsqrt_batch(xs, 15, 2, a=2 ** -8, b=1.0)
+    for x, y in zip(xs, outs):
+        single = g.invsqrt(x, 15, 2, a=2 ** -8, b=1.0)
+        assert np.array_equal(single.words(), y.words())
+
+
+# ---------------------------------------------------------------------------
+# N = 2^16 (full size): primitives bit-exact at several levels
+# ---------------------------------------------------------------------------
+def test_full_size_encrypt_and_ops(pair16):
+    g, o = pair16
+    x = inputs.log_uniform(g.n, 2 ** -10, 1.0, 1)
+    gx, ox = g.encrypt(x, 11, 2.0 ** 50, 3), o.encrypt(x, 11, 2.0 ** 50, 3)
+    same(gx, ox)
+    zg, zo = g.decrypt(gx), o.decrypt(ox)
+    assert np.max(np.abs(zg - zo)) <= 1e-12 * np.max(np.abs(zo))
+    gh, oh = g.mul_const_down(gx, 0.5), o.mul_const_down(ox, 0.5)
+    same(gh, oh)
+    gm, om = g.hmult(gh, gh), o.hmult(oh, oh)
+    same(gm, om)
+    same(g.rescale(gm), o.rescale(om))
+    same(g.rotate(gh, 5), o.rotate(oh, 5))
+    same(g.conjugate(gh), o.conjugate(oh))
+
+
+@pytest.mark.parametrize("lvl", [27, 19, 9, 1])
+def test_full_size_keyswitch_levels(pair16, lvl):
+    """hmult (tensor + hybrid key switch with 3/2/1 digits) and rescale on
+    uniform words at levels spanning every digit count."""
+    g, o = pair16
+    w = inputs.uniform_words((2, lvl + 1, g.N), g.primes[:lvl + 1], 70 + lvl)
+    ga, oa = g.ct_import(w, lvl, 2.0 ** 40), o.ct_import(w, lvl, 2.0 ** 40)
+    same(g.hmult(ga, ga), o.hmult(oa, oa))
+    same(g.rescale(ga), o.rescale(oa))
