@@ -171,8 +171,13 @@ ckks_status ckks_cheb_eval(ckks_ctx *ctx, const ckks_ct *x, const double *coeffs
  * degree+1 first-kind nodes (quad precision, rounded once). */
 ckks_status ckks_cheb_coeffs_invsqrt(uint32_t degree, double a, double b, double *coeffs);
 /* One Newton step for 1/sqrt (paper §2.2, Alg. 1 loop body) given
- * ct_half = x/2: y' = 1.5 y - (ct_half y) y^2.  Consumes 2 levels. */
-ckks_status ckks_newton_step(ckks_ctx *ctx, const ckks_ct *y, const ckks_ct *ct_half, ckks_ct **out);
+ * ct_half = x/2: y' = 1.5 y - (ct_half y) y^2, at level c = min(l_x, l_y)
+ * (needs c >= 2; result at c - 2, on the scale of the product term).  With
+ * raw_x = 0 ct_half is brought to level c on the canonical scale; with
+ * raw_x = 1 its limbs are only dropped, so it keeps its own scale (used for
+ * the last step of ckks_invsqrt, where x comes straight from the input). */
+ckks_status ckks_newton_step(ckks_ctx *ctx, const ckks_ct *y, const ckks_ct *ct_half, int raw_x,
+                             ckks_ct **out);
 
 /* Bootstrapping (paper §2.1 BTS) of a level-0..l ciphertext whose slot
  * values are real and lie in [-1, 1]: ModRaise, CoeffToSlot, EvalMod,
@@ -190,7 +195,11 @@ typedef struct {
 /*
  * CryptoInvSqrt (paper Alg. 1): y0 = Chebyshev interpolant of degree `degree`
  * of 1/sqrt on [a, b]; ct_x = x/2; `iters` Newton steps; bootstrapping of y
- * per the policy in opts.  ckks_invsqrt uses the defaults above.
+ * per the policy in opts.  The last Newton step takes x/2 directly from the
+ * input (limbs dropped, halving as an exact scale change, no rescale), so the
+ * result keeps the relative precision of the input's scale; its scale is the
+ * product of the step's scales (tracked exactly, not the canonical one).
+ * ckks_invsqrt uses the defaults above.
  */
 ckks_status ckks_invsqrt(ckks_ctx *ctx, const ckks_ct *x, uint32_t degree, uint32_t iters,
                          ckks_ct **out);

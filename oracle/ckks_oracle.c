@@ -1507,13 +1507,17 @@ fail:
 /*   tmp_a = Mul_P(y, 1.5); tmp_b = Mul_C(ct_x, y); y2 = Mul_C(y, y);        */
 /*   tmp_b = Mul_C(tmp_b, y2); y' = tmp_a - tmp_b                            */
 /* with ct_x = x/2.  Level placement: c = min(l_x, l_y) (needs c >= 2);      */
-/*   u = (ct_x@c)(y@c) -> c-1;  v = y*y -> l_y - 1, then level_to(c-1);     */
-/*   w = u*v -> c-2;  tmp_a = y dropped to c-1, Mul_P 1.5 landing on S_{c-2}. */
+/*   x at level c: level_to (canonical) or, with raw_x, a plain limb drop    */
+/*   that keeps x's own scale;  u = (x@c)(y@c) -> c-1;                       */
+/*   v = y*y -> l_y - 1, then level_to(c-1);  w = u*v -> c-2;                */
+/*   tmp_a = y dropped to c-1, Mul_P 1.5 at s_c = (scale(w) q_{c-1}) /       */
+/*   scale(y), rescaled, so that it lands exactly on scale(w).               */
 /* ------------------------------------------------------------------------ */
-orc_ct *orc_newton_step(orc_ctx *c, const orc_ct *y, const orc_ct *ctx_half) {
+orc_ct *orc_newton_step_ex(orc_ctx *c, const orc_ct *y, const orc_ct *ctx_half, int raw_x) {
     int lc = y->level < ctx_half->level ? y->level : ctx_half->level;
     if (lc < 2) { set_err("level"); return NULL; }
-    orc_ct *xa = orc_level_to(c, ctx_half, lc), *ya = orc_level_to(c, y, lc);
+    orc_ct *xa = raw_x ? orc_drop_level(c, ctx_half, lc) : orc_level_to(c, ctx_half, lc);
+    orc_ct *ya = orc_level_to(c, y, lc);
     orc_ct *u = mult_rs(c, xa, ya);
     orc_ct_free(xa); orc_ct_free(ya);
     orc_ct *v0 = mult_rs(c, y, y);
@@ -1522,11 +1526,17 @@ orc_ct *orc_newton_step(orc_ctx *c, const orc_ct *y, const orc_ct *ctx_half) {
     orc_ct *w = mult_rs(c, u, v);
     orc_ct_free(u); orc_ct_free(v);
     orc_ct *yd = orc_drop_level(c, y, lc - 1);
-    orc_ct *ta = mul_const_down(c, yd, 1.5);
+    double sc = (w->scale * (double)c->q[lc - 1]) / yd->scale;
+    orc_ct *tm = orc_mul_const(c, yd, 1.5, sc);
     orc_ct_free(yd);
+    orc_ct *ta = orc_rescale(c, tm);
+    orc_ct_free(tm);
     orc_ct *r = orc_sub(c, ta, w);
     orc_ct_free(ta); orc_ct_free(w);
     return r;
+}
+orc_ct *orc_newton_step(orc_ctx *c, const orc_ct *y, const orc_ct *ctx_half) {
+    return orc_newton_step_ex(c, y, ctx_half, 0);
 }
 
 /* forward declaration: bootstrapping of y with the 1/S_bts pre-scaling */
@@ -1537,8 +1547,13 @@ orc_ct *orc_bootstrap(orc_ctx *c, const orc_ct *a);
  *   ct_x = Mul_P(x, 0.5)                       (lands on S_{l-1})
  *   y    = ChebyshevApprox(x, d) on [a, b]
  *   if literal: y = BTS(y)
- *   repeat n times: [lazy policy: y = BTS(y) when min(l_x, l_y) < 2 and
- *                    l_y < 2]  y = NewtonStep(y, ct_x)
+ *   repeat n times: [lazy policy: y = BTS(y) when l_y < 2]
+ *                   y = NewtonStep(y, ct_x)
+ * The last Newton step takes x/2 directly from the input ciphertext: its
+ * limbs are dropped to the step's level and the halving is the exact
+ * scale change scale(x) -> 2 scale(x), with no rescale, so x keeps the
+ * precision of its input scale (the fixed point of the last step is the
+ * square root of the x it sees; earlier steps' errors are squared away).
  * BTS of y is done as  S * BTS(y / S)  with S = 64 (y <= 32 on the inputs of
  * interest) and the division folded into the scale: scale(y) *= S before,
  * integer multiply by S after.
@@ -1575,7 +1590,15 @@ orc_ct *orc_invsqrt(orc_ctx *c, const orc_ct *x, int d, int iters, double a, dou
             if (!t) { orc_ct_free(cx); return NULL; }
             y = t;
         }
-        orc_ct *yn = orc_newton_step(c, y, cx);
+        orc_ct *yn;
+        if (i == iters - 1) {
+            orc_ct *xr = ct_copy(c, x);
+            xr->scale = x->scale * 2.0;
+            yn = orc_newton_step_ex(c, y, xr, 1);
+            orc_ct_free(xr);
+        } else {
+            yn = orc_newton_step(c, y, cx);
+        }
         orc_ct_free(y);
         if (!yn) { orc_ct_free(cx); return NULL; }
         y = yn;

@@ -86,6 +86,7 @@ def lib():
         "orc_cheb_coeffs_cosmod": (C.c_int, [C.c_int, C.c_double, C.c_double, dblp]),
         "orc_cheb_eval": (vp, [vp, vp, dblp, C.c_int, C.c_double, C.c_double]),
         "orc_newton_step": (vp, [vp, vp, vp]),
+        "orc_newton_step_ex": (vp, [vp, vp, vp, C.c_int]),
         "orc_invsqrt": (vp, [vp, vp, C.c_int, C.c_int, C.c_double, C.c_double, C.c_int]),
         "orc_bootstrap": (vp, [vp, vp]),
         "orc_bts_scaled": (vp, [vp, vp, C.c_int]),
@@ -305,8 +306,8 @@ class Context:
         cf = np.ascontiguousarray(coeffs, dtype=np.float64)
         return Ct(self, lib().orc_cheb_eval(self.ptr, x.ptr, _p(cf, dblp), len(cf) - 1, a, b))
 
-    def newton_step(self, y, cx):
-        return Ct(self, lib().orc_newton_step(self.ptr, y.ptr, cx.ptr))
+    def newton_step(self, y, cx, raw_x=False):
+        return Ct(self, lib().orc_newton_step_ex(self.ptr, y.ptr, cx.ptr, int(raw_x)))
 
     def invsqrt(self, x, degree, iters, a, b, literal=False):
         return Ct(self, lib().orc_invsqrt(self.ptr, x.ptr, degree, iters, a, b, int(literal)))

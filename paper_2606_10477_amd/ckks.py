@@ -65,7 +65,7 @@ SIGNATURES = {
     "ckks_conjugate": (C.c_int, [vp, vp, C.POINTER(vp)]),
     "ckks_cheb_eval": (C.c_int, [vp, vp, dblp, C.c_uint32, C.c_double, C.c_double, C.POINTER(vp)]),
     "ckks_cheb_coeffs_invsqrt": (C.c_int, [C.c_uint32, C.c_double, C.c_double, dblp]),
-    "ckks_newton_step": (C.c_int, [vp, vp, vp, C.POINTER(vp)]),
+    "ckks_newton_step": (C.c_int, [vp, vp, vp, C.c_int, C.POINTER(vp)]),
     "ckks_bootstrap": (C.c_int, [vp, vp, C.POINTER(vp)]),
     "ckks_invsqrt": (C.c_int, [vp, vp, C.c_uint32, C.c_uint32, C.POINTER(vp)]),
     "ckks_invsqrt_ex": (C.c_int, [vp, vp, C.c_uint32, C.c_uint32, C.POINTER(InvsqrtOpts), C.POINTER(vp)]),
@@ -247,8 +247,8 @@ class Context:
         cf = np.ascontiguousarray(coeffs, dtype=np.float64)
         return self._ct(lib().ckks_cheb_eval, x.ptr, _p(cf, dblp), len(cf) - 1, a, b)
 
-    def newton_step(self, y, half_x):
-        return self._ct(lib().ckks_newton_step, y.ptr, half_x.ptr)
+    def newton_step(self, y, half_x, raw_x=False):
+        return self._ct(lib().ckks_newton_step, y.ptr, half_x.ptr, int(raw_x))
 
     def bootstrap(self, a):
         return self._ct(lib().ckks_bootstrap, a.ptr)

@@ -234,6 +234,11 @@ void ntt_p(ckks_ctx *c, uint64_t *data, int nlimb, int npoly, const LimbMap &m, 
     ProfScope ps(c, "ntt", 16.0 * (double)nlimb * npoly * c->N);
     gpu::ntt(c->T, data, nlimb, npoly, m, inverse, c->stream);
 }
+void ntt_oop_p(ckks_ctx *c, uint64_t *dst, const uint64_t *src, size_t src_stride, int nlimb, int npoly,
+               const LimbMap &m, bool inverse) {
+    ProfScope ps(c, "ntt", 16.0 * (double)nlimb * npoly * c->N);
+    gpu::ntt_oop(c->T, dst, src, src_stride, nlimb, npoly, m, inverse, c->stream);
+}
 
 // ---------------------------------------------------------------------------
 // context construction
@@ -442,10 +447,7 @@ Ct op_rescale(ckks_ctx *c, const ckks_ct *a) {
     const size_t N = c->N;
     Ct r = ct_new(c, l - 1, a->scale / (double)c->q[l]);
     Buf t(c->pool.get(), 2 * N);
-    for (int p = 0; p < 2; ++p)
-        hipchk(hipMemcpyAsync(t.p + p * N, poly(c, a, p) + (size_t)l * N, N * 8, hipMemcpyDeviceToDevice, c->stream),
-               "rescale copy");
-    ntt_p(c, t.p, 1, 2, map_q(l, 1), true);
+    ntt_oop_p(c, t.p, a->buf.p + (size_t)l * N, (size_t)(l + 1) * N, 1, 2, map_q(l, 1), true);
     Buf u(c->pool.get(), 2 * (size_t)l * N);
     gpu::rescale_lift(c->T, u.p, t.p, l, l, 2, N, c->stream);
     ntt_p(c, u.p, l, 2, map_q(0, l), false);
@@ -467,8 +469,7 @@ void keyswitch(ckks_ctx *c, int l, const u64 *d, const SwitchKey &key, u64 *out,
     ProfScope ps(c, "keyswitch", 8.0 * (double)N * ((double)nq + 2.0 * beta * ne + 2.0 * nq));
     Pool *P = c->pool.get();
     Buf dc(P, (size_t)nq * N);
-    hipchk(hipMemcpyAsync(dc.p, d, (size_t)nq * N * 8, hipMemcpyDeviceToDevice, c->stream), "ks copy");
-    ntt_p(c, dc.p, nq, 1, map_q(0, nq), true);
+    ntt_oop_p(c, dc.p, d, 0, nq, 1, map_q(0, nq), true);
     std::vector<Buf> ext;
     gpu::InnerArgs ia{};
     ia.ndig = beta;
@@ -493,11 +494,7 @@ void keyswitch(ckks_ctx *c, int l, const u64 *d, const SwitchKey &key, u64 *out,
     // ModDown of both polys
     ConvTable *md = moddown_table(c, l);
     Buf y(P, 2 * (size_t)c->K * N);
-    for (int b = 0; b < 2; ++b)
-        hipchk(hipMemcpyAsync(y.p + (size_t)b * c->K * N, acc.p + ((size_t)b * ne + nq) * N, (size_t)c->K * N * 8,
-                              hipMemcpyDeviceToDevice, c->stream),
-               "moddown copy");
-    ntt_p(c, y.p, c->K, 2, md->pin, true);
+    ntt_oop_p(c, y.p, acc.p + (size_t)nq * N, (size_t)ne * N, c->K, 2, md->pin, true);
     Buf z(P, 2 * (size_t)nq * N);
     gpu::BconvArgs bd{md->pin, md->pout, md->din, md->dout, md->hinv.p, md->hinv_sh.p, md->mat.p};
     gpu::bconv(c->T, z.p, y.p, bd, 2, (size_t)c->K * N, (size_t)nq * N, c->stream);
@@ -683,10 +680,14 @@ Ct op_cheb(ckks_ctx *c, const ckks_ct *x, const std::vector<double> &cf, double 
     return cheb_tree(c, pb, cf, m, bb);
 }
 
-Ct op_newton(ckks_ctx *c, const ckks_ct *y, const ckks_ct *half_x) {
+// One Newton step y' = 1.5 y - (x/2 * y) * y^2 at c = min(l_x, l_y).  With
+// raw_x the x operand is only limb-dropped (it keeps its own, larger scale);
+// 1.5 y is encoded to land exactly on the scale of the product term.
+Ct op_newton(ckks_ctx *c, const ckks_ct *y, const ckks_ct *half_x, bool raw_x) {
     const int lc = std::min(y->level, half_x->level);
     if (lc < 2) fail(CKKS_E_LEVEL, "Newton step needs 2 levels");
-    Ct xa = op_level_to(c, half_x, lc), ya = op_level_to(c, y, lc);
+    Ct xa = raw_x ? op_drop(c, half_x, lc) : op_level_to(c, half_x, lc);
+    Ct ya = op_level_to(c, y, lc);
     Ct u = mult_rs(c, xa.get(), ya.get());          // tmp_beta = ct_x * y
     xa.reset();
     ya.reset();
@@ -694,8 +695,13 @@ Ct op_newton(ckks_ctx *c, const ckks_ct *y, const ckks_ct *half_x) {
     Ct v = op_level_to(c, v0.get(), lc - 1);
     v0.reset();
     Ct w = mult_rs(c, u.get(), v.get());            // tmp_beta * y^2
+    u.reset();
+    v.reset();
     Ct yd = op_drop(c, y, lc - 1);
-    Ct ta = op_mul_const_down(c, yd.get(), 1.5);    // tmp_alpha = 1.5 y
+    double sc = (w->scale * (double)c->q[lc - 1]) / yd->scale;
+    Ct tm = op_mul_const(c, yd.get(), 1.5, sc);     // tmp_alpha = 1.5 y on scale(w)
+    yd.reset();
+    Ct ta = op_rescale(c, tm.get());
     return op_addsub(c, ta.get(), w.get(), true);
 }
 
@@ -722,7 +728,14 @@ Ct op_invsqrt(ckks_ctx *c, const ckks_ct *x, int degree, int iters, const ckks_i
             if (cx->level < 2) fail(CKKS_E_LEVEL, "x has too few levels for Newton");
             y = bts_scaled(c, y.get(), o.bts_scale);
         }
-        y = op_newton(c, y.get(), cx.get());
+        if (i == iters - 1) {
+            // last step: x/2 straight from the input (exact halving of the scale)
+            Ct xr = ct_copy(c, x);
+            xr->scale = x->scale * 2.0;
+            y = op_newton(c, y.get(), xr.get(), true);
+        } else {
+            y = op_newton(c, y.get(), cx.get(), false);
+        }
     }
     return y;
 }
@@ -1063,9 +1076,9 @@ ckks_status ckks_cheb_coeffs_invsqrt(uint32_t degree, double a, double b, double
     hm::cheb_invsqrt((int)degree, a, b, coeffs);
     return CKKS_OK;
 }
-ckks_status ckks_newton_step(ckks_ctx *c, const ckks_ct *y, const ckks_ct *h, ckks_ct **out) {
+ckks_status ckks_newton_step(ckks_ctx *c, const ckks_ct *y, const ckks_ct *h, int raw_x, ckks_ct **out) {
     if (!c || !y || !h) return CKKS_E_PARAM;
-    return guard_out(c, out, [&] { return op_newton(c, y, h); });
+    return guard_out(c, out, [&] { return op_newton(c, y, h, raw_x != 0); });
 }
 ckks_status ckks_bootstrap(ckks_ctx *c, const ckks_ct *a, ckks_ct **out) {
     CT_ARGS_CHECK();

@@ -37,6 +37,11 @@ struct Tables {
 // Batched in-place NTT / inverse NTT of nlimb * npoly limbs.
 void ntt(const Tables &T, uint64_t *data, int nlimb, int npoly, const LimbMap &m, bool inverse,
          hipStream_t s);
+// Out-of-place form: dst = NTT(src) (src may equal dst).  Source poly p,
+// limb e is at src + p * src_poly_stride + e * N (0 = contiguous); dst is
+// contiguous.
+void ntt_oop(const Tables &T, uint64_t *dst, const uint64_t *src, size_t src_poly_stride, int nlimb, int npoly,
+             const LimbMap &m, bool inverse, hipStream_t s);
 
 // Elementwise (all over nlimb limbs x npoly polys with limb map m):
 // out = a + b / a - b

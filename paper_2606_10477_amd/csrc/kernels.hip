@@ -189,9 +189,208 @@ __global__ void __launch_bounds__(kThreads) k_ntt_strided(u64 *data, int logN, i
     }
 }
 
+// ---------------------------------------------------------------------------
+// N = 2^16: two passes of 8 stages, each split into two radix-16 register
+// phases (4 butterfly stages on 16 words held by one thread) around one LDS
+// transpose.  Pass "rows": a block owns C = 16 consecutive columns of the
+// 256 x 256 view (element (k, c) at k*256 + c); pass "blocks": a block owns
+// 16 consecutive 256-word blocks.  256 threads, thread t -> (x = t & 15,
+// y = t >> 4).  Global accesses are 16 consecutive words per 16 threads.
+// ---------------------------------------------------------------------------
+constexpr int kPad = 17;   // LDS row pitch (words) for the 16-wide sub-tiles
+
+// forward butterflies (CT) on v[0..15] for 4 stages; element m pairs with
+// m + h (h = 8, 4, 2, 1); twiddle index for stage j (0..3): base_j + (m >> (4 - j))
+__device__ __forceinline__ void fwd16(u64 v[16], const u64 *W, const u64 *Ws, int s0, int base_shift_idx,
+                                      int hi_part, u64 q) {
+    // stage j: global stage s = s0 + j; twiddle index = 2^s + hi_part * 2^j + (m >> (4 - j))
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+        const int h = 8 >> j;
+#pragma unroll
+        for (int m = 0; m < 16; ++m) {
+            if (m & h) continue;
+            const int wi = (1 << (s0 + j)) + (hi_part << j) + (m >> (4 - j));
+            u64 U = v[m];
+            u64 V = mul_shoup(v[m + h], W[wi], Ws[wi], q);
+            v[m] = add_mod(U, V, q);
+            v[m + h] = sub_mod(U, V, q);
+        }
+    }
+    (void)base_shift_idx;
+}
+// inverse butterflies (GS) on v[0..15], distances h = 1, 2, 4, 8; group index
+// for distance h: hi_part * (16 / 2h) + (m >> (log2 h + 1)); twiddle index =
+// n_groups_total + group, with n_groups_total = N / (2 t_global).
+__device__ __forceinline__ void inv16(u64 v[16], const u64 *W, const u64 *Ws, int logN, int lt0, int hi_part,
+                                      u64 q) {
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+        const int h = 1 << j;
+#pragma unroll
+        for (int m = 0; m < 16; ++m) {
+            if (m & h) continue;
+            const int lt = lt0 + j;   // log2 of the global half-distance
+            const int wi = (1 << (logN - lt - 1)) + (hi_part << (3 - j)) + (m >> (j + 1));
+            u64 U = v[m], V = v[m + h];
+            v[m] = add_mod(U, V, q);
+            v[m + h] = mul_shoup(sub_mod(U, V, q), W[wi], Ws[wi], q);
+        }
+    }
+}
+
+// forward pass over rows (stages 0..7): reads src, writes dst
+__global__ void __launch_bounds__(256) k_ntt16_rows_fwd(u64 *dst, const u64 *src, size_t src_stride, int nlimb,
+                                                         LimbMap m, Tables T) {
+    __shared__ u64 tile[256 * kPad];
+    const int limb = blockIdx.y;
+    const int pi = m.p[limb % nlimb];
+    const u64 q = T.primes[pi].q;
+    const u64 *W = T.fw + ((size_t)pi << 16), *Ws = T.fw_sh + ((size_t)pi << 16);
+    const u64 *in = src + (size_t)(limb / nlimb) * src_stride + ((size_t)(limb % nlimb) << 16);
+    u64 *out = dst + ((size_t)limb << 16);
+    const int c0 = blockIdx.x * 16;
+    const int x = threadIdx.x & 15, y = threadIdx.x >> 4;
+    u64 v[16];
+    // phase 1: rows k = y + 16 m, column x; stages 0..3 (row distances 128..16)
+#pragma unroll
+    for (int mm = 0; mm < 16; ++mm) v[mm] = in[((y + 16 * mm) << 8) + c0 + x];
+    fwd16(v, W, Ws, 0, 0, 0, q);
+#pragma unroll
+    for (int mm = 0; mm < 16; ++mm) tile[(y + 16 * mm) * kPad + x] = v[mm];
+    __syncthreads();
+    // phase 2: rows k = 16 y + m, column x; stages 4..7 (distances 8..1)
+#pragma unroll
+    for (int mm = 0; mm < 16; ++mm) v[mm] = tile[(16 * y + mm) * kPad + x];
+    // twiddle index 2^s + (k >> (8 - s)), k = 16 y + m: hi_part = y
+    fwd16(v, W, Ws, 4, 0, y, q);
+#pragma unroll
+    for (int mm = 0; mm < 16; ++mm) out[((16 * y + mm) << 8) + c0 + x] = v[mm];
+}
+
+// forward pass over 256-word blocks (stages 8..15), in place
+__global__ void __launch_bounds__(256) k_ntt16_blocks_fwd(u64 *data, int nlimb, LimbMap m, Tables T) {
+    __shared__ u64 tile[256 * kPad];
+    const int limb = blockIdx.y;
+    const int pi = m.p[limb % nlimb];
+    const u64 q = T.primes[pi].q;
+    const u64 *W = T.fw + ((size_t)pi << 16), *Ws = T.fw_sh + ((size_t)pi << 16);
+    u64 *d = data + ((size_t)limb << 16) + ((size_t)blockIdx.x << 12);
+    const int blk0 = blockIdx.x * 16;   // global index of the first 256-block
+    const int x = threadIdx.x & 15, y = threadIdx.x >> 4;
+    u64 v[16];
+    // phase 1: block y, words x + 16 m; stages 8..11 (distances 128..16)
+#pragma unroll
+    for (int mm = 0; mm < 16; ++mm) v[mm] = d[(y << 8) + x + 16 * mm];
+    // twiddle 2^s + (J >> (16 - s)), J = 256 (blk0 + y) + x + 16 m: hi_part = blk0 + y
+    fwd16(v, W, Ws, 8, 0, blk0 + y, q);
+#pragma unroll
+    for (int mm = 0; mm < 16; ++mm) tile[(y * 16 + mm) * kPad + x] = v[mm];   // [block y][row mm][col x]
+    __syncthreads();
+    // phase 2: block y, words 16 x + m; stages 12..15 (distances 8..1)
+#pragma unroll
+    for (int mm = 0; mm < 16; ++mm) v[mm] = tile[(y * 16 + x) * kPad + mm];
+    fwd16(v, W, Ws, 12, 0, (blk0 + y) * 16 + x, q);
+    __syncthreads();
+#pragma unroll
+    for (int mm = 0; mm < 16; ++mm) tile[(y * 16 + x) * kPad + mm] = v[mm];
+    __syncthreads();
+#pragma unroll
+    for (int mm = 0; mm < 16; ++mm) d[(y << 8) + x + 16 * mm] = tile[(y * 16 + mm) * kPad + x];
+}
+
+// inverse pass over 256-word blocks (half-distances 1..128): reads src, writes dst
+__global__ void __launch_bounds__(256) k_ntt16_blocks_inv(u64 *dst, const u64 *src, size_t src_stride, int nlimb,
+                                                           LimbMap m, Tables T) {
+    __shared__ u64 tile[256 * kPad];
+    const int limb = blockIdx.y;
+    const int pi = m.p[limb % nlimb];
+    const u64 q = T.primes[pi].q;
+    const u64 *W = T.iw + ((size_t)pi << 16), *Ws = T.iw_sh + ((size_t)pi << 16);
+    const u64 *s_in = src + (size_t)(limb / nlimb) * src_stride + ((size_t)(limb % nlimb) << 16) +
+                      ((size_t)blockIdx.x << 12);
+    u64 *d = dst + ((size_t)limb << 16) + ((size_t)blockIdx.x << 12);
+    const int blk0 = blockIdx.x * 16;
+    const int x = threadIdx.x & 15, y = threadIdx.x >> 4;
+    u64 v[16];
+#pragma unroll
+    for (int mm = 0; mm < 16; ++mm) tile[(y * 16 + mm) * kPad + x] = s_in[(y << 8) + x + 16 * mm];
+    __syncthreads();
+    // phase A: block y, words 16 x + m; half-distances 1..8.  Group index of
+    // word J for distance t: J >> (lt + 1), J = 256 (blk0 + y) + 16 x + m
+#pragma unroll
+    for (int mm = 0; mm < 16; ++mm) v[mm] = tile[(y * 16 + x) * kPad + mm];
+    inv16(v, W, Ws, 16, 0, (blk0 + y) * 16 + x, q);
+#pragma unroll
+    for (int mm = 0; mm < 16; ++mm) tile[(y * 16 + x) * kPad + mm] = v[mm];
+    __syncthreads();
+    // phase B: block y, words x + 16 m; half-distances 16..128
+#pragma unroll
+    for (int mm = 0; mm < 16; ++mm) v[mm] = tile[(y * 16 + mm) * kPad + x];
+    inv16(v, W, Ws, 16, 4, blk0 + y, q);
+#pragma unroll
+    for (int mm = 0; mm < 16; ++mm) d[(y << 8) + x + 16 * mm] = v[mm];
+}
+
+// inverse pass over rows (half-distances 256..32768, row distances 1..128), in
+// place, with the final multiplication by N^-1
+__global__ void __launch_bounds__(256) k_ntt16_rows_inv(u64 *data, int nlimb, LimbMap m, Tables T) {
+    __shared__ u64 tile[256 * kPad];
+    const int limb = blockIdx.y;
+    const int pi = m.p[limb % nlimb];
+    const u64 q = T.primes[pi].q;
+    const u64 *W = T.iw + ((size_t)pi << 16), *Ws = T.iw_sh + ((size_t)pi << 16);
+    u64 *d = data + ((size_t)limb << 16);
+    const int c0 = blockIdx.x * 16;
+    const int x = threadIdx.x & 15, y = threadIdx.x >> 4;
+    u64 v[16];
+    // phase A: rows k = 16 y + m (row distances 1..8 = global 256..2048)
+#pragma unroll
+    for (int mm = 0; mm < 16; ++mm) v[mm] = d[((16 * y + mm) << 8) + c0 + x];
+    inv16(v, W, Ws, 16, 8, y, q);
+#pragma unroll
+    for (int mm = 0; mm < 16; ++mm) tile[(16 * y + mm) * kPad + x] = v[mm];
+    __syncthreads();
+    // phase B: rows k = y + 16 m (row distances 16..128)
+#pragma unroll
+    for (int mm = 0; mm < 16; ++mm) v[mm] = tile[(y + 16 * mm) * kPad + x];
+    inv16(v, W, Ws, 16, 12, 0, q);
+    const u64 ni = T.ninv[pi], nis = T.ninv_sh[pi];
+#pragma unroll
+    for (int mm = 0; mm < 16; ++mm) d[((y + 16 * mm) << 8) + c0 + x] = mul_shoup(v[mm], ni, nis, q);
+}
+
+void ntt_oop(const Tables &T, uint64_t *dst, const uint64_t *src, size_t src_poly_stride, int nlimb, int npoly,
+             const LimbMap &m, bool inverse, hipStream_t s) {
+    const int total = nlimb * npoly;
+    if (total == 0) return;
+    const size_t N = (size_t)1 << T.logN;
+    if (src_poly_stride == 0) src_poly_stride = (size_t)nlimb * N;
+    if (T.logN == 16) {
+        dim3 grid(16, total);
+        if (!inverse) {
+            hipLaunchKernelGGL(k_ntt16_rows_fwd, grid, dim3(256), 0, s, dst, src, src_poly_stride, nlimb, m, T);
+            hipLaunchKernelGGL(k_ntt16_blocks_fwd, grid, dim3(256), 0, s, dst, nlimb, m, T);
+        } else {
+            hipLaunchKernelGGL(k_ntt16_blocks_inv, grid, dim3(256), 0, s, dst, src, src_poly_stride, nlimb, m, T);
+            hipLaunchKernelGGL(k_ntt16_rows_inv, grid, dim3(256), 0, s, dst, nlimb, m, T);
+        }
+        return;
+    }
+    if (dst != src || src_poly_stride != (size_t)nlimb * N)
+        for (int p = 0; p < npoly; ++p)
+            (void)hipMemcpyAsync(dst + (size_t)p * nlimb * N, src + (size_t)p * src_poly_stride, (size_t)nlimb * N * 8,
+                                 hipMemcpyDeviceToDevice, s);
+    ntt(T, dst, nlimb, npoly, m, inverse, s);
+}
+
 void ntt(const Tables &T, uint64_t *data, int nlimb, int npoly, const LimbMap &m, bool inverse,
          hipStream_t s) {
     const int logN = T.logN;
+    if (logN == 16) {
+        ntt_oop(T, data, data, 0, nlimb, npoly, m, inverse, s);
+        return;
+    }
     const int N = 1 << logN;
     const int total = nlimb * npoly;
     if (total == 0) return;

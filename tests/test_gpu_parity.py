@@ -187,6 +187,8 @@ def test_cheb_newton_invsqrt_chain_small(pair12, oracle_mod):
     same(gh, oh)
     gn, on = g.newton_step(gy, gh), o.newton_step(oy, oh)
     same(gn, on)
+    gr, orr = g.newton_step(gy, gx, raw_x=True), o.newton_step(oy, ox, raw_x=True)
+    same(gr, orr)
     gi = g.invsqrt(gx, 15, 2, a=2 ** -8, b=1.0)
     oi = o.invsqrt(ox, 15, 2, 2 ** -8, 1.0)
     same(gi, oi)
@@ -237,3 +239,18 @@ def test_full_size_keyswitch_levels(pair16, lvl):
     ga, oa = g.ct_import(w, lvl, 2.0 ** 40), o.ct_import(w, lvl, 2.0 ** 40)
     same(g.hmult(ga, ga), o.hmult(oa, oa))
     same(g.rescale(ga), o.rescale(oa))
+
+
+def test_full_size_invsqrt_bit_exact_and_mre(pair16):
+    """CryptoInvSqrt at N = 2^16, degree 31, 3 Newton steps, x log-uniform in
+    [2^-10, 1] encrypted at level 13 with scale 2^50 (enough levels that no
+    bootstrapping is needed): result bit-exact, MRE <= 3.1e-8."""
+    g, o = pair16
+    x = inputs.log_uniform(g.n, 2 ** -10, 1.0, 1)
+    gx, ox = g.encrypt(x, 13, 2.0 ** 50, 3), o.encrypt(x, 13, 2.0 ** 50, 3)
+    gy = g.invsqrt(gx, 31, 3)
+    oy = o.invsqrt(ox, 31, 3, 2 ** -10, 1.0)
+    same(gy, oy)
+    ref = 1 / np.sqrt(x)
+    mre = np.mean(np.abs(g.decrypt(gy).real - ref) / ref)
+    assert mre <= 3.1e-8, mre
