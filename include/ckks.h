@@ -119,7 +119,8 @@ ckks_status ckks_encrypt(ckks_ctx *ctx, const double *x, uint32_t n, uint32_t le
  * `re`, imaginary parts to `im`; `im` may be NULL). */
 ckks_status ckks_decrypt(ckks_ctx *ctx, const ckks_ct *ct, double *re, double *im);
 
-/* Ciphertext transfer: host words [2][level+1][N] (fully reduced) <-> device. */
+/* Ciphertext transfer: host words [B][2][level+1][N] (fully reduced) <->
+ * device (import creates single ciphertexts, B = 1; export writes all B). */
 ckks_status ckks_ct_import(ckks_ctx *ctx, const uint64_t *host, uint32_t level, double scale,
                            ckks_ct **out);
 ckks_status ckks_ct_export(ckks_ctx *ctx, const ckks_ct *ct, uint64_t *host);
@@ -128,6 +129,18 @@ void *ckks_ct_device_ptr(const ckks_ct *ct);
 int32_t ckks_ct_level(const ckks_ct *ct);
 double ckks_ct_scale(const ckks_ct *ct);
 void ckks_ct_free(ckks_ctx *ctx, ckks_ct *ct);
+/*
+ * Batches.  A ciphertext object may hold B >= 1 ciphertexts at one level and
+ * scale, laid out [B][2][level+1][N]; every operation below accepts such an
+ * object (all its operands must hold the same B) and runs each step as one
+ * launch over all B, reading each switching-key word once per batch.
+ * ckks_ct_pack copies n single ciphertexts (same level, same scale) into one
+ * batch; ckks_ct_unpack writes its B members to outs[0..B-1] as new single
+ * ciphertexts; ckks_ct_count returns B.
+ */
+ckks_status ckks_ct_pack(ckks_ctx *ctx, const ckks_ct *const *cts, uint32_t n, ckks_ct **out);
+ckks_status ckks_ct_unpack(ckks_ctx *ctx, const ckks_ct *batch, ckks_ct **outs);
+int32_t ckks_ct_count(const ckks_ct *ct);
 
 /* Add_C / Sub_C: equal levels, |s_a/s_b - 1| <= 2^-30 (else CKKS_E_SCALE);
  * result scale s_a. */

@@ -72,6 +72,9 @@ SIGNATURES = {
     "ckks_invsqrt_batch": (C.c_int, [vp, C.POINTER(vp), C.c_uint32, C.c_uint32, C.c_uint32,
                                      C.POINTER(InvsqrtOpts), C.POINTER(vp)]),
     "ckks_ntt_device": (C.c_int, [vp, C.c_void_p, C.c_uint32, u32p, C.c_int]),
+    "ckks_ct_pack": (C.c_int, [vp, C.POINTER(vp), C.c_uint32, C.POINTER(vp)]),
+    "ckks_ct_unpack": (C.c_int, [vp, vp, C.POINTER(vp)]),
+    "ckks_ct_count": (C.c_int32, [vp]),
     "ckks_profile_enable": (C.c_int, [vp, C.c_int]),
     "ckks_profile_read": (C.c_int, [vp, C.c_char_p, u64p, dblp, dblp]),
 }
@@ -124,8 +127,14 @@ class Ciphertext:
     def scale(self):
         return lib().ckks_ct_scale(self.ptr)
 
+    @property
+    def count(self):
+        return lib().ckks_ct_count(self.ptr)
+
     def words(self):
-        out = np.zeros((2, self.level + 1, self.ctx.N), dtype=np.uint64)
+        B = self.count
+        shape = (2, self.level + 1, self.ctx.N) if B == 1 else (B, 2, self.level + 1, self.ctx.N)
+        out = np.zeros(shape, dtype=np.uint64)
         self.ctx._chk(lib().ckks_ct_export(self.ctx.ptr, self.ptr, _p(out, u64p)))
         return out
 
@@ -273,6 +282,16 @@ class Context:
         by = C.c_double()
         self._chk(lib().ckks_profile_read(self.ptr, family.encode(), C.byref(n), C.byref(ms), C.byref(by)))
         return n.value, ms.value, by.value
+
+    def pack(self, cts):
+        arr = (vp * len(cts))(*[x.ptr for x in cts])
+        return self._ct(lib().ckks_ct_pack, arr, len(cts))
+
+    def unpack(self, batch):
+        B = batch.count
+        outs = (vp * B)()
+        self._chk(lib().ckks_ct_unpack(self.ptr, batch.ptr, outs))
+        return [Ciphertext(self, outs[i]) for i in range(B)]
 
     def ntt_device(self, ptr, n_limbs, prime_idx, inverse=False):
         pi = np.ascontiguousarray(prime_idx, dtype=np.uint32)

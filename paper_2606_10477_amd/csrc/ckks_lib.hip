@@ -108,7 +108,8 @@ struct Buf {
 struct ckks_ct {
     int level;
     double scale;
-    Buf buf;   // [2][level+1][N]
+    int B = 1;  // ciphertexts held (all at this level and scale)
+    Buf buf;    // [B][2][level+1][N]
 };
 
 struct SwitchKey {
@@ -377,19 +378,25 @@ const int32_t *perm_for(ckks_ctx *c, int g) {
 // ciphertext helpers
 // ---------------------------------------------------------------------------
 typedef std::unique_ptr<ckks_ct> Ct;
+constexpr uint32_t kMaxBatch = 64;   // ciphertexts per batched launch sequence
 
-Ct ct_new(ckks_ctx *c, int level, double scale) {
+Ct ct_new(ckks_ctx *c, int level, double scale, int B = 1) {
     Ct r(new ckks_ct);
     r->level = level;
     r->scale = scale;
-    r->buf = Buf(c->pool.get(), c->words(level));
+    r->B = B;
+    r->buf = Buf(c->pool.get(), c->words(level) * B);
     return r;
 }
-u64 *poly(const ckks_ctx *c, const ckks_ct *ct, int p) { return ct->buf.p + (size_t)p * (ct->level + 1) * c->N; }
+// poly p of ciphertext b
+u64 *poly(const ckks_ctx *c, const ckks_ct *ct, int p, int b = 0) {
+    return ct->buf.p + ((size_t)b * 2 + p) * (ct->level + 1) * c->N;
+}
 
 Ct ct_copy(ckks_ctx *c, const ckks_ct *a) {
-    Ct r = ct_new(c, a->level, a->scale);
-    hipchk(hipMemcpyAsync(r->buf.p, a->buf.p, c->words(a->level) * 8, hipMemcpyDeviceToDevice, c->stream), "copy");
+    Ct r = ct_new(c, a->level, a->scale, a->B);
+    hipchk(hipMemcpyAsync(r->buf.p, a->buf.p, c->words(a->level) * a->B * 8, hipMemcpyDeviceToDevice, c->stream),
+           "copy");
     return r;
 }
 
@@ -398,19 +405,20 @@ bool scales_match(double a, double b) { return std::fabs(a / b - 1.0) <= 9.31322
 Ct op_addsub(ckks_ctx *c, const ckks_ct *a, const ckks_ct *b, bool sub) {
     if (a->level != b->level) fail(CKKS_E_LEVEL, "level mismatch");
     if (!scales_match(a->scale, b->scale)) fail(CKKS_E_SCALE, "scale mismatch");
-    Ct r = ct_new(c, a->level, a->scale);
-    gpu::add(c->T, r->buf.p, a->buf.p, b->buf.p, a->level + 1, 2, map_q(0, a->level + 1), sub, c->stream);
+    if (a->B != b->B) fail(CKKS_E_PARAM, "batch size mismatch");
+    Ct r = ct_new(c, a->level, a->scale, a->B);
+    gpu::add(c->T, r->buf.p, a->buf.p, b->buf.p, a->level + 1, 2 * a->B, map_q(0, a->level + 1), sub, c->stream);
     return r;
 }
 
 Ct op_mul_int(ckks_ctx *c, const ckks_ct *a, int64_t k, double new_scale) {
-    Ct r = ct_new(c, a->level, new_scale);
+    Ct r = ct_new(c, a->level, new_scale, a->B);
     LimbConsts kc{};
     for (int i = 0; i <= a->level; ++i) {
         kc.v[i] = mod_signed(k, c->q[i]);
         kc.sh[i] = shoup(kc.v[i], c->q[i]);
     }
-    gpu::mul_scalar(c->T, r->buf.p, a->buf.p, kc, a->level + 1, 2, map_q(0, a->level + 1), c->stream);
+    gpu::mul_scalar(c->T, r->buf.p, a->buf.p, kc, a->level + 1, 2 * a->B, map_q(0, a->level + 1), c->stream);
     return r;
 }
 
@@ -424,19 +432,20 @@ Ct op_add_const(ckks_ctx *c, const ckks_ct *a, double value) {
     double kd = std::rint(value * a->scale);
     if (!(std::fabs(kd) < 4.0e18)) fail(CKKS_E_RANGE, "constant out of range");
     const int64_t k = (int64_t)kd;
-    Ct r = ct_new(c, a->level, a->scale);
+    Ct r = ct_new(c, a->level, a->scale, a->B);
     LimbConsts kc{};
     for (int i = 0; i <= a->level; ++i) kc.v[i] = mod_signed(k, c->q[i]);
-    gpu::add_scalar(c->T, r->buf.p, a->buf.p, kc, a->level + 1, 2, map_q(0, a->level + 1), c->stream);
+    gpu::add_scalar(c->T, r->buf.p, a->buf.p, kc, a->level + 1, 2 * a->B, map_q(0, a->level + 1), c->stream);
     return r;
 }
 
 Ct op_drop(ckks_ctx *c, const ckks_ct *a, int level) {
     if (level < 0 || level > a->level) fail(CKKS_E_LEVEL, "bad target level");
-    Ct r = ct_new(c, level, a->scale);
-    const size_t row = (size_t)(level + 1) * c->N * 8;
-    for (int p = 0; p < 2; ++p)
-        hipchk(hipMemcpyAsync(poly(c, r.get(), p), poly(c, a, p), row, hipMemcpyDeviceToDevice, c->stream), "drop");
+    Ct r = ct_new(c, level, a->scale, a->B);
+    const size_t row = (size_t)(level + 1) * c->N * 8, src_pitch = (size_t)(a->level + 1) * c->N * 8;
+    hipchk(hipMemcpy2DAsync(r->buf.p, row, a->buf.p, src_pitch, row, 2 * (size_t)a->B, hipMemcpyDeviceToDevice,
+                            c->stream),
+           "drop");
     return r;
 }
 
@@ -445,60 +454,69 @@ Ct op_rescale(ckks_ctx *c, const ckks_ct *a) {
     const int l = a->level;
     if (l < 1) fail(CKKS_E_LEVEL, "rescale at level 0");
     const size_t N = c->N;
-    Ct r = ct_new(c, l - 1, a->scale / (double)c->q[l]);
-    Buf t(c->pool.get(), 2 * N);
-    ntt_oop_p(c, t.p, a->buf.p + (size_t)l * N, (size_t)(l + 1) * N, 1, 2, map_q(l, 1), true);
-    Buf u(c->pool.get(), 2 * (size_t)l * N);
-    gpu::rescale_lift(c->T, u.p, t.p, l, l, 2, N, c->stream);
-    ntt_p(c, u.p, l, 2, map_q(0, l), false);
+    const int np2 = 2 * a->B;
+    Ct r = ct_new(c, l - 1, a->scale / (double)c->q[l], a->B);
+    Buf t(c->pool.get(), np2 * N);
+    ntt_oop_p(c, t.p, a->buf.p + (size_t)l * N, (size_t)(l + 1) * N, 1, np2, map_q(l, 1), true);
+    Buf u(c->pool.get(), np2 * (size_t)l * N);
+    gpu::rescale_lift(c->T, u.p, t.p, l, l, np2, N, c->stream);
+    ntt_p(c, u.p, l, np2, map_q(0, l), false);
     LimbConsts inv{};
     for (int i = 0; i < l; ++i) {
         inv.v[i] = hm::invmod(c->q[l] % c->q[i], c->q[i]);
         inv.sh[i] = shoup(inv.v[i], c->q[i]);
     }
-    gpu::sub_mul(c->T, r->buf.p, a->buf.p, u.p, inv, l, 2, (size_t)(l + 1) * N, map_q(0, l), c->stream);
+    gpu::sub_mul(c->T, r->buf.p, a->buf.p, u.p, inv, l, np2, (size_t)(l + 1) * N, map_q(0, l), c->stream);
     return r;
 }
 
-// hybrid key switch of d (level l, NTT form); out0/out1 get (o0 + add0, o1 + add1)
-void keyswitch(ckks_ctx *c, int l, const u64 *d, const SwitchKey &key, u64 *out, const u64 *add) {
+// Hybrid key switch of nct polynomials d (level l, NTT form; ciphertext b's
+// polynomial at d + b * d_stride).  out ([nct][2][l+1][N]) receives
+// (o0, o1) plus add[b][p] for the polys p selected by add_mask.
+void keyswitch(ckks_ctx *c, int l, const u64 *d, size_t d_stride, int nct, const SwitchKey &key, u64 *out,
+               const u64 *add, int add_mask) {
     const size_t N = c->N;
     const int nq = l + 1, ne = nq + c->K;
     const int beta = (nq + c->alpha - 1) / c->alpha;
-    // algorithmic bytes: d (nq limbs) in, key (2 beta ne limbs) in, result (2 nq limbs) out
-    ProfScope ps(c, "keyswitch", 8.0 * (double)N * ((double)nq + 2.0 * beta * ne + 2.0 * nq));
+    // algorithmic bytes: d (nq limbs) in, key (2 beta ne limbs) in once, result (2 nq limbs) out, per ciphertext
+    ProfScope ps(c, "keyswitch", 8.0 * (double)N * ((double)nct * nq + 2.0 * beta * ne + 2.0 * nct * nq));
     Pool *P = c->pool.get();
-    Buf dc(P, (size_t)nq * N);
-    ntt_oop_p(c, dc.p, d, 0, nq, 1, map_q(0, nq), true);
+    Buf dc(P, (size_t)nct * nq * N);
+    ntt_oop_p(c, dc.p, d, d_stride, nq, nct, map_q(0, nq), true);
     std::vector<Buf> ext;
+    ext.reserve(beta);
     gpu::InnerArgs ia{};
     ia.ndig = beta;
+    ia.nct = nct;
     for (int j = 0; j < beta; ++j) {
         ConvTable *t = modup_table(c, l, j);
-        ext.emplace_back(P, (size_t)t->dout * N);
+        ext.emplace_back(P, (size_t)nct * t->dout * N);
         gpu::BconvArgs ba{t->pin, t->pout, t->din, t->dout, t->hinv.p, t->hinv_sh.p, t->mat.p};
         const int lo = j * c->alpha;
-        gpu::bconv(c->T, ext.back().p, dc.p + (size_t)lo * N, ba, 1, 0, 0, c->stream);
-        ntt_p(c, ext.back().p, t->dout, 1, t->pout, false);
+        gpu::bconv(c->T, ext.back().p, dc.p + (size_t)lo * N, ba, nct, (size_t)nq * N, (size_t)t->dout * N, c->stream);
+        ntt_p(c, ext.back().p, t->dout, nct, t->pout, false);
         ia.lo[j] = lo;
         ia.hi[j] = lo + t->din;
         ia.ext[j] = ext.back().p;
+        ia.ext_stride[j] = (size_t)t->dout * N;
     }
     ia.dsrc = d;
+    ia.dsrc_stride = d_stride;
     ia.key = key.k.p;
     ia.np = c->np;
     ia.m = map_ext(c, l);
     ia.ne = ne;
-    Buf acc(P, 2 * (size_t)ne * N);
+    Buf acc(P, (size_t)nct * 2 * ne * N);
     gpu::key_inner(c->T, acc.p, ia, c->stream);
-    // ModDown of both polys
+    // ModDown of all 2 nct polys
     ConvTable *md = moddown_table(c, l);
-    Buf y(P, 2 * (size_t)c->K * N);
-    ntt_oop_p(c, y.p, acc.p + (size_t)nq * N, (size_t)ne * N, c->K, 2, md->pin, true);
-    Buf z(P, 2 * (size_t)nq * N);
+    const int np2 = 2 * nct;
+    Buf y(P, (size_t)np2 * c->K * N);
+    ntt_oop_p(c, y.p, acc.p + (size_t)nq * N, (size_t)ne * N, c->K, np2, md->pin, true);
+    Buf z(P, (size_t)np2 * nq * N);
     gpu::BconvArgs bd{md->pin, md->pout, md->din, md->dout, md->hinv.p, md->hinv_sh.p, md->mat.p};
-    gpu::bconv(c->T, z.p, y.p, bd, 2, (size_t)c->K * N, (size_t)nq * N, c->stream);
-    ntt_p(c, z.p, nq, 2, map_q(0, nq), false);
+    gpu::bconv(c->T, z.p, y.p, bd, np2, (size_t)c->K * N, (size_t)nq * N, c->stream);
+    ntt_p(c, z.p, nq, np2, map_q(0, nq), false);
     LimbConsts pinv{};
     std::vector<int> pidx;
     for (int k = 0; k < c->K; ++k) pidx.push_back(c->L + 1 + k);
@@ -506,37 +524,33 @@ void keyswitch(ckks_ctx *c, int l, const u64 *d, const SwitchKey &key, u64 *out,
         pinv.v[i] = hm::invmod(prod_mod(c, pidx, -1, c->q[i]), c->q[i]);
         pinv.sh[i] = shoup(pinv.v[i], c->q[i]);
     }
-    gpu::moddown_finish(c->T, out, acc.p, (size_t)ne * N, z.p, add, pinv, nq, map_q(0, nq), c->stream);
+    gpu::moddown_finish(c->T, out, acc.p, (size_t)ne * N, z.p, add, add_mask, pinv, nq, nct, map_q(0, nq), c->stream);
 }
 
 Ct op_hmult(ckks_ctx *c, const ckks_ct *a, const ckks_ct *b) {
     if (!c->have_keys) fail(CKKS_E_NOKEY, "no keys");
     if (a->level != b->level) fail(CKKS_E_LEVEL, "level mismatch");
-    const int l = a->level, nq = l + 1;
+    if (a->B != b->B) fail(CKKS_E_PARAM, "batch size mismatch");
+    const int l = a->level, nq = l + 1, B = a->B;
     const size_t N = c->N;
-    Ct r = ct_new(c, l, a->scale * b->scale);
-    Buf d(c->pool.get(), 3 * (size_t)nq * N);
-    u64 *d0 = d.p, *d1 = d.p + (size_t)nq * N, *d2 = d.p + 2 * (size_t)nq * N;
-    gpu::tensor(c->T, d0, d1, d2, poly(c, a, 0), poly(c, a, 1), poly(c, b, 0), poly(c, b, 1), nq, map_q(0, nq),
-                c->stream);
-    keyswitch(c, l, d2, c->relin, r->buf.p, d0);   // (d0, d1) are contiguous like (r0, r1)
+    Ct r = ct_new(c, l, a->scale * b->scale, B);
+    Buf d01(c->pool.get(), (size_t)B * 2 * nq * N), d2(c->pool.get(), (size_t)B * nq * N);
+    gpu::tensor(c->T, d01.p, d2.p, a->buf.p, b->buf.p, nq, B, map_q(0, nq), c->stream);
+    keyswitch(c, l, d2.p, (size_t)nq * N, B, c->relin, r->buf.p, d01.p, 3);
     return r;
 }
 
 Ct op_automorphism(ckks_ctx *c, const ckks_ct *a, int g) {
     auto it = c->rot.find(g);
     if (it == c->rot.end()) fail(CKKS_E_NOKEY, "missing Galois key");
-    const int nq = a->level + 1;
+    const int nq = a->level + 1, B = a->B;
     const size_t N = c->N;
     const int32_t *perm = perm_for(c, g);
-    Buf s(c->pool.get(), 2 * (size_t)nq * N);
-    gpu::permute(c->T, s.p, a->buf.p, perm, nq, 2, c->stream);
-    Ct r = ct_new(c, a->level, a->scale);
-    // r = (s0 + ks0, ks1): add = (s0, 0)
-    Buf add(c->pool.get(), 2 * (size_t)nq * N);
-    hipchk(hipMemcpyAsync(add.p, s.p, (size_t)nq * N * 8, hipMemcpyDeviceToDevice, c->stream), "aut copy");
-    hipchk(hipMemsetAsync(add.p + (size_t)nq * N, 0, (size_t)nq * N * 8, c->stream), "aut zero");
-    keyswitch(c, a->level, s.p + (size_t)nq * N, it->second, r->buf.p, add.p);
+    Buf s(c->pool.get(), (size_t)B * 2 * nq * N);
+    gpu::permute(c->T, s.p, a->buf.p, perm, nq, 2 * B, c->stream);
+    Ct r = ct_new(c, a->level, a->scale, B);
+    // r = (sigma(c0) + ks0, ks1): key switch sigma(c1), add sigma(c0) to poly 0 only
+    keyswitch(c, a->level, s.p + (size_t)nq * N, (size_t)2 * nq * N, B, it->second, r->buf.p, s.p, 1);
     return r;
 }
 
@@ -863,6 +877,7 @@ Ct op_encrypt(ckks_ctx *c, const double *x, uint32_t n, int level, double scale,
 
 void op_decrypt(ckks_ctx *c, const ckks_ct *ct, double *re, double *im) {
     if (!c->have_keys) fail(CKKS_E_NOKEY, "no keys");
+    if (ct->B != 1) fail(CKKS_E_PARAM, "batched ciphertext object");
     const int nq = ct->level + 1;
     const size_t N = c->N;
     Buf m(c->pool.get(), (size_t)nq * N);
@@ -925,7 +940,7 @@ ckks_status ckks_ctx_create(const ckks_params *p, void *arena, size_t arena_byte
         c->K = (int)p->num_special;
         c->alpha = (int)p->digit_size;
         c->dnum = (c->L + 1 + c->alpha - 1) / c->alpha;
-        if (c->dnum > 64) fail(CKKS_E_PARAM, "too many digits");
+        if (c->dnum > gpu::kMaxDigits) fail(CKKS_E_PARAM, "too many digits");
         c->np = c->L + 1 + c->K;
         c->stream = (hipStream_t)hip_stream;
         c->pool.reset(new Pool(arena, arena_bytes));
@@ -999,7 +1014,8 @@ ckks_status ckks_ct_import(ckks_ctx *c, const uint64_t *host, uint32_t level, do
 ckks_status ckks_ct_export(ckks_ctx *c, const ckks_ct *ct, uint64_t *host) {
     if (!c || !ct || !host) return CKKS_E_PARAM;
     return guard(c, [&] {
-        hipchk(hipMemcpyAsync(host, ct->buf.p, c->words(ct->level) * 8, hipMemcpyDeviceToHost, c->stream), "export");
+        hipchk(hipMemcpyAsync(host, ct->buf.p, c->words(ct->level) * ct->B * 8, hipMemcpyDeviceToHost, c->stream),
+               "export");
         hipchk(hipStreamSynchronize(c->stream), "export sync");
     });
 }
@@ -1109,12 +1125,68 @@ ckks_status ckks_invsqrt_batch(ckks_ctx *c, const ckks_ct *const *xs, uint32_t n
     ckks_invsqrt_opts o = opts ? *opts : default_opts();
     for (uint32_t i = 0; i < n; ++i) outs[i] = nullptr;
     ckks_status st = guard(c, [&] {
-        for (uint32_t i = 0; i < n; ++i) outs[i] = op_invsqrt(c, xs[i], (int)degree, (int)iters, o).release();
+        if (n == 0) return;
+        for (uint32_t i = 0; i < n; ++i) {
+            if (!xs[i] || xs[i]->B != 1) fail(CKKS_E_PARAM, "bad input ciphertext");
+            if (xs[i]->level != xs[0]->level || xs[i]->scale != xs[0]->scale)
+                fail(CKKS_E_PARAM, "batched inputs must share level and scale");
+        }
+        const size_t w = c->words(xs[0]->level);
+        for (uint32_t off = 0; off < n; off += kMaxBatch) {
+            const int B = (int)std::min<uint32_t>(kMaxBatch, n - off);
+            Ct xb = ct_new(c, xs[0]->level, xs[0]->scale, B);
+            for (int b = 0; b < B; ++b)
+                hipchk(hipMemcpyAsync(xb->buf.p + (size_t)b * w, xs[off + b]->buf.p, w * 8, hipMemcpyDeviceToDevice,
+                                      c->stream),
+                       "gather");
+            Ct yb = op_invsqrt(c, xb.get(), (int)degree, (int)iters, o);
+            const size_t wy = c->words(yb->level);
+            for (int b = 0; b < B; ++b) {
+                Ct y1 = ct_new(c, yb->level, yb->scale, 1);
+                hipchk(hipMemcpyAsync(y1->buf.p, yb->buf.p + (size_t)b * wy, wy * 8, hipMemcpyDeviceToDevice,
+                                      c->stream),
+                       "scatter");
+                outs[off + b] = y1.release();
+            }
+        }
     });
     if (st != CKKS_OK)
         for (uint32_t i = 0; i < n; ++i) { delete outs[i]; outs[i] = nullptr; }
     return st;
 }
+ckks_status ckks_ct_pack(ckks_ctx *c, const ckks_ct *const *cts, uint32_t n, ckks_ct **out) {
+    if (!c || !cts || n == 0) return CKKS_E_PARAM;
+    return guard_out(c, out, [&] {
+        for (uint32_t i = 0; i < n; ++i) {
+            if (!cts[i] || cts[i]->B != 1) fail(CKKS_E_PARAM, "pack takes single ciphertexts");
+            if (cts[i]->level != cts[0]->level || cts[i]->scale != cts[0]->scale)
+                fail(CKKS_E_PARAM, "packed ciphertexts must share level and scale");
+        }
+        const size_t w = c->words(cts[0]->level);
+        Ct r = ct_new(c, cts[0]->level, cts[0]->scale, (int)n);
+        for (uint32_t i = 0; i < n; ++i)
+            hipchk(hipMemcpyAsync(r->buf.p + i * w, cts[i]->buf.p, w * 8, hipMemcpyDeviceToDevice, c->stream), "pack");
+        return r;
+    });
+}
+ckks_status ckks_ct_unpack(ckks_ctx *c, const ckks_ct *batch, ckks_ct **outs) {
+    if (!c || !batch || !outs) return CKKS_E_PARAM;
+    for (int i = 0; i < batch->B; ++i) outs[i] = nullptr;
+    ckks_status st = guard(c, [&] {
+        const size_t w = c->words(batch->level);
+        for (int i = 0; i < batch->B; ++i) {
+            Ct r = ct_new(c, batch->level, batch->scale, 1);
+            hipchk(hipMemcpyAsync(r->buf.p, batch->buf.p + i * w, w * 8, hipMemcpyDeviceToDevice, c->stream),
+                   "unpack");
+            outs[i] = r.release();
+        }
+    });
+    if (st != CKKS_OK)
+        for (int i = 0; i < batch->B; ++i) { delete outs[i]; outs[i] = nullptr; }
+    return st;
+}
+int32_t ckks_ct_count(const ckks_ct *ct) { return ct ? ct->B : 0; }
+
 ckks_status ckks_ntt_device(ckks_ctx *c, uint64_t *data, uint32_t n_limbs, const uint32_t *prime_idx, int inverse) {
     if (!c || !data || !prime_idx || n_limbs == 0) return CKKS_E_PARAM;
     return guard(c, [&] {

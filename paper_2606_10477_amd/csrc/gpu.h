@@ -54,16 +54,16 @@ struct LimbConsts {
 };
 void mul_scalar(const Tables &T, uint64_t *out, const uint64_t *a, const LimbConsts &c, int nlimb,
                 int npoly, const LimbMap &m, hipStream_t s);
-// out[l] = a[l] + c[l] (first poly only; the remaining polys copied)
+// out[l] = a[l] + c[l] on even-indexed polys (poly 0 of each ciphertext); odd polys copied
 void add_scalar(const Tables &T, uint64_t *out, const uint64_t *a, const LimbConsts &c, int nlimb,
                 int npoly, const LimbMap &m, hipStream_t s);
 // out[l][j] = a[l][perm[j]]
 void permute(const Tables &T, uint64_t *out, const uint64_t *a, const int32_t *perm, int nlimb, int npoly,
              hipStream_t s);
-// tensor: d0 = a0 b0, d1 = a0 b1 + a1 b0, d2 = a1 b1 (nlimb limbs each)
-void tensor(const Tables &T, uint64_t *d0, uint64_t *d1, uint64_t *d2, const uint64_t *a0,
-            const uint64_t *a1, const uint64_t *b0, const uint64_t *b1, int nlimb, const LimbMap &m,
-            hipStream_t s);
+// tensor of nct ciphertext pairs a, b ([nct][2][nlimb][N]):
+// d01 = (a0 b0, a0 b1 + a1 b0) laid out [nct][2][nlimb][N], d2 = a1 b1 [nct][nlimb][N]
+void tensor(const Tables &T, uint64_t *d01, uint64_t *d2, const uint64_t *a, const uint64_t *b, int nlimb, int nct,
+            const LimbMap &m, hipStream_t s);
 // out = a * b (pointwise), nlimb x npoly
 void mul_pointwise(const Tables &T, uint64_t *out, const uint64_t *a, const uint64_t *b, int nlimb,
                    int npoly, const LimbMap &m, hipStream_t s);
@@ -98,13 +98,19 @@ struct BconvArgs {
 void bconv(const Tables &T, uint64_t *out, const uint64_t *in, const BconvArgs &a, int npoly,
            size_t in_poly_stride, size_t out_poly_stride, hipStream_t s);
 
-// Key inner product: acc[b][e] = sum_j x_j[e] * key_j[b][prime(e)] for b = 0,1.
-// x_j[e] = e in [lo_j, hi_j) ? dsrc[e] : ext_j[compact(e)], compact(e) = e < lo_j ? e : e - (hi_j - lo_j).
+// Key inner product over nct ciphertexts: acc[ct][p][e] = sum_j x_j[ct][e] * key_j[p][prime(e)]
+// (p = 0, 1; acc laid out [nct][2][ne][N]), where
+// x_j[ct][e] = e in [lo_j, hi_j) ? dsrc[ct][e] : ext_j[ct][compact(e)],
+// compact(e) = e < lo_j ? e : e - (hi_j - lo_j).  Each key word is loaded once
+// per thread and used for every ciphertext of the batch.
+constexpr int kMaxDigits = 32;
 struct InnerArgs {
-    int ndig;
-    int lo[64], hi[64];
-    const uint64_t *ext[64];
+    int ndig, nct;
+    int lo[kMaxDigits], hi[kMaxDigits];
+    const uint64_t *ext[kMaxDigits];
+    size_t ext_stride[kMaxDigits];
     const uint64_t *dsrc;
+    size_t dsrc_stride;
     const uint64_t *key;   // [dnum][2][np][N]
     int np;
     LimbMap m;             // extended basis map (Q_l then P)
@@ -112,9 +118,10 @@ struct InnerArgs {
 };
 void key_inner(const Tables &T, uint64_t *acc, const InnerArgs &a, hipStream_t s);
 
-// ModDown finish: out_b,i = (acc_b,i - z_b,i) * Pinv_i (+ add_b,i if add != null)
+// ModDown finish over nct ciphertexts (2 polys each, poly index p = 2 ct + b):
+// out_p,i = (acc_p,i - z_p,i) * Pinv_i, plus add_p,i when bit (p & 1) of add_mask is set.
 void moddown_finish(const Tables &T, uint64_t *out, const uint64_t *acc, size_t acc_poly_stride,
-                    const uint64_t *z, const uint64_t *add, const LimbConsts &pinv, int nlimb,
+                    const uint64_t *z, const uint64_t *add, int add_mask, const LimbConsts &pinv, int nlimb, int nct,
                     const LimbMap &m, hipStream_t s);
 
 // decryption: m = c0 + c1 * s

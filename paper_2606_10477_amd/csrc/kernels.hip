@@ -423,13 +423,19 @@ static inline dim3 grid_for(size_t n) {
     if (b > 65535u * 8u) b = 65535u * 8u;
     return dim3((unsigned)b);
 }
+// row = word index >> logN (< 2^31); poly / limb split in 32-bit integer arithmetic
+#define ROW_SPLIT(i, logN, nlimb, poly, limb)               \
+    const uint32_t row_ = (uint32_t)((i) >> (logN));        \
+    const uint32_t poly = row_ / (uint32_t)(nlimb);         \
+    const uint32_t limb = row_ - poly * (uint32_t)(nlimb);
 #define GRID_LOOP(idx, total) \
     for (size_t idx = (size_t)blockIdx.x * blockDim.x + threadIdx.x; idx < (total); idx += (size_t)gridDim.x * blockDim.x)
 
 __global__ void k_add(u64 *out, const u64 *a, const u64 *b, int logN, int nlimb, size_t total, LimbMap m,
                       Tables T, int sub) {
     GRID_LOOP(i, total) {
-        int limb = (int)((i >> logN) % nlimb);
+        ROW_SPLIT(i, logN, nlimb, poly, limb)
+        (void)poly;
         u64 q = T.primes[m.p[limb]].q;
         out[i] = sub ? sub_mod(a[i], b[i], q) : add_mod(a[i], b[i], q);
     }
@@ -444,7 +450,8 @@ void add(const Tables &T, uint64_t *out, const uint64_t *a, const uint64_t *b, i
 __global__ void k_mul_scalar(u64 *out, const u64 *a, LimbConsts c, int logN, int nlimb, size_t total, LimbMap m,
                              Tables T) {
     GRID_LOOP(i, total) {
-        int limb = (int)((i >> logN) % nlimb);
+        ROW_SPLIT(i, logN, nlimb, poly, limb)
+        (void)poly;
         u64 q = T.primes[m.p[limb]].q;
         out[i] = mul_shoup(a[i], c.v[limb], c.sh[limb], q);
     }
@@ -458,10 +465,9 @@ void mul_scalar(const Tables &T, uint64_t *out, const uint64_t *a, const LimbCon
 
 __global__ void k_add_scalar(u64 *out, const u64 *a, LimbConsts c, int logN, int nlimb, size_t total, LimbMap m,
                              Tables T) {
-    const size_t first = (size_t)nlimb << logN;
     GRID_LOOP(i, total) {
-        if (i < first) {
-            int limb = (int)(i >> logN);
+        ROW_SPLIT(i, logN, nlimb, poly, limb)
+        if ((poly & 1) == 0) {
             u64 q = T.primes[m.p[limb]].q;
             out[i] = add_mod(a[i], c.v[limb], q);
         } else {
@@ -490,30 +496,37 @@ void permute(const Tables &T, uint64_t *out, const uint64_t *a, const int32_t *p
     hipLaunchKernelGGL(k_permute, grid_for(total), dim3(256), 0, s, out, a, perm, T.logN, total);
 }
 
-__global__ void k_tensor(u64 *d0, u64 *d1, u64 *d2, const u64 *a0, const u64 *a1, const u64 *b0, const u64 *b1,
-                         int logN, size_t total, LimbMap m, Tables T) {
+__global__ void k_tensor(u64 *d01, u64 *d2, const u64 *a, const u64 *b, int logN, int nlimb, size_t total,
+                         LimbMap m, Tables T) {
+    const size_t per = (size_t)nlimb << logN;   // words per poly
+    const size_t mask = ((size_t)1 << logN) - 1;
     GRID_LOOP(i, total) {
-        const DevPrime P = T.primes[m.p[i >> logN]];
-        u64 x0 = a0[i], x1 = a1[i], y0 = b0[i], y1 = b1[i];
-        d0[i] = mul_mod(x0, y0, P);
+        ROW_SPLIT(i, logN, nlimb, ct, limb)
+        const DevPrime P = T.primes[m.p[limb]];
+        const size_t rem = ((size_t)limb << logN) | (i & mask);
+        const size_t base = (size_t)ct * 2 * per + rem;
+        u64 x0 = a[base], x1 = a[base + per], y0 = b[base], y1 = b[base + per];
+        d01[base] = mul_mod(x0, y0, P);
         u64 hi = 0, lo = 0;
         mac128(hi, lo, x0, y1);
         mac128(hi, lo, x1, y0);
-        d1[i] = reduce128(hi, lo, P);
+        d01[base + per] = reduce128(hi, lo, P);
         d2[i] = mul_mod(x1, y1, P);
     }
 }
-void tensor(const Tables &T, uint64_t *d0, uint64_t *d1, uint64_t *d2, const uint64_t *a0, const uint64_t *a1,
-            const uint64_t *b0, const uint64_t *b1, int nlimb, const LimbMap &m, hipStream_t s) {
-    size_t total = (size_t)nlimb << T.logN;
+void tensor(const Tables &T, uint64_t *d01, uint64_t *d2, const uint64_t *a, const uint64_t *b, int nlimb, int nct,
+            const LimbMap &m, hipStream_t s) {
+    size_t total = ((size_t)nlimb * nct) << T.logN;
     if (!total) return;
-    hipLaunchKernelGGL(k_tensor, grid_for(total), dim3(256), 0, s, d0, d1, d2, a0, a1, b0, b1, T.logN, total, m, T);
+    hipLaunchKernelGGL(k_tensor, grid_for(total), dim3(256), 0, s, d01, d2, a, b, T.logN, nlimb, total, m, T);
 }
 
 __global__ void k_mul_pointwise(u64 *out, const u64 *a, const u64 *b, int logN, int nlimb, size_t total, LimbMap m,
                                 Tables T) {
     GRID_LOOP(i, total) {
-        const DevPrime P = T.primes[m.p[(i >> logN) % nlimb]];
+        ROW_SPLIT(i, logN, nlimb, poly, limb)
+        (void)poly;
+        const DevPrime P = T.primes[m.p[limb]];
         out[i] = mul_mod(a[i], b[i], P);
     }
 }
@@ -586,12 +599,10 @@ __global__ void k_rescale_lift(u64 *u, const u64 *t, int top, int logN, int nlim
     const DevPrime Pt = T.primes[top];
     const u64 half = (Pt.q - 1) >> 1;
     GRID_LOOP(i, total) {
-        size_t poly = i / ((size_t)nlimb * N);
-        size_t rem = i - poly * nlimb * N;
-        int limb = (int)(rem >> logN);
-        size_t j = rem & (N - 1);
+        ROW_SPLIT(i, logN, nlimb, poly, limb)
+        const size_t j = i & (N - 1);
         const DevPrime P = T.primes[limb];
-        u64 v = t[poly * t_stride + j];
+        u64 v = t[(size_t)poly * t_stride + j];
         u64 r = reduce64(v, P);
         if (v > half) r = sub_mod(r, reduce64(Pt.q, P), P.q);
         u[i] = r;
@@ -609,11 +620,10 @@ __global__ void k_sub_mul(u64 *out, const u64 *c, const u64 *u, LimbConsts inv, 
                           size_t c_stride, LimbMap m, Tables T) {
     const size_t N = (size_t)1 << logN;
     GRID_LOOP(i, total) {
-        size_t poly = i / ((size_t)nlimb * N);
-        size_t rem = i - poly * nlimb * N;
-        int limb = (int)(rem >> logN);
+        ROW_SPLIT(i, logN, nlimb, poly, limb)
+        const size_t rem = ((size_t)limb << logN) | (i & (N - 1));
         u64 q = T.primes[m.p[limb]].q;
-        out[i] = mul_shoup(sub_mod(c[poly * c_stride + rem], u[i], q), inv.v[limb], inv.sh[limb], q);
+        out[i] = mul_shoup(sub_mod(c[(size_t)poly * c_stride + rem], u[i], q), inv.v[limb], inv.sh[limb], q);
     }
 }
 void sub_mul(const Tables &T, uint64_t *out, const uint64_t *c, const uint64_t *u, const LimbConsts &inv, int nlimb,
@@ -660,25 +670,28 @@ void bconv(const Tables &T, uint64_t *out, const uint64_t *in, const BconvArgs &
 __global__ void k_key_inner(u64 *acc, InnerArgs a, int logN, size_t total, Tables T) {
     const size_t N = (size_t)1 << logN;
     GRID_LOOP(i, total) {
-        int e = (int)(i >> logN);
-        size_t j = i & (N - 1);
-        int pi = a.m.p[e];
+        const int e = (int)(i >> logN);
+        const size_t j = i & (N - 1);
+        const int pi = a.m.p[e];
         const DevPrime P = T.primes[pi];
-        u64 h0 = 0, l0 = 0, h1 = 0, l1 = 0;
-        for (int d = 0; d < a.ndig; ++d) {
-            u64 x;
-            if (e >= a.lo[d] && e < a.hi[d]) x = a.dsrc[(size_t)e * N + j];
-            else {
-                int ce = e < a.lo[d] ? e : e - (a.hi[d] - a.lo[d]);
-                x = a.ext[d][(size_t)ce * N + j];
+        for (int b = 0; b < a.nct; ++b) {
+            u64 h0 = 0, l0 = 0, h1 = 0, l1 = 0;
+            for (int d = 0; d < a.ndig; ++d) {
+                u64 x;
+                if (e >= a.lo[d] && e < a.hi[d]) x = a.dsrc[b * a.dsrc_stride + (size_t)e * N + j];
+                else {
+                    int ce = e < a.lo[d] ? e : e - (a.hi[d] - a.lo[d]);
+                    x = a.ext[d][b * a.ext_stride[d] + (size_t)ce * N + j];
+                }
+                const u64 *k0 = a.key + (((size_t)d * 2 + 0) * a.np + pi) * N;
+                const u64 *k1 = a.key + (((size_t)d * 2 + 1) * a.np + pi) * N;
+                mac128(h0, l0, x, k0[j]);
+                mac128(h1, l1, x, k1[j]);
             }
-            const u64 *k0 = a.key + (((size_t)d * 2 + 0) * a.np + pi) * N;
-            const u64 *k1 = a.key + (((size_t)d * 2 + 1) * a.np + pi) * N;
-            mac128(h0, l0, x, k0[j]);
-            mac128(h1, l1, x, k1[j]);
+            u64 *o = acc + (size_t)b * 2 * a.ne * N;
+            o[i] = reduce128(h0, l0, P);
+            o[(size_t)a.ne * N + i] = reduce128(h1, l1, P);
         }
-        acc[i] = reduce128(h0, l0, P);
-        acc[(size_t)a.ne * N + i] = reduce128(h1, l1, P);
     }
 }
 void key_inner(const Tables &T, uint64_t *acc, const InnerArgs &a, hipStream_t s) {
@@ -687,23 +700,24 @@ void key_inner(const Tables &T, uint64_t *acc, const InnerArgs &a, hipStream_t s
 }
 
 __global__ void k_moddown_finish(u64 *out, const u64 *acc, size_t acc_stride, const u64 *z, const u64 *add,
-                                 LimbConsts pinv, int logN, int nlimb, size_t total, LimbMap m, Tables T) {
+                                 int add_mask, LimbConsts pinv, int logN, int nlimb, size_t total, LimbMap m,
+                                 Tables T) {
     const size_t N = (size_t)1 << logN;
     GRID_LOOP(i, total) {
-        size_t poly = i / ((size_t)nlimb * N);
-        size_t rem = i - poly * nlimb * N;
-        int limb = (int)(rem >> logN);
+        ROW_SPLIT(i, logN, nlimb, poly, limb)
+        const size_t rem = ((size_t)limb << logN) | (i & (N - 1));
         u64 q = T.primes[m.p[limb]].q;
-        u64 v = mul_shoup(sub_mod(acc[poly * acc_stride + rem], z[i], q), pinv.v[limb], pinv.sh[limb], q);
-        if (add) v = add_mod(v, add[i], q);
+        u64 v = mul_shoup(sub_mod(acc[(size_t)poly * acc_stride + rem], z[i], q), pinv.v[limb], pinv.sh[limb], q);
+        if (add && ((add_mask >> (poly & 1)) & 1)) v = add_mod(v, add[i], q);
         out[i] = v;
     }
 }
 void moddown_finish(const Tables &T, uint64_t *out, const uint64_t *acc, size_t acc_poly_stride, const uint64_t *z,
-                    const uint64_t *add, const LimbConsts &pinv, int nlimb, const LimbMap &m, hipStream_t s) {
-    size_t total = ((size_t)nlimb * 2) << T.logN;
-    hipLaunchKernelGGL(k_moddown_finish, grid_for(total), dim3(256), 0, s, out, acc, acc_poly_stride, z, add, pinv,
-                       T.logN, nlimb, total, m, T);
+                    const uint64_t *add, int add_mask, const LimbConsts &pinv, int nlimb, int nct, const LimbMap &m,
+                    hipStream_t s) {
+    size_t total = ((size_t)nlimb * 2 * nct) << T.logN;
+    hipLaunchKernelGGL(k_moddown_finish, grid_for(total), dim3(256), 0, s, out, acc, acc_poly_stride, z, add, add_mask,
+                       pinv, T.logN, nlimb, total, m, T);
 }
 
 __global__ void k_decrypt(u64 *mo, const u64 *c0, const u64 *c1, const u64 *sk, int logN, size_t total, LimbMap m,

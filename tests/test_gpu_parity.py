@@ -202,6 +202,48 @@ def test_cheb_newton_invsqrt_chain_small(pair12, oracle_mod):
         same(g.cheb_eval(gx, cf, 2 ** -8, 1.0), o.cheb_eval(ox, cf, 2 ** -8, 1.0))
 
 
+def _batched_ops_match(g, lvl, seed0):
+    xs = [g.encrypt(inputs.log_uniform(g.n, 2 ** -8, 1.0, seed0 + i), lvl, 2.0 ** 40, seed0 + 10 + i)
+          for i in range(3)]
+    ys = [g.encrypt(inputs.log_uniform(g.n, 2 ** -8, 1.0, seed0 + 20 + i), lvl, 2.0 ** 40, seed0 + 30 + i)
+          for i in range(3)]
+    bx, by = g.pack(xs), g.pack(ys)
+    assert bx.count == 3
+
+    failures = []
+
+    def check(name, batched, singles):
+        parts = g.unpack(batched)
+        for i, (p, s1) in enumerate(zip(parts, singles)):
+            if p.level != s1.level or p.scale != s1.scale:
+                failures.append(f"{name}: member {i} level/scale")
+            elif not np.array_equal(p.words(), s1.words()):
+                failures.append(f"{name}: member {i} differs")
+
+    check("add", g.add(bx, by), [g.add(a, b) for a, b in zip(xs, ys)])
+    check("mul_int", g.mul_int(bx, -5), [g.mul_int(a, -5) for a in xs])
+    check("add_const", g.add_const(bx, 0.25), [g.add_const(a, 0.25) for a in xs])
+    check("drop", g.drop_level(bx, lvl - 2), [g.drop_level(a, lvl - 2) for a in xs])
+    check("rescale", g.rescale(bx), [g.rescale(a) for a in xs])
+    check("level_to", g.level_to(bx, lvl - 3), [g.level_to(a, lvl - 3) for a in xs])
+    check("rotate", g.rotate(bx, 1), [g.rotate(a, 1) for a in xs])
+    check("conjugate", g.conjugate(bx), [g.conjugate(a) for a in xs])
+    check("hmult", g.hmult(bx, by), [g.hmult(a, b) for a, b in zip(xs, ys)])
+    check("hmult_same", g.hmult(bx, bx), [g.hmult(a, a) for a in xs])
+    assert not failures, failures
+
+
+def test_batched_primitives_small(pair12):
+    g, _ = pair12
+    _batched_ops_match(g, 13, 100)
+    _batched_ops_match(g, 3, 200)
+
+
+def test_batched_primitives_full_size(pair16):
+    g, _ = pair16
+    _batched_ops_match(g, 13, 300)
+
+
 def test_batch_equals_single_small(pair12):
     g, o = pair12
     xs = [g.encrypt(inputs.log_uniform(g.n, 2 ** -8, 1.0, 10 + i), 13, 2.0 ** 50, 20 + i) for i in range(3)]
@@ -254,3 +296,13 @@ def test_full_size_invsqrt_bit_exact_and_mre(pair16):
     ref = 1 / np.sqrt(x)
     mre = np.mean(np.abs(g.decrypt(gy).real - ref) / ref)
     assert mre <= 3.1e-8, mre
+
+
+def test_full_size_batch_equals_single(pair16):
+    """A batch of 3 ciphertexts through one launch sequence gives the same
+    words as three single calls (N = 2^16, degree 31, 3 Newton steps)."""
+    g, _ = pair16
+    xs = [g.encrypt(inputs.log_uniform(g.n, 2 ** -10, 1.0, 30 + i), 13, 2.0 ** 50, 40 + i) for i in range(3)]
+    outs = g.invsqrt_batch(xs, 31, 3)
+    for x, y in zip(xs, outs):
+        assert np.array_equal(g.invsqrt(x, 31, 3).words(), y.words())
