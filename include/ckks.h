@@ -115,6 +115,12 @@ int32_t ckks_galois_rotation(const ckks_ctx *ctx, int32_t steps);
  */
 ckks_status ckks_encrypt(ckks_ctx *ctx, const double *x, uint32_t n, uint32_t level,
                          double scale, uint64_t seed, ckks_ct **out);
+/* Encrypt n_ct vectors (row i = x + i * n, n <= N/2 slots each) at one
+ * level and scale; ciphertext i uses seed seed0 + i and is identical to
+ * ckks_encrypt(x + i * n, n, level, scale, seed0 + i).  The host encoding
+ * and sampling run on up to 16 threads.  outs[i] receive single ciphertexts. */
+ckks_status ckks_encrypt_batch(ckks_ctx *ctx, const double *x, uint32_t n_ct, uint32_t n, uint32_t level,
+                               double scale, uint64_t seed0, ckks_ct **outs);
 /* Decrypt with the context's secret key and decode N/2 slots (real parts to
  * `re`, imaginary parts to `im`; `im` may be NULL). */
 ckks_status ckks_decrypt(ckks_ctx *ctx, const ckks_ct *ct, double *re, double *im);
@@ -250,6 +256,15 @@ ckks_status ckks_ntt_device(ckks_ctx *ctx, uint64_t *data, uint32_t n_limbs,
  * and the summed algorithmic bytes of a family (zeros if never recorded).
  */
 ckks_status ckks_profile_enable(ckks_ctx *ctx, int on);
+/*
+ * Opt-in operation trace for the cost model (enabling clears it): one text
+ * line "op level B" per primitive executed (op in hmult, rescale, rotate,
+ * mul_scalar, add, sub, add_const, drop, copy), in execution order.
+ * ckks_trace_read copies at most cap-1 bytes plus a terminating zero and
+ * returns the size needed (including the zero).
+ */
+ckks_status ckks_trace_enable(ckks_ctx *ctx, int on);
+size_t ckks_trace_read(const ckks_ctx *ctx, char *buf, size_t cap);
 ckks_status ckks_profile_read(ckks_ctx *ctx, const char *family, uint64_t *calls, double *gpu_ms,
                               double *alg_bytes);
 

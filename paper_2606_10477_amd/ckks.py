@@ -45,6 +45,8 @@ SIGNATURES = {
     "ckks_galois_rotation": (C.c_int32, [vp, C.c_int32]),
     "ckks_encrypt": (C.c_int, [vp, dblp, C.c_uint32, C.c_uint32, C.c_double, C.c_uint64, C.POINTER(vp)]),
     "ckks_decrypt": (C.c_int, [vp, vp, dblp, dblp]),
+    "ckks_encrypt_batch": (C.c_int, [vp, dblp, C.c_uint32, C.c_uint32, C.c_uint32, C.c_double, C.c_uint64,
+                                     C.POINTER(vp)]),
     "ckks_ct_import": (C.c_int, [vp, u64p, C.c_uint32, C.c_double, C.POINTER(vp)]),
     "ckks_ct_export": (C.c_int, [vp, vp, u64p]),
     "ckks_ct_device_ptr": (vp, [vp]),
@@ -76,6 +78,8 @@ SIGNATURES = {
     "ckks_ct_unpack": (C.c_int, [vp, vp, C.POINTER(vp)]),
     "ckks_ct_count": (C.c_int32, [vp]),
     "ckks_profile_enable": (C.c_int, [vp, C.c_int]),
+    "ckks_trace_enable": (C.c_int, [vp, C.c_int]),
+    "ckks_trace_read": (C.c_size_t, [vp, C.c_char_p, C.c_size_t]),
     "ckks_profile_read": (C.c_int, [vp, C.c_char_p, u64p, dblp, dblp]),
 }
 
@@ -205,6 +209,13 @@ class Context:
         x = np.ascontiguousarray(x, dtype=np.float64)
         return self._ct(lib().ckks_encrypt, _p(x, dblp), len(x), level, scale, seed)
 
+    def encrypt_batch(self, X, level, scale, seed0):
+        X = np.ascontiguousarray(X, dtype=np.float64)
+        n_ct, n = X.shape
+        outs = (vp * n_ct)()
+        self._chk(lib().ckks_encrypt_batch(self.ptr, _p(X, dblp), n_ct, n, level, scale, seed0, outs))
+        return [Ciphertext(self, outs[i]) for i in range(n_ct)]
+
     def decrypt(self, ct):
         re = np.zeros(self.n)
         im = np.zeros(self.n)
@@ -275,6 +286,19 @@ class Context:
 
     def profile(self, on=True):
         self._chk(lib().ckks_profile_enable(self.ptr, int(on)))
+
+    def trace(self, on=True):
+        self._chk(lib().ckks_trace_enable(self.ptr, int(on)))
+
+    def trace_read(self):
+        n = lib().ckks_trace_read(self.ptr, None, 0)
+        buf = C.create_string_buffer(n)
+        lib().ckks_trace_read(self.ptr, buf, n)
+        out = []
+        for line in buf.value.decode().splitlines():
+            op, lvl, B = line.split()
+            out.append((op, int(lvl), int(B)))
+        return out
 
     def profile_read(self, family):
         n = C.c_uint64()

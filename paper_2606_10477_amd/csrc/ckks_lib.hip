@@ -15,6 +15,7 @@
 #include <memory>
 #include <stdexcept>
 #include <string>
+#include <thread>
 #include <vector>
 
 #include "../../include/ckks.h"
@@ -149,6 +150,9 @@ struct ckks_ctx {
         uint64_t calls = 0;
     };
     bool prof_on = false;
+    // opt-in operation trace (op name, level, batch) for the cost model
+    bool trace_on = false;
+    std::string trace;
     std::map<std::string, ProfFamily> prof;
     std::vector<hipEvent_t> ev_free;
     u64 words(int level) const { return (u64)2 * (level + 1) * N; }
@@ -196,6 +200,16 @@ int bitrev(int x, int bits) {
     int r = 0;
     for (int i = 0; i < bits; ++i) { r = (r << 1) | (x & 1); x >>= 1; }
     return r;
+}
+
+void trace_op(ckks_ctx *c, const char *op, int level, int B) {
+    if (!c->trace_on) return;
+    c->trace += op;
+    c->trace += ' ';
+    c->trace += std::to_string(level);
+    c->trace += ' ';
+    c->trace += std::to_string(B);
+    c->trace += '\n';
 }
 
 hipEvent_t prof_event(ckks_ctx *c) {
@@ -394,6 +408,7 @@ u64 *poly(const ckks_ctx *c, const ckks_ct *ct, int p, int b = 0) {
 }
 
 Ct ct_copy(ckks_ctx *c, const ckks_ct *a) {
+    trace_op(c, "copy", a->level, a->B);
     Ct r = ct_new(c, a->level, a->scale, a->B);
     hipchk(hipMemcpyAsync(r->buf.p, a->buf.p, c->words(a->level) * a->B * 8, hipMemcpyDeviceToDevice, c->stream),
            "copy");
@@ -406,12 +421,14 @@ Ct op_addsub(ckks_ctx *c, const ckks_ct *a, const ckks_ct *b, bool sub) {
     if (a->level != b->level) fail(CKKS_E_LEVEL, "level mismatch");
     if (!scales_match(a->scale, b->scale)) fail(CKKS_E_SCALE, "scale mismatch");
     if (a->B != b->B) fail(CKKS_E_PARAM, "batch size mismatch");
+    trace_op(c, sub ? "sub" : "add", a->level, a->B);
     Ct r = ct_new(c, a->level, a->scale, a->B);
     gpu::add(c->T, r->buf.p, a->buf.p, b->buf.p, a->level + 1, 2 * a->B, map_q(0, a->level + 1), sub, c->stream);
     return r;
 }
 
 Ct op_mul_int(ckks_ctx *c, const ckks_ct *a, int64_t k, double new_scale) {
+    trace_op(c, "mul_scalar", a->level, a->B);
     Ct r = ct_new(c, a->level, new_scale, a->B);
     LimbConsts kc{};
     for (int i = 0; i <= a->level; ++i) {
@@ -432,6 +449,7 @@ Ct op_add_const(ckks_ctx *c, const ckks_ct *a, double value) {
     double kd = std::rint(value * a->scale);
     if (!(std::fabs(kd) < 4.0e18)) fail(CKKS_E_RANGE, "constant out of range");
     const int64_t k = (int64_t)kd;
+    trace_op(c, "add_const", a->level, a->B);
     Ct r = ct_new(c, a->level, a->scale, a->B);
     LimbConsts kc{};
     for (int i = 0; i <= a->level; ++i) kc.v[i] = mod_signed(k, c->q[i]);
@@ -441,6 +459,7 @@ Ct op_add_const(ckks_ctx *c, const ckks_ct *a, double value) {
 
 Ct op_drop(ckks_ctx *c, const ckks_ct *a, int level) {
     if (level < 0 || level > a->level) fail(CKKS_E_LEVEL, "bad target level");
+    trace_op(c, "drop", level, a->B);
     Ct r = ct_new(c, level, a->scale, a->B);
     const size_t row = (size_t)(level + 1) * c->N * 8, src_pitch = (size_t)(a->level + 1) * c->N * 8;
     hipchk(hipMemcpy2DAsync(r->buf.p, row, a->buf.p, src_pitch, row, 2 * (size_t)a->B, hipMemcpyDeviceToDevice,
@@ -453,6 +472,7 @@ Ct op_drop(ckks_ctx *c, const ckks_ct *a, int level) {
 Ct op_rescale(ckks_ctx *c, const ckks_ct *a) {
     const int l = a->level;
     if (l < 1) fail(CKKS_E_LEVEL, "rescale at level 0");
+    trace_op(c, "rescale", l, a->B);
     const size_t N = c->N;
     const int np2 = 2 * a->B;
     Ct r = ct_new(c, l - 1, a->scale / (double)c->q[l], a->B);
@@ -532,6 +552,7 @@ Ct op_hmult(ckks_ctx *c, const ckks_ct *a, const ckks_ct *b) {
     if (a->level != b->level) fail(CKKS_E_LEVEL, "level mismatch");
     if (a->B != b->B) fail(CKKS_E_PARAM, "batch size mismatch");
     const int l = a->level, nq = l + 1, B = a->B;
+    trace_op(c, "hmult", l, B);
     const size_t N = c->N;
     Ct r = ct_new(c, l, a->scale * b->scale, B);
     Buf d01(c->pool.get(), (size_t)B * 2 * nq * N), d2(c->pool.get(), (size_t)B * nq * N);
@@ -544,6 +565,7 @@ Ct op_automorphism(ckks_ctx *c, const ckks_ct *a, int g) {
     auto it = c->rot.find(g);
     if (it == c->rot.end()) fail(CKKS_E_NOKEY, "missing Galois key");
     const int nq = a->level + 1, B = a->B;
+    trace_op(c, "rotate", a->level, B);
     const size_t N = c->N;
     const int32_t *perm = perm_for(c, g);
     Buf s(c->pool.get(), (size_t)B * 2 * nq * N);
@@ -844,35 +866,52 @@ void keygen(ckks_ctx *c, uint64_t seed, const int32_t *gal, uint32_t ng) {
     c->have_keys = true;
 }
 
-Ct op_encrypt(ckks_ctx *c, const double *x, uint32_t n, int level, double scale, uint64_t seed) {
-    if (!c->have_keys) fail(CKKS_E_NOKEY, "no keys");
-    if (level < 0 || level > c->L) fail(CKKS_E_LEVEL, "bad level");
-    if (n > (uint32_t)c->N / 2) fail(CKKS_E_PARAM, "too many slots");
+// host stage of encryption: encoded message + sampled randomness
+struct EncHost {
+    std::vector<int64_t> v, e0m, e1;
+    bool ok = true;
+};
+void enc_host(const ckks_ctx *c, const double *x, uint32_t n, double scale, uint64_t seed, EncHost &h) {
     const size_t N = c->N;
-    const int nq = level + 1;
     std::vector<int64_t> m(N);
-    if (!hm::encode(c->logN, x, nullptr, n, scale, m.data())) fail(CKKS_E_RANGE, "value out of range for encoding");
+    h.ok = hm::encode(c->logN, x, nullptr, n, scale, m.data());
     std::vector<int8_t> v(N);
-    std::vector<int64_t> e0(N), e1(N);
+    h.e0m.assign(N, 0);
+    h.e1.assign(N, 0);
     hm::Shake256 xv(seed, hm::stream_tag(hm::kEncV, 0, 0));
     hm::ternary(xv, c->N, v.data());
     hm::Shake256 x0(seed, hm::stream_tag(hm::kEncE0, 0, 0));
-    hm::gaussian(x0, c->cdt, c->N, e0.data());
+    hm::gaussian(x0, c->cdt, c->N, h.e0m.data());
     hm::Shake256 x1(seed, hm::stream_tag(hm::kEncE1, 0, 0));
-    hm::gaussian(x1, c->cdt, c->N, e1.data());
-    for (size_t j = 0; j < N; ++j) e0[j] += m[j];
-    std::vector<int64_t> v64(v.begin(), v.end());
+    hm::gaussian(x1, c->cdt, c->N, h.e1.data());
+    for (size_t j = 0; j < N; ++j) h.e0m[j] += m[j];
+    h.v.assign(v.begin(), v.end());
+}
+// device stage: ct0 = v pk0 + e0 + m, ct1 = v pk1 + e1 (NTT domain)
+Ct enc_device(ckks_ctx *c, const EncHost &h, int level, double scale) {
+    const size_t N = c->N;
+    const int nq = level + 1;
     Pool *P = c->pool.get();
     Buf vN(P, (size_t)nq * N), a0(P, (size_t)nq * N), a1(P, (size_t)nq * N);
     LimbMap mq = map_q(0, nq);
-    upload_signed_ntt(c, vN.p, v64.data(), nq, mq);
-    upload_signed_ntt(c, a0.p, e0.data(), nq, mq);
-    upload_signed_ntt(c, a1.p, e1.data(), nq, mq);
+    upload_signed_ntt(c, vN.p, h.v.data(), nq, mq);
+    upload_signed_ntt(c, a0.p, h.e0m.data(), nq, mq);
+    upload_signed_ntt(c, a1.p, h.e1.data(), nq, mq);
     Ct r = ct_new(c, level, scale);
     const u64 *pk0 = c->pk.p, *pk1 = c->pk.p + (size_t)(c->L + 1) * N;
     gpu::mul_add(c->T, poly(c, r.get(), 0), vN.p, pk0, a0.p, nq, mq, c->stream);
     gpu::mul_add(c->T, poly(c, r.get(), 1), vN.p, pk1, a1.p, nq, mq, c->stream);
     return r;
+}
+
+Ct op_encrypt(ckks_ctx *c, const double *x, uint32_t n, int level, double scale, uint64_t seed) {
+    if (!c->have_keys) fail(CKKS_E_NOKEY, "no keys");
+    if (level < 0 || level > c->L) fail(CKKS_E_LEVEL, "bad level");
+    if (n > (uint32_t)c->N / 2) fail(CKKS_E_PARAM, "too many slots");
+    EncHost h;
+    enc_host(c, x, n, scale, seed, h);
+    if (!h.ok) fail(CKKS_E_RANGE, "value out of range for encoding");
+    return enc_device(c, h, level, scale);
 }
 
 void op_decrypt(ckks_ctx *c, const ckks_ct *ct, double *re, double *im) {
@@ -993,6 +1032,37 @@ ckks_status ckks_encrypt(ckks_ctx *c, const double *x, uint32_t n, uint32_t leve
                          ckks_ct **out) {
     if (!c || (n && !x)) return CKKS_E_PARAM;
     return guard_out(c, out, [&] { return op_encrypt(c, x, n, (int)level, scale, seed); });
+}
+
+ckks_status ckks_encrypt_batch(ckks_ctx *c, const double *x, uint32_t n_ct, uint32_t n, uint32_t level, double scale,
+                               uint64_t seed0, ckks_ct **outs) {
+    if (!c || (n_ct && (!x || !outs))) return CKKS_E_PARAM;
+    for (uint32_t i = 0; i < n_ct; ++i) outs[i] = nullptr;
+    ckks_status st = guard(c, [&] {
+        if (!c->have_keys) fail(CKKS_E_NOKEY, "no keys");
+        if ((int)level > c->L) fail(CKKS_E_LEVEL, "bad level");
+        if (n > (uint32_t)c->N / 2) fail(CKKS_E_PARAM, "too many slots");
+        const unsigned hw = std::max(1u, std::min(16u, std::thread::hardware_concurrency()));
+        const uint32_t chunk = 4 * hw;
+        for (uint32_t off = 0; off < n_ct; off += chunk) {
+            const uint32_t cnt = std::min(chunk, n_ct - off);
+            std::vector<EncHost> hs(cnt);
+            std::vector<std::thread> th;
+            for (unsigned t = 0; t < hw; ++t)
+                th.emplace_back([&, t] {
+                    for (uint32_t i = t; i < cnt; i += hw)
+                        enc_host(c, x + (size_t)(off + i) * n, n, scale, seed0 + off + i, hs[i]);
+                });
+            for (auto &t : th) t.join();
+            for (uint32_t i = 0; i < cnt; ++i) {
+                if (!hs[i].ok) fail(CKKS_E_RANGE, "value out of range for encoding");
+                outs[off + i] = enc_device(c, hs[i], (int)level, scale).release();
+            }
+        }
+    });
+    if (st != CKKS_OK)
+        for (uint32_t i = 0; i < n_ct; ++i) { delete outs[i]; outs[i] = nullptr; }
+    return st;
 }
 
 ckks_status ckks_decrypt(ckks_ctx *c, const ckks_ct *ct, double *re, double *im) {
@@ -1186,6 +1256,22 @@ ckks_status ckks_ct_unpack(ckks_ctx *c, const ckks_ct *batch, ckks_ct **outs) {
     return st;
 }
 int32_t ckks_ct_count(const ckks_ct *ct) { return ct ? ct->B : 0; }
+
+ckks_status ckks_trace_enable(ckks_ctx *c, int on) {
+    if (!c) return CKKS_E_PARAM;
+    c->trace.clear();
+    c->trace_on = on != 0;
+    return CKKS_OK;
+}
+size_t ckks_trace_read(const ckks_ctx *c, char *buf, size_t cap) {
+    if (!c) return 0;
+    if (buf && cap) {
+        size_t n = std::min(cap - 1, c->trace.size());
+        std::memcpy(buf, c->trace.data(), n);
+        buf[n] = 0;
+    }
+    return c->trace.size() + 1;
+}
 
 ckks_status ckks_ntt_device(ckks_ctx *c, uint64_t *data, uint32_t n_limbs, const uint32_t *prime_idx, int inverse) {
     if (!c || !data || !prime_idx || n_limbs == 0) return CKKS_E_PARAM;

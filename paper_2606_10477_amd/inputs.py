@@ -7,6 +7,8 @@ arithmetic.  Recipes (all numpy PCG64, ``np.random.default_rng(seed)``):
   inverse square root (n = N/2 slots per ciphertext).
 - ``linspace_input(n, A, B)``: the evenly spaced grid the paper uses for its
   provisioning runs (Alg. 3 encrypts linspace(A, B, N/2)).
+- ``column_table(rows, cols, seed)``: the synthetic statistics table: column c
+  ~ N(mu_c, sigma_c^2) with mu_c ~ U[-5, 5] and sigma_c ~ log-U[0.1, 10].
 - ``uniform_words(shape, primes, seed)``: uniform residues mod each prime (used
   as generic ciphertext/polynomial words for per-operation parity tests);
   axis -2 indexes the prime.
@@ -37,3 +39,28 @@ def uniform_words(shape, primes, seed):
 def small_ints(shape, bound, seed):
     rng = np.random.default_rng(seed)
     return rng.integers(-bound, bound + 1, size=shape, dtype=np.int64)
+
+
+def column_table(rows, cols, seed):
+    rng = np.random.default_rng(seed)
+    mu = rng.uniform(-5, 5, cols)
+    sigma = np.exp(rng.uniform(np.log(0.1), np.log(10), cols))
+    data = rng.standard_normal((cols, rows)) * sigma[:, None] + mu[:, None]
+    return data, mu, sigma
+
+
+def poisson_arrivals(n, rate, seed):
+    """Arrival times (s) of n requests of a Poisson process with `rate` per second."""
+    rng = np.random.default_rng(seed)
+    return np.cumsum(rng.exponential(1.0 / rate, n))
+
+
+def geometric_sizes(n, p, lo, hi, seed):
+    """Request sizes ~ Geometric(p) truncated to [lo, hi]."""
+    rng = np.random.default_rng(seed)
+    return np.clip(rng.geometric(p, n), lo, hi)
+
+
+def choice(n, options, seed):
+    rng = np.random.default_rng(seed)
+    return [options[k] for k in rng.integers(0, len(options), n)]

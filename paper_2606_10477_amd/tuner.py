@@ -1,0 +1,216 @@
+"""Degree-versus-iterations tuner for CryptoInvSqrt (paper §5.2).
+
+Host logic of the paper's provisioning step:
+  * ``get_opt_iter`` -- Alg. 2 (GetOptIter) after its loop: the threshold
+    MRE_delta = (floor(alpha) + delta) 10^l from MRE_min = alpha 10^l, and the
+    smallest iteration count whose MRE is within it;
+  * ``optimize_params`` -- Alg. 3's final selection per level: m_theta from the
+    level's smallest MRE, u1 = fastest tuple with m <= m_theta (accuracy
+    first), u2 = fastest tuple overall (speed first);
+  * ``level_cases`` -- Alg. 3's enumeration of input levels l_BTS+1..l_max and
+    the conditions under which c = 0 (l >= l_BTS + 3) and c = 1
+    (l < l_afterBTS - 1) are explored.
+
+On top of these, the cost model used on this GPU: the library records the
+operation trace of a run (op, level, batch); each primitive's unit cost is
+profiled on the device; the predicted time of a configuration is the sum of
+unit costs over its trace.  ``sweep`` measures MRE and time for a grid of
+(degree, iterations) at given input levels and ``select`` picks the pair that
+meets an MRE target at minimum predicted time.
+"""
+import math
+import time
+
+import numpy as np
+
+
+# --------------------------------------------------------------------------
+# Alg. 2 / Alg. 3 host rules
+# --------------------------------------------------------------------------
+def mantissa_exponent(m):
+    """m = alpha * 10^l with 1 <= alpha < 10 (l = floor(log10 m))."""
+    if not (m > 0 and math.isfinite(m)):
+        raise ValueError("MRE must be positive and finite")
+    l = math.floor(math.log10(m))
+    alpha = m / 10.0 ** l
+    # log10 rounding at exact powers of ten
+    if alpha >= 10.0:
+        alpha /= 10.0
+        l += 1
+    elif alpha < 1.0:
+        alpha *= 10.0
+        l -= 1
+    return alpha, l
+
+
+def threshold(m_min, delta):
+    """(floor(alpha) + delta) * 10^l for m_min = alpha * 10^l."""
+    alpha, l = mantissa_exponent(m_min)
+    return (math.floor(alpha) + delta) * 10.0 ** l
+
+
+def get_opt_iter(M, T, delta):
+    """Alg. 2 lines 11-16.  M[k], T[k] are the MRE and cumulative time after
+    k+1 Newton iterations.  Returns (I, M[I], T[I]) with I counted from 1.
+    If no iteration is within the threshold (possible for delta < 1), the
+    iteration with the smallest MRE is returned."""
+    m_min = min(M)
+    thr = threshold(m_min, delta)
+    within = [k for k, m in enumerate(M) if m <= thr]
+    k = within[0] if within else int(np.argmin(M))
+    return k + 1, M[k], T[k]
+
+
+def _argmin_time(rows):
+    # ties: lower MRE, then smaller degree
+    return min(rows, key=lambda r: (r["t"], r["m"], r["d"]))
+
+
+def optimize_params(D, theta):
+    """Alg. 3 lines 19-27.  D maps level -> list of dicts with keys d, c, i,
+    m, t.  Returns level -> (u1, u2), each a (d, c, i) tuple."""
+    R = {}
+    for l, rows in D.items():
+        if not rows:
+            continue
+        m_min = min(r["m"] for r in rows)
+        m_theta = threshold(m_min, theta)
+        u1 = _argmin_time([r for r in rows if r["m"] <= m_theta])
+        u2 = _argmin_time(rows)
+        R[l] = ((u1["d"], u1["c"], u1["i"]), (u2["d"], u2["c"], u2["i"]))
+    return R
+
+
+def level_cases(l_bts, l_after_bts, l_max):
+    """Alg. 3 lines 6-17: for each explored input level, which Pre-BTS
+    indicators are tried."""
+    out = {}
+    for l in range(l_bts + 1, l_max + 1):
+        cs = []
+        if l >= l_bts + 3:
+            cs.append(0)
+        if l < l_after_bts - 1:
+            cs.append(1)
+        out[l] = cs
+    return out
+
+
+def mre(values, ref):
+    values = np.asarray(values)
+    ref = np.asarray(ref)
+    return float(np.mean(np.abs(values - ref) / np.abs(ref)))
+
+
+# --------------------------------------------------------------------------
+# Cost model
+# --------------------------------------------------------------------------
+OPS = ("hmult", "rescale", "rotate", "mul_scalar", "add", "sub", "add_const", "drop", "copy")
+
+
+def _words(ctx, level, B, seed):
+    from . import inputs
+    return [inputs.uniform_words((2, level + 1, ctx.N), ctx.primes[:level + 1], seed + b) for b in range(B)]
+
+
+def profile_unit_costs(ctx, levels, batch=1, reps=5, rot_step=None):
+    """Median wall time (s, device-synchronised) of each primitive at each
+    level, on `batch` ciphertexts of uniform words."""
+    costs = {}
+    for lvl in levels:
+        singles = [ctx.ct_import(w, lvl, 2.0 ** 40) for w in _words(ctx, lvl, batch, 1000 + lvl)]
+        a = ctx.pack(singles) if batch > 1 else singles[0]
+        fns = {
+            "hmult": lambda: ctx.hmult(a, a),
+            "mul_scalar": lambda: ctx.mul_int(a, 3),
+            "add": lambda: ctx.add(a, a),
+            "sub": lambda: ctx.sub(a, a),
+            "add_const": lambda: ctx.add_const(a, 0.5),
+            "copy": lambda: ctx.drop_level(a, lvl),
+        }
+        if lvl >= 1:
+            fns["rescale"] = lambda: ctx.rescale(a)
+            fns["drop"] = lambda: ctx.drop_level(a, lvl - 1)
+        if rot_step is not None:
+            fns["rotate"] = lambda: ctx.rotate(a, rot_step)
+        for op, fn in fns.items():
+            fn()
+            ctx.sync()
+            ts = []
+            for _ in range(reps):
+                t0 = time.perf_counter()
+                r = fn()
+                ctx.sync()
+                ts.append(time.perf_counter() - t0)
+                del r
+            costs[(op, lvl)] = float(np.median(ts))
+    return costs
+
+
+def predict(trace, costs):
+    """Sum of unit costs over an operation trace [(op, level, B), ...]."""
+    total = 0.0
+    missing = set()
+    for op, lvl, _B in trace:
+        c = costs.get((op, lvl))
+        if c is None:
+            missing.add((op, lvl))
+            continue
+        total += c
+    return total, missing
+
+
+# --------------------------------------------------------------------------
+# Sweep and selection (one MI355X, encrypted runs with the tuner's own keys)
+# --------------------------------------------------------------------------
+def sweep(ctx, x, ct_by_level, degrees, iters, lo, hi, batch=1, reps=3, costs=None):
+    """For each input level and (degree, iterations): MRE of the decrypted
+    result against FP64 1/sqrt(x), measured time (median of `reps`, all
+    `batch` ciphertexts), the operation trace and the predicted time.  Pairs
+    that do not fit the levels are skipped (recorded with ok=False)."""
+    from .ckks import CkksError
+    ref = 1.0 / np.sqrt(x)
+    rows = []
+    for lvl, ct in ct_by_level.items():
+        cts = [ct] * batch
+        for d in degrees:
+            for it in iters:
+                row = {"level": lvl, "d": d, "i": it, "c": 0}
+                try:
+                    ctx.trace(True)
+                    y = ctx.invsqrt(ct, d, it, a=lo, b=hi) if batch == 1 else \
+                        ctx.invsqrt_batch(cts, d, it, a=lo, b=hi)[0]
+                    tr = ctx.trace_read()
+                    ctx.trace(False)
+                except CkksError:
+                    ctx.trace(False)
+                    row["ok"] = False
+                    rows.append(row)
+                    continue
+                row["ok"] = True
+                row["m"] = mre(ctx.decrypt(y).real, ref)
+                row["out_level"] = y.level
+                ts = []
+                for _ in range(reps):
+                    ctx.sync()
+                    t0 = time.perf_counter()
+                    if batch == 1:
+                        ctx.invsqrt(ct, d, it, a=lo, b=hi)
+                    else:
+                        ctx.invsqrt_batch(cts, d, it, a=lo, b=hi)
+                    ctx.sync()
+                    ts.append(time.perf_counter() - t0)
+                row["t"] = float(np.median(ts)) / batch
+                row["ops"] = len(tr)
+                if costs is not None:
+                    row["t_pred"] = predict(tr, costs)[0]
+                rows.append(row)
+    return rows
+
+
+def select(rows, target, level, key="t_pred"):
+    """The (degree, iterations) at `level` with MRE <= target at minimum
+    `key` time (ties: lower MRE, smaller degree); None if none qualifies."""
+    ok = [r for r in rows if r.get("ok") and r["level"] == level and r["m"] <= target and key in r]
+    if not ok:
+        return None
+    return min(ok, key=lambda r: (r[key], r["m"], r["d"]))

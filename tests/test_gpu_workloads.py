@@ -1,0 +1,149 @@
+"""GPU tests of the batched workloads: batch encryption, batched z-score
+standardisation (bit-exact against the oracle run column by column), and the
+serving loop (each result identical alone and in the mix)."""
+import math
+
+import numpy as np
+import pytest
+
+from paper_2606_10477_amd import inputs
+
+pytestmark = pytest.mark.gpu
+
+# N = 2^12 with 20 scaling primes (insecure, test only): enough levels for
+# squares, the two means, CryptoInvSqrt (degree 15, 2 steps) and the final product
+SMALL = dict(log_n=12, max_level=20, num_special=1, digit_size=1, hamming_weight=0)
+
+
+def _ck():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_2606_10477_amd import ckks
+    return ckks
+
+
+@pytest.fixture(scope="module")
+def small(oracle_mod):
+    ck = _ck()
+    g = ck.Context(**SMALL)
+    o = oracle_mod.Context(12, 20, 1, 1, h=0)
+    gal = [g.galois_rot(1 << k) for k in range(11)]
+    g.keygen(5, gal)
+    o.keygen(5, gal)
+    yield g, o
+    g.close()
+
+
+def test_encrypt_batch_equals_single(small):
+    g, _ = small
+    X = np.stack([inputs.log_uniform(g.n, 2 ** -8, 1.0, 60 + i) for i in range(5)])
+    outs = g.encrypt_batch(X, 20, 2.0 ** 45, 900)
+    for i in range(5):
+        assert np.array_equal(outs[i].words(), g.encrypt(X[i], 20, 2.0 ** 45, 900 + i).words())
+
+
+def _oracle_znorm(o, cts, rows, B, d, it, lo, hi):
+    s1 = cts[0]
+    sq = [o.rescale(o.hmult(x, x)) for x in cts]
+    s2 = sq[0]
+    for j in range(1, len(cts)):
+        s1 = o.add(s1, cts[j])
+        s2 = o.add(s2, sq[j])
+    for acc_name in ("s1", "s2"):
+        acc = s1 if acc_name == "s1" else s2
+        k = 1
+        while k < o.n:
+            acc = o.add(acc, o.rotate(acc, k))
+            k <<= 1
+        if acc_name == "s1":
+            s1 = acc
+        else:
+            s2 = acc
+    m1 = o.mul_const_down(s1, 1.0 / (rows * math.sqrt(B)))
+    m2 = o.mul_const_down(s2, 1.0 / (rows * B))
+    m1sq = o.rescale(o.hmult(m1, m1))
+    lv = min(m1sq.level, m2.level)
+    v = o.sub(o.level_to(m2, lv), o.level_to(m1sq, lv))
+    r = o.invsqrt(v, d, it, lo, hi)
+    rs = o.mul_const_down(r, 1.0 / math.sqrt(B))
+    mean = o.mul_const_down(s1, 1.0 / rows)
+    z = []
+    for x in cts:
+        lvd = min(x.level, mean.level, rs.level + 1)
+        diff = o.sub(o.level_to(x, lvd), o.level_to(mean, lvd))
+        lvm = min(diff.level, rs.level)
+        z.append(o.rescale(o.hmult(o.level_to(diff, lvm), o.level_to(rs, lvm))))
+    return z, v, r
+
+
+def test_znorm_batched_bit_exact_vs_oracle(small):
+    from paper_2606_10477_amd import znorm
+    g, o = small
+    cols, per = 3, 2
+    rows = per * g.n
+    data, mu, sigma = inputs.column_table(rows, cols, 7)
+    B, lo, hi, d, it = 128.0, 2.0 ** -14, 1.0, 15, 2
+    gcols, ocols = [], []
+    for c in range(cols):
+        chunks = data[c].reshape(per, g.n)
+        gcols.append([g.encrypt(chunks[j], 20, 2.0 ** 40, 100 * c + j) for j in range(per)])
+        ocols.append([o.encrypt(chunks[j], 20, 2.0 ** 40, 100 * c + j) for j in range(per)])
+    z, v, r = znorm.znorm(g, gcols, rows, B, d, it, lo, hi)
+    vparts = g.unpack(v)
+    for c in range(cols):
+        oz, ov, orr = _oracle_znorm(o, ocols[c], rows, B, d, it, lo, hi)
+        assert np.array_equal(vparts[c].words(), ov.words())
+        for j in range(per):
+            assert z[c][j].level == oz[j].level and z[c][j].scale == oz[j].scale
+            assert np.array_equal(z[c][j].words(), oz[j].words())
+    # accuracy against FP64 z-scores
+    c = 0
+    zz = np.concatenate([g.decrypt(z[c][j]).real for j in range(per)])
+    ref = (data[c] - data[c].mean()) / data[c].std()
+    assert np.max(np.abs(zz - ref)) < 1e-3
+
+
+def test_serving_alone_equals_in_the_mix(small):
+    from paper_2606_10477_amd import serve
+    g, _ = small
+    table = {"12": {"1e-06": {"degree": 15, "iters": 2}, "3.1e-08": {"degree": 15, "iters": 3}},
+             "16": {"1e-06": {"degree": 7, "iters": 3}, "3.1e-08": {"degree": 31, "iters": 3}}}
+    sizes = [3, 1, 4, 2, 2]
+    levels = [12, 16, 12, 16, 12]
+    targets = [1e-6, 3.1e-8, 1e-6, 1e-6, 3.1e-8]
+    reqs = []
+    for k in range(5):
+        X = np.stack([inputs.log_uniform(g.n, 2 ** -10, 1.0, 300 + 10 * k + j) for j in range(sizes[k])])
+        cts = g.encrypt_batch(X, levels[k], 2.0 ** 45, 500 + 10 * k)
+        reqs.append(serve.Request(k, 0.002 * k, cts, levels[k], targets[k]))
+    srv = serve.run_continuous(g, table, reqs, max_batch=16)
+    assert any(e["batch"] > max(sizes) for e in srv.log)   # requests shared a launch sequence
+    for r in reqs:
+        alone = g.invsqrt_batch(r.cts, r.degree, r.iters)
+        for k, y in enumerate(alone):
+            assert np.array_equal(r.outs[k].words(), y.words())
+
+
+def test_znorm_full_size_accuracy():
+    """N = 2^16 parameters, 4 columns of 2^17 rows (4 ciphertexts each),
+    tuned-style (31, 3) on [2^-14, 1]: z-scores against FP64."""
+    ck = _ck()
+    from paper_2606_10477_amd import znorm
+    g = ck.Context(log_n=16, max_level=27, num_special=7, digit_size=10, hamming_weight=192)
+    g.keygen(9, [g.galois_rot(s) for s in znorm.rotation_steps(g.n)])
+    cols, per = 4, 4
+    rows = per * g.n
+    data, _, _ = inputs.column_table(rows, cols, 8)
+    gcols = []
+    for c in range(cols):
+        gcols.append(g.encrypt_batch(data[c].reshape(per, g.n), 20, 2.0 ** 40, 1000 + 10 * c))
+    z, v, r = znorm.znorm(g, gcols, rows, 128.0, 31, 3, 2.0 ** -14, 1.0)
+    errs = []
+    for c in range(cols):
+        zz = np.concatenate([g.decrypt(z[c][j]).real for j in range(per)])
+        ref = (data[c] - data[c].mean()) / data[c].std()
+        errs.append(np.mean(np.abs(zz - ref) / np.maximum(np.abs(ref), 1e-3)))
+    print("znorm full size: mean relative error per column", errs, flush=True)
+    assert max(errs) < 1e-3
+    g.close()

@@ -1,0 +1,97 @@
+"""Scheduler logic of the serving loop, with a fake context (no GPU)."""
+import pytest
+
+from paper_2606_10477_amd import serve
+
+
+class FakeCt:
+    def __init__(self, tag):
+        self.tag = tag
+
+
+class FakeCtx:
+    N = 1 << 12
+
+    def __init__(self):
+        self.calls = []
+
+    def invsqrt_batch(self, cts, degree, iters, a=None, b=None):
+        self.calls.append((len(cts), degree, iters))
+        return [FakeCt(("y", c.tag, degree, iters)) for c in cts]
+
+    def sync(self):
+        pass
+
+
+TABLE = {"13": {"1e-06": {"degree": 15, "iters": 2}, "1e-07": {"degree": 31, "iters": 2},
+                "3.1e-08": {"degree": 31, "iters": 3}},
+         "17": {"1e-06": {"degree": 7, "iters": 3}, "1e-07": {"degree": 31, "iters": 2},
+                "3.1e-08": {"degree": 63, "iters": 2}}}
+
+
+def mk(rid, t, n, level, target):
+    return serve.Request(rid, t, [FakeCt((rid, k)) for k in range(n)], level, target)
+
+
+def test_lookup_exact_and_fallback():
+    assert serve.lookup(TABLE, 13, 3.1e-8) == (31, 3)
+    assert serve.lookup(TABLE, 19, 1e-6) == (7, 3)       # closest tuned level below
+    with pytest.raises(KeyError):
+        serve.lookup(TABLE, 5, 1e-6)
+
+
+def test_groups_share_one_batch_and_results_are_attributed():
+    ctx = FakeCtx()
+    srv = serve.Server(ctx, TABLE, max_batch=64, mem_budget=1 << 40)
+    for r in [mk(0, 0.0, 3, 13, 3.1e-8), mk(1, 0.0, 5, 13, 3.1e-8), mk(2, 0.0, 2, 17, 1e-6)]:
+        srv.submit(r)
+    reqs = list(srv.queue)
+    clock = lambda: 1.0
+    assert srv.step(clock) == 8              # both (13, 31, 3) requests in one launch sequence
+    assert ctx.calls[-1] == (8, 31, 3)
+    assert srv.step(clock) == 2
+    assert ctx.calls[-1] == (2, 7, 3)
+    for r in reqs:
+        assert r.done == 1.0 and len(r.outs) == len(r.cts)
+        for k, y in r.outs.items():
+            assert y.tag == ("y", (r.rid, k), r.degree, r.iters)
+
+
+def test_max_batch_splits_and_request_completes_when_all_parts_done():
+    ctx = FakeCtx()
+    srv = serve.Server(ctx, TABLE, max_batch=4, mem_budget=1 << 40)
+    r = mk(0, 0.0, 10, 13, 1e-6)
+    srv.submit(r)
+    sizes = []
+    t = [0.0]
+
+    def clock():
+        t[0] += 1
+        return t[0]
+    while srv.queue or srv.active:
+        sizes.append(srv.step(clock))
+    assert sizes == [4, 4, 2]
+    assert r.done is not None and sorted(r.outs) == list(range(10))
+
+
+def test_admission_by_memory_budget():
+    ctx = FakeCtx()
+    one = 2 * 14 * FakeCtx.N * 8 * 24       # estimate of one ciphertext at level 13
+    srv = serve.Server(ctx, TABLE, max_batch=64, mem_budget=3 * one)
+    a, b = mk(0, 0.0, 2, 13, 3.1e-8), mk(1, 0.1, 2, 13, 3.1e-8)
+    srv.submit(a)
+    srv.submit(b)
+    srv._admit(0.0)
+    assert srv.active == [a] and srv.queue == [b]   # b must wait for memory
+    srv.step(lambda: 1.0)
+    assert a.done == 1.0
+    srv.step(lambda: 2.0)                           # b admitted once a's memory is released
+    assert b.done == 2.0
+
+
+def test_summary():
+    rs = [mk(i, 0.1 * i, 2, 13, 1e-6) for i in range(4)]
+    for i, r in enumerate(rs):
+        r.done = r.arrival + 0.5 + 0.1 * i
+    s = serve.summarize(rs)
+    assert s["ciphertexts"] == 8 and s["p50_latency_s"] == pytest.approx(0.65)

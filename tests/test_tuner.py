@@ -1,0 +1,85 @@
+"""Host logic of the paper's provisioning algorithms (Alg. 2, Alg. 3) and of
+the cost model; no GPU."""
+import math
+
+import pytest
+
+from paper_2606_10477_amd import tuner
+
+
+def test_threshold_worked_example():
+    # MRE_min = 2.94e-8 -> l = -8, alpha = 2.94; with delta = 1 the threshold is 3e-8
+    alpha, l = tuner.mantissa_exponent(2.94e-8)
+    assert l == -8 and abs(alpha - 2.94) < 1e-12
+    assert abs(tuner.threshold(2.94e-8, 1) - 3e-8) < 1e-20
+    assert abs(tuner.threshold(2.94e-8, 0.5) - 2.5e-8) < 1e-20
+
+
+@pytest.mark.parametrize("m", [1e-8, 1e-3, 1.0, 100.0, 7.0e-9, 9.999999e-5])
+def test_mantissa_in_range(m):
+    alpha, l = tuner.mantissa_exponent(m)
+    assert 1.0 <= alpha < 10.0
+    assert math.isclose(alpha * 10.0 ** l, m, rel_tol=1e-12)
+
+
+def test_mantissa_rejects_nonpositive():
+    with pytest.raises(ValueError):
+        tuner.mantissa_exponent(0.0)
+
+
+def test_get_opt_iter_smallest_within_threshold():
+    # Newton MRE curve that falls then floors at noise: the first iteration
+    # within (floor(alpha)+delta)*10^l of the minimum is chosen, not the argmin
+    M = [2e-3, 2e-5, 3.4e-8, 3.1e-8, 3.05e-8, 3.2e-8]
+    T = [1, 2, 3, 4, 5, 6]
+    I, m, t = tuner.get_opt_iter(M, T, delta=1)
+    assert (I, m, t) == (3, 3.4e-8, 3)          # threshold 4e-8
+    I, m, t = tuner.get_opt_iter(M, T, delta=0.1)
+    assert (I, m, t) == (4, 3.1e-8, 4)          # threshold 3.1e-8
+    # delta below the mantissa fraction empties the set -> argmin fallback
+    I, m, t = tuner.get_opt_iter(M, T, delta=0.0)
+    assert (I, m) == (5, 3.05e-8)
+
+
+def test_optimize_params_u1_u2():
+    D = {7: [dict(d=126, c=0, i=5, m=3.06e-8, t=0.68), dict(d=126, c=1, i=4, m=9.25e-7, t=0.35),
+             dict(d=14, c=0, i=12, m=3.2e-8, t=0.90), dict(d=62, c=0, i=6, m=5.0e-8, t=0.50)]}
+    R = tuner.optimize_params(D, theta=1)
+    # m_theta = (3 + 1) e-8: accuracy-first picks the fastest tuple within it
+    assert R[7] == ((126, 0, 5), (126, 1, 4))
+    R = tuner.optimize_params(D, theta=3)       # m_theta = 6e-8 admits (62, 0, 6)
+    assert R[7][0] == (62, 0, 6)
+
+
+def test_level_cases_lattigo_and_heaan_sets():
+    # Lattigo: l_BTS = 0, l_afterBTS = l_max = 11 -> 11 levels; c = 0 only
+    # possible from level 3, c = 1 only below level 10
+    cases = tuner.level_cases(0, 11, 11)
+    assert sorted(cases) == list(range(1, 12))
+    assert [l for l, cs in cases.items() if cs == [0]] == [10, 11]
+    assert [l for l, cs in cases.items() if cs == [1]] == [1, 2]
+    assert all(cs == [0, 1] for l, cs in cases.items() if 3 <= l <= 9)
+    # HEaaN FGb: (l_max, l_BTS, l_afterBTS) = (12, 3, 12) -> levels 4..12 (9 levels)
+    cases = tuner.level_cases(3, 12, 12)
+    assert sorted(cases) == list(range(4, 13))
+    assert [l for l, cs in cases.items() if cs == [0]] == [11, 12]
+    assert [l for l, cs in cases.items() if cs == [1]] == [4, 5]
+
+
+def test_predict_sums_unit_costs():
+    costs = {("hmult", 5): 2.0, ("rescale", 5): 0.5, ("add", 4): 0.1}
+    trace = [("hmult", 5, 1), ("rescale", 5, 1), ("add", 4, 1), ("add", 4, 1)]
+    total, missing = tuner.predict(trace, costs)
+    assert total == pytest.approx(2.7) and not missing
+    total, missing = tuner.predict(trace + [("rotate", 3, 1)], costs)
+    assert missing == {("rotate", 3)}
+
+
+def test_select_meets_target_at_min_time():
+    rows = [dict(level=11, d=31, i=3, c=0, ok=True, m=1.1e-8, t_pred=5.0),
+            dict(level=11, d=63, i=2, c=0, ok=True, m=6.7e-9, t_pred=4.5),
+            dict(level=11, d=15, i=4, c=0, ok=True, m=4.0e-8, t_pred=3.0),
+            dict(level=11, d=127, i=1, c=0, ok=False)]
+    r = tuner.select(rows, 3.1e-8, 11)
+    assert (r["d"], r["i"]) == (63, 2)
+    assert tuner.select(rows, 1e-9, 11) is None
