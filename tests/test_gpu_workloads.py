@@ -10,9 +10,9 @@ from paper_2606_10477_amd import inputs
 
 pytestmark = pytest.mark.gpu
 
-# N = 2^12 with 20 scaling primes (insecure, test only): enough levels for
-# squares, the two means, CryptoInvSqrt (degree 15, 2 steps) and the final product
-SMALL = dict(log_n=12, max_level=20, num_special=1, digit_size=1, hamming_weight=0)
+# N = 2^12 with 24 scaling primes (insecure, test only): enough levels for
+# squares, the two means, CryptoInvSqrt (degree 127, 3 steps) and the final product
+SMALL = dict(log_n=12, max_level=24, num_special=1, digit_size=1, hamming_weight=0)
 
 
 def _ck():
@@ -27,7 +27,7 @@ def _ck():
 def small(oracle_mod):
     ck = _ck()
     g = ck.Context(**SMALL)
-    o = oracle_mod.Context(12, 20, 1, 1, h=0)
+    o = oracle_mod.Context(12, 24, 1, 1, h=0)
     gal = [g.galois_rot(1 << k) for k in range(11)]
     g.keygen(5, gal)
     o.keygen(5, gal)
@@ -60,14 +60,15 @@ def _oracle_znorm(o, cts, rows, B, d, it, lo, hi):
             s1 = acc
         else:
             s2 = acc
-    m1 = o.mul_const_down(s1, 1.0 / (rows * math.sqrt(B)))
-    m2 = o.mul_const_down(s2, 1.0 / (rows * B))
+    lr, lb = int(math.log2(rows)), int(math.log2(B))
+    m1 = o.rescale(o.mul_const(o.mul_const_down(s1, 1.0 / math.sqrt(B)), 2.0 ** -lr, 2.0 ** 40))
+    m2 = o.rescale(o.mul_const(s2, 2.0 ** -(lr + lb), 2.0 ** 40))
     m1sq = o.rescale(o.hmult(m1, m1))
-    lv = min(m1sq.level, m2.level)
+    lv = min(m1sq.level, m2.level) - 1
     v = o.sub(o.level_to(m2, lv), o.level_to(m1sq, lv))
     r = o.invsqrt(v, d, it, lo, hi)
     rs = o.mul_const_down(r, 1.0 / math.sqrt(B))
-    mean = o.mul_const_down(s1, 1.0 / rows)
+    mean = o.rescale(o.mul_const(s1, 2.0 ** -lr, 2.0 ** 40))
     z = []
     for x in cts:
         lvd = min(x.level, mean.level, rs.level + 1)
@@ -83,12 +84,12 @@ def test_znorm_batched_bit_exact_vs_oracle(small):
     cols, per = 3, 2
     rows = per * g.n
     data, mu, sigma = inputs.column_table(rows, cols, 7)
-    B, lo, hi, d, it = 128.0, 2.0 ** -14, 1.0, 15, 2
+    B, lo, hi, d, it = 128.0, 2.0 ** -14, 1.0, 127, 3
     gcols, ocols = [], []
     for c in range(cols):
         chunks = data[c].reshape(per, g.n)
-        gcols.append([g.encrypt(chunks[j], 20, 2.0 ** 40, 100 * c + j) for j in range(per)])
-        ocols.append([o.encrypt(chunks[j], 20, 2.0 ** 40, 100 * c + j) for j in range(per)])
+        gcols.append([g.encrypt(chunks[j], 24, 2.0 ** 40, 100 * c + j) for j in range(per)])
+        ocols.append([o.encrypt(chunks[j], 24, 2.0 ** 40, 100 * c + j) for j in range(per)])
     z, v, r = znorm.znorm(g, gcols, rows, B, d, it, lo, hi)
     vparts = g.unpack(v)
     for c in range(cols):
@@ -101,7 +102,7 @@ def test_znorm_batched_bit_exact_vs_oracle(small):
     c = 0
     zz = np.concatenate([g.decrypt(z[c][j]).real for j in range(per)])
     ref = (data[c] - data[c].mean()) / data[c].std()
-    assert np.max(np.abs(zz - ref)) < 1e-3
+    assert np.max(np.abs(zz - ref)) < 1e-4
 
 
 def test_serving_alone_equals_in_the_mix(small):
@@ -116,7 +117,7 @@ def test_serving_alone_equals_in_the_mix(small):
     for k in range(5):
         X = np.stack([inputs.log_uniform(g.n, 2 ** -10, 1.0, 300 + 10 * k + j) for j in range(sizes[k])])
         cts = g.encrypt_batch(X, levels[k], 2.0 ** 45, 500 + 10 * k)
-        reqs.append(serve.Request(k, 0.002 * k, cts, levels[k], targets[k]))
+        reqs.append(serve.Request(k, 0.0, cts, levels[k], targets[k]))
     srv = serve.run_continuous(g, table, reqs, max_batch=16)
     assert any(e["batch"] > max(sizes) for e in srv.log)   # requests shared a launch sequence
     for r in reqs:
@@ -127,7 +128,7 @@ def test_serving_alone_equals_in_the_mix(small):
 
 def test_znorm_full_size_accuracy():
     """N = 2^16 parameters, 4 columns of 2^17 rows (4 ciphertexts each),
-    tuned-style (31, 3) on [2^-14, 1]: z-scores against FP64."""
+    invsqrt (127, 3) on the variance domain [2^-14, 1]: z-scores against FP64."""
     ck = _ck()
     from paper_2606_10477_amd import znorm
     g = ck.Context(log_n=16, max_level=27, num_special=7, digit_size=10, hamming_weight=192)
@@ -137,13 +138,13 @@ def test_znorm_full_size_accuracy():
     data, _, _ = inputs.column_table(rows, cols, 8)
     gcols = []
     for c in range(cols):
-        gcols.append(g.encrypt_batch(data[c].reshape(per, g.n), 20, 2.0 ** 40, 1000 + 10 * c))
-    z, v, r = znorm.znorm(g, gcols, rows, 128.0, 31, 3, 2.0 ** -14, 1.0)
+        gcols.append(g.encrypt_batch(data[c].reshape(per, g.n), 22, 2.0 ** 40, 1000 + 10 * c))
+    z, v, r = znorm.znorm(g, gcols, rows, 128.0, 127, 3, 2.0 ** -14, 1.0)
     errs = []
     for c in range(cols):
         zz = np.concatenate([g.decrypt(z[c][j]).real for j in range(per)])
         ref = (data[c] - data[c].mean()) / data[c].std()
-        errs.append(np.mean(np.abs(zz - ref) / np.maximum(np.abs(ref), 1e-3)))
-    print("znorm full size: mean relative error per column", errs, flush=True)
-    assert max(errs) < 1e-3
+        errs.append(float(np.mean(np.abs(zz - ref))))
+    print("znorm full size: mean absolute z error per column", errs, flush=True)
+    assert max(errs) < 1e-5
     g.close()
