@@ -13,6 +13,7 @@
 #include <cstring>
 #include <map>
 #include <memory>
+#include <set>
 #include <stdexcept>
 #include <string>
 #include <thread>
@@ -39,47 +40,81 @@ void hipchk(hipError_t e, const char *what) {
 }
 
 // ---------------------------------------------------------------------------
-// Device memory pool: size-bucketed free lists over an optional caller arena
-// (bump allocation) or hipMalloc.  All users are ordered on one stream, so a
-// block freed after its last kernel was queued can be handed to the next
-// allocation immediately.
+// Device memory pool over an optional caller arena (bump allocation) or
+// hipMalloc.  Requests are rounded up to size classes (eight per octave above
+// 1 MiB, so at most 12.5% is wasted) and served best-fit from the cached free
+// blocks, taking any block of up to twice the class: batches of different
+// sizes reuse each other's blocks instead of allocating afresh.  All users are
+// ordered on one stream, so a block freed after its last kernel was queued can
+// be handed to the next allocation immediately.
 // ---------------------------------------------------------------------------
 class Pool {
 public:
     Pool(void *arena, size_t bytes) : base_((char *)arena), cap_(bytes), used_(0) {}
     ~Pool() {
-        for (void *p : owned_) (void)hipFree(p);
+        if (!base_)
+            for (auto &kv : size_) (void)hipFree(kv.first);
+    }
+    static size_t size_class(size_t b) {
+        b = (b + 255) & ~(size_t)255;
+        if (b <= ((size_t)1 << 20)) return b;
+        const int e = 63 - __builtin_clzll(b);
+        const size_t step = (size_t)1 << (e - 3);
+        return (b + step - 1) & ~(step - 1);
     }
     void *get(size_t bytes) {
-        bytes = (bytes + 255) & ~(size_t)255;
-        auto &fl = free_[bytes];
-        if (!fl.empty()) {
-            void *p = fl.back();
-            fl.pop_back();
-            return p;
-        }
-        if (base_) {
-            if (used_ + bytes > cap_) fail(CKKS_E_OOM, "arena exhausted");
-            void *p = base_ + used_;
-            used_ += bytes;
+        const size_t cls = size_class(bytes);
+        auto it = free_.lower_bound(cls);
+        if (it != free_.end() && it->first <= 2 * cls) {
+            void *p = it->second.back();
+            it->second.pop_back();
+            cached_ -= it->first;
+            if (it->second.empty()) free_.erase(it);
             return p;
         }
         void *p = nullptr;
-        if (hipMalloc(&p, bytes) != hipSuccess) fail(CKKS_E_OOM, "hipMalloc failed");
-        owned_.push_back(p);
+        if (base_) {
+            if (used_ + cls > cap_) fail(CKKS_E_OOM, "arena exhausted");
+            p = base_ + used_;
+            used_ += cls;
+        } else if (hipMalloc(&p, cls) != hipSuccess) {
+            // give the cached blocks back to the device and try once more
+            (void)hipGetLastError();
+            trim();
+            if (hipMalloc(&p, cls) != hipSuccess) {
+                (void)hipGetLastError();
+                fail(CKKS_E_OOM, "hipMalloc failed");
+            }
+        }
+        size_[p] = cls;
         return p;
     }
-    void put(void *p, size_t bytes) {
+    void put(void *p) {
         if (!p) return;
-        bytes = (bytes + 255) & ~(size_t)255;
-        free_[bytes].push_back(p);
+        const size_t sz = size_.at(p);
+        free_[sz].push_back(p);
+        cached_ += sz;
+        if (!base_ && cached_ > kCacheLimit) trim();
+    }
+    // free every cached block (blocks still queued for use by earlier work on
+    // the stream are safe: hipFree waits for outstanding work on the device)
+    void trim() {
+        if (base_) return;
+        for (auto &kv : free_)
+            for (void *p : kv.second) {
+                size_.erase(p);
+                (void)hipFree(p);
+            }
+        free_.clear();
+        cached_ = 0;
     }
 
 private:
+    static constexpr size_t kCacheLimit = (size_t)64 << 30;   // bytes of free blocks kept for reuse
     char *base_;
-    size_t cap_, used_;
-    std::map<size_t, std::vector<void *>> free_;
-    std::vector<void *> owned_;
+    size_t cap_, used_, cached_ = 0;
+    std::map<size_t, std::vector<void *>> free_;   // block size -> free blocks
+    std::map<void *, size_t> size_;                // every block -> its size
 };
 
 struct Buf {
@@ -89,14 +124,14 @@ struct Buf {
     Buf() = default;
     Buf(Pool *pl, size_t words) : pool(pl), bytes(words * 8) { p = (u64 *)pl->get(bytes); }
     ~Buf() {
-        if (pool && p) pool->put(p, bytes);
+        if (pool && p) pool->put(p);
     }
     Buf(const Buf &) = delete;
     Buf &operator=(const Buf &) = delete;
     Buf(Buf &&o) noexcept : pool(o.pool), p(o.p), bytes(o.bytes) { o.p = nullptr; }
     Buf &operator=(Buf &&o) noexcept {
         if (this != &o) {
-            if (pool && p) pool->put(p, bytes);
+            if (pool && p) pool->put(p);
             pool = o.pool; p = o.p; bytes = o.bytes;
             o.p = nullptr;
         }
