@@ -63,12 +63,19 @@ typedef enum {
  * uses digits of `digit_size` consecutive q-primes (dnum = ceil((L+1)/alpha)).
  * hamming_weight = 0 selects a dense ternary secret, otherwise a secret with
  * exactly that many +-1 coefficients.  sigma is the error standard deviation.
- * Bootstrapping (ckks_bootstrap) needs bts_levels > 0: the number of top
- * levels the bootstrapping circuit consumes (see ckks_bts_info).
+ *
+ * Bootstrapping chain (bts_evalmod_levels > 0): max_level is then the top
+ * level of computation, l_afterBTS of the paper (§2.1), and the levels that
+ * bootstrapping consumes are added above it: bts_stc_levels for SlotToCoeff
+ * (primes nearest 2^log_scale), bts_evalmod_levels for EvalMod (chosen top
+ * down like the computation levels but around 2^bts_log_scale) and
+ * bts_cts_levels for CoeffToSlot (primes nearest 2^bts_log_scale); the
+ * ciphertext modulus then has max_level + bts_stc_levels + bts_evalmod_levels
+ * + bts_cts_levels + 1 primes and digits are formed over all of them.
  */
 typedef struct {
     uint32_t log_n;           /* ring degree N = 2^log_n, 4..16 */
-    uint32_t max_level;       /* L: primes q_0..q_L */
+    uint32_t max_level;       /* L (plain chain) or l_afterBTS (bootstrapping chain) */
     uint32_t num_special;     /* K */
     uint32_t digit_size;      /* alpha */
     uint32_t hamming_weight;  /* 0 = dense ternary */
@@ -76,6 +83,10 @@ typedef struct {
     uint32_t log_scale;       /* 40 */
     uint32_t q0_bits;         /* 60 */
     uint32_t p_bits;          /* 60 */
+    uint32_t bts_stc_levels;      /* 3, or 0 for a plain chain */
+    uint32_t bts_evalmod_levels;  /* 10 for (K 25, r 4, degree 31), or 0 */
+    uint32_t bts_cts_levels;      /* 3, or 0 */
+    uint32_t bts_log_scale;       /* 52 */
 } ckks_params;
 
 /*
@@ -90,8 +101,9 @@ ckks_status ckks_ctx_create(const ckks_params *p, void *arena, size_t arena_byte
 void ckks_ctx_destroy(ckks_ctx *ctx);
 /* Last error message of this context (static text valid until the next call). */
 const char *ckks_last_error(const ckks_ctx *ctx);
-/* Copy the prime chain (L+1+K words: q_0..q_L, p_0..p_{K-1}) and the
- * canonical scale ladder S_0..S_L (L+1 doubles).  Either pointer may be NULL. */
+/* Copy the prime chain (L+1+K words: q_0..q_L, p_0..p_{K-1}, L the top
+ * level of the whole chain) and the canonical scale ladder S_0..S_L (L+1
+ * doubles).  Either pointer may be NULL. */
 ckks_status ckks_ctx_primes(const ckks_ctx *ctx, uint64_t *primes, double *ladder);
 /* Change the stream all later work is ordered on. */
 ckks_status ckks_set_stream(ckks_ctx *ctx, void *hip_stream);
@@ -198,23 +210,69 @@ ckks_status ckks_cheb_coeffs_invsqrt(uint32_t degree, double a, double b, double
 ckks_status ckks_newton_step(ckks_ctx *ctx, const ckks_ct *y, const ckks_ct *ct_half, int raw_x,
                              ckks_ct **out);
 
-/* Bootstrapping (paper §2.1 BTS) of a level-0..l ciphertext whose slot
- * values are real and lie in [-1, 1]: ModRaise, CoeffToSlot, EvalMod,
- * SlotToCoeff.  Needs the bootstrapping keys (ckks_bts_setup). */
-ckks_status ckks_bootstrap(ckks_ctx *ctx, const ckks_ct *a, ckks_ct **out);
+/*
+ * Bootstrapping (paper §2.1: BTS resets a ciphertext to level l_afterBTS).
+ * The slot transform of n = N/2 slots, z = V w with w_k = p_k + i p_{k+n}
+ * the coefficients of the plaintext p, factors into log2(n) butterfly stages
+ * (stage k: butterflies of length 2^k with twiddles exp(2 pi i (5^j mod
+ * 2^(k+2)) / 2^(k+2))) and a bit reversal; CoeffToSlot applies the inverse
+ * stages and SlotToCoeff the forward ones, the bit reversal cancelling.  The
+ * stages are grouped into three groups (one level each), each group
+ * evaluated as a baby-step giant-step sum over its nonzero diagonals.
+ *
+ * ckks_bts_setup: EvalMod approximates cos(2 pi (K u - 1/4) / 2^r) on
+ * u in [-1, 1] (u = t / K, t the ModRaised coefficient over q_0) by a
+ * Chebyshev interpolant of `degree`, then r double-angle steps give
+ * sin(2 pi t).  Needs a bootstrapping chain with bts_stc_levels = 3,
+ * bts_cts_levels = 3 and bts_evalmod_levels = depth(degree) + r, depth(d) =
+ * bitlen(d) + 1 for d >= 4 (the Chebyshev evaluation's consumption).
+ * Encodes the diagonal plaintexts of the six groups into device memory.
+ * The Galois keys listed by ckks_bts_rotations (left rotations) and the
+ * conjugation key (2N - 1) must be generated (ckks_keygen) before
+ * bootstrapping; ckks_bts_rotations writes at most cap steps and the count.
+ */
+ckks_status ckks_bts_setup(ckks_ctx *ctx, double K, uint32_t r, uint32_t degree);
+ckks_status ckks_bts_rotations(const ckks_ctx *ctx, int32_t *steps, uint32_t cap, uint32_t *count);
+/*
+ * ckks_bootstrap: a ciphertext at any level whose slot values are real and
+ * bounded by the integer `bound` in magnitude (its residues mod q_0 are
+ * used).  Steps: multiply by F = rint(s0 / (scale bound)), s0 = q_0 2^-5
+ * (exact integer, so the message fills about 2^-5 of q_0 whatever its
+ * scale); ModRaise; CoeffToSlot; re = y + conj(y), im = -i (y - conj(y));
+ * EvalMod of both (one batched evaluation); SlotToCoeff(re' + i im');
+ * multiply by `bound`.  Output at level l_afterBTS, scale
+ * S_out (scale F bound) / s0 with S_out ~ S_{l_afterBTS}.
+ * The steps are exposed for testing:
+ *   ckks_mod_raise: residues mod q_0 lifted to the centred range and
+ *     reduced mod q_0..q_L; declared scale 2 q_0 K.
+ *   ckks_coeff_to_slot: a ModRaised (level L) ciphertext -> level L - 3.
+ *   ckks_eval_mod: level L - 3 -> level l_afterBTS + 3.
+ *   ckks_slot_to_coeff: level l_afterBTS + 3 -> l_afterBTS.
+ *   ckks_mul_monomial: multiply by X^k (0 <= k < 2N), exact, no level
+ *     (X^(N/2) multiplies every slot by i).
+ */
+ckks_status ckks_bootstrap(ckks_ctx *ctx, const ckks_ct *a, int64_t bound, ckks_ct **out);
+ckks_status ckks_mod_raise(ckks_ctx *ctx, const ckks_ct *a, ckks_ct **out);
+ckks_status ckks_coeff_to_slot(ckks_ctx *ctx, const ckks_ct *a, ckks_ct **out);
+ckks_status ckks_eval_mod(ckks_ctx *ctx, const ckks_ct *a, ckks_ct **out);
+ckks_status ckks_slot_to_coeff(ckks_ctx *ctx, const ckks_ct *a, ckks_ct **out);
+ckks_status ckks_mul_monomial(ckks_ctx *ctx, const ckks_ct *a, int32_t k, ckks_ct **out);
 
 typedef struct {
     double a, b;        /* input domain of x (default 2^-10, 1) */
     int32_t literal;    /* 1: bootstrap y0 right after the Chebyshev step, as
                            Alg. 1 is written; 0 (default): bootstrap y only
                            when it has fewer than 2 levels before a step */
-    int32_t bts_scale;  /* y is bootstrapped as S * BTS(y / S), default 64 */
+    int32_t reserved;   /* 0 */
+    int64_t bts_bound;  /* message bound for bootstrapping y (0: 16 ceil(1/sqrt(a))) */
 } ckks_invsqrt_opts;
 
 /*
  * CryptoInvSqrt (paper Alg. 1): y0 = Chebyshev interpolant of degree `degree`
  * of 1/sqrt on [a, b]; ct_x = x/2; `iters` Newton steps; bootstrapping of y
- * per the policy in opts.  The last Newton step takes x/2 directly from the
+ * per the policy in opts.  Pre-BTS (the paper's c = 1): if x has fewer than
+ * depth(degree) + 1 levels or fewer than 3, x is bootstrapped first (bound
+ * 16 ceil(b)); otherwise x is never bootstrapped.  The last Newton step takes x/2 directly from the
  * input (limbs dropped, halving as an exact scale change, no rescale), so the
  * result keeps the relative precision of the input's scale; its scale is the
  * product of the step's scales (tracked exactly, not the canonical one).

@@ -8,7 +8,7 @@ import subprocess
 import sys
 
 HERE = os.path.dirname(os.path.abspath(__file__))
-SOURCES = ["ckks_oracle.c", "ckks_oracle_bts.c"]
+SOURCES = ["ckks_oracle.c"]
 
 
 def build(verbose=False):

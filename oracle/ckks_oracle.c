@@ -239,6 +239,9 @@ typedef struct orc_ctx {
     uint64_t *ipsi_br;       /* [np][N] psi^-br(k) */
     uint64_t *ninv;          /* [np] */
     double *ladder;          /* [L+1] canonical scale per level */
+    /* bootstrapping-shaped chain (all zero for a plain chain) */
+    int l_after, n_stc, n_evm, n_cts, bts_bits;
+    struct bts_plan *bts;    /* set by orc_bts_config */
     uint64_t cdt[64];        /* Gaussian CDT thresholds (53-bit) */
     int cdt_len;
     /* keys */
@@ -279,48 +282,81 @@ static int prime_used(const uint64_t *list, int cnt, uint64_t c) {
 
 /*
  * Prime chain (a reading: the paper gives only totals).
- *   q_0      : largest prime below 2^q0_bits with q = 1 mod 2N.
- *   q_L..q_1 : chosen top-down.  The canonical scale of level L is
- *              S_L = 2^log_delta and S_{l-1} = (S_l * S_l) / q_l.  q_l is
- *              the unused prime = 1 mod 2N closest to T = (S_l*S_l)/2^log_delta
- *              (first prime below T and first prime above T; the closer one
- *              wins, ties go to the lower).  This keeps every S_l close to
- *              2^log_delta, so a product of two level-l ciphertexts that
- *              carry S_l lands exactly on S_{l-1} after the rescale.
- *   p_0..p_{K-1}: the next primes = 1 mod 2N below q_0 (descending).
+ *   q_0 : largest prime below 2^q0_bits with q = 1 mod 2N.
+ *   Computation levels A..1 (A = L for a plain chain, A = l_after for a
+ *   bootstrapping chain): chosen top-down.  The canonical scale of level A
+ *   is S_A = 2^log_delta and S_{l-1} = (S_l * S_l) / q_l.  q_l is the unused
+ *   prime = 1 mod 2N closest to T = (S_l*S_l)/2^log_delta (first prime below
+ *   T and first prime above T; the closer one wins, ties go to the lower).
+ *   This keeps every S_l close to 2^log_delta, so a product of two level-l
+ *   ciphertexts that carry S_l lands exactly on S_{l-1} after the rescale.
+ * A bootstrapping chain adds, above level A, the levels that bootstrapping
+ * consumes (the ModRaised ciphertext enters at level L and leaves at A):
+ *   levels A+1..A+n_stc        SlotToCoeff: q_l = unused prime closest to
+ *                              2^log_delta (l ascending), S_l = 2^log_delta;
+ *   levels A+n_stc+1..E        EvalMod, E = A+n_stc+n_evm: the same adaptive
+ *                              rule as the computation levels, run top-down
+ *                              from S_E = 2^bts_bits (this also sets S at
+ *                              level A+n_stc, the EvalMod output);
+ *   levels E+1..L              CoeffToSlot: unused prime closest to
+ *                              2^bts_bits (l ascending), S_l = 2^bts_bits.
+ *   Selection order: q_0, computation levels, EvalMod, SlotToCoeff,
+ *   CoeffToSlot, then the special primes.
+ *   p_0..p_{K-1}: the next unused primes = 1 mod 2N below 2^p_bits (descending).
  */
+static uint64_t closest_prime(uint64_t M, double T, const uint64_t *chosen, int nch) {
+    uint64_t Ti = (uint64_t)floor(T);
+    uint64_t lo = Ti - ((Ti - 1) % M);          /* first candidate = 1 mod M at or below Ti */
+    uint64_t hi = lo + M;
+    while (!(orc_is_prime(lo) && !prime_used(chosen, nch, lo))) lo -= M;
+    while (!(orc_is_prime(hi) && !prime_used(chosen, nch, hi))) hi += M;
+    double dlo = T - (double)lo, dhi = (double)hi - T;
+    return (dhi < dlo) ? hi : lo;
+}
+/* adaptive top-down run over levels top..bot+1 starting from S_top = D */
+static void adaptive_run(orc_ctx *c, int top, int bot, double D, uint64_t *chosen, int *nch) {
+    uint64_t M = 2 * (uint64_t)c->N;
+    double S = D;
+    c->ladder[top] = S;
+    for (int l = top; l > bot; l--) {
+        double T = (S * S) / D;
+        uint64_t pick = closest_prime(M, T, chosen, *nch);
+        c->q[l] = pick;
+        chosen[(*nch)++] = pick;
+        S = (S * S) / (double)pick;
+        c->ladder[l - 1] = S;
+    }
+}
 static int gen_primes(orc_ctx *c, int q0_bits, int p_bits) {
     uint64_t M = 2 * (uint64_t)c->N;
-    int np = c->np;
     uint64_t *q = c->q;
-    int cnt = 0;
     uint64_t top = ((uint64_t)1 << q0_bits);
     uint64_t cand = top - ((top - 1) % M);      /* largest x <= top with x = 1 mod M */
     if (cand >= top) cand -= M;
     while (!orc_is_prime(cand)) cand -= M;
-    q[0] = cand; cnt = 1;
-    double S = ldexp(1.0, c->log_delta);
-    double two_d = ldexp(1.0, c->log_delta);
-    c->ladder[c->L] = S;
-    uint64_t chosen[128];
+    q[0] = cand;
+    uint64_t chosen[256];
     chosen[0] = q[0];
     int nch = 1;
-    for (int l = c->L; l >= 1; l--) {
-        double T = (S * S) / two_d;
-        uint64_t Ti = (uint64_t)floor(T);
-        /* first candidate = 1 mod M at or below Ti */
-        uint64_t lo = Ti - ((Ti - 1) % M);
-        uint64_t hi = lo + M;
-        while (!(orc_is_prime(lo) && !prime_used(chosen, nch, lo))) lo -= M;
-        while (!(orc_is_prime(hi) && !prime_used(chosen, nch, hi))) hi += M;
-        double dlo = T - (double)lo, dhi = (double)hi - T;
-        uint64_t pick = (dhi < dlo) ? hi : lo;
-        q[l] = pick;
-        chosen[nch++] = pick;
-        S = (S * S) / (double)pick;
-        c->ladder[l - 1] = S;
+    const double Dc = ldexp(1.0, c->log_delta);
+    const int A = c->l_after;
+    adaptive_run(c, A, 0, Dc, chosen, &nch);
+    if (c->n_evm > 0) {
+        const double Db = ldexp(1.0, c->bts_bits);
+        const int E = A + c->n_stc + c->n_evm;
+        adaptive_run(c, E, A + c->n_stc, Db, chosen, &nch);
+        for (int l = A + 1; l <= A + c->n_stc; l++) {
+            q[l] = closest_prime(M, Dc, chosen, nch);
+            chosen[nch++] = q[l];
+            if (l < A + c->n_stc) c->ladder[l] = Dc;
+        }
+        for (int l = E + 1; l <= c->L; l++) {
+            q[l] = closest_prime(M, Db, chosen, nch);
+            chosen[nch++] = q[l];
+            c->ladder[l] = Db;
+        }
     }
-    cnt = c->L + 1;
+    int cnt = c->L + 1;
     uint64_t ptop = ((uint64_t)1 << p_bits);
     uint64_t pc = ptop - ((ptop - 1) % M);
     if (pc >= ptop) pc -= M;
@@ -330,7 +366,6 @@ static int gen_primes(orc_ctx *c, int q0_bits, int p_bits) {
         chosen[nch++] = pc;
         pc -= M;
     }
-    (void)np;
     return 0;
 }
 
@@ -366,10 +401,14 @@ int orc_cdt(orc_ctx *c, uint64_t *out) {
     return c->cdt_len;
 }
 
-orc_ctx *orc_ctx_create(int logN, int L, int K, int alpha, int h, double sigma,
-                        int log_delta, int q0_bits, int p_bits) {
-    if (logN < 2 || logN > 17 || L < 1 || L > 60 || K < 1 || alpha < 1 ||
-        q0_bits > 61 || p_bits > 61 || log_delta < 20 || log_delta > 58) {
+orc_ctx *orc_ctx_create_bts(int logN, int l_after, int n_stc, int n_evm, int n_cts, int bts_bits,
+                            int K, int alpha, int h, double sigma, int log_delta, int q0_bits, int p_bits) {
+    const int bts = n_evm > 0;
+    const int L = l_after + n_stc + n_evm + n_cts;
+    if (logN < 2 || logN > 17 || l_after < 1 || L > 60 || K < 1 || alpha < 1 ||
+        q0_bits > 61 || p_bits > 61 || log_delta < 20 || log_delta > 58 ||
+        (bts && (n_stc < 1 || n_cts < 1 || bts_bits < 20 || bts_bits > 61 || logN < 4)) ||
+        (!bts && (n_stc || n_cts))) {
         set_err("bad parameters");
         return NULL;
     }
@@ -377,6 +416,7 @@ orc_ctx *orc_ctx_create(int logN, int L, int K, int alpha, int h, double sigma,
     c->logN = logN; c->N = 1 << logN; c->n = c->N / 2;
     c->L = L; c->K = K; c->alpha = alpha; c->h = h; c->sigma = sigma;
     c->log_delta = log_delta;
+    c->l_after = l_after; c->n_stc = n_stc; c->n_evm = n_evm; c->n_cts = n_cts; c->bts_bits = bts_bits;
     c->dnum = (L + 1 + alpha - 1) / alpha;
     c->np = L + 1 + K;
     c->q = calloc(c->np, sizeof(uint64_t));
@@ -400,8 +440,14 @@ orc_ctx *orc_ctx_create(int logN, int L, int K, int alpha, int h, double sigma,
     build_cdt(c);
     return c;
 }
+orc_ctx *orc_ctx_create(int logN, int L, int K, int alpha, int h, double sigma,
+                        int log_delta, int q0_bits, int p_bits) {
+    return orc_ctx_create_bts(logN, L, 0, 0, 0, 0, K, alpha, h, sigma, log_delta, q0_bits, p_bits);
+}
 
 static void evk_free(evk_t *e) { free(e->k); e->k = NULL; }
+struct bts_plan;
+static void bts_plan_free(struct bts_plan *b);
 void orc_ctx_free(orc_ctx *c) {
     if (!c) return;
     free(c->q); free(c->psi_br); free(c->ipsi_br); free(c->ninv); free(c->ladder);
@@ -409,6 +455,7 @@ void orc_ctx_free(orc_ctx *c) {
     evk_free(&c->relin);
     for (int i = 0; i < c->nrot; i++) evk_free(&c->rot[i]);
     free(c->rot);
+    bts_plan_free(c->bts);
     free(c);
 }
 int orc_ctx_info(orc_ctx *c, uint64_t *primes, double *ladder) {
@@ -1539,8 +1586,461 @@ orc_ct *orc_newton_step(orc_ctx *c, const orc_ct *y, const orc_ct *ctx_half) {
     return orc_newton_step_ex(c, y, ctx_half, 0);
 }
 
-/* forward declaration: bootstrapping of y with the 1/S_bts pre-scaling */
-orc_ct *orc_bootstrap(orc_ctx *c, const orc_ct *a);
+/* ------------------------------------------------------------------------ */
+/* Bootstrapping (§2.1: BTS resets a ciphertext's level to l_afterBTS; the  */
+/* scheme's bootstrapping as cited there).  Written from the CKKS           */
+/* bootstrapping construction: ModRaise, CoeffToSlot, EvalMod (cosine and   */
+/* double angle), SlotToCoeff.                                               */
+/*                                                                           */
+/* Slot transform.  With n = N/2 slots at the roots zeta^(5^j) (zeta =      */
+/* exp(i pi / N)), slot j of a real polynomial p is                          */
+/*   z_j = sum_{k<n} w_k zeta^(5^j k),   w_k = p_k + i p_{k+n},             */
+/* i.e. z = V w.  V factors as V = B_n B_{n/2} ... B_2 R, R the bit          */
+/* reversal of w and B_len (len = 2^k) block diagonal with blocks of length  */
+/* len, each butterfly pairing positions j and j + len/2 of its block:       */
+/*   y_j = x_j + t_j x_{j+len/2},  y_{j+len/2} = x_j - t_j x_{j+len/2},      */
+/*   t_j = exp(2 pi i (5^j mod 4 len) / (4 len)),  j < len/2.                */
+/* CoeffToSlot applies B_n^-1, ..., B_2^-1 (output: R w, coefficients in bit  */
+/* reversed order) and SlotToCoeff applies B_2, ..., B_n to R w, so R is      */
+/* never evaluated.  The log2(n) stages are grouped into three groups of     */
+/* floor(log2 n / 3) stages, the first (log2 n mod 3) groups, counted from   */
+/* the top stage, taking one more; each group is one plaintext-matrix        */
+/* product (one level), evaluated by baby-step giant-step over its nonzero   */
+/* diagonals.                                                                */
+/* ------------------------------------------------------------------------ */
+typedef struct {
+    int kmin, kmax;  /* stages k in [kmin, kmax] (butterfly length 2^k) */
+    int s;           /* offset stride 2^(kmin-1) */
+    int g;           /* giant step, in units of s */
+    int nm;          /* nonzero diagonals */
+    int *m;          /* their offsets in units of s, ascending */
+    cq **d;          /* d[t][j] = M[j][(j + m[t] s) mod n] */
+} lt_group;
+
+struct bts_plan {
+    double Kp;       /* EvalMod interval: t = p/q_0 in [-Kp, Kp] */
+    int r, deg;      /* double-angle steps, Chebyshev degree of the cosine */
+    double *cf;
+    lt_group cts[3], stc[3];   /* in application order */
+    double cts_sd[3], stc_sd[3];   /* plaintext scale of each stage */
+};
+
+static void lt_free(lt_group *G) {
+    for (int t = 0; t < G->nm; t++) free(G->d[t]);
+    free(G->d); free(G->m);
+    memset(G, 0, sizeof(*G));
+}
+static void bts_plan_free(struct bts_plan *b) {
+    if (!b) return;
+    for (int i = 0; i < 3; i++) { lt_free(&b->cts[i]); lt_free(&b->stc[i]); }
+    free(b->cf);
+    free(b);
+}
+
+/* the three nonzero diagonals of B_len (inv: of its inverse) at offsets
+ * 0, +len/2, -len/2 (mod n); with len = n the last two offsets coincide */
+static void stage_diags(int n, int k, int inv, cq *d0, cq *dp, cq *dm) {
+    int len = 1 << k, h = len / 2;
+    for (int j = 0; j < n; j++) {
+        int jj = j % len;
+        cq zero = {0, 0}, one = {1, 0};
+        d0[j] = zero; dp[j] = zero; dm[j] = zero;
+        if (jj < h) {
+            cq t = cq_root((int64_t)powmod(5, (uint64_t)jj, 4 * (uint64_t)len), 4 * (int64_t)len);
+            if (!inv) { d0[j] = one; dp[j] = t; }
+            else { cq half = {0.5Q, 0}; d0[j] = half; dp[j] = half; }
+        } else {
+            cq t = cq_root((int64_t)powmod(5, (uint64_t)(jj - h), 4 * (uint64_t)len), 4 * (int64_t)len);
+            if (!inv) { cq mt = {-t.re, -t.im}; d0[j] = mt; dm[j] = one; }
+            else {
+                /* 1 / (2 t) = conj(t) / 2 since |t| = 1 */
+                cq ih = {t.re / 2, -t.im / 2};
+                cq mih = {-ih.re, -ih.im};
+                dm[j] = ih; d0[j] = mih;
+            }
+        }
+    }
+}
+
+/* product of the stages ks[0..cnt-1] (applied in that order) in diagonal form */
+static void group_build(int n, const int *ks, int cnt, int inv, f128 cmul, lt_group *G) {
+    cq **cur = calloc(n, sizeof(cq *));
+    cur[0] = malloc(sizeof(cq) * n);
+    for (int j = 0; j < n; j++) { cur[0][j].re = cmul; cur[0][j].im = 0; }
+    cq *sd[3];
+    for (int i = 0; i < 3; i++) sd[i] = malloc(sizeof(cq) * n);
+    G->kmin = ks[0]; G->kmax = ks[0];
+    for (int t = 0; t < cnt; t++) {
+        int k = ks[t], h = 1 << (k - 1);
+        if (k < G->kmin) G->kmin = k;
+        if (k > G->kmax) G->kmax = k;
+        stage_diags(n, k, inv, sd[0], sd[1], sd[2]);
+        int off[3] = {0, h % n, (n - h) % n};
+        cq **nx = calloc(n, sizeof(cq *));
+        for (int p = 0; p < n; p++) {
+            if (!cur[p]) continue;
+            for (int e = 0; e < 3; e++) {
+                int o = off[e], dst = (o + p) % n;
+                if (!nx[dst]) nx[dst] = calloc(n, sizeof(cq));
+                for (int j = 0; j < n; j++) {
+                    cq v = cq_mul(sd[e][j], cur[p][(j + o) % n]);
+                    nx[dst][j] = cq_add(nx[dst][j], v);
+                }
+            }
+        }
+        for (int p = 0; p < n; p++) free(cur[p]);
+        free(cur);
+        cur = nx;
+    }
+    for (int i = 0; i < 3; i++) free(sd[i]);
+    G->s = 1 << (G->kmin - 1);
+    int ns = n / G->s, nk = G->kmax - G->kmin + 1;
+    int wrap = ns <= (1 << nk);
+    G->nm = 0;
+    G->m = malloc(sizeof(int) * n);
+    G->d = malloc(sizeof(cq *) * n);
+    /* collect nonzero diagonals, as signed offsets m (units of s) */
+    int *mm = malloc(sizeof(int) * n);
+    cq **dd = malloc(sizeof(cq *) * n);
+    int cntd = 0;
+    for (int o = 0; o < n; o++) {
+        if (!cur[o]) continue;
+        int nz = 0;
+        for (int j = 0; j < n && !nz; j++) nz = (cur[o][j].re != 0 || cur[o][j].im != 0);
+        if (!nz) { free(cur[o]); continue; }
+        int m = o / G->s;                    /* every offset is a multiple of s */
+        if (!wrap && m > ns / 2) m -= ns;
+        mm[cntd] = m; dd[cntd] = cur[o]; cntd++;
+    }
+    free(cur);
+    /* ascending m */
+    for (int i = 0; i < cntd; i++) {
+        int best = i;
+        for (int j = i + 1; j < cntd; j++) if (mm[j] < mm[best]) best = j;
+        int tm = mm[i]; mm[i] = mm[best]; mm[best] = tm;
+        cq *td = dd[i]; dd[i] = dd[best]; dd[best] = td;
+    }
+    for (int i = 0; i < cntd; i++) { G->m[i] = mm[i]; G->d[i] = dd[i]; }
+    G->nm = cntd;
+    free(mm); free(dd);
+    int span = G->m[cntd - 1] - G->m[0] + 1, e = 0;
+    while ((1 << e) < span) e++;
+    G->g = 1 << ((e + 1) / 2);
+}
+
+/* content scale of a unit message at the bootstrapping input: q_0 2^-5 */
+static double bts_content_scale(const orc_ctx *c) { return ldexp((double)c->q[0], -5); }
+
+static int floordiv(int a, int b) { int q = a / b; if ((a % b) != 0 && ((a < 0) != (b < 0))) q--; return q; }
+
+/*
+ * Configure bootstrapping: EvalMod approximates cos(2 pi (Kp u - 1/4) / 2^r)
+ * on u in [-1, 1] by a degree-`deg` Chebyshev interpolant (u = t / Kp,
+ * t = p / q_0 the ModRaised coefficient over q_0) and applies r double-angle
+ * steps cos(2a) = 2 cos(a)^2 - 1, giving sin(2 pi t).  Requires the chain's
+ * SlotToCoeff and CoeffToSlot regions to have three levels each and EvalMod
+ * to have cheb_depth(deg) + r levels.
+ */
+/* levels the Chebyshev evaluation above consumes for degree d on [-1, 1]:
+ * the baby powers T_1..T_{2^b - 1} take b levels (b >= 2), their scalar
+ * combination one more, and each of the m - b giant products one: m + 1
+ * with m = bitlen(d), except m <= 2 (a single baby power T_1): m */
+static int cheb_depth(int d) { int m = bitlen(d); return m >= 3 ? m + 1 : m; }
+int orc_bts_config(orc_ctx *c, double Kp, int r, int deg) {
+    if (c->n_evm <= 0) { set_err("chain has no bootstrapping levels"); return -1; }
+    if (c->n_stc != 3 || c->n_cts != 3 || c->n_evm != cheb_depth(deg) + r || Kp <= 1 || r < 0 || deg < 2) {
+        set_err("bootstrapping configuration does not match the chain");
+        return -1;
+    }
+    bts_plan_free(c->bts);
+    struct bts_plan *b = calloc(1, sizeof(*b));
+    b->Kp = Kp; b->r = r; b->deg = deg;
+    b->cf = malloc(sizeof(double) * (deg + 1));
+    orc_cheb_coeffs_cosmod(deg, Kp, ldexp(1.0, r), b->cf);
+    int n = c->n, logn = c->logN - 1;
+    int sizes[3], top = logn;
+    for (int i = 0; i < 3; i++) sizes[i] = logn / 3 + (i < logn % 3 ? 1 : 0);
+    f128 cs = (f128)c->q[0] / (2 * M_PIq * (f128)bts_content_scale(c));
+    for (int i = 0; i < 3; i++) {
+        int ks[32];
+        /* CoeffToSlot group i: stages top, top-1, ..., applied in that order */
+        for (int t = 0; t < sizes[i]; t++) ks[t] = top - t;
+        group_build(n, ks, sizes[i], 1, 1.0Q, &b->cts[i]);
+        /* the SlotToCoeff group with the same stages is applied at position 2-i,
+         * its stages ascending; the first one applied carries q_0 / (2 pi s_0),
+         * s_0 = q_0 2^-5 the input content scale of a unit message */
+        int kr[32];
+        for (int t = 0; t < sizes[i]; t++) kr[t] = top - sizes[i] + 1 + t;
+        group_build(n, kr, sizes[i], 0, i == 2 ? cs : 1.0Q, &b->stc[2 - i]);
+        top -= sizes[i];
+    }
+    /* plaintext scales from the nominal scale chain.  CoeffToSlot starts at
+     * the ModRaise scale D = 2 q_0 Kp and ends on S_{L-3}; SlotToCoeff starts
+     * at S_{l_after+3} (the EvalMod output) and ends on S_{l_after}.  With
+     * f = cbrt(end / start) the stage targets are start f, start f f, end;
+     * stage t at level lv has s_d = (target * q_lv) / s and leaves the
+     * scale (s * s_d) / q_lv. */
+    for (int pass = 0; pass < 2; pass++) {
+        int lv = pass == 0 ? c->L : c->l_after + 3;
+        double s = pass == 0 ? 2.0 * (double)c->q[0] * Kp : c->ladder[c->l_after + 3];
+        double end = pass == 0 ? c->ladder[c->L - 3] : c->ladder[c->l_after];
+        double f = cbrt(end / s);
+        double tg[3];
+        tg[0] = s * f;
+        tg[1] = tg[0] * f;
+        tg[2] = end;
+        double *sd = pass == 0 ? b->cts_sd : b->stc_sd;
+        for (int t = 0; t < 3; t++, lv--) {
+            sd[t] = (tg[t] * (double)c->q[lv]) / s;
+            s = (s * sd[t]) / (double)c->q[lv];
+        }
+    }
+    c->bts = b;
+    return 0;
+}
+
+static void lt_steps(const orc_ctx *c, const lt_group *G, int *seen, int n) {
+    for (int t = 0; t < G->nm; t++) {
+        int i = floordiv(G->m[t], G->g), bb = G->m[t] - G->g * i;
+        int kb = (int)(((int64_t)bb * G->s) % n);
+        int kg = (int)((((int64_t)G->g * i * G->s) % n + n) % n);
+        if (kb) seen[kb] = 1;
+        if (kg) seen[kg] = 1;
+    }
+    (void)c;
+}
+/* left-rotation amounts (in [1, n)) whose Galois keys bootstrapping uses,
+ * ascending; the conjugation key (2N - 1) is needed as well */
+int orc_bts_rotations(orc_ctx *c, int32_t *out, int max) {
+    if (!c->bts) { set_err("bootstrapping not configured"); return -1; }
+    int n = c->n, cnt = 0;
+    int *seen = calloc(n, sizeof(int));
+    for (int i = 0; i < 3; i++) { lt_steps(c, &c->bts->cts[i], seen, n); lt_steps(c, &c->bts->stc[i], seen, n); }
+    for (int k = 1; k < n; k++)
+        if (seen[k]) { if (out && cnt < max) out[cnt] = k; cnt++; }
+    free(seen);
+    return cnt;
+}
+
+static uint64_t i128_mod(i128 v, uint64_t q) {
+    i128 r = v % (i128)q;
+    if (r < 0) r += q;
+    return (uint64_t)r;
+}
+
+/* baby-step giant-step product of a group matrix with the slots of x:
+ *   out = sum_i rot_{g i s}( sum_b P_{i,b} * rot_{b s}(x) ),
+ *   P_{i,b} = diagonal m = g i + b rotated right by g i s, encoded at
+ *   scale sd;  one rescale at the end (scale (scale(x) sd) / q_l). */
+static orc_ct *lt_apply(orc_ctx *c, const orc_ct *x, const lt_group *G, double sd) {
+    int l = x->level, n = c->n;
+    size_t N = c->N;
+    if (l < 1) { set_err("level"); return NULL; }
+    int g = G->g;
+    orc_ct **R = calloc(g, sizeof(orc_ct *));
+    for (int t = 0; t < G->nm; t++) {
+        int i = floordiv(G->m[t], g), bb = G->m[t] - g * i;
+        if (!R[bb]) R[bb] = bb == 0 ? ct_copy(c, x) : orc_rotate(c, x, bb * G->s);
+        if (!R[bb]) { for (int k = 0; k < g; k++) orc_ct_free(R[k]); free(R); return NULL; }
+    }
+    cq *v = malloc(sizeof(cq) * n);
+    i128 *coef = malloc(sizeof(i128) * N);
+    uint64_t *pt = malloc(sizeof(uint64_t) * N);
+    orc_ct *acc = NULL;
+    int imin = floordiv(G->m[0], g), imax = floordiv(G->m[G->nm - 1], g);
+    int fail = 0;
+    for (int i = imin; i <= imax && !fail; i++) {
+        orc_ct *inner = NULL;
+        for (int t = 0; t < G->nm; t++) {
+            if (floordiv(G->m[t], g) != i) continue;
+            int bb = G->m[t] - g * i;
+            int64_t sh = (int64_t)g * i * G->s;
+            for (int j = 0; j < n; j++) {
+                int64_t src = (((int64_t)j - sh) % n + n) % n;
+                v[j] = G->d[t][src];
+            }
+            if (encode_q(c, v, (f128)sd, coef) != 0) { set_err("diagonal out of range"); fail = 1; break; }
+            if (!inner) { inner = ct_new(c, l, x->scale * sd); memset(inner->c, 0, sizeof(uint64_t) * 2 * (l + 1) * N); }
+            for (int li = 0; li <= l; li++) {
+                uint64_t q = c->q[li];
+                for (size_t k = 0; k < N; k++) pt[k] = i128_mod(coef[k], q);
+                ntt_fwd(c, li, pt);
+                for (int p = 0; p < 2; p++) {
+                    const uint64_t *src = ct_poly(c, R[bb], p) + (size_t)li * N;
+                    uint64_t *dst = ct_poly(c, inner, p) + (size_t)li * N;
+                    for (size_t k = 0; k < N; k++) dst[k] = addmod(dst[k], mulmod(pt[k], src[k], q), q);
+                }
+            }
+        }
+        if (fail || !inner) continue;
+        if (i != 0) {
+            orc_ct *ri = orc_rotate(c, inner, (int)(((int64_t)g * i * G->s) % n));
+            orc_ct_free(inner);
+            if (!ri) { fail = 1; break; }
+            inner = ri;
+        }
+        if (!acc) acc = inner;
+        else { orc_ct *t2 = orc_add(c, acc, inner); orc_ct_free(acc); orc_ct_free(inner); acc = t2; }
+    }
+    free(v); free(coef); free(pt);
+    for (int k = 0; k < g; k++) orc_ct_free(R[k]);
+    free(R);
+    if (fail || !acc) { orc_ct_free(acc); return NULL; }
+    orc_ct *r = orc_rescale(c, acc);
+    orc_ct_free(acc);
+    return r;
+}
+
+/* ModRaise: the residues mod q_0, lifted to the centred range (-q_0/2, q_0/2]
+ * and reduced mod every q_i of level L.  The result decrypts to m + q_0 I
+ * with a small integer polynomial I.  Declared scale 2 q_0 Kp, so that
+ * CoeffToSlot (whose matrices carry no extra constant) yields the
+ * coefficients over q_0 Kp after the conjugate split. */
+orc_ct *orc_mod_raise(orc_ctx *c, const orc_ct *a) {
+    if (!c->bts) { set_err("bootstrapping not configured"); return NULL; }
+    int L = c->L;
+    size_t N = c->N;
+    uint64_t q0 = c->q[0];
+    orc_ct *r = ct_new(c, L, 2.0 * (double)q0 * c->bts->Kp);
+    uint64_t *t = malloc(sizeof(uint64_t) * N);
+    for (int p = 0; p < 2; p++) {
+        memcpy(t, ct_poly(c, a, p), sizeof(uint64_t) * N);
+        ntt_inv(c, 0, t);
+        for (int i = 0; i <= L; i++) {
+            uint64_t *dst = ct_poly(c, r, p) + (size_t)i * N;
+            for (size_t k = 0; k < N; k++) {
+                int64_t u = t[k] <= (q0 - 1) / 2 ? (int64_t)t[k] : (int64_t)t[k] - (int64_t)q0;
+                dst[k] = smod(u, c->q[i]);
+            }
+            ntt_fwd(c, i, dst);
+        }
+    }
+    free(t);
+    return r;
+}
+
+/* multiply by the monomial X^k (0 <= k < 2N): exact, no level, same scale.
+ * X^(N/2) multiplies every slot by i. */
+orc_ct *orc_mul_monomial(orc_ctx *c, const orc_ct *a, int k) {
+    size_t N = c->N;
+    k %= 2 * c->N; if (k < 0) k += 2 * c->N;
+    orc_ct *r = ct_new(c, a->level, a->scale);
+    uint64_t *t = malloc(sizeof(uint64_t) * N);
+    for (int p = 0; p < 2; p++)
+        for (int i = 0; i <= a->level; i++) {
+            uint64_t q = c->q[i];
+            memcpy(t, ct_poly(c, a, p) + (size_t)i * N, sizeof(uint64_t) * N);
+            ntt_inv(c, i, t);
+            uint64_t *dst = ct_poly(c, r, p) + (size_t)i * N;
+            memset(dst, 0, sizeof(uint64_t) * N);
+            for (size_t j = 0; j < N; j++) {
+                size_t e = (j + (size_t)k) % (2 * N);
+                if (e < N) dst[e] = addmod(dst[e], t[j], q);
+                else dst[e - N] = submod(dst[e - N], t[j], q);
+            }
+            ntt_fwd(c, i, dst);
+        }
+    free(t);
+    return r;
+}
+
+/* CoeffToSlot on a ModRaised ciphertext (level L): the three groups with
+ * the configured plaintext scales (the scale reduction from the ModRaise
+ * scale to S_{L-3}, and with it the precision of the diagonal plaintexts,
+ * is shared evenly by the three stages) */
+orc_ct *orc_coeff_to_slot(orc_ctx *c, const orc_ct *a) {
+    if (!c->bts) { set_err("bootstrapping not configured"); return NULL; }
+    if (a->level != c->L) { set_err("CoeffToSlot expects a ModRaised ciphertext"); return NULL; }
+    orc_ct *x = ct_copy(c, a);
+    for (int t = 0; t < 3 && x; t++) {
+        orc_ct *y = lt_apply(c, x, &c->bts->cts[t], c->bts->cts_sd[t]);
+        orc_ct_free(x);
+        x = y;
+    }
+    return x;
+}
+/* SlotToCoeff from the EvalMod output level l_after + 3 down to l_after */
+orc_ct *orc_slot_to_coeff(orc_ctx *c, const orc_ct *a) {
+    if (!c->bts) { set_err("bootstrapping not configured"); return NULL; }
+    if (a->level != c->l_after + 3) { set_err("SlotToCoeff expects the EvalMod output level"); return NULL; }
+    orc_ct *x = ct_copy(c, a);
+    for (int t = 0; t < 3 && x; t++) {
+        orc_ct *y = lt_apply(c, x, &c->bts->stc[t], c->bts->stc_sd[t]);
+        orc_ct_free(x);
+        x = y;
+    }
+    return x;
+}
+/* EvalMod: Chebyshev interpolant of the scaled cosine, then r double angles */
+orc_ct *orc_eval_mod(orc_ctx *c, const orc_ct *u) {
+    if (!c->bts) { set_err("bootstrapping not configured"); return NULL; }
+    orc_ct *y = orc_cheb_eval(c, u, c->bts->cf, c->bts->deg, -1.0, 1.0);
+    for (int k = 0; k < c->bts->r && y; k++) {
+        orc_ct *sq = mult_rs(c, y, y);
+        orc_ct_free(y);
+        if (!sq) return NULL;
+        orc_ct *t2 = orc_mul_int(c, sq, 2);
+        orc_ct_free(sq);
+        y = orc_add_const(c, t2, -1.0);
+        orc_ct_free(t2);
+    }
+    return y;
+}
+
+/*
+ * Bootstrapping of a ciphertext at any level whose message is bounded by the
+ * integer M (|m| <= M); its residues mod q_0 are used.  The sine is
+ * linearised around the integers and bootstrapping adds an error of fixed
+ * size relative to q_0, so the message content is first brought to about
+ * s_0 / M with s_0 = q_0 2^-5 by an exact integer multiply:
+ *   F    = rint(s_0 / (scale(a) M))   (1 <= F < 2^40)
+ *   a'   = F a (mod q_0)
+ *   y    = CoeffToSlot(ModRaise(a'))
+ *   re   = y + conj(y),  im = -i (y - conj(y))     (-i: monomial X^(3N/2))
+ *   e_re = EvalMod(re), e_im = EvalMod(im)
+ *   z    = SlotToCoeff(e_re + i e_im)              (i: monomial X^(N/2))
+ *   out  = M z (integer multiply), scale(out) = scale(z) ((scale(a) F) M) / s_0
+ * Output at level l_afterBTS (the chain's l_after) with the message
+ * unchanged; its scale is within about 1/F of S_{l_after}.
+ */
+orc_ct *orc_bootstrap(orc_ctx *c, const orc_ct *a, int64_t M) {
+    if (!c->bts) { set_err("bootstrapping not configured"); return NULL; }
+    if (M < 1) { set_err("message bound must be >= 1"); return NULL; }
+    int N = c->N;
+    double s0 = bts_content_scale(c);
+    double Fd = rint(s0 / (a->scale * (double)M));
+    if (!(Fd >= 1.0 && Fd < 1099511627776.0)) { set_err("input scale out of range for bootstrapping"); return NULL; }
+    orc_ct *a0 = orc_drop_level(c, a, 0);
+    if (!a0) return NULL;
+    orc_ct *aF = mul_int64(c, a0, (int64_t)Fd, a0->scale);
+    orc_ct_free(a0);
+    orc_ct *raised = orc_mod_raise(c, aF);
+    orc_ct_free(aF);
+    orc_ct *y = raised ? orc_coeff_to_slot(c, raised) : NULL;
+    orc_ct_free(raised);
+    if (!y) return NULL;
+    orc_ct *yc = orc_conjugate(c, y);
+    if (!yc) { orc_ct_free(y); return NULL; }
+    orc_ct *sum = orc_add(c, y, yc), *dif = orc_sub(c, y, yc);
+    orc_ct_free(y); orc_ct_free(yc);
+    orc_ct *im = orc_mul_monomial(c, dif, 3 * N / 2);
+    orc_ct_free(dif);
+    orc_ct *er = orc_eval_mod(c, sum);
+    orc_ct *ei = er ? orc_eval_mod(c, im) : NULL;
+    orc_ct_free(sum); orc_ct_free(im);
+    if (!er || !ei) { orc_ct_free(er); orc_ct_free(ei); return NULL; }
+    orc_ct *eii = orc_mul_monomial(c, ei, N / 2);
+    orc_ct_free(ei);
+    orc_ct *w = orc_add(c, er, eii);
+    orc_ct_free(er); orc_ct_free(eii);
+    if (!w) return NULL;
+    orc_ct *z = orc_slot_to_coeff(c, w);
+    orc_ct_free(w);
+    if (!z) return NULL;
+    orc_ct *out = mul_int64(c, z, M, z->scale * (((a->scale * Fd) * (double)M) / s0));
+    orc_ct_free(z);
+    return out;
+}
 
 /*
  * CryptoInvSqrt (paper Alg. 1) for x in [a, b] subset (0, 1]:
@@ -1549,45 +2049,52 @@ orc_ct *orc_bootstrap(orc_ctx *c, const orc_ct *a);
  *   if literal: y = BTS(y)
  *   repeat n times: [lazy policy: y = BTS(y) when l_y < 2]
  *                   y = NewtonStep(y, ct_x)
- * The last Newton step takes x/2 directly from the input ciphertext: its
- * limbs are dropped to the step's level and the halving is the exact
- * scale change scale(x) -> 2 scale(x), with no rescale, so x keeps the
- * precision of its input scale (the fixed point of the last step is the
- * square root of the x it sees; earlier steps' errors are squared away).
- * BTS of y is done as  S * BTS(y / S)  with S = 64 (y <= 32 on the inputs of
- * interest) and the division folded into the scale: scale(y) *= S before,
- * integer multiply by S after.
+ * Pre-BTS (the paper's c = 1): when x has fewer than cheb_depth(d) + 1
+ * levels (the affine map and the Chebyshev tree) or fewer than 3 (ct_x needs
+ * 2 for Newton), x is bootstrapped first, with message bound 16 ceil(b).
+ * x itself is never bootstrapped otherwise (the c = 0 path).  y is
+ * bootstrapped with message bound bts_bound (0: 16 ceil(1 / sqrt(a)), y ~
+ * 1/sqrt(x) <= 1/sqrt(a)); the factor 16 keeps the message well inside the
+ * range where the sine is linear (the constant coefficient, the slot mean,
+ * is the largest).
+ * The last Newton step takes x/2 directly from the (possibly bootstrapped)
+ * input ciphertext: its limbs are dropped to the step's level and the
+ * halving is the exact scale change scale(x) -> 2 scale(x), with no rescale,
+ * so x keeps the precision of its own scale.
  */
-orc_ct *orc_bts_scaled(orc_ctx *c, const orc_ct *y, int S) {
-    orc_ct *t = ct_copy(c, y);
-    t->scale = y->scale * (double)S;
-    orc_ct *b = orc_bootstrap(c, t);
-    orc_ct_free(t);
-    if (!b) return NULL;
-    orc_ct *r = orc_mul_int(c, b, S);
-    orc_ct_free(b);
-    return r;
-}
-orc_ct *orc_invsqrt(orc_ctx *c, const orc_ct *x, int d, int iters, double a, double b, int literal) {
-    if (x->level < 2) { set_err("level"); return NULL; }
+orc_ct *orc_invsqrt(orc_ctx *c, const orc_ct *x, int d, int iters, double a, double b, int literal,
+                    int64_t bts_bound) {
     double *cf = malloc(sizeof(double) * (d + 1));
-    if (orc_cheb_coeffs_invsqrt(d, a, b, cf) != 0) { free(cf); set_err("bad interval"); return NULL; }
+    if (d < 1 || iters < 0 || orc_cheb_coeffs_invsqrt(d, a, b, cf) != 0) {
+        free(cf); set_err("bad degree / iterations / interval"); return NULL;
+    }
+    orc_ct *xb = NULL;
+    const int64_t My = bts_bound > 0 ? bts_bound : 16 * (int64_t)ceil(1.0 / sqrt(a));
+    if (x->level < cheb_depth(d) + 1 || x->level < 3) {
+        if (!c->bts) {
+            if (x->level < 2) { free(cf); set_err("level"); return NULL; }
+        } else {
+            xb = orc_bootstrap(c, x, 16 * (int64_t)ceil(b));
+            if (!xb) { free(cf); return NULL; }
+            x = xb;
+        }
+    }
     orc_ct *cx = mul_const_down(c, x, 0.5);
     orc_ct *y = orc_cheb_eval(c, x, cf, d, a, b);
     free(cf);
-    if (!cx || !y) { orc_ct_free(cx); orc_ct_free(y); return NULL; }
+    if (!cx || !y) { orc_ct_free(cx); orc_ct_free(y); orc_ct_free(xb); return NULL; }
     if (literal) {
-        orc_ct *t = orc_bts_scaled(c, y, 64);
+        orc_ct *t = orc_bootstrap(c, y, My);
         orc_ct_free(y);
-        if (!t) { orc_ct_free(cx); return NULL; }
+        if (!t) { orc_ct_free(cx); orc_ct_free(xb); return NULL; }
         y = t;
     }
     for (int i = 0; i < iters; i++) {
         if (y->level < 2) {
-            if (cx->level < 2) { orc_ct_free(y); orc_ct_free(cx); set_err("level"); return NULL; }
-            orc_ct *t = orc_bts_scaled(c, y, 64);
+            if (cx->level < 2) { orc_ct_free(y); orc_ct_free(cx); orc_ct_free(xb); set_err("level"); return NULL; }
+            orc_ct *t = orc_bootstrap(c, y, My);
             orc_ct_free(y);
-            if (!t) { orc_ct_free(cx); return NULL; }
+            if (!t) { orc_ct_free(cx); orc_ct_free(xb); return NULL; }
             y = t;
         }
         orc_ct *yn;
@@ -1600,11 +2107,10 @@ orc_ct *orc_invsqrt(orc_ctx *c, const orc_ct *x, int d, int iters, double a, dou
             yn = orc_newton_step(c, y, cx);
         }
         orc_ct_free(y);
-        if (!yn) { orc_ct_free(cx); return NULL; }
+        if (!yn) { orc_ct_free(cx); orc_ct_free(xb); return NULL; }
         y = yn;
     }
     orc_ct_free(cx);
+    orc_ct_free(xb);
     return y;
 }
-
-/* bootstrapping is defined in ckks_oracle_bts.c */

@@ -87,9 +87,17 @@ def lib():
         "orc_cheb_eval": (vp, [vp, vp, dblp, C.c_int, C.c_double, C.c_double]),
         "orc_newton_step": (vp, [vp, vp, vp]),
         "orc_newton_step_ex": (vp, [vp, vp, vp, C.c_int]),
-        "orc_invsqrt": (vp, [vp, vp, C.c_int, C.c_int, C.c_double, C.c_double, C.c_int]),
-        "orc_bootstrap": (vp, [vp, vp]),
-        "orc_bts_scaled": (vp, [vp, vp, C.c_int]),
+        "orc_invsqrt": (vp, [vp, vp, C.c_int, C.c_int, C.c_double, C.c_double, C.c_int, C.c_int64]),
+        "orc_bootstrap": (vp, [vp, vp, C.c_int64]),
+        "orc_ctx_create_bts": (vp, [C.c_int, C.c_int, C.c_int, C.c_int, C.c_int, C.c_int, C.c_int, C.c_int,
+                                    C.c_int, C.c_double, C.c_int, C.c_int, C.c_int]),
+        "orc_bts_config": (C.c_int, [vp, C.c_double, C.c_int, C.c_int]),
+        "orc_bts_rotations": (C.c_int, [vp, i32p, C.c_int]),
+        "orc_mod_raise": (vp, [vp, vp]),
+        "orc_mul_monomial": (vp, [vp, vp, C.c_int]),
+        "orc_coeff_to_slot": (vp, [vp, vp]),
+        "orc_slot_to_coeff": (vp, [vp, vp]),
+        "orc_eval_mod": (vp, [vp, vp]),
     }
     for name, (res, args) in sig.items():
         f = getattr(L, name, None)
@@ -143,11 +151,22 @@ class Ct:
 class Context:
     """Oracle parameter set + keys.  Arguments mirror the GPU library."""
 
-    def __init__(self, logN, L, K, alpha, h=0, sigma=3.2, log_delta=40, q0_bits=60, p_bits=60):
-        self.logN, self.L, self.K, self.alpha, self.h = logN, L, K, alpha, h
+    def __init__(self, logN, L, K, alpha, h=0, sigma=3.2, log_delta=40, q0_bits=60, p_bits=60, bts=None):
+        """bts = (n_stc, n_evm, n_cts, bts_bits): a bootstrapping chain whose
+        computation levels are 0..L and whose bootstrapping levels sit above."""
         self.N = 1 << logN
         self.n = self.N // 2
-        self.ptr = _chk(lib().orc_ctx_create(logN, L, K, alpha, h, sigma, log_delta, q0_bits, p_bits))
+        if bts:
+            n_stc, n_evm, n_cts, bts_bits = bts
+            self.l_after = L
+            ptr = lib().orc_ctx_create_bts(logN, L, n_stc, n_evm, n_cts, bts_bits, K, alpha, h, sigma,
+                                           log_delta, q0_bits, p_bits)
+            L = L + n_stc + n_evm + n_cts
+        else:
+            self.l_after = L
+            ptr = lib().orc_ctx_create(logN, L, K, alpha, h, sigma, log_delta, q0_bits, p_bits)
+        self.logN, self.L, self.K, self.alpha, self.h = logN, L, K, alpha, h
+        self.ptr = _chk(ptr)
         self.np_ = L + 1 + K
         self.primes = np.zeros(self.np_, dtype=np.uint64)
         self.ladder = np.zeros(L + 1, dtype=np.float64)
@@ -309,14 +328,44 @@ class Context:
     def newton_step(self, y, cx, raw_x=False):
         return Ct(self, lib().orc_newton_step_ex(self.ptr, y.ptr, cx.ptr, int(raw_x)))
 
-    def invsqrt(self, x, degree, iters, a, b, literal=False):
-        return Ct(self, lib().orc_invsqrt(self.ptr, x.ptr, degree, iters, a, b, int(literal)))
+    def invsqrt(self, x, degree, iters, a, b, literal=False, bts_bound=0):
+        return Ct(self, lib().orc_invsqrt(self.ptr, x.ptr, degree, iters, a, b, int(literal), int(bts_bound)))
 
-    def bootstrap(self, a):
-        return Ct(self, lib().orc_bootstrap(self.ptr, a.ptr))
+    # -- bootstrapping -------------------------------------------------------
+    def bts_config(self, K=25.0, r=4, degree=31):
+        if lib().orc_bts_config(self.ptr, K, r, degree) != 0:
+            raise OracleError(lib().orc_last_error().decode())
 
-    def bts_scaled(self, a, S=64):
-        return Ct(self, lib().orc_bts_scaled(self.ptr, a.ptr, S))
+    def bts_rotations(self):
+        k = lib().orc_bts_rotations(self.ptr, None, 0)
+        if k < 0:
+            raise OracleError(lib().orc_last_error().decode())
+        out = np.zeros(k, dtype=np.int32)
+        lib().orc_bts_rotations(self.ptr, _p(out, i32p), k)
+        return [int(v) for v in out]
+
+    def bts_galois(self):
+        """Galois elements of the keys bootstrapping needs (rotations + conjugation)."""
+        return [self.galois_rot(k) for k in self.bts_rotations()] + [2 * self.N - 1]
+
+    def mod_raise(self, a):
+        return Ct(self, lib().orc_mod_raise(self.ptr, a.ptr))
+
+    def mul_monomial(self, a, k):
+        return Ct(self, lib().orc_mul_monomial(self.ptr, a.ptr, k))
+
+    def coeff_to_slot(self, a):
+        return Ct(self, lib().orc_coeff_to_slot(self.ptr, a.ptr))
+
+    def slot_to_coeff(self, a):
+        return Ct(self, lib().orc_slot_to_coeff(self.ptr, a.ptr))
+
+    def eval_mod(self, a):
+        return Ct(self, lib().orc_eval_mod(self.ptr, a.ptr))
+
+    def bootstrap(self, a, bound=1):
+        """Bootstrap a ciphertext whose message is bounded by the integer `bound`."""
+        return Ct(self, lib().orc_bootstrap(self.ptr, a.ptr, int(bound)))
 
 
 def cheb_coeffs_invsqrt(d, a, b):

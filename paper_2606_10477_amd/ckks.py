@@ -26,11 +26,14 @@ STATUS = {0: "OK", -1: "E_PARAM", -2: "E_LEVEL", -3: "E_SCALE", -4: "E_NOKEY", -
 class Params(C.Structure):
     _fields_ = [("log_n", C.c_uint32), ("max_level", C.c_uint32), ("num_special", C.c_uint32),
                 ("digit_size", C.c_uint32), ("hamming_weight", C.c_uint32), ("sigma", C.c_double),
-                ("log_scale", C.c_uint32), ("q0_bits", C.c_uint32), ("p_bits", C.c_uint32)]
+                ("log_scale", C.c_uint32), ("q0_bits", C.c_uint32), ("p_bits", C.c_uint32),
+                ("bts_stc_levels", C.c_uint32), ("bts_evalmod_levels", C.c_uint32),
+                ("bts_cts_levels", C.c_uint32), ("bts_log_scale", C.c_uint32)]
 
 
 class InvsqrtOpts(C.Structure):
-    _fields_ = [("a", C.c_double), ("b", C.c_double), ("literal", C.c_int32), ("bts_scale", C.c_int32)]
+    _fields_ = [("a", C.c_double), ("b", C.c_double), ("literal", C.c_int32), ("reserved", C.c_int32),
+                ("bts_bound", C.c_int64)]
 
 
 # name -> (restype, argtypes): every symbol of include/ckks.h
@@ -68,7 +71,14 @@ SIGNATURES = {
     "ckks_cheb_eval": (C.c_int, [vp, vp, dblp, C.c_uint32, C.c_double, C.c_double, C.POINTER(vp)]),
     "ckks_cheb_coeffs_invsqrt": (C.c_int, [C.c_uint32, C.c_double, C.c_double, dblp]),
     "ckks_newton_step": (C.c_int, [vp, vp, vp, C.c_int, C.POINTER(vp)]),
-    "ckks_bootstrap": (C.c_int, [vp, vp, C.POINTER(vp)]),
+    "ckks_bootstrap": (C.c_int, [vp, vp, C.c_int64, C.POINTER(vp)]),
+    "ckks_bts_setup": (C.c_int, [vp, C.c_double, C.c_uint32, C.c_uint32]),
+    "ckks_bts_rotations": (C.c_int, [vp, i32p, C.c_uint32, u32p]),
+    "ckks_mod_raise": (C.c_int, [vp, vp, C.POINTER(vp)]),
+    "ckks_coeff_to_slot": (C.c_int, [vp, vp, C.POINTER(vp)]),
+    "ckks_eval_mod": (C.c_int, [vp, vp, C.POINTER(vp)]),
+    "ckks_slot_to_coeff": (C.c_int, [vp, vp, C.POINTER(vp)]),
+    "ckks_mul_monomial": (C.c_int, [vp, vp, C.c_int32, C.POINTER(vp)]),
     "ckks_invsqrt": (C.c_int, [vp, vp, C.c_uint32, C.c_uint32, C.POINTER(vp)]),
     "ckks_invsqrt_ex": (C.c_int, [vp, vp, C.c_uint32, C.c_uint32, C.POINTER(InvsqrtOpts), C.POINTER(vp)]),
     "ckks_invsqrt_batch": (C.c_int, [vp, C.POINTER(vp), C.c_uint32, C.c_uint32, C.c_uint32,
@@ -149,14 +159,20 @@ class Context:
     current torch stream orders all work."""
 
     def __init__(self, log_n, max_level, num_special, digit_size, hamming_weight=0, sigma=3.2,
-                 log_scale=40, q0_bits=60, p_bits=60, arena_bytes=0, stream=None):
+                 log_scale=40, q0_bits=60, p_bits=60, arena_bytes=0, stream=None, bts=None):
+        """bts = (stc_levels, evalmod_levels, cts_levels, bts_log_scale): a
+        bootstrapping chain whose computation levels are 0..max_level
+        (l_afterBTS) with the bootstrapping levels above."""
         import torch
         self.N = 1 << log_n
         self.n = self.N // 2
-        self.L = max_level
+        bl = tuple(bts) if bts else (0, 0, 0, 0)
+        self.l_after = max_level
+        self.L = max_level + bl[0] + bl[1] + bl[2]
         self.K = num_special
-        self.np_ = max_level + 1 + num_special
-        p = Params(log_n, max_level, num_special, digit_size, hamming_weight, sigma, log_scale, q0_bits, p_bits)
+        self.np_ = self.L + 1 + num_special
+        p = Params(log_n, max_level, num_special, digit_size, hamming_weight, sigma, log_scale, q0_bits, p_bits,
+                   *bl)
         self._arena = None
         arena_ptr = None
         if arena_bytes:
@@ -172,7 +188,7 @@ class Context:
             raise CkksError(st, "context creation failed")
         self.ptr = out.value
         self.primes = np.zeros(self.np_, dtype=np.uint64)
-        self.ladder = np.zeros(max_level + 1)
+        self.ladder = np.zeros(self.L + 1)
         lib().ckks_ctx_primes(self.ptr, _p(self.primes, u64p), _p(self.ladder, dblp))
 
     def close(self):
@@ -270,15 +286,45 @@ class Context:
     def newton_step(self, y, half_x, raw_x=False):
         return self._ct(lib().ckks_newton_step, y.ptr, half_x.ptr, int(raw_x))
 
-    def bootstrap(self, a):
-        return self._ct(lib().ckks_bootstrap, a.ptr)
+    # -- bootstrapping -------------------------------------------------------
+    def bts_setup(self, K=25.0, r=4, degree=31):
+        self._chk(lib().ckks_bts_setup(self.ptr, K, r, degree))
 
-    def invsqrt(self, x, degree, iters, a=2.0 ** -10, b=1.0, literal=False, bts_scale=64):
-        o = InvsqrtOpts(a, b, int(literal), bts_scale)
+    def bts_rotations(self):
+        cnt = C.c_uint32()
+        self._chk(lib().ckks_bts_rotations(self.ptr, None, 0, C.byref(cnt)))
+        out = np.zeros(cnt.value, dtype=np.int32)
+        self._chk(lib().ckks_bts_rotations(self.ptr, _p(out, i32p), cnt.value, C.byref(cnt)))
+        return [int(v) for v in out]
+
+    def bts_galois(self):
+        """Galois elements of the keys bootstrapping needs (rotations + conjugation)."""
+        return [self.galois_rot(k) for k in self.bts_rotations()] + [2 * self.N - 1]
+
+    def bootstrap(self, a, bound=1):
+        return self._ct(lib().ckks_bootstrap, a.ptr, int(bound))
+
+    def mod_raise(self, a):
+        return self._ct(lib().ckks_mod_raise, a.ptr)
+
+    def coeff_to_slot(self, a):
+        return self._ct(lib().ckks_coeff_to_slot, a.ptr)
+
+    def eval_mod(self, a):
+        return self._ct(lib().ckks_eval_mod, a.ptr)
+
+    def slot_to_coeff(self, a):
+        return self._ct(lib().ckks_slot_to_coeff, a.ptr)
+
+    def mul_monomial(self, a, k):
+        return self._ct(lib().ckks_mul_monomial, a.ptr, int(k))
+
+    def invsqrt(self, x, degree, iters, a=2.0 ** -10, b=1.0, literal=False, bts_bound=0):
+        o = InvsqrtOpts(a, b, int(literal), 0, int(bts_bound))
         return self._ct(lib().ckks_invsqrt_ex, x.ptr, degree, iters, C.byref(o))
 
-    def invsqrt_batch(self, xs, degree, iters, a=2.0 ** -10, b=1.0, literal=False, bts_scale=64):
-        o = InvsqrtOpts(a, b, int(literal), bts_scale)
+    def invsqrt_batch(self, xs, degree, iters, a=2.0 ** -10, b=1.0, literal=False, bts_bound=0):
+        o = InvsqrtOpts(a, b, int(literal), 0, int(bts_bound))
         arr = (vp * len(xs))(*[x.ptr for x in xs])
         outs = (vp * len(xs))()
         self._chk(lib().ckks_invsqrt_batch(self.ptr, arr, len(xs), degree, iters, C.byref(o), outs))

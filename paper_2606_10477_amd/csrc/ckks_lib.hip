@@ -158,9 +158,14 @@ struct ConvTable {
     int din, dout;
 };
 
+struct BtsPlan;
+
 struct ckks_ctx {
     ckks_params prm;
     int logN, N, L, K, alpha, dnum, np;
+    hm::ChainShape shape;         // l_after = L for a plain chain
+    std::unique_ptr<BtsPlan> bts;
+    std::map<int, Buf> mono;      // k -> NTT of X^k over q_0..q_L
     std::vector<u64> q;
     std::vector<double> ladder;
     hipStream_t stream;
@@ -191,12 +196,33 @@ struct ckks_ctx {
     std::map<std::string, ProfFamily> prof;
     std::vector<hipEvent_t> ev_free;
     u64 words(int level) const { return (u64)2 * (level + 1) * N; }
-    ~ckks_ctx() {
+    ~ckks_ctx();
+};
+
+// One slot-transform stage: a group matrix applied by baby-step giant-step.
+struct LtStage {
+    int level = 0;        // input level
+    int stride = 0, g = 0;
+    double sd = 0;        // plaintext scale
+    std::vector<int> giant, baby;   // per term
+    std::vector<Buf> pt;            // per term: [level+1][N] NTT form
+};
+struct BtsPlan {
+    double K = 0;
+    int r = 0, deg = 0;
+    std::vector<double> cf;
+    LtStage cts[3], stc[3];         // application order
+};
+
+ckks_ctx::~ckks_ctx() {
+    {
         for (auto &f : prof)
             for (auto &e : f.second.ev) { (void)hipEventDestroy(e.first); (void)hipEventDestroy(e.second); }
         for (hipEvent_t e : ev_free) (void)hipEventDestroy(e);
     }
-};
+    bts.reset();
+    mono.clear();
+}
 
 namespace {
 
@@ -776,28 +802,281 @@ Ct op_newton(ckks_ctx *c, const ckks_ct *y, const ckks_ct *half_x, bool raw_x) {
     return op_addsub(c, ta.get(), w.get(), true);
 }
 
-Ct op_bootstrap(ckks_ctx *c, const ckks_ct *a);
-
-Ct bts_scaled(ckks_ctx *c, const ckks_ct *y, int S) {
-    Ct t = ct_copy(c, y);
-    t->scale = y->scale * (double)S;
-    Ct b = op_bootstrap(c, t.get());
-    return op_mul_int(c, b.get(), S, b->scale);
+// ---------------------------------------------------------------------------
+// Bootstrapping (ModRaise, CoeffToSlot, EvalMod, SlotToCoeff)
+// ---------------------------------------------------------------------------
+int cheb_depth(int d) {
+    const int m = bit_length(d);
+    return m >= 3 ? m + 1 : m;
 }
 
-Ct op_invsqrt(ckks_ctx *c, const ckks_ct *x, int degree, int iters, const ckks_invsqrt_opts &o) {
-    if (x->level < 2) fail(CKKS_E_LEVEL, "input needs at least 2 levels");
+void upload_signed_ntt(ckks_ctx *c, u64 *dst, const int64_t *src_host, int nlimb, const LimbMap &m);
+
+// NTT of X^k (0 <= k < 2N) over q_0..q_L, cached
+const u64 *mono_table(ckks_ctx *c, int k) {
+    auto it = c->mono.find(k);
+    if (it != c->mono.end()) return it->second.p;
+    const int nq = c->L + 1;
+    std::vector<int64_t> coef(c->N, 0);
+    coef[k % c->N] = k < c->N ? 1 : -1;   // X^N = -1
+    Buf t(c->pool.get(), (size_t)nq * c->N);
+    upload_signed_ntt(c, t.p, coef.data(), nq, map_q(0, nq));
+    const u64 *p = t.p;
+    c->mono.emplace(k, std::move(t));
+    return p;
+}
+
+Ct op_mul_monomial(ckks_ctx *c, const ckks_ct *a, int k) {
+    k %= 2 * c->N;
+    if (k < 0) k += 2 * c->N;
+    const u64 *tab = mono_table(c, k);
+    trace_op(c, "mul_scalar", a->level, a->B);
+    Ct r = ct_new(c, a->level, a->scale, a->B);
+    gpu::MacArgs ma{};
+    ma.nterm = 1;
+    ma.pt[0] = tab;
+    ma.x[0] = a->buf.p;
+    gpu::pt_mac(c->T, r->buf.p, ma, a->level + 1, 2 * a->B, map_q(0, a->level + 1), c->stream);
+    return r;
+}
+
+// residues mod q_0 lifted to the centred range, reduced mod q_0..q_L
+Ct op_mod_raise(ckks_ctx *c, const ckks_ct *a) {
+    if (!c->bts) fail(CKKS_E_NOKEY, "bootstrapping not set up");
+    const int L = c->L, B = a->B, np2 = 2 * B;
+    const size_t N = c->N;
+    trace_op(c, "mod_raise", L, B);
+    Ct r = ct_new(c, L, 2.0 * (double)c->q[0] * c->bts->K, B);
+    Buf t(c->pool.get(), (size_t)np2 * N);
+    ntt_oop_p(c, t.p, a->buf.p, (size_t)(a->level + 1) * N, 1, np2, map_q(0, 1), true);
+    gpu::rescale_lift(c->T, r->buf.p, t.p, 0, L + 1, np2, N, c->stream);
+    ntt_p(c, r->buf.p, L + 1, np2, map_q(0, L + 1), false);
+    return r;
+}
+
+// sum_i rot_{g i s}( sum_b P_{i,b} * rot_{b s}(x) ), then one rescale
+Ct op_lt(ckks_ctx *c, const ckks_ct *x, const LtStage &st) {
+    if (x->level != st.level) fail(CKKS_E_LEVEL, "slot transform at the wrong level");
+    const int n = c->N / 2, nq = x->level + 1, B = x->B;
+    std::map<int, Ct> R;
+    for (size_t t = 0; t < st.baby.size(); ++t) {
+        const int b = st.baby[t];
+        if (b != 0 && !R.count(b)) R[b] = op_rotate(c, x, b * st.stride);
+    }
+    Ct acc;
+    size_t t = 0;
+    while (t < st.giant.size()) {
+        const int gi = st.giant[t];
+        gpu::MacArgs ma{};
+        while (t < st.giant.size() && st.giant[t] == gi) {
+            if (ma.nterm >= gpu::kMaxMac) fail(CKKS_E_PARAM, "too many baby steps");
+            const int b = st.baby[t];
+            ma.pt[ma.nterm] = st.pt[t].p;
+            ma.x[ma.nterm] = b == 0 ? x->buf.p : R[b]->buf.p;
+            ++ma.nterm;
+            ++t;
+        }
+        Ct inner = ct_new(c, x->level, x->scale * st.sd, B);
+        trace_op(c, "mul_plain", x->level, B);
+        gpu::pt_mac(c->T, inner->buf.p, ma, nq, 2 * B, map_q(0, nq), c->stream);
+        if (gi != 0) {
+            const long long k = ((long long)st.g * gi * st.stride) % n;
+            inner = op_rotate(c, inner.get(), (int)k);
+        }
+        acc = acc ? op_addsub(c, acc.get(), inner.get(), false) : std::move(inner);
+    }
+    return op_rescale(c, acc.get());
+}
+
+Ct op_coeff_to_slot(ckks_ctx *c, const ckks_ct *a) {
+    if (!c->bts) fail(CKKS_E_NOKEY, "bootstrapping not set up");
+    if (a->level != c->L) fail(CKKS_E_LEVEL, "CoeffToSlot expects a ModRaised ciphertext");
+    Ct x = op_lt(c, a, c->bts->cts[0]);
+    x = op_lt(c, x.get(), c->bts->cts[1]);
+    return op_lt(c, x.get(), c->bts->cts[2]);
+}
+Ct op_slot_to_coeff(ckks_ctx *c, const ckks_ct *a) {
+    if (!c->bts) fail(CKKS_E_NOKEY, "bootstrapping not set up");
+    if (a->level != c->shape.l_after + 3) fail(CKKS_E_LEVEL, "SlotToCoeff expects the EvalMod output level");
+    Ct x = op_lt(c, a, c->bts->stc[0]);
+    x = op_lt(c, x.get(), c->bts->stc[1]);
+    return op_lt(c, x.get(), c->bts->stc[2]);
+}
+Ct op_eval_mod(ckks_ctx *c, const ckks_ct *u) {
+    if (!c->bts) fail(CKKS_E_NOKEY, "bootstrapping not set up");
+    Ct y = op_cheb(c, u, c->bts->cf, -1.0, 1.0);
+    for (int k = 0; k < c->bts->r; ++k) {
+        Ct sq = mult_rs(c, y.get(), y.get());
+        Ct two = op_mul_int(c, sq.get(), 2, sq->scale);
+        y = op_add_const(c, two.get(), -1.0);
+    }
+    return y;
+}
+
+// two ciphertext objects of equal level, scale and B as one batch of 2B
+Ct concat2(ckks_ctx *c, const ckks_ct *a, const ckks_ct *b) {
+    const size_t w = c->words(a->level) * a->B;
+    Ct r = ct_new(c, a->level, a->scale, 2 * a->B);
+    hipchk(hipMemcpyAsync(r->buf.p, a->buf.p, w * 8, hipMemcpyDeviceToDevice, c->stream), "concat");
+    hipchk(hipMemcpyAsync(r->buf.p + w, b->buf.p, w * 8, hipMemcpyDeviceToDevice, c->stream), "concat");
+    return r;
+}
+Ct half_of(ckks_ctx *c, const ckks_ct *ab, int which) {
+    const int B = ab->B / 2;
+    const size_t w = c->words(ab->level) * B;
+    Ct r = ct_new(c, ab->level, ab->scale, B);
+    hipchk(hipMemcpyAsync(r->buf.p, ab->buf.p + (size_t)which * w, w * 8, hipMemcpyDeviceToDevice, c->stream),
+           "split");
+    return r;
+}
+
+Ct op_bootstrap(ckks_ctx *c, const ckks_ct *a, int64_t bound) {
+    if (!c->bts) fail(CKKS_E_NOKEY, "bootstrapping not set up");
+    if (bound < 1) fail(CKKS_E_PARAM, "message bound must be >= 1");
+    const int N = c->N;
+    const double s0 = std::ldexp((double)c->q[0], -5);
+    const double Fd = std::rint(s0 / (a->scale * (double)bound));
+    if (!(Fd >= 1.0 && Fd < 1099511627776.0)) fail(CKKS_E_RANGE, "input scale out of range for bootstrapping");
+    trace_op(c, "bootstrap", a->level, a->B);
+    Ct a0 = op_drop(c, a, 0);
+    Ct aF = op_mul_int(c, a0.get(), (int64_t)Fd, a0->scale);
+    a0.reset();
+    Ct raised = op_mod_raise(c, aF.get());
+    aF.reset();
+    Ct y = op_coeff_to_slot(c, raised.get());
+    raised.reset();
+    Ct yc = op_automorphism(c, y.get(), 2 * N - 1);
+    Ct sum = op_addsub(c, y.get(), yc.get(), false);
+    Ct dif = op_addsub(c, y.get(), yc.get(), true);
+    y.reset();
+    yc.reset();
+    Ct im = op_mul_monomial(c, dif.get(), 3 * N / 2);
+    dif.reset();
+    Ct both = concat2(c, sum.get(), im.get());
+    sum.reset();
+    im.reset();
+    Ct e = op_eval_mod(c, both.get());
+    both.reset();
+    Ct er = half_of(c, e.get(), 0), ei = half_of(c, e.get(), 1);
+    e.reset();
+    Ct eii = op_mul_monomial(c, ei.get(), N / 2);
+    ei.reset();
+    Ct w = op_addsub(c, er.get(), eii.get(), false);
+    er.reset();
+    eii.reset();
+    Ct z = op_slot_to_coeff(c, w.get());
+    return op_mul_int(c, z.get(), bound, z->scale * (((a->scale * Fd) * (double)bound) / s0));
+}
+
+void bts_setup(ckks_ctx *c, double K, int r, int deg) {
+    const hm::ChainShape &sh = c->shape;
+    if (sh.n_evm <= 0) fail(CKKS_E_PARAM, "chain has no bootstrapping levels");
+    if (sh.n_stc != 3 || sh.n_cts != 3 || deg < 2 || r < 0 || !(K > 1) || sh.n_evm != cheb_depth(deg) + r)
+        fail(CKKS_E_PARAM, "bootstrapping configuration does not match the chain");
+    std::unique_ptr<BtsPlan> b(new BtsPlan);
+    b->K = K;
+    b->r = r;
+    b->deg = deg;
+    b->cf.resize(deg + 1);
+    hm::cheb_cosmod(deg, K, std::ldexp(1.0, r), b->cf.data());
+    const int logn = c->logN - 1, L = c->L, A = sh.l_after;
+    const double s0 = std::ldexp((double)c->q[0], -5);
+    int sizes[3], top = logn;
+    for (int i = 0; i < 3; ++i) sizes[i] = logn / 3 + (i < logn % 3 ? 1 : 0);
+    // Nominal scale chains.  CoeffToSlot: from the ModRaise scale 2 q_0 K to
+    // S_{L-3}; SlotToCoeff: from S_{A+3} (the EvalMod output) to S_A.  With
+    // f = cbrt(end / start) the targets are start f, start f f, end; stage t
+    // at level lv uses s_d = (target q_lv) / s and leaves s <- (s s_d) / q_lv.
+    double sd[2][3];
+    for (int pass = 0; pass < 2; ++pass) {
+        int lv = pass == 0 ? L : A + 3;
+        double s = pass == 0 ? 2.0 * (double)c->q[0] * K : c->ladder[A + 3];
+        const double end = pass == 0 ? c->ladder[L - 3] : c->ladder[A];
+        const double f = std::cbrt(end / s);
+        double tg[3];
+        tg[0] = s * f;
+        tg[1] = tg[0] * f;
+        tg[2] = end;
+        for (int t = 0; t < 3; ++t, --lv) {
+            sd[pass][t] = (tg[t] * (double)c->q[lv]) / s;
+            s = (s * sd[pass][t]) / (double)c->q[lv];
+        }
+    }
+    auto build = [&](LtStage &st, const std::vector<int> &ks, bool inverse, bool carry_const, int level,
+                     double scale) {
+        hm::LtGroupPlan gp;
+        if (!hm::lt_group(c->logN, ks.data(), (int)ks.size(), inverse, c->q[0], carry_const ? s0 : 0.0, scale, gp))
+            fail(CKKS_E_RANGE, "diagonal plaintext out of range");
+        st.level = level;
+        st.stride = gp.stride;
+        st.g = gp.g;
+        st.sd = scale;
+        const int nq = level + 1;
+        for (auto &t : gp.terms) {
+            st.giant.push_back(t.giant);
+            st.baby.push_back(t.baby);
+            Buf pt(c->pool.get(), (size_t)nq * c->N);
+            upload_signed_ntt(c, pt.p, t.coef.data(), nq, map_q(0, nq));
+            st.pt.push_back(std::move(pt));
+        }
+    };
+    for (int i = 0; i < 3; ++i) {
+        std::vector<int> ks, kr;
+        for (int t = 0; t < sizes[i]; ++t) ks.push_back(top - t);
+        for (int t = 0; t < sizes[i]; ++t) kr.push_back(top - sizes[i] + 1 + t);
+        build(b->cts[i], ks, true, false, L - i, sd[0][i]);
+        build(b->stc[2 - i], kr, false, i == 2, A + 3 - (2 - i), sd[1][2 - i]);
+        top -= sizes[i];
+    }
+    c->bts = std::move(b);
+}
+
+std::vector<int> bts_rotations(const ckks_ctx *c) {
+    if (!c->bts) fail(CKKS_E_NOKEY, "bootstrapping not set up");
+    const int n = c->N / 2;
+    std::vector<char> seen(n, 0);
+    const LtStage *all[6] = {&c->bts->cts[0], &c->bts->cts[1], &c->bts->cts[2],
+                             &c->bts->stc[0], &c->bts->stc[1], &c->bts->stc[2]};
+    for (const LtStage *st : all)
+        for (size_t t = 0; t < st->giant.size(); ++t) {
+            const long long kb = ((long long)st->baby[t] * st->stride) % n;
+            const long long kg = (((long long)st->g * st->giant[t] * st->stride) % n + n) % n;
+            if (kb) seen[kb] = 1;
+            if (kg) seen[kg] = 1;
+        }
+    std::vector<int> out;
+    for (int k = 1; k < n; ++k)
+        if (seen[k]) out.push_back(k);
+    return out;
+}
+
+// CryptoInvSqrt with the bootstrapping policy: Pre-BTS of x (paper's c = 1)
+// when it cannot carry the Chebyshev step or ct_x; otherwise x is never
+// bootstrapped.  Lazy bootstrapping of y before a Newton step that lacks 2
+// levels (or right after the Chebyshev step with `literal`).
+Ct op_invsqrt(ckks_ctx *c, const ckks_ct *x0, int degree, int iters, const ckks_invsqrt_opts &o) {
     if (degree < 1 || iters < 0) fail(CKKS_E_PARAM, "bad degree / iterations");
     if (!(o.a > 0) || !(o.b > o.a)) fail(CKKS_E_PARAM, "bad interval");
+    const int64_t My = o.bts_bound > 0 ? o.bts_bound : 16 * (int64_t)std::ceil(1.0 / std::sqrt(o.a));
+    const ckks_ct *x = x0;
+    Ct xb;
+    if (x->level < cheb_depth(degree) + 1 || x->level < 3) {
+        if (!c->bts) {
+            if (x->level < 2) fail(CKKS_E_LEVEL, "input needs at least 2 levels");
+        } else {
+            xb = op_bootstrap(c, x, 16 * (int64_t)std::ceil(o.b));
+            x = xb.get();
+        }
+    }
     std::vector<double> cf(degree + 1);
     hm::cheb_invsqrt(degree, o.a, o.b, cf.data());
     Ct cx = op_mul_const_down(c, x, 0.5);
     Ct y = op_cheb(c, x, cf, o.a, o.b);
-    if (o.literal) y = bts_scaled(c, y.get(), o.bts_scale);
+    if (o.literal) y = op_bootstrap(c, y.get(), My);
     for (int i = 0; i < iters; ++i) {
         if (y->level < 2) {
             if (cx->level < 2) fail(CKKS_E_LEVEL, "x has too few levels for Newton");
-            y = bts_scaled(c, y.get(), o.bts_scale);
+            y = op_bootstrap(c, y.get(), My);
         }
         if (i == iters - 1) {
             // last step: x/2 straight from the input (exact halving of the scale)
@@ -809,12 +1088,6 @@ Ct op_invsqrt(ckks_ctx *c, const ckks_ct *x, int degree, int iters, const ckks_i
         }
     }
     return y;
-}
-
-Ct op_bootstrap(ckks_ctx *c, const ckks_ct *a) {
-    (void)c;
-    (void)a;
-    fail(CKKS_E_NOKEY, "bootstrapping keys not set up");
 }
 
 // ---------------------------------------------------------------------------
@@ -1000,17 +1273,28 @@ extern "C" {
 ckks_status ckks_ctx_create(const ckks_params *p, void *arena, size_t arena_bytes, void *hip_stream, ckks_ctx **out) {
     if (!p || !out) return CKKS_E_PARAM;
     *out = nullptr;
+    const bool bts = p->bts_evalmod_levels > 0;
+    const uint32_t Ltot = p->max_level + p->bts_stc_levels + p->bts_evalmod_levels + p->bts_cts_levels;
     if (p->log_n < 4 || p->log_n > 16 || p->max_level < 1 || p->num_special < 1 || p->digit_size < 1 ||
-        p->max_level + 1 + p->num_special > (uint32_t)gpu::kMaxLimbs || p->q0_bits > 61 || p->p_bits > 61 ||
+        Ltot + 1 + p->num_special > (uint32_t)gpu::kMaxLimbs || p->q0_bits > 61 || p->p_bits > 61 ||
         p->q0_bits < 30 || p->p_bits < 30 || p->log_scale < 20 || p->log_scale > 58 ||
-        p->hamming_weight > (1u << p->log_n) || !(p->sigma > 0))
+        p->hamming_weight > (1u << p->log_n) || !(p->sigma > 0) ||
+        (bts && (p->bts_stc_levels < 1 || p->bts_cts_levels < 1 || p->bts_log_scale < 20 || p->bts_log_scale > 60)) ||
+        (!bts && (p->bts_stc_levels || p->bts_cts_levels)))
         return CKKS_E_PARAM;
     ckks_ctx *c = new ckks_ctx();
     ckks_status st = guard(c, [&] {
         c->prm = *p;
         c->logN = (int)p->log_n;
         c->N = 1 << c->logN;
-        c->L = (int)p->max_level;
+        c->L = (int)Ltot;
+        c->shape.l_after = (int)p->max_level;
+        if (bts) {
+            c->shape.n_stc = (int)p->bts_stc_levels;
+            c->shape.n_evm = (int)p->bts_evalmod_levels;
+            c->shape.n_cts = (int)p->bts_cts_levels;
+            c->shape.bts_bits = (int)p->bts_log_scale;
+        }
         c->K = (int)p->num_special;
         c->alpha = (int)p->digit_size;
         c->dnum = (c->L + 1 + c->alpha - 1) / c->alpha;
@@ -1018,7 +1302,8 @@ ckks_status ckks_ctx_create(const ckks_params *p, void *arena, size_t arena_byte
         c->np = c->L + 1 + c->K;
         c->stream = (hipStream_t)hip_stream;
         c->pool.reset(new Pool(arena, arena_bytes));
-        hm::prime_chain(c->logN, c->L, c->K, (int)p->log_scale, (int)p->q0_bits, (int)p->p_bits, c->q, c->ladder);
+        hm::prime_chain(c->logN, c->L, c->K, (int)p->log_scale, (int)p->q0_bits, (int)p->p_bits, c->shape, c->q,
+                        c->ladder);
         c->cdt = hm::gaussian_table(p->sigma);
         build_tables(c);
     });
@@ -1201,16 +1486,49 @@ ckks_status ckks_newton_step(ckks_ctx *c, const ckks_ct *y, const ckks_ct *h, in
     if (!c || !y || !h) return CKKS_E_PARAM;
     return guard_out(c, out, [&] { return op_newton(c, y, h, raw_x != 0); });
 }
-ckks_status ckks_bootstrap(ckks_ctx *c, const ckks_ct *a, ckks_ct **out) {
+ckks_status ckks_bts_setup(ckks_ctx *c, double K, uint32_t r, uint32_t degree) {
+    if (!c) return CKKS_E_PARAM;
+    return guard(c, [&] { bts_setup(c, K, (int)r, (int)degree); });
+}
+ckks_status ckks_bts_rotations(const ckks_ctx *c, int32_t *steps, uint32_t cap, uint32_t *count) {
+    if (!c || !count) return CKKS_E_PARAM;
+    return guard(const_cast<ckks_ctx *>(c), [&] {
+        std::vector<int> v = bts_rotations(c);
+        *count = (uint32_t)v.size();
+        for (uint32_t i = 0; i < cap && i < v.size(); ++i) steps[i] = v[i];
+    });
+}
+ckks_status ckks_bootstrap(ckks_ctx *c, const ckks_ct *a, int64_t bound, ckks_ct **out) {
     CT_ARGS_CHECK();
-    return guard_out(c, out, [&] { return op_bootstrap(c, a); });
+    return guard_out(c, out, [&] { return op_bootstrap(c, a, bound); });
+}
+ckks_status ckks_mod_raise(ckks_ctx *c, const ckks_ct *a, ckks_ct **out) {
+    CT_ARGS_CHECK();
+    return guard_out(c, out, [&] { return op_mod_raise(c, a); });
+}
+ckks_status ckks_coeff_to_slot(ckks_ctx *c, const ckks_ct *a, ckks_ct **out) {
+    CT_ARGS_CHECK();
+    return guard_out(c, out, [&] { return op_coeff_to_slot(c, a); });
+}
+ckks_status ckks_eval_mod(ckks_ctx *c, const ckks_ct *a, ckks_ct **out) {
+    CT_ARGS_CHECK();
+    return guard_out(c, out, [&] { return op_eval_mod(c, a); });
+}
+ckks_status ckks_slot_to_coeff(ckks_ctx *c, const ckks_ct *a, ckks_ct **out) {
+    CT_ARGS_CHECK();
+    return guard_out(c, out, [&] { return op_slot_to_coeff(c, a); });
+}
+ckks_status ckks_mul_monomial(ckks_ctx *c, const ckks_ct *a, int32_t k, ckks_ct **out) {
+    CT_ARGS_CHECK();
+    return guard_out(c, out, [&] { return op_mul_monomial(c, a, k); });
 }
 static ckks_invsqrt_opts default_opts() {
     ckks_invsqrt_opts o;
     o.a = 0.0009765625;   // 2^-10
     o.b = 1.0;
     o.literal = 0;
-    o.bts_scale = 64;
+    o.reserved = 0;
+    o.bts_bound = 0;
     return o;
 }
 ckks_status ckks_invsqrt(ckks_ctx *c, const ckks_ct *x, uint32_t degree, uint32_t iters, ckks_ct **out) {

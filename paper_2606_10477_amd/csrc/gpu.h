@@ -124,6 +124,20 @@ void moddown_finish(const Tables &T, uint64_t *out, const uint64_t *acc, size_t 
                     const uint64_t *z, const uint64_t *add, int add_mask, const LimbConsts &pinv, int nlimb, int nct,
                     const LimbMap &m, hipStream_t s);
 
+// Plaintext-ciphertext multiply-accumulate: out[p][l] = sum_t pt_t[l] * x_t[p][l]
+// over npoly polys of nlimb limbs (x_t poly stride nlimb N, same layout as
+// out); each plaintext pt_t ([nlimb][N]) is shared by all polys.  The
+// products are summed in 128 bits and reduced once (primes < 2^61, nterm
+// <= kMaxMac).
+constexpr int kMaxMac = 16;
+struct MacArgs {
+    int nterm;
+    const uint64_t *pt[kMaxMac];
+    const uint64_t *x[kMaxMac];
+};
+void pt_mac(const Tables &T, uint64_t *out, const MacArgs &a, int nlimb, int npoly, const LimbMap &m,
+            hipStream_t s);
+
 // decryption: m = c0 + c1 * s
 void decrypt_combine(const Tables &T, uint64_t *m, const uint64_t *c0, const uint64_t *c1, const uint64_t *sk,
                      int nlimb, const LimbMap &m_, hipStream_t s);

@@ -20,6 +20,8 @@
 #include <cstring>
 #include <quadmath.h>
 #include <algorithm>
+#include <map>
+#include <thread>
 
 namespace hm {
 
@@ -62,39 +64,75 @@ bool is_prime(uint64_t n) {
     return true;
 }
 
-void prime_chain(int logN, int L, int K, int log_scale, int q0_bits, int p_bits,
+// unused prime = 1 (mod step) nearest to T (first below vs first above; ties
+// to the lower)
+static uint64_t nearest_prime(double T, uint64_t step, const std::vector<uint64_t> &taken_list) {
+    auto taken = [&](uint64_t c) { return std::find(taken_list.begin(), taken_list.end(), c) != taken_list.end(); };
+    uint64_t t = (uint64_t)std::floor(T);
+    uint64_t below = ((t - 1) / step) * step + 1;     // <= t, = 1 mod step
+    uint64_t above = below + step;
+    while (!is_prime(below) || taken(below)) below -= step;
+    while (!is_prime(above) || taken(above)) above += step;
+    return ((double)above - T < T - (double)below) ? above : below;
+}
+
+// Computation levels A..1 (A = l_after) top-down from S_A = 2^log_scale with
+// q_l nearest to S_l^2 / 2^log_scale.  A bootstrapping chain then adds the
+// EvalMod levels (same rule from S_E = 2^bts_bits at E = A + n_stc + n_evm,
+// down to level A + n_stc), the SlotToCoeff primes (levels A+1..A+n_stc,
+// nearest to 2^log_scale, S = 2^log_scale below the EvalMod output) and the
+// CoeffToSlot primes (levels E+1..L, nearest to 2^bts_bits, S = 2^bts_bits),
+// in that order, then the special primes below 2^p_bits.
+void prime_chain(int logN, int L, int K, int log_scale, int q0_bits, int p_bits, const ChainShape &shape,
                  std::vector<uint64_t> &primes, std::vector<double> &ladder) {
     const uint64_t step = (uint64_t)2 << logN;   // 2N
     primes.assign(L + 1 + K, 0);
     ladder.assign(L + 1, 0.0);
-    auto taken = [&](uint64_t c) { return std::find(primes.begin(), primes.end(), c) != primes.end(); };
+    std::vector<uint64_t> taken;
     // q_0: walk down from the largest 1 (mod 2N) number below 2^q0_bits
     uint64_t lim = (uint64_t)1 << q0_bits;
     uint64_t c = ((lim - 1) / step) * step + 1;
     if (c >= lim) c -= step;
     while (!is_prime(c)) c -= step;
     primes[0] = c;
-    double S = std::ldexp(1.0, log_scale);
+    taken.push_back(c);
+    auto adaptive = [&](int top, int bot, double D) {
+        double S = D;
+        ladder[top] = S;
+        for (int l = top; l > bot; --l) {
+            double T = (S * S) / D;
+            uint64_t pick = nearest_prime(T, step, taken);
+            primes[l] = pick;
+            taken.push_back(pick);
+            S = (S * S) / (double)pick;
+            ladder[l - 1] = S;
+        }
+    };
     const double D = std::ldexp(1.0, log_scale);
-    ladder[L] = S;
-    for (int l = L; l >= 1; --l) {
-        double T = (S * S) / D;
-        uint64_t t = (uint64_t)std::floor(T);
-        uint64_t below = ((t - 1) / step) * step + 1;     // <= t, = 1 mod 2N
-        uint64_t above = below + step;
-        while (!is_prime(below) || taken(below)) below -= step;
-        while (!is_prime(above) || taken(above)) above += step;
-        uint64_t pick = ((double)above - T < T - (double)below) ? above : below;
-        primes[l] = pick;
-        S = (S * S) / (double)pick;
-        ladder[l - 1] = S;
+    const int A = shape.n_evm > 0 ? shape.l_after : L;
+    adaptive(A, 0, D);
+    if (shape.n_evm > 0) {
+        const double Db = std::ldexp(1.0, shape.bts_bits);
+        const int E = A + shape.n_stc + shape.n_evm;
+        adaptive(E, A + shape.n_stc, Db);
+        for (int l = A + 1; l <= A + shape.n_stc; ++l) {
+            primes[l] = nearest_prime(D, step, taken);
+            taken.push_back(primes[l]);
+            if (l < A + shape.n_stc) ladder[l] = D;
+        }
+        for (int l = E + 1; l <= L; ++l) {
+            primes[l] = nearest_prime(Db, step, taken);
+            taken.push_back(primes[l]);
+            ladder[l] = Db;
+        }
     }
     uint64_t plim = (uint64_t)1 << p_bits;
     uint64_t pc = ((plim - 1) / step) * step + 1;
     if (pc >= plim) pc -= step;
     for (int k = 0; k < K; ++k) {
-        while (!is_prime(pc) || taken(pc)) pc -= step;
+        while (!is_prime(pc) || std::find(taken.begin(), taken.end(), pc) != taken.end()) pc -= step;
         primes[L + 1 + k] = pc;
+        taken.push_back(pc);
         pc -= step;
     }
 }
@@ -321,6 +359,117 @@ bool encode(int logN, const double *re, const double *im, size_t nslots, double 
     std::vector<cplx> z(n, cplx{0, 0});
     for (size_t j = 0; j < nslots && j < n; ++j) z[j] = {(quad)re[j], im ? (quad)im[j] : (quad)0};
     return encode_slots(logN, z, scale, out);
+}
+
+// ---------------------------------------------------------------------------
+// Bootstrapping slot transforms (quad precision)
+// ---------------------------------------------------------------------------
+// Butterfly stage k (length len = 2^k, half h) on n slots, as three
+// diagonals at offsets 0, +h, -h.  Forward: y_j = x_j + t_j x_{j+h},
+// y_{j+h} = x_j - t_j x_{j+h}; inverse: x_j = (y_j + y_{j+h}) / 2,
+// x_{j+h} = (y_j - y_{j+h}) / (2 t_j); t_j = exp(2 pi i (5^j mod 4 len) / (4 len)).
+static void butterfly_diagonals(size_t n, int k, bool inverse, std::vector<cplx> d[3]) {
+    const size_t len = (size_t)1 << k, h = len / 2;
+    for (int e = 0; e < 3; ++e) d[e].assign(n, cplx{0, 0});
+    std::vector<cplx> tw(h);
+    uint64_t p5 = 1;
+    for (size_t j = 0; j < h; ++j) {
+        tw[j] = unit_root((long long)p5, 4 * (long long)len);
+        p5 = (p5 * 5) % (4 * len);
+    }
+    for (size_t j = 0; j < n; ++j) {
+        const size_t jj = j % len;
+        if (jj < h) {
+            if (!inverse) { d[0][j] = {1, 0}; d[1][j] = tw[jj]; }
+            else { d[0][j] = {0.5Q, 0}; d[1][j] = {0.5Q, 0}; }
+        } else {
+            const cplx t = tw[jj - h];
+            if (!inverse) { d[0][j] = {-t.r, -t.i}; d[2][j] = {1, 0}; }
+            else { d[2][j] = {t.r / 2, -t.i / 2}; d[0][j] = {-t.r / 2, t.i / 2}; }   // 1/(2t) = conj(t)/2
+        }
+    }
+}
+
+bool lt_group(int logN, const int *ks, int cnt, bool inverse, uint64_t q0, double s0, double sd,
+              LtGroupPlan &out) {
+    const size_t n = (size_t)1 << (logN - 1);
+    // diagonal form of the product, offset (mod n) -> values
+    std::map<size_t, std::vector<cplx>> cur;
+    cur[0].assign(n, cplx{1, 0});
+    int kmin = ks[0], kmax = ks[0];
+    std::vector<cplx> d[3];
+    for (int t = 0; t < cnt; ++t) {
+        const int k = ks[t];
+        kmin = std::min(kmin, k);
+        kmax = std::max(kmax, k);
+        butterfly_diagonals(n, k, inverse, d);
+        const size_t h = (size_t)1 << (k - 1);
+        const size_t off[3] = {0, h % n, (n - h) % n};
+        std::map<size_t, std::vector<cplx>> nxt;
+        for (auto &kv : cur)
+            for (int e = 0; e < 3; ++e) {
+                auto &dst = nxt[(off[e] + kv.first) % n];
+                if (dst.empty()) dst.assign(n, cplx{0, 0});
+                for (size_t j = 0; j < n; ++j) {
+                    cplx v = cmul(d[e][j], kv.second[(j + off[e]) % n]);
+                    dst[j].r += v.r;
+                    dst[j].i += v.i;
+                }
+            }
+        cur.swap(nxt);
+    }
+    const quad cm = s0 > 0 ? (quad)q0 / (2 * M_PIq * (quad)s0) : (quad)1;
+    const size_t stride = (size_t)1 << (kmin - 1);
+    const long long ns = (long long)(n / stride);
+    const bool wrap = ns <= (1LL << (kmax - kmin + 1));
+    std::vector<std::pair<long long, const std::vector<cplx> *>> diag;
+    for (auto &kv : cur) {
+        bool nz = false;
+        for (const cplx &v : kv.second)
+            if (v.r != 0 || v.i != 0) { nz = true; break; }
+        if (!nz) continue;
+        long long m = (long long)(kv.first / stride);
+        if (!wrap && m > ns / 2) m -= ns;
+        diag.emplace_back(m, &kv.second);
+    }
+    std::sort(diag.begin(), diag.end(), [](const auto &x, const auto &y) { return x.first < y.first; });
+    const long long span = diag.back().first - diag.front().first + 1;
+    int e = 0;
+    while ((1LL << e) < span) ++e;
+    const int g = 1 << ((e + 1) / 2);
+    out.stride = (int)stride;
+    out.g = g;
+    out.terms.assign(diag.size(), LtTerm{});
+    std::vector<char> ok(diag.size(), 1);
+    auto work = [&](size_t lo, size_t hi) {
+        std::vector<cplx> z(n);
+        for (size_t t = lo; t < hi; ++t) {
+            const long long m = diag[t].first;
+            long long gi = m / g;
+            if (m % g != 0 && m < 0) --gi;        // floor division
+            const long long b = m - gi * g;
+            const long long sh = gi * g * (long long)stride;
+            const std::vector<cplx> &v = *diag[t].second;
+            for (size_t j = 0; j < n; ++j) {
+                long long src = (((long long)j - sh) % (long long)n + (long long)n) % (long long)n;
+                z[j] = {v[src].r * cm, v[src].i * cm};
+            }
+            LtTerm &T = out.terms[t];
+            T.giant = (int)gi;
+            T.baby = (int)b;
+            T.coef.resize(2 * n);
+            ok[t] = encode_slots(logN, z, sd, T.coef.data());
+        }
+    };
+    const size_t nt = diag.size();
+    const unsigned hw = std::max(1u, std::min(16u, std::thread::hardware_concurrency()));
+    std::vector<std::thread> th;
+    const size_t chunk = (nt + hw - 1) / hw;
+    for (size_t lo = 0; lo < nt; lo += chunk) th.emplace_back(work, lo, std::min(nt, lo + chunk));
+    for (auto &t : th) t.join();
+    for (char o : ok)
+        if (!o) return false;
+    return true;
 }
 
 // ---------------------------------------------------------------------------

@@ -15,8 +15,14 @@ uint64_t mulmod(uint64_t a, uint64_t b, uint64_t q);
 uint64_t powmod(uint64_t a, uint64_t e, uint64_t q);
 uint64_t invmod(uint64_t a, uint64_t q);
 
+// Shape of a bootstrapping chain: levels l_after+1..L are consumed by
+// bootstrapping (SlotToCoeff n_stc, EvalMod n_evm, CoeffToSlot n_cts, from
+// the bottom up).  n_evm = 0: a plain chain with l_after = L.
+struct ChainShape {
+    int l_after = 0, n_stc = 0, n_evm = 0, n_cts = 0, bts_bits = 0;
+};
 // Prime chain q_0..q_L, p_0..p_{K-1} and the canonical scale ladder S_0..S_L.
-void prime_chain(int logN, int L, int K, int log_scale, int q0_bits, int p_bits,
+void prime_chain(int logN, int L, int K, int log_scale, int q0_bits, int p_bits, const ChainShape &shape,
                  std::vector<uint64_t> &primes, std::vector<double> &ladder);
 // 2N-th root of unity of q: g^((q-1)/2N) for the least g >= 2 of order 2N.
 uint64_t root_2n(uint64_t q, int N);
@@ -57,6 +63,24 @@ bool encode(int logN, const double *re, const double *im, size_t nslots, double 
 // -> N/2 slots divided by `scale`.
 void decode_residues(int logN, const uint64_t *res, int nlimbs, const uint64_t *primes,
                      double scale, double *re, double *im);
+
+// Bootstrapping slot transforms.  One group of butterfly stages (stage k:
+// butterflies of length 2^k; ks[] in the order they are applied; inverse
+// stages for CoeffToSlot, forward for SlotToCoeff), as a matrix on the N/2
+// slots, optionally multiplied by q0 / (2 pi s0) (s0 > 0).  Its nonzero
+// diagonals m (offset m * stride slots) are split m = g i + b (0 <= b < g);
+// each term's plaintext is diagonal m rotated right by g i stride slots,
+// encoded at scale sd.  Returns false if a coefficient does not fit int64.
+struct LtTerm {
+    int giant, baby;
+    std::vector<int64_t> coef;   // N encoded coefficients
+};
+struct LtGroupPlan {
+    int stride = 0, g = 0;
+    std::vector<LtTerm> terms;   // ascending m
+};
+bool lt_group(int logN, const int *ks, int cnt, bool inverse, uint64_t q0, double s0, double sd,
+              LtGroupPlan &out);
 
 // Chebyshev interpolant of 1/sqrt on [a, b] (degree d, first-kind nodes).
 void cheb_invsqrt(int d, double a, double b, double *coeffs);

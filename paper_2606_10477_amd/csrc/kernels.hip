@@ -720,6 +720,25 @@ void moddown_finish(const Tables &T, uint64_t *out, const uint64_t *acc, size_t 
                        pinv, T.logN, nlimb, total, m, T);
 }
 
+__global__ void k_pt_mac(u64 *out, MacArgs a, int logN, int nlimb, size_t total, LimbMap m, Tables T) {
+    const size_t N = (size_t)1 << logN;
+    GRID_LOOP(i, total) {
+        ROW_SPLIT(i, logN, nlimb, poly, limb)
+        (void)poly;
+        const size_t rem = ((size_t)limb << logN) | (i & (N - 1));
+        const DevPrime P = T.primes[m.p[limb]];
+        u64 h = 0, l = 0;
+        for (int t = 0; t < a.nterm; ++t) mac128(h, l, a.pt[t][rem], a.x[t][i]);
+        out[i] = reduce128(h, l, P);
+    }
+}
+void pt_mac(const Tables &T, uint64_t *out, const MacArgs &a, int nlimb, int npoly, const LimbMap &m,
+            hipStream_t s) {
+    size_t total = ((size_t)nlimb * npoly) << T.logN;
+    if (!total) return;
+    hipLaunchKernelGGL(k_pt_mac, grid_for(total), dim3(256), 0, s, out, a, T.logN, nlimb, total, m, T);
+}
+
 __global__ void k_decrypt(u64 *mo, const u64 *c0, const u64 *c1, const u64 *sk, int logN, size_t total, LimbMap m,
                           Tables T) {
     GRID_LOOP(i, total) {
