@@ -1,0 +1,167 @@
+"""Pins of the oracle's bootstrapping (paper §2.1 BTS) against facts that do
+not come from the oracle itself:
+
+* ModRaise: the raised ciphertext decrypts, exactly (big-integer CRT of the
+  residues, secret key from the oracle), to m + q_0 I with I an integer
+  polynomial of small norm, and to m again modulo q_0;
+* CoeffToSlot: slots of the output hold (p_k + i p_{k+n}) / (2 q_0 K) in
+  bit-reversed order, p the exact raised plaintext (numpy, from the
+  definition of the canonical embedding's coefficient packing);
+* EvalMod: the output equals sin(2 pi K u) for the decrypted input u
+  (closed form of cos(2^r theta) composed with the shift by a quarter turn);
+* monomials: X^(N/2) multiplies every slot by i, X^N is negation (compared
+  with the integer multiply by -1), X^(2N) is the identity;
+* bootstrap and CryptoInvSqrt with bootstrapping: decrypted values against
+  FP64 (values / 1/sqrt(x)).
+"""
+import numpy as np
+import pytest
+
+from paper_2606_10477_amd import inputs
+
+BTS = (3, 10, 3, 52)
+
+
+@pytest.fixture(scope="module")
+def o8(oracle_mod):
+    o = oracle_mod.Context(8, 3, 2, 2, h=16, bts=BTS)
+    o.bts_config(25.0, 4, 31)
+    o.keygen(3, o.bts_galois())
+    return o
+
+
+@pytest.fixture(scope="module")
+def o10(oracle_mod):
+    o = oracle_mod.Context(10, 7, 2, 2, h=192, bts=BTS)
+    o.bts_config(25.0, 4, 31)
+    o.keygen(4, o.bts_galois())
+    return o
+
+
+def test_bootstrapping_chain_shape(o10):
+    o = o10
+    bits = [int(p).bit_length() for p in o.primes]
+    N = o.N
+    assert o.L == 7 + 16
+    assert bits[0] == 60
+    assert all(40 <= b <= 41 for b in bits[1:11])          # computation + SlotToCoeff
+    assert all(52 <= b <= 53 for b in bits[11:24])         # EvalMod + CoeffToSlot
+    assert len(set(int(p) for p in o.primes)) == len(o.primes)
+    assert all(int(p) % (2 * N) == 1 for p in o.primes)
+    # canonical scales: ~2^40 on the computation levels, ~2^52 on EvalMod
+    assert np.all(np.abs(np.log2(o.ladder[:8]) - 40) < 1e-3)
+    assert np.all(np.abs(np.log2(o.ladder[10:21]) - 52) < 1e-3)
+    with pytest.raises(Exception):
+        o.bts_config(25.0, 3, 31)                           # depth 6 + 3 != 10 EvalMod levels
+
+
+def _exact_plain(o, ct):
+    """Exact centred plaintext c0 + c1 s of a ciphertext (Python big ints)."""
+    w = ct.words()
+    s = o.secret().astype(int)
+    nz = np.nonzero(s)[0]
+    L = ct.level
+    N = o.N
+    qs = [int(q) for q in o.primes[:L + 1]]
+    res = []
+    for i, q in enumerate(qs):
+        c0 = [int(v) for v in o.intt(i, w[0, i])]
+        c1 = [int(v) for v in o.intt(i, w[1, i])]
+        m = list(c0)
+        for j in nz:
+            sj = int(s[j])
+            for k in range(N):
+                t = k + j
+                if t < N:
+                    m[t] = (m[t] + sj * c1[k]) % q
+                else:
+                    m[t - N] = (m[t - N] - sj * c1[k]) % q
+        res.append(m)
+    Q = 1
+    for q in qs:
+        Q *= q
+    out = []
+    for k in range(N):
+        x = 0
+        for i, q in enumerate(qs):
+            Qi = Q // q
+            x += res[i][k] * Qi * pow(Qi, -1, q)
+        x %= Q
+        out.append(x - Q if x > Q // 2 else x)
+    return out
+
+
+def _bitrev(n):
+    b = n.bit_length() - 1
+    return np.array([int(format(i, '0%db' % b)[::-1], 2) for i in range(n)])
+
+
+def test_mod_raise_invariant_and_coeff_to_slot(o8):
+    o = o8
+    q0 = int(o.primes[0])
+    x = inputs.log_uniform(o.n, 1.0, 32.0, 1)
+    ct = o.encrypt(x, 0, o.ladder[0], 5)
+    m0 = _exact_plain(o, ct)                     # centred mod q_0
+    raised = o.mod_raise(ct)
+    assert raised.level == o.L
+    p = _exact_plain(o, raised)
+    I = [(pk - mk) // q0 for pk, mk in zip(p, m0)]
+    assert all((pk - mk) % q0 == 0 for pk, mk in zip(p, m0))
+    assert max(abs(i) for i in I) <= 12            # h = 16: |I| well below K = 25
+    assert max(abs(i) for i in I) >= 1
+    # CoeffToSlot: slot k holds (p_br(k) + i p_{br(k)+n}) / (2 q_0 K)
+    y = o.coeff_to_slot(raised)
+    assert y.level == o.L - 3
+    z = o.decrypt(y)
+    n = o.n
+    br = _bitrev(n)
+    K = 25.0
+    want = (np.array([p[k] for k in br], dtype=float) + 1j * np.array([p[k + n] for k in br], dtype=float)) / (2 * q0 * K)
+    assert np.max(np.abs(z - want)) < 1e-9
+
+
+def test_eval_mod_is_the_shifted_cosine_composition(o8):
+    o = o8
+    K = 25.0
+    rng = np.random.default_rng(3)
+    t = rng.integers(-10, 11, o.n) + rng.uniform(-0.01, 0.01, o.n)
+    u = t / K
+    ct = o.encrypt(u, o.L - 3, o.ladder[o.L - 3], 6)
+    e = o.eval_mod(ct)
+    assert e.level == o.l_after + 3
+    got = o.decrypt(e).real
+    assert np.max(np.abs(got - np.sin(2 * np.pi * K * u))) < 1e-7
+
+
+def test_monomials(o8):
+    o = o8
+    x = inputs.log_uniform(o.n, 1.0, 2.0, 2)
+    ct = o.encrypt(x, 2, o.ladder[2], 7)
+    N = o.N
+    z = o.decrypt(ct)
+    zi = o.decrypt(o.mul_monomial(ct, N // 2))
+    assert np.max(np.abs(zi - 1j * z)) < 1e-9
+    assert np.array_equal(o.mul_monomial(ct, N).words(), o.mul_int(ct, -1).words())
+    assert np.array_equal(o.mul_monomial(o.mul_monomial(ct, N // 2), 3 * N // 2).words(), ct.words())
+
+
+def test_bootstrap_accuracy(o10):
+    o = o10
+    x = inputs.log_uniform(o.n, 1.0, 32.0, 3)
+    ct = o.encrypt(x, 1, o.ladder[1], 8)
+    b = o.bootstrap(ct, 512)
+    assert b.level == o.l_after
+    assert abs(np.log2(b.scale) - 40) < 1e-3
+    rel = np.abs(o.decrypt(b).real - x) / x
+    assert np.mean(rel) < 1e-4 and np.max(rel) < 1e-3
+
+
+def test_invsqrt_with_lazy_bootstrap(o10):
+    o = o10
+    lo, hi = 2.0 ** -10, 1.0
+    x = inputs.log_uniform(o.n, lo, hi, 4)
+    ct = o.encrypt(x, 7, 2.0 ** 50, 9)
+    y = o.invsqrt(ct, 31, 3, lo, hi)
+    ref = 1 / np.sqrt(x)
+    assert y.level == 0
+    assert np.mean(np.abs(o.decrypt(y).real - ref) / ref) < 1e-7
