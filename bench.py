@@ -1,15 +1,20 @@
 """Benchmark: encrypted inverse square roots per second at N = 2^16.
 
 One step = CryptoInvSqrt (paper Alg. 1: Chebyshev initial value, Newton
-steps, bootstrapping when levels run out) over a batch of ciphertexts already
-resident in HBM.  Prints one JSON line (see the contract in the design notes):
-value = ciphertexts/s for the whole job, plus the roofline of the dominant
-kernel family measured live with HIP events on the library's stream, the MRE
-of the result against FP64, and the CPU oracle timed on a bounded sample.
+steps, bootstrapping whenever levels run out) of the fixed configuration
+(degree 31, 3 Newton steps) on one ciphertext (--batch: several, as one
+batched launch sequence) already resident in HBM, on the 128-bit parameter
+set with bootstrapping (log2 QP ~ 1556, dnum 3, h 192): from the top
+computation level 7 the chain bootstraps once.  Prints one JSON line: value =
+ciphertexts/s for the whole job, the roofline of the dominant kernel family
+measured live with HIP events on the library's stream, the MRE of the result
+against FP64, the same chain batched (ciphertexts/s at --extra-batch), and the
+CPU oracle timed on a bounded sample.
 """
 import argparse
 import json
 import os
+import subprocess
 import sys
 import time
 
@@ -19,7 +24,8 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0          # MI355X HBM3E, published
-P16 = dict(log_n=16, max_level=27, num_special=7, digit_size=10, hamming_weight=192)
+P16B = dict(log_n=16, max_level=7, num_special=7, digit_size=8, hamming_weight=192, bts=(3, 10, 3, 52))
+EVALMOD = (25.0, 4, 31)
 LO, HI = 2.0 ** -10, 1.0
 
 
@@ -31,25 +37,40 @@ def parse():
     ap.add_argument("--batch", type=int, default=1, help="ciphertexts per step")
     ap.add_argument("--degree", type=int, default=31)
     ap.add_argument("--iters", type=int, default=3)
-    ap.add_argument("--level", type=int, default=13, help="input level")
+    ap.add_argument("--level", type=int, default=7, help="input level")
+    ap.add_argument("--extra-batch", type=int, default=16, help="also time this many ciphertexts per step (0: skip)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--cpu-samples", type=int, default=1)
+    ap.add_argument("--cpu-limit", type=int, default=360,
+                    help="seconds after the start the CPU baseline may run until")
     return ap.parse_args()
 
 
-def cpu_baseline(args, x_list):
-    """The oracle, as it stands, on the same chain for `cpu_samples` ciphertexts."""
-    from oracle import oracle as O
-    o = O.Context(16, 27, 7, 10, h=192)
-    o.keygen(9)
-    cts = [o.encrypt(x, args.level, 2.0 ** 50, 100 + i) for i, x in enumerate(x_list[:args.cpu_samples])]
-    t0 = time.perf_counter()
-    for ct in cts:
-        o.invsqrt(ct, args.degree, args.iters, LO, HI)
-    dt = time.perf_counter() - t0
-    return {"value": len(cts) / dt, "unit": "ciphertexts/s", "cores": 1, "kind": "oracle",
-            "sample": f"{len(cts)} full invsqrt (degree {args.degree}, {args.iters} Newton steps) "
-                      f"at N=2^16 from level {args.level}, single-threaded, {dt:.1f} s"}
+def start_cpu_baseline(args):
+    """Start the oracle on the same chain for one ciphertext in a child
+    process (single-threaded, plain CPU; it never touches the GPU), before
+    this process initialises the GPU, so that it runs alongside."""
+    cmd = [sys.executable, "-m", "oracle.chain_timer", "--level", str(args.level), "--degree", str(args.degree),
+           "--iters", str(args.iters)]
+    env = dict(os.environ, OMP_NUM_THREADS="1")
+    return subprocess.Popen(cmd, cwd=ROOT, stdout=subprocess.PIPE, stderr=subprocess.PIPE, text=True, env=env)
+
+
+def finish_cpu_baseline(proc, args, limit_s):
+    try:
+        out, err = proc.communicate(timeout=limit_s)
+    except subprocess.TimeoutExpired:
+        proc.kill()
+        proc.communicate()
+        return {"value": None, "unit": "ciphertexts/s", "cores": 1, "kind": "oracle",
+                "sample": f"oracle did not finish within the time limit ({limit_s:.0f} s left at the end of the GPU run)"}
+    if proc.returncode != 0:
+        return {"value": None, "unit": "ciphertexts/s", "cores": 1, "kind": "oracle",
+                "sample": "oracle failed: " + err.strip()[-200:]}
+    r = json.loads(out.strip().splitlines()[-1])
+    return {"value": round(1.0 / r["seconds"], 6), "unit": "ciphertexts/s", "cores": r["cores"], "kind": "oracle",
+            "sample": f"1 ciphertext through the same chain (degree {args.degree}, {args.iters} Newton steps, "
+                      f"bootstrapping when levels run out) at N=2^16 from level {args.level}, single-threaded: "
+                      f"{r['seconds']:.1f} s (set-up {r['setup_seconds']:.0f} s not timed), MRE {r['mre']:.3g}"}
 
 
 def main():
@@ -57,30 +78,39 @@ def main():
     if args.gpus != 1:
         print(json.dumps({"error": "this build runs on one GPU; --gpus must be 1"}))
         sys.exit(2)
+    t_start = time.perf_counter()
+    cpu_proc = None if args.no_cpu_baseline else start_cpu_baseline(args)
     import torch
     from paper_2606_10477_amd import ckks, inputs
 
     torch.cuda.set_device(0)
-    ctx = ckks.Context(**P16)
-    ctx.keygen(9)
-    xs = [inputs.log_uniform(ctx.n, LO, HI, 1 + i) for i in range(args.batch)]
-    cts = [ctx.encrypt(x, args.level, 2.0 ** 50, 3 + i) for i, x in enumerate(xs)]
+    ctx = ckks.Context(**P16B)
+    ctx.bts_setup(*EVALMOD)
+    ctx.keygen(9, ctx.bts_galois())
+    nmax = max(args.batch, args.extra_batch)
+    xs = [inputs.log_uniform(ctx.n, LO, HI, 1 + i) for i in range(nmax)]
+    cts = ctx.encrypt_batch(np.stack(xs), args.level, 2.0 ** 50, 3)
     ctx.sync()
 
-    def step():
-        if args.batch == 1:
+    def step(B):
+        if B == 1:
             return [ctx.invsqrt(cts[0], args.degree, args.iters, a=LO, b=HI)]
-        return ctx.invsqrt_batch(cts, args.degree, args.iters, a=LO, b=HI)
+        return ctx.invsqrt_batch(cts[:B], args.degree, args.iters, a=LO, b=HI)
 
     for _ in range(args.warmup):
-        out = step()
+        out = step(args.batch)
         del out
     ctx.sync()
     torch.cuda.synchronize()
+    ctx.trace(True)
+    out = step(args.batch)
+    n_bts = sum(1 for op in ctx.trace_read() if op[0] == "bootstrap")
+    ctx.trace(False)
+    ctx.sync()
     ctx.profile(True)
     t0 = time.perf_counter()
     for _ in range(args.steps):
-        out = step()
+        out = step(args.batch)
     ctx.sync()
     torch.cuda.synchronize()
     dt = time.perf_counter() - t0
@@ -89,14 +119,28 @@ def main():
         n, ms, by = ctx.profile_read(name)
         fam[name] = (n, ms, by)
     ctx.profile(False)
+    batched = None
+    if args.extra_batch > 1:
+        out2 = step(args.extra_batch)
+        del out2
+        ctx.sync()
+        t1 = time.perf_counter()
+        for _ in range(args.steps):
+            out2 = step(args.extra_batch)
+        ctx.sync()
+        dtb = time.perf_counter() - t1
+        batched = {"batch": args.extra_batch, "ciphertexts_per_s": round(args.extra_batch * args.steps / dtb, 3),
+                   "ms_per_step": round(dtb * 1e3 / args.steps, 3)}
+        del out2
 
     ref = 1 / np.sqrt(xs[0])
     z = ctx.decrypt(out[0]).real
     mre = float(np.mean(np.abs(z - ref) / ref))
     out_level = out[0].level
 
-    # dominant kernel family: the one with the most GPU time
-    dom = max(fam, key=lambda k: fam[k][1])
+    # roofline of the NTT (the metric's kernel and the largest share of kernel
+    # time: forward + inverse passes); the key switch is reported beside it
+    dom = "ntt"
     n, ms, by = fam[dom]
     achieved = (by / (ms / 1e3)) / 1e9 if ms > 0 else 0.0
     roof = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
@@ -120,20 +164,24 @@ def main():
         "vs_baseline": None,
         "dtype": "u64",
         "data": "synthetic",
-        "config": {"workload": f"CryptoInvSqrt degree {args.degree}, {args.iters} Newton steps, "
-                               f"x log-uniform in [2^-10,1], input level {args.level} (no bootstrap needed)",
+        "config": {"workload": f"CryptoInvSqrt fixed configuration: degree {args.degree}, {args.iters} Newton steps, "
+                               f"bootstrapping whenever levels run out ({n_bts} per ciphertext), "
+                               f"x log-uniform in [2^-10,1], input level {args.level}",
                    "ring_degree": 65536, "slots": 32768, "batch": args.batch,
-                   "params": "q0 60-bit + 27 x 40-bit, 7 x 60-bit special, dnum 3, h 192",
-                   "output_level": out_level},
+                   "params": "log2 QP 1556: q0 60-bit, 10 x 40-bit, 13 x 52-bit (EvalMod/CoeffToSlot), "
+                             "7 x 60-bit special, dnum 3, h 192; l_afterBTS 7",
+                   "bootstraps_per_ct": n_bts, "output_level": out_level},
         "mre": mre,
+        "batched": batched,
         "roofline": roof,
         "kernel_families": others,
     }
-    if not args.no_cpu_baseline:
-        res["cpu_baseline"] = cpu_baseline(args, xs if len(xs) >= args.cpu_samples else
-                                           [inputs.log_uniform(ctx.n, LO, HI, 1 + i) for i in range(args.cpu_samples)])
-    print(json.dumps(res), flush=True)
     ctx.close()
+    if cpu_proc is not None:
+        print("waiting for the CPU baseline (oracle, one ciphertext)", file=sys.stderr, flush=True)
+        left = max(10.0, args.cpu_limit - (time.perf_counter() - t_start))
+        res["cpu_baseline"] = finish_cpu_baseline(cpu_proc, args, left)
+    print(json.dumps(res), flush=True)
 
 
 if __name__ == "__main__":
