@@ -1,4 +1,4 @@
-"""Provision the degree-versus-iterations table on this GPU (paper §5.2).
+"""Provision the degree-versus-iterations table on this GPU (paper §4.2, Alg. 2 and 3).
 
 Runs the encrypted inverse square root with the tuner's own keys over a grid
 of Chebyshev degrees x Newton iterations at several input levels, measures the

@@ -1,4 +1,4 @@
-"""Degree-versus-iterations tuner for CryptoInvSqrt (paper §5.2).
+"""Degree-versus-iterations tuner for CryptoInvSqrt (paper §4.2, Alg. 2 and 3).
 
 Host logic of the paper's provisioning step:
   * ``get_opt_iter`` -- Alg. 2 (GetOptIter) after its loop: the threshold

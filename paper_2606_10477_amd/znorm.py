@@ -1,4 +1,4 @@
-"""Batched z-score standardisation of an encrypted table (paper §6.2's ZNorm,
+"""Batched z-score standardisation of an encrypted table (the Z-score normalisation of paper §5.3,
 invsqrt of the variance in the denominator).
 
 Each column of R rows is packed into R / (N/2) ciphertexts.  All columns go

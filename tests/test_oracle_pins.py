@@ -3,7 +3,7 @@ than itself -- a published test vector, a brute-force definition at tiny N, an
 exact big-integer identity, a library routine, or a value the paper prints.
 
 Paper passages pinned here: the Newton step for 1/sqrt (§2.2), the Chebyshev
-initial value (§2.3) and the statement in §5.3 that a degree-14 initial value
+initial value (§2.3) and the statement in §4.3 that a degree-14 initial value
 needs at least 12 Newton iterations to converge in plaintext.
 """
 import hashlib
@@ -391,7 +391,7 @@ def test_constants_and_level_to(oracle_mod, p12):
 
 
 # --------------------------------------------------------------------------
-# Chebyshev initial value and Newton (paper §2.2, §2.3, §5.3)
+# Chebyshev initial value and Newton (paper §2.2, §2.3, §4.3)
 # --------------------------------------------------------------------------
 @pytest.mark.parametrize("d,a,b", [(15, 2 ** -8, 1.0), (31, 2 ** -10, 1.0), (14, 1e-5, 1.0), (127, 2 ** -10, 1.0)])
 def test_cheb_coeffs_match_numpy_interpolation(oracle_mod, d, a, b):
@@ -423,7 +423,7 @@ def _plain_chain(x, coeffs, a, b, iters):
 
 
 def test_paper_degree14_needs_12_iterations(oracle_mod):
-    """§5.3: with the degree 2^4-2 initial value, at least 12 Newton iterations
+    """§4.3: with the degree 2^4-2 initial value, at least 12 Newton iterations
     are needed to converge in plaintext (input range [0.001, 100], B = 100)."""
     A, B, Bn = 0.001, 100.0, 100.0
     x = inputs.linspace_input(2 ** 15, A, B) / Bn
