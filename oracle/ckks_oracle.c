@@ -1129,21 +1129,22 @@ orc_ct *orc_rescale(orc_ctx *c, const orc_ct *a) {
  *   4. ModDown: y = iNTT_P(acc_b|P); z_i = NTT_{q_i}( sum_k [y_k * Phat_k^{-1}]_{p_k}
  *      * (Phat_k mod q_i) );  o_b,i = (acc_b,i - z_i) * P^{-1} mod q_i.
  */
-static void keyswitch(orc_ctx *c, int l, const uint64_t *d, const evk_t *ek, uint64_t *o0, uint64_t *o1) {
+/* ModUp of d (NTT form, level l): for each digit j the extended
+ * representation X_j[e] over Q_l and P (e = 0..ne-1), NTT form:
+ * d's own limb for e in digit j, the base conversion of the digit otherwise.
+ * Returns X laid out [beta][ne][N]. */
+static uint64_t *modup(orc_ctx *c, int l, const uint64_t *d) {
     size_t N = c->N;
     int K = c->K, L = c->L;
     int nq = l + 1, ne = nq + K;
-    /* extended basis index list: Q_l then P */
+    int beta = (nq + c->alpha - 1) / c->alpha;
     int *ext = malloc(sizeof(int) * ne);
     for (int i = 0; i < nq; i++) ext[i] = i;
     for (int k = 0; k < K; k++) ext[nq + k] = L + 1 + k;
     uint64_t *dc = malloc(sizeof(uint64_t) * nq * N);
     memcpy(dc, d, sizeof(uint64_t) * nq * N);
     for (int i = 0; i < nq; i++) ntt_inv(c, i, dc + (size_t)i * N);
-    uint64_t *acc = calloc((size_t)2 * ne * N, sizeof(uint64_t));
-    uint64_t *x = malloc(sizeof(uint64_t) * N);
-    uint64_t *tmp = malloc(sizeof(uint64_t) * N);
-    int beta = (nq + c->alpha - 1) / c->alpha;
+    uint64_t *X = malloc(sizeof(uint64_t) * (size_t)beta * ne * N);
     for (int j = 0; j < beta; j++) {
         int lo = j * c->alpha, hi = lo + c->alpha;
         if (hi > nq) hi = nq;
@@ -1160,6 +1161,7 @@ static void keyswitch(orc_ctx *c, int l, const uint64_t *d, const evk_t *ek, uin
         for (int e = 0; e < ne; e++) {
             int pi = ext[e];
             uint64_t r = c->q[pi];
+            uint64_t *x = X + ((size_t)j * ne + e) * N;
             if (e >= lo && e < hi) {
                 memcpy(x, d + (size_t)e * N, sizeof(uint64_t) * N);
             } else {
@@ -1173,15 +1175,36 @@ static void keyswitch(orc_ctx *c, int l, const uint64_t *d, const evk_t *ek, uin
                 }
                 ntt_fwd(c, pi, x);
             }
-            /* key limb for extended basis prime pi */
+        }
+        free(y);
+    }
+    free(ext); free(dc);
+    return X;
+}
+
+/* Inner product of the digits X (optionally read through the automorphism's
+ * NTT-domain index map: X_j[e][perm[t]]) with the key, then ModDown by P. */
+static void ks_finish(orc_ctx *c, int l, const uint64_t *X, const int *perm, const evk_t *ek, uint64_t *o0,
+                      uint64_t *o1) {
+    size_t N = c->N;
+    int K = c->K, L = c->L;
+    int nq = l + 1, ne = nq + K;
+    int beta = (nq + c->alpha - 1) / c->alpha;
+    uint64_t *acc = calloc((size_t)2 * ne * N, sizeof(uint64_t));
+    uint64_t *x = malloc(sizeof(uint64_t) * N);
+    uint64_t *tmp = malloc(sizeof(uint64_t) * N);
+    for (int j = 0; j < beta; j++)
+        for (int e = 0; e < ne; e++) {
+            int pi = e < nq ? e : L + 1 + (e - nq);
+            uint64_t r = c->q[pi];
+            const uint64_t *xs = X + ((size_t)j * ne + e) * N;
+            for (size_t t = 0; t < N; t++) x[t] = perm ? xs[perm[t]] : xs[t];
             for (int b = 0; b < 2; b++) {
                 const uint64_t *kl = ek->k + (((size_t)j * 2 + b) * c->np + pi) * N;
                 uint64_t *ac = acc + ((size_t)b * ne + e) * N;
                 for (size_t t = 0; t < N; t++) ac[t] = addmod(ac[t], mulmod(x[t], kl[t], r), r);
             }
         }
-        free(y);
-    }
     /* ModDown */
     for (int b = 0; b < 2; b++) {
         uint64_t *ac = acc + (size_t)b * ne * N;
@@ -1214,7 +1237,13 @@ static void keyswitch(orc_ctx *c, int l, const uint64_t *d, const evk_t *ek, uin
         }
         free(yk);
     }
-    free(ext); free(dc); free(acc); free(x); free(tmp);
+    free(acc); free(x); free(tmp);
+}
+
+static void keyswitch(orc_ctx *c, int l, const uint64_t *d, const evk_t *ek, uint64_t *o0, uint64_t *o1) {
+    uint64_t *X = modup(c, l, d);
+    ks_finish(c, l, X, NULL, ek, o0, o1);
+    free(X);
 }
 /* exported for tests: key switch of a raw polynomial with the relin key (-1) or rotation key */
 int orc_keyswitch(orc_ctx *c, int which, int level, const uint64_t *d, uint64_t *o0, uint64_t *o1) {
@@ -1301,6 +1330,46 @@ orc_ct *orc_rotate(orc_ctx *c, const orc_ct *a, int k) {
     return orc_automorphism(c, a, g);
 }
 orc_ct *orc_conjugate(orc_ctx *c, const orc_ct *a) { return orc_automorphism(c, a, 2 * c->N - 1); }
+
+/*
+ * Hoisted rotations (Halevi-Shoup): the ModUp of c1 is computed once and
+ * every rotation applies its automorphism to the extended digits (an index
+ * map in the NTT domain, identical for every prime), then the inner product
+ * with its key and ModDown; c0 is permuted and added.  Same result as a key
+ * switch of the rotated c1 up to the base conversion's overflow term, so the
+ * bits differ from orc_rotate; the slot values agree within noise.
+ * steps[i] = 0 gives a copy.
+ */
+int orc_rotate_hoisted(orc_ctx *c, const orc_ct *a, const int *steps, int n, orc_ct **outs) {
+    int l = a->level;
+    size_t N = c->N, nq = l + 1;
+    for (int i = 0; i < n; i++) outs[i] = NULL;
+    uint64_t *X = NULL;
+    int *perm = malloc(sizeof(int) * N);
+    for (int i = 0; i < n; i++) {
+        int g = orc_galois_rot(c, steps[i]);
+        if (g == 1) { outs[i] = ct_copy(c, a); continue; }
+        int ri = find_rot(c, g);
+        if (ri < 0) {
+            set_err("missing galois key");
+            for (int k = 0; k < i; k++) { orc_ct_free(outs[k]); outs[k] = NULL; }
+            free(X); free(perm);
+            return -1;
+        }
+        if (!X) X = modup(c, l, ct_poly(c, a, 1));
+        automorph_idx(c, g, perm);
+        orc_ct *r = ct_new(c, l, a->scale);
+        uint64_t *r0 = ct_poly(c, r, 0), *r1 = ct_poly(c, r, 1);
+        ks_finish(c, l, X, perm, &c->rot[ri], r0, r1);
+        const uint64_t *a0 = ct_poly(c, a, 0);
+        for (size_t li = 0; li < nq; li++)
+            for (size_t t = 0; t < N; t++)
+                r0[li * N + t] = addmod(r0[li * N + t], a0[li * N + perm[t]], c->q[li]);
+        outs[i] = r;
+    }
+    free(X); free(perm);
+    return 0;
+}
 
 /*
  * Bring a ciphertext to level `target` (< its level) carrying the canonical
@@ -1837,12 +1906,21 @@ static orc_ct *lt_apply(orc_ctx *c, const orc_ct *x, const lt_group *G, double s
     size_t N = c->N;
     if (l < 1) { set_err("level"); return NULL; }
     int g = G->g;
+    /* baby steps: every used b, rotated by b s, all from one hoisted ModUp */
     orc_ct **R = calloc(g, sizeof(orc_ct *));
+    int *used = calloc(g, sizeof(int)), *bsteps = malloc(sizeof(int) * g), nb = 0;
     for (int t = 0; t < G->nm; t++) {
         int i = floordiv(G->m[t], g), bb = G->m[t] - g * i;
-        if (!R[bb]) R[bb] = bb == 0 ? ct_copy(c, x) : orc_rotate(c, x, bb * G->s);
-        if (!R[bb]) { for (int k = 0; k < g; k++) orc_ct_free(R[k]); free(R); return NULL; }
+        used[bb] = 1;
     }
+    for (int bb = 0; bb < g; bb++) if (used[bb]) bsteps[nb++] = bb;
+    orc_ct **Rb = calloc(g, sizeof(orc_ct *));
+    int *kst = malloc(sizeof(int) * g);
+    for (int t = 0; t < nb; t++) kst[t] = bsteps[t] * G->s;
+    int rc = orc_rotate_hoisted(c, x, kst, nb, Rb);
+    for (int t = 0; t < nb; t++) R[bsteps[t]] = Rb[t];
+    free(Rb); free(kst); free(used); free(bsteps);
+    if (rc != 0) { free(R); return NULL; }
     cq *v = malloc(sizeof(cq) * n);
     i128 *coef = malloc(sizeof(i128) * N);
     uint64_t *pt = malloc(sizeof(uint64_t) * N);

@@ -95,6 +95,7 @@ def lib():
         "orc_bts_rotations": (C.c_int, [vp, i32p, C.c_int]),
         "orc_mod_raise": (vp, [vp, vp]),
         "orc_mul_monomial": (vp, [vp, vp, C.c_int]),
+        "orc_rotate_hoisted": (C.c_int, [vp, vp, i32p, C.c_int, C.POINTER(vp)]),
         "orc_coeff_to_slot": (vp, [vp, vp]),
         "orc_slot_to_coeff": (vp, [vp, vp]),
         "orc_eval_mod": (vp, [vp, vp]),
@@ -320,6 +321,14 @@ class Context:
 
     def conjugate(self, a):
         return Ct(self, lib().orc_conjugate(self.ptr, a.ptr))
+
+    def rotate_hoisted(self, a, steps):
+        """Rotations of one ciphertext sharing one ModUp (hoisted)."""
+        st = np.ascontiguousarray(steps, dtype=np.int32)
+        outs = (vp * len(st))()
+        if lib().orc_rotate_hoisted(self.ptr, a.ptr, _p(st, i32p), len(st), outs) != 0:
+            raise OracleError(lib().orc_last_error().decode())
+        return [Ct(self, outs[i]) for i in range(len(st))]
 
     def cheb_eval(self, x, coeffs, a, b):
         cf = np.ascontiguousarray(coeffs, dtype=np.float64)

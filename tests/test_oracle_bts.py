@@ -165,3 +165,19 @@ def test_invsqrt_with_lazy_bootstrap(o10):
     ref = 1 / np.sqrt(x)
     assert y.level == 0
     assert np.mean(np.abs(o.decrypt(y).real - ref) / ref) < 1e-7
+
+
+def test_hoisted_rotations_roll_the_slots(o8):
+    """Hoisted rotations (one ModUp for several automorphisms) decrypt to the
+    rolled slot vector, as the plain rotation does; their words differ from
+    the plain rotation's only by key-switching noise."""
+    o = o8
+    x = inputs.log_uniform(o.n, 1.0, 2.0, 11)
+    ct = o.encrypt(x, 5, o.ladder[5], 12)
+    steps = o.bts_rotations()[:3]
+    outs = o.rotate_hoisted(ct, [0] + steps)
+    assert np.array_equal(outs[0].words(), ct.words())
+    for k, r in zip(steps, outs[1:]):
+        assert np.max(np.abs(o.decrypt(r).real - np.roll(x, -k))) < 1e-6
+        plain = o.decrypt(o.rotate(ct, k)).real
+        assert np.max(np.abs(o.decrypt(r).real - plain)) < 1e-6
