@@ -187,6 +187,12 @@ ckks_status ckks_hmult_relin(ckks_ctx *ctx, const ckks_ct *a, const ckks_ct *b, 
 /* Left rotation of the slots by `steps` (automorphism X -> X^(5^steps) and
  * key switch; CKKS_E_NOKEY without the Galois key). */
 ckks_status ckks_rotate(ckks_ctx *ctx, const ckks_ct *a, int32_t steps, ckks_ct **out);
+/* Rotations of one ciphertext by n step counts sharing one ModUp (hoisting):
+ * outs[i] holds the slots rotated left by steps[i] (0: a copy).  Same slot
+ * values as ckks_rotate, different key-switching noise (the digits are
+ * converted before the automorphism).  On error every outs[i] is NULL. */
+ckks_status ckks_rotate_hoisted(ckks_ctx *ctx, const ckks_ct *a, const int32_t *steps, uint32_t n,
+                                ckks_ct **outs);
 /* Complex conjugation of the slots (X -> X^(2N-1)). */
 ckks_status ckks_conjugate(ckks_ctx *ctx, const ckks_ct *a, ckks_ct **out);
 

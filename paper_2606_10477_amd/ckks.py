@@ -68,6 +68,7 @@ SIGNATURES = {
     "ckks_hmult_relin": (C.c_int, [vp, vp, vp, C.POINTER(vp)]),
     "ckks_rotate": (C.c_int, [vp, vp, C.c_int32, C.POINTER(vp)]),
     "ckks_conjugate": (C.c_int, [vp, vp, C.POINTER(vp)]),
+    "ckks_rotate_hoisted": (C.c_int, [vp, vp, i32p, C.c_uint32, C.POINTER(vp)]),
     "ckks_cheb_eval": (C.c_int, [vp, vp, dblp, C.c_uint32, C.c_double, C.c_double, C.POINTER(vp)]),
     "ckks_cheb_coeffs_invsqrt": (C.c_int, [C.c_uint32, C.c_double, C.c_double, dblp]),
     "ckks_newton_step": (C.c_int, [vp, vp, vp, C.c_int, C.POINTER(vp)]),
@@ -285,6 +286,12 @@ class Context:
 
     def newton_step(self, y, half_x, raw_x=False):
         return self._ct(lib().ckks_newton_step, y.ptr, half_x.ptr, int(raw_x))
+
+    def rotate_hoisted(self, a, steps):
+        st = np.ascontiguousarray(steps, dtype=np.int32)
+        outs = (vp * len(st))()
+        self._chk(lib().ckks_rotate_hoisted(self.ptr, a.ptr, _p(st, i32p), len(st), outs))
+        return [Ciphertext(self, outs[i]) for i in range(len(st))]
 
     # -- bootstrapping -------------------------------------------------------
     def bts_setup(self, K=25.0, r=4, degree=31):

@@ -551,42 +551,62 @@ Ct op_rescale(ckks_ctx *c, const ckks_ct *a) {
     return r;
 }
 
-// Hybrid key switch of nct polynomials d (level l, NTT form; ciphertext b's
-// polynomial at d + b * d_stride).  out ([nct][2][l+1][N]) receives
-// (o0, o1) plus add[b][p] for the polys p selected by add_mask.
-void keyswitch(ckks_ctx *c, int l, const u64 *d, size_t d_stride, int nct, const SwitchKey &key, u64 *out,
-               const u64 *add, int add_mask) {
+// ModUp of nct polynomials d (level l, NTT form; ciphertext b's polynomial
+// at d + b * d_stride): per digit j the base conversion of the digit's limbs
+// to the other primes of Q_l and P, NTT form.  The digits' own limbs stay in
+// d (read in place by the inner product).
+struct ModUp {
+    int l = 0, nct = 0;
+    std::vector<Buf> ext;
+    gpu::InnerArgs ia{};
+};
+void modup(ckks_ctx *c, int l, const u64 *d, size_t d_stride, int nct, ModUp &mu) {
     const size_t N = c->N;
     const int nq = l + 1, ne = nq + c->K;
     const int beta = (nq + c->alpha - 1) / c->alpha;
-    // algorithmic bytes: d (nq limbs) in, key (2 beta ne limbs) in once, result (2 nq limbs) out, per ciphertext
-    ProfScope ps(c, "keyswitch", 8.0 * (double)N * ((double)nct * nq + 2.0 * beta * ne + 2.0 * nct * nq));
     Pool *P = c->pool.get();
+    mu.l = l;
+    mu.nct = nct;
     Buf dc(P, (size_t)nct * nq * N);
     ntt_oop_p(c, dc.p, d, d_stride, nq, nct, map_q(0, nq), true);
-    std::vector<Buf> ext;
-    ext.reserve(beta);
-    gpu::InnerArgs ia{};
+    mu.ext.clear();
+    mu.ext.reserve(beta);
+    gpu::InnerArgs &ia = mu.ia;
+    ia = gpu::InnerArgs{};
     ia.ndig = beta;
     ia.nct = nct;
     for (int j = 0; j < beta; ++j) {
         ConvTable *t = modup_table(c, l, j);
-        ext.emplace_back(P, (size_t)nct * t->dout * N);
+        mu.ext.emplace_back(P, (size_t)nct * t->dout * N);
         gpu::BconvArgs ba{t->pin, t->pout, t->din, t->dout, t->hinv.p, t->hinv_sh.p, t->mat.p};
         const int lo = j * c->alpha;
-        gpu::bconv(c->T, ext.back().p, dc.p + (size_t)lo * N, ba, nct, (size_t)nq * N, (size_t)t->dout * N, c->stream);
-        ntt_p(c, ext.back().p, t->dout, nct, t->pout, false);
+        gpu::bconv(c->T, mu.ext.back().p, dc.p + (size_t)lo * N, ba, nct, (size_t)nq * N, (size_t)t->dout * N,
+                   c->stream);
+        ntt_p(c, mu.ext.back().p, t->dout, nct, t->pout, false);
         ia.lo[j] = lo;
         ia.hi[j] = lo + t->din;
-        ia.ext[j] = ext.back().p;
+        ia.ext[j] = mu.ext.back().p;
         ia.ext_stride[j] = (size_t)t->dout * N;
     }
     ia.dsrc = d;
     ia.dsrc_stride = d_stride;
-    ia.key = key.k.p;
     ia.np = c->np;
     ia.m = map_ext(c, l);
     ia.ne = ne;
+    ia.perm = nullptr;
+}
+// Inner product of the ModUp digits (read through `perm`, the NTT-domain
+// index map of an automorphism, when given) with the key, ModDown by P.  out
+// ([nct][2][l+1][N]) receives (o0, o1) plus add[b][p] for the polys p
+// selected by add_mask.
+void ks_finish(ckks_ctx *c, const ModUp &mu, const SwitchKey &key, const int32_t *perm, u64 *out, const u64 *add,
+               int add_mask) {
+    const size_t N = c->N;
+    const int l = mu.l, nct = mu.nct, nq = l + 1, ne = nq + c->K;
+    Pool *P = c->pool.get();
+    gpu::InnerArgs ia = mu.ia;
+    ia.key = key.k.p;
+    ia.perm = perm;
     Buf acc(P, (size_t)nct * 2 * ne * N);
     gpu::key_inner(c->T, acc.p, ia, c->stream);
     // ModDown of all 2 nct polys
@@ -606,6 +626,21 @@ void keyswitch(ckks_ctx *c, int l, const u64 *d, size_t d_stride, int nct, const
         pinv.sh[i] = shoup(pinv.v[i], c->q[i]);
     }
     gpu::moddown_finish(c->T, out, acc.p, (size_t)ne * N, z.p, add, add_mask, pinv, nq, nct, map_q(0, nq), c->stream);
+}
+
+// Hybrid key switch of nct polynomials d (level l, NTT form; ciphertext b's
+// polynomial at d + b * d_stride).  out ([nct][2][l+1][N]) receives
+// (o0, o1) plus add[b][p] for the polys p selected by add_mask.
+void keyswitch(ckks_ctx *c, int l, const u64 *d, size_t d_stride, int nct, const SwitchKey &key, u64 *out,
+               const u64 *add, int add_mask) {
+    const size_t N = c->N;
+    const int nq = l + 1, ne = nq + c->K;
+    const int beta = (nq + c->alpha - 1) / c->alpha;
+    // algorithmic bytes: d (nq limbs) in, key (2 beta ne limbs) in once, result (2 nq limbs) out, per ciphertext
+    ProfScope ps(c, "keyswitch", 8.0 * (double)N * ((double)nct * nq + 2.0 * beta * ne + 2.0 * nct * nq));
+    ModUp mu;
+    modup(c, l, d, d_stride, nct, mu);
+    ks_finish(c, mu, key, nullptr, out, add, add_mask);
 }
 
 Ct op_hmult(ckks_ctx *c, const ckks_ct *a, const ckks_ct *b) {
@@ -635,6 +670,43 @@ Ct op_automorphism(ckks_ctx *c, const ckks_ct *a, int g) {
     // r = (sigma(c0) + ks0, ks1): key switch sigma(c1), add sigma(c0) to poly 0 only
     keyswitch(c, a->level, s.p + (size_t)nq * N, (size_t)2 * nq * N, B, it->second, r->buf.p, s.p, 1);
     return r;
+}
+
+int galois_rot(const ckks_ctx *c, int k);
+
+// Rotations of one ciphertext object by several steps sharing one ModUp of
+// c1 (hoisting): each applies its automorphism to the digits inside the inner
+// product, then ModDown, plus the permuted c0.  Step 0 gives a copy.
+std::vector<Ct> op_rotate_hoisted(ckks_ctx *c, const ckks_ct *a, const std::vector<int> &steps) {
+    const int l = a->level, nq = l + 1, B = a->B;
+    const size_t N = c->N;
+    std::vector<Ct> outs(steps.size());
+    ModUp mu;
+    bool have = false;
+    for (size_t i = 0; i < steps.size(); ++i) {
+        const int g = galois_rot(c, steps[i]);
+        if (g == 1) {
+            outs[i] = ct_copy(c, a);
+            continue;
+        }
+        auto it = c->rot.find(g);
+        if (it == c->rot.end()) fail(CKKS_E_NOKEY, "missing Galois key");
+        const int beta = (nq + c->alpha - 1) / c->alpha, ne = nq + c->K;
+        if (!have) {
+            ProfScope ps(c, "keyswitch", 8.0 * (double)N * B * nq);
+            modup(c, l, a->buf.p + (size_t)nq * N, (size_t)2 * nq * N, B, mu);
+            have = true;
+        }
+        trace_op(c, "rotate_hoisted", l, B);
+        const int32_t *perm = perm_for(c, g);
+        Buf s(c->pool.get(), (size_t)B * 2 * nq * N);
+        gpu::permute(c->T, s.p, a->buf.p, perm, nq, 2 * B, c->stream);
+        Ct r = ct_new(c, l, a->scale, B);
+        ProfScope ps(c, "keyswitch", 8.0 * (double)N * (2.0 * beta * ne + 2.0 * B * nq));
+        ks_finish(c, mu, it->second, perm, r->buf.p, s.p, 1);
+        outs[i] = std::move(r);
+    }
+    return outs;
 }
 
 int galois_rot(const ckks_ctx *c, int k) {
@@ -858,11 +930,16 @@ Ct op_mod_raise(ckks_ctx *c, const ckks_ct *a) {
 Ct op_lt(ckks_ctx *c, const ckks_ct *x, const LtStage &st) {
     if (x->level != st.level) fail(CKKS_E_LEVEL, "slot transform at the wrong level");
     const int n = c->N / 2, nq = x->level + 1, B = x->B;
+    // baby steps: every used b, rotated by b * stride, from one hoisted ModUp
+    std::vector<int> bs;
+    for (int b : st.baby)
+        if (b != 0 && std::find(bs.begin(), bs.end(), b) == bs.end()) bs.push_back(b);
+    std::sort(bs.begin(), bs.end());
+    std::vector<int> ks;
+    for (int b : bs) ks.push_back(b * st.stride);
+    std::vector<Ct> rot = op_rotate_hoisted(c, x, ks);
     std::map<int, Ct> R;
-    for (size_t t = 0; t < st.baby.size(); ++t) {
-        const int b = st.baby[t];
-        if (b != 0 && !R.count(b)) R[b] = op_rotate(c, x, b * st.stride);
-    }
+    for (size_t t = 0; t < bs.size(); ++t) R[bs[t]] = std::move(rot[t]);
     Ct acc;
     size_t t = 0;
     while (t < st.giant.size()) {
@@ -1464,6 +1541,15 @@ ckks_status ckks_hmult_relin(ckks_ctx *c, const ckks_ct *a, const ckks_ct *b, ck
 ckks_status ckks_rotate(ckks_ctx *c, const ckks_ct *a, int32_t steps, ckks_ct **out) {
     CT_ARGS_CHECK();
     return guard_out(c, out, [&] { return op_rotate(c, a, steps); });
+}
+ckks_status ckks_rotate_hoisted(ckks_ctx *c, const ckks_ct *a, const int32_t *steps, uint32_t n, ckks_ct **outs) {
+    if (!c || !a || (n && (!steps || !outs))) return CKKS_E_PARAM;
+    for (uint32_t i = 0; i < n; ++i) outs[i] = nullptr;
+    return guard(c, [&] {
+        std::vector<int> ks(steps, steps + n);
+        std::vector<Ct> r = op_rotate_hoisted(c, a, ks);
+        for (uint32_t i = 0; i < n; ++i) outs[i] = r[i].release();
+    });
 }
 ckks_status ckks_conjugate(ckks_ctx *c, const ckks_ct *a, ckks_ct **out) {
     CT_ARGS_CHECK();

@@ -99,6 +99,7 @@ void bconv(const Tables &T, uint64_t *out, const uint64_t *in, const BconvArgs &
            size_t in_poly_stride, size_t out_poly_stride, hipStream_t s);
 
 // Key inner product over nct ciphertexts: acc[ct][p][e] = sum_j x_j[ct][e] * key_j[p][prime(e)]
+// (with perm: x_j read at word perm[j] of each limb, keys at word j)
 // (p = 0, 1; acc laid out [nct][2][ne][N]), where
 // x_j[ct][e] = e in [lo_j, hi_j) ? dsrc[ct][e] : ext_j[ct][compact(e)],
 // compact(e) = e < lo_j ? e : e - (hi_j - lo_j).  Each key word is loaded once
@@ -115,6 +116,7 @@ struct InnerArgs {
     int np;
     LimbMap m;             // extended basis map (Q_l then P)
     int ne;
+    const int32_t *perm;   // nullable: digits read at perm[j] (automorphism of hoisted digits)
 };
 void key_inner(const Tables &T, uint64_t *acc, const InnerArgs &a, hipStream_t s);
 

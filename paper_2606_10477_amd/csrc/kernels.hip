@@ -672,16 +672,17 @@ __global__ void k_key_inner(u64 *acc, InnerArgs a, int logN, size_t total, Table
     GRID_LOOP(i, total) {
         const int e = (int)(i >> logN);
         const size_t j = i & (N - 1);
+        const size_t jx = a.perm ? (size_t)a.perm[j] : j;
         const int pi = a.m.p[e];
         const DevPrime P = T.primes[pi];
         for (int b = 0; b < a.nct; ++b) {
             u64 h0 = 0, l0 = 0, h1 = 0, l1 = 0;
             for (int d = 0; d < a.ndig; ++d) {
                 u64 x;
-                if (e >= a.lo[d] && e < a.hi[d]) x = a.dsrc[b * a.dsrc_stride + (size_t)e * N + j];
+                if (e >= a.lo[d] && e < a.hi[d]) x = a.dsrc[b * a.dsrc_stride + (size_t)e * N + jx];
                 else {
                     int ce = e < a.lo[d] ? e : e - (a.hi[d] - a.lo[d]);
-                    x = a.ext[d][b * a.ext_stride[d] + (size_t)ce * N + j];
+                    x = a.ext[d][b * a.ext_stride[d] + (size_t)ce * N + jx];
                 }
                 const u64 *k0 = a.key + (((size_t)d * 2 + 0) * a.np + pi) * N;
                 const u64 *k1 = a.key + (((size_t)d * 2 + 1) * a.np + pi) * N;

@@ -74,6 +74,15 @@ def test_mod_raise_and_monomial_bit_exact(pair):
         same(g.mul_monomial(gc, k), o.mul_monomial(oc, k))
 
 
+def test_hoisted_rotations_bit_exact(pair):
+    g, o = pair
+    x = inputs.log_uniform(g.n, 1.0, 2.0, 9)
+    gc, oc = g.encrypt(x, 12, g.ladder[12], 69), o.encrypt(x, 12, o.ladder[12], 69)
+    steps = [0] + g.bts_rotations()[:4]
+    for gr, orr in zip(g.rotate_hoisted(gc, steps), o.rotate_hoisted(oc, steps)):
+        same(gr, orr)
+
+
 def test_slot_transforms_and_evalmod_bit_exact(pair):
     g, o = pair
     x = inputs.log_uniform(g.n, 1.0, 32.0, 6)
