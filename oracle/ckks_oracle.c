@@ -1899,6 +1899,7 @@ static uint64_t i128_mod(i128 v, uint64_t q) {
 
 /* baby-step giant-step product of a group matrix with the slots of x:
  *   out = sum_i rot_{g i s}( sum_b P_{i,b} * rot_{b s}(x) ),
+ *   every rotation in the hoisted form (the babies share one ModUp of x),
  *   P_{i,b} = diagonal m = g i + b rotated right by g i s, encoded at
  *   scale sd;  one rescale at the end (scale (scale(x) sd) / q_l). */
 static orc_ct *lt_apply(orc_ctx *c, const orc_ct *x, const lt_group *G, double sd) {
@@ -1952,9 +1953,13 @@ static orc_ct *lt_apply(orc_ctx *c, const orc_ct *x, const lt_group *G, double s
         }
         if (fail || !inner) continue;
         if (i != 0) {
-            orc_ct *ri = orc_rotate(c, inner, (int)(((int64_t)g * i * G->s) % n));
+            /* giant rotation in the hoisted form too (automorphism applied to
+             * the ModUp digits of the inner sum) */
+            int kk = (int)(((int64_t)g * i * G->s) % n);
+            orc_ct *ri = NULL;
+            int rc2 = orc_rotate_hoisted(c, inner, &kk, 1, &ri);
             orc_ct_free(inner);
-            if (!ri) { fail = 1; break; }
+            if (rc2 != 0 || !ri) { fail = 1; break; }
             inner = ri;
         }
         if (!acc) acc = inner;
