@@ -674,6 +674,60 @@ Ct op_automorphism(ckks_ctx *c, const ckks_ct *a, int g) {
 
 int galois_rot(const ckks_ctx *c, int k);
 
+// One rotation of a batch of inputs in a job list (see ks_rot_jobs).
+struct RotJob {
+    const SwitchKey *key;
+    const int32_t *perm;
+    int ct0;          // first of the job's B inputs in the ModUp
+    u64 *out;         // [B][2][l+1][N]
+    const u64 *add;   // [B][2][l+1][N]: its c0 (poly 0), read through perm, is added
+};
+// Key switching of rotation jobs over one ModUp: inner products and ModDown
+// of up to kMaxJobs jobs run as one launch sequence.
+void ks_rot_jobs(ckks_ctx *c, const ModUp &mu, int B, const std::vector<RotJob> &jobs) {
+    const size_t N = c->N;
+    const int l = mu.l, nq = l + 1, ne = nq + c->K;
+    const int beta = (nq + c->alpha - 1) / c->alpha;
+    Pool *P = c->pool.get();
+    ConvTable *md = moddown_table(c, l);
+    LimbConsts pinv{};
+    std::vector<int> pidx;
+    for (int k = 0; k < c->K; ++k) pidx.push_back(c->L + 1 + k);
+    for (int i = 0; i < nq; ++i) {
+        pinv.v[i] = hm::invmod(prod_mod(c, pidx, -1, c->q[i]), c->q[i]);
+        pinv.sh[i] = shoup(pinv.v[i], c->q[i]);
+    }
+    // at most 64 ciphertexts' worth of extended accumulators per launch sequence
+    const size_t per = (size_t)std::max(1, std::min(gpu::kMaxJobs, 64 / std::max(1, B)));
+    for (size_t j0 = 0; j0 < jobs.size(); j0 += per) {
+        const int nj = (int)std::min<size_t>(per, jobs.size() - j0);
+        ProfScope ps(c, "keyswitch", 8.0 * (double)N * ((double)nj * 2.0 * beta * ne + 2.0 * nj * B * nq));
+        gpu::KsJobs kj{};
+        gpu::FinishJobs fj{};
+        kj.njob = nj;
+        kj.B = B;
+        for (int t = 0; t < nj; ++t) {
+            const RotJob &jb = jobs[j0 + t];
+            kj.ct0[t] = jb.ct0;
+            kj.key[t] = jb.key->k.p;
+            kj.perm[t] = jb.perm;
+            fj.out[t] = jb.out;
+            fj.add[t] = jb.add;
+            fj.perm[t] = jb.perm;
+        }
+        const int np2 = 2 * nj * B;
+        Buf acc(P, (size_t)np2 * ne * N);
+        gpu::key_inner_jobs(c->T, acc.p, mu.ia, kj, c->stream);
+        Buf y(P, (size_t)np2 * c->K * N);
+        ntt_oop_p(c, y.p, acc.p + (size_t)nq * N, (size_t)ne * N, c->K, np2, md->pin, true);
+        Buf z(P, (size_t)np2 * nq * N);
+        gpu::BconvArgs bd{md->pin, md->pout, md->din, md->dout, md->hinv.p, md->hinv_sh.p, md->mat.p};
+        gpu::bconv(c->T, z.p, y.p, bd, np2, (size_t)c->K * N, (size_t)nq * N, c->stream);
+        ntt_p(c, z.p, nq, np2, map_q(0, nq), false);
+        gpu::moddown_finish_jobs(c->T, fj, acc.p, (size_t)ne * N, z.p, pinv, nq, nj, B, map_q(0, nq), c->stream);
+    }
+}
+
 // Rotations of one ciphertext object by several steps sharing one ModUp of
 // c1 (hoisting): each applies its automorphism to the digits inside the inner
 // product, then ModDown, plus the permuted c0.  Step 0 gives a copy.
@@ -681,8 +735,7 @@ std::vector<Ct> op_rotate_hoisted(ckks_ctx *c, const ckks_ct *a, const std::vect
     const int l = a->level, nq = l + 1, B = a->B;
     const size_t N = c->N;
     std::vector<Ct> outs(steps.size());
-    ModUp mu;
-    bool have = false;
+    std::vector<RotJob> jobs;
     for (size_t i = 0; i < steps.size(); ++i) {
         const int g = galois_rot(c, steps[i]);
         if (g == 1) {
@@ -691,21 +744,17 @@ std::vector<Ct> op_rotate_hoisted(ckks_ctx *c, const ckks_ct *a, const std::vect
         }
         auto it = c->rot.find(g);
         if (it == c->rot.end()) fail(CKKS_E_NOKEY, "missing Galois key");
-        const int beta = (nq + c->alpha - 1) / c->alpha, ne = nq + c->K;
-        if (!have) {
-            ProfScope ps(c, "keyswitch", 8.0 * (double)N * B * nq);
-            modup(c, l, a->buf.p + (size_t)nq * N, (size_t)2 * nq * N, B, mu);
-            have = true;
-        }
         trace_op(c, "rotate_hoisted", l, B);
-        const int32_t *perm = perm_for(c, g);
-        Buf s(c->pool.get(), (size_t)B * 2 * nq * N);
-        gpu::permute(c->T, s.p, a->buf.p, perm, nq, 2 * B, c->stream);
-        Ct r = ct_new(c, l, a->scale, B);
-        ProfScope ps(c, "keyswitch", 8.0 * (double)N * (2.0 * beta * ne + 2.0 * B * nq));
-        ks_finish(c, mu, it->second, perm, r->buf.p, s.p, 1);
-        outs[i] = std::move(r);
+        outs[i] = ct_new(c, l, a->scale, B);
+        jobs.push_back(RotJob{&it->second, perm_for(c, g), 0, outs[i]->buf.p, a->buf.p});
     }
+    if (jobs.empty()) return outs;
+    ModUp mu;
+    {
+        ProfScope ps(c, "keyswitch", 8.0 * (double)N * B * nq);
+        modup(c, l, a->buf.p + (size_t)nq * N, (size_t)2 * nq * N, B, mu);
+    }
+    ks_rot_jobs(c, mu, B, jobs);
     return outs;
 }
 
@@ -940,27 +989,61 @@ Ct op_lt(ckks_ctx *c, const ckks_ct *x, const LtStage &st) {
     std::vector<Ct> rot = op_rotate_hoisted(c, x, ks);
     std::map<int, Ct> R;
     for (size_t t = 0; t < bs.size(); ++t) R[bs[t]] = std::move(rot[t]);
-    Ct acc;
-    size_t t = 0;
-    while (t < st.giant.size()) {
-        const int gi = st.giant[t];
+    // inner sums of every giant step into one buffer [giant][B][2][nq][N]:
+    // the rotated giants first (their ModUp is one batch), giant 0 last
+    std::vector<int> gis;
+    for (int gi : st.giant)
+        if (std::find(gis.begin(), gis.end(), gi) == gis.end()) gis.push_back(gi);
+    std::stable_partition(gis.begin(), gis.end(), [](int gi) { return gi != 0; });
+    const size_t N = c->N, member = (size_t)2 * nq * N, gstride = member * B;
+    Buf inner(c->pool.get(), gstride * gis.size());
+    for (size_t k = 0; k < gis.size(); ++k) {
         gpu::MacArgs ma{};
-        while (t < st.giant.size() && st.giant[t] == gi) {
+        for (size_t t = 0; t < st.giant.size(); ++t) {
+            if (st.giant[t] != gis[k]) continue;
             if (ma.nterm >= gpu::kMaxMac) fail(CKKS_E_PARAM, "too many baby steps");
             const int b = st.baby[t];
             ma.pt[ma.nterm] = st.pt[t].p;
             ma.x[ma.nterm] = b == 0 ? x->buf.p : R[b]->buf.p;
             ++ma.nterm;
-            ++t;
         }
-        Ct inner = ct_new(c, x->level, x->scale * st.sd, B);
         trace_op(c, "mul_plain", x->level, B);
-        gpu::pt_mac(c->T, inner->buf.p, ma, nq, 2 * B, map_q(0, nq), c->stream);
-        if (gi != 0) {
-            const long long k = ((long long)st.g * gi * st.stride) % n;
-            inner = op_rotate(c, inner.get(), (int)k);
+        gpu::pt_mac(c->T, inner.p + k * gstride, ma, nq, 2 * B, map_q(0, nq), c->stream);
+    }
+    const size_t nrot = gis.size() - (gis.back() == 0 ? 1 : 0);
+    Ct acc = ct_new(c, x->level, x->scale * st.sd, B);
+    if (nrot > 0) {
+        Buf rot(c->pool.get(), gstride * nrot);
+        std::vector<RotJob> jobs;
+        for (size_t k = 0; k < nrot; ++k) {
+            const long long steps = ((long long)st.g * gis[k] * st.stride) % n;
+            const int g = galois_rot(c, (int)steps);
+            auto it = c->rot.find(g);
+            if (it == c->rot.end()) fail(CKKS_E_NOKEY, "missing Galois key");
+            trace_op(c, "rotate", x->level, B);
+            jobs.push_back(RotJob{&it->second, perm_for(c, g), (int)(k * B), rot.p + k * gstride, inner.p + k * gstride});
         }
-        acc = acc ? op_addsub(c, acc.get(), inner.get(), false) : std::move(inner);
+        ModUp mu;
+        {
+            ProfScope ps(c, "keyswitch", 8.0 * (double)N * nrot * B * nq);
+            modup(c, x->level, inner.p + (size_t)nq * N, member, (int)(nrot * B), mu);
+        }
+        ks_rot_jobs(c, mu, B, jobs);
+        // sum of the rotated giants (and giant 0)
+        const u64 *first = rot.p;
+        if (nrot == 1 && gis.size() == 1) {
+            hipchk(hipMemcpyAsync(acc->buf.p, first, gstride * 8, hipMemcpyDeviceToDevice, c->stream), "copy");
+        } else {
+            const u64 *second = nrot > 1 ? rot.p + gstride : inner.p + nrot * gstride;
+            gpu::add(c->T, acc->buf.p, first, second, nq, 2 * B, map_q(0, nq), false, c->stream);
+            for (size_t k = 2; k < nrot; ++k)
+                gpu::add(c->T, acc->buf.p, acc->buf.p, rot.p + k * gstride, nq, 2 * B, map_q(0, nq), false, c->stream);
+            if (nrot > 1 && gis.size() > nrot)
+                gpu::add(c->T, acc->buf.p, acc->buf.p, inner.p + nrot * gstride, nq, 2 * B, map_q(0, nq), false,
+                         c->stream);
+        }
+    } else {
+        hipchk(hipMemcpyAsync(acc->buf.p, inner.p, gstride * 8, hipMemcpyDeviceToDevice, c->stream), "copy");
     }
     return op_rescale(c, acc.get());
 }

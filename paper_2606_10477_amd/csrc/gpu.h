@@ -140,6 +140,31 @@ struct MacArgs {
 void pt_mac(const Tables &T, uint64_t *out, const MacArgs &a, int nlimb, int npoly, const LimbMap &m,
             hipStream_t s);
 
+// Rotation key-switch jobs over one ModUp of nct inputs: job t applies key
+// key[t] to the B inputs ct0[t] .. ct0[t]+B-1, reading their digits through
+// perm[t] (the automorphism's NTT-domain index map).  acc is laid out
+// [njob][B][2][ne][N].  Each key word is loaded once per job and used for the
+// job's B inputs.
+constexpr int kMaxJobs = 32;
+struct KsJobs {
+    int njob, B;
+    int ct0[kMaxJobs];
+    const uint64_t *key[kMaxJobs];
+    const int32_t *perm[kMaxJobs];
+};
+void key_inner_jobs(const Tables &T, uint64_t *acc, const InnerArgs &a, const KsJobs &j, hipStream_t s);
+// ModDown finish of rotation jobs: out[t] ([B][2][nlimb][N]) receives
+// (acc - z) * Pinv for job t, plus on poly 0 the word add[t][...][perm[t][j]]
+// (the rotated c0 of the job's input, [B][2][nlimb][N]) when add[t] is set.
+struct FinishJobs {
+    uint64_t *out[kMaxJobs];
+    const uint64_t *add[kMaxJobs];
+    const int32_t *perm[kMaxJobs];
+};
+void moddown_finish_jobs(const Tables &T, const FinishJobs &f, const uint64_t *acc, size_t acc_poly_stride,
+                         const uint64_t *z, const LimbConsts &pinv, int nlimb, int njob, int B, const LimbMap &m,
+                         hipStream_t s);
+
 // decryption: m = c0 + c1 * s
 void decrypt_combine(const Tables &T, uint64_t *m, const uint64_t *c0, const uint64_t *c1, const uint64_t *sk,
                      int nlimb, const LimbMap &m_, hipStream_t s);

@@ -700,6 +700,73 @@ void key_inner(const Tables &T, uint64_t *acc, const InnerArgs &a, hipStream_t s
     hipLaunchKernelGGL(k_key_inner, grid_for(total), dim3(256), 0, s, acc, a, T.logN, total, T);
 }
 
+__global__ void k_key_inner_jobs(u64 *acc, InnerArgs a, KsJobs J, int logN, size_t total, Tables T) {
+    const size_t N = (size_t)1 << logN;
+    GRID_LOOP(i, total) {
+        const int e = (int)(i >> logN);
+        const size_t j = i & (N - 1);
+        const int pi = a.m.p[e];
+        const DevPrime P = T.primes[pi];
+        for (int t = 0; t < J.njob; ++t) {
+            const size_t jx = J.perm[t] ? (size_t)J.perm[t][j] : j;
+            const u64 *key = J.key[t];
+            for (int b = 0; b < J.B; ++b) {
+                const size_t ct = (size_t)(J.ct0[t] + b);
+                u64 h0 = 0, l0 = 0, h1 = 0, l1 = 0;
+                for (int d = 0; d < a.ndig; ++d) {
+                    u64 x;
+                    if (e >= a.lo[d] && e < a.hi[d]) x = a.dsrc[ct * a.dsrc_stride + (size_t)e * N + jx];
+                    else {
+                        int ce = e < a.lo[d] ? e : e - (a.hi[d] - a.lo[d]);
+                        x = a.ext[d][ct * a.ext_stride[d] + (size_t)ce * N + jx];
+                    }
+                    const u64 *k0 = key + (((size_t)d * 2 + 0) * a.np + pi) * N;
+                    const u64 *k1 = key + (((size_t)d * 2 + 1) * a.np + pi) * N;
+                    mac128(h0, l0, x, k0[j]);
+                    mac128(h1, l1, x, k1[j]);
+                }
+                u64 *o = acc + ((size_t)t * J.B + b) * 2 * a.ne * N;
+                o[i] = reduce128(h0, l0, P);
+                o[(size_t)a.ne * N + i] = reduce128(h1, l1, P);
+            }
+        }
+    }
+}
+void key_inner_jobs(const Tables &T, uint64_t *acc, const InnerArgs &a, const KsJobs &j, hipStream_t s) {
+    size_t total = (size_t)a.ne << T.logN;
+    if (!total || j.njob <= 0) return;
+    hipLaunchKernelGGL(k_key_inner_jobs, grid_for(total), dim3(256), 0, s, acc, a, j, T.logN, total, T);
+}
+
+__global__ void k_moddown_finish_jobs(FinishJobs F, const u64 *acc, size_t acc_stride, const u64 *z, LimbConsts pinv,
+                                      int logN, int nlimb, int B, size_t total, LimbMap m, Tables T) {
+    const size_t N = (size_t)1 << logN;
+    const size_t member = (size_t)2 * nlimb * N;
+    GRID_LOOP(i, total) {
+        ROW_SPLIT(i, logN, nlimb, poly, limb)
+        const uint32_t t = poly / (2u * (uint32_t)B);
+        const uint32_t r2 = poly - t * 2u * (uint32_t)B;
+        const uint32_t b = r2 >> 1, pp = r2 & 1u;
+        const size_t j = i & (N - 1);
+        const size_t rem = ((size_t)limb << logN) | j;
+        const u64 q = T.primes[m.p[limb]].q;
+        u64 v = mul_shoup(sub_mod(acc[(size_t)poly * acc_stride + rem], z[i], q), pinv.v[limb], pinv.sh[limb], q);
+        if (pp == 0 && F.add[t]) {
+            const size_t jx = F.perm[t] ? (size_t)F.perm[t][j] : j;
+            v = add_mod(v, F.add[t][b * member + ((size_t)limb << logN) + jx], q);
+        }
+        F.out[t][b * member + (size_t)pp * nlimb * N + rem] = v;
+    }
+}
+void moddown_finish_jobs(const Tables &T, const FinishJobs &f, const uint64_t *acc, size_t acc_poly_stride,
+                         const uint64_t *z, const LimbConsts &pinv, int nlimb, int njob, int B, const LimbMap &m,
+                         hipStream_t s) {
+    size_t total = ((size_t)nlimb * 2 * njob * B) << T.logN;
+    if (!total) return;
+    hipLaunchKernelGGL(k_moddown_finish_jobs, grid_for(total), dim3(256), 0, s, f, acc, acc_poly_stride, z, pinv,
+                       T.logN, nlimb, B, total, m, T);
+}
+
 __global__ void k_moddown_finish(u64 *out, const u64 *acc, size_t acc_stride, const u64 *z, const u64 *add,
                                  int add_mask, LimbConsts pinv, int logN, int nlimb, size_t total, LimbMap m,
                                  Tables T) {
