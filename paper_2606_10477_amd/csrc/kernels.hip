@@ -637,31 +637,52 @@ void sub_mul(const Tables &T, uint64_t *out, const uint64_t *c, const uint64_t *
 // ---------------------------------------------------------------------------
 // Fast base conversion
 // ---------------------------------------------------------------------------
+// One thread per coefficient j of a polynomial: the DIN input residues are
+// scaled by [Dhat_i^-1]_{q_i} (kept in registers: DIN is a template
+// parameter, so the arrays are fully unrolled), then each output limb is one
+// 128-bit multiply-accumulate over them, reduced once.
+template <int DIN>
 __global__ void __launch_bounds__(256) k_bconv(u64 *out, const u64 *in, BconvArgs a, int logN, size_t in_stride,
                                                size_t out_stride, Tables T) {
     const size_t N = (size_t)1 << logN;
     const int poly = blockIdx.y;
     const size_t j = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (j >= N) return;
-    u64 y[kMaxLimbs < 16 ? kMaxLimbs : 16];
+    u64 y[DIN];
     const u64 *src = in + poly * in_stride;
-    for (int i = 0; i < a.din; ++i) {
-        const DevPrime P = T.primes[a.pin.p[i]];
-        y[i] = mul_shoup(src[(size_t)i * N + j], a.hinv[i], a.hinv_sh[i], P.q);
+#pragma unroll
+    for (int i = 0; i < DIN; ++i) {
+        const u64 q = T.primes[a.pin.p[i]].q;
+        y[i] = mul_shoup(src[(size_t)i * N + j], a.hinv[i], a.hinv_sh[i], q);
     }
     u64 *dst = out + poly * out_stride;
     for (int r = 0; r < a.dout; ++r) {
         const DevPrime P = T.primes[a.pout.p[r]];
         u64 hi = 0, lo = 0;
-        for (int i = 0; i < a.din; ++i) mac128(hi, lo, y[i], a.mat[(size_t)i * a.dout + r]);
+#pragma unroll
+        for (int i = 0; i < DIN; ++i) mac128(hi, lo, y[i], a.mat[(size_t)i * a.dout + r]);
         dst[(size_t)r * N + j] = reduce128(hi, lo, P);
     }
 }
-void bconv(const Tables &T, uint64_t *out, const uint64_t *in, const BconvArgs &a, int npoly, size_t in_poly_stride,
-           size_t out_poly_stride, hipStream_t s) {
+template <int DIN>
+static void bconv_launch(const Tables &T, uint64_t *out, const uint64_t *in, const BconvArgs &a, int npoly,
+                         size_t in_poly_stride, size_t out_poly_stride, hipStream_t s) {
     const size_t N = (size_t)1 << T.logN;
     dim3 grid((unsigned)((N + 255) / 256), npoly);
-    hipLaunchKernelGGL(k_bconv, grid, dim3(256), 0, s, out, in, a, T.logN, in_poly_stride, out_poly_stride, T);
+    hipLaunchKernelGGL(k_bconv<DIN>, grid, dim3(256), 0, s, out, in, a, T.logN, in_poly_stride, out_poly_stride, T);
+}
+void bconv(const Tables &T, uint64_t *out, const uint64_t *in, const BconvArgs &a, int npoly, size_t in_poly_stride,
+           size_t out_poly_stride, hipStream_t s) {
+    if (npoly <= 0 || a.dout <= 0) return;
+    switch (a.din) {
+#define BCONV_CASE(D) \
+    case D: bconv_launch<D>(T, out, in, a, npoly, in_poly_stride, out_poly_stride, s); break;
+        BCONV_CASE(1) BCONV_CASE(2) BCONV_CASE(3) BCONV_CASE(4) BCONV_CASE(5) BCONV_CASE(6) BCONV_CASE(7)
+        BCONV_CASE(8) BCONV_CASE(9) BCONV_CASE(10) BCONV_CASE(11) BCONV_CASE(12) BCONV_CASE(13) BCONV_CASE(14)
+        BCONV_CASE(15) BCONV_CASE(16)
+#undef BCONV_CASE
+        default: break;   // the host rejects digits of more than 16 primes
+    }
 }
 
 // ---------------------------------------------------------------------------
