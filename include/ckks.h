@@ -269,16 +269,18 @@ typedef struct {
     int32_t literal;    /* 1: bootstrap y0 right after the Chebyshev step, as
                            Alg. 1 is written; 0 (default): bootstrap y only
                            when it has fewer than 2 levels before a step */
-    int32_t reserved;   /* 0 */
+    int32_t pre_bts;    /* 1: bootstrap x before the Chebyshev step (the
+                           paper's Pre-BTS indicator c = 1); 0: only when x
+                           lacks the levels for it */
     int64_t bts_bound;  /* message bound for bootstrapping y (0: 16 ceil(1/sqrt(a))) */
 } ckks_invsqrt_opts;
 
 /*
  * CryptoInvSqrt (paper Alg. 1): y0 = Chebyshev interpolant of degree `degree`
  * of 1/sqrt on [a, b]; ct_x = x/2; `iters` Newton steps; bootstrapping of y
- * per the policy in opts.  Pre-BTS (the paper's c = 1): if x has fewer than
- * depth(degree) + 1 levels or fewer than 3, x is bootstrapped first (bound
- * 16 ceil(b)); otherwise x is never bootstrapped.  The last Newton step takes x/2 directly from the
+ * per the policy in opts.  Pre-BTS (the paper's c = 1): with opts.pre_bts,
+ * or if x has fewer than depth(degree) + 1 levels or fewer than 3, x is
+ * bootstrapped first (bound 16 ceil(b)); otherwise x is never bootstrapped.  The last Newton step takes x/2 directly from the
  * input (limbs dropped, halving as an exact scale change, no rescale), so the
  * result keeps the relative precision of the input's scale; its scale is the
  * product of the step's scales (tracked exactly, not the canonical one).
@@ -323,7 +325,9 @@ ckks_status ckks_profile_enable(ckks_ctx *ctx, int on);
 /*
  * Opt-in operation trace for the cost model (enabling clears it): one text
  * line "op level B" per primitive executed (op in hmult, rescale, rotate,
- * mul_scalar, add, sub, add_const, drop, copy), in execution order.
+ * rotate_hoisted, mul_scalar, mul_plain, add, sub, add_const, drop, copy,
+ * mod_raise, bootstrap), in execution order; a bootstrap is one line (its
+ * internal operations are not listed).
  * ckks_trace_read copies at most cap-1 bytes plus a terminating zero and
  * returns the size needed (including the zero).
  */

@@ -2132,9 +2132,10 @@ orc_ct *orc_bootstrap(orc_ctx *c, const orc_ct *a, int64_t M) {
  *   if literal: y = BTS(y)
  *   repeat n times: [lazy policy: y = BTS(y) when l_y < 2]
  *                   y = NewtonStep(y, ct_x)
- * Pre-BTS (the paper's c = 1): when x has fewer than cheb_depth(d) + 1
- * levels (the affine map and the Chebyshev tree) or fewer than 3 (ct_x needs
- * 2 for Newton), x is bootstrapped first, with message bound 16 ceil(b).
+ * Pre-BTS (the paper's c = 1): when asked for (pre_bts), or when x has fewer
+ * than cheb_depth(d) + 1 levels (the affine map and the Chebyshev tree) or
+ * fewer than 3 (ct_x needs 2 for Newton), x is bootstrapped first, with
+ * message bound 16 ceil(b).
  * x itself is never bootstrapped otherwise (the c = 0 path).  y is
  * bootstrapped with message bound bts_bound (0: 16 ceil(1 / sqrt(a)), y ~
  * 1/sqrt(x) <= 1/sqrt(a)); the factor 16 keeps the message well inside the
@@ -2146,16 +2147,16 @@ orc_ct *orc_bootstrap(orc_ctx *c, const orc_ct *a, int64_t M) {
  * so x keeps the precision of its own scale.
  */
 orc_ct *orc_invsqrt(orc_ctx *c, const orc_ct *x, int d, int iters, double a, double b, int literal,
-                    int64_t bts_bound) {
+                    int64_t bts_bound, int pre_bts) {
     double *cf = malloc(sizeof(double) * (d + 1));
     if (d < 1 || iters < 0 || orc_cheb_coeffs_invsqrt(d, a, b, cf) != 0) {
         free(cf); set_err("bad degree / iterations / interval"); return NULL;
     }
     orc_ct *xb = NULL;
     const int64_t My = bts_bound > 0 ? bts_bound : 16 * (int64_t)ceil(1.0 / sqrt(a));
-    if (x->level < cheb_depth(d) + 1 || x->level < 3) {
+    if (pre_bts || x->level < cheb_depth(d) + 1 || x->level < 3) {
         if (!c->bts) {
-            if (x->level < 2) { free(cf); set_err("level"); return NULL; }
+            if (pre_bts || x->level < 2) { free(cf); set_err("level"); return NULL; }
         } else {
             xb = orc_bootstrap(c, x, 16 * (int64_t)ceil(b));
             if (!xb) { free(cf); return NULL; }

@@ -87,7 +87,7 @@ def lib():
         "orc_cheb_eval": (vp, [vp, vp, dblp, C.c_int, C.c_double, C.c_double]),
         "orc_newton_step": (vp, [vp, vp, vp]),
         "orc_newton_step_ex": (vp, [vp, vp, vp, C.c_int]),
-        "orc_invsqrt": (vp, [vp, vp, C.c_int, C.c_int, C.c_double, C.c_double, C.c_int, C.c_int64]),
+        "orc_invsqrt": (vp, [vp, vp, C.c_int, C.c_int, C.c_double, C.c_double, C.c_int, C.c_int64, C.c_int]),
         "orc_bootstrap": (vp, [vp, vp, C.c_int64]),
         "orc_ctx_create_bts": (vp, [C.c_int, C.c_int, C.c_int, C.c_int, C.c_int, C.c_int, C.c_int, C.c_int,
                                     C.c_int, C.c_double, C.c_int, C.c_int, C.c_int]),
@@ -337,8 +337,9 @@ class Context:
     def newton_step(self, y, cx, raw_x=False):
         return Ct(self, lib().orc_newton_step_ex(self.ptr, y.ptr, cx.ptr, int(raw_x)))
 
-    def invsqrt(self, x, degree, iters, a, b, literal=False, bts_bound=0):
-        return Ct(self, lib().orc_invsqrt(self.ptr, x.ptr, degree, iters, a, b, int(literal), int(bts_bound)))
+    def invsqrt(self, x, degree, iters, a, b, literal=False, bts_bound=0, pre_bts=False):
+        return Ct(self, lib().orc_invsqrt(self.ptr, x.ptr, degree, iters, a, b, int(literal), int(bts_bound),
+                                          int(pre_bts)))
 
     # -- bootstrapping -------------------------------------------------------
     def bts_config(self, K=25.0, r=4, degree=31):

@@ -32,7 +32,7 @@ class Params(C.Structure):
 
 
 class InvsqrtOpts(C.Structure):
-    _fields_ = [("a", C.c_double), ("b", C.c_double), ("literal", C.c_int32), ("reserved", C.c_int32),
+    _fields_ = [("a", C.c_double), ("b", C.c_double), ("literal", C.c_int32), ("pre_bts", C.c_int32),
                 ("bts_bound", C.c_int64)]
 
 
@@ -326,12 +326,12 @@ class Context:
     def mul_monomial(self, a, k):
         return self._ct(lib().ckks_mul_monomial, a.ptr, int(k))
 
-    def invsqrt(self, x, degree, iters, a=2.0 ** -10, b=1.0, literal=False, bts_bound=0):
-        o = InvsqrtOpts(a, b, int(literal), 0, int(bts_bound))
+    def invsqrt(self, x, degree, iters, a=2.0 ** -10, b=1.0, literal=False, bts_bound=0, pre_bts=False):
+        o = InvsqrtOpts(a, b, int(literal), int(pre_bts), int(bts_bound))
         return self._ct(lib().ckks_invsqrt_ex, x.ptr, degree, iters, C.byref(o))
 
-    def invsqrt_batch(self, xs, degree, iters, a=2.0 ** -10, b=1.0, literal=False, bts_bound=0):
-        o = InvsqrtOpts(a, b, int(literal), 0, int(bts_bound))
+    def invsqrt_batch(self, xs, degree, iters, a=2.0 ** -10, b=1.0, literal=False, bts_bound=0, pre_bts=False):
+        o = InvsqrtOpts(a, b, int(literal), int(pre_bts), int(bts_bound))
         arr = (vp * len(xs))(*[x.ptr for x in xs])
         outs = (vp * len(xs))()
         self._chk(lib().ckks_invsqrt_batch(self.ptr, arr, len(xs), degree, iters, C.byref(o), outs))

@@ -192,6 +192,7 @@ struct ckks_ctx {
     bool prof_on = false;
     // opt-in operation trace (op name, level, batch) for the cost model
     bool trace_on = false;
+    int trace_mute = 0;           // > 0 inside bootstrapping (traced as one op)
     std::string trace;
     std::map<std::string, ProfFamily> prof;
     std::vector<hipEvent_t> ev_free;
@@ -264,7 +265,7 @@ int bitrev(int x, int bits) {
 }
 
 void trace_op(ckks_ctx *c, const char *op, int level, int B) {
-    if (!c->trace_on) return;
+    if (!c->trace_on || c->trace_mute > 0) return;
     c->trace += op;
     c->trace += ' ';
     c->trace += std::to_string(level);
@@ -1098,6 +1099,11 @@ Ct op_bootstrap(ckks_ctx *c, const ckks_ct *a, int64_t bound) {
     const double Fd = std::rint(s0 / (a->scale * (double)bound));
     if (!(Fd >= 1.0 && Fd < 1099511627776.0)) fail(CKKS_E_RANGE, "input scale out of range for bootstrapping");
     trace_op(c, "bootstrap", a->level, a->B);
+    struct Mute {
+        ckks_ctx *c;
+        explicit Mute(ckks_ctx *c_) : c(c_) { ++c->trace_mute; }
+        ~Mute() { --c->trace_mute; }
+    } mute(c);
     Ct a0 = op_drop(c, a, 0);
     Ct aF = op_mul_int(c, a0.get(), (int64_t)Fd, a0->scale);
     a0.reset();
@@ -1211,8 +1217,8 @@ std::vector<int> bts_rotations(const ckks_ctx *c) {
 }
 
 // CryptoInvSqrt with the bootstrapping policy: Pre-BTS of x (paper's c = 1)
-// when it cannot carry the Chebyshev step or ct_x; otherwise x is never
-// bootstrapped.  Lazy bootstrapping of y before a Newton step that lacks 2
+// when asked for (opts.pre_bts) or when x cannot carry the Chebyshev step or
+// ct_x; otherwise x is never bootstrapped.  Lazy bootstrapping of y before a Newton step that lacks 2
 // levels (or right after the Chebyshev step with `literal`).
 Ct op_invsqrt(ckks_ctx *c, const ckks_ct *x0, int degree, int iters, const ckks_invsqrt_opts &o) {
     if (degree < 1 || iters < 0) fail(CKKS_E_PARAM, "bad degree / iterations");
@@ -1220,8 +1226,9 @@ Ct op_invsqrt(ckks_ctx *c, const ckks_ct *x0, int degree, int iters, const ckks_
     const int64_t My = o.bts_bound > 0 ? o.bts_bound : 16 * (int64_t)std::ceil(1.0 / std::sqrt(o.a));
     const ckks_ct *x = x0;
     Ct xb;
-    if (x->level < cheb_depth(degree) + 1 || x->level < 3) {
+    if (o.pre_bts || x->level < cheb_depth(degree) + 1 || x->level < 3) {
         if (!c->bts) {
+            if (o.pre_bts) fail(CKKS_E_NOKEY, "Pre-BTS needs bootstrapping");
             if (x->level < 2) fail(CKKS_E_LEVEL, "input needs at least 2 levels");
         } else {
             xb = op_bootstrap(c, x, 16 * (int64_t)std::ceil(o.b));
@@ -1696,7 +1703,7 @@ static ckks_invsqrt_opts default_opts() {
     o.a = 0.0009765625;   // 2^-10
     o.b = 1.0;
     o.literal = 0;
-    o.reserved = 0;
+    o.pre_bts = 0;
     o.bts_bound = 0;
     return o;
 }

@@ -1,11 +1,12 @@
 """Serving loop for encrypted inverse square roots with continuous batching.
 
 Requests arrive over time; each carries 1..32 ciphertexts at one input level
-and an MRE target, which the tuning table maps to a (degree, iterations)
-pair.  The scheduler admits arrived requests while their estimated device
-working set fits the memory budget, groups the admitted ciphertexts of all
-requests by (level, degree, iterations) and runs the oldest group as one
-batched launch sequence (up to `max_batch` ciphertexts).  Requests that arrive
+and an MRE target, which the tuning table maps to a (degree, Pre-BTS
+indicator c, iterations) setting.  The scheduler admits arrived requests while
+their estimated device working set fits the memory budget, groups the
+admitted ciphertexts of all requests by (level, degree, c, iterations) and
+runs the oldest group as one batched launch sequence (up to `max_batch`
+ciphertexts), bootstrapping keys resident in HBM.  Requests that arrive
 while a batch is on the GPU are admitted at the next scheduling round, so work
 from different requests shares launches.  Every ciphertext's result is the same
 alone and in the mix: batch members never interact.
@@ -28,15 +29,17 @@ class Request:
     target: float
     degree: int = 0
     iters: int = 0
+    c: int = 0
     outs: dict = field(default_factory=dict)
     admitted: float = None
     done: float = None
 
 
 def lookup(table, level, target):
-    """(degree, iters) for (level, target) from a tuning table
-    {level: {target: {"degree": d, "iters": i}}}; falls back to the closest
-    tuned level not above `level`, then to the strictest target."""
+    """(degree, c, iters) for (level, target) from a tuning table
+    {level: {target: {"degree": d, "c": c, "iters": i}}} (c defaults to 0);
+    falls back to the closest tuned level not above `level`, then to the
+    strictest target."""
     lv = str(level)
     if lv not in table:
         below = [int(k) for k in table if int(k) <= level]
@@ -48,7 +51,7 @@ def lookup(table, level, target):
     ent = row.get(key)
     if ent is None:
         ent = next(v for k, v in sorted(row.items(), key=lambda kv: float(kv[0])) if v is not None)
-    return ent["degree"], ent["iters"]
+    return ent["degree"], ent.get("c", 0), ent["iters"]
 
 
 class Server:
@@ -72,7 +75,7 @@ class Server:
         return len(req.cts) * 2 * (req.level + 1) * self.ctx.N * 8 * self.ct_factor
 
     def submit(self, req):
-        req.degree, req.iters = lookup(self.table, req.level, req.target)
+        req.degree, req.c, req.iters = lookup(self.table, req.level, req.target)
         self.queue.append(req)
 
     def _admit(self, now):
@@ -93,16 +96,16 @@ class Server:
         if not self.active:
             return 0
         oldest = min(self.active, key=lambda r: r.arrival)
-        key = (oldest.level, oldest.degree, oldest.iters)
+        key = (oldest.level, oldest.degree, oldest.c, oldest.iters)
         work = []                          # (request, ct index)
         for r in sorted(self.active, key=lambda r: r.arrival):
-            if (r.level, r.degree, r.iters) != key:
+            if (r.level, r.degree, r.c, r.iters) != key:
                 continue
             for k in range(len(r.cts)):
                 if k not in r.outs and len(work) < self.max_batch:
                     work.append((r, k))
         cts = [r.cts[k] for r, k in work]
-        outs = self.ctx.invsqrt_batch(cts, key[1], key[2], a=self.lo, b=self.hi)
+        outs = self.ctx.invsqrt_batch(cts, key[1], key[3], a=self.lo, b=self.hi, pre_bts=bool(key[2]))
         self.ctx.sync()
         t = clock()
         for (r, k), y in zip(work, outs):
@@ -142,12 +145,12 @@ def run_one_at_a_time(ctx, table, requests, lo=2.0 ** -10, hi=1.0):
     t0 = time.perf_counter()
     clock = lambda: time.perf_counter() - t0
     for r in sorted(requests, key=lambda r: r.arrival):
-        r.degree, r.iters = lookup(table, r.level, r.target)
+        r.degree, r.c, r.iters = lookup(table, r.level, r.target)
         wait = r.arrival - clock()
         if wait > 0:
             time.sleep(wait)
         r.admitted = clock()
-        outs = ctx.invsqrt_batch(r.cts, r.degree, r.iters, a=lo, b=hi)
+        outs = ctx.invsqrt_batch(r.cts, r.degree, r.iters, a=lo, b=hi, pre_bts=bool(r.c))
         ctx.sync()
         r.outs = dict(enumerate(outs))
         r.done = clock()
@@ -163,14 +166,18 @@ def summarize(requests):
             "mean_latency_s": float(lat.mean()), "ciphertexts_per_s": n_ct / span, "span_s": span}
 
 
-DEFAULT_TABLE = {"13": {"1e-06": {"degree": 15, "iters": 3}, "1e-07": {"degree": 31, "iters": 3},
-                        "3.1e-08": {"degree": 31, "iters": 3}}}
+DEFAULT_TABLE = {"7": {"1e-06": {"degree": 31, "c": 0, "iters": 3}, "1e-07": {"degree": 31, "c": 0, "iters": 3},
+                       "3.1e-08": {"degree": 31, "c": 0, "iters": 3}}}
+P16B = dict(log_n=16, max_level=7, num_special=7, digit_size=8, hamming_weight=192, bts=(3, 10, 3, 52))
+EVALMOD = (25.0, 4, 31)
 
 
 def main(argv=None):
-    """Serving sweep at N = 2^16: Poisson arrivals at each rate, request sizes
-    Geometric(0.25) truncated to [1, 32], levels and MRE targets drawn per
-    request; continuous batching versus one request at a time."""
+    """Serving sweep at N = 2^16 on the bootstrapping parameter set (relin,
+    rotation and conjugation keys resident): Poisson arrivals at each rate,
+    request sizes Geometric(0.25) truncated to [1, 32], levels in [3, 7] and
+    MRE targets drawn per request; continuous batching versus one request at a
+    time."""
     import argparse
     import json
 
@@ -181,7 +188,7 @@ def main(argv=None):
     ap = argparse.ArgumentParser()
     ap.add_argument("--rates", default="10,40,160")
     ap.add_argument("--requests", type=int, default=48)
-    ap.add_argument("--levels", default="13,17,21")
+    ap.add_argument("--levels", default="3,4,5,6,7")
     ap.add_argument("--table", default=None, help="tuning JSON from paper_2606_10477_amd.tune")
     ap.add_argument("--max-batch", type=int, default=64)
     ap.add_argument("--out", default=None)
@@ -191,8 +198,9 @@ def main(argv=None):
         with open(args.table) as f:
             table = json.load(f)["table"]
     torch.cuda.set_device(0)
-    ctx = ckks.Context(log_n=16, max_level=27, num_special=7, digit_size=10, hamming_weight=192)
-    ctx.keygen(9)
+    ctx = ckks.Context(**P16B)
+    ctx.bts_setup(*EVALMOD)
+    ctx.keygen(9, ctx.bts_galois())
     levels = [int(v) for v in args.levels.split(",")]
     out = {"workload": "CryptoInvSqrt serving at N=2^16, Poisson arrivals, sizes Geometric(0.25) in [1,32], "
                        f"levels {levels}, targets 1e-6/1e-7/3.1e-8", "runs": []}

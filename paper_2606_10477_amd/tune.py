@@ -1,12 +1,15 @@
 """Provision the degree-versus-iterations table on this GPU (paper §4.2, Alg. 2 and 3).
 
-Runs the encrypted inverse square root with the tuner's own keys over a grid
-of Chebyshev degrees x Newton iterations at several input levels, measures the
-MRE against FP64 and the time of each configuration, profiles the unit cost of
-every primitive at every level, predicts each configuration's time from its
-operation trace, and selects, per (level, MRE target), the pair with minimum
-predicted time.  Writes a JSON report (the tuning table plus predicted versus
-measured times and the speedup over a fixed configuration).
+Runs the encrypted inverse square root with the tuner's own keys on the
+bootstrapping parameter set over a grid of Chebyshev degrees x Newton
+iterations x Pre-BTS indicator (the cases Alg. 3 allows per input level),
+measures the MRE against FP64 and the time of each setting, profiles the unit
+cost of every primitive at every level and of a bootstrap, predicts each
+setting's time from its operation trace, and selects, per (level, MRE
+target), the (degree, c, iterations) with minimum predicted time.  Also runs
+Alg. 2 / Alg. 3 on the measured curves (u1 accuracy-first, u2 speed-first per
+level).  Writes a JSON report (tables, predicted versus measured times, the
+speedup over the fixed configuration (31, 3)).
 
     python -m paper_2606_10477_amd.tune --out tuning.json
 """
@@ -18,50 +21,63 @@ import time
 
 import numpy as np
 
-P16 = dict(log_n=16, max_level=27, num_special=7, digit_size=10, hamming_weight=192)
+P16B = dict(log_n=16, max_level=7, num_special=7, digit_size=8, hamming_weight=192, bts=(3, 10, 3, 52))
+EVALMOD = (25.0, 4, 31)
 
 
 def run(levels, degrees, iters, targets, lo, hi, batch, reps, fixed, tuner_seed=777, quiet=False):
+    import math
+
     import torch
     from . import ckks, inputs, tuner
 
     torch.cuda.set_device(0)
     t_start = time.perf_counter()
-    ctx = ckks.Context(**P16)
-    ctx.keygen(tuner_seed)              # the tuner's own keys, not a client's
+    ctx = ckks.Context(**P16B)
+    ctx.bts_setup(*EVALMOD)
+    ctx.keygen(tuner_seed, ctx.bts_galois())      # the tuner's own keys, not a client's
     x = inputs.log_uniform(ctx.n, lo, hi, 11)
     cts = {l: ctx.encrypt(x, l, 2.0 ** 50, 12 + l) for l in levels}
-    lv = sorted(set(range(0, max(levels) + 1)))
-    costs = tuner.profile_unit_costs(ctx, lv, batch=batch, reps=reps)
+    # Alg. 3's cases with l_BTS = 0, l_afterBTS = l_max = the chain's top computation level
+    cases = tuner.level_cases(0, ctx.l_after, ctx.l_after)
+    cs = {l: cases.get(l, [0]) or [0] for l in levels}
+    bound = 16 * int(math.ceil(1.0 / math.sqrt(lo)))
+    costs = tuner.profile_unit_costs(ctx, list(range(0, ctx.l_after + 1)), batch=batch, reps=reps, bts_bound=bound)
     if not quiet:
-        print(f"profiled {len(costs)} unit costs", file=sys.stderr, flush=True)
-    rows = tuner.sweep(ctx, x, cts, degrees, iters, lo, hi, batch=batch, reps=reps, costs=costs)
+        print(f"profiled {len(costs)} unit costs (bootstrap {costs[('bootstrap', tuner.BTS_ANY_LEVEL)] * 1e3:.1f} ms)",
+              file=sys.stderr, flush=True)
+    rows = tuner.sweep(ctx, x, cts, degrees, iters, lo, hi, batch=batch, reps=reps, costs=costs, cs_by_level=cs)
     table = {}
     for l in levels:
         for tgt in targets:
             r = tuner.select(rows, tgt, l)
             table.setdefault(str(l), {})[f"{tgt:.3g}"] = None if r is None else \
-                {"degree": r["d"], "iters": r["i"], "mre": r["m"], "t_pred": r["t_pred"], "t_meas": r["t"]}
+                {"degree": r["d"], "c": r["c"], "iters": r["i"], "bts": r["bts"], "mre": r["m"],
+                 "t_pred": r["t_pred"], "t_meas": r["t"]}
     fixed_rows = {l: next((r for r in rows if r["level"] == l and r["d"] == fixed[0] and r["i"] == fixed[1]
-                           and r.get("ok")), None) for l in levels}
+                           and r["c"] == 0 and r.get("ok")), None) for l in levels}
     speedup = {}
     for l in levels:
         best = tuner.select(rows, targets[-1], l)
         fr = fixed_rows[l]
         if best and fr:
-            speedup[str(l)] = {"fixed": [fixed[0], fixed[1]], "fixed_t": fr["t"], "fixed_mre": fr["m"],
-                               "tuned": [best["d"], best["i"]], "tuned_t": best["t"], "tuned_mre": best["m"],
-                               "speedup": fr["t"] / best["t"]}
+            speedup[str(l)] = {"fixed": [fixed[0], 0, fixed[1]], "fixed_t": fr["t"], "fixed_mre": fr["m"],
+                               "tuned": [best["d"], best["c"], best["i"]], "tuned_t": best["t"],
+                               "tuned_mre": best["m"], "speedup": fr["t"] / best["t"]}
+    D, R = tuner.alg3_from_rows(rows)
     ok = [r for r in rows if r.get("ok")]
     err = [abs(r["t_pred"] - r["t"]) / r["t"] for r in ok]
     report = {
-        "params": "N=2^16, q0 60-bit + 27 x 40-bit, 7 x 60-bit special, dnum 3, h 192",
+        "params": "N=2^16, log2 QP 1556: q0 60-bit, 10 x 40-bit, 13 x 52-bit, 7 x 60-bit special, dnum 3, h 192; "
+                  "l_BTS 0, l_afterBTS = l_max 7",
         "input": f"x log-uniform in [{lo}, {hi}], encrypted at scale 2^50",
-        "batch": batch, "grid": {"degrees": degrees, "iters": iters, "levels": levels},
+        "batch": batch, "grid": {"degrees": degrees, "iters": iters, "levels": levels, "c": cs},
         "targets": targets, "table": table, "speedup_vs_fixed": speedup,
+        "alg3": {str(l): {"u1_accuracy_first": list(R[l][0]), "u2_speed_first": list(R[l][1]),
+                          "per_degree": D[l]} for l in sorted(R)},
         "prediction_rel_error": {"median": float(np.median(err)), "max": float(np.max(err))} if err else None,
-        "rows": rows, "tuning_wall_s": time.perf_counter() - t_start,
         "unit_costs": {f"{op}@{l}": v for (op, l), v in sorted(costs.items(), key=lambda kv: (kv[0][1], kv[0][0]))},
+        "rows": rows, "tuning_wall_s": time.perf_counter() - t_start,
     }
     ctx.close()
     return report
@@ -70,7 +86,7 @@ def run(levels, degrees, iters, targets, lo, hi, batch, reps, fixed, tuner_seed=
 def main(argv=None):
     ap = argparse.ArgumentParser()
     ap.add_argument("--out", default="gpurun_out/tuning.json")
-    ap.add_argument("--levels", default="13,17,21,27")
+    ap.add_argument("--levels", default="3,4,5,6,7")
     ap.add_argument("--degrees", default="7,15,31,63,127")
     ap.add_argument("--iters", default="1,2,3,4,5,6")
     ap.add_argument("--targets", default="1e-6,1e-7,3.1e-8")
@@ -84,6 +100,7 @@ def main(argv=None):
     with open(args.out, "w") as f:
         json.dump(rep, f, indent=1)
     summary = {"table": rep["table"], "speedup_vs_fixed": rep["speedup_vs_fixed"],
+               "alg3": {l: {k: v for k, v in e.items() if k != "per_degree"} for l, e in rep["alg3"].items()},
                "prediction_rel_error": rep["prediction_rel_error"], "tuning_wall_s": rep["tuning_wall_s"]}
     print(json.dumps(summary), flush=True)
 

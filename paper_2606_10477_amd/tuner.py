@@ -104,7 +104,8 @@ def mre(values, ref):
 # --------------------------------------------------------------------------
 # Cost model
 # --------------------------------------------------------------------------
-OPS = ("hmult", "rescale", "rotate", "mul_scalar", "add", "sub", "add_const", "drop", "copy")
+OPS = ("hmult", "rescale", "rotate", "mul_scalar", "add", "sub", "add_const", "drop", "copy", "bootstrap")
+BTS_ANY_LEVEL = -1     # a bootstrap costs the same from any input level (it starts at level 0)
 
 
 def _words(ctx, level, B, seed):
@@ -112,10 +113,25 @@ def _words(ctx, level, B, seed):
     return [inputs.uniform_words((2, level + 1, ctx.N), ctx.primes[:level + 1], seed + b) for b in range(B)]
 
 
-def profile_unit_costs(ctx, levels, batch=1, reps=5, rot_step=None):
+def profile_unit_costs(ctx, levels, batch=1, reps=5, rot_step=None, bts_bound=None):
     """Median wall time (s, device-synchronised) of each primitive at each
-    level, on `batch` ciphertexts of uniform words."""
+    level, on `batch` ciphertexts of uniform words.  With bts_bound, also the
+    bootstrap (message bound bts_bound), stored under level BTS_ANY_LEVEL."""
     costs = {}
+    if bts_bound is not None:
+        lvl = min(levels)
+        singles = [ctx.ct_import(w, lvl, 2.0 ** 40) for w in _words(ctx, lvl, batch, 2000)]
+        a = ctx.pack(singles) if batch > 1 else singles[0]
+        ctx.bootstrap(a, bts_bound)
+        ctx.sync()
+        ts = []
+        for _ in range(reps):
+            t0 = time.perf_counter()
+            r = ctx.bootstrap(a, bts_bound)
+            ctx.sync()
+            ts.append(time.perf_counter() - t0)
+            del r
+        costs[("bootstrap", BTS_ANY_LEVEL)] = float(np.median(ts))
     for lvl in levels:
         singles = [ctx.ct_import(w, lvl, 2.0 ** 40) for w in _words(ctx, lvl, batch, 1000 + lvl)]
         a = ctx.pack(singles) if batch > 1 else singles[0]
@@ -151,7 +167,7 @@ def predict(trace, costs):
     total = 0.0
     missing = set()
     for op, lvl, _B in trace:
-        c = costs.get((op, lvl))
+        c = costs.get((op, BTS_ANY_LEVEL if op == "bootstrap" else lvl))
         if c is None:
             missing.add((op, lvl))
             continue
@@ -162,55 +178,86 @@ def predict(trace, costs):
 # --------------------------------------------------------------------------
 # Sweep and selection (one MI355X, encrypted runs with the tuner's own keys)
 # --------------------------------------------------------------------------
-def sweep(ctx, x, ct_by_level, degrees, iters, lo, hi, batch=1, reps=3, costs=None):
-    """For each input level and (degree, iterations): MRE of the decrypted
-    result against FP64 1/sqrt(x), measured time (median of `reps`, all
-    `batch` ciphertexts), the operation trace and the predicted time.  Pairs
-    that do not fit the levels are skipped (recorded with ok=False)."""
-    from .ckks import CkksError
+def sweep(ctx, x, ct_by_level, degrees, iters, lo, hi, batch=1, reps=3, costs=None, cs_by_level=None):
+    """For each input level, Pre-BTS indicator c (cs_by_level[level], default
+    [0]) and (degree, iterations): MRE of the decrypted result against FP64
+    1/sqrt(x), measured time (median of `reps`, all `batch` ciphertexts), the
+    operation trace (bootstraps counted) and the predicted time.  Settings
+    that do not fit the levels are recorded with ok=False."""
     ref = 1.0 / np.sqrt(x)
     rows = []
     for lvl, ct in ct_by_level.items():
-        cts = [ct] * batch
-        for d in degrees:
-            for it in iters:
-                row = {"level": lvl, "d": d, "i": it, "c": 0}
-                try:
-                    ctx.trace(True)
-                    y = ctx.invsqrt(ct, d, it, a=lo, b=hi) if batch == 1 else \
-                        ctx.invsqrt_batch(cts, d, it, a=lo, b=hi)[0]
-                    tr = ctx.trace_read()
-                    ctx.trace(False)
-                except CkksError:
-                    ctx.trace(False)
-                    row["ok"] = False
-                    rows.append(row)
-                    continue
-                row["ok"] = True
-                row["m"] = mre(ctx.decrypt(y).real, ref)
-                row["out_level"] = y.level
-                ts = []
-                for _ in range(reps):
-                    ctx.sync()
-                    t0 = time.perf_counter()
-                    if batch == 1:
-                        ctx.invsqrt(ct, d, it, a=lo, b=hi)
-                    else:
-                        ctx.invsqrt_batch(cts, d, it, a=lo, b=hi)
-                    ctx.sync()
-                    ts.append(time.perf_counter() - t0)
-                row["t"] = float(np.median(ts)) / batch
-                row["ops"] = len(tr)
-                if costs is not None:
-                    row["t_pred"] = predict(tr, costs)[0]
-                rows.append(row)
+        for c in (cs_by_level or {}).get(lvl, [0]):
+            for d in degrees:
+                for it in iters:
+                    rows.append(_measure(ctx, ct, lvl, c, d, it, lo, hi, batch, reps, costs, ref))
     return rows
 
 
+def _measure(ctx, ct, lvl, c, d, it, lo, hi, batch, reps, costs, ref):
+    from .ckks import CkksError
+    cts = [ct] * batch
+
+    def run():
+        if batch == 1:
+            return ctx.invsqrt(ct, d, it, a=lo, b=hi, pre_bts=bool(c))
+        return ctx.invsqrt_batch(cts, d, it, a=lo, b=hi, pre_bts=bool(c))[0]
+
+    row = {"level": lvl, "d": d, "i": it, "c": c}
+    try:
+        ctx.trace(True)
+        y = run()
+        tr = ctx.trace_read()
+        ctx.trace(False)
+    except CkksError:
+        ctx.trace(False)
+        row["ok"] = False
+        return row
+    row["ok"] = True
+    row["m"] = mre(ctx.decrypt(y).real, ref)
+    row["out_level"] = y.level
+    ts = []
+    for _ in range(reps):
+        ctx.sync()
+        t0 = time.perf_counter()
+        run()
+        ctx.sync()
+        ts.append(time.perf_counter() - t0)
+    row["t"] = float(np.median(ts)) / batch
+    row["ops"] = len(tr)
+    row["bts"] = sum(1 for op in tr if op[0] == "bootstrap")
+    if costs is not None:
+        row["t_pred"] = predict(tr, costs)[0]
+    return row
+
+
 def select(rows, target, level, key="t_pred"):
-    """The (degree, iterations) at `level` with MRE <= target at minimum
-    `key` time (ties: lower MRE, smaller degree); None if none qualifies."""
+    """The (degree, c, iterations) at `level` with MRE <= target at minimum
+    `key` time (ties: lower MRE, fewer bootstraps, smaller degree); None if
+    none qualifies."""
     ok = [r for r in rows if r.get("ok") and r["level"] == level and r["m"] <= target and key in r]
     if not ok:
         return None
-    return min(ok, key=lambda r: (r[key], r["m"], r["d"]))
+    return min(ok, key=lambda r: (r[key], r["m"], r.get("bts", 0), r["d"]))
+
+
+def alg3_from_rows(rows, delta=1.0, theta=1.0, key="t"):
+    """Alg. 3's table from sweep rows: for each (level, d, c) the iteration
+    curve M[1..i_max], T[1..i_max] (T is the time of the whole run up to that
+    iteration), Alg. 2 picks the iteration count, and optimize_params the
+    accuracy-first u1 and speed-first u2 per level.  Curves with a missing
+    iteration (infeasible settings) are skipped."""
+    by = {}
+    for r in rows:
+        if r.get("ok") and key in r:
+            by.setdefault((r["level"], r["d"], r["c"]), {})[r["i"]] = r
+    D = {}
+    for (lvl, d, c), its in sorted(by.items()):
+        n = max(its)
+        if sorted(its) != list(range(1, n + 1)):
+            continue
+        M = [its[i]["m"] for i in range(1, n + 1)]
+        T = [its[i][key] for i in range(1, n + 1)]
+        I, m, t = get_opt_iter(M, T, delta)
+        D.setdefault(lvl, []).append({"d": d, "c": c, "i": I, "m": m, "t": t})
+    return D, optimize_params(D, theta)

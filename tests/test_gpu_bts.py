@@ -119,17 +119,19 @@ def test_bootstrap_batch_equals_single(pair):
         same(y, g.bootstrap(c, 512))
 
 
-@pytest.mark.parametrize("degree,iters,level,literal", [(31, 3, 7, False), (7, 5, 7, False), (15, 3, 7, True),
-                                                        (31, 2, 4, False)])
-def test_invsqrt_with_bootstrapping_bit_exact(pair, degree, iters, level, literal):
+@pytest.mark.parametrize("degree,iters,level,literal,pre", [(31, 3, 7, False, False), (7, 5, 7, False, False),
+                                                            (15, 3, 7, True, False), (31, 2, 4, False, False),
+                                                            (15, 2, 5, False, True)])
+def test_invsqrt_with_bootstrapping_bit_exact(pair, degree, iters, level, literal, pre):
     """Lazy BTS of y (one or two bootstraps), the Alg.-1-literal BTS after the
-    Chebyshev step, and the Pre-BTS of x (level 4 < depth 6 + 1 for degree 31)."""
+    Chebyshev step, the Pre-BTS of x forced by its level (level 4 < depth 6 + 1
+    for degree 31) and asked for (c = 1 at level 5)."""
     g, o = pair
     lo, hi = 2.0 ** -10, 1.0
     x = inputs.log_uniform(g.n, lo, hi, 8)
     gc, oc = g.encrypt(x, level, 2.0 ** 50, 73), o.encrypt(x, level, 2.0 ** 50, 73)
-    gy = g.invsqrt(gc, degree, iters, lo, hi, literal=literal)
-    oy = o.invsqrt(oc, degree, iters, lo, hi, literal=literal)
+    gy = g.invsqrt(gc, degree, iters, lo, hi, literal=literal, pre_bts=pre)
+    oy = o.invsqrt(oc, degree, iters, lo, hi, literal=literal, pre_bts=pre)
     same(gy, oy)
     if (degree, iters, level) == (31, 3, 7):
         ref = 1 / np.sqrt(x)

@@ -15,8 +15,8 @@ class FakeCtx:
     def __init__(self):
         self.calls = []
 
-    def invsqrt_batch(self, cts, degree, iters, a=None, b=None):
-        self.calls.append((len(cts), degree, iters))
+    def invsqrt_batch(self, cts, degree, iters, a=None, b=None, pre_bts=False):
+        self.calls.append((len(cts), degree, iters) + ((1,) if pre_bts else ()))
         return [FakeCt(("y", c.tag, degree, iters)) for c in cts]
 
     def sync(self):
@@ -26,7 +26,8 @@ class FakeCtx:
 TABLE = {"13": {"1e-06": {"degree": 15, "iters": 2}, "1e-07": {"degree": 31, "iters": 2},
                 "3.1e-08": {"degree": 31, "iters": 3}},
          "17": {"1e-06": {"degree": 7, "iters": 3}, "1e-07": {"degree": 31, "iters": 2},
-                "3.1e-08": {"degree": 63, "iters": 2}}}
+                "3.1e-08": {"degree": 63, "iters": 2}},
+         "20": {"1e-06": {"degree": 15, "c": 1, "iters": 3}}}
 
 
 def mk(rid, t, n, level, target):
@@ -34,8 +35,9 @@ def mk(rid, t, n, level, target):
 
 
 def test_lookup_exact_and_fallback():
-    assert serve.lookup(TABLE, 13, 3.1e-8) == (31, 3)
-    assert serve.lookup(TABLE, 19, 1e-6) == (7, 3)       # closest tuned level below
+    assert serve.lookup(TABLE, 13, 3.1e-8) == (31, 0, 3)
+    assert serve.lookup(TABLE, 19, 1e-6) == (7, 0, 3)    # closest tuned level below
+    assert serve.lookup(TABLE, 20, 1e-6) == (15, 1, 3)   # Pre-BTS setting
     with pytest.raises(KeyError):
         serve.lookup(TABLE, 5, 1e-6)
 
@@ -55,6 +57,18 @@ def test_groups_share_one_batch_and_results_are_attributed():
         assert r.done == 1.0 and len(r.outs) == len(r.cts)
         for k, y in r.outs.items():
             assert y.tag == ("y", (r.rid, k), r.degree, r.iters)
+
+
+def test_pre_bts_setting_is_its_own_group():
+    ctx = FakeCtx()
+    srv = serve.Server(ctx, TABLE, max_batch=64, mem_budget=1 << 40)
+    for r in [mk(0, 0.0, 2, 20, 1e-6), mk(1, 0.5, 3, 13, 1e-6)]:
+        srv.submit(r)
+    clock = lambda: 1.0
+    assert srv.step(clock) == 2
+    assert ctx.calls[-1] == (2, 15, 3, 1)      # bootstraps x first
+    assert srv.step(clock) == 3
+    assert ctx.calls[-1] == (3, 15, 2)
 
 
 def test_max_batch_splits_and_request_completes_when_all_parts_done():

@@ -83,3 +83,19 @@ def test_select_meets_target_at_min_time():
     r = tuner.select(rows, 3.1e-8, 11)
     assert (r["d"], r["i"]) == (63, 2)
     assert tuner.select(rows, 1e-9, 11) is None
+
+
+def test_alg3_from_measured_rows():
+    """Alg. 2 on each (level, degree, c) curve, then Alg. 3's u1 / u2."""
+    rows = []
+    for i, (m, t) in enumerate([(2e-3, 1.0), (2e-5, 2.0), (3.0e-8, 3.0), (2.9e-8, 4.0)], 1):
+        rows.append({"level": 5, "d": 7, "c": 0, "i": i, "m": m, "t": t, "ok": True})
+    for i, (m, t) in enumerate([(1e-4, 2.5), (2.5e-6, 3.5)], 1):
+        rows.append({"level": 5, "d": 31, "c": 1, "i": i, "m": m, "t": t, "ok": True})
+    rows.append({"level": 5, "d": 63, "c": 0, "i": 1, "ok": False})
+    D, R = tuner.alg3_from_rows(rows, delta=1.0, theta=1.0)
+    # (7, 0): threshold from 2.9e-8 -> 3e-8, first within is i = 3 (t = 3.0)
+    # (31, 1): threshold from 2.5e-6 -> 3e-6, i = 2 (t = 3.5)
+    assert {(e["d"], e["c"], e["i"]) for e in D[5]} == {(7, 0, 3), (31, 1, 2)}
+    # accuracy-first: m_theta from 3.0e-8 -> 4e-8 keeps only (7, 0, 3); speed-first: fastest
+    assert R[5] == ((7, 0, 3), (7, 0, 3))
