@@ -130,8 +130,11 @@ class Ciphertext:
         self.free()
 
     def free(self):
-        if getattr(self, "ptr", None) and self.ctx.ptr:
-            lib().ckks_ct_free(self.ctx.ptr, self.ptr)
+        try:
+            if getattr(self, "ptr", None) and self.ctx.ptr:
+                lib().ckks_ct_free(self.ctx.ptr, self.ptr)
+        except TypeError:      # interpreter shutdown: the module's globals are gone
+            pass
         self.ptr = None
 
     @property

@@ -110,7 +110,10 @@ public:
     }
 
 private:
-    static constexpr size_t kCacheLimit = (size_t)64 << 30;   // bytes of free blocks kept for reuse
+    // bytes of free blocks kept for reuse: a bootstrapping batch of 64 cycles
+    // through tens of GB of distinct block sizes; trimming below that would
+    // free and re-allocate (with device synchronisation) on every step
+    static constexpr size_t kCacheLimit = (size_t)192 << 30;
     char *base_;
     size_t cap_, used_, cached_ = 0;
     std::map<size_t, std::vector<void *>> free_;   // block size -> free blocks

@@ -14,6 +14,7 @@ alone and in the mix: batch members never interact.
 The baseline ("one at a time") serves requests strictly in arrival order, each
 request's ciphertexts in one batched call, with no sharing across requests.
 """
+import os
 import time
 from dataclasses import dataclass, field
 
@@ -40,9 +41,10 @@ def lookup(table, level, target):
     {level: {target: {"degree": d, "c": c, "iters": i}}} (c defaults to 0);
     falls back to the closest tuned level not above `level`, then to the
     strictest target."""
+    usable = {k for k, row in table.items() if any(v is not None for v in row.values())}
     lv = str(level)
-    if lv not in table:
-        below = [int(k) for k in table if int(k) <= level]
+    if lv not in usable:
+        below = [int(k) for k in usable if int(k) <= level]
         if not below:
             raise KeyError(f"no tuned level <= {level}")
         lv = str(max(below))
@@ -188,13 +190,15 @@ def main(argv=None):
     ap = argparse.ArgumentParser()
     ap.add_argument("--rates", default="10,40,160")
     ap.add_argument("--requests", type=int, default=48)
-    ap.add_argument("--levels", default="3,4,5,6,7")
-    ap.add_argument("--table", default=None, help="tuning JSON from paper_2606_10477_amd.tune")
-    ap.add_argument("--max-batch", type=int, default=64)
+    ap.add_argument("--levels", default="5,6,7", help="input levels (those the tuning table can serve)")
+    ap.add_argument("--table", default=os.path.join(os.path.dirname(os.path.abspath(__file__)), "tuning_mi355x_bts.json"),
+                    help="tuning JSON from paper_2606_10477_amd.tune")
+    ap.add_argument("--max-batch", type=int, default=16,
+                    help="ciphertexts per launch sequence (bootstrapping throughput saturates near 8-16)")
     ap.add_argument("--out", default=None)
     args = ap.parse_args(argv)
     table = DEFAULT_TABLE
-    if args.table:
+    if args.table and os.path.exists(args.table):
         with open(args.table) as f:
             table = json.load(f)["table"]
     torch.cuda.set_device(0)
@@ -202,8 +206,9 @@ def main(argv=None):
     ctx.bts_setup(*EVALMOD)
     ctx.keygen(9, ctx.bts_galois())
     levels = [int(v) for v in args.levels.split(",")]
-    out = {"workload": "CryptoInvSqrt serving at N=2^16, Poisson arrivals, sizes Geometric(0.25) in [1,32], "
-                       f"levels {levels}, targets 1e-6/1e-7/3.1e-8", "runs": []}
+    out = {"workload": "CryptoInvSqrt serving at N=2^16 with bootstrapping keys resident, Poisson arrivals, "
+                       f"sizes Geometric(0.25) in [1,32], levels {levels}, targets 1e-6/1e-7/3.1e-8",
+           "table": args.table, "runs": []}
     for rate in [float(v) for v in args.rates.split(",")]:
         n = args.requests
         arr = inputs.poisson_arrivals(n, rate, 40)

@@ -38,6 +38,10 @@ def test_lookup_exact_and_fallback():
     assert serve.lookup(TABLE, 13, 3.1e-8) == (31, 0, 3)
     assert serve.lookup(TABLE, 19, 1e-6) == (7, 0, 3)    # closest tuned level below
     assert serve.lookup(TABLE, 20, 1e-6) == (15, 1, 3)   # Pre-BTS setting
+    nulls = {"3": {"1e-06": None}, "5": {"1e-06": {"degree": 7, "c": 0, "iters": 6}}}
+    assert serve.lookup(nulls, 5, 1e-6) == (7, 0, 6)
+    with pytest.raises(KeyError):
+        serve.lookup(nulls, 4, 1e-6)                     # level 3 has no feasible setting
     with pytest.raises(KeyError):
         serve.lookup(TABLE, 5, 1e-6)
 
