@@ -240,15 +240,24 @@ __device__ __forceinline__ void inv16(u64 v[16], const u64 *W, const u64 *Ws, in
 }
 
 // forward pass over rows (stages 0..7): reads src, writes dst
+// Grid of the N = 2^16 passes: blockIdx.x = 4096-word tile, blockIdx.y =
+// limb * npoly + poly (prime-major), so the same tile of the same prime for
+// consecutive polys runs on the same XCD and its twiddles come from L2.
+#define NTT16_INDEX(nlimb, npoly)                                                \
+    const uint32_t y_ = blockIdx.y;                                           \
+    const uint32_t lidx = y_ / (uint32_t)(npoly);                             \
+    const uint32_t pidx = y_ - lidx * (uint32_t)(npoly);                      \
+    const size_t row_off = ((size_t)pidx * (uint32_t)(nlimb) + lidx) << 16;
+
 __global__ void __launch_bounds__(256) k_ntt16_rows_fwd(u64 *dst, const u64 *src, size_t src_stride, int nlimb,
-                                                         LimbMap m, Tables T) {
+                                                         int npoly, LimbMap m, Tables T) {
     __shared__ u64 tile[256 * kPad];
-    const int limb = blockIdx.y;
-    const int pi = m.p[limb % nlimb];
+    NTT16_INDEX(nlimb, npoly)
+    const int pi = m.p[lidx];
     const u64 q = T.primes[pi].q;
     const u64 *W = T.fw + ((size_t)pi << 16), *Ws = T.fw_sh + ((size_t)pi << 16);
-    const u64 *in = src + (size_t)(limb / nlimb) * src_stride + ((size_t)(limb % nlimb) << 16);
-    u64 *out = dst + ((size_t)limb << 16);
+    const u64 *in = src + (size_t)pidx * src_stride + ((size_t)lidx << 16);
+    u64 *out = dst + row_off;
     const int c0 = blockIdx.x * 16;
     const int x = threadIdx.x & 15, y = threadIdx.x >> 4;
     u64 v[16];
@@ -269,13 +278,13 @@ __global__ void __launch_bounds__(256) k_ntt16_rows_fwd(u64 *dst, const u64 *src
 }
 
 // forward pass over 256-word blocks (stages 8..15), in place
-__global__ void __launch_bounds__(256) k_ntt16_blocks_fwd(u64 *data, int nlimb, LimbMap m, Tables T) {
+__global__ void __launch_bounds__(256) k_ntt16_blocks_fwd(u64 *data, int nlimb, int npoly, LimbMap m, Tables T) {
     __shared__ u64 tile[256 * kPad];
-    const int limb = blockIdx.y;
-    const int pi = m.p[limb % nlimb];
+    NTT16_INDEX(nlimb, npoly)
+    const int pi = m.p[lidx];
     const u64 q = T.primes[pi].q;
     const u64 *W = T.fw + ((size_t)pi << 16), *Ws = T.fw_sh + ((size_t)pi << 16);
-    u64 *d = data + ((size_t)limb << 16) + ((size_t)blockIdx.x << 12);
+    u64 *d = data + row_off + ((size_t)blockIdx.x << 12);
     const int blk0 = blockIdx.x * 16;   // global index of the first 256-block
     const int x = threadIdx.x & 15, y = threadIdx.x >> 4;
     u64 v[16];
@@ -301,15 +310,14 @@ __global__ void __launch_bounds__(256) k_ntt16_blocks_fwd(u64 *data, int nlimb, 
 
 // inverse pass over 256-word blocks (half-distances 1..128): reads src, writes dst
 __global__ void __launch_bounds__(256) k_ntt16_blocks_inv(u64 *dst, const u64 *src, size_t src_stride, int nlimb,
-                                                           LimbMap m, Tables T) {
+                                                           int npoly, LimbMap m, Tables T) {
     __shared__ u64 tile[256 * kPad];
-    const int limb = blockIdx.y;
-    const int pi = m.p[limb % nlimb];
+    NTT16_INDEX(nlimb, npoly)
+    const int pi = m.p[lidx];
     const u64 q = T.primes[pi].q;
     const u64 *W = T.iw + ((size_t)pi << 16), *Ws = T.iw_sh + ((size_t)pi << 16);
-    const u64 *s_in = src + (size_t)(limb / nlimb) * src_stride + ((size_t)(limb % nlimb) << 16) +
-                      ((size_t)blockIdx.x << 12);
-    u64 *d = dst + ((size_t)limb << 16) + ((size_t)blockIdx.x << 12);
+    const u64 *s_in = src + (size_t)pidx * src_stride + ((size_t)lidx << 16) + ((size_t)blockIdx.x << 12);
+    u64 *d = dst + row_off + ((size_t)blockIdx.x << 12);
     const int blk0 = blockIdx.x * 16;
     const int x = threadIdx.x & 15, y = threadIdx.x >> 4;
     u64 v[16];
@@ -334,13 +342,13 @@ __global__ void __launch_bounds__(256) k_ntt16_blocks_inv(u64 *dst, const u64 *s
 
 // inverse pass over rows (half-distances 256..32768, row distances 1..128), in
 // place, with the final multiplication by N^-1
-__global__ void __launch_bounds__(256) k_ntt16_rows_inv(u64 *data, int nlimb, LimbMap m, Tables T) {
+__global__ void __launch_bounds__(256) k_ntt16_rows_inv(u64 *data, int nlimb, int npoly, LimbMap m, Tables T) {
     __shared__ u64 tile[256 * kPad];
-    const int limb = blockIdx.y;
-    const int pi = m.p[limb % nlimb];
+    NTT16_INDEX(nlimb, npoly)
+    const int pi = m.p[lidx];
     const u64 q = T.primes[pi].q;
     const u64 *W = T.iw + ((size_t)pi << 16), *Ws = T.iw_sh + ((size_t)pi << 16);
-    u64 *d = data + ((size_t)limb << 16);
+    u64 *d = data + row_off;
     const int c0 = blockIdx.x * 16;
     const int x = threadIdx.x & 15, y = threadIdx.x >> 4;
     u64 v[16];
@@ -369,11 +377,13 @@ void ntt_oop(const Tables &T, uint64_t *dst, const uint64_t *src, size_t src_pol
     if (T.logN == 16) {
         dim3 grid(16, total);
         if (!inverse) {
-            hipLaunchKernelGGL(k_ntt16_rows_fwd, grid, dim3(256), 0, s, dst, src, src_poly_stride, nlimb, m, T);
-            hipLaunchKernelGGL(k_ntt16_blocks_fwd, grid, dim3(256), 0, s, dst, nlimb, m, T);
+            hipLaunchKernelGGL(k_ntt16_rows_fwd, grid, dim3(256), 0, s, dst, src, src_poly_stride, nlimb, npoly, m,
+                               T);
+            hipLaunchKernelGGL(k_ntt16_blocks_fwd, grid, dim3(256), 0, s, dst, nlimb, npoly, m, T);
         } else {
-            hipLaunchKernelGGL(k_ntt16_blocks_inv, grid, dim3(256), 0, s, dst, src, src_poly_stride, nlimb, m, T);
-            hipLaunchKernelGGL(k_ntt16_rows_inv, grid, dim3(256), 0, s, dst, nlimb, m, T);
+            hipLaunchKernelGGL(k_ntt16_blocks_inv, grid, dim3(256), 0, s, dst, src, src_poly_stride, nlimb, npoly, m,
+                               T);
+            hipLaunchKernelGGL(k_ntt16_rows_inv, grid, dim3(256), 0, s, dst, nlimb, npoly, m, T);
         }
         return;
     }
