@@ -302,6 +302,23 @@ ckks_status ckks_invsqrt_batch(ckks_ctx *ctx, const ckks_ct *const *xs, uint32_t
                                ckks_ct **outs);
 
 /*
+ * HIP graph of the CryptoInvSqrt chain for inputs shaped like x (same level,
+ * scale and batch size B).  Creation runs the chain once eagerly (so every
+ * table and pool block it needs exists), then captures it on the context's
+ * stream; the device memory it uses stays reserved for the graph until
+ * ckks_graph_destroy.  ckks_invsqrt_graph_run copies x into the graph's
+ * input, replays the graph (no per-kernel host launches) and returns a new
+ * ciphertext object with a copy of the result, identical to
+ * ckks_invsqrt_ex / ckks_invsqrt_batch on the same input.  A graph is bound
+ * to its context and stream; runs are stream-ordered.
+ */
+typedef struct ckks_graph ckks_graph;
+ckks_status ckks_invsqrt_graph_create(ckks_ctx *ctx, const ckks_ct *x, uint32_t degree, uint32_t iters,
+                                      const ckks_invsqrt_opts *opts, ckks_graph **out);
+ckks_status ckks_invsqrt_graph_run(ckks_ctx *ctx, ckks_graph *g, const ckks_ct *x, ckks_ct **out);
+void ckks_graph_destroy(ckks_ctx *ctx, ckks_graph *g);
+
+/*
  * Forward (inverse = 0) or inverse (inverse = 1) negacyclic NTT, in place, of
  * `n_limbs` device-resident limbs of N words each at `data` (limb-major).
  * prime_idx[i] (host array) is the index, in the chain q_0..q_L,p_0..p_{K-1},

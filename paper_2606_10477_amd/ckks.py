@@ -85,6 +85,10 @@ SIGNATURES = {
     "ckks_invsqrt_batch": (C.c_int, [vp, C.POINTER(vp), C.c_uint32, C.c_uint32, C.c_uint32,
                                      C.POINTER(InvsqrtOpts), C.POINTER(vp)]),
     "ckks_ntt_device": (C.c_int, [vp, C.c_void_p, C.c_uint32, u32p, C.c_int]),
+    "ckks_invsqrt_graph_create": (C.c_int, [vp, vp, C.c_uint32, C.c_uint32, C.POINTER(InvsqrtOpts),
+                                            C.POINTER(vp)]),
+    "ckks_invsqrt_graph_run": (C.c_int, [vp, vp, vp, C.POINTER(vp)]),
+    "ckks_graph_destroy": (None, [vp, vp]),
     "ckks_ct_pack": (C.c_int, [vp, C.POINTER(vp), C.c_uint32, C.POINTER(vp)]),
     "ckks_ct_unpack": (C.c_int, [vp, vp, C.POINTER(vp)]),
     "ckks_ct_count": (C.c_int32, [vp]),
@@ -155,6 +159,28 @@ class Ciphertext:
         out = np.zeros(shape, dtype=np.uint64)
         self.ctx._chk(lib().ckks_ct_export(self.ctx.ptr, self.ptr, _p(out, u64p)))
         return out
+
+
+class InvsqrtGraph:
+    """A captured CryptoInvSqrt chain (see ckks_invsqrt_graph_create)."""
+
+    def __init__(self, ctx, ptr):
+        self.ctx = ctx
+        self.ptr = ptr
+
+    def run(self, x):
+        return self.ctx._ct(lib().ckks_invsqrt_graph_run, self.ptr, x.ptr)
+
+    def close(self):
+        try:
+            if self.ptr and self.ctx.ptr:
+                lib().ckks_graph_destroy(self.ctx.ptr, self.ptr)
+        except TypeError:      # interpreter shutdown
+            pass
+        self.ptr = None
+
+    def __del__(self):
+        self.close()
 
 
 class Context:
@@ -362,6 +388,14 @@ class Context:
         by = C.c_double()
         self._chk(lib().ckks_profile_read(self.ptr, family.encode(), C.byref(n), C.byref(ms), C.byref(by)))
         return n.value, ms.value, by.value
+
+    def invsqrt_graph(self, x, degree, iters, a=2.0 ** -10, b=1.0, literal=False, bts_bound=0, pre_bts=False):
+        """Capture the chain for inputs shaped like x (level, scale, batch);
+        returns an InvsqrtGraph whose run(x) replays it."""
+        o = InvsqrtOpts(a, b, int(literal), int(pre_bts), int(bts_bound))
+        out = vp()
+        self._chk(lib().ckks_invsqrt_graph_create(self.ptr, x.ptr, degree, iters, C.byref(o), C.byref(out)))
+        return InvsqrtGraph(self, out.value)
 
     def pack(self, cts):
         arr = (vp * len(cts))(*[x.ptr for x in cts])

@@ -70,6 +70,7 @@ public:
             it->second.pop_back();
             cached_ -= it->first;
             if (it->second.empty()) free_.erase(it);
+            if (capturing_) captured_.insert(p);
             return p;
         }
         void *p = nullptr;
@@ -87,10 +88,46 @@ public:
             }
         }
         size_[p] = cls;
+        if (capturing_) captured_.insert(p);
         return p;
+    }
+    // HIP graph capture: every block handed out while capturing is recorded;
+    // at the end those blocks belong to the graph (its nodes address them on
+    // every replay) and are not handed out again until release_graph.
+    void begin_capture() {
+        capturing_ = true;
+        captured_.clear();
+    }
+    std::vector<void *> end_capture() {
+        capturing_ = false;
+        std::vector<void *> own(captured_.begin(), captured_.end());
+        for (void *p : own) {
+            graph_owned_.insert(p);
+            const size_t sz = size_.at(p);
+            auto it = free_.find(sz);
+            if (it == free_.end()) continue;
+            auto &v = it->second;
+            auto f = std::find(v.begin(), v.end(), p);
+            if (f == v.end()) continue;
+            v.erase(f);
+            cached_ -= sz;
+            if (v.empty()) free_.erase(it);
+        }
+        captured_.clear();
+        return own;
+    }
+    // blocks of a destroyed graph (no longer held by any buffer) back to the cache
+    void release_graph(const std::vector<void *> &own) {
+        for (void *p : own) {
+            graph_owned_.erase(p);
+            const size_t sz = size_.at(p);
+            free_[sz].push_back(p);
+            cached_ += sz;
+        }
     }
     void put(void *p) {
         if (!p) return;
+        if (graph_owned_.count(p)) return;   // the graph keeps it
         const size_t sz = size_.at(p);
         free_[sz].push_back(p);
         cached_ += sz;
@@ -99,7 +136,7 @@ public:
     // free every cached block (blocks still queued for use by earlier work on
     // the stream are safe: hipFree waits for outstanding work on the device)
     void trim() {
-        if (base_) return;
+        if (base_ || capturing_) return;
         for (auto &kv : free_)
             for (void *p : kv.second) {
                 size_.erase(p);
@@ -118,6 +155,8 @@ private:
     size_t cap_, used_, cached_ = 0;
     std::map<size_t, std::vector<void *>> free_;   // block size -> free blocks
     std::map<void *, size_t> size_;                // every block -> its size
+    bool capturing_ = false;
+    std::set<void *> captured_, graph_owned_;
 };
 
 struct Buf {
@@ -172,6 +211,7 @@ struct ckks_ctx {
     std::vector<u64> q;
     std::vector<double> ladder;
     hipStream_t stream;
+    hipStream_t cap_stream = nullptr;   // private stream for graph capture (created on first use)
     std::unique_ptr<Pool> pool;
     gpu::Tables T;
     Buf d_primes, d_fw, d_fwsh, d_iw, d_iwsh, d_ninv, d_ninvsh;
@@ -226,6 +266,7 @@ ckks_ctx::~ckks_ctx() {
     }
     bts.reset();
     mono.clear();
+    if (cap_stream) (void)hipStreamDestroy(cap_stream);
 }
 
 namespace {
@@ -1406,6 +1447,93 @@ void op_decrypt(ckks_ctx *c, const ckks_ct *ct, double *re, double *im) {
     hm::decode_residues(c->logN, host.data(), nq, c->q.data(), ct->scale, re, im);
 }
 
+}  // namespace
+
+// A captured CryptoInvSqrt chain for inputs of one shape (level, scale, B).
+struct ckks_graph {
+    Ct in, out;
+    hipGraph_t g = nullptr;
+    hipGraphExec_t ex = nullptr;
+    std::vector<void *> owned;
+};
+
+namespace {
+
+void graph_free(ckks_ctx *c, ckks_graph *G) {
+    if (G->ex) (void)hipGraphExecDestroy(G->ex);
+    if (G->g) (void)hipGraphDestroy(G->g);
+    G->out.reset();
+    G->in.reset();
+    c->pool->release_graph(G->owned);
+    delete G;
+}
+
+// Capture: one eager run first (fills every first-use table and the pool's
+// cache, so the captured run neither synchronises nor allocates device
+// memory), then the same chain on a dedicated input under stream capture.
+ckks_graph *graph_create(ckks_ctx *c, const ckks_ct *x, int degree, int iters, const ckks_invsqrt_opts &o) {
+    {
+        Ct warm = op_invsqrt(c, x, degree, iters, o);
+    }
+    hipchk(hipStreamSynchronize(c->stream), "sync");
+    std::unique_ptr<ckks_graph> G(new ckks_graph);
+    G->in = ct_copy(c, x);
+    hipchk(hipStreamSynchronize(c->stream), "sync");
+    // capture on a private stream (the context's stream may be the null
+    // stream, which cannot be captured); replays go to the context's stream
+    if (!c->cap_stream) hipchk(hipStreamCreateWithFlags(&c->cap_stream, hipStreamNonBlocking), "capture stream");
+    hipStream_t user = c->stream;
+    const bool prof = c->prof_on;
+    c->prof_on = false;
+    c->stream = c->cap_stream;
+    c->pool->begin_capture();
+    auto restore = [&] {
+        c->stream = user;
+        c->prof_on = prof;
+    };
+    if (hipStreamBeginCapture(c->stream, hipStreamCaptureModeRelaxed) != hipSuccess) {
+        G->owned = c->pool->end_capture();
+        restore();
+        graph_free(c, G.release());
+        fail(CKKS_E_DEVICE, "stream capture could not begin");
+    }
+    try {
+        G->out = op_invsqrt(c, G->in.get(), degree, iters, o);
+    } catch (...) {
+        hipGraph_t dead = nullptr;
+        (void)hipStreamEndCapture(c->stream, &dead);
+        if (dead) (void)hipGraphDestroy(dead);
+        G->owned = c->pool->end_capture();
+        restore();
+        graph_free(c, G.release());
+        throw;
+    }
+    hipError_t e = hipStreamEndCapture(c->stream, &G->g);
+    G->owned = c->pool->end_capture();
+    restore();
+    if (e != hipSuccess) {
+        graph_free(c, G.release());
+        fail(CKKS_E_DEVICE, "stream capture failed");
+    }
+    if (hipGraphInstantiate(&G->ex, G->g, nullptr, nullptr, 0) != hipSuccess) {
+        graph_free(c, G.release());
+        fail(CKKS_E_DEVICE, "graph instantiation failed");
+    }
+    return G.release();
+}
+
+Ct graph_run(ckks_ctx *c, ckks_graph *G, const ckks_ct *x) {
+    if (x->level != G->in->level || x->scale != G->in->scale || x->B != G->in->B)
+        fail(CKKS_E_PARAM, "input shape differs from the captured one");
+    const size_t w = c->words(x->level) * x->B;
+    hipchk(hipMemcpyAsync(G->in->buf.p, x->buf.p, w * 8, hipMemcpyDeviceToDevice, c->stream), "graph input");
+    hipchk(hipGraphLaunch(G->ex, c->stream), "graph launch");
+    Ct r = ct_new(c, G->out->level, G->out->scale, G->out->B);
+    hipchk(hipMemcpyAsync(r->buf.p, G->out->buf.p, c->words(r->level) * r->B * 8, hipMemcpyDeviceToDevice, c->stream),
+           "graph output");
+    return r;
+}
+
 // C-ABI wrapper: run f, map exceptions to a status
 template <class F>
 ckks_status guard(ckks_ctx *c, F &&f) {
@@ -1755,6 +1883,22 @@ ckks_status ckks_invsqrt_batch(ckks_ctx *c, const ckks_ct *const *xs, uint32_t n
     if (st != CKKS_OK)
         for (uint32_t i = 0; i < n; ++i) { delete outs[i]; outs[i] = nullptr; }
     return st;
+}
+ckks_status ckks_invsqrt_graph_create(ckks_ctx *c, const ckks_ct *x, uint32_t degree, uint32_t iters,
+                                      const ckks_invsqrt_opts *opts, ckks_graph **out) {
+    if (!c || !x || !out) return CKKS_E_PARAM;
+    *out = nullptr;
+    ckks_invsqrt_opts o = opts ? *opts : default_opts();
+    return guard(c, [&] { *out = graph_create(c, x, (int)degree, (int)iters, o); });
+}
+ckks_status ckks_invsqrt_graph_run(ckks_ctx *c, ckks_graph *g, const ckks_ct *x, ckks_ct **out) {
+    if (!c || !g || !x) return CKKS_E_PARAM;
+    return guard_out(c, out, [&] { return graph_run(c, g, x); });
+}
+void ckks_graph_destroy(ckks_ctx *c, ckks_graph *g) {
+    if (!c || !g) return;
+    (void)hipStreamSynchronize(c->stream);
+    graph_free(c, g);
 }
 ckks_status ckks_ct_pack(ckks_ctx *c, const ckks_ct *const *cts, uint32_t n, ckks_ct **out) {
     if (!c || !cts || n == 0) return CKKS_E_PARAM;

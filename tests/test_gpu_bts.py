@@ -189,3 +189,30 @@ def test_full_size_invsqrt_with_one_bootstrap(full):
     print(f"N=2^16 (31,3) from level 7: {n_bts} bootstrap(s), output level {y.level}, MRE {mre:.3g}", flush=True)
     assert n_bts == 1
     assert mre <= 3.1e-8
+
+
+def test_invsqrt_graph_replays_match_eager(pair):
+    """The captured chain (with its bootstrap) replayed several times, on
+    different inputs of the captured shape, with eager work and
+    synchronisations between the replays: every replay equals the eager
+    result word for word; the same for a batch of 3."""
+    g, _ = pair
+    lo, hi = 2.0 ** -10, 1.0
+    xs = [inputs.log_uniform(g.n, lo, hi, 40 + i) for i in range(4)]
+    cts = [g.encrypt(x, 7, 2.0 ** 50, 90 + i) for i, x in enumerate(xs)]
+    graph = g.invsqrt_graph(cts[0], 31, 3, lo, hi)
+    for rep in range(3):
+        for ct in cts:
+            eager = g.invsqrt(ct, 31, 3, lo, hi)
+            same(graph.run(ct), eager)
+            g.sync()
+            g.rescale(g.hmult(ct, ct))      # eager work between replays
+    graph.close()
+    batch = g.pack(cts[:3])
+    gb = g.invsqrt_graph(batch, 15, 3, lo, hi)
+    for rep in range(2):
+        outs = g.unpack(gb.run(batch))
+        for ct, y in zip(cts[:3], outs):
+            same(y, g.invsqrt(ct, 15, 3, lo, hi))
+        g.sync()
+    gb.close()
