@@ -818,12 +818,50 @@ Ct op_rotate(ckks_ctx *c, const ckks_ct *a, int k) {
     return op_automorphism(c, a, g);
 }
 
+// Linear combination sum_t rint(v_t s_t) x_t over the lowest level+1 limbs of
+// each x_t (one kernel: no limb-drop copies, one pass over the inputs); the
+// result carries the scale of the first term, scale(x_0) s_0, and every
+// term's scale(x_t) s_t must match it (as for a chain of Mul_P and Add).
+Ct op_lincomb(ckks_ctx *c, const std::vector<const ckks_ct *> &xs, const std::vector<double> &v,
+              const std::vector<double> &sc, int level) {
+    const int B = xs[0]->B;
+    const size_t N = c->N;
+    const double scale = xs[0]->scale * sc[0];
+    Ct r = ct_new(c, level, scale, B);
+    for (size_t t0 = 0; t0 < xs.size(); t0 += gpu::kMaxComb) {
+        gpu::CombArgs ca{};
+        const size_t t1 = std::min(xs.size(), t0 + gpu::kMaxComb);
+        if (t0 > 0) {   // carry the partial sum as a term with constant 1
+            ca.x[0] = r->buf.p;
+            ca.member_stride[0] = (size_t)2 * (level + 1) * N;
+            ca.poly_stride[0] = (size_t)(level + 1) * N;
+            ca.k[0] = 1;
+            ca.nterm = 1;
+        }
+        for (size_t t = t0; t < t1; ++t) {
+            const ckks_ct *x = xs[t];
+            if (x->level < level || x->B != B) fail(CKKS_E_LEVEL, "bad term for the linear combination");
+            if (t > 0 && !scales_match(scale, x->scale * sc[t])) fail(CKKS_E_SCALE, "scale mismatch");
+            const double kd = std::rint(v[t] * sc[t]);
+            if (!(std::fabs(kd) < 4.0e18)) fail(CKKS_E_RANGE, "constant out of range");
+            trace_op(c, "mul_scalar", level, B);
+            if (t > 0) trace_op(c, "add", level, B);
+            const int n = ca.nterm++;
+            ca.x[n] = x->buf.p;
+            ca.member_stride[n] = (size_t)2 * (x->level + 1) * N;
+            ca.poly_stride[n] = (size_t)(x->level + 1) * N;
+            ca.k[n] = (int64_t)kd;
+        }
+        gpu::lincomb(c->T, r->buf.p, ca, level + 1, B, map_q(0, level + 1), c->stream);
+    }
+    return r;
+}
+
 Ct op_level_to(ckks_ctx *c, const ckks_ct *a, int target) {
     if (target == a->level) return ct_copy(c, a);
     if (target > a->level || target < 0) fail(CKKS_E_LEVEL, "bad target level");
-    Ct d = op_drop(c, a, target + 1);
     double sc = (c->ladder[target] * (double)c->q[target + 1]) / a->scale;
-    Ct m = op_mul_const(c, d.get(), 1.0, sc);
+    Ct m = op_lincomb(c, {a}, {1.0}, {sc}, target + 1);
     return op_rescale(c, m.get());
 }
 
@@ -887,14 +925,15 @@ Ct baby_sum(ckks_ctx *c, PowerBasis &pb, const std::vector<double> &cf) {
     int lmin = 1 << 30;
     for (int i : terms) lmin = std::min(lmin, pb.T[i]->level);
     if (lmin < 1) fail(CKKS_E_LEVEL, "no level for the baby-step sum");
-    Ct acc;
+    std::vector<const ckks_ct *> xs;
+    std::vector<double> v, sc;
     for (int i : terms) {
         const ckks_ct *Ti = pb.T[i].get();
-        Ct d = op_drop(c, Ti, lmin);
-        double sc = (c->ladder[lmin - 1] * (double)c->q[lmin]) / Ti->scale;
-        Ct m = op_mul_const(c, d.get(), none ? 0.0 : cf[i], sc);
-        acc = acc ? op_addsub(c, acc.get(), m.get(), false) : std::move(m);
+        xs.push_back(Ti);
+        v.push_back(none ? 0.0 : cf[i]);
+        sc.push_back((c->ladder[lmin - 1] * (double)c->q[lmin]) / Ti->scale);
     }
+    Ct acc = op_lincomb(c, xs, v, sc, lmin);
     Ct r = op_rescale(c, acc.get());
     return op_add_const(c, r.get(), cf[0]);
 }
@@ -960,10 +999,8 @@ Ct op_newton(ckks_ctx *c, const ckks_ct *y, const ckks_ct *half_x, bool raw_x) {
     Ct w = mult_rs(c, u.get(), v.get());            // tmp_beta * y^2
     u.reset();
     v.reset();
-    Ct yd = op_drop(c, y, lc - 1);
-    double sc = (w->scale * (double)c->q[lc - 1]) / yd->scale;
-    Ct tm = op_mul_const(c, yd.get(), 1.5, sc);     // tmp_alpha = 1.5 y on scale(w)
-    yd.reset();
+    double sc = (w->scale * (double)c->q[lc - 1]) / y->scale;
+    Ct tm = op_lincomb(c, {y}, {1.5}, {sc}, lc - 1);   // tmp_alpha = 1.5 y (limbs to lc-1) on scale(w)
     Ct ta = op_rescale(c, tm.get());
     return op_addsub(c, ta.get(), w.get(), true);
 }

@@ -165,6 +165,21 @@ void moddown_finish_jobs(const Tables &T, const FinishJobs &f, const uint64_t *a
                          const uint64_t *z, const LimbConsts &pinv, int nlimb, int njob, int B, const LimbMap &m,
                          hipStream_t s);
 
+// Linear combination of ciphertext objects at (possibly) different levels:
+// out[b][p][l] = sum_t k_t * x_t[b][p][l] over the nlimb lowest limbs (signed
+// integer constants k_t, reduced per prime in the kernel; products summed in
+// 128 bits, reduced once; nterm <= kMaxComb).  x_t has member stride
+// member_stride[t] and poly stride poly_stride[t] (words).
+constexpr int kMaxComb = 16;
+struct CombArgs {
+    int nterm;
+    const uint64_t *x[kMaxComb];
+    size_t member_stride[kMaxComb];
+    size_t poly_stride[kMaxComb];
+    int64_t k[kMaxComb];
+};
+void lincomb(const Tables &T, uint64_t *out, const CombArgs &a, int nlimb, int B, const LimbMap &m, hipStream_t s);
+
 // decryption: m = c0 + c1 * s
 void decrypt_combine(const Tables &T, uint64_t *m, const uint64_t *c0, const uint64_t *c1, const uint64_t *sk,
                      int nlimb, const LimbMap &m_, hipStream_t s);

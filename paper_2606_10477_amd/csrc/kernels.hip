@@ -838,6 +838,30 @@ void pt_mac(const Tables &T, uint64_t *out, const MacArgs &a, int nlimb, int npo
     hipLaunchKernelGGL(k_pt_mac, grid_for(total), dim3(256), 0, s, out, a, T.logN, nlimb, total, m, T);
 }
 
+__global__ void k_lincomb(u64 *out, CombArgs a, int logN, int nlimb, size_t total, LimbMap m, Tables T) {
+    const size_t N = (size_t)1 << logN;
+    GRID_LOOP(i, total) {
+        ROW_SPLIT(i, logN, nlimb, poly, limb)
+        const uint32_t b = poly >> 1, pp = poly & 1u;
+        const size_t j = i & (N - 1);
+        const DevPrime P = T.primes[m.p[limb]];
+        u64 h = 0, l = 0;
+        for (int t = 0; t < a.nterm; ++t) {
+            const int64_t k = a.k[t];
+            u64 kv = reduce64(k < 0 ? (u64)(-(k + 1)) + 1 : (u64)k, P);
+            if (k < 0 && kv) kv = P.q - kv;
+            const u64 x = a.x[t][b * a.member_stride[t] + pp * a.poly_stride[t] + ((size_t)limb << logN) + j];
+            mac128(h, l, x, kv);
+        }
+        out[i] = reduce128(h, l, P);
+    }
+}
+void lincomb(const Tables &T, uint64_t *out, const CombArgs &a, int nlimb, int B, const LimbMap &m, hipStream_t s) {
+    size_t total = ((size_t)nlimb * 2 * B) << T.logN;
+    if (!total || a.nterm <= 0) return;
+    hipLaunchKernelGGL(k_lincomb, grid_for(total), dim3(256), 0, s, out, a, T.logN, nlimb, total, m, T);
+}
+
 __global__ void k_decrypt(u64 *mo, const u64 *c0, const u64 *c1, const u64 *sk, int logN, size_t total, LimbMap m,
                           Tables T) {
     GRID_LOOP(i, total) {
