@@ -199,6 +199,17 @@ __global__ void __launch_bounds__(kThreads) k_ntt_strided(u64 *data, int logN, i
 // ---------------------------------------------------------------------------
 constexpr int kPad = 17;   // LDS row pitch (words) for the 16-wide sub-tiles
 
+// Lazy (Harvey) butterflies for the N = 2^16 passes: a Shoup product without
+// its final correction lies in [0, 2q) for any 64-bit input; forward values
+// stay in [0, 4q), inverse values in [0, 2q) (q < 2^61), and are reduced to
+// [0, q) only where a pass writes its final output.
+DEV u64 mul_shoup_lazy(u64 a, u64 w, u64 wsh, u64 q) { return a * w - __umul64hi(a, wsh) * q; }
+DEV u64 reduce_4q(u64 x, u64 q) {
+    const u64 q2 = 2 * q;
+    x = x >= q2 ? x - q2 : x;
+    return x >= q ? x - q : x;
+}
+
 // forward butterflies (CT) on v[0..15] for 4 stages; element m pairs with
 // m + h (h = 8, 4, 2, 1); twiddle index for stage j (0..3): base_j + (m >> (4 - j))
 __device__ __forceinline__ void fwd16(u64 v[16], const u64 *W, const u64 *Ws, int s0, int base_shift_idx,
@@ -211,10 +222,11 @@ __device__ __forceinline__ void fwd16(u64 v[16], const u64 *W, const u64 *Ws, in
         for (int m = 0; m < 16; ++m) {
             if (m & h) continue;
             const int wi = (1 << (s0 + j)) + (hi_part << j) + (m >> (4 - j));
-            u64 U = v[m];
-            u64 V = mul_shoup(v[m + h], W[wi], Ws[wi], q);
-            v[m] = add_mod(U, V, q);
-            v[m + h] = sub_mod(U, V, q);
+            const u64 q2 = 2 * q;
+            u64 U = v[m] >= q2 ? v[m] - q2 : v[m];               // [0, 2q)
+            u64 V = mul_shoup_lazy(v[m + h], W[wi], Ws[wi], q);  // [0, 2q)
+            v[m] = U + V;                                        // [0, 4q)
+            v[m + h] = U - V + q2;                               // (0, 4q)
         }
     }
     (void)base_shift_idx;
@@ -232,9 +244,11 @@ __device__ __forceinline__ void inv16(u64 v[16], const u64 *W, const u64 *Ws, in
             if (m & h) continue;
             const int lt = lt0 + j;   // log2 of the global half-distance
             const int wi = (1 << (logN - lt - 1)) + (hi_part << (3 - j)) + (m >> (j + 1));
-            u64 U = v[m], V = v[m + h];
-            v[m] = add_mod(U, V, q);
-            v[m + h] = mul_shoup(sub_mod(U, V, q), W[wi], Ws[wi], q);
+            const u64 q2 = 2 * q;
+            u64 U = v[m], V = v[m + h];                          // [0, 2q)
+            u64 S = U + V;
+            v[m] = S >= q2 ? S - q2 : S;                         // [0, 2q)
+            v[m + h] = mul_shoup_lazy(U - V + q2, W[wi], Ws[wi], q);   // [0, 2q)
         }
     }
 }
@@ -302,7 +316,7 @@ __global__ void __launch_bounds__(256) k_ntt16_blocks_fwd(u64 *data, int nlimb, 
     fwd16(v, W, Ws, 12, 0, (blk0 + y) * 16 + x, q);
     __syncthreads();
 #pragma unroll
-    for (int mm = 0; mm < 16; ++mm) tile[(y * 16 + x) * kPad + mm] = v[mm];
+    for (int mm = 0; mm < 16; ++mm) tile[(y * 16 + x) * kPad + mm] = reduce_4q(v[mm], q);
     __syncthreads();
 #pragma unroll
     for (int mm = 0; mm < 16; ++mm) d[(y << 8) + x + 16 * mm] = tile[(y * 16 + mm) * kPad + x];
