@@ -328,6 +328,18 @@ ckks_status ckks_ntt_device(ckks_ctx *ctx, uint64_t *data, uint32_t n_limbs,
                             const uint32_t *prime_idx, int inverse);
 
 /*
+ * Schedule of the N = 2^16 transforms (a tuning knob; results are identical
+ * under every schedule).  A forward or inverse NTT call covering at most
+ * `r4_max_limbs` limbs in total runs with 4 words per thread, one of at most
+ * `r8_max_limbs` limbs with 8, larger calls with 16: fewer words per thread
+ * give more, shorter waves (better for small calls), more words fewer LDS
+ * exchanges (better for large ones).  -1 restores the library's default for
+ * that bound; values below -1 give CKKS_E_PARAM.  Takes effect for launches
+ * issued after the call.
+ */
+ckks_status ckks_ntt_schedule(ckks_ctx *ctx, int32_t r4_max_limbs, int32_t r8_max_limbs);
+
+/*
  * Opt-in timing of kernel families on the context's stream (HIP events
  * recorded around each call; enabling clears previous records).  Families:
  *   "ntt"       every forward/inverse NTT call of the hot path; algorithmic

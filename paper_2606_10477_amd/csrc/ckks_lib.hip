@@ -202,6 +202,11 @@ struct ConvTable {
 
 struct BtsPlan;
 
+// Default N = 2^16 transform schedule (ckks_ntt_schedule overrides it):
+// calls of at most this many limbs in total use 4 / 8 words per thread.
+constexpr int kNttR4Max = 28;
+constexpr int kNttR8Max = 28;
+
 struct ckks_ctx {
     ckks_params prm;
     int logN, N, L, K, alpha, dnum, np;
@@ -417,6 +422,8 @@ void build_tables(ckks_ctx *c) {
     c->T.ninv = c->d_ninv.p;
     c->T.ninv_sh = c->d_ninvsh.p;
     c->T.logN = c->logN;
+    c->T.ntt_r4_max = kNttR4Max;
+    c->T.ntt_r8_max = kNttR8Max;
 }
 
 // product of primes (indices idx, skipping `skip`) modulo m
@@ -1999,6 +2006,14 @@ ckks_status ckks_ntt_device(ckks_ctx *c, uint64_t *data, uint32_t n_limbs, const
             }
             gpu::ntt(c->T, data + (size_t)off * c->N, (int)cnt, 1, m, inverse != 0, c->stream);
         }
+    });
+}
+
+ckks_status ckks_ntt_schedule(ckks_ctx *c, int32_t r4_max_limbs, int32_t r8_max_limbs) {
+    if (!c || r4_max_limbs < -1 || r8_max_limbs < -1) return CKKS_E_PARAM;
+    return guard(c, [&] {
+        c->T.ntt_r4_max = r4_max_limbs < 0 ? kNttR4Max : r4_max_limbs;
+        c->T.ntt_r8_max = r8_max_limbs < 0 ? kNttR8Max : r8_max_limbs;
     });
 }
 

@@ -32,6 +32,9 @@ struct Tables {
     const uint64_t *fw, *fw_sh, *iw, *iw_sh;
     const uint64_t *ninv, *ninv_sh;   // [np]
     int logN;
+    // N = 2^16 transforms: calls of at most ntt_r4_max (ntt_r8_max) limbs in
+    // total use 4 (8) words per thread, larger ones 16
+    int ntt_r4_max, ntt_r8_max;
 };
 
 // Batched in-place NTT / inverse NTT of nlimb * npoly limbs.

@@ -209,11 +209,33 @@ DEV u64 reduce_4q(u64 x, u64 q) {
     x = x >= q2 ? x - q2 : x;
     return x >= q ? x - q : x;
 }
+// x mod q for any 64-bit x: Shoup product by 1 (quotient constant floor(2^64/q)),
+// which lands in [0, 2q), then one correction
+DEV u64 reduce_any(u64 x, u64 inv64, u64 q) {
+    u64 r = x - __umul64hi(x, inv64) * q;
+    return r >= q ? r - q : r;
+}
+// Shoup product with a truncated quotient: of the four 32 x 32 partial products
+// of a * wsh only the high words of the three upper ones are kept, so the
+// quotient is short by at most 2 and the result lies in [0, 4q) for any 64-bit
+// a (three multiplications fewer than the exact high word).
+DEV u64 mul_shoup_lazy4(u64 a, u64 w, u64 wsh, u64 q) {
+    const uint32_t a0 = (uint32_t)a, a1 = (uint32_t)(a >> 32);
+    const uint32_t s0 = (uint32_t)wsh, s1 = (uint32_t)(wsh >> 32);
+    const u64 Q = (u64)a1 * s1 + __umulhi(a1, s0) + __umulhi(a0, s1);
+    return a * w - Q * q;
+}
+// Primes below 2^57 leave headroom for 16 forward stages with no reduction at
+// all: with the truncated-quotient product V in [0, 4q), each stage adds at
+// most 4q to the bound (U + V and U - V + 4q), so a pass fed with [0, Bq) ends
+// below (B + 32) q and the whole transform from [0, q) below 65 q < 2^64.  The
+// inverse butterflies keep every value in [0, 4q) for these primes.
+constexpr u64 kSmallPrime = 1ull << 57;
 
 // forward butterflies (CT) on v[0..15] for 4 stages; element m pairs with
 // m + h (h = 8, 4, 2, 1); twiddle index for stage j (0..3): base_j + (m >> (4 - j))
-__device__ __forceinline__ void fwd16(u64 v[16], const u64 *W, const u64 *Ws, int s0, int base_shift_idx,
-                                      int hi_part, u64 q) {
+template <bool SMALL>
+__device__ __forceinline__ void fwd16(u64 v[16], const u64 *W, const u64 *Ws, int s0, int hi_part, u64 q) {
     // stage j: global stage s = s0 + j; twiddle index = 2^s + hi_part * 2^j + (m >> (4 - j))
 #pragma unroll
     for (int j = 0; j < 4; ++j) {
@@ -222,18 +244,28 @@ __device__ __forceinline__ void fwd16(u64 v[16], const u64 *W, const u64 *Ws, in
         for (int m = 0; m < 16; ++m) {
             if (m & h) continue;
             const int wi = (1 << (s0 + j)) + (hi_part << j) + (m >> (4 - j));
-            const u64 q2 = 2 * q;
-            u64 U = v[m] >= q2 ? v[m] - q2 : v[m];               // [0, 2q)
-            u64 V = mul_shoup_lazy(v[m + h], W[wi], Ws[wi], q);  // [0, 2q)
-            v[m] = U + V;                                        // [0, 4q)
-            v[m + h] = U - V + q2;                               // (0, 4q)
+            if (SMALL) {
+                const u64 q4 = 4 * q;
+                const u64 U = v[m];
+                const u64 V = mul_shoup_lazy4(v[m + h], W[wi], Ws[wi], q);   // [0, 4q)
+                v[m] = U + V;
+                v[m + h] = U - V + q4;
+            } else {
+                const u64 q2 = 2 * q;
+                const u64 U = v[m] >= q2 ? v[m] - q2 : v[m];                // [0, 2q)
+                const u64 V = mul_shoup_lazy(v[m + h], W[wi], Ws[wi], q);   // [0, 2q)
+                v[m] = U + V;                                               // [0, 4q)
+                v[m + h] = U - V + q2;                                      // (0, 4q)
+            }
         }
     }
-    (void)base_shift_idx;
 }
 // inverse butterflies (GS) on v[0..15], distances h = 1, 2, 4, 8; group index
 // for distance h: hi_part * (16 / 2h) + (m >> (log2 h + 1)); twiddle index =
-// n_groups_total + group, with n_groups_total = N / (2 t_global).
+// n_groups_total + group, with n_groups_total = N / (2 t_global).  Values stay
+// in [0, 2q) (large primes, exact lazy product) or [0, 4q) (primes below
+// 2^57, truncated-quotient product).
+template <bool SMALL>
 __device__ __forceinline__ void inv16(u64 v[16], const u64 *W, const u64 *Ws, int logN, int lt0, int hi_part,
                                       u64 q) {
 #pragma unroll
@@ -244,11 +276,12 @@ __device__ __forceinline__ void inv16(u64 v[16], const u64 *W, const u64 *Ws, in
             if (m & h) continue;
             const int lt = lt0 + j;   // log2 of the global half-distance
             const int wi = (1 << (logN - lt - 1)) + (hi_part << (3 - j)) + (m >> (j + 1));
-            const u64 q2 = 2 * q;
-            u64 U = v[m], V = v[m + h];                          // [0, 2q)
-            u64 S = U + V;
-            v[m] = S >= q2 ? S - q2 : S;                         // [0, 2q)
-            v[m + h] = mul_shoup_lazy(U - V + q2, W[wi], Ws[wi], q);   // [0, 2q)
+            const u64 B = SMALL ? 4 * q : 2 * q;
+            const u64 U = v[m], V = v[m + h];                        // [0, B)
+            const u64 S = U + V;
+            v[m] = S >= B ? S - B : S;                               // [0, B)
+            v[m + h] = SMALL ? mul_shoup_lazy4(U - V + B, W[wi], Ws[wi], q)
+                             : mul_shoup_lazy(U - V + B, W[wi], Ws[wi], q);   // [0, B)
         }
     }
 }
@@ -278,7 +311,9 @@ __global__ void __launch_bounds__(256) k_ntt16_rows_fwd(u64 *dst, const u64 *src
     // phase 1: rows k = y + 16 m, column x; stages 0..3 (row distances 128..16)
 #pragma unroll
     for (int mm = 0; mm < 16; ++mm) v[mm] = in[((y + 16 * mm) << 8) + c0 + x];
-    fwd16(v, W, Ws, 0, 0, 0, q);
+    const bool small = q < kSmallPrime;
+    if (small) fwd16<true>(v, W, Ws, 0, 0, q);
+    else fwd16<false>(v, W, Ws, 0, 0, q);
 #pragma unroll
     for (int mm = 0; mm < 16; ++mm) tile[(y + 16 * mm) * kPad + x] = v[mm];
     __syncthreads();
@@ -286,7 +321,8 @@ __global__ void __launch_bounds__(256) k_ntt16_rows_fwd(u64 *dst, const u64 *src
 #pragma unroll
     for (int mm = 0; mm < 16; ++mm) v[mm] = tile[(16 * y + mm) * kPad + x];
     // twiddle index 2^s + (k >> (8 - s)), k = 16 y + m: hi_part = y
-    fwd16(v, W, Ws, 4, 0, y, q);
+    if (small) fwd16<true>(v, W, Ws, 4, y, q);
+    else fwd16<false>(v, W, Ws, 4, y, q);
 #pragma unroll
     for (int mm = 0; mm < 16; ++mm) out[((16 * y + mm) << 8) + c0 + x] = v[mm];
 }
@@ -306,17 +342,28 @@ __global__ void __launch_bounds__(256) k_ntt16_blocks_fwd(u64 *data, int nlimb, 
 #pragma unroll
     for (int mm = 0; mm < 16; ++mm) v[mm] = d[(y << 8) + x + 16 * mm];
     // twiddle 2^s + (J >> (16 - s)), J = 256 (blk0 + y) + x + 16 m: hi_part = blk0 + y
-    fwd16(v, W, Ws, 8, 0, blk0 + y, q);
+    const bool small = q < kSmallPrime;
+    if (small) fwd16<true>(v, W, Ws, 8, blk0 + y, q);
+    else fwd16<false>(v, W, Ws, 8, blk0 + y, q);
 #pragma unroll
     for (int mm = 0; mm < 16; ++mm) tile[(y * 16 + mm) * kPad + x] = v[mm];   // [block y][row mm][col x]
     __syncthreads();
     // phase 2: block y, words 16 x + m; stages 12..15 (distances 8..1)
 #pragma unroll
     for (int mm = 0; mm < 16; ++mm) v[mm] = tile[(y * 16 + x) * kPad + mm];
-    fwd16(v, W, Ws, 12, 0, (blk0 + y) * 16 + x, q);
+    if (small) {
+        fwd16<true>(v, W, Ws, 12, (blk0 + y) * 16 + x, q);
+        const u64 inv64 = T.primes[pi].mu2_hi;
+#pragma unroll
+        for (int mm = 0; mm < 16; ++mm) v[mm] = reduce_any(v[mm], inv64, q);
+    } else {
+        fwd16<false>(v, W, Ws, 12, (blk0 + y) * 16 + x, q);
+#pragma unroll
+        for (int mm = 0; mm < 16; ++mm) v[mm] = reduce_4q(v[mm], q);
+    }
     __syncthreads();
 #pragma unroll
-    for (int mm = 0; mm < 16; ++mm) tile[(y * 16 + x) * kPad + mm] = reduce_4q(v[mm], q);
+    for (int mm = 0; mm < 16; ++mm) tile[(y * 16 + x) * kPad + mm] = v[mm];
     __syncthreads();
 #pragma unroll
     for (int mm = 0; mm < 16; ++mm) d[(y << 8) + x + 16 * mm] = tile[(y * 16 + mm) * kPad + x];
@@ -342,14 +389,17 @@ __global__ void __launch_bounds__(256) k_ntt16_blocks_inv(u64 *dst, const u64 *s
     // word J for distance t: J >> (lt + 1), J = 256 (blk0 + y) + 16 x + m
 #pragma unroll
     for (int mm = 0; mm < 16; ++mm) v[mm] = tile[(y * 16 + x) * kPad + mm];
-    inv16(v, W, Ws, 16, 0, (blk0 + y) * 16 + x, q);
+    const bool small = q < kSmallPrime;
+    if (small) inv16<true>(v, W, Ws, 16, 0, (blk0 + y) * 16 + x, q);
+    else inv16<false>(v, W, Ws, 16, 0, (blk0 + y) * 16 + x, q);
 #pragma unroll
     for (int mm = 0; mm < 16; ++mm) tile[(y * 16 + x) * kPad + mm] = v[mm];
     __syncthreads();
     // phase B: block y, words x + 16 m; half-distances 16..128
 #pragma unroll
     for (int mm = 0; mm < 16; ++mm) v[mm] = tile[(y * 16 + mm) * kPad + x];
-    inv16(v, W, Ws, 16, 4, blk0 + y, q);
+    if (small) inv16<true>(v, W, Ws, 16, 4, blk0 + y, q);
+    else inv16<false>(v, W, Ws, 16, 4, blk0 + y, q);
 #pragma unroll
     for (int mm = 0; mm < 16; ++mm) d[(y << 8) + x + 16 * mm] = v[mm];
 }
@@ -369,17 +419,245 @@ __global__ void __launch_bounds__(256) k_ntt16_rows_inv(u64 *data, int nlimb, in
     // phase A: rows k = 16 y + m (row distances 1..8 = global 256..2048)
 #pragma unroll
     for (int mm = 0; mm < 16; ++mm) v[mm] = d[((16 * y + mm) << 8) + c0 + x];
-    inv16(v, W, Ws, 16, 8, y, q);
+    const bool small = q < kSmallPrime;
+    if (small) inv16<true>(v, W, Ws, 16, 8, y, q);
+    else inv16<false>(v, W, Ws, 16, 8, y, q);
 #pragma unroll
     for (int mm = 0; mm < 16; ++mm) tile[(16 * y + mm) * kPad + x] = v[mm];
     __syncthreads();
     // phase B: rows k = y + 16 m (row distances 16..128)
 #pragma unroll
     for (int mm = 0; mm < 16; ++mm) v[mm] = tile[(y + 16 * mm) * kPad + x];
-    inv16(v, W, Ws, 16, 12, 0, q);
+    if (small) inv16<true>(v, W, Ws, 16, 12, 0, q);
+    else inv16<false>(v, W, Ws, 16, 12, 0, q);
     const u64 ni = T.ninv[pi], nis = T.ninv_sh[pi];
 #pragma unroll
     for (int mm = 0; mm < 16; ++mm) d[((y + 16 * mm) << 8) + c0 + x] = mul_shoup(v[mm], ni, nis, q);
+}
+
+// ---------------------------------------------------------------------------
+// N = 2^16 passes with R = 4 or 8 words per thread.  Same two passes and same
+// 4096-word tiles as above (16 independent 256-point sub-transforms, "lanes":
+// 16 columns of the 256 x 256 view, or 16 blocks of 256 words), but each
+// sub-transform is shared by 256 / R threads, so a tile takes 4096 / R
+// threads and every wave carries a shorter chain of dependent work: more waves
+// in flight when a call covers few limbs.  Phase p holds the r = log2(R) bits
+// [lo, lo + r) of the 8-bit index k within the sub-transform in registers (the
+// thread supplies the other 8 - r bits) and runs the stages of the phase's
+// bits; phases exchange through LDS.  Forward passes take the bits from the
+// top (the last phase may repeat bits already done), inverse passes from the
+// bottom.  Twiddle indices follow from the global word index J: forward stage
+// s pairs J and J + 2^(15 - s) with twiddle 2^s + (J >> (16 - s)); inverse
+// half-distance 2^t uses 2^(15 - t) + (J >> (t + 1)).
+// ---------------------------------------------------------------------------
+template <int R> struct Geo {
+    static constexpr int r = R == 4 ? 2 : 3;
+    static constexpr int T = 256 / R;         // threads per sub-transform
+    static constexpr int NT = 16 * T;         // threads per block
+    static constexpr int NPH = (8 + r - 1) / r;
+    static constexpr int tb = 8 - r;          // thread bits of k
+};
+// register bits [lo, lo + r) of phase p; stage bits [s_lo, s_hi)
+template <int R> __device__ constexpr int fwd_lo(int p) {
+    return 8 - Geo<R>::r * (p + 1) > 0 ? 8 - Geo<R>::r * (p + 1) : 0;
+}
+template <int R> __device__ constexpr int inv_lo(int p) {
+    return Geo<R>::r * p < 8 - Geo<R>::r ? Geo<R>::r * p : 8 - Geo<R>::r;
+}
+// k of register m for thread sub-index u when the register bits start at lo
+template <int R> __device__ __forceinline__ int k_of(int u, int m, int lo) {
+    return ((u >> lo) << (lo + Geo<R>::r)) | (m << lo) | (u & ((1 << lo) - 1));
+}
+// LDS address of (lane, k): rows view [k][lane] with pitch 17, blocks view
+// [lane][k >> 4][k & 15] with pitch 17 per 16 words
+template <bool ROWS> __device__ __forceinline__ int lds_at(int lane, int k) {
+    return ROWS ? k * kPad + lane : (lane * 16 + (k >> 4)) * kPad + (k & 15);
+}
+
+// forward butterflies of stage bit b (global stage s) on registers pairing
+// m and m + 2^j, j = b - lo; the twiddle index comes from J of the lower word
+template <int R, bool ROWS, bool SMALL>
+__device__ __forceinline__ void fwd_stage(u64 *v, int u, int lo, int b, int blkg, const u64 *W, const u64 *Ws,
+                                          u64 q) {
+    const int j = b - lo;
+#pragma unroll
+    for (int m = 0; m < R; ++m) {
+        if (m & (1 << j)) continue;
+        const int k = k_of<R>(u, m, lo);
+        const int wi = ROWS ? (1 << (7 - b)) + (k >> (b + 1))
+                            : (1 << (15 - b)) + (blkg << (7 - b)) + (k >> (b + 1));
+        const int h = 1 << j;
+        if (SMALL) {
+            const u64 U = v[m];
+            const u64 V = mul_shoup_lazy4(v[m + h], W[wi], Ws[wi], q);
+            v[m] = U + V;
+            v[m + h] = U - V + 4 * q;
+        } else {
+            const u64 q2 = 2 * q;
+            const u64 U = v[m] >= q2 ? v[m] - q2 : v[m];
+            const u64 V = mul_shoup_lazy(v[m + h], W[wi], Ws[wi], q);
+            v[m] = U + V;
+            v[m + h] = U - V + q2;
+        }
+    }
+}
+template <int R, bool ROWS, bool SMALL>
+__device__ __forceinline__ void inv_stage(u64 *v, int u, int lo, int b, int blkg, const u64 *W, const u64 *Ws,
+                                          u64 q) {
+    const int j = b - lo;
+#pragma unroll
+    for (int m = 0; m < R; ++m) {
+        if (m & (1 << j)) continue;
+        const int k = k_of<R>(u, m, lo);
+        const int wi = ROWS ? (1 << (7 - b)) + (k >> (b + 1))
+                            : (1 << (15 - b)) + (blkg << (7 - b)) + (k >> (b + 1));
+        const int h = 1 << j;
+        const u64 B = SMALL ? 4 * q : 2 * q;
+        const u64 U = v[m], V = v[m + h];
+        const u64 S = U + V;
+        v[m] = S >= B ? S - B : S;
+        v[m + h] = SMALL ? mul_shoup_lazy4(U - V + B, W[wi], Ws[wi], q)
+                         : mul_shoup_lazy(U - V + B, W[wi], Ws[wi], q);
+    }
+}
+
+// all phases of one pass on registers v (loaded for phase 0 by the caller);
+// leaves the registers holding the last phase's words
+template <int R, bool ROWS, bool FWD, bool SMALL>
+__device__ __forceinline__ void pass_phases(u64 *v, u64 *tile, int lane, int u, int blkg, const u64 *W,
+                                            const u64 *Ws, u64 q) {
+    constexpr int r = Geo<R>::r, NPH = Geo<R>::NPH;
+#pragma unroll
+    for (int p = 0; p < NPH; ++p) {
+        const int lo = FWD ? fwd_lo<R>(p) : inv_lo<R>(p);
+        if (p > 0) {
+            __syncthreads();   // the previous phase's words are all in LDS
+#pragma unroll
+            for (int m = 0; m < R; ++m) v[m] = tile[lds_at<ROWS>(lane, k_of<R>(u, m, lo))];
+        }
+        if (FWD) {
+            const int b_hi = 8 - r * p - 1, b_lo = lo;   // stage bits, high to low
+#pragma unroll
+            for (int b = b_hi; b >= b_lo; --b) fwd_stage<R, ROWS, SMALL>(v, u, lo, b, blkg, W, Ws, q);
+        } else {
+            const int b_lo = r * p, b_hi = (r * (p + 1) < 8 ? r * (p + 1) : 8) - 1;
+#pragma unroll
+            for (int b = b_lo; b <= b_hi; ++b) inv_stage<R, ROWS, SMALL>(v, u, lo, b, blkg, W, Ws, q);
+        }
+        if (p + 1 < NPH) {
+            // each thread writes back exactly the words it read in this phase
+#pragma unroll
+            for (int m = 0; m < R; ++m) tile[lds_at<ROWS>(lane, k_of<R>(u, m, lo))] = v[m];
+        }
+    }
+}
+
+// forward rows pass (stages 0..7): src -> dst
+template <int R>
+__global__ void __launch_bounds__(Geo<R>::NT) k_nttr_rows_fwd(u64 *dst, const u64 *src, size_t src_stride, int nlimb,
+                                                               int npoly, LimbMap m, Tables T) {
+    __shared__ u64 tile[256 * kPad];
+    NTT16_INDEX(nlimb, npoly)
+    const int pi = m.p[lidx];
+    const u64 q = T.primes[pi].q;
+    const u64 *W = T.fw + ((size_t)pi << 16), *Ws = T.fw_sh + ((size_t)pi << 16);
+    const u64 *in = src + (size_t)pidx * src_stride + ((size_t)lidx << 16);
+    u64 *out = dst + row_off;
+    const int c0 = blockIdx.x * 16;
+    const int lane = threadIdx.x & 15, u = threadIdx.x >> 4;
+    constexpr int lo0 = fwd_lo<R>(0), loL = fwd_lo<R>(Geo<R>::NPH - 1);
+    u64 v[R];
+#pragma unroll
+    for (int mm = 0; mm < R; ++mm) v[mm] = in[(k_of<R>(u, mm, lo0) << 8) + c0 + lane];
+    if (q < kSmallPrime) pass_phases<R, true, true, true>(v, tile, lane, u, 0, W, Ws, q);
+    else pass_phases<R, true, true, false>(v, tile, lane, u, 0, W, Ws, q);
+#pragma unroll
+    for (int mm = 0; mm < R; ++mm) out[(k_of<R>(u, mm, loL) << 8) + c0 + lane] = v[mm];
+}
+// forward blocks pass (stages 8..15), in place, output reduced to [0, q)
+template <int R>
+__global__ void __launch_bounds__(Geo<R>::NT) k_nttr_blocks_fwd(u64 *data, int nlimb, int npoly, LimbMap m,
+                                                                 Tables T) {
+    __shared__ u64 tile[256 * kPad];
+    NTT16_INDEX(nlimb, npoly)
+    const int pi = m.p[lidx];
+    const u64 q = T.primes[pi].q;
+    const u64 *W = T.fw + ((size_t)pi << 16), *Ws = T.fw_sh + ((size_t)pi << 16);
+    u64 *d = data + row_off + ((size_t)blockIdx.x << 12);
+    const int lane = threadIdx.x / Geo<R>::T, u = threadIdx.x % Geo<R>::T;
+    const int blkg = blockIdx.x * 16 + lane;
+    constexpr int lo0 = fwd_lo<R>(0), loL = fwd_lo<R>(Geo<R>::NPH - 1);
+    u64 v[R];
+#pragma unroll
+    for (int mm = 0; mm < R; ++mm) v[mm] = d[(lane << 8) + k_of<R>(u, mm, lo0)];
+    if (q < kSmallPrime) {
+        pass_phases<R, false, true, true>(v, tile, lane, u, blkg, W, Ws, q);
+        const u64 inv64 = T.primes[pi].mu2_hi;
+#pragma unroll
+        for (int mm = 0; mm < R; ++mm) v[mm] = reduce_any(v[mm], inv64, q);
+    } else {
+        pass_phases<R, false, true, false>(v, tile, lane, u, blkg, W, Ws, q);
+#pragma unroll
+        for (int mm = 0; mm < R; ++mm) v[mm] = reduce_4q(v[mm], q);
+    }
+#pragma unroll
+    for (int mm = 0; mm < R; ++mm) d[(lane << 8) + k_of<R>(u, mm, loL)] = v[mm];
+}
+// inverse blocks pass (half-distances 1..128): src -> dst
+template <int R>
+__global__ void __launch_bounds__(Geo<R>::NT) k_nttr_blocks_inv(u64 *dst, const u64 *src, size_t src_stride,
+                                                                 int nlimb, int npoly, LimbMap m, Tables T) {
+    __shared__ u64 tile[256 * kPad];
+    NTT16_INDEX(nlimb, npoly)
+    const int pi = m.p[lidx];
+    const u64 q = T.primes[pi].q;
+    const u64 *W = T.iw + ((size_t)pi << 16), *Ws = T.iw_sh + ((size_t)pi << 16);
+    const u64 *s_in = src + (size_t)pidx * src_stride + ((size_t)lidx << 16) + ((size_t)blockIdx.x << 12);
+    u64 *d = dst + row_off + ((size_t)blockIdx.x << 12);
+    const int lane = threadIdx.x / Geo<R>::T, u = threadIdx.x % Geo<R>::T;
+    const int blkg = blockIdx.x * 16 + lane;
+    constexpr int lo0 = inv_lo<R>(0), loL = inv_lo<R>(Geo<R>::NPH - 1);
+    u64 v[R];
+#pragma unroll
+    for (int mm = 0; mm < R; ++mm) v[mm] = s_in[(lane << 8) + k_of<R>(u, mm, lo0)];
+    if (q < kSmallPrime) pass_phases<R, false, false, true>(v, tile, lane, u, blkg, W, Ws, q);
+    else pass_phases<R, false, false, false>(v, tile, lane, u, blkg, W, Ws, q);
+#pragma unroll
+    for (int mm = 0; mm < R; ++mm) d[(lane << 8) + k_of<R>(u, mm, loL)] = v[mm];
+}
+// inverse rows pass (half-distances 256..32768), in place, times N^-1
+template <int R>
+__global__ void __launch_bounds__(Geo<R>::NT) k_nttr_rows_inv(u64 *data, int nlimb, int npoly, LimbMap m, Tables T) {
+    __shared__ u64 tile[256 * kPad];
+    NTT16_INDEX(nlimb, npoly)
+    const int pi = m.p[lidx];
+    const u64 q = T.primes[pi].q;
+    const u64 *W = T.iw + ((size_t)pi << 16), *Ws = T.iw_sh + ((size_t)pi << 16);
+    u64 *d = data + row_off;
+    const int c0 = blockIdx.x * 16;
+    const int lane = threadIdx.x & 15, u = threadIdx.x >> 4;
+    constexpr int lo0 = inv_lo<R>(0), loL = inv_lo<R>(Geo<R>::NPH - 1);
+    u64 v[R];
+#pragma unroll
+    for (int mm = 0; mm < R; ++mm) v[mm] = d[(k_of<R>(u, mm, lo0) << 8) + c0 + lane];
+    if (q < kSmallPrime) pass_phases<R, true, false, true>(v, tile, lane, u, 0, W, Ws, q);
+    else pass_phases<R, true, false, false>(v, tile, lane, u, 0, W, Ws, q);
+    const u64 ni = T.ninv[pi], nis = T.ninv_sh[pi];
+#pragma unroll
+    for (int mm = 0; mm < R; ++mm) d[(k_of<R>(u, mm, loL) << 8) + c0 + lane] = mul_shoup(v[mm], ni, nis, q);
+}
+
+template <int R>
+static void launch_nttr(const Tables &T, uint64_t *dst, const uint64_t *src, size_t src_poly_stride, int nlimb,
+                        int npoly, const LimbMap &m, bool inverse, hipStream_t s) {
+    dim3 grid(16, nlimb * npoly), block(Geo<R>::NT);
+    if (!inverse) {
+        hipLaunchKernelGGL(k_nttr_rows_fwd<R>, grid, block, 0, s, dst, src, src_poly_stride, nlimb, npoly, m, T);
+        hipLaunchKernelGGL(k_nttr_blocks_fwd<R>, grid, block, 0, s, dst, nlimb, npoly, m, T);
+    } else {
+        hipLaunchKernelGGL(k_nttr_blocks_inv<R>, grid, block, 0, s, dst, src, src_poly_stride, nlimb, npoly, m, T);
+        hipLaunchKernelGGL(k_nttr_rows_inv<R>, grid, block, 0, s, dst, nlimb, npoly, m, T);
+    }
 }
 
 void ntt_oop(const Tables &T, uint64_t *dst, const uint64_t *src, size_t src_poly_stride, int nlimb, int npoly,
@@ -389,6 +667,16 @@ void ntt_oop(const Tables &T, uint64_t *dst, const uint64_t *src, size_t src_pol
     const size_t N = (size_t)1 << T.logN;
     if (src_poly_stride == 0) src_poly_stride = (size_t)nlimb * N;
     if (T.logN == 16) {
+        // words per thread from the call's size (tunable per context): short
+        // per-wave chains for small calls, fewer LDS exchanges for large ones
+        if (total <= T.ntt_r4_max) {
+            launch_nttr<4>(T, dst, src, src_poly_stride, nlimb, npoly, m, inverse, s);
+            return;
+        }
+        if (total <= T.ntt_r8_max) {
+            launch_nttr<8>(T, dst, src, src_poly_stride, nlimb, npoly, m, inverse, s);
+            return;
+        }
         dim3 grid(16, total);
         if (!inverse) {
             hipLaunchKernelGGL(k_ntt16_rows_fwd, grid, dim3(256), 0, s, dst, src, src_poly_stride, nlimb, npoly, m,

@@ -99,6 +99,36 @@ def test_ntt_bit_exact(pair12, pair16, which):
         assert np.array_equal(got2[i], o.intt(int(i), host[i])), f"inverse limb {i}"
 
 
+@pytest.mark.parametrize("words_per_thread", [4, 8, 16])
+def test_ntt16_schedules_bit_exact(pair16, words_per_thread):
+    """Every N = 2^16 transform variant (4, 8 or 16 words per thread) against
+    the oracle's negacyclic NTT, on single limbs, a ragged count and all limbs
+    of the chain (60-bit and 40-bit primes), including all-(q-1) limbs."""
+    import torch
+    g, o = pair16
+    big = 1 << 20
+    g.ntt_schedule(*{4: (big, big), 8: (0, big), 16: (0, 0)}[words_per_thread])
+    try:
+        for n in (1, 3, g.np_):
+            idx = np.array([(5 * i + 1) % g.np_ for i in range(n)], dtype=np.uint32)
+            host = inputs.uniform_words((g.np_, g.N), g.primes, 43 + n)[idx]
+            host[0] = g.primes[idx[0]] - 1
+            dev = torch.from_numpy(host.view(np.int64)).cuda()
+            g.ntt_device(dev.data_ptr(), n, idx, inverse=False)
+            torch.cuda.synchronize()
+            got = dev.cpu().numpy().view(np.uint64)
+            for i in range(n):
+                assert np.array_equal(got[i], o.ntt(int(idx[i]), host[i])), f"forward {n} limbs, limb {i}"
+            dev2 = torch.from_numpy(host.view(np.int64)).cuda()
+            g.ntt_device(dev2.data_ptr(), n, idx, inverse=True)
+            torch.cuda.synchronize()
+            got2 = dev2.cpu().numpy().view(np.uint64)
+            for i in range(n):
+                assert np.array_equal(got2[i], o.intt(int(idx[i]), host[i])), f"inverse {n} limbs, limb {i}"
+    finally:
+        g.ntt_schedule(-1, -1)
+
+
 def test_encrypt_decrypt_parity(pair12):
     g, o = pair12
     x = inputs.log_uniform(g.n, 2 ** -8, 1.0, 1)
