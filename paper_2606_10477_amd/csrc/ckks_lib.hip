@@ -1086,7 +1086,25 @@ Ct op_lt(ckks_ctx *c, const ckks_ct *x, const LtStage &st) {
     std::stable_partition(gis.begin(), gis.end(), [](int gi) { return gi != 0; });
     const size_t N = c->N, member = (size_t)2 * nq * N, gstride = member * B;
     Buf inner(c->pool.get(), gstride * gis.size());
-    for (size_t k = 0; k < gis.size(); ++k) {
+    if (bs.size() + 1 <= (size_t)gpu::kMaxBaby && gis.size() <= (size_t)gpu::kMaxGiant) {
+        // every inner sum in one pass over the babies
+        gpu::GiantArgs ga{};
+        ga.nb = (int)bs.size() + 1;
+        ga.ng = (int)gis.size();
+        ga.x[0] = x->buf.p;
+        for (size_t t = 0; t < bs.size(); ++t) ga.x[t + 1] = R[bs[t]]->buf.p;
+        for (size_t k = 0; k < gis.size(); ++k) {
+            for (size_t t = 0; t < st.giant.size(); ++t) {
+                if (st.giant[t] != gis[k]) continue;
+                const int b = st.baby[t];
+                const int bi = b == 0 ? 0 : 1 + (int)(std::find(bs.begin(), bs.end(), b) - bs.begin());
+                if (ga.pt[k][bi]) fail(CKKS_E_PARAM, "repeated diagonal in a slot transform");
+                ga.pt[k][bi] = st.pt[t].p;
+            }
+            trace_op(c, "mul_plain", x->level, B);
+        }
+        gpu::pt_mac_giants(c->T, inner.p, gstride, ga, nq, B, map_q(0, nq), c->stream);
+    } else for (size_t k = 0; k < gis.size(); ++k) {
         gpu::MacArgs ma{};
         for (size_t t = 0; t < st.giant.size(); ++t) {
             if (st.giant[t] != gis[k]) continue;

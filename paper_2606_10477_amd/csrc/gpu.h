@@ -143,6 +143,20 @@ struct MacArgs {
 void pt_mac(const Tables &T, uint64_t *out, const MacArgs &a, int nlimb, int npoly, const LimbMap &m,
             hipStream_t s);
 
+// All giant-step inner sums of a baby-step giant-step transform in one pass:
+// out[k][member][p] = sum_b pt[k][b] * x_b[member][p] over the babies b with a
+// plaintext (pt[k][b] non-null), p = 0, 1; every baby word is read once.
+// Layouts: x_b and out[k] as ciphertext batches [B][2][nlimb][N] (out[k] at
+// out + k * gstride); plaintexts [nlimb][N].
+constexpr int kMaxBaby = 16, kMaxGiant = 16;
+struct GiantArgs {
+    int nb, ng;
+    const uint64_t *x[kMaxBaby];
+    const uint64_t *pt[kMaxGiant][kMaxBaby];
+};
+void pt_mac_giants(const Tables &T, uint64_t *out, size_t gstride, const GiantArgs &a, int nlimb, int B,
+                   const LimbMap &m, hipStream_t s);
+
 // Rotation key-switch jobs over one ModUp of nct inputs: job t applies key
 // key[t] to the B inputs ct0[t] .. ct0[t]+B-1, reading their digits through
 // perm[t] (the automorphism's NTT-domain index map).  acc is laid out

@@ -953,13 +953,17 @@ void sub_mul(const Tables &T, uint64_t *out, const uint64_t *c, const uint64_t *
 // scaled by [Dhat_i^-1]_{q_i} (kept in registers: DIN is a template
 // parameter, so the arrays are fully unrolled), then each output limb is one
 // 128-bit multiply-accumulate over them, reduced once.
+// blockIdx.z splits the output limbs into chunks of `per` (each chunk scales
+// the inputs again): more and shorter waves when a call covers few polys.
 template <int DIN>
 __global__ void __launch_bounds__(256) k_bconv(u64 *out, const u64 *in, BconvArgs a, int logN, size_t in_stride,
-                                               size_t out_stride, Tables T) {
+                                               size_t out_stride, int per, Tables T) {
     const size_t N = (size_t)1 << logN;
     const int poly = blockIdx.y;
     const size_t j = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (j >= N) return;
+    const int r0 = blockIdx.z * per;
+    const int r1 = r0 + per < a.dout ? r0 + per : a.dout;
     u64 y[DIN];
     const u64 *src = in + poly * in_stride;
 #pragma unroll
@@ -968,7 +972,7 @@ __global__ void __launch_bounds__(256) k_bconv(u64 *out, const u64 *in, BconvArg
         y[i] = mul_shoup(src[(size_t)i * N + j], a.hinv[i], a.hinv_sh[i], q);
     }
     u64 *dst = out + poly * out_stride;
-    for (int r = 0; r < a.dout; ++r) {
+    for (int r = r0; r < r1; ++r) {
         const DevPrime P = T.primes[a.pout.p[r]];
         u64 hi = 0, lo = 0;
 #pragma unroll
@@ -980,8 +984,17 @@ template <int DIN>
 static void bconv_launch(const Tables &T, uint64_t *out, const uint64_t *in, const BconvArgs &a, int npoly,
                          size_t in_poly_stride, size_t out_poly_stride, hipStream_t s) {
     const size_t N = (size_t)1 << T.logN;
-    dim3 grid((unsigned)((N + 255) / 256), npoly);
-    hipLaunchKernelGGL(k_bconv<DIN>, grid, dim3(256), 0, s, out, in, a, T.logN, in_poly_stride, out_poly_stride, T);
+    const int bx = (int)((N + 255) / 256);
+    // aim at >= 2048 blocks (8 waves per SIMD) with chunks of >= 4 outputs
+    int nchunk = (2048 + bx * npoly - 1) / (bx * npoly);
+    const int max_chunk = (a.dout + 3) / 4;
+    if (nchunk > max_chunk) nchunk = max_chunk;
+    if (nchunk < 1) nchunk = 1;
+    const int per = (a.dout + nchunk - 1) / nchunk;
+    nchunk = (a.dout + per - 1) / per;
+    dim3 grid((unsigned)bx, npoly, nchunk);
+    hipLaunchKernelGGL(k_bconv<DIN>, grid, dim3(256), 0, s, out, in, a, T.logN, in_poly_stride, out_poly_stride, per,
+                       T);
 }
 void bconv(const Tables &T, uint64_t *out, const uint64_t *in, const BconvArgs &a, int npoly, size_t in_poly_stride,
            size_t out_poly_stride, hipStream_t s) {
@@ -1138,6 +1151,62 @@ void pt_mac(const Tables &T, uint64_t *out, const MacArgs &a, int nlimb, int npo
     size_t total = ((size_t)nlimb * npoly) << T.logN;
     if (!total) return;
     hipLaunchKernelGGL(k_pt_mac, grid_for(total), dim3(256), 0, s, out, a, T.logN, nlimb, total, m, T);
+}
+
+// one thread per (member, limb, word): both polys of every baby in registers
+// (NB is a template parameter so that the arrays stay in registers), then one
+// accumulation per giant
+template <int NB>
+__global__ void __launch_bounds__(256) k_pt_mac_giants(u64 *out, size_t gstride, GiantArgs a, int logN, int nlimb,
+                                                       size_t total, LimbMap m, Tables T) {
+    const size_t N = (size_t)1 << logN;
+    const size_t per = (size_t)nlimb << logN;   // words of one poly
+    GRID_LOOP(i, total) {
+        const uint32_t row = (uint32_t)(i >> logN);
+        const uint32_t mb = row / (uint32_t)nlimb;
+        const uint32_t e = row - mb * (uint32_t)nlimb;
+        const size_t rem = ((size_t)e << logN) | (i & (N - 1));
+        const size_t base = (size_t)mb * 2 * per + rem;
+        const DevPrime P = T.primes[m.p[e]];
+        u64 x0[NB], x1[NB];
+#pragma unroll
+        for (int b = 0; b < NB; ++b) {
+            x0[b] = a.x[b][base];
+            x1[b] = a.x[b][base + per];
+        }
+        for (int k = 0; k < a.ng; ++k) {
+            u64 h0 = 0, l0 = 0, h1 = 0, l1 = 0;
+#pragma unroll
+            for (int b = 0; b < NB; ++b) {
+                const u64 *p = a.pt[k][b];
+                if (p) {
+                    const u64 w = p[rem];
+                    mac128(h0, l0, w, x0[b]);
+                    mac128(h1, l1, w, x1[b]);
+                }
+            }
+            u64 *o = out + k * gstride + base;
+            o[0] = reduce128(h0, l0, P);
+            o[per] = reduce128(h1, l1, P);
+        }
+    }
+}
+void pt_mac_giants(const Tables &T, uint64_t *out, size_t gstride, const GiantArgs &a, int nlimb, int B,
+                   const LimbMap &m, hipStream_t s) {
+    const size_t total = ((size_t)nlimb * B) << T.logN;
+    if (!total || a.ng <= 0) return;
+    switch (a.nb) {
+#define GIANT_CASE(D)                                                                                            \
+    case D:                                                                                                      \
+        hipLaunchKernelGGL(k_pt_mac_giants<D>, grid_for(total), dim3(256), 0, s, out, gstride, a, T.logN, nlimb, \
+                           total, m, T);                                                                         \
+        break;
+        GIANT_CASE(1) GIANT_CASE(2) GIANT_CASE(3) GIANT_CASE(4) GIANT_CASE(5) GIANT_CASE(6) GIANT_CASE(7)
+        GIANT_CASE(8) GIANT_CASE(9) GIANT_CASE(10) GIANT_CASE(11) GIANT_CASE(12) GIANT_CASE(13) GIANT_CASE(14)
+        GIANT_CASE(15) GIANT_CASE(16)
+#undef GIANT_CASE
+        default: break;   // the host checks nb <= kMaxBaby
+    }
 }
 
 __global__ void k_lincomb(u64 *out, CombArgs a, int logN, int nlimb, size_t total, LimbMap m, Tables T) {
