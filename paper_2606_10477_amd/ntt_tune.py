@@ -1,0 +1,90 @@
+"""Tuner of the N = 2^16 transform schedule: times forward and inverse NTT
+calls of several sizes with 4, 8 and 16 words per thread on this GPU and picks
+the limb-count bounds for ckks_ntt_schedule (the largest call sizes at which
+the 4- and 8-word variants are still the fastest).  Results are identical
+under every schedule; only the time changes.
+
+    python -m paper_2606_10477_amd.ntt_tune [--limbs 1,2,4,...] [--json PATH]
+"""
+import argparse
+import json
+import time
+
+SIZES = (1, 2, 3, 4, 6, 8, 10, 12, 16, 20, 24, 28, 32, 40, 48, 64, 96)
+BIG = 1 << 20
+VARIANTS = ((4, (BIG, BIG)), (8, (0, BIG)), (16, (0, 0)))
+
+
+def time_calls(ctx, x, n, idx, inverse, reps):
+    ctx.ntt_device(x.data_ptr(), n, idx, inverse=inverse)
+    ctx.sync()
+    t0 = time.perf_counter()
+    for _ in range(reps):
+        ctx.ntt_device(x.data_ptr(), n, idx, inverse=inverse)
+    ctx.sync()
+    return (time.perf_counter() - t0) / reps
+
+
+def scan(ctx, sizes, nprimes):
+    import numpy as np
+    import torch
+    rows = []
+    for n in sizes:
+        # a mix of all primes of the chain (40/52/60-bit), as in the key switch
+        idx = np.array([(7 * i) % nprimes for i in range(n)], dtype=np.uint32)
+        x = torch.randint(0, 1 << 30, (n, 1 << 16), dtype=torch.int64, device="cuda")
+        reps = max(10, 600 // n)
+        row = {"limbs": n}
+        for R, sched in VARIANTS:
+            ctx.ntt_schedule(*sched)
+            row[f"fwd_R{R}_us"] = 1e6 * time_calls(ctx, x, n, idx, False, reps)
+            row[f"inv_R{R}_us"] = 1e6 * time_calls(ctx, x, n, idx, True, reps)
+        rows.append(row)
+        print(json.dumps({k: round(v, 1) if isinstance(v, float) else v for k, v in row.items()}), flush=True)
+    ctx.ntt_schedule(-1, -1)
+    return rows
+
+
+def choose(rows):
+    """Bounds (r4_max, r8_max): every call size up to r4_max is fastest (fwd +
+    inv) with 4 words per thread, up to r8_max with 4 or 8."""
+    best = []
+    for r in rows:
+        t = {R: r[f"fwd_R{R}_us"] + r[f"inv_R{R}_us"] for R, _ in VARIANTS}
+        best.append((r["limbs"], min(t, key=t.get)))
+    r4 = 0
+    for n, R in best:
+        if R != 4:
+            break
+        r4 = n
+    r8 = r4
+    for n, R in best:
+        if n <= r4:
+            continue
+        if R != 8:
+            break
+        r8 = n
+    return r4, r8, best
+
+
+def main(argv=None):
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--limbs", default=",".join(str(s) for s in SIZES))
+    ap.add_argument("--json", default=None)
+    a = ap.parse_args(argv)
+    import torch
+    from . import ckks
+    torch.cuda.set_device(0)
+    ctx = ckks.Context(log_n=16, max_level=7, num_special=7, digit_size=8, hamming_weight=192, bts=(3, 10, 3, 52))
+    rows = scan(ctx, [int(s) for s in a.limbs.split(",")], ctx.np_)
+    r4, r8, best = choose(rows)
+    res = {"r4_max_limbs": r4, "r8_max_limbs": r8, "fastest_words_per_thread": best, "rows": rows}
+    print(json.dumps({"r4_max_limbs": r4, "r8_max_limbs": r8, "fastest_words_per_thread": best}), flush=True)
+    if a.json:
+        with open(a.json, "w") as f:
+            json.dump(res, f, indent=1)
+    ctx.close()
+
+
+if __name__ == "__main__":
+    main()
