@@ -220,6 +220,7 @@ struct ckks_ctx {
     std::unique_ptr<Pool> pool;
     gpu::Tables T;
     Buf d_primes, d_fw, d_fwsh, d_iw, d_iwsh, d_ninv, d_ninvsh;
+    Buf d_rsinv, d_rsinvsh;       // [L+1][L+1]: (q_l)^-1 mod q_i and Shoup quotient, for rescale from level l
     std::string err;
     // keys
     bool have_keys = false;
@@ -414,6 +415,19 @@ void build_tables(ckks_ctx *c) {
     upload(c->d_iwsh, iwsh.data(), iwsh.size() * 8, c->stream);
     upload(c->d_ninv, ninv.data(), np * 8, c->stream);
     upload(c->d_ninvsh, ninvsh.data(), np * 8, c->stream);
+    {
+        const int L1 = c->L + 1;
+        std::vector<u64> rs((size_t)L1 * L1, 0), rssh((size_t)L1 * L1, 0);
+        for (int l = 1; l < L1; ++l)
+            for (int i = 0; i < l; ++i) {
+                rs[(size_t)l * L1 + i] = hm::invmod(c->q[l] % c->q[i], c->q[i]);
+                rssh[(size_t)l * L1 + i] = shoup(rs[(size_t)l * L1 + i], c->q[i]);
+            }
+        c->d_rsinv = Buf(P, rs.size());
+        c->d_rsinvsh = Buf(P, rs.size());
+        upload(c->d_rsinv, rs.data(), rs.size() * 8, c->stream);
+        upload(c->d_rsinvsh, rssh.data(), rssh.size() * 8, c->stream);
+    }
     c->T.primes = (const gpu::DevPrime *)c->d_primes.p;
     c->T.fw = c->d_fw.p;
     c->T.fw_sh = c->d_fwsh.p;
@@ -592,6 +606,16 @@ Ct op_rescale(ckks_ctx *c, const ckks_ct *a) {
     Buf t(c->pool.get(), np2 * N);
     ntt_oop_p(c, t.p, a->buf.p + (size_t)l * N, (size_t)(l + 1) * N, 1, np2, map_q(l, 1), true);
     Buf u(c->pool.get(), np2 * (size_t)l * N);
+    if (c->logN == 16) {
+        // lift fused into the transform's first pass, (c - u) / q_l into its last
+        const size_t L1 = (size_t)c->L + 1;
+        gpu::NttLift lf{t.p, N, l};
+        gpu::NttEpi ep{r->buf.p, a->buf.p, (size_t)(l + 1) * N, c->d_rsinv.p + (size_t)l * L1,
+                       c->d_rsinvsh.p + (size_t)l * L1};
+        ProfScope ps(c, "ntt", 16.0 * (double)l * np2 * N);
+        gpu::ntt16_fwd_fused(c->T, u.p, &lf, &ep, l, np2, map_q(0, l), c->stream);
+        return r;
+    }
     gpu::rescale_lift(c->T, u.p, t.p, l, l, np2, N, c->stream);
     ntt_p(c, u.p, l, np2, map_q(0, l), false);
     LimbConsts inv{};
@@ -1059,6 +1083,12 @@ Ct op_mod_raise(ckks_ctx *c, const ckks_ct *a) {
     Ct r = ct_new(c, L, 2.0 * (double)c->q[0] * c->bts->K, B);
     Buf t(c->pool.get(), (size_t)np2 * N);
     ntt_oop_p(c, t.p, a->buf.p, (size_t)(a->level + 1) * N, 1, np2, map_q(0, 1), true);
+    if (c->logN == 16) {
+        gpu::NttLift lf{t.p, N, 0};   // the lift fused into the transform's first pass
+        ProfScope ps(c, "ntt", 16.0 * (double)(L + 1) * np2 * N);
+        gpu::ntt16_fwd_fused(c->T, r->buf.p, &lf, nullptr, L + 1, np2, map_q(0, L + 1), c->stream);
+        return r;
+    }
     gpu::rescale_lift(c->T, r->buf.p, t.p, 0, L + 1, np2, N, c->stream);
     ntt_p(c, r->buf.p, L + 1, np2, map_q(0, L + 1), false);
     return r;

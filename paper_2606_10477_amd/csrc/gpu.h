@@ -37,6 +37,28 @@ struct Tables {
     int ntt_r4_max, ntt_r8_max;
 };
 
+// Forward N = 2^16 NTT with a fused source and epilogue (rescale / ModRaise):
+//   lift (non-null): the input of limb e of poly p is the centred lift of
+//     t[p * t_stride + j] (coefficient form mod q_top) to limb e's prime,
+//     instead of work's contents;
+//   epi (non-null): the transform's output x is not stored in work; instead
+//     out[p][e][j] = (c[p * c_stride + e * N + j] - x) * inv[e] mod q_e
+//     (inv / inv_sh: per-limb constant and Shoup quotient, device arrays).
+// work ([npoly][nlimb][N]) holds the intermediate between the two passes.
+struct NttLift {
+    const uint64_t *t;
+    size_t t_stride;
+    int top;
+};
+struct NttEpi {
+    uint64_t *out;
+    const uint64_t *c;
+    size_t c_stride;
+    const uint64_t *inv, *inv_sh;
+};
+void ntt16_fwd_fused(const Tables &T, uint64_t *work, const NttLift *lift, const NttEpi *epi, int nlimb, int npoly,
+                     const LimbMap &m, hipStream_t s);
+
 // Batched in-place NTT / inverse NTT of nlimb * npoly limbs.
 void ntt(const Tables &T, uint64_t *data, int nlimb, int npoly, const LimbMap &m, bool inverse,
          hipStream_t s);

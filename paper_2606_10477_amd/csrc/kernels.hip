@@ -189,6 +189,23 @@ __global__ void __launch_bounds__(kThreads) k_ntt_strided(u64 *data, int logN, i
     }
 }
 
+// centred lift of a word mod q_top to the prime of index pi (rescale, ModRaise)
+struct Lifter {
+    u64 half, qt_mod;
+    DevPrime P;
+    DEV Lifter(const Tables &T, int top, int pi) : P(T.primes[pi]) {
+        const u64 qt = T.primes[top].q;
+        half = (qt - 1) >> 1;
+        qt_mod = reduce64(qt, P);
+    }
+    DEV u64 operator()(u64 v) const {
+        const u64 r = reduce64(v, P);
+        return v > half ? sub_mod(r, qt_mod, P.q) : r;
+    }
+};
+// epilogue of a fused forward transform: (c - x) * inv mod q
+DEV u64 epi_word(u64 x, u64 c, u64 iv, u64 ivs, u64 q) { return mul_shoup(sub_mod(c, x, q), iv, ivs, q); }
+
 // ---------------------------------------------------------------------------
 // N = 2^16: two passes of 8 stages, each split into two radix-16 register
 // phases (4 butterfly stages on 16 words held by one thread) around one LDS
@@ -296,14 +313,15 @@ __device__ __forceinline__ void inv16(u64 v[16], const u64 *W, const u64 *Ws, in
     const uint32_t pidx = y_ - lidx * (uint32_t)(npoly);                      \
     const size_t row_off = ((size_t)pidx * (uint32_t)(nlimb) + lidx) << 16;
 
+template <bool LIFT>
 __global__ void __launch_bounds__(256) k_ntt16_rows_fwd(u64 *dst, const u64 *src, size_t src_stride, int nlimb,
-                                                         int npoly, LimbMap m, Tables T) {
+                                                         int npoly, LimbMap m, Tables T, NttLift lf) {
     __shared__ u64 tile[256 * kPad];
     NTT16_INDEX(nlimb, npoly)
     const int pi = m.p[lidx];
     const u64 q = T.primes[pi].q;
     const u64 *W = T.fw + ((size_t)pi << 16), *Ws = T.fw_sh + ((size_t)pi << 16);
-    const u64 *in = src + (size_t)pidx * src_stride + ((size_t)lidx << 16);
+    const u64 *in = LIFT ? lf.t + (size_t)pidx * lf.t_stride : src + (size_t)pidx * src_stride + ((size_t)lidx << 16);
     u64 *out = dst + row_off;
     const int c0 = blockIdx.x * 16;
     const int x = threadIdx.x & 15, y = threadIdx.x >> 4;
@@ -311,6 +329,11 @@ __global__ void __launch_bounds__(256) k_ntt16_rows_fwd(u64 *dst, const u64 *src
     // phase 1: rows k = y + 16 m, column x; stages 0..3 (row distances 128..16)
 #pragma unroll
     for (int mm = 0; mm < 16; ++mm) v[mm] = in[((y + 16 * mm) << 8) + c0 + x];
+    if (LIFT) {
+        const Lifter L(T, lf.top, pi);
+#pragma unroll
+        for (int mm = 0; mm < 16; ++mm) v[mm] = L(v[mm]);
+    }
     const bool small = q < kSmallPrime;
     if (small) fwd16<true>(v, W, Ws, 0, 0, q);
     else fwd16<false>(v, W, Ws, 0, 0, q);
@@ -328,7 +351,9 @@ __global__ void __launch_bounds__(256) k_ntt16_rows_fwd(u64 *dst, const u64 *src
 }
 
 // forward pass over 256-word blocks (stages 8..15), in place
-__global__ void __launch_bounds__(256) k_ntt16_blocks_fwd(u64 *data, int nlimb, int npoly, LimbMap m, Tables T) {
+template <bool EPI>
+__global__ void __launch_bounds__(256) k_ntt16_blocks_fwd(u64 *data, int nlimb, int npoly, LimbMap m, Tables T,
+                                                           NttEpi ep) {
     __shared__ u64 tile[256 * kPad];
     NTT16_INDEX(nlimb, npoly)
     const int pi = m.p[lidx];
@@ -365,8 +390,20 @@ __global__ void __launch_bounds__(256) k_ntt16_blocks_fwd(u64 *data, int nlimb, 
 #pragma unroll
     for (int mm = 0; mm < 16; ++mm) tile[(y * 16 + x) * kPad + mm] = v[mm];
     __syncthreads();
+    if (EPI) {
+        const size_t off = ((size_t)blockIdx.x << 12);
+        const u64 *cc = ep.c + (size_t)pidx * ep.c_stride + ((size_t)lidx << 16) + off;
+        u64 *o = ep.out + row_off + off;
+        const u64 iv = ep.inv[lidx], ivs = ep.inv_sh[lidx];
 #pragma unroll
-    for (int mm = 0; mm < 16; ++mm) d[(y << 8) + x + 16 * mm] = tile[(y * 16 + mm) * kPad + x];
+        for (int mm = 0; mm < 16; ++mm) {
+            const int at = (y << 8) + x + 16 * mm;
+            o[at] = epi_word(tile[(y * 16 + mm) * kPad + x], cc[at], iv, ivs, q);
+        }
+    } else {
+#pragma unroll
+        for (int mm = 0; mm < 16; ++mm) d[(y << 8) + x + 16 * mm] = tile[(y * 16 + mm) * kPad + x];
+    }
 }
 
 // inverse pass over 256-word blocks (half-distances 1..128): reads src, writes dst
@@ -553,15 +590,15 @@ __device__ __forceinline__ void pass_phases(u64 *v, u64 *tile, int lane, int u, 
 }
 
 // forward rows pass (stages 0..7): src -> dst
-template <int R>
+template <int R, bool LIFT>
 __global__ void __launch_bounds__(Geo<R>::NT) k_nttr_rows_fwd(u64 *dst, const u64 *src, size_t src_stride, int nlimb,
-                                                               int npoly, LimbMap m, Tables T) {
+                                                               int npoly, LimbMap m, Tables T, NttLift lf) {
     __shared__ u64 tile[256 * kPad];
     NTT16_INDEX(nlimb, npoly)
     const int pi = m.p[lidx];
     const u64 q = T.primes[pi].q;
     const u64 *W = T.fw + ((size_t)pi << 16), *Ws = T.fw_sh + ((size_t)pi << 16);
-    const u64 *in = src + (size_t)pidx * src_stride + ((size_t)lidx << 16);
+    const u64 *in = LIFT ? lf.t + (size_t)pidx * lf.t_stride : src + (size_t)pidx * src_stride + ((size_t)lidx << 16);
     u64 *out = dst + row_off;
     const int c0 = blockIdx.x * 16;
     const int lane = threadIdx.x & 15, u = threadIdx.x >> 4;
@@ -569,15 +606,20 @@ __global__ void __launch_bounds__(Geo<R>::NT) k_nttr_rows_fwd(u64 *dst, const u6
     u64 v[R];
 #pragma unroll
     for (int mm = 0; mm < R; ++mm) v[mm] = in[(k_of<R>(u, mm, lo0) << 8) + c0 + lane];
+    if (LIFT) {
+        const Lifter L(T, lf.top, pi);
+#pragma unroll
+        for (int mm = 0; mm < R; ++mm) v[mm] = L(v[mm]);
+    }
     if (q < kSmallPrime) pass_phases<R, true, true, true>(v, tile, lane, u, 0, W, Ws, q);
     else pass_phases<R, true, true, false>(v, tile, lane, u, 0, W, Ws, q);
 #pragma unroll
     for (int mm = 0; mm < R; ++mm) out[(k_of<R>(u, mm, loL) << 8) + c0 + lane] = v[mm];
 }
 // forward blocks pass (stages 8..15), in place, output reduced to [0, q)
-template <int R>
+template <int R, bool EPI>
 __global__ void __launch_bounds__(Geo<R>::NT) k_nttr_blocks_fwd(u64 *data, int nlimb, int npoly, LimbMap m,
-                                                                 Tables T) {
+                                                                 Tables T, NttEpi ep) {
     __shared__ u64 tile[256 * kPad];
     NTT16_INDEX(nlimb, npoly)
     const int pi = m.p[lidx];
@@ -600,8 +642,20 @@ __global__ void __launch_bounds__(Geo<R>::NT) k_nttr_blocks_fwd(u64 *data, int n
 #pragma unroll
         for (int mm = 0; mm < R; ++mm) v[mm] = reduce_4q(v[mm], q);
     }
+    if (EPI) {
+        const size_t off = ((size_t)blockIdx.x << 12);
+        const u64 *cc = ep.c + (size_t)pidx * ep.c_stride + ((size_t)lidx << 16) + off;
+        u64 *o = ep.out + row_off + off;
+        const u64 iv = ep.inv[lidx], ivs = ep.inv_sh[lidx];
 #pragma unroll
-    for (int mm = 0; mm < R; ++mm) d[(lane << 8) + k_of<R>(u, mm, loL)] = v[mm];
+        for (int mm = 0; mm < R; ++mm) {
+            const int at = (lane << 8) + k_of<R>(u, mm, loL);
+            o[at] = epi_word(v[mm], cc[at], iv, ivs, q);
+        }
+    } else {
+#pragma unroll
+        for (int mm = 0; mm < R; ++mm) d[(lane << 8) + k_of<R>(u, mm, loL)] = v[mm];
+    }
 }
 // inverse blocks pass (half-distances 1..128): src -> dst
 template <int R>
@@ -652,12 +706,42 @@ static void launch_nttr(const Tables &T, uint64_t *dst, const uint64_t *src, siz
                         int npoly, const LimbMap &m, bool inverse, hipStream_t s) {
     dim3 grid(16, nlimb * npoly), block(Geo<R>::NT);
     if (!inverse) {
-        hipLaunchKernelGGL(k_nttr_rows_fwd<R>, grid, block, 0, s, dst, src, src_poly_stride, nlimb, npoly, m, T);
-        hipLaunchKernelGGL(k_nttr_blocks_fwd<R>, grid, block, 0, s, dst, nlimb, npoly, m, T);
+        k_nttr_rows_fwd<R, false><<<grid, block, 0, s>>>(dst, src, src_poly_stride, nlimb, npoly, m, T, NttLift{});
+        k_nttr_blocks_fwd<R, false><<<grid, block, 0, s>>>(dst, nlimb, npoly, m, T, NttEpi{});
     } else {
         hipLaunchKernelGGL(k_nttr_blocks_inv<R>, grid, block, 0, s, dst, src, src_poly_stride, nlimb, npoly, m, T);
         hipLaunchKernelGGL(k_nttr_rows_inv<R>, grid, block, 0, s, dst, nlimb, npoly, m, T);
     }
+}
+
+void ntt16_fwd_fused(const Tables &T, uint64_t *work, const NttLift *lift, const NttEpi *epi, int nlimb, int npoly,
+                     const LimbMap &m, hipStream_t s) {
+    const int total = nlimb * npoly;
+    if (total == 0 || T.logN != 16) return;
+    const NttLift lf = lift ? *lift : NttLift{};
+    const NttEpi ep = epi ? *epi : NttEpi{};
+    const size_t stride = (size_t)nlimb << 16;
+    dim3 grid(16, total);
+    if (total <= T.ntt_r4_max || total <= T.ntt_r8_max) {
+        const bool r4 = total <= T.ntt_r4_max;
+        dim3 block(r4 ? Geo<4>::NT : Geo<8>::NT);
+        if (r4) {
+            if (lift) k_nttr_rows_fwd<4, true><<<grid, block, 0, s>>>(work, work, stride, nlimb, npoly, m, T, lf);
+            else k_nttr_rows_fwd<4, false><<<grid, block, 0, s>>>(work, work, stride, nlimb, npoly, m, T, lf);
+            if (epi) k_nttr_blocks_fwd<4, true><<<grid, block, 0, s>>>(work, nlimb, npoly, m, T, ep);
+            else k_nttr_blocks_fwd<4, false><<<grid, block, 0, s>>>(work, nlimb, npoly, m, T, ep);
+        } else {
+            if (lift) k_nttr_rows_fwd<8, true><<<grid, block, 0, s>>>(work, work, stride, nlimb, npoly, m, T, lf);
+            else k_nttr_rows_fwd<8, false><<<grid, block, 0, s>>>(work, work, stride, nlimb, npoly, m, T, lf);
+            if (epi) k_nttr_blocks_fwd<8, true><<<grid, block, 0, s>>>(work, nlimb, npoly, m, T, ep);
+            else k_nttr_blocks_fwd<8, false><<<grid, block, 0, s>>>(work, nlimb, npoly, m, T, ep);
+        }
+        return;
+    }
+    if (lift) k_ntt16_rows_fwd<true><<<grid, dim3(256), 0, s>>>(work, work, stride, nlimb, npoly, m, T, lf);
+    else k_ntt16_rows_fwd<false><<<grid, dim3(256), 0, s>>>(work, work, stride, nlimb, npoly, m, T, lf);
+    if (epi) k_ntt16_blocks_fwd<true><<<grid, dim3(256), 0, s>>>(work, nlimb, npoly, m, T, ep);
+    else k_ntt16_blocks_fwd<false><<<grid, dim3(256), 0, s>>>(work, nlimb, npoly, m, T, ep);
 }
 
 void ntt_oop(const Tables &T, uint64_t *dst, const uint64_t *src, size_t src_poly_stride, int nlimb, int npoly,
@@ -679,9 +763,9 @@ void ntt_oop(const Tables &T, uint64_t *dst, const uint64_t *src, size_t src_pol
         }
         dim3 grid(16, total);
         if (!inverse) {
-            hipLaunchKernelGGL(k_ntt16_rows_fwd, grid, dim3(256), 0, s, dst, src, src_poly_stride, nlimb, npoly, m,
-                               T);
-            hipLaunchKernelGGL(k_ntt16_blocks_fwd, grid, dim3(256), 0, s, dst, nlimb, npoly, m, T);
+            k_ntt16_rows_fwd<false><<<grid, dim3(256), 0, s>>>(dst, src, src_poly_stride, nlimb, npoly, m, T,
+                                                               NttLift{});
+            k_ntt16_blocks_fwd<false><<<grid, dim3(256), 0, s>>>(dst, nlimb, npoly, m, T, NttEpi{});
         } else {
             hipLaunchKernelGGL(k_ntt16_blocks_inv, grid, dim3(256), 0, s, dst, src, src_poly_stride, nlimb, npoly, m,
                                T);
