@@ -221,6 +221,7 @@ struct ckks_ctx {
     gpu::Tables T;
     Buf d_primes, d_fw, d_fwsh, d_iw, d_iwsh, d_ninv, d_ninvsh;
     Buf d_rsinv, d_rsinvsh;       // [L+1][L+1]: (q_l)^-1 mod q_i and Shoup quotient, for rescale from level l
+    Buf d_pinv, d_pinvsh;         // [L+1]: P^-1 mod q_i and Shoup quotient (ModDown)
     std::string err;
     // keys
     bool have_keys = false;
@@ -370,6 +371,8 @@ void ntt_oop_p(ckks_ctx *c, uint64_t *dst, const uint64_t *src, size_t src_strid
 // ---------------------------------------------------------------------------
 // context construction
 // ---------------------------------------------------------------------------
+u64 prod_mod(const ckks_ctx *c, const std::vector<int> &idx, int skip, u64 m);
+
 void build_tables(ckks_ctx *c) {
     const int N = c->N, np = c->np;
     std::vector<gpu::DevPrime> dp(np);
@@ -423,6 +426,17 @@ void build_tables(ckks_ctx *c) {
                 rs[(size_t)l * L1 + i] = hm::invmod(c->q[l] % c->q[i], c->q[i]);
                 rssh[(size_t)l * L1 + i] = shoup(rs[(size_t)l * L1 + i], c->q[i]);
             }
+        std::vector<u64> pv(L1), pvsh(L1);
+        std::vector<int> sp;
+        for (int k = 0; k < c->K; ++k) sp.push_back(c->L + 1 + k);
+        for (int i = 0; i < L1; ++i) {
+            pv[i] = hm::invmod(prod_mod(c, sp, -1, c->q[i]), c->q[i]);
+            pvsh[i] = shoup(pv[i], c->q[i]);
+        }
+        c->d_pinv = Buf(P, L1);
+        c->d_pinvsh = Buf(P, L1);
+        upload(c->d_pinv, pv.data(), L1 * 8, c->stream);
+        upload(c->d_pinvsh, pvsh.data(), L1 * 8, c->stream);
         c->d_rsinv = Buf(P, rs.size());
         c->d_rsinvsh = Buf(P, rs.size());
         upload(c->d_rsinv, rs.data(), rs.size() * 8, c->stream);
@@ -611,7 +625,7 @@ Ct op_rescale(ckks_ctx *c, const ckks_ct *a) {
         const size_t L1 = (size_t)c->L + 1;
         gpu::NttLift lf{t.p, N, l};
         gpu::NttEpi ep{r->buf.p, a->buf.p, (size_t)(l + 1) * N, c->d_rsinv.p + (size_t)l * L1,
-                       c->d_rsinvsh.p + (size_t)l * L1};
+                       c->d_rsinvsh.p + (size_t)l * L1, nullptr, 0};
         ProfScope ps(c, "ntt", 16.0 * (double)l * np2 * N);
         gpu::ntt16_fwd_fused(c->T, u.p, &lf, &ep, l, np2, map_q(0, l), c->stream);
         return r;
@@ -693,6 +707,13 @@ void ks_finish(ckks_ctx *c, const ModUp &mu, const SwitchKey &key, const int32_t
     Buf z(P, (size_t)np2 * nq * N);
     gpu::BconvArgs bd{md->pin, md->pout, md->din, md->dout, md->hinv.p, md->hinv_sh.p, md->mat.p};
     gpu::bconv(c->T, z.p, y.p, bd, np2, (size_t)c->K * N, (size_t)nq * N, c->stream);
+    if (c->logN == 16) {
+        // (acc - z) P^-1 (+ add) fused into the transform's last pass
+        gpu::NttEpi ep{out, acc.p, (size_t)ne * N, c->d_pinv.p, c->d_pinvsh.p, add, add_mask};
+        ProfScope ps(c, "ntt", 16.0 * (double)nq * np2 * N);
+        gpu::ntt16_fwd_fused(c->T, z.p, nullptr, &ep, nq, np2, map_q(0, nq), c->stream);
+        return;
+    }
     ntt_p(c, z.p, nq, np2, map_q(0, nq), false);
     LimbConsts pinv{};
     std::vector<int> pidx;

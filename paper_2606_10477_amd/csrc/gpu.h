@@ -43,7 +43,9 @@ struct Tables {
 //     instead of work's contents;
 //   epi (non-null): the transform's output x is not stored in work; instead
 //     out[p][e][j] = (c[p * c_stride + e * N + j] - x) * inv[e] mod q_e
-//     (inv / inv_sh: per-limb constant and Shoup quotient, device arrays).
+//     (inv / inv_sh: per-limb constant and Shoup quotient, device arrays),
+//     plus add[p][e][j] (same layout as out) when add is non-null and bit
+//     (p & 1) of add_mask is set (ModDown's finish).
 // work ([npoly][nlimb][N]) holds the intermediate between the two passes.
 struct NttLift {
     const uint64_t *t;
@@ -55,6 +57,8 @@ struct NttEpi {
     const uint64_t *c;
     size_t c_stride;
     const uint64_t *inv, *inv_sh;
+    const uint64_t *add;
+    int add_mask;
 };
 void ntt16_fwd_fused(const Tables &T, uint64_t *work, const NttLift *lift, const NttEpi *epi, int nlimb, int npoly,
                      const LimbMap &m, hipStream_t s);

@@ -395,10 +395,12 @@ __global__ void __launch_bounds__(256) k_ntt16_blocks_fwd(u64 *data, int nlimb, 
         const u64 *cc = ep.c + (size_t)pidx * ep.c_stride + ((size_t)lidx << 16) + off;
         u64 *o = ep.out + row_off + off;
         const u64 iv = ep.inv[lidx], ivs = ep.inv_sh[lidx];
+        const u64 *ad = ep.add && ((ep.add_mask >> (pidx & 1)) & 1) ? ep.add + row_off + off : nullptr;
 #pragma unroll
         for (int mm = 0; mm < 16; ++mm) {
             const int at = (y << 8) + x + 16 * mm;
-            o[at] = epi_word(tile[(y * 16 + mm) * kPad + x], cc[at], iv, ivs, q);
+            const u64 r = epi_word(tile[(y * 16 + mm) * kPad + x], cc[at], iv, ivs, q);
+            o[at] = ad ? add_mod(r, ad[at], q) : r;
         }
     } else {
 #pragma unroll
@@ -647,10 +649,12 @@ __global__ void __launch_bounds__(Geo<R>::NT) k_nttr_blocks_fwd(u64 *data, int n
         const u64 *cc = ep.c + (size_t)pidx * ep.c_stride + ((size_t)lidx << 16) + off;
         u64 *o = ep.out + row_off + off;
         const u64 iv = ep.inv[lidx], ivs = ep.inv_sh[lidx];
+        const u64 *ad = ep.add && ((ep.add_mask >> (pidx & 1)) & 1) ? ep.add + row_off + off : nullptr;
 #pragma unroll
         for (int mm = 0; mm < R; ++mm) {
             const int at = (lane << 8) + k_of<R>(u, mm, loL);
-            o[at] = epi_word(v[mm], cc[at], iv, ivs, q);
+            const u64 r = epi_word(v[mm], cc[at], iv, ivs, q);
+            o[at] = ad ? add_mod(r, ad[at], q) : r;
         }
     } else {
 #pragma unroll
