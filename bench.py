@@ -39,6 +39,7 @@ def parse():
     ap.add_argument("--iters", type=int, default=3)
     ap.add_argument("--level", type=int, default=7, help="input level")
     ap.add_argument("--extra-batch", type=int, default=16, help="also time this many ciphertexts per step (0: skip)")
+    ap.add_argument("--latency-runs", type=int, default=20, help="single-ciphertext runs timed one by one (p50/p99)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-limit", type=int, default=360,
                     help="seconds after the start the CPU baseline may run until")
@@ -143,6 +144,18 @@ def main():
         n, ms, by = ctx.profile_read(name)
         fam[name] = (n, ms, by)
     ctx.profile(False)
+    # single-ciphertext latency: each run synchronised on its own
+    lat = []
+    for _ in range(args.latency_runs):
+        t1 = time.perf_counter()
+        o1 = step(1)
+        ctx.sync()
+        lat.append(1e3 * (time.perf_counter() - t1))
+        del o1
+    latency = None
+    if lat:
+        latency = {"runs": len(lat), "p50_ms": round(float(np.percentile(lat, 50)), 3),
+                   "p99_ms": round(float(np.percentile(lat, 99)), 3)}
     batched = None
     if args.extra_batch > 1:
         out2 = step(args.extra_batch)
@@ -197,6 +210,7 @@ def main():
                              "7 x 60-bit special, dnum 3, h 192; l_afterBTS 7",
                    "bootstraps_per_ct": n_bts, "output_level": out_level},
         "mre": mre,
+        "latency": latency,
         "batched": batched,
         "roofline": roof,
         "kernel_families": others,

@@ -49,6 +49,26 @@ def column_table(rows, cols, seed):
     return data, mu, sigma
 
 
+def skewed_table(rows, cols, seed):
+    """Columns for the moment statistics: column c has mean ~ U[-5, 5] and
+    std ~ logU[0.1, 10] like column_table, but a standardised gamma shape
+    (shape k ~ U[1, 10]: skewness 2/sqrt(k), excess kurtosis 6/k), and each odd
+    column is correlated with the even one before it (rho ~ U[-0.9, 0.9])."""
+    rng = np.random.default_rng(seed)
+    mu = rng.uniform(-5, 5, cols)
+    sigma = np.exp(rng.uniform(np.log(0.1), np.log(10), cols))
+    k = rng.uniform(1, 10, cols)
+    rho = rng.uniform(-0.9, 0.9, cols)
+    z = np.empty((cols, rows))
+    for c in range(cols):
+        g = (rng.gamma(k[c], 1.0, rows) - k[c]) / np.sqrt(k[c])
+        if c % 2 == 1:
+            g = rho[c] * z[c - 1] + np.sqrt(1 - rho[c] ** 2) * g
+        z[c] = g
+    data = z * sigma[:, None] + mu[:, None]
+    return data, mu, sigma
+
+
 def poisson_arrivals(n, rate, seed):
     """Arrival times (s) of n requests of a Poisson process with `rate` per second."""
     rng = np.random.default_rng(seed)

@@ -105,6 +105,42 @@ def test_znorm_batched_bit_exact_vs_oracle(small):
     assert np.max(np.abs(zz - ref)) < 1e-4
 
 
+def test_moments_batched_bit_exact_vs_oracle(small):
+    """Skewness, excess kurtosis and PCC (from the z-scores) of 3 skewed,
+    pairwise-correlated columns, batched on the GPU, against the oracle run
+    column by column (pair by pair), word for word; values against FP64."""
+    from paper_2606_10477_amd import moments, znorm
+    g, o = small
+    cols, per = 3, 2
+    rows = per * g.n
+    data, _, _ = inputs.skewed_table(rows, cols, 11)
+    # degree 127: var / B reaches 1e-4 here, where degree 31 + 3 steps has not converged
+    B, lo, hi, d, it = 128.0, 2.0 ** -14, 1.0, 127, 3
+    gcols, ocols = [], []
+    for c in range(cols):
+        chunks = data[c].reshape(per, g.n)
+        gcols.append([g.encrypt(chunks[j], 24, 2.0 ** 40, 200 * c + j) for j in range(per)])
+        ocols.append([o.encrypt(chunks[j], 24, 2.0 ** 40, 200 * c + j) for j in range(per)])
+    gz, _, _ = znorm.znorm(g, gcols, rows, B, d, it, lo, hi)
+    oz = [_oracle_znorm(o, ocols[c], rows, B, d, it, lo, hi)[0] for c in range(cols)]
+    pairs = [(0, 1), (1, 2)]
+    gs, gk = moments.skew_kurt(g, gz, rows)
+    gp = moments.pcc(g, gz, rows, pairs)
+    for c in range(cols):
+        os_, ok = moments.skew_kurt(o, [oz[c]], rows)
+        assert np.array_equal(gs[c].words(), os_[0].words()), f"skewness column {c}"
+        assert np.array_equal(gk[c].words(), ok[0].words()), f"kurtosis column {c}"
+    for k, (a, b) in enumerate(pairs):
+        op = moments.pcc(o, [oz[a], oz[b]], rows, [(0, 1)])
+        assert np.array_equal(gp[k].words(), op[0].words()), f"pcc pair {a, b}"
+    rs, rk, rp = moments.reference(data, pairs)
+    for c in range(cols):
+        assert abs(g.decrypt(gs[c]).real[0] - rs[c]) < 1e-4
+        assert abs(g.decrypt(gk[c]).real[0] - rk[c]) < 1e-3
+    for k in range(len(pairs)):
+        assert abs(g.decrypt(gp[k]).real[0] - rp[k]) < 1e-4
+
+
 def test_serving_alone_equals_in_the_mix(small):
     from paper_2606_10477_amd import serve
     g, _ = small

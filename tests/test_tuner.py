@@ -99,3 +99,18 @@ def test_alg3_from_measured_rows():
     assert {(e["d"], e["c"], e["i"]) for e in D[5]} == {(7, 0, 3), (31, 1, 2)}
     # accuracy-first: m_theta from 3.0e-8 -> 4e-8 keeps only (7, 0, 3); speed-first: fastest
     assert R[5] == ((7, 0, 3), (7, 0, 3))
+
+
+def test_moment_reference_matches_scipy():
+    """The FP64 reference of the moment statistics (population skewness,
+    excess kurtosis, Pearson correlation) against scipy's definitions."""
+    import numpy as np
+    from scipy import stats
+    from paper_2606_10477_amd import inputs, moments
+    data, _, _ = inputs.skewed_table(4096, 4, 5)
+    sk, ku, r = moments.reference(data, [(0, 1), (2, 3)])
+    assert np.allclose(sk, stats.skew(data, axis=1, bias=True), rtol=1e-10, atol=1e-12)
+    assert np.allclose(ku, stats.kurtosis(data, axis=1, fisher=True, bias=True), rtol=1e-10, atol=1e-12)
+    assert np.allclose(r, [stats.pearsonr(data[0], data[1])[0], stats.pearsonr(data[2], data[3])[0]], rtol=1e-10)
+    # the generator's shapes: skewness 2/sqrt(k) > 0.6, correlated odd columns
+    assert sk[0] > 0.5 and sk[2] > 0.5 and abs(r[0]) > 0.05
