@@ -25,7 +25,7 @@ P16B = dict(log_n=16, max_level=7, num_special=7, digit_size=8, hamming_weight=1
 EVALMOD = (25.0, 4, 31)
 
 
-def run(levels, degrees, iters, targets, lo, hi, batch, reps, fixed, tuner_seed=777, quiet=False):
+def run(levels, degrees, iters, targets, lo, hi, batch, reps, fixed, tuner_seed=777, quiet=False, domain="logu"):
     import math
 
     import torch
@@ -36,7 +36,11 @@ def run(levels, degrees, iters, targets, lo, hi, batch, reps, fixed, tuner_seed=
     ctx = ckks.Context(**P16B)
     ctx.bts_setup(*EVALMOD)
     ctx.keygen(tuner_seed, ctx.bts_galois())      # the tuner's own keys, not a client's
-    x = inputs.log_uniform(ctx.n, lo, hi, 11)
+    if domain == "paper":
+        # the paper's own workload (§5.1): linspace over [0.001, 100], pre-normalised by B = 100
+        x = np.linspace(0.001, 100.0, ctx.n) / 100.0
+    else:
+        x = inputs.log_uniform(ctx.n, lo, hi, 11)
     cts = {l: ctx.encrypt(x, l, 2.0 ** 50, 12 + l) for l in levels}
     # Alg. 3's cases with l_BTS = 0, l_afterBTS = l_max = the chain's top computation level
     cases = tuner.level_cases(0, ctx.l_after, ctx.l_after)
@@ -70,7 +74,9 @@ def run(levels, degrees, iters, targets, lo, hi, batch, reps, fixed, tuner_seed=
     report = {
         "params": "N=2^16, log2 QP 1556: q0 60-bit, 10 x 40-bit, 13 x 52-bit, 7 x 60-bit special, dnum 3, h 192; "
                   "l_BTS 0, l_afterBTS = l_max 7",
-        "input": f"x log-uniform in [{lo}, {hi}], encrypted at scale 2^50",
+        "input": (f"x = linspace(0.001, 100, N/2) / 100 (B = 100), interval [{lo}, {hi}], encrypted at scale 2^50"
+                  if domain == "paper" else f"x log-uniform in [{lo}, {hi}], encrypted at scale 2^50"),
+        "fixed": list(fixed),
         "batch": batch, "grid": {"degrees": degrees, "iters": iters, "levels": levels, "c": cs},
         "targets": targets, "table": table, "speedup_vs_fixed": speedup,
         "alg3": {str(l): {"u1_accuracy_first": list(R[l][0]), "u2_speed_first": list(R[l][1]),
@@ -92,10 +98,15 @@ def main(argv=None):
     ap.add_argument("--targets", default="1e-6,1e-7,3.1e-8")
     ap.add_argument("--batch", type=int, default=1)
     ap.add_argument("--reps", type=int, default=3)
+    ap.add_argument("--domain", choices=["logu", "paper"], default="logu",
+                    help="logu: x log-uniform in [2^-10, 1]; paper: linspace(0.001, 100) / 100 on [1e-5, 1]")
+    ap.add_argument("--fixed", default="31,3", help="fixed (degree, iterations) the tuned choice is compared with")
     args = ap.parse_args(argv)
     ints = lambda s: [int(v) for v in s.split(",")]
+    lo, hi = (1e-5, 1.0) if args.domain == "paper" else (2.0 ** -10, 1.0)
     rep = run(ints(args.levels), ints(args.degrees), ints(args.iters),
-              [float(v) for v in args.targets.split(",")], 2.0 ** -10, 1.0, args.batch, args.reps, (31, 3))
+              [float(v) for v in args.targets.split(",")], lo, hi, args.batch, args.reps, tuple(ints(args.fixed)),
+              domain=args.domain)
     os.makedirs(os.path.dirname(os.path.abspath(args.out)), exist_ok=True)
     with open(args.out, "w") as f:
         json.dump(rep, f, indent=1)
