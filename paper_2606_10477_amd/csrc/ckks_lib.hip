@@ -11,6 +11,7 @@
 #include <algorithm>
 #include <cmath>
 #include <cstring>
+#include <functional>
 #include <map>
 #include <memory>
 #include <set>
@@ -935,6 +936,67 @@ Ct mult_aligned(ckks_ctx *c, const ckks_ct *a, const ckks_ct *b) {
     Ct x = op_level_to(c, a, l), y = op_level_to(c, b, l);
     return mult_rs(c, x.get(), y.get());
 }
+// Products a_i * b_i, each pair aligned to the lower of its two levels (as
+// mult_aligned), then multiplied and rescaled; pairs that land on the same
+// level share one launch sequence (their operands copied into one batch
+// object).  Words and scales of every result are exactly those of
+// mult_aligned(a_i, b_i): the kernels do not read the scale, and each result
+// gets (scale(a_i) scale(b_i)) / q_l as op_hmult and op_rescale compute it.
+constexpr int kMaxWaveBatch = 4;   // ciphertexts per operand above which products are not regrouped
+std::vector<Ct> mult_aligned_many(ckks_ctx *c, const std::vector<std::pair<const ckks_ct *, const ckks_ct *>> &pairs) {
+    const size_t n = pairs.size();
+    std::vector<Ct> out(n), own_a(n), own_b(n);
+    std::vector<const ckks_ct *> A(n), Bc(n);
+    std::vector<int> lv(n);
+    for (size_t i = 0; i < n; ++i) {
+        const ckks_ct *a = pairs[i].first, *b = pairs[i].second;
+        const int l = std::min(a->level, b->level);
+        if (l < 1) fail(CKKS_E_LEVEL, "no level for Mul_C");
+        if (a->B != b->B || a->B != pairs[0].first->B) fail(CKKS_E_PARAM, "batch size mismatch");
+        lv[i] = l;
+        if (a->level != l) own_a[i] = op_level_to(c, a, l);
+        if (b == a) own_b[i] = Ct();
+        else if (b->level != l) own_b[i] = op_level_to(c, b, l);
+        A[i] = own_a[i] ? own_a[i].get() : a;
+        Bc[i] = b == a ? A[i] : (own_b[i] ? own_b[i].get() : b);
+    }
+    std::vector<char> done(n, 0);
+    for (size_t i0 = 0; i0 < n; ++i0) {
+        if (done[i0]) continue;
+        std::vector<size_t> grp;
+        for (size_t i = i0; i < n; ++i)
+            if (!done[i] && lv[i] == lv[i0]) grp.push_back(i), done[i] = 1;
+        const int l = lv[i0];
+        if (grp.size() == 1 || A[i0]->B > kMaxWaveBatch) {
+            // a large batch fills the GPU by itself: the copies would cost more than they save
+            for (size_t i : grp) out[i] = mult_rs(c, A[i], Bc[i]);
+            continue;
+        }
+        const int B = A[i0]->B, G = (int)grp.size();
+        const size_t w = c->words(l) * B;
+        Ct la = ct_new(c, l, A[i0]->scale, G * B), lb = ct_new(c, l, Bc[i0]->scale, G * B);
+        for (int k = 0; k < G; ++k) {
+            hipchk(hipMemcpyAsync(la->buf.p + k * w, A[grp[k]]->buf.p, w * 8, hipMemcpyDeviceToDevice, c->stream),
+                   "batch");
+            hipchk(hipMemcpyAsync(lb->buf.p + k * w, Bc[grp[k]]->buf.p, w * 8, hipMemcpyDeviceToDevice, c->stream),
+                   "batch");
+        }
+        Ct m = op_hmult(c, la.get(), lb.get());
+        la.reset();
+        lb.reset();
+        Ct r = op_rescale(c, m.get());
+        m.reset();
+        const size_t wr = c->words(l - 1) * B;
+        for (int k = 0; k < G; ++k) {
+            const size_t i = grp[k];
+            Ct o = ct_new(c, l - 1, (A[i]->scale * Bc[i]->scale) / (double)c->q[l], B);
+            hipchk(hipMemcpyAsync(o->buf.p, r->buf.p + k * wr, wr * 8, hipMemcpyDeviceToDevice, c->stream), "split");
+            out[i] = std::move(o);
+        }
+    }
+    return out;
+}
+
 Ct addsub_aligned(ckks_ctx *c, const ckks_ct *a, const ckks_ct *b, bool sub) {
     int l = std::min(a->level, b->level);
     Ct x = op_level_to(c, a, l), y = op_level_to(c, b, l);
@@ -955,15 +1017,50 @@ struct PowerBasis {
         if (i % 2 == 0) {   // T_2k = 2 T_k^2 - 1
             ckks_ct *h = get(i / 2);
             Ct sq = mult_rs(c, h, h);
-            Ct two = op_mul_int(c, sq.get(), 2, sq->scale);
-            return op_add_const(c, two.get(), -1.0);
+            return finish(i, std::move(sq));
         }
         // T_2k+1 = 2 T_k+1 T_k - T_1
         ckks_ct *hi = get((i + 1) / 2);
         ckks_ct *lo = get((i - 1) / 2);
         Ct p = mult_aligned(c, hi, lo);
+        return finish(i, std::move(p));
+    }
+    // T_i from its product: 2 p - 1 (even i) or 2 p - T_1 (odd i)
+    Ct finish(int i, Ct p) {
         Ct two = op_mul_int(c, p.get(), 2, p->scale);
+        if (i % 2 == 0) return op_add_const(c, two.get(), -1.0);
         return addsub_aligned(c, two.get(), T[1].get(), true);
+    }
+    // every T_i of `want` (and what they need), wave by wave: the products of
+    // one wave whose operands are ready share launch sequences
+    void ensure(const std::vector<int> &want) {
+        std::vector<int> need;
+        std::function<void(int)> add = [&](int i) {
+            if (i <= 1 || T[i] || std::find(need.begin(), need.end(), i) != need.end()) return;
+            need.push_back(i);
+            if (i % 2 == 0) add(i / 2);
+            else { add((i + 1) / 2); add((i - 1) / 2); }
+        };
+        for (int i : want) add(i);
+        std::sort(need.begin(), need.end());
+        while (!need.empty()) {
+            std::vector<int> ready;
+            std::vector<std::pair<const ckks_ct *, const ckks_ct *>> pairs;
+            for (int i : need) {
+                const int a = i % 2 == 0 ? i / 2 : (i + 1) / 2, b = i % 2 == 0 ? i / 2 : (i - 1) / 2;
+                if (T[a] && T[b]) {
+                    ready.push_back(i);
+                    pairs.emplace_back(T[a].get(), T[b].get());
+                }
+            }
+            if (ready.empty()) fail(CKKS_E_PARAM, "power basis: unresolved dependency");
+            std::vector<Ct> P = mult_aligned_many(c, pairs);
+            for (size_t k = 0; k < ready.size(); ++k) T[ready[k]] = finish(ready[k], std::move(P[k]));
+            std::vector<int> rest;
+            for (int i : need)
+                if (!T[i]) rest.push_back(i);
+            need.swap(rest);
+        }
     }
 };
 
@@ -990,20 +1087,57 @@ Ct baby_sum(ckks_ctx *c, PowerBasis &pb, const std::vector<double> &cf) {
     return op_add_const(c, r.get(), cf[0]);
 }
 
-Ct cheb_tree(ckks_ctx *c, PowerBasis &pb, const std::vector<double> &cf, int k, int b) {
-    const int deg = (int)cf.size() - 1;
-    if (k <= b) return baby_sum(c, pb, cf);
+// Several trees of the same height k at once (the quotient and remainder
+// parts of one split are evaluated side by side): every tree's result is the
+// recursive split p = q T_M + r of the coefficients, computed op for op as
+// one tree alone would, with the products q T_M of all trees at one height
+// sharing launch sequences.
+std::vector<Ct> cheb_trees(ckks_ctx *c, PowerBasis &pb, const std::vector<std::vector<double>> &cfs, int k, int b) {
+    const size_t n = cfs.size();
+    std::vector<Ct> out(n);
+    if (k <= b) {
+        for (size_t t = 0; t < n; ++t) out[t] = baby_sum(c, pb, cfs[t]);
+        return out;
+    }
     const int M = 1 << (k - 1);
-    if (deg < M) return cheb_tree(c, pb, cf, k - 1, b);
-    const int dq = deg - M;
-    std::vector<double> qc(dq + 1), rc(cf.begin(), cf.begin() + M);
-    qc[0] = cf[M];
-    for (int j = 1; j <= dq; ++j) qc[j] = 2.0 * cf[M + j];
-    for (int j = 1; j <= dq; ++j) rc[M - j] = cf[M - j] - cf[M + j];
-    Ct Q = cheb_tree(c, pb, qc, k - 1, b);
-    Ct R = cheb_tree(c, pb, rc, k - 1, b);
-    Ct P = mult_aligned(c, Q.get(), pb.get(M));
-    return addsub_aligned(c, P.get(), R.get(), false);
+    std::vector<std::vector<double>> sub;
+    std::vector<int> qi(n, -1), ri(n, -1);
+    for (size_t t = 0; t < n; ++t) {
+        const std::vector<double> &cf = cfs[t];
+        const int deg = (int)cf.size() - 1;
+        if (deg < M) {   // no split at this height
+            ri[t] = (int)sub.size();
+            sub.push_back(cf);
+            continue;
+        }
+        const int dq = deg - M;
+        std::vector<double> qc(dq + 1), rc(cf.begin(), cf.begin() + M);
+        qc[0] = cf[M];
+        for (int j = 1; j <= dq; ++j) qc[j] = 2.0 * cf[M + j];
+        for (int j = 1; j <= dq; ++j) rc[M - j] = cf[M - j] - cf[M + j];
+        qi[t] = (int)sub.size();
+        sub.push_back(std::move(qc));
+        ri[t] = (int)sub.size();
+        sub.push_back(std::move(rc));
+    }
+    std::vector<Ct> S = cheb_trees(c, pb, sub, k - 1, b);
+    std::vector<std::pair<const ckks_ct *, const ckks_ct *>> pairs;
+    for (size_t t = 0; t < n; ++t)
+        if (qi[t] >= 0) pairs.emplace_back(S[qi[t]].get(), pb.get(M));
+    std::vector<Ct> P = mult_aligned_many(c, pairs);
+    for (size_t t = 0, j = 0; t < n; ++t) {
+        if (qi[t] < 0) {
+            out[t] = std::move(S[ri[t]]);
+            continue;
+        }
+        out[t] = addsub_aligned(c, P[j].get(), S[ri[t]].get(), false);
+        ++j;
+    }
+    return out;
+}
+Ct cheb_tree(ckks_ctx *c, PowerBasis &pb, const std::vector<double> &cf, int k, int b) {
+    std::vector<Ct> r = cheb_trees(c, pb, {cf}, k, b);
+    return std::move(r[0]);
 }
 
 int bit_length(int d) {
@@ -1029,8 +1163,10 @@ Ct op_cheb(ckks_ctx *c, const ckks_ct *x, const std::vector<double> &cf, double 
     PowerBasis pb{c, {}};
     pb.T.resize((1 << m) + 1);
     pb.T[1] = std::move(t);
-    for (int i = 2; i < (1 << bb) && i <= d; ++i) pb.get(i);
-    for (int k = bb; k < m; ++k) pb.get(1 << k);
+    std::vector<int> want;
+    for (int i = 2; i < (1 << bb) && i <= d; ++i) want.push_back(i);
+    for (int k = bb; k < m; ++k) want.push_back(1 << k);
+    pb.ensure(want);
     return cheb_tree(c, pb, cf, m, bb);
 }
 

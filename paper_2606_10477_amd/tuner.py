@@ -148,6 +148,13 @@ def profile_unit_costs(ctx, levels, batch=1, reps=5, rot_step=None, bts_bound=No
             fns["drop"] = lambda: ctx.drop_level(a, lvl - 1)
         if rot_step is not None:
             fns["rotate"] = lambda: ctx.rotate(a, rot_step)
+        # products of a Chebyshev wave share one launch sequence (2-4 of them
+        # in a batch): profile hmult and rescale at 2x and 4x the batch too
+        for m in BATCH_MULTIPLES:
+            am = ctx.pack(singles * m)
+            fns[f"hmult*{m}"] = (lambda am=am: ctx.hmult(am, am))
+            if lvl >= 1:
+                fns[f"rescale*{m}"] = (lambda am=am: ctx.rescale(am))
         for op, fn in fns.items():
             fn()
             ctx.sync()
@@ -162,12 +169,34 @@ def profile_unit_costs(ctx, levels, batch=1, reps=5, rot_step=None, bts_bound=No
     return costs
 
 
-def predict(trace, costs):
-    """Sum of unit costs over an operation trace [(op, level, B), ...]."""
+BATCH_MULTIPLES = (2, 4)
+
+
+def _unit_cost(costs, op, lvl, m):
+    """Cost of `op` at `lvl` on m times the profiled batch: piecewise linear
+    through the profiled multiples (1, 2, 4), extended linearly; m times the
+    single cost when only that was profiled."""
+    c1 = costs.get((op, BTS_ANY_LEVEL if op == "bootstrap" else lvl))
+    if c1 is None or m <= 1:
+        return c1
+    pts = [(1, c1)] + [(k, costs[(f"{op}*{k}", lvl)]) for k in BATCH_MULTIPLES if (f"{op}*{k}", lvl) in costs]
+    if len(pts) == 1:
+        return c1 * m
+    for (m0, t0), (m1, t1) in zip(pts, pts[1:]):
+        if m <= m1:
+            return t0 + (t1 - t0) * (m - m0) / (m1 - m0)
+    (m0, t0), (m1, t1) = pts[-2], pts[-1]
+    return t1 + (t1 - t0) * (m - m1) / (m1 - m0)
+
+
+def predict(trace, costs, base_batch=1):
+    """Sum of unit costs over an operation trace [(op, level, B), ...] of a run
+    on base_batch ciphertexts (an op on B = m base_batch ciphertexts, such as
+    a Chebyshev wave's batched products, costs the profiled m-fold batch)."""
     total = 0.0
     missing = set()
-    for op, lvl, _B in trace:
-        c = costs.get((op, BTS_ANY_LEVEL if op == "bootstrap" else lvl))
+    for op, lvl, B in trace:
+        c = _unit_cost(costs, op, lvl, max(1, int(B) // max(1, base_batch)))
         if c is None:
             missing.add((op, lvl))
             continue
@@ -227,7 +256,7 @@ def _measure(ctx, ct, lvl, c, d, it, lo, hi, batch, reps, costs, ref):
     row["ops"] = len(tr)
     row["bts"] = sum(1 for op in tr if op[0] == "bootstrap")
     if costs is not None:
-        row["t_pred"] = predict(tr, costs)[0]
+        row["t_pred"] = predict(tr, costs, base_batch=batch)[0]
     return row
 
 

@@ -75,6 +75,19 @@ def test_predict_sums_unit_costs():
     assert missing == {("rotate", 3)}
 
 
+def test_predict_batched_products():
+    """An op on m x the base batch costs the profiled m-fold batch
+    (interpolated between the profiled multiples, extended past the last)."""
+    costs = {("hmult", 5): 2.0, ("hmult*2", 5): 2.5, ("hmult*4", 5): 3.5, ("add", 5): 0.1}
+    assert tuner.predict([("hmult", 5, 2)], costs)[0] == pytest.approx(2.5)
+    assert tuner.predict([("hmult", 5, 3)], costs)[0] == pytest.approx(3.0)
+    assert tuner.predict([("hmult", 5, 6)], costs)[0] == pytest.approx(4.5)
+    # relative to the run's own batch: B = 8 on a batch-4 run is the 2-fold cost
+    assert tuner.predict([("hmult", 5, 8)], costs, base_batch=4)[0] == pytest.approx(2.5)
+    # no multiples profiled: linear in m
+    assert tuner.predict([("add", 5, 3)], costs)[0] == pytest.approx(0.3)
+
+
 def test_select_meets_target_at_min_time():
     rows = [dict(level=11, d=31, i=3, c=0, ok=True, m=1.1e-8, t_pred=5.0),
             dict(level=11, d=63, i=2, c=0, ok=True, m=6.7e-9, t_pred=4.5),
