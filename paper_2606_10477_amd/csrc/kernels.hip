@@ -216,16 +216,10 @@ DEV u64 epi_word(u64 x, u64 c, u64 iv, u64 ivs, u64 q) { return mul_shoup(sub_mo
 // ---------------------------------------------------------------------------
 constexpr int kPad = 17;   // LDS row pitch (words) for the 16-wide sub-tiles
 
-// Lazy (Harvey) butterflies for the N = 2^16 passes: a Shoup product without
-// its final correction lies in [0, 2q) for any 64-bit input; forward values
-// stay in [0, 4q), inverse values in [0, 2q) (q < 2^61), and are reduced to
-// [0, q) only where a pass writes its final output.
-DEV u64 mul_shoup_lazy(u64 a, u64 w, u64 wsh, u64 q) { return a * w - __umul64hi(a, wsh) * q; }
-DEV u64 reduce_4q(u64 x, u64 q) {
-    const u64 q2 = 2 * q;
-    x = x >= q2 ? x - q2 : x;
-    return x >= q ? x - q : x;
-}
+// Lazy (Harvey) butterflies for the N = 2^16 passes (primes q < 2^61): the
+// products are Shoup products with a truncated quotient (below), which lie in
+// [0, 4q) for any 64-bit input; values are reduced to [0, q) only where a
+// transform writes its final output.
 // x mod q for any 64-bit x: Shoup product by 1 (quotient constant floor(2^64/q)),
 // which lands in [0, 2q), then one correction
 DEV u64 reduce_any(u64 x, u64 inv64, u64 q) {
@@ -242,11 +236,13 @@ DEV u64 mul_shoup_lazy4(u64 a, u64 w, u64 wsh, u64 q) {
     const u64 Q = (u64)a1 * s1 + __umulhi(a1, s0) + __umulhi(a0, s1);
     return a * w - Q * q;
 }
-// Primes below 2^57 leave headroom for 16 forward stages with no reduction at
-// all: with the truncated-quotient product V in [0, 4q), each stage adds at
-// most 4q to the bound (U + V and U - V + 4q), so a pass fed with [0, Bq) ends
-// below (B + 32) q and the whole transform from [0, q) below 65 q < 2^64.  The
-// inverse butterflies keep every value in [0, 4q) for these primes.
+// Forward (CT) butterflies: U + V and U - V + 4q with V in [0, 4q).  Primes
+// below 2^57 leave headroom for all 16 stages with no reduction: each stage
+// adds at most 4q to the bound, so a transform from [0, q) ends below 65 q <
+// 2^64.  For larger primes (q < 2^61) U is first brought into [0, 4q) by one
+// conditional subtraction, which keeps every value below 8q < 2^64.  Inverse
+// (GS) butterflies keep every value in [0, 4q) for every prime: S = U + V
+// corrected by 4q, D = U - V + 4q < 8q into the product.
 constexpr u64 kSmallPrime = 1ull << 57;
 
 // forward butterflies (CT) on v[0..15] for 4 stages; element m pairs with
@@ -268,11 +264,11 @@ __device__ __forceinline__ void fwd16(u64 v[16], const u64 *W, const u64 *Ws, in
                 v[m] = U + V;
                 v[m + h] = U - V + q4;
             } else {
-                const u64 q2 = 2 * q;
-                const u64 U = v[m] >= q2 ? v[m] - q2 : v[m];                // [0, 2q)
-                const u64 V = mul_shoup_lazy(v[m + h], W[wi], Ws[wi], q);   // [0, 2q)
-                v[m] = U + V;                                               // [0, 4q)
-                v[m + h] = U - V + q2;                                      // (0, 4q)
+                const u64 q4 = 4 * q;
+                const u64 U = v[m] >= q4 ? v[m] - q4 : v[m];                // [0, 4q)
+                const u64 V = mul_shoup_lazy4(v[m + h], W[wi], Ws[wi], q);  // [0, 4q)
+                v[m] = U + V;                                               // [0, 8q)
+                v[m + h] = U - V + q4;                                      // (0, 8q)
             }
         }
     }
@@ -280,9 +276,7 @@ __device__ __forceinline__ void fwd16(u64 v[16], const u64 *W, const u64 *Ws, in
 // inverse butterflies (GS) on v[0..15], distances h = 1, 2, 4, 8; group index
 // for distance h: hi_part * (16 / 2h) + (m >> (log2 h + 1)); twiddle index =
 // n_groups_total + group, with n_groups_total = N / (2 t_global).  Values stay
-// in [0, 2q) (large primes, exact lazy product) or [0, 4q) (primes below
-// 2^57, truncated-quotient product).
-template <bool SMALL>
+// in [0, 4q).
 __device__ __forceinline__ void inv16(u64 v[16], const u64 *W, const u64 *Ws, int logN, int lt0, int hi_part,
                                       u64 q) {
 #pragma unroll
@@ -293,12 +287,11 @@ __device__ __forceinline__ void inv16(u64 v[16], const u64 *W, const u64 *Ws, in
             if (m & h) continue;
             const int lt = lt0 + j;   // log2 of the global half-distance
             const int wi = (1 << (logN - lt - 1)) + (hi_part << (3 - j)) + (m >> (j + 1));
-            const u64 B = SMALL ? 4 * q : 2 * q;
-            const u64 U = v[m], V = v[m + h];                        // [0, B)
+            const u64 B = 4 * q;
+            const u64 U = v[m], V = v[m + h];                        // [0, 4q)
             const u64 S = U + V;
-            v[m] = S >= B ? S - B : S;                               // [0, B)
-            v[m + h] = SMALL ? mul_shoup_lazy4(U - V + B, W[wi], Ws[wi], q)
-                             : mul_shoup_lazy(U - V + B, W[wi], Ws[wi], q);   // [0, B)
+            v[m] = S >= B ? S - B : S;                               // [0, 4q)
+            v[m + h] = mul_shoup_lazy4(U - V + B, W[wi], Ws[wi], q);   // [0, 4q)
         }
     }
 }
@@ -383,8 +376,9 @@ __global__ void __launch_bounds__(256) k_ntt16_blocks_fwd(u64 *data, int nlimb, 
         for (int mm = 0; mm < 16; ++mm) v[mm] = reduce_any(v[mm], inv64, q);
     } else {
         fwd16<false>(v, W, Ws, 12, (blk0 + y) * 16 + x, q);
+        const u64 inv64 = T.primes[pi].mu2_hi;
 #pragma unroll
-        for (int mm = 0; mm < 16; ++mm) v[mm] = reduce_4q(v[mm], q);
+        for (int mm = 0; mm < 16; ++mm) v[mm] = reduce_any(v[mm], inv64, q);
     }
     __syncthreads();
 #pragma unroll
@@ -428,17 +422,14 @@ __global__ void __launch_bounds__(256) k_ntt16_blocks_inv(u64 *dst, const u64 *s
     // word J for distance t: J >> (lt + 1), J = 256 (blk0 + y) + 16 x + m
 #pragma unroll
     for (int mm = 0; mm < 16; ++mm) v[mm] = tile[(y * 16 + x) * kPad + mm];
-    const bool small = q < kSmallPrime;
-    if (small) inv16<true>(v, W, Ws, 16, 0, (blk0 + y) * 16 + x, q);
-    else inv16<false>(v, W, Ws, 16, 0, (blk0 + y) * 16 + x, q);
+    inv16(v, W, Ws, 16, 0, (blk0 + y) * 16 + x, q);
 #pragma unroll
     for (int mm = 0; mm < 16; ++mm) tile[(y * 16 + x) * kPad + mm] = v[mm];
     __syncthreads();
     // phase B: block y, words x + 16 m; half-distances 16..128
 #pragma unroll
     for (int mm = 0; mm < 16; ++mm) v[mm] = tile[(y * 16 + mm) * kPad + x];
-    if (small) inv16<true>(v, W, Ws, 16, 4, blk0 + y, q);
-    else inv16<false>(v, W, Ws, 16, 4, blk0 + y, q);
+    inv16(v, W, Ws, 16, 4, blk0 + y, q);
 #pragma unroll
     for (int mm = 0; mm < 16; ++mm) d[(y << 8) + x + 16 * mm] = v[mm];
 }
@@ -458,17 +449,14 @@ __global__ void __launch_bounds__(256) k_ntt16_rows_inv(u64 *data, int nlimb, in
     // phase A: rows k = 16 y + m (row distances 1..8 = global 256..2048)
 #pragma unroll
     for (int mm = 0; mm < 16; ++mm) v[mm] = d[((16 * y + mm) << 8) + c0 + x];
-    const bool small = q < kSmallPrime;
-    if (small) inv16<true>(v, W, Ws, 16, 8, y, q);
-    else inv16<false>(v, W, Ws, 16, 8, y, q);
+    inv16(v, W, Ws, 16, 8, y, q);
 #pragma unroll
     for (int mm = 0; mm < 16; ++mm) tile[(16 * y + mm) * kPad + x] = v[mm];
     __syncthreads();
     // phase B: rows k = y + 16 m (row distances 16..128)
 #pragma unroll
     for (int mm = 0; mm < 16; ++mm) v[mm] = tile[(y + 16 * mm) * kPad + x];
-    if (small) inv16<true>(v, W, Ws, 16, 12, 0, q);
-    else inv16<false>(v, W, Ws, 16, 12, 0, q);
+    inv16(v, W, Ws, 16, 12, 0, q);
     const u64 ni = T.ninv[pi], nis = T.ninv_sh[pi];
 #pragma unroll
     for (int mm = 0; mm < 16; ++mm) d[((y + 16 * mm) << 8) + c0 + x] = mul_shoup(v[mm], ni, nis, q);
@@ -532,11 +520,11 @@ __device__ __forceinline__ void fwd_stage(u64 *v, int u, int lo, int b, int blkg
             v[m] = U + V;
             v[m + h] = U - V + 4 * q;
         } else {
-            const u64 q2 = 2 * q;
-            const u64 U = v[m] >= q2 ? v[m] - q2 : v[m];
-            const u64 V = mul_shoup_lazy(v[m + h], W[wi], Ws[wi], q);
+            const u64 q4 = 4 * q;
+            const u64 U = v[m] >= q4 ? v[m] - q4 : v[m];
+            const u64 V = mul_shoup_lazy4(v[m + h], W[wi], Ws[wi], q);
             v[m] = U + V;
-            v[m + h] = U - V + q2;
+            v[m + h] = U - V + q4;
         }
     }
 }
@@ -551,12 +539,11 @@ __device__ __forceinline__ void inv_stage(u64 *v, int u, int lo, int b, int blkg
         const int wi = ROWS ? (1 << (7 - b)) + (k >> (b + 1))
                             : (1 << (15 - b)) + (blkg << (7 - b)) + (k >> (b + 1));
         const int h = 1 << j;
-        const u64 B = SMALL ? 4 * q : 2 * q;
+        const u64 B = 4 * q;
         const u64 U = v[m], V = v[m + h];
         const u64 S = U + V;
         v[m] = S >= B ? S - B : S;
-        v[m + h] = SMALL ? mul_shoup_lazy4(U - V + B, W[wi], Ws[wi], q)
-                         : mul_shoup_lazy(U - V + B, W[wi], Ws[wi], q);
+        v[m + h] = mul_shoup_lazy4(U - V + B, W[wi], Ws[wi], q);
     }
 }
 
@@ -641,8 +628,9 @@ __global__ void __launch_bounds__(Geo<R>::NT) k_nttr_blocks_fwd(u64 *data, int n
         for (int mm = 0; mm < R; ++mm) v[mm] = reduce_any(v[mm], inv64, q);
     } else {
         pass_phases<R, false, true, false>(v, tile, lane, u, blkg, W, Ws, q);
+        const u64 inv64 = T.primes[pi].mu2_hi;
 #pragma unroll
-        for (int mm = 0; mm < R; ++mm) v[mm] = reduce_4q(v[mm], q);
+        for (int mm = 0; mm < R; ++mm) v[mm] = reduce_any(v[mm], inv64, q);
     }
     if (EPI) {
         const size_t off = ((size_t)blockIdx.x << 12);
@@ -678,8 +666,7 @@ __global__ void __launch_bounds__(Geo<R>::NT) k_nttr_blocks_inv(u64 *dst, const 
     u64 v[R];
 #pragma unroll
     for (int mm = 0; mm < R; ++mm) v[mm] = s_in[(lane << 8) + k_of<R>(u, mm, lo0)];
-    if (q < kSmallPrime) pass_phases<R, false, false, true>(v, tile, lane, u, blkg, W, Ws, q);
-    else pass_phases<R, false, false, false>(v, tile, lane, u, blkg, W, Ws, q);
+    pass_phases<R, false, false, true>(v, tile, lane, u, blkg, W, Ws, q);   // inverse: one path for all primes
 #pragma unroll
     for (int mm = 0; mm < R; ++mm) d[(lane << 8) + k_of<R>(u, mm, loL)] = v[mm];
 }
@@ -698,8 +685,7 @@ __global__ void __launch_bounds__(Geo<R>::NT) k_nttr_rows_inv(u64 *data, int nli
     u64 v[R];
 #pragma unroll
     for (int mm = 0; mm < R; ++mm) v[mm] = d[(k_of<R>(u, mm, lo0) << 8) + c0 + lane];
-    if (q < kSmallPrime) pass_phases<R, true, false, true>(v, tile, lane, u, 0, W, Ws, q);
-    else pass_phases<R, true, false, false>(v, tile, lane, u, 0, W, Ws, q);
+    pass_phases<R, true, false, true>(v, tile, lane, u, 0, W, Ws, q);   // inverse: one path for all primes
     const u64 ni = T.ninv[pi], nis = T.ninv_sh[pi];
 #pragma unroll
     for (int mm = 0; mm < R; ++mm) d[(k_of<R>(u, mm, loL) << 8) + c0 + lane] = mul_shoup(v[mm], ni, nis, q);
