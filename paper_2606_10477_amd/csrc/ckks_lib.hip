@@ -205,8 +205,8 @@ struct BtsPlan;
 
 // Default N = 2^16 transform schedule (ckks_ntt_schedule overrides it):
 // calls of at most this many limbs in total use 4 / 8 words per thread.
-constexpr int kNttR4Max = 28;
-constexpr int kNttR8Max = 28;
+constexpr int kNttR4Max = 32;
+constexpr int kNttR8Max = 32;
 
 struct ckks_ctx {
     ckks_params prm;

@@ -45,13 +45,16 @@ def scan(ctx, sizes, nprimes):
     return rows
 
 
-def choose(rows):
+def choose(rows, tol=0.01):
     """Bounds (r4_max, r8_max): every call size up to r4_max is fastest (fwd +
-    inv) with 4 words per thread, up to r8_max with 4 or 8."""
+    inv) with 4 words per thread, up to r8_max with 4 or 8.  A variant within
+    `tol` (relative) of the fastest counts as fastest, preferring fewer words
+    per thread, so that timing noise at near-ties does not end a run early."""
     best = []
     for r in rows:
         t = {R: r[f"fwd_R{R}_us"] + r[f"inv_R{R}_us"] for R, _ in VARIANTS}
-        best.append((r["limbs"], min(t, key=t.get)))
+        tmin = min(t.values())
+        best.append((r["limbs"], min(R for R in t if t[R] <= tmin * (1 + tol))))
     r4 = 0
     for n, R in best:
         if R != 4:

@@ -24,3 +24,10 @@ def test_choose_stops_at_first_loss():
     # a later win of the 4-word variant after a loss does not extend the bound
     rows = [_row(1, 5, 6, 7), _row(2, 8, 6, 7), _row(3, 5, 6, 7)]
     assert ntt_tune.choose(rows)[:2] == (1, 2)
+
+
+def test_choose_tolerates_near_ties():
+    # 24 limbs: the 4-word variant is 0.5 % slower than the 16-word one
+    rows = [_row(16, 10, 11, 11), _row(24, 27.25, 28, 27.1), _row(32, 28, 29, 29), _row(40, 36, 36, 33)]
+    assert ntt_tune.choose(rows)[:2] == (32, 32)
+    assert ntt_tune.choose(rows, tol=0.0)[:2] == (16, 16)
