@@ -782,7 +782,18 @@ struct RotJob {
 };
 // Key switching of rotation jobs over one ModUp: inner products and ModDown
 // of up to kMaxJobs jobs run as one launch sequence.
+void ks_rot_jobs_impl(ckks_ctx *c, const ModUp &mu, int B, const std::vector<RotJob> &jobs, u64 *sum_out,
+                      const u64 *sum_extra);
 void ks_rot_jobs(ckks_ctx *c, const ModUp &mu, int B, const std::vector<RotJob> &jobs) {
+    ks_rot_jobs_impl(c, mu, B, jobs, nullptr, nullptr);
+}
+// the jobs' results summed into sum_out ([B][2][l+1][N]) plus sum_extra (nullable)
+void ks_rot_jobs_sum(ckks_ctx *c, const ModUp &mu, int B, const std::vector<RotJob> &jobs, u64 *sum_out,
+                     const u64 *sum_extra) {
+    ks_rot_jobs_impl(c, mu, B, jobs, sum_out, sum_extra);
+}
+void ks_rot_jobs_impl(ckks_ctx *c, const ModUp &mu, int B, const std::vector<RotJob> &jobs, u64 *sum_out,
+                      const u64 *sum_extra) {
     const size_t N = c->N;
     const int l = mu.l, nq = l + 1, ne = nq + c->K;
     const int beta = (nq + c->alpha - 1) / c->alpha;
@@ -822,7 +833,11 @@ void ks_rot_jobs(ckks_ctx *c, const ModUp &mu, int B, const std::vector<RotJob> 
         gpu::BconvArgs bd{md->pin, md->pout, md->din, md->dout, md->hinv.p, md->hinv_sh.p, md->mat.p};
         gpu::bconv(c->T, z.p, y.p, bd, np2, (size_t)c->K * N, (size_t)nq * N, c->stream);
         ntt_p(c, z.p, nq, np2, map_q(0, nq), false);
-        gpu::moddown_finish_jobs(c->T, fj, acc.p, (size_t)ne * N, z.p, pinv, nq, nj, B, map_q(0, nq), c->stream);
+        if (sum_out)
+            gpu::moddown_finish_jobs_sum(c->T, fj, sum_out, sum_extra, j0 > 0, acc.p, (size_t)ne * N, z.p, pinv, nq,
+                                         nj, B, map_q(0, nq), c->stream);
+        else
+            gpu::moddown_finish_jobs(c->T, fj, acc.p, (size_t)ne * N, z.p, pinv, nq, nj, B, map_q(0, nq), c->stream);
     }
 }
 
@@ -1307,7 +1322,6 @@ Ct op_lt(ckks_ctx *c, const ckks_ct *x, const LtStage &st) {
     const size_t nrot = gis.size() - (gis.back() == 0 ? 1 : 0);
     Ct acc = ct_new(c, x->level, x->scale * st.sd, B);
     if (nrot > 0) {
-        Buf rot(c->pool.get(), gstride * nrot);
         std::vector<RotJob> jobs;
         for (size_t k = 0; k < nrot; ++k) {
             const long long steps = ((long long)st.g * gis[k] * st.stride) % n;
@@ -1315,27 +1329,15 @@ Ct op_lt(ckks_ctx *c, const ckks_ct *x, const LtStage &st) {
             auto it = c->rot.find(g);
             if (it == c->rot.end()) fail(CKKS_E_NOKEY, "missing Galois key");
             trace_op(c, "rotate", x->level, B);
-            jobs.push_back(RotJob{&it->second, perm_for(c, g), (int)(k * B), rot.p + k * gstride, inner.p + k * gstride});
+            jobs.push_back(RotJob{&it->second, perm_for(c, g), (int)(k * B), nullptr, inner.p + k * gstride});
         }
         ModUp mu;
         {
             ProfScope ps(c, "keyswitch", 8.0 * (double)N * nrot * B * nq);
             modup(c, x->level, inner.p + (size_t)nq * N, member, (int)(nrot * B), mu);
         }
-        ks_rot_jobs(c, mu, B, jobs);
-        // sum of the rotated giants (and giant 0)
-        const u64 *first = rot.p;
-        if (nrot == 1 && gis.size() == 1) {
-            hipchk(hipMemcpyAsync(acc->buf.p, first, gstride * 8, hipMemcpyDeviceToDevice, c->stream), "copy");
-        } else {
-            const u64 *second = nrot > 1 ? rot.p + gstride : inner.p + nrot * gstride;
-            gpu::add(c->T, acc->buf.p, first, second, nq, 2 * B, map_q(0, nq), false, c->stream);
-            for (size_t k = 2; k < nrot; ++k)
-                gpu::add(c->T, acc->buf.p, acc->buf.p, rot.p + k * gstride, nq, 2 * B, map_q(0, nq), false, c->stream);
-            if (nrot > 1 && gis.size() > nrot)
-                gpu::add(c->T, acc->buf.p, acc->buf.p, inner.p + nrot * gstride, nq, 2 * B, map_q(0, nq), false,
-                         c->stream);
-        }
+        // the rotated giants summed (with giant 0's inner sum) in the ModDown's last kernel
+        ks_rot_jobs_sum(c, mu, B, jobs, acc->buf.p, gis.size() > nrot ? inner.p + nrot * gstride : nullptr);
     } else {
         hipchk(hipMemcpyAsync(acc->buf.p, inner.p, gstride * 8, hipMemcpyDeviceToDevice, c->stream), "copy");
     }

@@ -207,6 +207,13 @@ struct FinishJobs {
 void moddown_finish_jobs(const Tables &T, const FinishJobs &f, const uint64_t *acc, size_t acc_poly_stride,
                          const uint64_t *z, const LimbConsts &pinv, int nlimb, int njob, int B, const LimbMap &m,
                          hipStream_t s);
+// The same jobs summed into one ciphertext batch: out = base + sum_t job_t,
+// where base is out itself (accumulate), `extra` (non-null) or zero; f.out is
+// not used.  (Modular sums: the words equal those of adding the jobs' own
+// outputs one by one.)
+void moddown_finish_jobs_sum(const Tables &T, const FinishJobs &f, uint64_t *out, const uint64_t *extra,
+                             bool accumulate, const uint64_t *acc, size_t acc_poly_stride, const uint64_t *z,
+                             const LimbConsts &pinv, int nlimb, int njob, int B, const LimbMap &m, hipStream_t s);
 
 // Linear combination of ciphertext objects at (possibly) different levels:
 // out[b][p][l] = sum_t k_t * x_t[b][p][l] over the nlimb lowest limbs (signed

@@ -1187,6 +1187,41 @@ void moddown_finish_jobs(const Tables &T, const FinishJobs &f, const uint64_t *a
                        T.logN, nlimb, B, total, m, T);
 }
 
+// one thread per (member, poly, limb, word): every job's finished word summed
+__global__ void k_moddown_finish_jobs_sum(FinishJobs F, u64 *out, const u64 *extra, int accumulate, const u64 *acc,
+                                          size_t acc_stride, const u64 *z, LimbConsts pinv, int logN, int nlimb,
+                                          int njob, int B, size_t total, LimbMap m, Tables T) {
+    const size_t N = (size_t)1 << logN;
+    const size_t member = (size_t)2 * nlimb * N;
+    GRID_LOOP(i, total) {
+        ROW_SPLIT(i, logN, nlimb, r2, limb)   // r2 = 2 b + pp over the output batch
+        const uint32_t b = r2 >> 1, pp = r2 & 1u;
+        const size_t j = i & (N - 1);
+        const size_t rem = ((size_t)limb << logN) | j;
+        const u64 q = T.primes[m.p[limb]].q;
+        u64 sum = accumulate ? out[i] : (extra ? extra[i] : 0);
+        for (int t = 0; t < njob; ++t) {
+            const size_t poly = (size_t)t * 2 * B + r2;
+            u64 v = mul_shoup(sub_mod(acc[poly * acc_stride + rem], z[poly * nlimb * N + rem], q), pinv.v[limb],
+                              pinv.sh[limb], q);
+            if (pp == 0 && F.add[t]) {
+                const size_t jx = F.perm[t] ? (size_t)F.perm[t][j] : j;
+                v = add_mod(v, F.add[t][b * member + ((size_t)limb << logN) + jx], q);
+            }
+            sum = add_mod(sum, v, q);
+        }
+        out[i] = sum;
+    }
+}
+void moddown_finish_jobs_sum(const Tables &T, const FinishJobs &f, uint64_t *out, const uint64_t *extra,
+                             bool accumulate, const uint64_t *acc, size_t acc_poly_stride, const uint64_t *z,
+                             const LimbConsts &pinv, int nlimb, int njob, int B, const LimbMap &m, hipStream_t s) {
+    size_t total = ((size_t)nlimb * 2 * B) << T.logN;
+    if (!total || njob <= 0) return;
+    hipLaunchKernelGGL(k_moddown_finish_jobs_sum, grid_for(total), dim3(256), 0, s, f, out, extra, (int)accumulate,
+                       acc, acc_poly_stride, z, pinv, T.logN, nlimb, njob, B, total, m, T);
+}
+
 __global__ void k_moddown_finish(u64 *out, const u64 *acc, size_t acc_stride, const u64 *z, const u64 *add,
                                  int add_mask, LimbConsts pinv, int logN, int nlimb, size_t total, LimbMap m,
                                  Tables T) {
