@@ -189,6 +189,8 @@ struct ckks_ct {
     double scale;
     int B = 1;  // ciphertexts held (all at this level and scale)
     Buf buf;    // [B][2][level+1][N]
+    // a view into another object's memory (buf not owned): keeps it alive
+    std::shared_ptr<ckks_ct> keep;
 };
 
 struct SwitchKey {
@@ -544,6 +546,19 @@ Ct ct_new(ckks_ctx *c, int level, double scale, int B = 1) {
     r->buf = Buf(c->pool.get(), c->words(level) * B);
     return r;
 }
+// members [first, first + B) of a batch object as a ciphertext object of their
+// own, without a copy (the view keeps the batch's memory alive)
+Ct ct_view(ckks_ctx *c, const std::shared_ptr<ckks_ct> &batch, int first, int B, double scale) {
+    Ct v(new ckks_ct);
+    v->level = batch->level;
+    v->scale = scale;
+    v->B = B;
+    v->buf.pool = nullptr;
+    v->buf.p = batch->buf.p + c->words(batch->level) * (size_t)first;
+    v->buf.bytes = c->words(batch->level) * (size_t)B * 8;
+    v->keep = batch;
+    return v;
+}
 // poly p of ciphertext b
 u64 *poly(const ckks_ctx *c, const ckks_ct *ct, int p, int b = 0) {
     return ct->buf.p + ((size_t)b * 2 + p) * (ct->level + 1) * c->N;
@@ -752,6 +767,32 @@ Ct op_hmult(ckks_ctx *c, const ckks_ct *a, const ckks_ct *b) {
     Buf d01(c->pool.get(), (size_t)B * 2 * nq * N), d2(c->pool.get(), (size_t)B * nq * N);
     gpu::tensor(c->T, d01.p, d2.p, a->buf.p, b->buf.p, nq, B, map_q(0, nq), c->stream);
     keyswitch(c, l, d2.p, (size_t)nq * N, B, c->relin, r->buf.p, d01.p, 3);
+    return r;
+}
+
+// products of several pairs of equal level and batch size as one batch object
+// (ciphertext k * B + j is member j of pair k); its scale is that of pair 0
+// (callers that mix scales give each member its own afterwards)
+Ct op_hmult_many(ckks_ctx *c, const std::vector<const ckks_ct *> &A, const std::vector<const ckks_ct *> &Bv) {
+    if (!c->have_keys) fail(CKKS_E_NOKEY, "no keys");
+    const int G = (int)A.size();
+    if (G < 1 || G > gpu::kMaxGather || Bv.size() != A.size()) fail(CKKS_E_PARAM, "bad product list");
+    const int l = A[0]->level, nq = l + 1, B = A[0]->B;
+    for (int k = 0; k < G; ++k)
+        if (A[k]->level != l || Bv[k]->level != l || A[k]->B != B || Bv[k]->B != B)
+            fail(CKKS_E_LEVEL, "level or batch mismatch");
+    trace_op(c, "hmult", l, G * B);
+    const size_t N = c->N;
+    Ct r = ct_new(c, l, A[0]->scale * Bv[0]->scale, G * B);
+    Buf d01(c->pool.get(), (size_t)G * B * 2 * nq * N), d2(c->pool.get(), (size_t)G * B * nq * N);
+    gpu::GatherPtrs gp{};
+    gp.per_src = B;
+    for (int k = 0; k < G; ++k) {
+        gp.a[k] = A[k]->buf.p;
+        gp.b[k] = Bv[k]->buf.p;
+    }
+    gpu::tensor_gather(c->T, d01.p, d2.p, gp, nq, G * B, map_q(0, nq), c->stream);
+    keyswitch(c, l, d2.p, (size_t)nq * N, G * B, c->relin, r->buf.p, d01.p, 3);
     return r;
 }
 
@@ -982,31 +1023,24 @@ std::vector<Ct> mult_aligned_many(ckks_ctx *c, const std::vector<std::pair<const
         for (size_t i = i0; i < n; ++i)
             if (!done[i] && lv[i] == lv[i0]) grp.push_back(i), done[i] = 1;
         const int l = lv[i0];
-        if (grp.size() == 1 || A[i0]->B > kMaxWaveBatch) {
+        if (grp.size() == 1 || A[i0]->B > kMaxWaveBatch || grp.size() > (size_t)gpu::kMaxGather) {
             // a large batch fills the GPU by itself: the copies would cost more than they save
             for (size_t i : grp) out[i] = mult_rs(c, A[i], Bc[i]);
             continue;
         }
         const int B = A[i0]->B, G = (int)grp.size();
-        const size_t w = c->words(l) * B;
-        Ct la = ct_new(c, l, A[i0]->scale, G * B), lb = ct_new(c, l, Bc[i0]->scale, G * B);
-        for (int k = 0; k < G; ++k) {
-            hipchk(hipMemcpyAsync(la->buf.p + k * w, A[grp[k]]->buf.p, w * 8, hipMemcpyDeviceToDevice, c->stream),
-                   "batch");
-            hipchk(hipMemcpyAsync(lb->buf.p + k * w, Bc[grp[k]]->buf.p, w * 8, hipMemcpyDeviceToDevice, c->stream),
-                   "batch");
+        std::vector<const ckks_ct *> ga, gb;
+        for (size_t i : grp) {
+            ga.push_back(A[i]);
+            gb.push_back(Bc[i]);
         }
-        Ct m = op_hmult(c, la.get(), lb.get());
-        la.reset();
-        lb.reset();
+        Ct m = op_hmult_many(c, ga, gb);   // operands read in place (gathered)
         Ct r = op_rescale(c, m.get());
         m.reset();
-        const size_t wr = c->words(l - 1) * B;
-        for (int k = 0; k < G; ++k) {
+        std::shared_ptr<ckks_ct> rs(r.release());
+        for (int k = 0; k < G; ++k) {   // members as views of the batch, each with its own scale
             const size_t i = grp[k];
-            Ct o = ct_new(c, l - 1, (A[i]->scale * Bc[i]->scale) / (double)c->q[l], B);
-            hipchk(hipMemcpyAsync(o->buf.p, r->buf.p + k * wr, wr * 8, hipMemcpyDeviceToDevice, c->stream), "split");
-            out[i] = std::move(o);
+            out[i] = ct_view(c, rs, k * B, B, (A[i]->scale * Bc[i]->scale) / (double)c->q[l]);
         }
     }
     return out;
@@ -1418,8 +1452,9 @@ Ct op_bootstrap(ckks_ctx *c, const ckks_ct *a, int64_t bound) {
     im.reset();
     Ct e = op_eval_mod(c, both.get());
     both.reset();
-    Ct er = half_of(c, e.get(), 0), ei = half_of(c, e.get(), 1);
-    e.reset();
+    std::shared_ptr<ckks_ct> es(e.release());   // the real and imaginary halves as views
+    Ct er = ct_view(c, es, 0, es->B / 2, es->scale), ei = ct_view(c, es, es->B / 2, es->B / 2, es->scale);
+    es.reset();
     Ct eii = op_mul_monomial(c, ei.get(), N / 2);
     ei.reset();
     Ct w = op_addsub(c, er.get(), eii.get(), false);

@@ -93,6 +93,17 @@ void permute(const Tables &T, uint64_t *out, const uint64_t *a, const int32_t *p
 // d01 = (a0 b0, a0 b1 + a1 b0) laid out [nct][2][nlimb][N], d2 = a1 b1 [nct][nlimb][N]
 void tensor(const Tables &T, uint64_t *d01, uint64_t *d2, const uint64_t *a, const uint64_t *b, int nlimb, int nct,
             const LimbMap &m, hipStream_t s);
+// the same tensor with the operands gathered from several ciphertext objects:
+// ciphertext k of the product reads a[k / per_src] (and b[...]) at member
+// k % per_src (each source holds per_src ciphertexts [per_src][2][nlimb][N])
+constexpr int kMaxGather = 16;
+struct GatherPtrs {
+    const uint64_t *a[kMaxGather];
+    const uint64_t *b[kMaxGather];
+    int per_src;
+};
+void tensor_gather(const Tables &T, uint64_t *d01, uint64_t *d2, const GatherPtrs &g, int nlimb, int nct,
+                   const LimbMap &m, hipStream_t s);
 // out = a * b (pointwise), nlimb x npoly
 void mul_pointwise(const Tables &T, uint64_t *out, const uint64_t *a, const uint64_t *b, int nlimb,
                    int npoly, const LimbMap &m, hipStream_t s);

@@ -907,6 +907,34 @@ void tensor(const Tables &T, uint64_t *d01, uint64_t *d2, const uint64_t *a, con
     hipLaunchKernelGGL(k_tensor, grid_for(total), dim3(256), 0, s, d01, d2, a, b, T.logN, nlimb, total, m, T);
 }
 
+__global__ void k_tensor_gather(u64 *d01, u64 *d2, GatherPtrs g, int logN, int nlimb, size_t total, LimbMap m,
+                                Tables T) {
+    const size_t per = (size_t)nlimb << logN;   // words per poly
+    const size_t mask = ((size_t)1 << logN) - 1;
+    GRID_LOOP(i, total) {
+        ROW_SPLIT(i, logN, nlimb, ct, limb)
+        const DevPrime P = T.primes[m.p[limb]];
+        const size_t rem = ((size_t)limb << logN) | (i & mask);
+        const uint32_t src = ct / (uint32_t)g.per_src, loc = ct - src * (uint32_t)g.per_src;
+        const size_t sb = (size_t)loc * 2 * per + rem;
+        const u64 *a = g.a[src], *b = g.b[src];
+        const u64 x0 = a[sb], x1 = a[sb + per], y0 = b[sb], y1 = b[sb + per];
+        const size_t base = (size_t)ct * 2 * per + rem;
+        d01[base] = mul_mod(x0, y0, P);
+        u64 hi = 0, lo = 0;
+        mac128(hi, lo, x0, y1);
+        mac128(hi, lo, x1, y0);
+        d01[base + per] = reduce128(hi, lo, P);
+        d2[i] = mul_mod(x1, y1, P);
+    }
+}
+void tensor_gather(const Tables &T, uint64_t *d01, uint64_t *d2, const GatherPtrs &g, int nlimb, int nct,
+                   const LimbMap &m, hipStream_t s) {
+    size_t total = ((size_t)nlimb * nct) << T.logN;
+    if (!total) return;
+    hipLaunchKernelGGL(k_tensor_gather, grid_for(total), dim3(256), 0, s, d01, d2, g, T.logN, nlimb, total, m, T);
+}
+
 __global__ void k_mul_pointwise(u64 *out, const u64 *a, const u64 *b, int logN, int nlimb, size_t total, LimbMap m,
                                 Tables T) {
     GRID_LOOP(i, total) {
