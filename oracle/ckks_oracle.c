@@ -1625,7 +1625,8 @@ fail:
 /* with ct_x = x/2.  Level placement: c = min(l_x, l_y) (needs c >= 2);      */
 /*   x at level c: level_to (canonical) or, with raw_x, a plain limb drop    */
 /*   that keeps x's own scale;  u = (x@c)(y@c) -> c-1;                       */
-/*   v = y*y -> l_y - 1, then level_to(c-1);  w = u*v -> c-2;                */
+/*   v = (y@c)(y@c) -> c-1 (y aligned once, both products at one level);    */
+/*   w = u*v -> c-2;                                                         */
 /*   tmp_a = y dropped to c-1, Mul_P 1.5 at s_c = (scale(w) q_{c-1}) /       */
 /*   scale(y), rescaled, so that it lands exactly on scale(w).               */
 /* ------------------------------------------------------------------------ */
@@ -1635,10 +1636,8 @@ orc_ct *orc_newton_step_ex(orc_ctx *c, const orc_ct *y, const orc_ct *ctx_half, 
     orc_ct *xa = raw_x ? orc_drop_level(c, ctx_half, lc) : orc_level_to(c, ctx_half, lc);
     orc_ct *ya = orc_level_to(c, y, lc);
     orc_ct *u = mult_rs(c, xa, ya);
+    orc_ct *v = mult_rs(c, ya, ya);
     orc_ct_free(xa); orc_ct_free(ya);
-    orc_ct *v0 = mult_rs(c, y, y);
-    orc_ct *v = orc_level_to(c, v0, lc - 1);
-    orc_ct_free(v0);
     orc_ct *w = mult_rs(c, u, v);
     orc_ct_free(u); orc_ct_free(v);
     orc_ct *yd = orc_drop_level(c, y, lc - 1);

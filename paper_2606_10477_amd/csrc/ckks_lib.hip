@@ -1227,12 +1227,11 @@ Ct op_newton(ckks_ctx *c, const ckks_ct *y, const ckks_ct *half_x, bool raw_x) {
     if (lc < 2) fail(CKKS_E_LEVEL, "Newton step needs 2 levels");
     Ct xa = raw_x ? op_drop(c, half_x, lc) : op_level_to(c, half_x, lc);
     Ct ya = op_level_to(c, y, lc);
-    Ct u = mult_rs(c, xa.get(), ya.get());          // tmp_beta = ct_x * y
+    // tmp_beta = ct_x * y and y^2, both from y at the step's level: one wave
+    std::vector<Ct> uv = mult_aligned_many(c, {{xa.get(), ya.get()}, {ya.get(), ya.get()}});
     xa.reset();
     ya.reset();
-    Ct v0 = mult_rs(c, y, y);                       // y^2
-    Ct v = op_level_to(c, v0.get(), lc - 1);
-    v0.reset();
+    Ct u = std::move(uv[0]), v = std::move(uv[1]);
     Ct w = mult_rs(c, u.get(), v.get());            // tmp_beta * y^2
     u.reset();
     v.reset();
