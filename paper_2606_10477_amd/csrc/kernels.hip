@@ -1074,7 +1074,20 @@ __global__ void __launch_bounds__(256) k_bconv(u64 *out, const u64 *in, BconvArg
         y[i] = mul_shoup(src[(size_t)i * N + j], a.hinv[i], a.hinv_sh[i], q);
     }
     u64 *dst = out + poly * out_stride;
-    for (int r = r0; r < r1; ++r) {
+    int r = r0;
+    // two output limbs at a time: two independent 128-bit accumulation chains
+    for (; r + 1 < r1; r += 2) {
+        const DevPrime P0 = T.primes[a.pout.p[r]], P1 = T.primes[a.pout.p[r + 1]];
+        u64 h0 = 0, l0 = 0, h1 = 0, l1 = 0;
+#pragma unroll
+        for (int i = 0; i < DIN; ++i) {
+            mac128(h0, l0, y[i], a.mat[(size_t)i * a.dout + r]);
+            mac128(h1, l1, y[i], a.mat[(size_t)i * a.dout + r + 1]);
+        }
+        dst[(size_t)r * N + j] = reduce128(h0, l0, P0);
+        dst[(size_t)(r + 1) * N + j] = reduce128(h1, l1, P1);
+    }
+    if (r < r1) {
         const DevPrime P = T.primes[a.pout.p[r]];
         u64 hi = 0, lo = 0;
 #pragma unroll
