@@ -1184,15 +1184,15 @@ static uint64_t *modup(orc_ctx *c, int l, const uint64_t *d) {
 
 /* Inner product of the digits X (optionally read through the automorphism's
  * NTT-domain index map: X_j[e][perm[t]]) with the key, then ModDown by P. */
-static void ks_finish(orc_ctx *c, int l, const uint64_t *X, const int *perm, const evk_t *ek, uint64_t *o0,
-                      uint64_t *o1) {
+/* inner product of the digits with the key: acc_b = sum_j X_j * ek_j[b] over
+ * Q_l and P (b = 0, 1), laid out [2][ne][N] */
+static uint64_t *ks_inner(orc_ctx *c, int l, const uint64_t *X, const int *perm, const evk_t *ek) {
     size_t N = c->N;
     int K = c->K, L = c->L;
     int nq = l + 1, ne = nq + K;
     int beta = (nq + c->alpha - 1) / c->alpha;
     uint64_t *acc = calloc((size_t)2 * ne * N, sizeof(uint64_t));
     uint64_t *x = malloc(sizeof(uint64_t) * N);
-    uint64_t *tmp = malloc(sizeof(uint64_t) * N);
     for (int j = 0; j < beta; j++)
         for (int e = 0; e < ne; e++) {
             int pi = e < nq ? e : L + 1 + (e - nq);
@@ -1205,6 +1205,18 @@ static void ks_finish(orc_ctx *c, int l, const uint64_t *X, const int *perm, con
                 for (size_t t = 0; t < N; t++) ac[t] = addmod(ac[t], mulmod(x[t], kl[t], r), r);
             }
         }
+    free(x);
+    return acc;
+}
+
+static void ks_finish(orc_ctx *c, int l, const uint64_t *X, const int *perm, const evk_t *ek, uint64_t *o0,
+                      uint64_t *o1) {
+    size_t N = c->N;
+    int K = c->K, L = c->L;
+    int nq = l + 1, ne = nq + K;
+    uint64_t *acc = ks_inner(c, l, X, perm, ek);
+    uint64_t *x = malloc(sizeof(uint64_t) * N);
+    uint64_t *tmp = malloc(sizeof(uint64_t) * N);
     /* ModDown */
     for (int b = 0; b < 2; b++) {
         uint64_t *ac = acc + (size_t)b * ne * N;
@@ -1404,14 +1416,93 @@ orc_ct *orc_mul_const_down(orc_ctx *c, const orc_ct *a, double value) {
     if (a->level < 1) { set_err("level"); return NULL; }
     return mul_const_down(c, a, value);
 }
-/* Mul_C, relinearise, rescale */
+/*
+ * Mul_C, relinearise and rescale, with the rescale merged into the key
+ * switch's ModDown (one division by P q_l instead of a division by P, then a
+ * rounding division by q_l).  With the tensor (d0, d1, d2), the key switch's
+ * accumulator acc_b over Q_l and P (inner product of ModUp(d2) with the
+ * relinearisation key), t_b = acc_b + P d_b (d_b over Q_l only; zero mod P)
+ * and D = {q_l, p_0..p_{K-1}}:
+ *   o_b,i = (t_b,i - Conv_D(t_b)_i) (P q_l)^{-1}  mod q_i,  i < l,
+ *   Conv_D(t)_i = NTT_{q_i}( sum_{d in D} [iNTT_d(t_d) (D/d)^{-1}]_d (D/d mod q_i) ),
+ * computed as (acc_b,i - Conv_D(t_b)_i) (P q_l)^{-1} + d_b,i q_l^{-1}.  This is
+ * t / (P q_l) up to the approximate conversion's small overshoot (as in
+ * ModDown); scale' = s_a s_b / q_l, level l - 1.
+ */
 static orc_ct *mult_rs(orc_ctx *c, const orc_ct *a, const orc_ct *b) {
-    orc_ct *m = orc_hmult(c, a, b);
-    if (!m) return NULL;
-    orc_ct *r = orc_rescale(c, m);
-    orc_ct_free(m);
+    if (a->level != b->level) { set_err("level mismatch"); return NULL; }
+    if (!c->have_sk) { set_err("no keys"); return NULL; }
+    int l = a->level;
+    if (l < 1) { set_err("level"); return NULL; }
+    size_t N = c->N;
+    int K = c->K, L = c->L, nq = l + 1, ne = nq + K;
+    uint64_t *d = malloc(sizeof(uint64_t) * 2 * nq * N), *d2 = malloc(sizeof(uint64_t) * nq * N);
+    const uint64_t *a0 = ct_poly(c, a, 0), *a1 = ct_poly(c, a, 1);
+    const uint64_t *b0 = ct_poly(c, b, 0), *b1 = ct_poly(c, b, 1);
+    for (int i = 0; i < nq; i++) {
+        uint64_t q = c->q[i];
+        for (size_t t = 0; t < N; t++) {
+            size_t o = (size_t)i * N + t;
+            d[o] = mulmod(a0[o], b0[o], q);
+            d[(size_t)nq * N + o] = addmod(mulmod(a0[o], b1[o], q), mulmod(a1[o], b0[o], q), q);
+            d2[o] = mulmod(a1[o], b1[o], q);
+        }
+    }
+    uint64_t *X = modup(c, l, d2);
+    uint64_t *acc = ks_inner(c, l, X, NULL, &c->relin);
+    free(X); free(d2);
+    /* D as prime indices: q_l, then the special primes */
+    int nd = K + 1;
+    int *dp = malloc(sizeof(int) * nd);
+    dp[0] = l;
+    for (int k = 0; k < K; k++) dp[1 + k] = L + 1 + k;
+    orc_ct *r = ct_new(c, l - 1, a->scale * b->scale / (double)c->q[l]);
+    uint64_t *yd = malloc(sizeof(uint64_t) * nd * N), *x = malloc(sizeof(uint64_t) * N);
+    for (int bb = 0; bb < 2; bb++) {
+        const uint64_t *ac = acc + (size_t)bb * ne * N, *db = d + (size_t)bb * nq * N;
+        /* t on D, coefficient form, times (D/d)^{-1} mod d */
+        for (int jd = 0; jd < nd; jd++) {
+            int pi = dp[jd];
+            uint64_t p = c->q[pi], dh = 1;
+            uint64_t *y = yd + (size_t)jd * N;
+            if (jd == 0) {   /* q_l: acc + P d (P mod q_l) */
+                uint64_t Pm = 1;
+                for (int k = 0; k < K; k++) Pm = mulmod(Pm, c->q[L + 1 + k] % p, p);
+                for (size_t t = 0; t < N; t++)
+                    y[t] = addmod(ac[(size_t)l * N + t], mulmod(db[(size_t)l * N + t], Pm, p), p);
+            } else {         /* special prime: acc (P d = 0 there) */
+                memcpy(y, ac + (size_t)(nq + jd - 1) * N, sizeof(uint64_t) * N);
+            }
+            ntt_inv(c, pi, y);
+            for (int kk = 0; kk < nd; kk++) if (kk != jd) dh = mulmod(dh, c->q[dp[kk]] % p, p);
+            uint64_t dhinv = invmod(dh, p);
+            for (size_t t = 0; t < N; t++) y[t] = mulmod(y[t], dhinv, p);
+        }
+        uint64_t *o = r->c + (size_t)bb * l * N;
+        for (int i = 0; i < l; i++) {
+            uint64_t q = c->q[i];
+            memset(x, 0, sizeof(uint64_t) * N);
+            uint64_t Dm = 1;
+            for (int jd = 0; jd < nd; jd++) {
+                uint64_t dh = 1;
+                for (int kk = 0; kk < nd; kk++) if (kk != jd) dh = mulmod(dh, c->q[dp[kk]] % q, q);
+                for (size_t t = 0; t < N; t++) x[t] = addmod(x[t], mulmod(yd[(size_t)jd * N + t] % q, dh, q), q);
+                Dm = mulmod(Dm, c->q[dp[jd]] % q, q);
+            }
+            ntt_fwd(c, i, x);
+            uint64_t Dinv = invmod(Dm, q), qlinv = invmod(c->q[l] % q, q);
+            for (size_t t = 0; t < N; t++) {
+                size_t e = (size_t)i * N + t;
+                o[e] = addmod(mulmod(submod(ac[e], x[t], q), Dinv, q), mulmod(db[e], qlinv, q), q);
+            }
+        }
+    }
+    free(yd); free(x); free(dp); free(acc); free(d);
     return r;
 }
+/* exported for tests: the merged relinearise-and-rescale product */
+orc_ct *orc_mult_rs(orc_ctx *c, const orc_ct *a, const orc_ct *b) { return mult_rs(c, a, b); }
+
 /* aligned product: both operands brought to the lower of their levels */
 static orc_ct *mult_aligned(orc_ctx *c, const orc_ct *a, const orc_ct *b) {
     int l = a->level < b->level ? a->level : b->level;

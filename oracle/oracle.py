@@ -78,6 +78,7 @@ def lib():
         "orc_level_to": (vp, [vp, vp, C.c_int]),
         "orc_keyswitch": (C.c_int, [vp, C.c_int, C.c_int, u64p, u64p, u64p]),
         "orc_hmult": (vp, [vp, vp, vp]),
+        "orc_mult_rs": (vp, [vp, vp, vp]),
         "orc_automorphism": (vp, [vp, vp, C.c_int]),
         "orc_galois_rot": (C.c_int, [vp, C.c_int]),
         "orc_rotate": (vp, [vp, vp, C.c_int]),
@@ -312,6 +313,10 @@ class Context:
 
     def hmult(self, a, b):
         return Ct(self, lib().orc_hmult(self.ptr, a.ptr, b.ptr))
+
+    def mult_rs(self, a, b):
+        """Product, relinearisation and rescale in one ModDown (as the chains use)."""
+        return Ct(self, lib().orc_mult_rs(self.ptr, a.ptr, b.ptr))
 
     def automorphism(self, a, g):
         return Ct(self, lib().orc_automorphism(self.ptr, a.ptr, g))

@@ -225,6 +225,7 @@ struct ckks_ctx {
     Buf d_primes, d_fw, d_fwsh, d_iw, d_iwsh, d_ninv, d_ninvsh;
     Buf d_rsinv, d_rsinvsh;       // [L+1][L+1]: (q_l)^-1 mod q_i and Shoup quotient, for rescale from level l
     Buf d_pinv, d_pinvsh;         // [L+1]: P^-1 mod q_i and Shoup quotient (ModDown)
+    Buf d_pqinv, d_pqinvsh;       // [L+1][L+1]: (P q_l)^-1 mod q_i (ModDown merged with the rescale from l)
     std::string err;
     // keys
     bool have_keys = false;
@@ -235,6 +236,7 @@ struct ckks_ctx {
     std::map<int, Buf> perms;     // galois -> int32[N] (stored in a u64 buffer)
     std::map<std::pair<int, int>, std::unique_ptr<ConvTable>> modup;   // (level, digit)
     std::map<int, std::unique_ptr<ConvTable>> moddown;                 // level
+    std::map<int, std::unique_ptr<ConvTable>> moddown_rs;              // level: {q_l} + P -> Q_{l-1}
     hm::Cdt cdt;
     // opt-in timing of kernel families with HIP events on the context stream
     struct ProfFamily {
@@ -440,6 +442,17 @@ void build_tables(ckks_ctx *c) {
         c->d_pinvsh = Buf(P, L1);
         upload(c->d_pinv, pv.data(), L1 * 8, c->stream);
         upload(c->d_pinvsh, pvsh.data(), L1 * 8, c->stream);
+        std::vector<u64> pq((size_t)L1 * L1, 0), pqsh((size_t)L1 * L1, 0);
+        for (int l = 1; l < L1; ++l)
+            for (int i = 0; i < l; ++i) {
+                const u64 q = c->q[i];
+                pq[(size_t)l * L1 + i] = hm::mulmod(pv[i], rs[(size_t)l * L1 + i], q);
+                pqsh[(size_t)l * L1 + i] = shoup(pq[(size_t)l * L1 + i], q);
+            }
+        c->d_pqinv = Buf(P, pq.size());
+        c->d_pqinvsh = Buf(P, pq.size());
+        upload(c->d_pqinv, pq.data(), pq.size() * 8, c->stream);
+        upload(c->d_pqinvsh, pqsh.data(), pqsh.size() * 8, c->stream);
         c->d_rsinv = Buf(P, rs.size());
         c->d_rsinvsh = Buf(P, rs.size());
         upload(c->d_rsinv, rs.data(), rs.size() * 8, c->stream);
@@ -512,6 +525,19 @@ ConvTable *moddown_table(ckks_ctx *c, int level) {
     for (int i = 0; i <= level; ++i) out.push_back(i);
     ConvTable *t = make_conv(c, in, out);
     c->moddown[level].reset(t);
+    return t;
+}
+
+// conversion from D = {q_l, p_0..p_{K-1}} to q_0..q_{l-1} (ModDown merged
+// with the rescale from level l)
+ConvTable *moddown_rs_table(ckks_ctx *c, int level) {
+    auto it = c->moddown_rs.find(level);
+    if (it != c->moddown_rs.end()) return it->second.get();
+    std::vector<int> in{level}, out;
+    for (int k = 0; k < c->K; ++k) in.push_back(c->L + 1 + k);
+    for (int i = 0; i < level; ++i) out.push_back(i);
+    ConvTable *t = make_conv(c, in, out);
+    c->moddown_rs[level].reset(t);
     return t;
 }
 
@@ -796,6 +822,72 @@ Ct op_hmult_many(ckks_ctx *c, const std::vector<const ckks_ct *> &A, const std::
     return r;
 }
 
+// Mul_C, relinearisation and rescale with the rescale merged into the key
+// switch's ModDown (one division by P q_l), for several pairs of equal level
+// and batch size as one batch object (ciphertext k * B + j is member j of pair
+// k; its scale is that of pair 0, callers give members their own).  With the
+// tensor (d0, d1, d2), acc = <ModUp(d2), relin key> over Q_l and P, t = acc +
+// P (d0, d1) and D = {q_l} + P: out_i = (acc_i - Conv_D(t)_i) (P q_l)^-1 +
+// d_i q_l^-1 mod q_i for i < l.
+Ct op_hmult_rs_many(ckks_ctx *c, const std::vector<const ckks_ct *> &A, const std::vector<const ckks_ct *> &Bv) {
+    if (!c->have_keys) fail(CKKS_E_NOKEY, "no keys");
+    const int G = (int)A.size();
+    if (G < 1 || G > gpu::kMaxGather || Bv.size() != A.size()) fail(CKKS_E_PARAM, "bad product list");
+    const int l = A[0]->level, nq = l + 1, B = A[0]->B, K = c->K, ne = nq + K;
+    if (l < 1) fail(CKKS_E_LEVEL, "no level for Mul_C");
+    for (int k = 0; k < G; ++k)
+        if (A[k]->level != l || Bv[k]->level != l || A[k]->B != B || Bv[k]->B != B)
+            fail(CKKS_E_LEVEL, "level or batch mismatch");
+    trace_op(c, "hmult", l, G * B);
+    trace_op(c, "rescale", l, G * B);
+    const size_t N = c->N;
+    const int nct = G * B, np2 = 2 * nct;
+    Pool *P = c->pool.get();
+    Ct r = ct_new(c, l - 1, (A[0]->scale * Bv[0]->scale) / (double)c->q[l], nct);
+    Buf d01(P, (size_t)nct * 2 * nq * N), d2(P, (size_t)nct * nq * N);
+    gpu::GatherPtrs gp{};
+    gp.per_src = B;
+    for (int k = 0; k < G; ++k) {
+        gp.a[k] = A[k]->buf.p;
+        gp.b[k] = Bv[k]->buf.p;
+    }
+    gpu::tensor_gather(c->T, d01.p, d2.p, gp, nq, nct, map_q(0, nq), c->stream);
+    const int beta = (nq + c->alpha - 1) / c->alpha;
+    ProfScope ps(c, "keyswitch", 8.0 * (double)N * ((double)nct * nq + 2.0 * beta * ne + 2.0 * nct * l));
+    ModUp mu;
+    modup(c, l, d2.p, (size_t)nq * N, nct, mu);
+    gpu::InnerArgs ia = mu.ia;
+    ia.key = c->relin.k.p;
+    ia.perm = nullptr;
+    Buf acc(P, (size_t)np2 * ne * N);
+    gpu::key_inner(c->T, acc.p, ia, c->stream);
+    // t on q_l: acc + (P mod q_l) d
+    std::vector<int> pidx;
+    for (int k = 0; k < K; ++k) pidx.push_back(c->L + 1 + k);
+    const u64 ql = c->q[l], pm = prod_mod(c, pidx, -1, ql);
+    gpu::add_scaled_limb(c->T, acc.p + (size_t)l * N, (size_t)ne * N, d01.p + (size_t)l * N, (size_t)nq * N, np2, l,
+                         pm, shoup(pm, ql), c->stream);
+    ConvTable *md = moddown_rs_table(c, l);
+    Buf y(P, (size_t)np2 * (K + 1) * N);
+    ntt_oop_p(c, y.p, acc.p + (size_t)l * N, (size_t)ne * N, K + 1, np2, md->pin, true);
+    Buf z(P, (size_t)np2 * l * N);
+    gpu::BconvArgs bd{md->pin, md->pout, md->din, md->dout, md->hinv.p, md->hinv_sh.p, md->mat.p};
+    gpu::bconv(c->T, z.p, y.p, bd, np2, (size_t)(K + 1) * N, (size_t)l * N, c->stream);
+    const size_t L1 = (size_t)c->L + 1;
+    const u64 *inv = c->d_pqinv.p + (size_t)l * L1, *inv_sh = c->d_pqinvsh.p + (size_t)l * L1;
+    const u64 *w = c->d_rsinv.p + (size_t)l * L1, *w_sh = c->d_rsinvsh.p + (size_t)l * L1;
+    if (c->logN == 16) {
+        gpu::NttEpi ep{r->buf.p, acc.p, (size_t)ne * N, inv, inv_sh, d01.p, 3, (size_t)nq * N, w, w_sh};
+        ProfScope pn(c, "ntt", 16.0 * (double)l * np2 * N);
+        gpu::ntt16_fwd_fused(c->T, z.p, nullptr, &ep, l, np2, map_q(0, l), c->stream);
+    } else {
+        ntt_p(c, z.p, l, np2, map_q(0, l), false);
+        gpu::sub_mul_add_scaled(c->T, r->buf.p, acc.p, (size_t)ne * N, z.p, d01.p, (size_t)nq * N, inv, inv_sh, w,
+                                w_sh, l, np2, map_q(0, l), c->stream);
+    }
+    return r;
+}
+
 Ct op_automorphism(ckks_ctx *c, const ckks_ct *a, int g) {
     auto it = c->rot.find(g);
     if (it == c->rot.end()) fail(CKKS_E_NOKEY, "missing Galois key");
@@ -982,9 +1074,11 @@ Ct op_mul_const_down(ckks_ctx *c, const ckks_ct *a, double value) {
     return op_rescale(c, m.get());
 }
 
+// Mul_C, relinearise, rescale (the rescale merged into the ModDown)
 Ct mult_rs(ckks_ctx *c, const ckks_ct *a, const ckks_ct *b) {
-    Ct m = op_hmult(c, a, b);
-    return op_rescale(c, m.get());
+    if (a->level != b->level) fail(CKKS_E_LEVEL, "level mismatch");
+    if (a->B != b->B) fail(CKKS_E_PARAM, "batch size mismatch");
+    return op_hmult_rs_many(c, {a}, {b});
 }
 Ct mult_aligned(ckks_ctx *c, const ckks_ct *a, const ckks_ct *b) {
     int l = std::min(a->level, b->level);
@@ -1034,9 +1128,7 @@ std::vector<Ct> mult_aligned_many(ckks_ctx *c, const std::vector<std::pair<const
             ga.push_back(A[i]);
             gb.push_back(Bc[i]);
         }
-        Ct m = op_hmult_many(c, ga, gb);   // operands read in place (gathered)
-        Ct r = op_rescale(c, m.get());
-        m.reset();
+        Ct r = op_hmult_rs_many(c, ga, gb);   // operands read in place (gathered)
         std::shared_ptr<ckks_ct> rs(r.release());
         for (int k = 0; k < G; ++k) {   // members as views of the batch, each with its own scale
             const size_t i = grp[k];

@@ -59,6 +59,10 @@ struct NttEpi {
     const uint64_t *inv, *inv_sh;
     const uint64_t *add;
     int add_mask;
+    // optional: add read with a per-poly stride of add_stride words (0: out's
+    // layout) and multiplied by add_w[e] (Shoup quotient add_wsh[e]) first
+    size_t add_stride;
+    const uint64_t *add_w, *add_wsh;
 };
 void ntt16_fwd_fused(const Tables &T, uint64_t *work, const NttLift *lift, const NttEpi *epi, int nlimb, int npoly,
                      const LimbMap &m, hipStream_t s);
@@ -104,6 +108,17 @@ struct GatherPtrs {
 };
 void tensor_gather(const Tables &T, uint64_t *d01, uint64_t *d2, const GatherPtrs &g, int nlimb, int nct,
                    const LimbMap &m, hipStream_t s);
+// dst_p += k * src_p (mod q_prime) over one limb of npoly polys (poly p at
+// dst + p * dst_stride, src + p * src_stride)
+void add_scaled_limb(const Tables &T, uint64_t *dst, size_t dst_stride, const uint64_t *src, size_t src_stride,
+                     int npoly, int prime, uint64_t k, uint64_t k_sh, hipStream_t s);
+// out_p,e = (c_p,e - z_p,e) inv[e] + a_p,e w[e]  (mod q_e) over nlimb limbs of
+// npoly polys: c at stride c_stride per poly, a at a_stride, z and out
+// contiguous [npoly][nlimb][N]; inv / w with Shoup quotients, device arrays
+void sub_mul_add_scaled(const Tables &T, uint64_t *out, const uint64_t *c, size_t c_stride, const uint64_t *z,
+                        const uint64_t *a, size_t a_stride, const uint64_t *inv, const uint64_t *inv_sh,
+                        const uint64_t *w, const uint64_t *w_sh, int nlimb, int npoly, const LimbMap &m,
+                        hipStream_t s);
 // out = a * b (pointwise), nlimb x npoly
 void mul_pointwise(const Tables &T, uint64_t *out, const uint64_t *a, const uint64_t *b, int nlimb,
                    int npoly, const LimbMap &m, hipStream_t s);

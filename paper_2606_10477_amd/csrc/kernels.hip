@@ -205,6 +205,12 @@ struct Lifter {
 };
 // epilogue of a fused forward transform: (c - x) * inv mod q
 DEV u64 epi_word(u64 x, u64 c, u64 iv, u64 ivs, u64 q) { return mul_shoup(sub_mod(c, x, q), iv, ivs, q); }
+// the epilogue's added term for poly pidx, limb lidx, tile offset off (null if none)
+DEV const u64 *epi_add_ptr(const NttEpi &ep, uint32_t pidx, uint32_t lidx, size_t row_off, size_t off) {
+    if (!ep.add || !((ep.add_mask >> (pidx & 1)) & 1)) return nullptr;
+    if (ep.add_stride) return ep.add + (size_t)pidx * ep.add_stride + ((size_t)lidx << 16) + off;
+    return ep.add + row_off + off;
+}
 
 // ---------------------------------------------------------------------------
 // N = 2^16: two passes of 8 stages, each split into two radix-16 register
@@ -389,12 +395,13 @@ __global__ void __launch_bounds__(256) k_ntt16_blocks_fwd(u64 *data, int nlimb, 
         const u64 *cc = ep.c + (size_t)pidx * ep.c_stride + ((size_t)lidx << 16) + off;
         u64 *o = ep.out + row_off + off;
         const u64 iv = ep.inv[lidx], ivs = ep.inv_sh[lidx];
-        const u64 *ad = ep.add && ((ep.add_mask >> (pidx & 1)) & 1) ? ep.add + row_off + off : nullptr;
+        const u64 *ad = epi_add_ptr(ep, pidx, lidx, row_off, off);
+        const u64 aw = ep.add_w ? ep.add_w[lidx] : 0, aws = ep.add_w ? ep.add_wsh[lidx] : 0;
 #pragma unroll
         for (int mm = 0; mm < 16; ++mm) {
             const int at = (y << 8) + x + 16 * mm;
             const u64 r = epi_word(tile[(y * 16 + mm) * kPad + x], cc[at], iv, ivs, q);
-            o[at] = ad ? add_mod(r, ad[at], q) : r;
+            o[at] = ad ? add_mod(r, ep.add_w ? mul_shoup(ad[at], aw, aws, q) : ad[at], q) : r;
         }
     } else {
 #pragma unroll
@@ -637,12 +644,13 @@ __global__ void __launch_bounds__(Geo<R>::NT) k_nttr_blocks_fwd(u64 *data, int n
         const u64 *cc = ep.c + (size_t)pidx * ep.c_stride + ((size_t)lidx << 16) + off;
         u64 *o = ep.out + row_off + off;
         const u64 iv = ep.inv[lidx], ivs = ep.inv_sh[lidx];
-        const u64 *ad = ep.add && ((ep.add_mask >> (pidx & 1)) & 1) ? ep.add + row_off + off : nullptr;
+        const u64 *ad = epi_add_ptr(ep, pidx, lidx, row_off, off);
+        const u64 aw = ep.add_w ? ep.add_w[lidx] : 0, aws = ep.add_w ? ep.add_wsh[lidx] : 0;
 #pragma unroll
         for (int mm = 0; mm < R; ++mm) {
             const int at = (lane << 8) + k_of<R>(u, mm, loL);
             const u64 r = epi_word(v[mm], cc[at], iv, ivs, q);
-            o[at] = ad ? add_mod(r, ad[at], q) : r;
+            o[at] = ad ? add_mod(r, ep.add_w ? mul_shoup(ad[at], aw, aws, q) : ad[at], q) : r;
         }
     } else {
 #pragma unroll
@@ -1226,6 +1234,43 @@ void moddown_finish_jobs(const Tables &T, const FinishJobs &f, const uint64_t *a
     if (!total) return;
     hipLaunchKernelGGL(k_moddown_finish_jobs, grid_for(total), dim3(256), 0, s, f, acc, acc_poly_stride, z, pinv,
                        T.logN, nlimb, B, total, m, T);
+}
+
+__global__ void k_add_scaled_limb(u64 *dst, size_t dst_stride, const u64 *src, size_t src_stride, int logN,
+                                  size_t total, int prime, u64 k, u64 k_sh, Tables T) {
+    const u64 q = T.primes[prime].q;
+    GRID_LOOP(i, total) {
+        const size_t p = i >> logN, j = i & (((size_t)1 << logN) - 1);
+        u64 *d = dst + p * dst_stride + j;
+        *d = add_mod(*d, mul_shoup(src[p * src_stride + j], k, k_sh, q), q);
+    }
+}
+void add_scaled_limb(const Tables &T, uint64_t *dst, size_t dst_stride, const uint64_t *src, size_t src_stride,
+                     int npoly, int prime, uint64_t k, uint64_t k_sh, hipStream_t s) {
+    const size_t total = (size_t)npoly << T.logN;
+    if (!total) return;
+    hipLaunchKernelGGL(k_add_scaled_limb, grid_for(total), dim3(256), 0, s, dst, dst_stride, src, src_stride, T.logN,
+                       total, prime, k, k_sh, T);
+}
+__global__ void k_sub_mul_add_scaled(u64 *out, const u64 *c, size_t c_stride, const u64 *z, const u64 *a,
+                                     size_t a_stride, const u64 *inv, const u64 *inv_sh, const u64 *w,
+                                     const u64 *w_sh, int logN, int nlimb, size_t total, LimbMap m, Tables T) {
+    GRID_LOOP(i, total) {
+        ROW_SPLIT(i, logN, nlimb, poly, limb)
+        const size_t rem = ((size_t)limb << logN) | (i & (((size_t)1 << logN) - 1));
+        const u64 q = T.primes[m.p[limb]].q;
+        const u64 r = mul_shoup(sub_mod(c[(size_t)poly * c_stride + rem], z[i], q), inv[limb], inv_sh[limb], q);
+        out[i] = add_mod(r, mul_shoup(a[(size_t)poly * a_stride + rem], w[limb], w_sh[limb], q), q);
+    }
+}
+void sub_mul_add_scaled(const Tables &T, uint64_t *out, const uint64_t *c, size_t c_stride, const uint64_t *z,
+                        const uint64_t *a, size_t a_stride, const uint64_t *inv, const uint64_t *inv_sh,
+                        const uint64_t *w, const uint64_t *w_sh, int nlimb, int npoly, const LimbMap &m,
+                        hipStream_t s) {
+    const size_t total = ((size_t)nlimb * npoly) << T.logN;
+    if (!total) return;
+    hipLaunchKernelGGL(k_sub_mul_add_scaled, grid_for(total), dim3(256), 0, s, out, c, c_stride, z, a, a_stride, inv,
+                       inv_sh, w, w_sh, T.logN, nlimb, total, m, T);
 }
 
 // one thread per (member, poly, limb, word): every job's finished word summed

@@ -375,6 +375,25 @@ def test_hmult_rotate_conjugate_decrypt(oracle_mod, p12):
         p12.add(a, m)               # level mismatch
 
 
+def test_merged_product_matches_separate_ops(oracle_mod, p12):
+    """The chains' product (relinearisation and rescale in one ModDown by
+    P q_l) against Mul_C then Rescale: the two decryptions differ by no more
+    than the roundings of the two divisions (a few units of the output scale
+    times the secret's weight), and both match the FP64 product."""
+    x = inputs.log_uniform(p12.n, 2 ** -8, 1.0, 11)
+    x2 = inputs.log_uniform(p12.n, 2 ** -8, 1.0, 12)
+    for lvl in (13, 5, 1):
+        a = p12.encrypt(x, lvl, 2.0 ** 40, 13 + lvl)
+        b = p12.encrypt(x2, lvl, 2.0 ** 40, 14 + lvl)
+        sep = p12.rescale(p12.hmult(a, b))
+        mer = p12.mult_rs(a, b)
+        assert mer.level == lvl - 1 and mer.scale == sep.scale
+        cs, cm = p12.decrypt_coeffs(sep), p12.decrypt_coeffs(mer)
+        weight = int(np.sum(np.abs(p12.secret())))
+        assert np.max(np.abs(np.asarray(cm, dtype=float) - np.asarray(cs, dtype=float))) <= 3 * (weight + 1)
+        assert np.max(np.abs(p12.decrypt(mer) - x * x2)) < 1e-6
+
+
 def test_constants_and_level_to(oracle_mod, p12):
     x = inputs.log_uniform(p12.n, 2 ** -8, 1.0, 1)
     a = p12.encrypt(x, 13, 2.0 ** 50, 3)
