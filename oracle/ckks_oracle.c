@@ -1417,46 +1417,21 @@ orc_ct *orc_mul_const_down(orc_ctx *c, const orc_ct *a, double value) {
     return mul_const_down(c, a, value);
 }
 /*
- * Mul_C, relinearise and rescale, with the rescale merged into the key
- * switch's ModDown (one division by P q_l instead of a division by P, then a
- * rounding division by q_l).  With the tensor (d0, d1, d2), the key switch's
- * accumulator acc_b over Q_l and P (inner product of ModUp(d2) with the
- * relinearisation key), t_b = acc_b + P d_b (d_b over Q_l only; zero mod P)
- * and D = {q_l, p_0..p_{K-1}}:
- *   o_b,i = (t_b,i - Conv_D(t_b)_i) (P q_l)^{-1}  mod q_i,  i < l,
- *   Conv_D(t)_i = NTT_{q_i}( sum_{d in D} [iNTT_d(t_d) (D/d)^{-1}]_d (D/d mod q_i) ),
- * computed as (acc_b,i - Conv_D(t_b)_i) (P q_l)^{-1} + d_b,i q_l^{-1}.  This is
- * t / (P q_l) up to the approximate conversion's small overshoot (as in
- * ModDown); scale' = s_a s_b / q_l, level l - 1.
+ * ModDown by P q_l of t_b = acc_b + P d_b (b = 0, 1): acc over Q_l and P
+ * ([2][ne][N], NTT form), d over Q_l ([2][nq][N]); D = {q_l, p_0..p_{K-1}}:
+ *   o_b,i = (acc_b,i - Conv_D(t_b)_i) (P q_l)^{-1} + d_b,i q_l^{-1}  mod q_i,  i < l,
+ *   Conv_D(t)_i = NTT_{q_i}( sum_{d in D} [iNTT_d(t_d) (D/d)^{-1}]_d (D/d mod q_i) ).
+ * Returns the ciphertext at level l - 1 with the given scale.
  */
-static orc_ct *mult_rs(orc_ctx *c, const orc_ct *a, const orc_ct *b) {
-    if (a->level != b->level) { set_err("level mismatch"); return NULL; }
-    if (!c->have_sk) { set_err("no keys"); return NULL; }
-    int l = a->level;
-    if (l < 1) { set_err("level"); return NULL; }
+static orc_ct *moddown_rescale(orc_ctx *c, int l, const uint64_t *acc, const uint64_t *d, double scale) {
     size_t N = c->N;
     int K = c->K, L = c->L, nq = l + 1, ne = nq + K;
-    uint64_t *d = malloc(sizeof(uint64_t) * 2 * nq * N), *d2 = malloc(sizeof(uint64_t) * nq * N);
-    const uint64_t *a0 = ct_poly(c, a, 0), *a1 = ct_poly(c, a, 1);
-    const uint64_t *b0 = ct_poly(c, b, 0), *b1 = ct_poly(c, b, 1);
-    for (int i = 0; i < nq; i++) {
-        uint64_t q = c->q[i];
-        for (size_t t = 0; t < N; t++) {
-            size_t o = (size_t)i * N + t;
-            d[o] = mulmod(a0[o], b0[o], q);
-            d[(size_t)nq * N + o] = addmod(mulmod(a0[o], b1[o], q), mulmod(a1[o], b0[o], q), q);
-            d2[o] = mulmod(a1[o], b1[o], q);
-        }
-    }
-    uint64_t *X = modup(c, l, d2);
-    uint64_t *acc = ks_inner(c, l, X, NULL, &c->relin);
-    free(X); free(d2);
     /* D as prime indices: q_l, then the special primes */
     int nd = K + 1;
     int *dp = malloc(sizeof(int) * nd);
     dp[0] = l;
     for (int k = 0; k < K; k++) dp[1 + k] = L + 1 + k;
-    orc_ct *r = ct_new(c, l - 1, a->scale * b->scale / (double)c->q[l]);
+    orc_ct *r = ct_new(c, l - 1, scale);
     uint64_t *yd = malloc(sizeof(uint64_t) * nd * N), *x = malloc(sizeof(uint64_t) * N);
     for (int bb = 0; bb < 2; bb++) {
         const uint64_t *ac = acc + (size_t)bb * ne * N, *db = d + (size_t)bb * nq * N;
@@ -1497,7 +1472,47 @@ static orc_ct *mult_rs(orc_ctx *c, const orc_ct *a, const orc_ct *b) {
             }
         }
     }
-    free(yd); free(x); free(dp); free(acc); free(d);
+    free(yd); free(x); free(dp);
+    return r;
+}
+
+/*
+ * Mul_C, relinearise and rescale, with the rescale merged into the key
+ * switch's ModDown (one division by P q_l instead of a division by P, then a
+ * rounding division by q_l).  With the tensor (d0, d1, d2), the key switch's
+ * accumulator acc_b over Q_l and P (inner product of ModUp(d2) with the
+ * relinearisation key), t_b = acc_b + P d_b (d_b over Q_l only; zero mod P)
+ * and D = {q_l, p_0..p_{K-1}}:
+ *   o_b,i = (t_b,i - Conv_D(t_b)_i) (P q_l)^{-1}  mod q_i,  i < l,
+ *   Conv_D(t)_i = NTT_{q_i}( sum_{d in D} [iNTT_d(t_d) (D/d)^{-1}]_d (D/d mod q_i) ),
+ * computed as (acc_b,i - Conv_D(t_b)_i) (P q_l)^{-1} + d_b,i q_l^{-1}.  This is
+ * t / (P q_l) up to the approximate conversion's small overshoot (as in
+ * ModDown); scale' = s_a s_b / q_l, level l - 1.
+ */
+static orc_ct *mult_rs(orc_ctx *c, const orc_ct *a, const orc_ct *b) {
+    if (a->level != b->level) { set_err("level mismatch"); return NULL; }
+    if (!c->have_sk) { set_err("no keys"); return NULL; }
+    int l = a->level;
+    if (l < 1) { set_err("level"); return NULL; }
+    size_t N = c->N;
+    int K = c->K, L = c->L, nq = l + 1, ne = nq + K;
+    uint64_t *d = malloc(sizeof(uint64_t) * 2 * nq * N), *d2 = malloc(sizeof(uint64_t) * nq * N);
+    const uint64_t *a0 = ct_poly(c, a, 0), *a1 = ct_poly(c, a, 1);
+    const uint64_t *b0 = ct_poly(c, b, 0), *b1 = ct_poly(c, b, 1);
+    for (int i = 0; i < nq; i++) {
+        uint64_t q = c->q[i];
+        for (size_t t = 0; t < N; t++) {
+            size_t o = (size_t)i * N + t;
+            d[o] = mulmod(a0[o], b0[o], q);
+            d[(size_t)nq * N + o] = addmod(mulmod(a0[o], b1[o], q), mulmod(a1[o], b0[o], q), q);
+            d2[o] = mulmod(a1[o], b1[o], q);
+        }
+    }
+    uint64_t *X = modup(c, l, d2);
+    uint64_t *acc = ks_inner(c, l, X, NULL, &c->relin);
+    free(X); free(d2);
+    orc_ct *r = moddown_rescale(c, l, acc, d, a->scale * b->scale / (double)c->q[l]);
+    free(acc); free(d);
     return r;
 }
 /* exported for tests: the merged relinearise-and-rescale product */
@@ -2015,6 +2030,14 @@ static orc_ct *lt_apply(orc_ctx *c, const orc_ct *x, const lt_group *G, double s
     cq *v = malloc(sizeof(cq) * n);
     i128 *coef = malloc(sizeof(i128) * N);
     uint64_t *pt = malloc(sizeof(uint64_t) * N);
+    /* giant steps: the rotated ones' key-switch accumulators summed over Q_l
+     * and P (A), their rotated c0 and giant 0's inner sum summed over Q_l (E);
+     * the output is ModDown by P q_l of A + P E (the rescale merged) */
+    int K = c->K, nq = l + 1, ne = nq + K;
+    uint64_t *A = calloc((size_t)2 * ne * N, sizeof(uint64_t));
+    uint64_t *E = calloc((size_t)2 * nq * N, sizeof(uint64_t));
+    int *perm = malloc(sizeof(int) * N);
+    int nrot = 0;
     orc_ct *acc = NULL;
     int imin = floordiv(G->m[0], g), imax = floordiv(G->m[G->nm - 1], g);
     int fail = 0;
@@ -2043,24 +2066,53 @@ static orc_ct *lt_apply(orc_ctx *c, const orc_ct *x, const lt_group *G, double s
         }
         if (fail || !inner) continue;
         if (i != 0) {
-            /* giant rotation in the hoisted form too (automorphism applied to
-             * the ModUp digits of the inner sum) */
+            /* giant rotation in the hoisted form (automorphism applied to the
+             * ModUp digits of the inner sum), kept before its ModDown */
             int kk = (int)(((int64_t)g * i * G->s) % n);
-            orc_ct *ri = NULL;
-            int rc2 = orc_rotate_hoisted(c, inner, &kk, 1, &ri);
+            int ga = orc_galois_rot(c, kk), ri = find_rot(c, ga);
+            if (ri < 0) { set_err("missing galois key"); orc_ct_free(inner); fail = 1; break; }
+            automorph_idx(c, ga, perm);
+            uint64_t *X = modup(c, l, ct_poly(c, inner, 1));
+            uint64_t *ai = ks_inner(c, l, X, perm, &c->rot[ri]);
+            free(X);
+            for (int b = 0; b < 2; b++)
+                for (int e = 0; e < ne; e++) {
+                    uint64_t r = c->q[e < nq ? e : c->L + 1 + (e - nq)];
+                    uint64_t *dst = A + ((size_t)b * ne + e) * N;
+                    const uint64_t *src = ai + ((size_t)b * ne + e) * N;
+                    for (size_t t = 0; t < N; t++) dst[t] = addmod(dst[t], src[t], r);
+                }
+            free(ai);
+            const uint64_t *c0 = ct_poly(c, inner, 0);
+            for (int li = 0; li < nq; li++)
+                for (size_t t = 0; t < N; t++)
+                    E[(size_t)li * N + t] = addmod(E[(size_t)li * N + t], c0[(size_t)li * N + perm[t]], c->q[li]);
+            nrot++;
             orc_ct_free(inner);
-            if (rc2 != 0 || !ri) { fail = 1; break; }
-            inner = ri;
+            continue;
         }
-        if (!acc) acc = inner;
-        else { orc_ct *t2 = orc_add(c, acc, inner); orc_ct_free(acc); orc_ct_free(inner); acc = t2; }
+        for (int p2 = 0; p2 < 2; p2++) {
+            const uint64_t *src = ct_poly(c, inner, p2);
+            for (int li = 0; li < nq; li++)
+                for (size_t t = 0; t < N; t++) {
+                    size_t e = ((size_t)p2 * nq + li) * N + t;
+                    E[e] = addmod(E[e], src[(size_t)li * N + t], c->q[li]);
+                }
+        }
+        if (!acc) acc = inner;   /* giant 0 alone: rescaled below */
+        else orc_ct_free(inner);
     }
-    free(v); free(coef); free(pt);
+    free(v); free(coef); free(pt); free(perm);
     for (int k = 0; k < g; k++) orc_ct_free(R[k]);
     free(R);
-    if (fail || !acc) { orc_ct_free(acc); return NULL; }
-    orc_ct *r = orc_rescale(c, acc);
+    orc_ct *r = NULL;
+    if (!fail && nrot > 0) {
+        r = moddown_rescale(c, l, A, E, x->scale * sd / (double)c->q[l]);
+    } else if (!fail && acc) {
+        r = orc_rescale(c, acc);
+    }
     orc_ct_free(acc);
+    free(A); free(E);
     return r;
 }
 

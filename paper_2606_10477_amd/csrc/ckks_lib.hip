@@ -822,6 +822,41 @@ Ct op_hmult_many(ckks_ctx *c, const std::vector<const ckks_ct *> &A, const std::
     return r;
 }
 
+// ModDown by P q_l of t = acc + P d over np2 polys (the rescale from level l
+// merged into the key switch's ModDown): acc [np2][l+1+K][N] over Q_l and P
+// (its q_l limb is overwritten with t's), d [np2][l+1][N] over Q_l, out
+// [np2][l][N]: out_i = (acc_i - Conv_D(t)_i) (P q_l)^-1 + d_i q_l^-1 mod q_i,
+// D = {q_l} + P, with the approximate conversion.
+void moddown_rescale(ckks_ctx *c, int l, u64 *acc, const u64 *d, int np2, u64 *out) {
+    const size_t N = c->N;
+    const int nq = l + 1, K = c->K, ne = nq + K;
+    Pool *P = c->pool.get();
+    std::vector<int> pidx;
+    for (int k = 0; k < K; ++k) pidx.push_back(c->L + 1 + k);
+    const u64 ql = c->q[l], pm = prod_mod(c, pidx, -1, ql);
+    // t on q_l: acc + (P mod q_l) d
+    gpu::add_scaled_limb(c->T, acc + (size_t)l * N, (size_t)ne * N, d + (size_t)l * N, (size_t)nq * N, np2, l, pm,
+                         shoup(pm, ql), c->stream);
+    ConvTable *md = moddown_rs_table(c, l);
+    Buf y(P, (size_t)np2 * (K + 1) * N);
+    ntt_oop_p(c, y.p, acc + (size_t)l * N, (size_t)ne * N, K + 1, np2, md->pin, true);
+    Buf z(P, (size_t)np2 * l * N);
+    gpu::BconvArgs bd{md->pin, md->pout, md->din, md->dout, md->hinv.p, md->hinv_sh.p, md->mat.p};
+    gpu::bconv(c->T, z.p, y.p, bd, np2, (size_t)(K + 1) * N, (size_t)l * N, c->stream);
+    const size_t L1 = (size_t)c->L + 1;
+    const u64 *inv = c->d_pqinv.p + (size_t)l * L1, *inv_sh = c->d_pqinvsh.p + (size_t)l * L1;
+    const u64 *w = c->d_rsinv.p + (size_t)l * L1, *w_sh = c->d_rsinvsh.p + (size_t)l * L1;
+    if (c->logN == 16) {
+        gpu::NttEpi ep{out, acc, (size_t)ne * N, inv, inv_sh, d, 3, (size_t)nq * N, w, w_sh};
+        ProfScope pn(c, "ntt", 16.0 * (double)l * np2 * N);
+        gpu::ntt16_fwd_fused(c->T, z.p, nullptr, &ep, l, np2, map_q(0, l), c->stream);
+    } else {
+        ntt_p(c, z.p, l, np2, map_q(0, l), false);
+        gpu::sub_mul_add_scaled(c->T, out, acc, (size_t)ne * N, z.p, d, (size_t)nq * N, inv, inv_sh, w, w_sh, l, np2,
+                                map_q(0, l), c->stream);
+    }
+}
+
 // Mul_C, relinearisation and rescale with the rescale merged into the key
 // switch's ModDown (one division by P q_l), for several pairs of equal level
 // and batch size as one batch object (ciphertext k * B + j is member j of pair
@@ -861,30 +896,7 @@ Ct op_hmult_rs_many(ckks_ctx *c, const std::vector<const ckks_ct *> &A, const st
     ia.perm = nullptr;
     Buf acc(P, (size_t)np2 * ne * N);
     gpu::key_inner(c->T, acc.p, ia, c->stream);
-    // t on q_l: acc + (P mod q_l) d
-    std::vector<int> pidx;
-    for (int k = 0; k < K; ++k) pidx.push_back(c->L + 1 + k);
-    const u64 ql = c->q[l], pm = prod_mod(c, pidx, -1, ql);
-    gpu::add_scaled_limb(c->T, acc.p + (size_t)l * N, (size_t)ne * N, d01.p + (size_t)l * N, (size_t)nq * N, np2, l,
-                         pm, shoup(pm, ql), c->stream);
-    ConvTable *md = moddown_rs_table(c, l);
-    Buf y(P, (size_t)np2 * (K + 1) * N);
-    ntt_oop_p(c, y.p, acc.p + (size_t)l * N, (size_t)ne * N, K + 1, np2, md->pin, true);
-    Buf z(P, (size_t)np2 * l * N);
-    gpu::BconvArgs bd{md->pin, md->pout, md->din, md->dout, md->hinv.p, md->hinv_sh.p, md->mat.p};
-    gpu::bconv(c->T, z.p, y.p, bd, np2, (size_t)(K + 1) * N, (size_t)l * N, c->stream);
-    const size_t L1 = (size_t)c->L + 1;
-    const u64 *inv = c->d_pqinv.p + (size_t)l * L1, *inv_sh = c->d_pqinvsh.p + (size_t)l * L1;
-    const u64 *w = c->d_rsinv.p + (size_t)l * L1, *w_sh = c->d_rsinvsh.p + (size_t)l * L1;
-    if (c->logN == 16) {
-        gpu::NttEpi ep{r->buf.p, acc.p, (size_t)ne * N, inv, inv_sh, d01.p, 3, (size_t)nq * N, w, w_sh};
-        ProfScope pn(c, "ntt", 16.0 * (double)l * np2 * N);
-        gpu::ntt16_fwd_fused(c->T, z.p, nullptr, &ep, l, np2, map_q(0, l), c->stream);
-    } else {
-        ntt_p(c, z.p, l, np2, map_q(0, l), false);
-        gpu::sub_mul_add_scaled(c->T, r->buf.p, acc.p, (size_t)ne * N, z.p, d01.p, (size_t)nq * N, inv, inv_sh, w,
-                                w_sh, l, np2, map_q(0, l), c->stream);
-    }
+    moddown_rescale(c, l, acc.p, d01.p, np2, r->buf.p);
     return r;
 }
 
@@ -915,18 +927,7 @@ struct RotJob {
 };
 // Key switching of rotation jobs over one ModUp: inner products and ModDown
 // of up to kMaxJobs jobs run as one launch sequence.
-void ks_rot_jobs_impl(ckks_ctx *c, const ModUp &mu, int B, const std::vector<RotJob> &jobs, u64 *sum_out,
-                      const u64 *sum_extra);
 void ks_rot_jobs(ckks_ctx *c, const ModUp &mu, int B, const std::vector<RotJob> &jobs) {
-    ks_rot_jobs_impl(c, mu, B, jobs, nullptr, nullptr);
-}
-// the jobs' results summed into sum_out ([B][2][l+1][N]) plus sum_extra (nullable)
-void ks_rot_jobs_sum(ckks_ctx *c, const ModUp &mu, int B, const std::vector<RotJob> &jobs, u64 *sum_out,
-                     const u64 *sum_extra) {
-    ks_rot_jobs_impl(c, mu, B, jobs, sum_out, sum_extra);
-}
-void ks_rot_jobs_impl(ckks_ctx *c, const ModUp &mu, int B, const std::vector<RotJob> &jobs, u64 *sum_out,
-                      const u64 *sum_extra) {
     const size_t N = c->N;
     const int l = mu.l, nq = l + 1, ne = nq + c->K;
     const int beta = (nq + c->alpha - 1) / c->alpha;
@@ -966,11 +967,7 @@ void ks_rot_jobs_impl(ckks_ctx *c, const ModUp &mu, int B, const std::vector<Rot
         gpu::BconvArgs bd{md->pin, md->pout, md->din, md->dout, md->hinv.p, md->hinv_sh.p, md->mat.p};
         gpu::bconv(c->T, z.p, y.p, bd, np2, (size_t)c->K * N, (size_t)nq * N, c->stream);
         ntt_p(c, z.p, nq, np2, map_q(0, nq), false);
-        if (sum_out)
-            gpu::moddown_finish_jobs_sum(c->T, fj, sum_out, sum_extra, j0 > 0, acc.p, (size_t)ne * N, z.p, pinv, nq,
-                                         nj, B, map_q(0, nq), c->stream);
-        else
-            gpu::moddown_finish_jobs(c->T, fj, acc.p, (size_t)ne * N, z.p, pinv, nq, nj, B, map_q(0, nq), c->stream);
+        gpu::moddown_finish_jobs(c->T, fj, acc.p, (size_t)ne * N, z.p, pinv, nq, nj, B, map_q(0, nq), c->stream);
     }
 }
 
@@ -1445,7 +1442,6 @@ Ct op_lt(ckks_ctx *c, const ckks_ct *x, const LtStage &st) {
         gpu::pt_mac(c->T, inner.p + k * gstride, ma, nq, 2 * B, map_q(0, nq), c->stream);
     }
     const size_t nrot = gis.size() - (gis.back() == 0 ? 1 : 0);
-    Ct acc = ct_new(c, x->level, x->scale * st.sd, B);
     if (nrot > 0) {
         std::vector<RotJob> jobs;
         for (size_t k = 0; k < nrot; ++k) {
@@ -1461,11 +1457,41 @@ Ct op_lt(ckks_ctx *c, const ckks_ct *x, const LtStage &st) {
             ProfScope ps(c, "keyswitch", 8.0 * (double)N * nrot * B * nq);
             modup(c, x->level, inner.p + (size_t)nq * N, member, (int)(nrot * B), mu);
         }
-        // the rotated giants summed (with giant 0's inner sum) in the ModDown's last kernel
-        ks_rot_jobs_sum(c, mu, B, jobs, acc->buf.p, gis.size() > nrot ? inner.p + nrot * gstride : nullptr);
-    } else {
-        hipchk(hipMemcpyAsync(acc->buf.p, inner.p, gstride * 8, hipMemcpyDeviceToDevice, c->stream), "copy");
+        // the rotated giants' inner products summed over Q_l and P (A), their
+        // rotated c0 and giant 0's inner sum over Q_l (E); then one ModDown by
+        // P q_l of A + P E: the rotations' ModDowns, their sum and the
+        // rescale in one
+        const int l = x->level, K = c->K, ne = nq + K;
+        const int beta = (nq + c->alpha - 1) / c->alpha;
+        ProfScope ps(c, "keyswitch", 8.0 * (double)N * ((double)nrot * 2.0 * beta * ne + 2.0 * B * l));
+        Pool *Pl = c->pool.get();
+        Buf A(Pl, (size_t)B * 2 * ne * N), E(Pl, (size_t)B * 2 * nq * N);
+        const u64 *g0 = gis.size() > nrot ? inner.p + nrot * gstride : nullptr;
+        for (size_t j0 = 0; j0 < jobs.size(); j0 += gpu::kMaxJobs) {
+            const int nj = (int)std::min<size_t>(gpu::kMaxJobs, jobs.size() - j0);
+            gpu::KsJobs kj{};
+            gpu::FinishJobs fj{};
+            kj.njob = nj;
+            kj.B = B;
+            for (int t = 0; t < nj; ++t) {
+                const RotJob &jb = jobs[j0 + t];
+                kj.ct0[t] = jb.ct0;
+                kj.key[t] = jb.key->k.p;
+                kj.perm[t] = jb.perm;
+                fj.add[t] = jb.add;
+                fj.perm[t] = jb.perm;
+            }
+            gpu::key_inner_jobs_sum(c->T, A.p, mu.ia, kj, j0 > 0, c->stream);
+            gpu::rot_c0_sum(c->T, fj, E.p, g0, j0 > 0, nq, nj, B, map_q(0, nq), c->stream);
+        }
+        trace_op(c, "rescale", l, B);
+        Ct r = ct_new(c, l - 1, (x->scale * st.sd) / (double)c->q[l], B);
+        moddown_rescale(c, l, A.p, E.p, 2 * B, r->buf.p);
+        return r;
     }
+    // giant 0 alone: its inner sum, rescaled
+    Ct acc = ct_new(c, x->level, x->scale * st.sd, B);
+    hipchk(hipMemcpyAsync(acc->buf.p, inner.p, gstride * 8, hipMemcpyDeviceToDevice, c->stream), "copy");
     return op_rescale(c, acc.get());
 }
 

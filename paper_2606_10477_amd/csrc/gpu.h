@@ -222,6 +222,10 @@ struct KsJobs {
     const int32_t *perm[kMaxJobs];
 };
 void key_inner_jobs(const Tables &T, uint64_t *acc, const InnerArgs &a, const KsJobs &j, hipStream_t s);
+// the jobs' inner products summed into one accumulator [B][2][ne][N]
+// (added to its contents when accumulate is set)
+void key_inner_jobs_sum(const Tables &T, uint64_t *acc, const InnerArgs &a, const KsJobs &j, bool accumulate,
+                        hipStream_t s);
 // ModDown finish of rotation jobs: out[t] ([B][2][nlimb][N]) receives
 // (acc - z) * Pinv for job t, plus on poly 0 the word add[t][...][perm[t][j]]
 // (the rotated c0 of the job's input, [B][2][nlimb][N]) when add[t] is set.
@@ -233,13 +237,10 @@ struct FinishJobs {
 void moddown_finish_jobs(const Tables &T, const FinishJobs &f, const uint64_t *acc, size_t acc_poly_stride,
                          const uint64_t *z, const LimbConsts &pinv, int nlimb, int njob, int B, const LimbMap &m,
                          hipStream_t s);
-// The same jobs summed into one ciphertext batch: out = base + sum_t job_t,
-// where base is out itself (accumulate), `extra` (non-null) or zero; f.out is
-// not used.  (Modular sums: the words equal those of adding the jobs' own
-// outputs one by one.)
-void moddown_finish_jobs_sum(const Tables &T, const FinishJobs &f, uint64_t *out, const uint64_t *extra,
-                             bool accumulate, const uint64_t *acc, size_t acc_poly_stride, const uint64_t *z,
-                             const LimbConsts &pinv, int nlimb, int njob, int B, const LimbMap &m, hipStream_t s);
+// the jobs' rotated c0 summed: out ([B][2][nlimb][N]) = base + on poly 0
+// sum_t add[t][...][perm[t][j]], base = out itself (accumulate), extra or zero
+void rot_c0_sum(const Tables &T, const FinishJobs &f, uint64_t *out, const uint64_t *extra, bool accumulate,
+                int nlimb, int njob, int B, const LimbMap &m, hipStream_t s);
 
 // Linear combination of ciphertext objects at (possibly) different levels:
 // out[b][p][l] = sum_t k_t * x_t[b][p][l] over the nlimb lowest limbs (signed

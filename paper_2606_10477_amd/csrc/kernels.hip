@@ -1207,6 +1207,78 @@ void key_inner_jobs(const Tables &T, uint64_t *acc, const InnerArgs &a, const Ks
     hipLaunchKernelGGL(k_key_inner_jobs, grid_for(total), dim3(256), 0, s, acc, a, j, T.logN, total, T);
 }
 
+__global__ void k_key_inner_jobs_sum(u64 *acc, InnerArgs a, KsJobs J, int accumulate, int logN, size_t total,
+                                     Tables T) {
+    const size_t N = (size_t)1 << logN;
+    GRID_LOOP(i, total) {
+        const int e = (int)(i >> logN);
+        const size_t j = i & (N - 1);
+        const int pi = a.m.p[e];
+        const DevPrime P = T.primes[pi];
+        for (int b = 0; b < J.B; ++b) {
+            u64 h0 = 0, l0 = 0, h1 = 0, l1 = 0;   // < 2^127 for up to 128 terms of < 2^120
+            for (int t = 0; t < J.njob; ++t) {
+                const size_t jx = J.perm[t] ? (size_t)J.perm[t][j] : j;
+                const u64 *key = J.key[t];
+                const size_t ct = (size_t)(J.ct0[t] + b);
+                for (int d = 0; d < a.ndig; ++d) {
+                    u64 x;
+                    if (e >= a.lo[d] && e < a.hi[d]) x = a.dsrc[ct * a.dsrc_stride + (size_t)e * N + jx];
+                    else {
+                        int ce = e < a.lo[d] ? e : e - (a.hi[d] - a.lo[d]);
+                        x = a.ext[d][ct * a.ext_stride[d] + (size_t)ce * N + jx];
+                    }
+                    const u64 *k0 = key + (((size_t)d * 2 + 0) * a.np + pi) * N;
+                    const u64 *k1 = key + (((size_t)d * 2 + 1) * a.np + pi) * N;
+                    mac128(h0, l0, x, k0[j]);
+                    mac128(h1, l1, x, k1[j]);
+                }
+            }
+            u64 *o = acc + (size_t)b * 2 * a.ne * N;
+            u64 v0 = reduce128(h0, l0, P), v1 = reduce128(h1, l1, P);
+            if (accumulate) {
+                v0 = add_mod(v0, o[i], P.q);
+                v1 = add_mod(v1, o[(size_t)a.ne * N + i], P.q);
+            }
+            o[i] = v0;
+            o[(size_t)a.ne * N + i] = v1;
+        }
+    }
+}
+void key_inner_jobs_sum(const Tables &T, uint64_t *acc, const InnerArgs &a, const KsJobs &j, bool accumulate,
+                        hipStream_t s) {
+    size_t total = (size_t)a.ne << T.logN;
+    if (!total || j.njob <= 0) return;
+    hipLaunchKernelGGL(k_key_inner_jobs_sum, grid_for(total), dim3(256), 0, s, acc, a, j, (int)accumulate, T.logN,
+                       total, T);
+}
+
+__global__ void k_rot_c0_sum(FinishJobs F, u64 *out, const u64 *extra, int accumulate, int logN, int nlimb, int njob,
+                             size_t total, LimbMap m, Tables T) {
+    const size_t N = (size_t)1 << logN;
+    const size_t member = (size_t)2 * nlimb * N;
+    GRID_LOOP(i, total) {
+        ROW_SPLIT(i, logN, nlimb, r2, limb)   // r2 = 2 b + pp over the output batch
+        const uint32_t b = r2 >> 1, pp = r2 & 1u;
+        const size_t j = i & (N - 1);
+        const u64 q = T.primes[m.p[limb]].q;
+        u64 sum = accumulate ? out[i] : (extra ? extra[i] : 0);
+        if (pp == 0)
+            for (int t = 0; t < njob; ++t) {
+                const size_t jx = F.perm[t] ? (size_t)F.perm[t][j] : j;
+                sum = add_mod(sum, F.add[t][b * member + ((size_t)limb << logN) + jx], q);
+            }
+        out[i] = sum;
+    }
+}
+void rot_c0_sum(const Tables &T, const FinishJobs &f, uint64_t *out, const uint64_t *extra, bool accumulate,
+                int nlimb, int njob, int B, const LimbMap &m, hipStream_t s) {
+    size_t total = ((size_t)nlimb * 2 * B) << T.logN;
+    if (!total) return;
+    hipLaunchKernelGGL(k_rot_c0_sum, grid_for(total), dim3(256), 0, s, f, out, extra, (int)accumulate, T.logN, nlimb,
+                       njob, total, m, T);
+}
+
 __global__ void k_moddown_finish_jobs(FinishJobs F, const u64 *acc, size_t acc_stride, const u64 *z, LimbConsts pinv,
                                       int logN, int nlimb, int B, size_t total, LimbMap m, Tables T) {
     const size_t N = (size_t)1 << logN;
@@ -1271,41 +1343,6 @@ void sub_mul_add_scaled(const Tables &T, uint64_t *out, const uint64_t *c, size_
     if (!total) return;
     hipLaunchKernelGGL(k_sub_mul_add_scaled, grid_for(total), dim3(256), 0, s, out, c, c_stride, z, a, a_stride, inv,
                        inv_sh, w, w_sh, T.logN, nlimb, total, m, T);
-}
-
-// one thread per (member, poly, limb, word): every job's finished word summed
-__global__ void k_moddown_finish_jobs_sum(FinishJobs F, u64 *out, const u64 *extra, int accumulate, const u64 *acc,
-                                          size_t acc_stride, const u64 *z, LimbConsts pinv, int logN, int nlimb,
-                                          int njob, int B, size_t total, LimbMap m, Tables T) {
-    const size_t N = (size_t)1 << logN;
-    const size_t member = (size_t)2 * nlimb * N;
-    GRID_LOOP(i, total) {
-        ROW_SPLIT(i, logN, nlimb, r2, limb)   // r2 = 2 b + pp over the output batch
-        const uint32_t b = r2 >> 1, pp = r2 & 1u;
-        const size_t j = i & (N - 1);
-        const size_t rem = ((size_t)limb << logN) | j;
-        const u64 q = T.primes[m.p[limb]].q;
-        u64 sum = accumulate ? out[i] : (extra ? extra[i] : 0);
-        for (int t = 0; t < njob; ++t) {
-            const size_t poly = (size_t)t * 2 * B + r2;
-            u64 v = mul_shoup(sub_mod(acc[poly * acc_stride + rem], z[poly * nlimb * N + rem], q), pinv.v[limb],
-                              pinv.sh[limb], q);
-            if (pp == 0 && F.add[t]) {
-                const size_t jx = F.perm[t] ? (size_t)F.perm[t][j] : j;
-                v = add_mod(v, F.add[t][b * member + ((size_t)limb << logN) + jx], q);
-            }
-            sum = add_mod(sum, v, q);
-        }
-        out[i] = sum;
-    }
-}
-void moddown_finish_jobs_sum(const Tables &T, const FinishJobs &f, uint64_t *out, const uint64_t *extra,
-                             bool accumulate, const uint64_t *acc, size_t acc_poly_stride, const uint64_t *z,
-                             const LimbConsts &pinv, int nlimb, int njob, int B, const LimbMap &m, hipStream_t s) {
-    size_t total = ((size_t)nlimb * 2 * B) << T.logN;
-    if (!total || njob <= 0) return;
-    hipLaunchKernelGGL(k_moddown_finish_jobs_sum, grid_for(total), dim3(256), 0, s, f, out, extra, (int)accumulate,
-                       acc, acc_poly_stride, z, pinv, T.logN, nlimb, njob, B, total, m, T);
 }
 
 __global__ void k_moddown_finish(u64 *out, const u64 *acc, size_t acc_stride, const u64 *z, const u64 *add,
