@@ -9,7 +9,9 @@ setting's time from its operation trace, and selects, per (level, MRE
 target), the (degree, c, iterations) with minimum predicted time.  Also runs
 Alg. 2 / Alg. 3 on the measured curves (u1 accuracy-first, u2 speed-first per
 level).  Writes a JSON report (tables, predicted versus measured times, the
-speedup over the fixed configuration (31, 3)).
+speedup over the fixed configuration (31, 3), and the exploration cost of
+timing every setting against predicting it from unit costs, with the
+prediction's regret per pick).
 
     python -m paper_2606_10477_amd.tune --out tuning.json
 """
@@ -22,10 +24,13 @@ import time
 import numpy as np
 
 P16B = dict(log_n=16, max_level=7, num_special=7, digit_size=8, hamming_weight=192, bts=(3, 10, 3, 52))
+# the plain set: no bootstrapping, 27 computation levels of 40 bits
+P16 = dict(log_n=16, max_level=27, num_special=7, digit_size=10, hamming_weight=192)
 EVALMOD = (25.0, 4, 31)
 
 
-def run(levels, degrees, iters, targets, lo, hi, batch, reps, fixed, tuner_seed=777, quiet=False, domain="logu"):
+def run(levels, degrees, iters, targets, lo, hi, batch, reps, fixed, tuner_seed=777, quiet=False, domain="logu",
+        params="bts"):
     import math
 
     import torch
@@ -33,22 +38,33 @@ def run(levels, degrees, iters, targets, lo, hi, batch, reps, fixed, tuner_seed=
 
     torch.cuda.set_device(0)
     t_start = time.perf_counter()
-    ctx = ckks.Context(**P16B)
-    ctx.bts_setup(*EVALMOD)
-    ctx.keygen(tuner_seed, ctx.bts_galois())      # the tuner's own keys, not a client's
+    bts = params == "bts"
+    ctx = ckks.Context(**(P16B if bts else P16))
+    if bts:
+        ctx.bts_setup(*EVALMOD)
+    ctx.keygen(tuner_seed, ctx.bts_galois() if bts else [])      # the tuner's own keys, not a client's
     if domain == "paper":
         # the paper's own workload (§5.1): linspace over [0.001, 100], pre-normalised by B = 100
         x = np.linspace(0.001, 100.0, ctx.n) / 100.0
     else:
         x = inputs.log_uniform(ctx.n, lo, hi, 11)
     cts = {l: ctx.encrypt(x, l, 2.0 ** 50, 12 + l) for l in levels}
-    # Alg. 3's cases with l_BTS = 0, l_afterBTS = l_max = the chain's top computation level
-    cases = tuner.level_cases(0, ctx.l_after, ctx.l_after)
-    cs = {l: cases.get(l, [0]) or [0] for l in levels}
-    bound = 16 * int(math.ceil(1.0 / math.sqrt(lo)))
-    costs = tuner.profile_unit_costs(ctx, list(range(0, ctx.l_after + 1)), batch=batch, reps=reps, bts_bound=bound)
+    if bts:
+        # Alg. 3's cases with l_BTS = 0, l_afterBTS = l_max = the chain's top computation level
+        cases = tuner.level_cases(0, ctx.l_after, ctx.l_after)
+        cs = {l: cases.get(l, [0]) or [0] for l in levels}
+        bound = 16 * int(math.ceil(1.0 / math.sqrt(lo)))
+        prof_levels = list(range(0, ctx.l_after + 1))
+    else:
+        cs = {l: [0] for l in levels}      # no bootstrapping: x is never bootstrapped
+        bound = None
+        prof_levels = list(range(0, max(levels) + 1))
+    t_prof = time.perf_counter()
+    costs = tuner.profile_unit_costs(ctx, prof_levels, batch=batch, reps=reps, bts_bound=bound)
+    t_prof = time.perf_counter() - t_prof
     if not quiet:
-        print(f"profiled {len(costs)} unit costs (bootstrap {costs[('bootstrap', tuner.BTS_ANY_LEVEL)] * 1e3:.1f} ms)",
+        bt = costs.get(("bootstrap", tuner.BTS_ANY_LEVEL))
+        print(f"profiled {len(costs)} unit costs" + (f" (bootstrap {bt * 1e3:.1f} ms)" if bt else ""),
               file=sys.stderr, flush=True)
     rows = tuner.sweep(ctx, x, cts, degrees, iters, lo, hi, batch=batch, reps=reps, costs=costs, cs_by_level=cs)
     table = {}
@@ -72,8 +88,9 @@ def run(levels, degrees, iters, targets, lo, hi, batch, reps, fixed, tuner_seed=
     ok = [r for r in rows if r.get("ok")]
     err = [abs(r["t_pred"] - r["t"]) / r["t"] for r in ok]
     report = {
-        "params": "N=2^16, log2 QP 1556: q0 60-bit, 10 x 40-bit, 13 x 52-bit, 7 x 60-bit special, dnum 3, h 192; "
-                  "l_BTS 0, l_afterBTS = l_max 7",
+        "params": ("N=2^16, log2 QP 1556: q0 60-bit, 10 x 40-bit, 13 x 52-bit, 7 x 60-bit special, dnum 3, h 192; "
+                   "l_BTS 0, l_afterBTS = l_max 7") if bts else
+                  "N=2^16, q0 60-bit + 27 x 40-bit, 7 x 60-bit special, dnum 3, h 192; no bootstrapping",
         "input": (f"x = linspace(0.001, 100, N/2) / 100 (B = 100), interval [{lo}, {hi}], encrypted at scale 2^50"
                   if domain == "paper" else f"x log-uniform in [{lo}, {hi}], encrypted at scale 2^50"),
         "fixed": list(fixed),
@@ -83,6 +100,7 @@ def run(levels, degrees, iters, targets, lo, hi, batch, reps, fixed, tuner_seed=
                           "per_degree": D[l]} for l in sorted(R)},
         "prediction_rel_error": {"median": float(np.median(err)), "max": float(np.max(err))} if err else None,
         "unit_costs": {f"{op}@{l}": v for (op, l), v in sorted(costs.items(), key=lambda kv: (kv[0][1], kv[0][0]))},
+        "exploration": tuner.exploration_report(rows, levels, targets, t_prof),
         "rows": rows, "tuning_wall_s": time.perf_counter() - t_start,
     }
     ctx.close()
@@ -101,18 +119,22 @@ def main(argv=None):
     ap.add_argument("--domain", choices=["logu", "paper"], default="logu",
                     help="logu: x log-uniform in [2^-10, 1]; paper: linspace(0.001, 100) / 100 on [1e-5, 1]")
     ap.add_argument("--fixed", default="31,3", help="fixed (degree, iterations) the tuned choice is compared with")
+    ap.add_argument("--params", choices=["bts", "plain"], default="bts",
+                    help="bts: the bootstrapping set (levels 3-7); plain: 27 levels, no bootstrapping "
+                         "(use e.g. --levels 13,17,21,27)")
     args = ap.parse_args(argv)
     ints = lambda s: [int(v) for v in s.split(",")]
     lo, hi = (1e-5, 1.0) if args.domain == "paper" else (2.0 ** -10, 1.0)
     rep = run(ints(args.levels), ints(args.degrees), ints(args.iters),
               [float(v) for v in args.targets.split(",")], lo, hi, args.batch, args.reps, tuple(ints(args.fixed)),
-              domain=args.domain)
+              domain=args.domain, params=args.params)
     os.makedirs(os.path.dirname(os.path.abspath(args.out)), exist_ok=True)
     with open(args.out, "w") as f:
         json.dump(rep, f, indent=1)
     summary = {"table": rep["table"], "speedup_vs_fixed": rep["speedup_vs_fixed"],
                "alg3": {l: {k: v for k, v in e.items() if k != "per_degree"} for l, e in rep["alg3"].items()},
-               "prediction_rel_error": rep["prediction_rel_error"], "tuning_wall_s": rep["tuning_wall_s"]}
+               "prediction_rel_error": rep["prediction_rel_error"], "tuning_wall_s": rep["tuning_wall_s"],
+               "exploration": {k: v for k, v in rep["exploration"].items() if k != "picks"}}
     print(json.dumps(summary), flush=True)
 
 

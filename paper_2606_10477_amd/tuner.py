@@ -235,7 +235,11 @@ def _measure(ctx, ct, lvl, c, d, it, lo, hi, batch, reps, costs, ref):
     row = {"level": lvl, "d": d, "i": it, "c": c}
     try:
         ctx.trace(True)
+        ctx.sync()
+        t0 = time.perf_counter()
         y = run()
+        ctx.sync()
+        row["t_first_s"] = time.perf_counter() - t0   # the traced run that also yields the MRE
         tr = ctx.trace_read()
         ctx.trace(False)
     except CkksError:
@@ -253,6 +257,7 @@ def _measure(ctx, ct, lvl, c, d, it, lo, hi, batch, reps, costs, ref):
         ctx.sync()
         ts.append(time.perf_counter() - t0)
     row["t"] = float(np.median(ts)) / batch
+    row["t_timed_s"] = float(np.sum(ts))
     row["ops"] = len(tr)
     row["bts"] = sum(1 for op in tr if op[0] == "bootstrap")
     if costs is not None:
@@ -268,6 +273,36 @@ def select(rows, target, level, key="t_pred"):
     if not ok:
         return None
     return min(ok, key=lambda r: (r[key], r["m"], r.get("bts", 0), r["d"]))
+
+
+def exploration_report(rows, levels, targets, profile_s):
+    """Measured-time exhaustive exploration (every setting timed, as the
+    paper's Alg. 3 does) against the cost model (every setting run once for
+    its MRE and operation trace; times predicted from the profiled unit
+    costs).  Per (level, target): the measured-time pick, the cost-model pick
+    and the cost-model pick's regret (its measured time over the measured
+    optimum, minus 1); and the GPU seconds each route spends."""
+    ok = [r for r in rows if r.get("ok")]
+    picks = {}
+    regrets = []
+    for lvl in levels:
+        for tgt in targets:
+            rm = select(rows, tgt, lvl, key="t")
+            rp = select(rows, tgt, lvl, key="t_pred")
+            if rm is None or rp is None:
+                picks.setdefault(str(lvl), {})[f"{tgt:.3g}"] = None
+                continue
+            reg = rp["t"] / rm["t"] - 1.0
+            regrets.append(reg)
+            picks.setdefault(str(lvl), {})[f"{tgt:.3g}"] = {
+                "measured": [rm["d"], rm["c"], rm["i"]], "predicted": [rp["d"], rp["c"], rp["i"]],
+                "same": (rm["d"], rm["c"], rm["i"]) == (rp["d"], rp["c"], rp["i"]), "regret": reg}
+    first = float(sum(r.get("t_first_s", 0.0) for r in rows))
+    timed = float(sum(r.get("t_timed_s", 0.0) for r in ok))
+    return {"settings": len(rows), "feasible": len(ok), "picks": picks,
+            "max_regret": max(regrets) if regrets else None,
+            "measured_exhaustive_s": first + timed, "cost_model_s": first + profile_s,
+            "runs_for_mre_s": first, "timing_runs_s": timed, "unit_cost_profile_s": profile_s}
 
 
 def alg3_from_rows(rows, delta=1.0, theta=1.0, key="t"):

@@ -114,6 +114,26 @@ def test_alg3_from_measured_rows():
     assert R[5] == ((7, 0, 3), (7, 0, 3))
 
 
+def test_exploration_report_regret_and_cost():
+    """Measured-time picks against cost-model picks: where the prediction
+    ranks two settings the wrong way round, the regret is the measured time
+    of its pick over the measured optimum; the cost model's GPU seconds leave
+    out the timing runs."""
+    rows = [dict(level=7, d=31, i=3, c=0, ok=True, m=1e-8, t=2.0, t_pred=2.2, t_first_s=2.5, t_timed_s=6.0),
+            dict(level=7, d=15, i=4, c=0, ok=True, m=2e-8, t=2.1, t_pred=2.0, t_first_s=2.6, t_timed_s=6.3),
+            dict(level=7, d=7, i=6, c=0, ok=True, m=2e-6, t=3.0, t_pred=3.0, t_first_s=3.5, t_timed_s=9.0),
+            dict(level=7, d=63, i=1, c=0, ok=False, t_first_s=0.1)]
+    rep = tuner.exploration_report(rows, [7], [1e-5, 3.1e-8, 1e-9], profile_s=4.0)
+    p = rep["picks"]["7"]
+    assert p["3.1e-08"]["measured"] == [31, 0, 3] and p["3.1e-08"]["predicted"] == [15, 0, 4]
+    assert not p["3.1e-08"]["same"] and p["3.1e-08"]["regret"] == pytest.approx(0.05)
+    assert p["1e-09"] is None
+    assert rep["max_regret"] == pytest.approx(0.05)
+    assert rep["measured_exhaustive_s"] == pytest.approx(8.7 + 21.3)
+    assert rep["cost_model_s"] == pytest.approx(8.7 + 4.0)
+    assert (rep["settings"], rep["feasible"]) == (4, 3)
+
+
 def test_moment_reference_matches_scipy():
     """The FP64 reference of the moment statistics (population skewness,
     excess kurtosis, Pearson correlation) against scipy's definitions."""
