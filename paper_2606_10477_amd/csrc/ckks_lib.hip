@@ -201,6 +201,7 @@ struct ConvTable {
     Buf hinv, hinv_sh, mat;
     LimbMap pin, pout;
     int din, dout;
+    int split;   // every prime of the conversion below 2^60
 };
 
 struct BtsPlan;
@@ -488,7 +489,7 @@ ConvTable *make_conv(ckks_ctx *c, const std::vector<int> &in, const std::vector<
         const u64 qi = c->q[in[a]];
         hinv[a] = hm::invmod(prod_mod(c, in, in[a], qi), qi);
         hinvsh[a] = shoup(hinv[a], qi);
-        for (int r = 0; r < t->dout; ++r) mat[(size_t)a * t->dout + r] = prod_mod(c, in, in[a], c->q[out[r]]);
+        for (int r = 0; r < t->dout; ++r) mat[(size_t)r * t->din + a] = prod_mod(c, in, in[a], c->q[out[r]]);
     }
     Pool *P = c->pool.get();
     t->hinv = Buf(P, t->din);
@@ -499,6 +500,9 @@ ConvTable *make_conv(ckks_ctx *c, const std::vector<int> &in, const std::vector<
     upload(t->mat, mat.data(), mat.size() * 8, c->stream);
     t->pin = map_list(in);
     t->pout = map_list(out);
+    t->split = 1;
+    for (int i : in) t->split &= c->q[i] < (1ull << 60);
+    for (int i : out) t->split &= c->q[i] < (1ull << 60);
     return t.release();
 }
 
@@ -710,7 +714,7 @@ void modup(ckks_ctx *c, int l, const u64 *d, size_t d_stride, int nct, ModUp &mu
     for (int j = 0; j < beta; ++j) {
         ConvTable *t = modup_table(c, l, j);
         mu.ext.emplace_back(P, (size_t)nct * t->dout * N);
-        gpu::BconvArgs ba{t->pin, t->pout, t->din, t->dout, t->hinv.p, t->hinv_sh.p, t->mat.p};
+        gpu::BconvArgs ba{t->pin, t->pout, t->din, t->dout, t->hinv.p, t->hinv_sh.p, t->mat.p, t->split};
         const int lo = j * c->alpha;
         gpu::bconv(c->T, mu.ext.back().p, dc.p + (size_t)lo * N, ba, nct, (size_t)nq * N, (size_t)t->dout * N,
                    c->stream);
@@ -747,7 +751,7 @@ void ks_finish(ckks_ctx *c, const ModUp &mu, const SwitchKey &key, const int32_t
     Buf y(P, (size_t)np2 * c->K * N);
     ntt_oop_p(c, y.p, acc.p + (size_t)nq * N, (size_t)ne * N, c->K, np2, md->pin, true);
     Buf z(P, (size_t)np2 * nq * N);
-    gpu::BconvArgs bd{md->pin, md->pout, md->din, md->dout, md->hinv.p, md->hinv_sh.p, md->mat.p};
+    gpu::BconvArgs bd{md->pin, md->pout, md->din, md->dout, md->hinv.p, md->hinv_sh.p, md->mat.p, md->split};
     gpu::bconv(c->T, z.p, y.p, bd, np2, (size_t)c->K * N, (size_t)nq * N, c->stream);
     if (c->logN == 16) {
         // (acc - z) P^-1 (+ add) fused into the transform's last pass
@@ -841,7 +845,7 @@ void moddown_rescale(ckks_ctx *c, int l, u64 *acc, const u64 *d, int np2, u64 *o
     Buf y(P, (size_t)np2 * (K + 1) * N);
     ntt_oop_p(c, y.p, acc + (size_t)l * N, (size_t)ne * N, K + 1, np2, md->pin, true);
     Buf z(P, (size_t)np2 * l * N);
-    gpu::BconvArgs bd{md->pin, md->pout, md->din, md->dout, md->hinv.p, md->hinv_sh.p, md->mat.p};
+    gpu::BconvArgs bd{md->pin, md->pout, md->din, md->dout, md->hinv.p, md->hinv_sh.p, md->mat.p, md->split};
     gpu::bconv(c->T, z.p, y.p, bd, np2, (size_t)(K + 1) * N, (size_t)l * N, c->stream);
     const size_t L1 = (size_t)c->L + 1;
     const u64 *inv = c->d_pqinv.p + (size_t)l * L1, *inv_sh = c->d_pqinvsh.p + (size_t)l * L1;
@@ -964,7 +968,7 @@ void ks_rot_jobs(ckks_ctx *c, const ModUp &mu, int B, const std::vector<RotJob> 
         Buf y(P, (size_t)np2 * c->K * N);
         ntt_oop_p(c, y.p, acc.p + (size_t)nq * N, (size_t)ne * N, c->K, np2, md->pin, true);
         Buf z(P, (size_t)np2 * nq * N);
-        gpu::BconvArgs bd{md->pin, md->pout, md->din, md->dout, md->hinv.p, md->hinv_sh.p, md->mat.p};
+        gpu::BconvArgs bd{md->pin, md->pout, md->din, md->dout, md->hinv.p, md->hinv_sh.p, md->mat.p, md->split};
         gpu::bconv(c->T, z.p, y.p, bd, np2, (size_t)c->K * N, (size_t)nq * N, c->stream);
         ntt_p(c, z.p, nq, np2, map_q(0, nq), false);
         gpu::moddown_finish_jobs(c->T, fj, acc.p, (size_t)ne * N, z.p, pinv, nq, nj, B, map_q(0, nq), c->stream);

@@ -148,7 +148,8 @@ struct BconvArgs {
     LimbMap pin, pout;
     int din, dout;
     const uint64_t *hinv, *hinv_sh;   // device [din]
-    const uint64_t *mat;              // device [din][dout]
+    const uint64_t *mat;              // device [dout][din]: output-major, one output's row contiguous
+    int split;                        // every input and output prime below 2^60 (30-bit split products)
 };
 void bconv(const Tables &T, uint64_t *out, const uint64_t *in, const BconvArgs &a, int npoly,
            size_t in_poly_stride, size_t out_poly_stride, hipStream_t s);

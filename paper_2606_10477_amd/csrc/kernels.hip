@@ -1062,11 +1062,30 @@ void sub_mul(const Tables &T, uint64_t *out, const uint64_t *c, const uint64_t *
 // One thread per coefficient j of a polynomial: the DIN input residues are
 // scaled by [Dhat_i^-1]_{q_i} (kept in registers: DIN is a template
 // parameter, so the arrays are fully unrolled), then each output limb is one
-// 128-bit multiply-accumulate over them, reduced once.
+// multiply-accumulate over them, reduced once.
 // blockIdx.z splits the output limbs into chunks of `per` (each chunk scales
 // the inputs again): more and shorter waves when a call covers few polys.
-template <int DIN>
-__global__ void __launch_bounds__(256) k_bconv(u64 *out, const u64 *in, BconvArgs a, int logN, size_t in_stride,
+//
+// SPLIT (every prime of the conversion below 2^60): residues and matrix
+// entries are cut at bit 30, y = y1 2^30 + y0 and m = m1 2^30 + m0, and the
+// four partial sums  sum y0 m0, sum y0 m1, sum y1 m0, sum y1 m1  are kept in
+// separate 64-bit accumulators; each term is below 2^60, so up to 16 inputs
+// add up without a carry, and each term is one 32 x 32 + 64-bit multiply-add.
+// The sums are joined into the same 128-bit value sum y m as the plain
+// 128-bit accumulation, so the reduced output is identical.
+DEV void join30(u64 &hi, u64 &lo, u64 l, u64 a, u64 b, u64 h) {
+    const u64 m = a + b, mc = m < a;   // a + b = mc 2^64 + m
+    lo = l + (m << 30);
+    hi = (m >> 34) + (mc << 30) + (lo < l);
+    const u64 t = h << 60;
+    lo += t;
+    hi += (h >> 4) + (lo < t);
+}
+DEV u64 mad32(uint32_t a, uint32_t b, u64 c) { return (u64)a * b + c; }
+
+template <int DIN, bool SPLIT>
+__global__ void __launch_bounds__(256) k_bconv(u64 *__restrict__ out, const u64 *__restrict__ in,
+                                               const u64 *__restrict__ mat, BconvArgs a, int logN, size_t in_stride,
                                                size_t out_stride, int per, Tables T) {
     const size_t N = (size_t)1 << logN;
     const int poly = blockIdx.y;
@@ -1083,14 +1102,63 @@ __global__ void __launch_bounds__(256) k_bconv(u64 *out, const u64 *in, BconvArg
     }
     u64 *dst = out + poly * out_stride;
     int r = r0;
+    if (SPLIT) {
+        constexpr u64 kLow30 = (1ull << 30) - 1;
+        uint32_t y0[DIN], y1[DIN];
+#pragma unroll
+        for (int i = 0; i < DIN; ++i) {
+            y0[i] = (uint32_t)(y[i] & kLow30);
+            y1[i] = (uint32_t)(y[i] >> 30);
+        }
+        for (; r + 1 < r1; r += 2) {
+            const DevPrime P0 = T.primes[a.pout.p[r]], P1 = T.primes[a.pout.p[r + 1]];
+            u64 l0 = 0, a0 = 0, b0 = 0, h0 = 0, l1 = 0, a1 = 0, b1 = 0, h1 = 0;
+#pragma unroll
+            for (int i = 0; i < DIN; ++i) {
+                const u64 m = mat[(size_t)r * DIN + i], n = mat[(size_t)(r + 1) * DIN + i];
+                const uint32_t m0 = (uint32_t)(m & kLow30), m1 = (uint32_t)(m >> 30);
+                const uint32_t n0 = (uint32_t)(n & kLow30), n1 = (uint32_t)(n >> 30);
+                l0 = mad32(y0[i], m0, l0);
+                a0 = mad32(y0[i], m1, a0);
+                b0 = mad32(y1[i], m0, b0);
+                h0 = mad32(y1[i], m1, h0);
+                l1 = mad32(y0[i], n0, l1);
+                a1 = mad32(y0[i], n1, a1);
+                b1 = mad32(y1[i], n0, b1);
+                h1 = mad32(y1[i], n1, h1);
+            }
+            u64 hi0, lo0, hi1, lo1;
+            join30(hi0, lo0, l0, a0, b0, h0);
+            join30(hi1, lo1, l1, a1, b1, h1);
+            dst[(size_t)r * N + j] = reduce128(hi0, lo0, P0);
+            dst[(size_t)(r + 1) * N + j] = reduce128(hi1, lo1, P1);
+        }
+        if (r < r1) {
+            const DevPrime P = T.primes[a.pout.p[r]];
+            u64 l0 = 0, a0 = 0, b0 = 0, h0 = 0;
+#pragma unroll
+            for (int i = 0; i < DIN; ++i) {
+                const u64 m = mat[(size_t)r * DIN + i];
+                const uint32_t m0 = (uint32_t)(m & kLow30), m1 = (uint32_t)(m >> 30);
+                l0 = mad32(y0[i], m0, l0);
+                a0 = mad32(y0[i], m1, a0);
+                b0 = mad32(y1[i], m0, b0);
+                h0 = mad32(y1[i], m1, h0);
+            }
+            u64 hi, lo;
+            join30(hi, lo, l0, a0, b0, h0);
+            dst[(size_t)r * N + j] = reduce128(hi, lo, P);
+        }
+        return;
+    }
     // two output limbs at a time: two independent 128-bit accumulation chains
     for (; r + 1 < r1; r += 2) {
         const DevPrime P0 = T.primes[a.pout.p[r]], P1 = T.primes[a.pout.p[r + 1]];
         u64 h0 = 0, l0 = 0, h1 = 0, l1 = 0;
 #pragma unroll
         for (int i = 0; i < DIN; ++i) {
-            mac128(h0, l0, y[i], a.mat[(size_t)i * a.dout + r]);
-            mac128(h1, l1, y[i], a.mat[(size_t)i * a.dout + r + 1]);
+            mac128(h0, l0, y[i], mat[(size_t)r * DIN + i]);
+            mac128(h1, l1, y[i], mat[(size_t)(r + 1) * DIN + i]);
         }
         dst[(size_t)r * N + j] = reduce128(h0, l0, P0);
         dst[(size_t)(r + 1) * N + j] = reduce128(h1, l1, P1);
@@ -1099,7 +1167,7 @@ __global__ void __launch_bounds__(256) k_bconv(u64 *out, const u64 *in, BconvArg
         const DevPrime P = T.primes[a.pout.p[r]];
         u64 hi = 0, lo = 0;
 #pragma unroll
-        for (int i = 0; i < DIN; ++i) mac128(hi, lo, y[i], a.mat[(size_t)i * a.dout + r]);
+        for (int i = 0; i < DIN; ++i) mac128(hi, lo, y[i], mat[(size_t)r * DIN + i]);
         dst[(size_t)r * N + j] = reduce128(hi, lo, P);
     }
 }
@@ -1116,8 +1184,12 @@ static void bconv_launch(const Tables &T, uint64_t *out, const uint64_t *in, con
     const int per = (a.dout + nchunk - 1) / nchunk;
     nchunk = (a.dout + per - 1) / per;
     dim3 grid((unsigned)bx, npoly, nchunk);
-    hipLaunchKernelGGL(k_bconv<DIN>, grid, dim3(256), 0, s, out, in, a, T.logN, in_poly_stride, out_poly_stride, per,
-                       T);
+    if (a.split)
+        hipLaunchKernelGGL((k_bconv<DIN, true>), grid, dim3(256), 0, s, out, in, a.mat, a, T.logN, in_poly_stride,
+                           out_poly_stride, per, T);
+    else
+        hipLaunchKernelGGL((k_bconv<DIN, false>), grid, dim3(256), 0, s, out, in, a.mat, a, T.logN, in_poly_stride,
+                           out_poly_stride, per, T);
 }
 void bconv(const Tables &T, uint64_t *out, const uint64_t *in, const BconvArgs &a, int npoly, size_t in_poly_stride,
            size_t out_poly_stride, hipStream_t s) {
