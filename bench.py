@@ -40,6 +40,9 @@ def parse():
     ap.add_argument("--level", type=int, default=7, help="input level")
     ap.add_argument("--extra-batch", type=int, default=16, help="also time this many ciphertexts per step (0: skip)")
     ap.add_argument("--latency-runs", type=int, default=20, help="single-ciphertext runs timed one by one (p50/p99)")
+    ap.add_argument("--graph-runs", type=int, default=10,
+                    help="replays of the one-ciphertext chain captured as a HIP graph, against as many eager runs "
+                         "(0: skip)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-limit", type=int, default=360,
                     help="seconds after the start the CPU baseline may run until")
@@ -156,6 +159,30 @@ def main():
     if lat:
         latency = {"runs": len(lat), "p50_ms": round(float(np.percentile(lat, 50)), 3),
                    "p99_ms": round(float(np.percentile(lat, 99)), 3)}
+    # the one-ciphertext chain captured as a HIP graph: replay time against
+    # eager runs of the same chain, and the replay's words against eager's
+    graph = None
+    if args.graph_runs > 0:
+        ref_words = step(1)[0].words()
+        gr = ctx.invsqrt_graph(cts[0], args.degree, args.iters, a=LO, b=HI)
+        same = bool(np.array_equal(gr.run(cts[0]).words(), ref_words))
+        ctx.sync()
+        t1 = time.perf_counter()
+        for _ in range(args.graph_runs):
+            o1 = step(1)
+            del o1
+        ctx.sync()
+        te = (time.perf_counter() - t1) / args.graph_runs
+        t1 = time.perf_counter()
+        for _ in range(args.graph_runs):
+            o1 = gr.run(cts[0])
+            del o1
+        ctx.sync()
+        tg = (time.perf_counter() - t1) / args.graph_runs
+        same = same and bool(np.array_equal(gr.run(cts[0]).words(), ref_words))
+        gr.close()
+        graph = {"runs": args.graph_runs, "eager_ms": round(te * 1e3, 3), "replay_ms": round(tg * 1e3, 3),
+                 "replay_equals_eager": same}
     batched = None
     if args.extra_batch > 1:
         out2 = step(args.extra_batch)
@@ -212,6 +239,7 @@ def main():
         "mre": mre,
         "latency": latency,
         "batched": batched,
+        "graph": graph,
         "roofline": roof,
         "kernel_families": others,
     }

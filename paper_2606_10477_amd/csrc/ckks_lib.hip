@@ -644,6 +644,25 @@ Ct op_add_const(ckks_ctx *c, const ckks_ct *a, double value) {
     return r;
 }
 
+// k a + value at a's scale in one pass: the words of op_mul_int(a, k, scale(a))
+// followed by op_add_const(value)
+Ct op_mul_int_add_const(ckks_ctx *c, const ckks_ct *a, int64_t k, double value) {
+    const double kd = std::rint(value * a->scale);
+    if (!(std::fabs(kd) < 4.0e18)) fail(CKKS_E_RANGE, "constant out of range");
+    trace_op(c, "mul_scalar", a->level, a->B);
+    Ct r = ct_new(c, a->level, a->scale, a->B);
+    LimbConsts kc{};
+    gpu::LimbWords cc{};
+    for (int i = 0; i <= a->level; ++i) {
+        kc.v[i] = mod_signed(k, c->q[i]);
+        kc.sh[i] = shoup(kc.v[i], c->q[i]);
+        cc.v[i] = mod_signed((int64_t)kd, c->q[i]);
+    }
+    gpu::mul_add_scalar(c->T, r->buf.p, a->buf.p, kc, cc, a->level + 1, 2 * a->B, map_q(0, a->level + 1),
+                        c->stream);
+    return r;
+}
+
 Ct op_drop(ckks_ctx *c, const ckks_ct *a, int level) {
     if (level < 0 || level > a->level) fail(CKKS_E_LEVEL, "bad target level");
     trace_op(c, "drop", level, a->B);
@@ -1169,9 +1188,20 @@ struct PowerBasis {
     }
     // T_i from its product: 2 p - 1 (even i) or 2 p - T_1 (odd i)
     Ct finish(int i, Ct p) {
-        Ct two = op_mul_int(c, p.get(), 2, p->scale);
-        if (i % 2 == 0) return op_add_const(c, two.get(), -1.0);
-        return addsub_aligned(c, two.get(), T[1].get(), true);
+        if (i % 2 == 0) return op_mul_int_add_const(c, p.get(), 2, -1.0);
+        // 2 p - T_1 as one linear combination, T_1 first brought to p's level
+        // (and scale) when it sits higher
+        Ct t1;
+        const ckks_ct *u = T[1].get();
+        if (u->level < p->level) {
+            Ct two = op_mul_int(c, p.get(), 2, p->scale);
+            return addsub_aligned(c, two.get(), u, true);
+        }
+        if (u->level > p->level) {
+            t1 = op_level_to(c, u, p->level);
+            u = t1.get();
+        }
+        return op_lincomb(c, {p.get(), u}, {2.0, -1.0}, {1.0, 1.0}, p->level);
     }
     // every T_i of `want` (and what they need), wave by wave: the products of
     // one wave whose operands are ready share launch sequences
@@ -1518,8 +1548,7 @@ Ct op_eval_mod(ckks_ctx *c, const ckks_ct *u) {
     Ct y = op_cheb(c, u, c->bts->cf, -1.0, 1.0);
     for (int k = 0; k < c->bts->r; ++k) {
         Ct sq = mult_rs(c, y.get(), y.get());
-        Ct two = op_mul_int(c, sq.get(), 2, sq->scale);
-        y = op_add_const(c, two.get(), -1.0);
+        y = op_mul_int_add_const(c, sq.get(), 2, -1.0);   // cos 2t = 2 cos^2 t - 1
     }
     return y;
 }

@@ -85,11 +85,17 @@ struct LimbConsts {
     uint64_t v[kMaxLimbs];
     uint64_t sh[kMaxLimbs];
 };
+struct LimbWords {
+    uint64_t v[kMaxLimbs];
+};
 void mul_scalar(const Tables &T, uint64_t *out, const uint64_t *a, const LimbConsts &c, int nlimb,
                 int npoly, const LimbMap &m, hipStream_t s);
 // out[l] = a[l] + c[l] on even-indexed polys (poly 0 of each ciphertext); odd polys copied
 void add_scalar(const Tables &T, uint64_t *out, const uint64_t *a, const LimbConsts &c, int nlimb,
                 int npoly, const LimbMap &m, hipStream_t s);
+// out[l] = k[l] a[l], plus c[l] on even-indexed polys: mul_scalar and add_scalar in one pass
+void mul_add_scalar(const Tables &T, uint64_t *out, const uint64_t *a, const LimbConsts &k, const LimbWords &c,
+                    int nlimb, int npoly, const LimbMap &m, hipStream_t s);
 // out[l][j] = a[l][perm[j]]
 void permute(const Tables &T, uint64_t *out, const uint64_t *a, const int32_t *perm, int nlimb, int npoly,
              hipStream_t s);

@@ -857,6 +857,24 @@ void mul_scalar(const Tables &T, uint64_t *out, const uint64_t *a, const LimbCon
     hipLaunchKernelGGL(k_mul_scalar, grid_for(total), dim3(256), 0, s, out, a, c, T.logN, nlimb, total, m, T);
 }
 
+// k a, plus the constant c on poly 0 of every member: an integer multiply and
+// a constant addition in one pass
+__global__ void k_mul_add_scalar(u64 *out, const u64 *a, LimbConsts k, LimbWords c, int logN, int nlimb,
+                                 size_t total, LimbMap m, Tables T) {
+    GRID_LOOP(i, total) {
+        ROW_SPLIT(i, logN, nlimb, poly, limb)
+        const u64 q = T.primes[m.p[limb]].q;
+        const u64 r = mul_shoup(a[i], k.v[limb], k.sh[limb], q);
+        out[i] = (poly & 1) ? r : add_mod(r, c.v[limb], q);
+    }
+}
+void mul_add_scalar(const Tables &T, uint64_t *out, const uint64_t *a, const LimbConsts &k, const LimbWords &c,
+                    int nlimb, int npoly, const LimbMap &m, hipStream_t s) {
+    size_t total = ((size_t)nlimb * npoly) << T.logN;
+    if (!total) return;
+    hipLaunchKernelGGL(k_mul_add_scalar, grid_for(total), dim3(256), 0, s, out, a, k, c, T.logN, nlimb, total, m, T);
+}
+
 __global__ void k_add_scalar(u64 *out, const u64 *a, LimbConsts c, int logN, int nlimb, size_t total, LimbMap m,
                              Tables T) {
     GRID_LOOP(i, total) {
