@@ -1259,6 +1259,63 @@ Ct baby_sum(ckks_ctx *c, PowerBasis &pb, const std::vector<double> &cf) {
     return op_add_const(c, r.get(), cf[0]);
 }
 
+// The baby-step sums of several leaves at once, when they combine the same
+// basis elements (every leaf of one evaluation does, unless a coefficient is
+// exactly 0): one pass reads each T_i once for every leaf, the leaves' sums
+// are rescaled as one batch, then each gets its constant term.  Every word
+// equals baby_sum's for the leaf alone.  Returns false where it does not apply.
+bool baby_sums_together(ckks_ctx *c, PowerBasis &pb, const std::vector<std::vector<double>> &cfs,
+                        std::vector<Ct> &out) {
+    const size_t n = cfs.size();
+    if (n < 2 || n > (size_t)gpu::kMaxSum || c->logN < 8) return false;
+    std::vector<int> terms;
+    for (size_t t = 0; t < n; ++t) {
+        std::vector<int> tt;
+        for (int i = 1; i < (int)cfs[t].size(); ++i)
+            if (cfs[t][i] != 0.0) tt.push_back(i);
+        if (tt.empty() || (t > 0 && tt != terms)) return false;
+        terms = tt;
+    }
+    if (terms.size() > (size_t)gpu::kMaxComb) return false;
+    int lmin = 1 << 30;
+    for (int i : terms) lmin = std::min(lmin, pb.T[i]->level);
+    if (lmin < 1) fail(CKKS_E_LEVEL, "no level for the baby-step sum");
+    const int B = pb.T[terms[0]]->B;
+    const size_t N = c->N;
+    const double scale = pb.T[terms[0]]->scale * ((c->ladder[lmin - 1] * (double)c->q[lmin]) / pb.T[terms[0]]->scale);
+    gpu::CombMultiArgs ma{};
+    ma.nsum = (int)n;
+    ma.out_stride = c->words(lmin) * (size_t)B;
+    for (size_t u = 0; u < terms.size(); ++u) {
+        const ckks_ct *Ti = pb.T[terms[u]].get();
+        if (Ti->B != B) return false;
+        const double sc = (c->ladder[lmin - 1] * (double)c->q[lmin]) / Ti->scale;
+        if (u > 0 && !scales_match(scale, Ti->scale * sc)) fail(CKKS_E_SCALE, "scale mismatch");
+        ma.c.x[u] = Ti->buf.p;
+        ma.c.member_stride[u] = (size_t)2 * (Ti->level + 1) * N;
+        ma.c.poly_stride[u] = (size_t)(Ti->level + 1) * N;
+        for (size_t t = 0; t < n; ++t) {
+            const double kd = std::rint(cfs[t][terms[u]] * sc);
+            if (!(std::fabs(kd) < 4.0e18)) fail(CKKS_E_RANGE, "constant out of range");
+            ma.k[t][u] = (int64_t)kd;
+        }
+    }
+    ma.c.nterm = (int)terms.size();
+    for (size_t t = 0; t < n; ++t)
+        for (size_t u = 0; u < terms.size(); ++u) {
+            trace_op(c, "mul_scalar", lmin, B);
+            if (u > 0) trace_op(c, "add", lmin, B);
+        }
+    Ct acc = ct_new(c, lmin, scale, (int)n * B);
+    gpu::lincomb_multi(c->T, acc->buf.p, ma, lmin + 1, B, map_q(0, lmin + 1), c->stream);
+    std::shared_ptr<ckks_ct> rs(op_rescale(c, acc.get()).release());
+    for (size_t t = 0; t < n; ++t) {
+        Ct v = ct_view(c, rs, (int)t * B, B, rs->scale);
+        out[t] = op_add_const(c, v.get(), cfs[t][0]);
+    }
+    return true;
+}
+
 // Several trees of the same height k at once (the quotient and remainder
 // parts of one split are evaluated side by side): every tree's result is the
 // recursive split p = q T_M + r of the coefficients, computed op for op as
@@ -1268,6 +1325,7 @@ std::vector<Ct> cheb_trees(ckks_ctx *c, PowerBasis &pb, const std::vector<std::v
     const size_t n = cfs.size();
     std::vector<Ct> out(n);
     if (k <= b) {
+        if (baby_sums_together(c, pb, cfs, out)) return out;
         for (size_t t = 0; t < n; ++t) out[t] = baby_sum(c, pb, cfs[t]);
         return out;
     }

@@ -263,6 +263,19 @@ struct CombArgs {
     int64_t k[kMaxComb];
 };
 void lincomb(const Tables &T, uint64_t *out, const CombArgs &a, int nlimb, int B, const LimbMap &m, hipStream_t s);
+// Several linear combinations of the same terms at once (the baby-step sums of
+// one Chebyshev evaluation): out[s] = sum_t k[s][t] * x_t, each term read once
+// for every sum; out[s] starts at out + s * out_stride.  Needs N >= 256 (the
+// host falls back to one lincomb per sum otherwise); nsum <= kMaxSum.
+constexpr int kMaxSum = 8;
+struct CombMultiArgs {
+    CombArgs c;               // terms (c.k unused)
+    int nsum;
+    size_t out_stride;
+    int64_t k[kMaxSum][kMaxComb];
+};
+void lincomb_multi(const Tables &T, uint64_t *out, const CombMultiArgs &a, int nlimb, int B, const LimbMap &m,
+                   hipStream_t s);
 
 // decryption: m = c0 + c1 * s
 void decrypt_combine(const Tables &T, uint64_t *m, const uint64_t *c0, const uint64_t *c1, const uint64_t *sk,

@@ -1531,28 +1531,98 @@ void pt_mac_giants(const Tables &T, uint64_t *out, size_t gstride, const GiantAr
     }
 }
 
+// UNI (N >= 64): the 64 words of a wave lie in one row (waves start at
+// multiples of 64), so the row, its prime and the terms' residues are wave
+// uniform and are computed once per wave on the scalar unit
+template <bool UNI>
 __global__ void k_lincomb(u64 *out, CombArgs a, int logN, int nlimb, size_t total, LimbMap m, Tables T) {
     const size_t N = (size_t)1 << logN;
     GRID_LOOP(i, total) {
-        ROW_SPLIT(i, logN, nlimb, poly, limb)
+        uint32_t row_ = (uint32_t)(i >> logN);
+        if (UNI) row_ = __builtin_amdgcn_readfirstlane(row_);
+        const uint32_t poly = row_ / (uint32_t)nlimb;
+        const uint32_t limb = row_ - poly * (uint32_t)nlimb;
         const uint32_t b = poly >> 1, pp = poly & 1u;
         const size_t j = i & (N - 1);
         const DevPrime P = T.primes[m.p[limb]];
         u64 h = 0, l = 0;
-        for (int t = 0; t < a.nterm; ++t) {
-            const int64_t k = a.k[t];
-            u64 kv = reduce64(k < 0 ? (u64)(-(k + 1)) + 1 : (u64)k, P);
-            if (k < 0 && kv) kv = P.q - kv;
-            const u64 x = a.x[t][b * a.member_stride[t] + pp * a.poly_stride[t] + ((size_t)limb << logN) + j];
-            mac128(h, l, x, kv);
+        // terms in groups of 8: the group's loads are all issued before its
+        // multiply-accumulates, so a wave keeps several loads in flight
+        for (int t0 = 0; t0 < a.nterm; t0 += 8) {
+            u64 xv[8];
+#pragma unroll
+            for (int u = 0; u < 8; ++u) {
+                const int t = t0 + u;
+                xv[u] = t < a.nterm
+                            ? a.x[t][b * a.member_stride[t] + pp * a.poly_stride[t] + ((size_t)limb << logN) + j]
+                            : 0;
+            }
+#pragma unroll
+            for (int u = 0; u < 8; ++u) {
+                const int t = t0 + u;
+                if (t >= a.nterm) break;
+                const int64_t k = a.k[t];
+                u64 kv = reduce64(k < 0 ? (u64)(-(k + 1)) + 1 : (u64)k, P);
+                if (k < 0 && kv) kv = P.q - kv;
+                mac128(h, l, xv[u], kv);
+            }
         }
         out[i] = reduce128(h, l, P);
     }
 }
+// Blocks of 256 words lie in one row (N >= 256), so a block computes the
+// row's residues of every k[s][t] once, in LDS; the loop runs over block
+// starts, so every thread of a block takes the same number of iterations and
+// reaches every barrier.
+__global__ void __launch_bounds__(256) k_lincomb_multi(u64 *out, CombMultiArgs a, int logN, int nlimb, size_t total,
+                                                       LimbMap m, Tables T) {
+    __shared__ u64 kres[kMaxSum * kMaxComb];
+    const size_t N = (size_t)1 << logN;
+    const int nt = a.c.nterm, nk = a.nsum * nt;
+    for (size_t base = (size_t)blockIdx.x * 256; base < total; base += (size_t)gridDim.x * 256) {
+        const uint32_t row_ = (uint32_t)(base >> logN);
+        const uint32_t poly = row_ / (uint32_t)nlimb;
+        const uint32_t limb = row_ - poly * (uint32_t)nlimb;
+        const uint32_t b = poly >> 1, pp = poly & 1u;
+        const DevPrime P = T.primes[m.p[limb]];
+        __syncthreads();   // the previous row's residues are no longer read
+        if ((int)threadIdx.x < nk) {
+            const int sidx = threadIdx.x / nt, t = threadIdx.x - sidx * nt;
+            const int64_t k = a.k[sidx][t];
+            u64 kv = reduce64(k < 0 ? (u64)(-(k + 1)) + 1 : (u64)k, P);
+            if (k < 0 && kv) kv = P.q - kv;
+            kres[threadIdx.x] = kv;
+        }
+        __syncthreads();
+        const size_t i = base + threadIdx.x;
+        const size_t j = i & (N - 1);
+        u64 xv[kMaxComb];
+#pragma unroll
+        for (int t = 0; t < kMaxComb; ++t)
+            xv[t] = t < nt ? a.c.x[t][b * a.c.member_stride[t] + pp * a.c.poly_stride[t] + ((size_t)limb << logN) + j]
+                           : 0;
+        for (int sidx = 0; sidx < a.nsum; ++sidx) {
+            u64 h = 0, l = 0;
+#pragma unroll
+            for (int t = 0; t < kMaxComb; ++t)
+                if (t < nt) mac128(h, l, xv[t], kres[sidx * nt + t]);
+            out[sidx * a.out_stride + i] = reduce128(h, l, P);
+        }
+    }
+}
+void lincomb_multi(const Tables &T, uint64_t *out, const CombMultiArgs &a, int nlimb, int B, const LimbMap &m,
+                   hipStream_t s) {
+    const size_t total = ((size_t)nlimb * 2 * B) << T.logN;
+    if (!total || a.c.nterm <= 0 || a.nsum <= 0) return;
+    hipLaunchKernelGGL(k_lincomb_multi, grid_for(total), dim3(256), 0, s, out, a, T.logN, nlimb, total, m, T);
+}
 void lincomb(const Tables &T, uint64_t *out, const CombArgs &a, int nlimb, int B, const LimbMap &m, hipStream_t s) {
     size_t total = ((size_t)nlimb * 2 * B) << T.logN;
     if (!total || a.nterm <= 0) return;
-    hipLaunchKernelGGL(k_lincomb, grid_for(total), dim3(256), 0, s, out, a, T.logN, nlimb, total, m, T);
+    if (T.logN >= 6)
+        hipLaunchKernelGGL(k_lincomb<true>, grid_for(total), dim3(256), 0, s, out, a, T.logN, nlimb, total, m, T);
+    else
+        hipLaunchKernelGGL(k_lincomb<false>, grid_for(total), dim3(256), 0, s, out, a, T.logN, nlimb, total, m, T);
 }
 
 __global__ void k_decrypt(u64 *mo, const u64 *c0, const u64 *c1, const u64 *sk, int logN, size_t total, LimbMap m,

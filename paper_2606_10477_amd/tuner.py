@@ -113,9 +113,13 @@ def _words(ctx, level, B, seed):
     return [inputs.uniform_words((2, level + 1, ctx.N), ctx.primes[:level + 1], seed + b) for b in range(B)]
 
 
+PIPELINE = 8
+
+
 def profile_unit_costs(ctx, levels, batch=1, reps=5, rot_step=None, bts_bound=None):
-    """Median wall time (s, device-synchronised) of each primitive at each
-    level, on `batch` ciphertexts of uniform words.  With bts_bound, also the
+    """Median wall time (s) of each primitive at each level, on `batch`
+    ciphertexts of uniform words, per call of PIPELINE calls issued back to
+    back and then synchronised.  With bts_bound, also the
     bootstrap (message bound bts_bound), stored under level BTS_ANY_LEVEL."""
     costs = {}
     if bts_bound is not None:
@@ -160,11 +164,15 @@ def profile_unit_costs(ctx, levels, batch=1, reps=5, rot_step=None, bts_bound=No
             ctx.sync()
             ts = []
             for _ in range(reps):
+                # PIPELINE calls back to back, as ops follow each other in a
+                # chain: the GPU queue then hides the host's launch overhead,
+                # which a synchronised single call would count in full
                 t0 = time.perf_counter()
-                r = fn()
+                for _ in range(PIPELINE):
+                    r = fn()
+                    del r
                 ctx.sync()
-                ts.append(time.perf_counter() - t0)
-                del r
+                ts.append((time.perf_counter() - t0) / PIPELINE)
             costs[(op, lvl)] = float(np.median(ts))
     return costs
 
