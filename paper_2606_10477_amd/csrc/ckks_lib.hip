@@ -1267,7 +1267,7 @@ Ct baby_sum(ckks_ctx *c, PowerBasis &pb, const std::vector<double> &cf) {
 bool baby_sums_together(ckks_ctx *c, PowerBasis &pb, const std::vector<std::vector<double>> &cfs,
                         std::vector<Ct> &out) {
     const size_t n = cfs.size();
-    if (n < 2 || n > (size_t)gpu::kMaxSum || c->logN < 8) return false;
+    if (n < 2 || n > (size_t)gpu::kMaxSum || c->logN < 9) return false;
     std::vector<int> terms;
     for (size_t t = 0; t < n; ++t) {
         std::vector<int> tt;

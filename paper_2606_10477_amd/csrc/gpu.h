@@ -265,7 +265,7 @@ struct CombArgs {
 void lincomb(const Tables &T, uint64_t *out, const CombArgs &a, int nlimb, int B, const LimbMap &m, hipStream_t s);
 // Several linear combinations of the same terms at once (the baby-step sums of
 // one Chebyshev evaluation): out[s] = sum_t k[s][t] * x_t, each term read once
-// for every sum; out[s] starts at out + s * out_stride.  Needs N >= 256 (the
+// for every sum; out[s] starts at out + s * out_stride.  Needs N >= 512 (the
 // host falls back to one lincomb per sum otherwise); nsum <= kMaxSum.
 constexpr int kMaxSum = 8;
 struct CombMultiArgs {

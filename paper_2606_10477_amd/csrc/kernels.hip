@@ -868,11 +868,42 @@ __global__ void k_mul_add_scalar(u64 *out, const u64 *a, LimbConsts k, LimbWords
         out[i] = (poly & 1) ? r : add_mod(r, c.v[limb], q);
     }
 }
+// the same with 4 words per thread (N >= 1024): a block covers 1024
+// consecutive words of one row, each load instruction still coalesced, and
+// the row's constants are block uniform
+__global__ void __launch_bounds__(256) k_mul_add_scalar4(u64 *out, const u64 *a, LimbConsts k, LimbWords c,
+                                                         int logN, int nlimb, size_t total, LimbMap m, Tables T) {
+    for (size_t base = (size_t)blockIdx.x * 1024; base < total; base += (size_t)gridDim.x * 1024) {
+        const uint32_t row_ = (uint32_t)(base >> logN);
+        const uint32_t poly = row_ / (uint32_t)nlimb;
+        const uint32_t limb = row_ - poly * (uint32_t)nlimb;
+        const u64 q = T.primes[m.p[limb]].q;
+        const size_t i0 = base + threadIdx.x;
+        u64 x[4];
+#pragma unroll
+        for (int e = 0; e < 4; ++e) x[e] = a[i0 + 256 * e];
+#pragma unroll
+        for (int e = 0; e < 4; ++e) {
+            const u64 r = mul_shoup(x[e], k.v[limb], k.sh[limb], q);
+            out[i0 + 256 * e] = (poly & 1) ? r : add_mod(r, c.v[limb], q);
+        }
+    }
+}
+static inline dim3 grid_for4(size_t n) {
+    size_t b = (n + 1023) / 1024;
+    if (b > 65535u * 8u) b = 65535u * 8u;
+    return dim3((unsigned)b);
+}
 void mul_add_scalar(const Tables &T, uint64_t *out, const uint64_t *a, const LimbConsts &k, const LimbWords &c,
                     int nlimb, int npoly, const LimbMap &m, hipStream_t s) {
     size_t total = ((size_t)nlimb * npoly) << T.logN;
     if (!total) return;
-    hipLaunchKernelGGL(k_mul_add_scalar, grid_for(total), dim3(256), 0, s, out, a, k, c, T.logN, nlimb, total, m, T);
+    if (T.logN >= 10)
+        hipLaunchKernelGGL(k_mul_add_scalar4, grid_for4(total), dim3(256), 0, s, out, a, k, c, T.logN, nlimb, total,
+                           m, T);
+    else
+        hipLaunchKernelGGL(k_mul_add_scalar, grid_for(total), dim3(256), 0, s, out, a, k, c, T.logN, nlimb, total, m,
+                           T);
 }
 
 __global__ void k_add_scalar(u64 *out, const u64 *a, LimbConsts c, int logN, int nlimb, size_t total, LimbMap m,
@@ -1570,20 +1601,32 @@ __global__ void k_lincomb(u64 *out, CombArgs a, int logN, int nlimb, size_t tota
         out[i] = reduce128(h, l, P);
     }
 }
-// Blocks of 256 words lie in one row (N >= 256), so a block computes the
-// row's residues of every k[s][t] once, in LDS; the loop runs over block
-// starts, so every thread of a block takes the same number of iterations and
-// reaches every barrier.
+// A block covers 512 consecutive words of one row (N >= 512), 2 per thread,
+// so the block computes the row's residues of every k[s][t] once, in LDS.
+// The terms' words are loaded before that (they do not depend on it), so
+// their latency overlaps the residue computation and its barriers.  The loop
+// runs over block starts: every thread of a block takes the same number of
+// iterations and reaches every barrier.
 __global__ void __launch_bounds__(256) k_lincomb_multi(u64 *out, CombMultiArgs a, int logN, int nlimb, size_t total,
                                                        LimbMap m, Tables T) {
     __shared__ u64 kres[kMaxSum * kMaxComb];
     const size_t N = (size_t)1 << logN;
     const int nt = a.c.nterm, nk = a.nsum * nt;
-    for (size_t base = (size_t)blockIdx.x * 256; base < total; base += (size_t)gridDim.x * 256) {
+    for (size_t base = (size_t)blockIdx.x * 512; base < total; base += (size_t)gridDim.x * 512) {
         const uint32_t row_ = (uint32_t)(base >> logN);
         const uint32_t poly = row_ / (uint32_t)nlimb;
         const uint32_t limb = row_ - poly * (uint32_t)nlimb;
         const uint32_t b = poly >> 1, pp = poly & 1u;
+        const size_t j0 = (base & (N - 1)) + threadIdx.x;
+        u64 xv[kMaxComb][2];
+#pragma unroll
+        for (int t = 0; t < kMaxComb; ++t) {
+            const u64 *px = t < nt ? a.c.x[t] + b * a.c.member_stride[t] + pp * a.c.poly_stride[t] +
+                                         ((size_t)limb << logN) + j0
+                                   : nullptr;
+            xv[t][0] = px ? px[0] : 0;
+            xv[t][1] = px ? px[256] : 0;
+        }
         const DevPrime P = T.primes[m.p[limb]];
         __syncthreads();   // the previous row's residues are no longer read
         if ((int)threadIdx.x < nk) {
@@ -1594,19 +1637,18 @@ __global__ void __launch_bounds__(256) k_lincomb_multi(u64 *out, CombMultiArgs a
             kres[threadIdx.x] = kv;
         }
         __syncthreads();
-        const size_t i = base + threadIdx.x;
-        const size_t j = i & (N - 1);
-        u64 xv[kMaxComb];
-#pragma unroll
-        for (int t = 0; t < kMaxComb; ++t)
-            xv[t] = t < nt ? a.c.x[t][b * a.c.member_stride[t] + pp * a.c.poly_stride[t] + ((size_t)limb << logN) + j]
-                           : 0;
+        const size_t i0 = base + threadIdx.x;
         for (int sidx = 0; sidx < a.nsum; ++sidx) {
-            u64 h = 0, l = 0;
+            u64 h0 = 0, l0 = 0, h1 = 0, l1 = 0;
 #pragma unroll
             for (int t = 0; t < kMaxComb; ++t)
-                if (t < nt) mac128(h, l, xv[t], kres[sidx * nt + t]);
-            out[sidx * a.out_stride + i] = reduce128(h, l, P);
+                if (t < nt) {
+                    const u64 kv = kres[sidx * nt + t];
+                    mac128(h0, l0, xv[t][0], kv);
+                    mac128(h1, l1, xv[t][1], kv);
+                }
+            out[sidx * a.out_stride + i0] = reduce128(h0, l0, P);
+            out[sidx * a.out_stride + i0 + 256] = reduce128(h1, l1, P);
         }
     }
 }
@@ -1614,12 +1656,56 @@ void lincomb_multi(const Tables &T, uint64_t *out, const CombMultiArgs &a, int n
                    hipStream_t s) {
     const size_t total = ((size_t)nlimb * 2 * B) << T.logN;
     if (!total || a.c.nterm <= 0 || a.nsum <= 0) return;
-    hipLaunchKernelGGL(k_lincomb_multi, grid_for(total), dim3(256), 0, s, out, a, T.logN, nlimb, total, m, T);
+    size_t nb = (total + 511) / 512;
+    if (nb > 65535u * 8u) nb = 65535u * 8u;
+    hipLaunchKernelGGL(k_lincomb_multi, dim3((unsigned)nb), dim3(256), 0, s, out, a, T.logN, nlimb, total, m, T);
+}
+// 4 words per thread (N >= 1024): a block covers 1024 consecutive words of
+// one row (so the row, its prime and the terms' residues are block uniform);
+// four terms' loads (16 words) are issued before their multiply-accumulates
+__global__ void __launch_bounds__(256) k_lincomb4(u64 *out, CombArgs a, int logN, int nlimb, size_t total, LimbMap m,
+                                                  Tables T) {
+    const size_t N = (size_t)1 << logN;
+    for (size_t base = (size_t)blockIdx.x * 1024; base < total; base += (size_t)gridDim.x * 1024) {
+        const uint32_t row_ = (uint32_t)(base >> logN);
+        const uint32_t poly = row_ / (uint32_t)nlimb;
+        const uint32_t limb = row_ - poly * (uint32_t)nlimb;
+        const uint32_t b = poly >> 1, pp = poly & 1u;
+        const size_t j0 = (base & (N - 1)) + threadIdx.x;
+        const DevPrime P = T.primes[m.p[limb]];
+        u64 h[4] = {0, 0, 0, 0}, l[4] = {0, 0, 0, 0};
+        for (int t0 = 0; t0 < a.nterm; t0 += 4) {
+            u64 xv[4][4];
+#pragma unroll
+            for (int u = 0; u < 4; ++u) {
+                const int t = t0 + u;
+                const u64 *px = t < a.nterm ? a.x[t] + b * a.member_stride[t] + pp * a.poly_stride[t] +
+                                                  ((size_t)limb << logN) + j0
+                                            : nullptr;
+#pragma unroll
+                for (int e = 0; e < 4; ++e) xv[u][e] = px ? px[256 * e] : 0;
+            }
+#pragma unroll
+            for (int u = 0; u < 4; ++u) {
+                const int t = t0 + u;
+                if (t >= a.nterm) break;
+                const int64_t k = a.k[t];
+                u64 kv = reduce64(k < 0 ? (u64)(-(k + 1)) + 1 : (u64)k, P);
+                if (k < 0 && kv) kv = P.q - kv;
+#pragma unroll
+                for (int e = 0; e < 4; ++e) mac128(h[e], l[e], xv[u][e], kv);
+            }
+        }
+#pragma unroll
+        for (int e = 0; e < 4; ++e) out[base + threadIdx.x + 256 * e] = reduce128(h[e], l[e], P);
+    }
 }
 void lincomb(const Tables &T, uint64_t *out, const CombArgs &a, int nlimb, int B, const LimbMap &m, hipStream_t s) {
     size_t total = ((size_t)nlimb * 2 * B) << T.logN;
     if (!total || a.nterm <= 0) return;
-    if (T.logN >= 6)
+    if (T.logN >= 10)
+        hipLaunchKernelGGL(k_lincomb4, grid_for4(total), dim3(256), 0, s, out, a, T.logN, nlimb, total, m, T);
+    else if (T.logN >= 6)
         hipLaunchKernelGGL(k_lincomb<true>, grid_for(total), dim3(256), 0, s, out, a, T.logN, nlimb, total, m, T);
     else
         hipLaunchKernelGGL(k_lincomb<false>, grid_for(total), dim3(256), 0, s, out, a, T.logN, nlimb, total, m, T);
