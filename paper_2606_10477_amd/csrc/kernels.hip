@@ -985,10 +985,52 @@ __global__ void k_tensor_gather(u64 *d01, u64 *d2, GatherPtrs g, int logN, int n
         d2[i] = mul_mod(x1, y1, P);
     }
 }
+// the same with 2 words per thread (N >= 512): a block covers 512 consecutive
+// words of one row, whose prime and operand pointers are block uniform
+__global__ void __launch_bounds__(256) k_tensor_gather2(u64 *d01, u64 *d2, GatherPtrs g, int logN, int nlimb,
+                                                        size_t total, LimbMap m, Tables T) {
+    const size_t per = (size_t)nlimb << logN;
+    const size_t mask = ((size_t)1 << logN) - 1;
+    for (size_t base = (size_t)blockIdx.x * 512; base < total; base += (size_t)gridDim.x * 512) {
+        const uint32_t row_ = (uint32_t)(base >> logN);
+        const uint32_t ct = row_ / (uint32_t)nlimb;
+        const uint32_t limb = row_ - ct * (uint32_t)nlimb;
+        const DevPrime P = T.primes[m.p[limb]];
+        const size_t rem = ((size_t)limb << logN) | ((base & mask) + threadIdx.x);
+        const uint32_t src = ct / (uint32_t)g.per_src, loc = ct - src * (uint32_t)g.per_src;
+        const size_t sb = (size_t)loc * 2 * per + rem;
+        const u64 *a = g.a[src], *b = g.b[src];
+        u64 x0[2], x1[2], y0[2], y1[2];
+#pragma unroll
+        for (int e = 0; e < 2; ++e) {
+            x0[e] = a[sb + 256 * e];
+            x1[e] = a[sb + per + 256 * e];
+            y0[e] = b[sb + 256 * e];
+            y1[e] = b[sb + per + 256 * e];
+        }
+        const size_t ob = (size_t)ct * 2 * per + rem;
+#pragma unroll
+        for (int e = 0; e < 2; ++e) {
+            d01[ob + 256 * e] = mul_mod(x0[e], y0[e], P);
+            u64 hi = 0, lo = 0;
+            mac128(hi, lo, x0[e], y1[e]);
+            mac128(hi, lo, x1[e], y0[e]);
+            d01[ob + per + 256 * e] = reduce128(hi, lo, P);
+            d2[base + threadIdx.x + 256 * e] = mul_mod(x1[e], y1[e], P);
+        }
+    }
+}
 void tensor_gather(const Tables &T, uint64_t *d01, uint64_t *d2, const GatherPtrs &g, int nlimb, int nct,
                    const LimbMap &m, hipStream_t s) {
     size_t total = ((size_t)nlimb * nct) << T.logN;
     if (!total) return;
+    if (T.logN >= 9) {
+        size_t nb = (total + 511) / 512;
+        if (nb > 65535u * 8u) nb = 65535u * 8u;
+        hipLaunchKernelGGL(k_tensor_gather2, dim3((unsigned)nb), dim3(256), 0, s, d01, d2, g, T.logN, nlimb, total, m,
+                           T);
+        return;
+    }
     hipLaunchKernelGGL(k_tensor_gather, grid_for(total), dim3(256), 0, s, d01, d2, g, T.logN, nlimb, total, m, T);
 }
 
