@@ -96,7 +96,7 @@ def ntt_traffic(alg_bytes_per_launch):
 def main():
     args = parse()
     if args.gpus != 1:
-        print(json.dumps({"error": "this build runs on one GPU; --gpus must be 1"}))
+        print(json.dumps({"error": "the library runs on one GPU; --gpus must be 1"}))
         sys.exit(2)
     t_start = time.perf_counter()
     cpu_proc = None if args.no_cpu_baseline else start_cpu_baseline(args)

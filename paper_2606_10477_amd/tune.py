@@ -109,7 +109,7 @@ def run(levels, degrees, iters, targets, lo, hi, batch, reps, fixed, tuner_seed=
 
 def main(argv=None):
     ap = argparse.ArgumentParser()
-    ap.add_argument("--out", default="gpurun_out/tuning.json")
+    ap.add_argument("--out", default="tuning_report.json")
     ap.add_argument("--levels", default="3,4,5,6,7")
     ap.add_argument("--degrees", default="7,15,31,63,127")
     ap.add_argument("--iters", default="1,2,3,4,5,6")
