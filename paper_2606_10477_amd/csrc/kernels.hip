@@ -1462,11 +1462,56 @@ __global__ void k_moddown_finish_jobs(FinishJobs F, const u64 *acc, size_t acc_s
         F.out[t][b * member + (size_t)pp * nlimb * N + rem] = v;
     }
 }
+// the same with 4 words per thread (N >= 1024): a block covers 1024
+// consecutive words of one row, so the job, member, poly, limb and their
+// pointers and constants are block uniform; the accumulator, conversion and
+// permutation words of all four are loaded before the dependent c0 gathers
+__global__ void __launch_bounds__(256) k_moddown_finish_jobs4(FinishJobs F, const u64 *acc, size_t acc_stride,
+                                                              const u64 *z, LimbConsts pinv, int logN, int nlimb,
+                                                              int B, size_t total, LimbMap m, Tables T) {
+    const size_t N = (size_t)1 << logN;
+    const size_t member = (size_t)2 * nlimb * N;
+    for (size_t base = (size_t)blockIdx.x * 1024; base < total; base += (size_t)gridDim.x * 1024) {
+        const uint32_t row_ = (uint32_t)(base >> logN);
+        const uint32_t poly = row_ / (uint32_t)nlimb;
+        const uint32_t limb = row_ - poly * (uint32_t)nlimb;
+        const uint32_t t = poly / (2u * (uint32_t)B);
+        const uint32_t r2 = poly - t * 2u * (uint32_t)B;
+        const uint32_t b = r2 >> 1, pp = r2 & 1u;
+        const size_t j0 = (base & (N - 1)) + threadIdx.x;
+        const size_t rem0 = ((size_t)limb << logN) | j0;
+        const u64 q = T.primes[m.p[limb]].q;
+        const u64 *ap = acc + (size_t)poly * acc_stride + rem0;
+        const u64 *zp = z + base + threadIdx.x;
+        const u64 *add = pp == 0 ? F.add[t] : nullptr;
+        const int32_t *perm = F.perm[t];
+        u64 x[4], y[4];
+        size_t jx[4];
+#pragma unroll
+        for (int e = 0; e < 4; ++e) {
+            x[e] = ap[256 * e];
+            y[e] = zp[256 * e];
+            jx[e] = (add && perm) ? (size_t)perm[j0 + 256 * e] : j0 + 256 * e;
+        }
+        u64 *o = F.out[t] + b * member + (size_t)pp * nlimb * N + rem0;
+#pragma unroll
+        for (int e = 0; e < 4; ++e) {
+            u64 v = mul_shoup(sub_mod(x[e], y[e], q), pinv.v[limb], pinv.sh[limb], q);
+            if (add) v = add_mod(v, add[b * member + ((size_t)limb << logN) + jx[e]], q);
+            o[256 * e] = v;
+        }
+    }
+}
 void moddown_finish_jobs(const Tables &T, const FinishJobs &f, const uint64_t *acc, size_t acc_poly_stride,
                          const uint64_t *z, const LimbConsts &pinv, int nlimb, int njob, int B, const LimbMap &m,
                          hipStream_t s) {
     size_t total = ((size_t)nlimb * 2 * njob * B) << T.logN;
     if (!total) return;
+    if (T.logN >= 10) {
+        hipLaunchKernelGGL(k_moddown_finish_jobs4, grid_for4(total), dim3(256), 0, s, f, acc, acc_poly_stride, z,
+                           pinv, T.logN, nlimb, B, total, m, T);
+        return;
+    }
     hipLaunchKernelGGL(k_moddown_finish_jobs, grid_for(total), dim3(256), 0, s, f, acc, acc_poly_stride, z, pinv,
                        T.logN, nlimb, B, total, m, T);
 }
