@@ -232,6 +232,33 @@ def test_cheb_newton_invsqrt_chain_small(pair12, oracle_mod):
         same(g.cheb_eval(gx, cf, 2 ** -8, 1.0), o.cheb_eval(ox, cf, 2 ** -8, 1.0))
 
 
+@pytest.mark.parametrize("log_n", [8, 9])
+def test_small_ring_paths_bit_exact(oracle_mod, log_n):
+    """N = 2^8 and 2^9: the launch shapes used below 2^10 (one word per thread
+    in the linear combinations, ModDown finish and multiply-add passes; leaf by
+    leaf baby-step sums at 2^8, the one-pass form at 2^9): a Chebyshev +
+    Newton chain, products and hoisted rotations bit-exact vs the oracle."""
+    ck = _gpu_mod()
+    g = ck.Context(log_n=log_n, max_level=11, num_special=1, digit_size=2, hamming_weight=0)
+    o = oracle_mod.Context(log_n, 11, 1, 2, h=0)
+    try:
+        steps = [1, -3, 7]
+        gal = _galois(g, steps)
+        g.keygen(5, gal)
+        o.keygen(5, gal)
+        x = inputs.log_uniform(g.n, 2 ** -8, 1.0, 40 + log_n)
+        gx, ox = g.encrypt(x, 11, 2.0 ** 50, 7), o.encrypt(x, 11, 2.0 ** 50, 7)
+        same(gx, ox)
+        cf = oracle_mod.cheb_coeffs_invsqrt(15, 2 ** -8, 1.0)
+        same(g.cheb_eval(gx, cf, 2 ** -8, 1.0), o.cheb_eval(ox, cf, 2 ** -8, 1.0))
+        same(g.invsqrt(gx, 15, 2, a=2 ** -8, b=1.0), o.invsqrt(ox, 15, 2, 2 ** -8, 1.0))
+        same(g.hmult(gx, gx), o.hmult(ox, ox))
+        for gr, orr in zip(g.rotate_hoisted(gx, steps), o.rotate_hoisted(ox, steps)):
+            same(gr, orr)
+    finally:
+        g.close()
+
+
 def _batched_ops_match(g, lvl, seed0):
     xs = [g.encrypt(inputs.log_uniform(g.n, 2 ** -8, 1.0, seed0 + i), lvl, 2.0 ** 40, seed0 + 10 + i)
           for i in range(3)]
