@@ -1307,6 +1307,42 @@ __global__ void k_key_inner(u64 *acc, InnerArgs a, int logN, size_t total, Table
         const size_t jx = a.perm ? (size_t)a.perm[j] : j;
         const int pi = a.m.p[e];
         const DevPrime P = T.primes[pi];
+        if (a.ndig <= 4) {
+            // up to 4 digits: every key word of the thread loaded once, up
+            // front, then per ciphertext all digits' words loaded together
+            u64 k0v[4], k1v[4];
+#pragma unroll
+            for (int d = 0; d < 4; ++d) {
+                const bool on = d < a.ndig;
+                k0v[d] = on ? a.key[(((size_t)d * 2 + 0) * a.np + pi) * N + j] : 0;
+                k1v[d] = on ? a.key[(((size_t)d * 2 + 1) * a.np + pi) * N + j] : 0;
+            }
+            for (int b = 0; b < a.nct; ++b) {
+                u64 xv[4];
+#pragma unroll
+                for (int d = 0; d < 4; ++d) {
+                    if (d >= a.ndig) {
+                        xv[d] = 0;
+                    } else if (e >= a.lo[d] && e < a.hi[d]) {
+                        xv[d] = a.dsrc[b * a.dsrc_stride + (size_t)e * N + jx];
+                    } else {
+                        const int ce = e < a.lo[d] ? e : e - (a.hi[d] - a.lo[d]);
+                        xv[d] = a.ext[d][b * a.ext_stride[d] + (size_t)ce * N + jx];
+                    }
+                }
+                u64 h0 = 0, l0 = 0, h1 = 0, l1 = 0;
+#pragma unroll
+                for (int d = 0; d < 4; ++d) {
+                    if (d >= a.ndig) break;
+                    mac128(h0, l0, xv[d], k0v[d]);
+                    mac128(h1, l1, xv[d], k1v[d]);
+                }
+                u64 *o = acc + (size_t)b * 2 * a.ne * N;
+                o[i] = reduce128(h0, l0, P);
+                o[(size_t)a.ne * N + i] = reduce128(h1, l1, P);
+            }
+            continue;
+        }
         for (int b = 0; b < a.nct; ++b) {
             u64 h0 = 0, l0 = 0, h1 = 0, l1 = 0;
             for (int d = 0; d < a.ndig; ++d) {
