@@ -834,10 +834,33 @@ __global__ void k_add(u64 *out, const u64 *a, const u64 *b, int logN, int nlimb,
         out[i] = sub ? sub_mod(a[i], b[i], q) : add_mod(a[i], b[i], q);
     }
 }
+// the same with 4 words per thread (N >= 1024; blocks of 1024 words of one row)
+__global__ void __launch_bounds__(256) k_add4(u64 *out, const u64 *a, const u64 *b, int logN, int nlimb,
+                                              size_t total, LimbMap m, Tables T, int sub) {
+    for (size_t base = (size_t)blockIdx.x * 1024; base < total; base += (size_t)gridDim.x * 1024) {
+        const uint32_t row_ = (uint32_t)(base >> logN);
+        const uint32_t limb = row_ % (uint32_t)nlimb;
+        const u64 q = T.primes[m.p[limb]].q;
+        const size_t i0 = base + threadIdx.x;
+        u64 x[4], y[4];
+#pragma unroll
+        for (int e = 0; e < 4; ++e) {
+            x[e] = a[i0 + 256 * e];
+            y[e] = b[i0 + 256 * e];
+        }
+#pragma unroll
+        for (int e = 0; e < 4; ++e) out[i0 + 256 * e] = sub ? sub_mod(x[e], y[e], q) : add_mod(x[e], y[e], q);
+    }
+}
+static inline dim3 grid_for4(size_t n);
 void add(const Tables &T, uint64_t *out, const uint64_t *a, const uint64_t *b, int nlimb, int npoly,
          const LimbMap &m, bool sub, hipStream_t s) {
     size_t total = ((size_t)nlimb * npoly) << T.logN;
     if (!total) return;
+    if (T.logN >= 10) {
+        hipLaunchKernelGGL(k_add4, grid_for4(total), dim3(256), 0, s, out, a, b, T.logN, nlimb, total, m, T, (int)sub);
+        return;
+    }
     hipLaunchKernelGGL(k_add, grid_for(total), dim3(256), 0, s, out, a, b, T.logN, nlimb, total, m, T, (int)sub);
 }
 
@@ -1470,10 +1493,65 @@ __global__ void k_rot_c0_sum(FinishJobs F, u64 *out, const u64 *extra, int accum
         out[i] = sum;
     }
 }
+// the same with 4 words per thread (N >= 1024): a block covers 1024
+// consecutive words of one row (block-uniform member, poly and limb); the
+// jobs go in groups of 4, each group's permutation words loaded together and
+// then its 16 gathers
+__global__ void __launch_bounds__(256) k_rot_c0_sum4(FinishJobs F, u64 *out, const u64 *extra, int accumulate,
+                                                     int logN, int nlimb, int njob, size_t total, LimbMap m,
+                                                     Tables T) {
+    const size_t N = (size_t)1 << logN;
+    const size_t member = (size_t)2 * nlimb * N;
+    for (size_t base = (size_t)blockIdx.x * 1024; base < total; base += (size_t)gridDim.x * 1024) {
+        const uint32_t row_ = (uint32_t)(base >> logN);
+        const uint32_t r2 = row_ / (uint32_t)nlimb;
+        const uint32_t limb = row_ - r2 * (uint32_t)nlimb;
+        const uint32_t b = r2 >> 1, pp = r2 & 1u;
+        const size_t j0 = (base & (N - 1)) + threadIdx.x;
+        const size_t i0 = base + threadIdx.x;
+        const u64 q = T.primes[m.p[limb]].q;
+        u64 sum[4];
+#pragma unroll
+        for (int e = 0; e < 4; ++e) sum[e] = accumulate ? out[i0 + 256 * e] : (extra ? extra[i0 + 256 * e] : 0);
+        if (pp == 0) {
+            const size_t rowoff = b * member + ((size_t)limb << logN);
+            for (int t0 = 0; t0 < njob; t0 += 4) {
+                size_t jx[4][4];
+#pragma unroll
+                for (int u = 0; u < 4; ++u) {
+                    const int t = t0 + u;
+                    const int32_t *pm = t < njob ? F.perm[t] : nullptr;
+#pragma unroll
+                    for (int e = 0; e < 4; ++e) jx[u][e] = pm ? (size_t)pm[j0 + 256 * e] : j0 + 256 * e;
+                }
+                u64 w[4][4];
+#pragma unroll
+                for (int u = 0; u < 4; ++u) {
+                    const int t = t0 + u;
+#pragma unroll
+                    for (int e = 0; e < 4; ++e) w[u][e] = t < njob ? F.add[t][rowoff + jx[u][e]] : 0;
+                }
+#pragma unroll
+                for (int u = 0; u < 4; ++u) {
+                    if (t0 + u >= njob) break;
+#pragma unroll
+                    for (int e = 0; e < 4; ++e) sum[e] = add_mod(sum[e], w[u][e], q);
+                }
+            }
+        }
+#pragma unroll
+        for (int e = 0; e < 4; ++e) out[i0 + 256 * e] = sum[e];
+    }
+}
 void rot_c0_sum(const Tables &T, const FinishJobs &f, uint64_t *out, const uint64_t *extra, bool accumulate,
                 int nlimb, int njob, int B, const LimbMap &m, hipStream_t s) {
     size_t total = ((size_t)nlimb * 2 * B) << T.logN;
     if (!total) return;
+    if (T.logN >= 10) {
+        hipLaunchKernelGGL(k_rot_c0_sum4, grid_for4(total), dim3(256), 0, s, f, out, extra, (int)accumulate, T.logN,
+                           nlimb, njob, total, m, T);
+        return;
+    }
     hipLaunchKernelGGL(k_rot_c0_sum, grid_for(total), dim3(256), 0, s, f, out, extra, (int)accumulate, T.logN, nlimb,
                        njob, total, m, T);
 }
