@@ -4,14 +4,17 @@ One step = CryptoInvSqrt (paper Alg. 1: Chebyshev initial value, Newton
 steps, bootstrapping whenever levels run out) of the fixed configuration
 (degree 31, 3 Newton steps) on one ciphertext (--batch: several, as one
 batched launch sequence) already resident in HBM, on the 128-bit parameter
-set with bootstrapping (log2 QP ~ 1556, dnum 3, h 192): from the top
-computation level 7 the chain bootstraps once.  Prints one JSON line: value =
+set with bootstrapping "p16b" (log2 QP ~ 1544, dnum 3, h 192): from the top
+computation level 8 the chain bootstraps once.  Prints one JSON line: value =
 ciphertexts/s for the whole job, the roofline of the dominant kernel family
 measured live with HIP events on the library's stream, the MRE of the result
-against FP64, the same chain batched (ciphertexts/s at --extra-batch), and the
-CPU oracle timed on a bounded sample.
+against FP64, the same chain batched (ciphertexts/s at --extra-batch), the
+CPU oracle timed on a bounded sample (one ciphertext on one core, then one
+ciphertext per process on all cores after the GPU work), and whether the
+GPU's result words equal the oracle's.
 """
 import argparse
+import hashlib
 import json
 import os
 import subprocess
@@ -24,8 +27,7 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0          # MI355X HBM3E, published
-P16B = dict(log_n=16, max_level=7, num_special=7, digit_size=8, hamming_weight=192, bts=(3, 10, 3, 52))
-EVALMOD = (25.0, 4, 31)
+PARAMS = "p16b"
 LO, HI = 2.0 ** -10, 1.0
 
 
@@ -37,44 +39,69 @@ def parse():
     ap.add_argument("--batch", type=int, default=1, help="ciphertexts per step")
     ap.add_argument("--degree", type=int, default=31)
     ap.add_argument("--iters", type=int, default=3)
-    ap.add_argument("--level", type=int, default=7, help="input level")
+    ap.add_argument("--level", type=int, default=8, help="input level")
     ap.add_argument("--extra-batch", type=int, default=16, help="also time this many ciphertexts per step (0: skip)")
     ap.add_argument("--latency-runs", type=int, default=20, help="single-ciphertext runs timed one by one (p50/p99)")
     ap.add_argument("--graph-runs", type=int, default=10,
                     help="replays of the one-ciphertext chain captured as a HIP graph, against as many eager runs "
                          "(0: skip)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--cpu-limit", type=int, default=360,
+    ap.add_argument("--cpu-limit", type=int, default=480,
                     help="seconds after the start the CPU baseline may run until")
+    ap.add_argument("--cpu-procs", type=int, default=0,
+                    help="processes of the all-core CPU phase (0: the CPUs this process may use, at most 16)")
     return ap.parse_args()
 
 
 def start_cpu_baseline(args):
-    """Start the oracle on the same chain for one ciphertext in a child
-    process (single-threaded, plain CPU; it never touches the GPU), before
-    this process initialises the GPU, so that it runs alongside."""
+    """Start the oracle on the same chain in a child process (plain CPU; it
+    never touches the GPU), before this process initialises the GPU, so that
+    its set-up and its one-core run go alongside the GPU timing; its
+    all-core phase waits for a line on stdin (sent when the GPU work ends)."""
+    procs = args.cpu_procs or min(16, len(os.sched_getaffinity(0)))
     cmd = [sys.executable, "-m", "oracle.chain_timer", "--level", str(args.level), "--degree", str(args.degree),
-           "--iters", str(args.iters)]
+           "--iters", str(args.iters), "--procs", str(procs), "--wait-go"]
     env = dict(os.environ, OMP_NUM_THREADS="1")
-    return subprocess.Popen(cmd, cwd=ROOT, stdout=subprocess.PIPE, stderr=subprocess.PIPE, text=True, env=env)
+    return subprocess.Popen(cmd, cwd=ROOT, stdin=subprocess.PIPE, stdout=subprocess.PIPE, stderr=subprocess.PIPE,
+                            text=True, env=env)
 
 
 def finish_cpu_baseline(proc, args, limit_s):
+    """(cpu_baseline dict, the oracle's one-core result record or None)."""
+    try:
+        proc.stdin.write("go\n")
+        proc.stdin.flush()
+    except OSError:
+        pass
     try:
         out, err = proc.communicate(timeout=limit_s)
     except subprocess.TimeoutExpired:
         proc.kill()
         proc.communicate()
-        return {"value": None, "unit": "ciphertexts/s", "cores": 1, "kind": "oracle",
-                "sample": f"oracle did not finish within the time limit ({limit_s:.0f} s left at the end of the GPU run)"}
+        return {"value": None, "unit": "ciphertexts/s", "cores": None, "kind": "oracle",
+                "sample": f"oracle did not finish within the time limit ({limit_s:.0f} s left at the end of the GPU run)"}, None
     if proc.returncode != 0:
-        return {"value": None, "unit": "ciphertexts/s", "cores": 1, "kind": "oracle",
-                "sample": "oracle failed: " + err.strip()[-200:]}
+        return {"value": None, "unit": "ciphertexts/s", "cores": None, "kind": "oracle",
+                "sample": "oracle failed: " + err.strip()[-200:]}, None
     r = json.loads(out.strip().splitlines()[-1])
-    return {"value": round(1.0 / r["seconds"], 6), "unit": "ciphertexts/s", "cores": r["cores"], "kind": "oracle",
-            "sample": f"1 ciphertext through the same chain (degree {args.degree}, {args.iters} Newton steps, "
-                      f"bootstrapping when levels run out) at N=2^16 from level {args.level}, single-threaded: "
-                      f"{r['seconds']:.1f} s (set-up {r['setup_seconds']:.0f} s not timed), MRE {r['mre']:.3g}"}
+    chain = (f"the same chain (degree {args.degree}, {args.iters} Newton steps, bootstrapping when levels run "
+             f"out) at N=2^16 from level {args.level}")
+    single = {"value": round(1.0 / r["seconds"], 6), "cores": 1, "seconds": round(r["seconds"], 2),
+              "mre": r["mre"]}
+    base = {"unit": "ciphertexts/s", "kind": "oracle", "cpu_model": r["cpu_model"], "nproc": r["nproc"],
+            "affinity": r["affinity"], "setup_seconds": round(r["setup_seconds"], 1), "single_core": single}
+    a = r.get("allcore")
+    if a and a["completed"]:
+        base.update({"value": round(a["ciphertexts_per_s"], 6), "cores": a["procs"],
+                     "sample": f"{a['completed']} ciphertexts through {chain}, one per process on {a['procs']} "
+                               f"processes (keys shared copy-on-write after one set-up, not timed), after the GPU "
+                               f"work: {a['wall_seconds']:.1f} s wall, {a['per_ct_seconds_mean']:.1f} s per "
+                               f"ciphertext; one ciphertext alone on one core: {r['seconds']:.1f} s"})
+    else:
+        base.update({"value": single["value"], "cores": 1,
+                     "sample": f"1 ciphertext through {chain}, single-threaded: {r['seconds']:.1f} s "
+                               f"(set-up {r['setup_seconds']:.0f} s not timed)"})
+    return base, r
 
 
 def ntt_traffic(alg_bytes_per_launch):
@@ -104,8 +131,7 @@ def main():
     from paper_2606_10477_amd import ckks, inputs
 
     torch.cuda.set_device(0)
-    ctx = ckks.Context(**P16B)
-    ctx.bts_setup(*EVALMOD)
+    ctx = ckks.Context.from_set(PARAMS)
     ctx.keygen(9, ctx.bts_galois())
     nmax = max(args.batch, args.extra_batch)
     xs = [inputs.log_uniform(ctx.n, LO, HI, 1 + i) for i in range(nmax)]
@@ -137,6 +163,7 @@ def main():
     # kernel-family timing: HIP events around every NTT / key-switch call on
     # the library's stream, over a second pass of the same steps (the events
     # add gaps between kernels, so the throughput above is taken without them)
+    print(f"timed {args.steps} steps: {dt * 1e3 / args.steps:.2f} ms per step", file=sys.stderr, flush=True)
     ctx.profile(True)
     for _ in range(args.steps):
         out_p = step(args.batch)
@@ -147,6 +174,7 @@ def main():
         n, ms, by = ctx.profile_read(name)
         fam[name] = (n, ms, by)
     ctx.profile(False)
+    print("kernel-family timing done", file=sys.stderr, flush=True)
     # single-ciphertext latency: each run synchronised on its own
     lat = []
     for _ in range(args.latency_runs):
@@ -183,6 +211,7 @@ def main():
         gr.close()
         graph = {"runs": args.graph_runs, "eager_ms": round(te * 1e3, 3), "replay_ms": round(tg * 1e3, 3),
                  "replay_equals_eager": same}
+    print("latency and graph runs done", file=sys.stderr, flush=True)
     batched = None
     if args.extra_batch > 1:
         out2 = step(args.extra_batch)
@@ -201,6 +230,9 @@ def main():
     z = ctx.decrypt(out[0]).real
     mre = float(np.mean(np.abs(z - ref) / ref))
     out_level = out[0].level
+    gpu_sha = hashlib.sha256(np.ascontiguousarray(out[0].words(), dtype="<u8").tobytes()).hexdigest()
+    gpu_scale = float(out[0].scale).hex()
+    logqp = float(sum(np.log2(float(p)) for p in ctx.primes))
 
     # roofline of the NTT (the metric's kernel and the largest share of kernel
     # time: forward + inverse passes); the key switch is reported beside it
@@ -233,8 +265,9 @@ def main():
                                f"bootstrapping whenever levels run out ({n_bts} per ciphertext), "
                                f"x log-uniform in [2^-10,1], input level {args.level}",
                    "ring_degree": 65536, "slots": 32768, "batch": args.batch,
-                   "params": "log2 QP 1556: q0 60-bit, 10 x 40-bit, 13 x 52-bit (EvalMod/CoeffToSlot), "
-                             "7 x 60-bit special, dnum 3, h 192; l_afterBTS 7",
+                   "params": f"{PARAMS}: log2 QP {logqp:.0f}: q0 60-bit, {ctx.l_after + 3} x 40-bit, "
+                             f"{ctx.L - ctx.l_after - 3} x 52-bit (EvalMod/CoeffToSlot), 7 x 60-bit special, "
+                             f"dnum 3, h 192; l_afterBTS {ctx.l_after}",
                    "bootstraps_per_ct": n_bts, "output_level": out_level},
         "mre": mre,
         "latency": latency,
@@ -247,7 +280,12 @@ def main():
     if cpu_proc is not None:
         print("waiting for the CPU baseline (oracle, one ciphertext)", file=sys.stderr, flush=True)
         left = max(10.0, args.cpu_limit - (time.perf_counter() - t_start))
-        res["cpu_baseline"] = finish_cpu_baseline(cpu_proc, args, left)
+        res["cpu_baseline"], orc = finish_cpu_baseline(cpu_proc, args, left)
+        if orc is not None and args.batch >= 1:
+            res["parity_words_equal"] = bool(orc["sha256"] == gpu_sha and orc["level"] == out_level
+                                             and orc["scale"] == gpu_scale)
+            res["parity"] = {"what": "SHA-256 of the result words of ciphertext 0, GPU vs the oracle on the same "
+                                     "seeds", "gpu": gpu_sha[:16], "oracle": orc["sha256"][:16]}
     print(json.dumps(res), flush=True)
 
 

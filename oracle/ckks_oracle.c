@@ -1583,17 +1583,27 @@ int orc_cheb_coeffs_cosmod(int d, double K, double two_r, double *out) {
 
 /*
  * Chebyshev-basis evaluation by baby-step / giant-step (a reading: the paper
- * names only "ChebyshevApprox").  For degree d:
+ * names only "ChebyshevApprox"; it fixes the depth, §4.3: a degree-2^{d_e}-2
+ * polynomial consumes d_e levels, §3: degree 2^9-2 has depth 9).  For
+ * degree d:
  *   m = bit length of d, b = ceil(m/2);
  *   baby powers T_1..T_{2^b - 1}, giant powers T_{2^b}, T_{2^{b+1}}, ..., T_{2^{m-1}}
  *   T_{2k} = 2 T_k^2 - 1,  T_{2k+1} = 2 T_{k+1} T_k - T_1   (k >= 1), products
- *   taken on operands brought to the lower level (level_to) and rescaled.
- *   eval(p, k) for deg p < 2^k:  k <= b  -> baby linear combination;
- *     else M = 2^{k-1}; if deg < M recurse with k-1; else split
+ *   taken on operands brought to the lower level (level_to) and rescaled;
+ *   T_i then sits ceil(log2 i) levels below t.
+ *   eval(p, k, D) for deg p < 2^k, with a budget of D >= k levels below t:
+ *     leaf if k <= b and deg p <= 2^{D-1} (every T_i it combines is at most
+ *       D-1 levels down, and the combination takes one level): baby linear
+ *       combination;
+ *     else M = 2^{k-1}; if deg < M recurse with (k-1, D); else split
  *     p = q*T_M + r with q_0 = c_M, q_j = 2 c_{M+j} (j >= 1),
  *     r_i = c_i (i < M) then r_{M-j} = c_{M-j} - c_{M+j} (j >= 1);
- *     result = level-aligned (eval(q, k-1) * T_M) + eval(r, k-1).
- *   baby combination of c_0..c_t (t < 2^b): terms i >= 1 with c_i != 0 (if
+ *     result = level-aligned (eval(q, k-1, D-1) * T_M) + eval(r, k-1, D).
+ *   The whole polynomial is eval(p, m, m): only the leading quotient chain
+ *   has D = k, and it is split below the baby-step height down to degree 1
+ *   (its products by T_{2^j}, j < b, replace the baby combination that
+ *   would cost one level more), so the evaluation takes exactly m levels.
+ *   baby combination of c_0..c_t: terms i >= 1 with c_i != 0 (if
  *   none, i = 1 with coefficient 0.0); l_min = lowest level of those T_i;
  *   each T_i is dropped to l_min and multiplied by c_i at
  *   s_c = (S_{l_min - 1} * q_{l_min}) / scale(T_i); the products are summed
@@ -1664,10 +1674,10 @@ static orc_ct *baby_combo(orc_ctx *c, powtab *pt, const double *cf, int deg) {
     orc_ct_free(r);
     return r2;
 }
-static orc_ct *cheb_rec(orc_ctx *c, powtab *pt, const double *cf, int deg, int k, int b) {
-    if (k <= b) return baby_combo(c, pt, cf, deg);
+static orc_ct *cheb_rec(orc_ctx *c, powtab *pt, const double *cf, int deg, int k, int D, int b) {
+    if (k <= b && deg <= (1 << (D - 1))) return baby_combo(c, pt, cf, deg);
     int M = 1 << (k - 1);
-    if (deg < M) return cheb_rec(c, pt, cf, deg, k - 1, b);
+    if (deg < M) return cheb_rec(c, pt, cf, deg, k - 1, D, b);
     int dq = deg - M;
     double *qc = malloc(sizeof(double) * (dq + 1));
     double *rc = malloc(sizeof(double) * M);
@@ -1675,8 +1685,8 @@ static orc_ct *cheb_rec(orc_ctx *c, powtab *pt, const double *cf, int deg, int k
     for (int j = 1; j <= dq; j++) qc[j] = 2.0 * cf[M + j];
     for (int i = 0; i < M; i++) rc[i] = cf[i];
     for (int j = 1; j <= dq; j++) rc[M - j] = cf[M - j] - cf[M + j];
-    orc_ct *Q = cheb_rec(c, pt, qc, dq, k - 1, b);
-    orc_ct *R = Q ? cheb_rec(c, pt, rc, M - 1, k - 1, b) : NULL;
+    orc_ct *Q = cheb_rec(c, pt, qc, dq, k - 1, D - 1, b);
+    orc_ct *R = Q ? cheb_rec(c, pt, rc, M - 1, k - 1, D, b) : NULL;
     free(qc); free(rc);
     if (!Q || !R) { orc_ct_free(Q); orc_ct_free(R); return NULL; }
     orc_ct *TM = pw_get(c, pt, M);
@@ -1713,7 +1723,7 @@ orc_ct *orc_cheb_eval(orc_ctx *c, const orc_ct *x, const double *cf, int d, doub
     /* giant powers */
     for (int k = bb; k < m; k++) if (!pw_get(c, &pt, 1 << k)) goto fail;
     {
-        orc_ct *r = cheb_rec(c, &pt, cf, d, m, bb);
+        orc_ct *r = cheb_rec(c, &pt, cf, d, m, m, bb);
         for (int i = 1; i <= pt.maxT; i++) orc_ct_free(pt.T[i]);
         free(pt.T);
         return r;
@@ -1916,10 +1926,9 @@ static int floordiv(int a, int b) { int q = a / b; if ((a % b) != 0 && ((a < 0) 
  * to have cheb_depth(deg) + r levels.
  */
 /* levels the Chebyshev evaluation above consumes for degree d on [-1, 1]:
- * the baby powers T_1..T_{2^b - 1} take b levels (b >= 2), their scalar
- * combination one more, and each of the m - b giant products one: m + 1
- * with m = bitlen(d), except m <= 2 (a single baby power T_1): m */
-static int cheb_depth(int d) { int m = bitlen(d); return m >= 3 ? m + 1 : m; }
+ * the bit length of d (§4.3's d_e for degree 2^{d_e} - 2) */
+static int cheb_depth(int d) { return bitlen(d); }
+int orc_cheb_depth(int d) { return d >= 1 ? cheb_depth(d) : -1; }
 int orc_bts_config(orc_ctx *c, double Kp, int r, int deg) {
     if (c->n_evm <= 0) { set_err("chain has no bootstrapping levels"); return -1; }
     if (c->n_stc != 3 || c->n_cts != 3 || c->n_evm != cheb_depth(deg) + r || Kp <= 1 || r < 0 || deg < 2) {

@@ -85,6 +85,7 @@ def lib():
         "orc_conjugate": (vp, [vp, vp]),
         "orc_cheb_coeffs_invsqrt": (C.c_int, [C.c_int, C.c_double, C.c_double, dblp]),
         "orc_cheb_coeffs_cosmod": (C.c_int, [C.c_int, C.c_double, C.c_double, dblp]),
+        "orc_cheb_depth": (C.c_int, [C.c_int]),
         "orc_cheb_eval": (vp, [vp, vp, dblp, C.c_int, C.c_double, C.c_double]),
         "orc_newton_step": (vp, [vp, vp, vp]),
         "orc_newton_step_ex": (vp, [vp, vp, vp, C.c_int]),
@@ -175,6 +176,22 @@ class Context:
         lib().orc_ctx_info(self.ptr, _p(self.primes, u64p), _p(self.ladder, dblp))
         self.dnum = lib().orc_dnum(self.ptr)
         self.galois = []
+
+    @classmethod
+    def from_set(cls, name, bootstrapping=True):
+        """The named parameter set (the JSON data file of the library's
+        package: numbers only, the primes are generated here) with its
+        bootstrapping configured when it has one."""
+        import json
+        path = os.path.join(os.path.dirname(_HERE), "paper_2606_10477_amd", "params.json")
+        with open(path) as f:
+            s = json.load(f)[name]
+        o = cls(s["log_n"], s["max_level"], s["num_special"], s["digit_size"], h=s["hamming_weight"],
+                bts=tuple(s["bts"]) if "bts" in s else None)
+        if bootstrapping and "evalmod" in s:
+            e = s["evalmod"]
+            o.bts_config(float(e["K"]), int(e["r"]), int(e["degree"]))
+        return o
 
     def __del__(self):
         try:
@@ -388,6 +405,12 @@ def cheb_coeffs_invsqrt(d, a, b):
     if lib().orc_cheb_coeffs_invsqrt(d, a, b, _p(out, dblp)) != 0:
         raise OracleError("cheb coeffs")
     return out
+
+
+def cheb_depth(d):
+    """Levels the oracle's Chebyshev evaluation of degree d consumes (on
+    [-1, 1]; another interval adds the affine map's level)."""
+    return int(lib().orc_cheb_depth(d))
 
 
 def cheb_coeffs_cosmod(d, K, two_r):

@@ -222,6 +222,18 @@ class Context:
         self.ladder = np.zeros(self.L + 1)
         lib().ckks_ctx_primes(self.ptr, _p(self.primes, u64p), _p(self.ladder, dblp))
 
+    @classmethod
+    def from_set(cls, name, bootstrapping=True, **kw):
+        """A context on the named parameter set of params.json; on a
+        bootstrapping set its EvalMod is configured too (bootstrapping=True).
+        Keys still come from keygen."""
+        from . import params
+        ctx = cls(**params.context_kwargs(name), **kw)
+        ev = params.evalmod(name)
+        if bootstrapping and ev is not None:
+            ctx.bts_setup(*ev)
+        return ctx
+
     def close(self):
         if self.ptr:
             lib().ckks_ctx_destroy(self.ptr)

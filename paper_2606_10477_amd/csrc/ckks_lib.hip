@@ -1320,24 +1320,43 @@ bool baby_sums_together(ckks_ctx *c, PowerBasis &pb, const std::vector<std::vect
 // parts of one split are evaluated side by side): every tree's result is the
 // recursive split p = q T_M + r of the coefficients, computed op for op as
 // one tree alone would, with the products q T_M of all trees at one height
-// sharing launch sequences.
-std::vector<Ct> cheb_trees(ckks_ctx *c, PowerBasis &pb, const std::vector<std::vector<double>> &cfs, int k, int b) {
+// sharing launch sequences.  D[t] is tree t's level budget below T_1 (D >= k):
+// a tree ends in a baby-step sum when k <= b and its degree is at most
+// 2^(D-1) (each T_i it combines then sits at most D-1 levels down and the
+// sum takes one more); otherwise it is split by T_(2^(k-1)), the quotient
+// with budget D-1, the remainder with D.  Only the leading quotient chain of
+// a polynomial has D = k, so it alone is split below the baby-step height,
+// and degree d takes bit_length(d) levels (the depth the paper states).
+std::vector<Ct> cheb_trees(ckks_ctx *c, PowerBasis &pb, const std::vector<std::vector<double>> &cfs,
+                           const std::vector<int> &D, int k, int b) {
     const size_t n = cfs.size();
     std::vector<Ct> out(n);
-    if (k <= b) {
-        if (baby_sums_together(c, pb, cfs, out)) return out;
-        for (size_t t = 0; t < n; ++t) out[t] = baby_sum(c, pb, cfs[t]);
-        return out;
+    std::vector<size_t> leaf, rest;
+    for (size_t t = 0; t < n; ++t) {
+        const int deg = (int)cfs[t].size() - 1;
+        if (k <= b && deg <= (1 << (D[t] - 1))) leaf.push_back(t);
+        else rest.push_back(t);
     }
+    if (!leaf.empty()) {
+        std::vector<std::vector<double>> lc;
+        for (size_t t : leaf) lc.push_back(cfs[t]);
+        std::vector<Ct> lo(lc.size());
+        if (!baby_sums_together(c, pb, lc, lo))
+            for (size_t u = 0; u < lc.size(); ++u) lo[u] = baby_sum(c, pb, lc[u]);
+        for (size_t u = 0; u < leaf.size(); ++u) out[leaf[u]] = std::move(lo[u]);
+    }
+    if (rest.empty()) return out;
     const int M = 1 << (k - 1);
     std::vector<std::vector<double>> sub;
+    std::vector<int> subD;
     std::vector<int> qi(n, -1), ri(n, -1);
-    for (size_t t = 0; t < n; ++t) {
+    for (size_t t : rest) {
         const std::vector<double> &cf = cfs[t];
         const int deg = (int)cf.size() - 1;
         if (deg < M) {   // no split at this height
             ri[t] = (int)sub.size();
             sub.push_back(cf);
+            subD.push_back(D[t]);
             continue;
         }
         const int dq = deg - M;
@@ -1347,15 +1366,18 @@ std::vector<Ct> cheb_trees(ckks_ctx *c, PowerBasis &pb, const std::vector<std::v
         for (int j = 1; j <= dq; ++j) rc[M - j] = cf[M - j] - cf[M + j];
         qi[t] = (int)sub.size();
         sub.push_back(std::move(qc));
+        subD.push_back(D[t] - 1);
         ri[t] = (int)sub.size();
         sub.push_back(std::move(rc));
+        subD.push_back(D[t]);
     }
-    std::vector<Ct> S = cheb_trees(c, pb, sub, k - 1, b);
+    std::vector<Ct> S = cheb_trees(c, pb, sub, subD, k - 1, b);
     std::vector<std::pair<const ckks_ct *, const ckks_ct *>> pairs;
-    for (size_t t = 0; t < n; ++t)
+    for (size_t t : rest)
         if (qi[t] >= 0) pairs.emplace_back(S[qi[t]].get(), pb.get(M));
     std::vector<Ct> P = mult_aligned_many(c, pairs);
-    for (size_t t = 0, j = 0; t < n; ++t) {
+    size_t j = 0;
+    for (size_t t : rest) {
         if (qi[t] < 0) {
             out[t] = std::move(S[ri[t]]);
             continue;
@@ -1366,7 +1388,7 @@ std::vector<Ct> cheb_trees(ckks_ctx *c, PowerBasis &pb, const std::vector<std::v
     return out;
 }
 Ct cheb_tree(ckks_ctx *c, PowerBasis &pb, const std::vector<double> &cf, int k, int b) {
-    std::vector<Ct> r = cheb_trees(c, pb, {cf}, k, b);
+    std::vector<Ct> r = cheb_trees(c, pb, {cf}, {k}, k, b);
     return std::move(r[0]);
 }
 
@@ -1425,10 +1447,9 @@ Ct op_newton(ckks_ctx *c, const ckks_ct *y, const ckks_ct *half_x, bool raw_x) {
 // ---------------------------------------------------------------------------
 // Bootstrapping (ModRaise, CoeffToSlot, EvalMod, SlotToCoeff)
 // ---------------------------------------------------------------------------
-int cheb_depth(int d) {
-    const int m = bit_length(d);
-    return m >= 3 ? m + 1 : m;
-}
+// levels op_cheb consumes for degree d on [-1, 1] (another interval adds the
+// affine map's level): the bit length of d
+int cheb_depth(int d) { return bit_length(d); }
 
 void upload_signed_ntt(ckks_ctx *c, u64 *dst, const int64_t *src_host, int nlimb, const LimbMap &m);
 

@@ -78,7 +78,7 @@ def main(argv=None):
     import torch
     from . import ckks
     torch.cuda.set_device(0)
-    ctx = ckks.Context(log_n=16, max_level=7, num_special=7, digit_size=8, hamming_weight=192, bts=(3, 10, 3, 52))
+    ctx = ckks.Context.from_set("p16b", bootstrapping=False)
     rows = scan(ctx, [int(s) for s in a.limbs.split(",")], ctx.np_)
     r4, r8, best = choose(rows)
     res = {"r4_max_limbs": r4, "r8_max_limbs": r8, "fastest_words_per_thread": best, "rows": rows}

@@ -168,16 +168,14 @@ def summarize(requests):
             "mean_latency_s": float(lat.mean()), "ciphertexts_per_s": n_ct / span, "span_s": span}
 
 
-DEFAULT_TABLE = {"7": {"1e-06": {"degree": 31, "c": 0, "iters": 3}, "1e-07": {"degree": 31, "c": 0, "iters": 3},
+DEFAULT_TABLE = {"8": {"1e-06": {"degree": 31, "c": 0, "iters": 3}, "1e-07": {"degree": 31, "c": 0, "iters": 3},
                        "3.1e-08": {"degree": 31, "c": 0, "iters": 3}}}
-P16B = dict(log_n=16, max_level=7, num_special=7, digit_size=8, hamming_weight=192, bts=(3, 10, 3, 52))
-EVALMOD = (25.0, 4, 31)
 
 
 def main(argv=None):
     """Serving sweep at N = 2^16 on the bootstrapping parameter set (relin,
     rotation and conjugation keys resident): Poisson arrivals at each rate,
-    request sizes Geometric(0.25) truncated to [1, 32], levels in [3, 7] and
+    request sizes Geometric(0.25) truncated to [1, 32], levels in [5, 8] and
     MRE targets drawn per request; continuous batching versus one request at a
     time."""
     import argparse
@@ -190,7 +188,7 @@ def main(argv=None):
     ap = argparse.ArgumentParser()
     ap.add_argument("--rates", default="10,40,160")
     ap.add_argument("--requests", type=int, default=48)
-    ap.add_argument("--levels", default="5,6,7", help="input levels (those the tuning table can serve)")
+    ap.add_argument("--levels", default="5,6,7,8", help="input levels (those the tuning table can serve)")
     ap.add_argument("--table", default=os.path.join(os.path.dirname(os.path.abspath(__file__)), "tuning_mi355x_bts.json"),
                     help="tuning JSON from paper_2606_10477_amd.tune")
     ap.add_argument("--max-batch", type=int, default=16,
@@ -202,8 +200,7 @@ def main(argv=None):
         with open(args.table) as f:
             table = json.load(f)["table"]
     torch.cuda.set_device(0)
-    ctx = ckks.Context(**P16B)
-    ctx.bts_setup(*EVALMOD)
+    ctx = ckks.Context.from_set("p16b")
     ctx.keygen(9, ctx.bts_galois())
     levels = [int(v) for v in args.levels.split(",")]
     out = {"workload": "CryptoInvSqrt serving at N=2^16 with bootstrapping keys resident, Poisson arrivals, "

@@ -23,10 +23,6 @@ import time
 
 import numpy as np
 
-P16B = dict(log_n=16, max_level=7, num_special=7, digit_size=8, hamming_weight=192, bts=(3, 10, 3, 52))
-# the plain set: no bootstrapping, 27 computation levels of 40 bits
-P16 = dict(log_n=16, max_level=27, num_special=7, digit_size=10, hamming_weight=192)
-EVALMOD = (25.0, 4, 31)
 
 
 def run(levels, degrees, iters, targets, lo, hi, batch, reps, fixed, tuner_seed=777, quiet=False, domain="logu",
@@ -39,9 +35,7 @@ def run(levels, degrees, iters, targets, lo, hi, batch, reps, fixed, tuner_seed=
     torch.cuda.set_device(0)
     t_start = time.perf_counter()
     bts = params == "bts"
-    ctx = ckks.Context(**(P16B if bts else P16))
-    if bts:
-        ctx.bts_setup(*EVALMOD)
+    ctx = ckks.Context.from_set("p16b" if bts else "p16")   # plain set: 27 levels, no bootstrapping
     ctx.keygen(tuner_seed, ctx.bts_galois() if bts else [])      # the tuner's own keys, not a client's
     if domain == "paper":
         # the paper's own workload (§5.1): linspace over [0.001, 100], pre-normalised by B = 100
@@ -89,7 +83,7 @@ def run(levels, degrees, iters, targets, lo, hi, batch, reps, fixed, tuner_seed=
     err = [abs(r["t_pred"] - r["t"]) / r["t"] for r in ok]
     report = {
         "params": ("N=2^16, log2 QP 1556: q0 60-bit, 10 x 40-bit, 13 x 52-bit, 7 x 60-bit special, dnum 3, h 192; "
-                   "l_BTS 0, l_afterBTS = l_max 7") if bts else
+                   "l_BTS 0, l_afterBTS = l_max 8") if bts else
                   "N=2^16, q0 60-bit + 27 x 40-bit, 7 x 60-bit special, dnum 3, h 192; no bootstrapping",
         "input": (f"x = linspace(0.001, 100, N/2) / 100 (B = 100), interval [{lo}, {hi}], encrypted at scale 2^50"
                   if domain == "paper" else f"x log-uniform in [{lo}, {hi}], encrypted at scale 2^50"),
@@ -110,7 +104,7 @@ def run(levels, degrees, iters, targets, lo, hi, batch, reps, fixed, tuner_seed=
 def main(argv=None):
     ap = argparse.ArgumentParser()
     ap.add_argument("--out", default="tuning_report.json")
-    ap.add_argument("--levels", default="3,4,5,6,7")
+    ap.add_argument("--levels", default="3,4,5,6,7,8")
     ap.add_argument("--degrees", default="7,15,31,63,127")
     ap.add_argument("--iters", default="1,2,3,4,5,6")
     ap.add_argument("--targets", default="1e-6,1e-7,3.1e-8")
@@ -120,7 +114,7 @@ def main(argv=None):
                     help="logu: x log-uniform in [2^-10, 1]; paper: linspace(0.001, 100) / 100 on [1e-5, 1]")
     ap.add_argument("--fixed", default="31,3", help="fixed (degree, iterations) the tuned choice is compared with")
     ap.add_argument("--params", choices=["bts", "plain"], default="bts",
-                    help="bts: the bootstrapping set (levels 3-7); plain: 27 levels, no bootstrapping "
+                    help="bts: the bootstrapping set (levels 3-8); plain: 27 levels, no bootstrapping "
                          "(use e.g. --levels 13,17,21,27)")
     args = ap.parse_args(argv)
     ints = lambda s: [int(v) for v in s.split(",")]

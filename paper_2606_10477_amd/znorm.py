@@ -120,7 +120,7 @@ def main(argv=None):
     ap.add_argument("--out", default=None)
     args = ap.parse_args(argv)
     torch.cuda.set_device(0)
-    ctx = ckks.Context(log_n=16, max_level=27, num_special=7, digit_size=10, hamming_weight=192)
+    ctx = ckks.Context.from_set("p16")
     ctx.keygen(9, [ctx.galois_rot(s) for s in rotation_steps(ctx.n)])
     per = args.rows // ctx.n
     data, _, _ = inputs.column_table(args.rows, args.cols, 21)

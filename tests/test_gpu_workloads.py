@@ -105,10 +105,40 @@ def test_znorm_batched_bit_exact_vs_oracle(small):
     assert np.max(np.abs(zz - ref)) < 1e-4
 
 
+def _oracle_mean(o, cts, rows):
+    """mean over all slots of a column's ciphertexts: sum the ciphertexts,
+    rotate-and-sum over the slots, times 2^-log2(rows) as an exact integer
+    plaintext at scale 2^40 and one rescale."""
+    s = cts[0]
+    for c in cts[1:]:
+        s = o.add(s, c)
+    k = 1
+    while k < o.n:
+        s = o.add(s, o.rotate(s, k))
+        k <<= 1
+    return o.rescale(o.mul_const(s, 2.0 ** -int(math.log2(rows)), 2.0 ** 40))
+
+
+def _oracle_skew_kurt(o, z, rows):
+    """Population skewness mean(z^3) and excess kurtosis mean(z^4) - 3 of one
+    column's z-scores, on the oracle, written here from the definitions."""
+    z2 = [o.rescale(o.hmult(v, v)) for v in z]
+    z3 = [o.rescale(o.hmult(a, o.level_to(v, a.level))) for a, v in zip(z2, z)]
+    z4 = [o.rescale(o.hmult(a, a)) for a in z2]
+    return _oracle_mean(o, z3, rows), o.add_const(_oracle_mean(o, z4, rows), -3.0)
+
+
+def _oracle_pcc(o, za, zb, rows):
+    """Pearson correlation mean(z_a z_b) of two columns' z-scores."""
+    return _oracle_mean(o, [o.rescale(o.hmult(a, b)) for a, b in zip(za, zb)], rows)
+
+
 def test_moments_batched_bit_exact_vs_oracle(small):
     """Skewness, excess kurtosis and PCC (from the z-scores) of 3 skewed,
-    pairwise-correlated columns, batched on the GPU, against the oracle run
-    column by column (pair by pair), word for word; values against FP64."""
+    pairwise-correlated columns, batched on the GPU (moments.py), against the
+    oracle run column by column (pair by pair) through the composition
+    written in this file from the definitions, word for word; values
+    against FP64."""
     from paper_2606_10477_amd import moments, znorm
     g, o = small
     cols, per = 3, 2
@@ -127,12 +157,12 @@ def test_moments_batched_bit_exact_vs_oracle(small):
     gs, gk = moments.skew_kurt(g, gz, rows)
     gp = moments.pcc(g, gz, rows, pairs)
     for c in range(cols):
-        os_, ok = moments.skew_kurt(o, [oz[c]], rows)
-        assert np.array_equal(gs[c].words(), os_[0].words()), f"skewness column {c}"
-        assert np.array_equal(gk[c].words(), ok[0].words()), f"kurtosis column {c}"
+        os_, ok = _oracle_skew_kurt(o, oz[c], rows)
+        assert np.array_equal(gs[c].words(), os_.words()), f"skewness column {c}"
+        assert np.array_equal(gk[c].words(), ok.words()), f"kurtosis column {c}"
     for k, (a, b) in enumerate(pairs):
-        op = moments.pcc(o, [oz[a], oz[b]], rows, [(0, 1)])
-        assert np.array_equal(gp[k].words(), op[0].words()), f"pcc pair {a, b}"
+        op = _oracle_pcc(o, oz[a], oz[b], rows)
+        assert np.array_equal(gp[k].words(), op.words()), f"pcc pair {a, b}"
     rs, rk, rp = moments.reference(data, pairs)
     for c in range(cols):
         assert abs(g.decrypt(gs[c]).real[0] - rs[c]) < 1e-4
@@ -167,7 +197,7 @@ def test_znorm_full_size_accuracy():
     invsqrt (127, 3) on the variance domain [2^-14, 1]: z-scores against FP64."""
     ck = _ck()
     from paper_2606_10477_amd import znorm
-    g = ck.Context(log_n=16, max_level=27, num_special=7, digit_size=10, hamming_weight=192)
+    g = ck.Context.from_set("p16")
     g.keygen(9, [g.galois_rot(s) for s in znorm.rotation_steps(g.n)])
     cols, per = 4, 4
     rows = per * g.n

@@ -19,7 +19,7 @@ import pytest
 
 from paper_2606_10477_amd import inputs
 
-BTS = (3, 10, 3, 52)
+BTS = (3, 9, 3, 52)
 
 
 @pytest.fixture(scope="module")
@@ -32,7 +32,7 @@ def o8(oracle_mod):
 
 @pytest.fixture(scope="module")
 def o10(oracle_mod):
-    o = oracle_mod.Context(10, 7, 2, 2, h=192, bts=BTS)
+    o = oracle_mod.Context(10, 8, 2, 2, h=192, bts=BTS)
     o.bts_config(25.0, 4, 31)
     o.keygen(4, o.bts_galois())
     return o
@@ -42,17 +42,17 @@ def test_bootstrapping_chain_shape(o10):
     o = o10
     bits = [int(p).bit_length() for p in o.primes]
     N = o.N
-    assert o.L == 7 + 16
+    assert o.L == 8 + 15
     assert bits[0] == 60
-    assert all(40 <= b <= 41 for b in bits[1:11])          # computation + SlotToCoeff
-    assert all(52 <= b <= 53 for b in bits[11:24])         # EvalMod + CoeffToSlot
+    assert all(40 <= b <= 41 for b in bits[1:12])          # computation + SlotToCoeff
+    assert all(52 <= b <= 53 for b in bits[12:24])         # EvalMod + CoeffToSlot
     assert len(set(int(p) for p in o.primes)) == len(o.primes)
     assert all(int(p) % (2 * N) == 1 for p in o.primes)
     # canonical scales: ~2^40 on the computation levels, ~2^52 on EvalMod
-    assert np.all(np.abs(np.log2(o.ladder[:8]) - 40) < 1e-3)
-    assert np.all(np.abs(np.log2(o.ladder[10:21]) - 52) < 1e-3)
+    assert np.all(np.abs(np.log2(o.ladder[:9]) - 40) < 1e-3)
+    assert np.all(np.abs(np.log2(o.ladder[11:21]) - 52) < 1e-3)
     with pytest.raises(Exception):
-        o.bts_config(25.0, 3, 31)                           # depth 6 + 3 != 10 EvalMod levels
+        o.bts_config(25.0, 3, 31)                           # depth 5 + 3 != 9 EvalMod levels
 
 
 def _exact_plain(o, ct):
@@ -160,10 +160,12 @@ def test_invsqrt_with_lazy_bootstrap(o10):
     o = o10
     lo, hi = 2.0 ** -10, 1.0
     x = inputs.log_uniform(o.n, lo, hi, 4)
-    ct = o.encrypt(x, 7, 2.0 ** 50, 9)
+    ct = o.encrypt(x, 8, 2.0 ** 50, 9)
     y = o.invsqrt(ct, 31, 3, lo, hi)
     ref = 1 / np.sqrt(x)
-    assert y.level == 0
+    # 8 -> affine 7 -> Chebyshev (5 levels) 2 -> Newton 0 -> BTS 8 -> Newton
+    # (x/2 at 7) 5 -> last Newton (x at 8) 3
+    assert y.level == 3
     assert np.mean(np.abs(o.decrypt(y).real - ref) / ref) < 1e-7
 
 
@@ -181,3 +183,96 @@ def test_hoisted_rotations_roll_the_slots(o8):
         assert np.max(np.abs(o.decrypt(r).real - np.roll(x, -k))) < 1e-6
         plain = o.decrypt(o.rotate(ct, k)).real
         assert np.max(np.abs(o.decrypt(r).real - plain)) < 1e-6
+
+
+def _plain_chain(x, cf, lo, hi, iters):
+    """FP64 CryptoInvSqrt: Chebyshev value of the same coefficients, then the
+    Newton iteration of §2.2 (no encryption)."""
+    t = (2 * x - lo - hi) / (hi - lo)
+    y = np.polynomial.chebyshev.chebval(t, cf)
+    for _ in range(iters):
+        y = 0.5 * y * (3 - x * y * y)
+    return y
+
+
+def test_invsqrt_literal_branch(oracle_mod, o10):
+    """Alg. 1 as printed bootstraps y0 right after the Chebyshev step (its
+    line 4).  From level 8 with degree 15: y0 at 8 - 1 - 4 = 3 is
+    bootstrapped to 8, then the three Newton steps run at 7, 5 and 3 (the
+    last one on x itself at 8), ending at 1 -- two levels lower than the lazy
+    schedule (no bootstrap until a step lacks levels, ending at 3).  The
+    result follows the FP64 chain: the bootstrap's error in y0 (~1e-4 at
+    message bound 512) is squared away by the Newton steps."""
+    o = o10
+    lo, hi = 2.0 ** -10, 1.0
+    x = inputs.log_uniform(o.n, lo, hi, 21)
+    ct = o.encrypt(x, 8, 2.0 ** 50, 22)
+    cf = oracle_mod.cheb_coeffs_invsqrt(15, lo, hi)
+    lit = o.invsqrt(ct, 15, 3, lo, hi, literal=True)
+    lazy = o.invsqrt(ct, 15, 3, lo, hi)
+    assert lit.level == 1 and lazy.level == 3
+    plain = _plain_chain(x, cf, lo, hi, 3)
+    ref = 1 / np.sqrt(x)
+    mre_plain = np.mean(np.abs(plain - ref) / ref)     # degree 15, 3 steps: ~1.4e-4 in FP64
+    for y in (lit, lazy):
+        z = o.decrypt(y).real
+        assert np.max(np.abs(z - plain) / ref) < 1e-5
+        assert abs(np.mean(np.abs(z - ref) / ref) - mre_plain) < 0.01 * mre_plain
+
+
+def test_invsqrt_pre_bts_branch(oracle_mod, o10):
+    """Pre-BTS (§4.2's c = 1): x is bootstrapped first (message bound
+    16 ceil(b)) and the whole chain -- the Chebyshev step, ct_x and the last
+    step's x -- then runs on the bootstrapped x~.  So the result is the FP64
+    chain applied to x~ (the decrypted bootstrap of x, computed separately),
+    up to the chain's own noise, while against 1/sqrt(x) it carries x~'s error
+    (the Pre-BTS floor).  Forced by the level (5 < depth 5 + 1 for degree 31)
+    and asked for at level 8; the bootstrapped x sits at l_afterBTS = 8."""
+    o = o10
+    lo, hi = 2.0 ** -10, 1.0
+    x = inputs.log_uniform(o.n, lo, hi, 23)
+    for level, ask, d, it in ((5, False, 31, 2), (8, True, 15, 3)):
+        ct = o.encrypt(x, level, 2.0 ** 50, 24 + level)
+        y = o.invsqrt(ct, d, it, lo, hi, pre_bts=ask)
+        xb = o.decrypt(o.bootstrap(ct, 16)).real
+        cf = oracle_mod.cheb_coeffs_invsqrt(d, lo, hi)
+        want = _plain_chain(xb, cf, lo, hi, it)
+        z = o.decrypt(y).real
+        ref = 1 / np.sqrt(x)
+        assert np.max(np.abs(z - want) / ref) < 1e-5
+        # the floor: x~'s relative error passes to 1/sqrt as half of it
+        floor = np.mean(np.abs(xb - x) / x) / 2
+        assert np.mean(np.abs(z - ref) / ref) < 4 * floor + 1e-6
+        assert np.mean(np.abs(z - ref) / ref) > floor / 4
+
+
+def _bitrev_idx(n):
+    b = n.bit_length() - 1
+    return np.array([int(format(i, '0%db' % b)[::-1], 2) for i in range(n)])
+
+
+def test_slot_to_coeff_is_the_packing(o8):
+    """SlotToCoeff of a fresh ciphertext with slots w (at the EvalMod output
+    level l_afterBTS + 3) yields the polynomial whose coefficients k' = br(k)
+    and br(k) + n hold Re(w_k) and Im(w_k) (the inverse of CoeffToSlot's
+    packing, pinned in test_mod_raise_invariant_and_coeff_to_slot) times the
+    constant q_0 / (2 pi s_0) = 2^5 / (2 pi) that SlotToCoeff absorbs (the
+    sine's 1/(2 pi) and the content scale s_0 = q_0 2^-5 of a unit message).
+    Checked on the decrypted coefficients (numpy, no transform)."""
+    o = o8
+    rng = np.random.default_rng(8)
+    n, N = o.n, o.N
+    wr, wi = rng.uniform(-1, 1, n), rng.uniform(-1, 1, n)
+    lv = o.l_after + 3
+    cr = o.encrypt(wr, lv, o.ladder[lv], 31)
+    ci = o.encrypt(wi, lv, o.ladder[lv], 32)
+    w = o.add(cr, o.mul_monomial(ci, N // 2))
+    z = o.slot_to_coeff(w)
+    assert z.level == o.l_after
+    m = o.decrypt_coeffs(z) / z.scale
+    br = _bitrev_idx(n)
+    want = np.zeros(N)
+    want[br] = wr
+    want[br + n] = wi
+    want *= 2.0 ** 5 / (2 * np.pi)
+    assert np.max(np.abs(m - want)) < 1e-6

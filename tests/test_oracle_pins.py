@@ -459,15 +459,55 @@ def test_cheb_eval_encrypted(oracle_mod, p12):
     for d in (7, 15):
         cf = oracle_mod.cheb_coeffs_invsqrt(d, 2 ** -8, 1.0)
         y = p12.cheb_eval(ct, cf, 2 ** -8, 1.0)
-        m = d.bit_length()
-        assert y.level == 13 - 1 - (m + 1)
+        assert y.level == 13 - 1 - d.bit_length()
         ref = _plain_chain(x, cf, 2 ** -8, 1.0, 0)[0]
         assert np.max(np.abs(p12.decrypt(y).real - ref)) < 1e-5
     # a [-1, 1] polynomial with a zero coefficient block skips the affine step
     cf = np.array([0.25, 0.0, -0.5, 0.0, 0.125])
     t = p12.encrypt(np.linspace(-1, 1, p12.n), 13, 2.0 ** 40, 5)
     y = p12.cheb_eval(t, cf, -1.0, 1.0)
+    assert y.level == 13 - 3
     assert np.max(np.abs(p12.decrypt(y).real - np.polynomial.chebyshev.chebval(np.linspace(-1, 1, p12.n), cf))) < 1e-6
+
+
+@pytest.mark.parametrize("d_e", [4, 5, 6, 7])
+def test_cheb_depth_is_the_papers(oracle_mod, p12, d_e):
+    """§4.3: a Chebyshev polynomial of degree 2^{d_e} - 2 consumes d_e levels
+    (§3: degree 2^9 - 2 has depth 9); with the affine map to [-1, 1] (the
+    one scaling level) the output sits d_e + 1 levels below the input.
+    Values against numpy's chebval of the same coefficients, within the
+    noise of scale 2^40 (|y| <= 16 on [2^-8, 1])."""
+    a, b = 2.0 ** -8, 1.0
+    x = inputs.log_uniform(p12.n, a, b, 2)
+    ct = p12.encrypt(x, 13, 2.0 ** 50, 4)
+    t = (2 * x - a - b) / (b - a)
+    for d in (2 ** d_e - 2, 2 ** d_e - 1):
+        assert oracle_mod.cheb_depth(d) == d_e
+        cf = oracle_mod.cheb_coeffs_invsqrt(d, a, b)
+        y = p12.cheb_eval(ct, cf, a, b)
+        assert y.level == 13 - 1 - d_e
+        ref = np.polynomial.chebyshev.chebval(t, cf)
+        assert np.max(np.abs(p12.decrypt(y).real - ref)) < 1e-5
+
+
+def test_cheb_eval_sparse_and_odd_coefficients(oracle_mod, p12):
+    """Coefficient patterns that change which leaves the tree combines
+    (zero leading blocks, odd-only, a lone top coefficient) still evaluate
+    to chebval of the same coefficients at the stated depth."""
+    u = np.linspace(-1, 1, p12.n)
+    ct = p12.encrypt(u, 12, p12.ladder[12], 6)
+    rng = np.random.default_rng(5)
+    for cf in (np.r_[np.zeros(31), 0.5],                                  # T_31 alone
+               np.where(np.arange(32) % 2 == 1, rng.uniform(-0.2, 0.2, 32), 0.0),   # odd
+               np.r_[rng.uniform(-0.2, 0.2, 8), np.zeros(8), rng.uniform(-0.2, 0.2, 16)],
+               np.r_[rng.uniform(-0.2, 0.2, 17)]):                        # degree 16 = 2^4
+        d = len(cf) - 1
+        y = p12.cheb_eval(ct, cf, -1.0, 1.0)
+        assert y.level == 12 - d.bit_length()
+        # the input's encryption noise (~1e-7 at scale 2^40) is amplified by
+        # |p'| <= sum k^2 |c_k| (Markov's inequality for T_k)
+        tol = 1e-6 + 1e-7 * float(np.sum(np.arange(d + 1) ** 2 * np.abs(cf)))
+        assert np.max(np.abs(p12.decrypt(y).real - np.polynomial.chebyshev.chebval(u, cf))) < tol
 
 
 def test_invsqrt_small_ring_matches_plain_chain(oracle_mod, p12):
@@ -475,7 +515,7 @@ def test_invsqrt_small_ring_matches_plain_chain(oracle_mod, p12):
     x = inputs.log_uniform(p12.n, 2 ** -8, 1.0, 1)
     ct = p12.encrypt(x, 13, 2.0 ** 50, 3)
     y = p12.invsqrt(ct, 15, 2, 2 ** -8, 1.0)
-    assert y.level == 13 - 1 - 5 - 2 - 2
+    assert y.level == 13 - 1 - 4 - 2 - 2
     z = p12.decrypt(y).real
     cf = oracle_mod.cheb_coeffs_invsqrt(15, 2 ** -8, 1.0)
     plain = _plain_chain(x, cf, 2 ** -8, 1.0, 2)[-1]
