@@ -184,6 +184,33 @@ ckks_status ckks_level_to(ckks_ctx *ctx, const ckks_ct *a, uint32_t level, ckks_
 ckks_status ckks_rescale(ckks_ctx *ctx, const ckks_ct *a, ckks_ct **out);
 /* Mul_C with relinearisation (hybrid key switching), no rescale; scale s_a s_b. */
 ckks_status ckks_hmult_relin(ckks_ctx *ctx, const ckks_ct *a, const ckks_ct *b, ckks_ct **out);
+
+/*
+ * For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid allocation): the
+ * product of ckks_hmult_relin, word for word, written to caller memory and
+ * computed with every temporary in a fixed array of the library,
+ * CKKS_SCRATCH_BYTES of device memory on each GPU the library runs on (held
+ * until the process ends).  Nothing is allocated: no hipMalloc, no pool, no
+ * tables (ckks_keygen builds every level's key-switching tables).
+ *   out        device memory of the context's GPU receiving [B][2][l+1][N]
+ *              words (B = a's ciphertext count, l = a's level), owned by the
+ *              caller; out_scale (host) receives scale(a) * scale(b).
+ * Errors: CKKS_E_PARAM when the product needs more scratch than
+ * CKKS_SCRATCH_BYTES (at N = 2^16 and K = 7 one ciphertext fits at every
+ * level up to 23 with digits of 8 primes and up to 26 with digits of 10:
+ * 227 and 251 limbs of 512 KiB; level 27 with digits of 10 would need 259)
+ * -- nothing is launched
+ * then; CKKS_E_NOKEY, CKKS_E_LEVEL as ckks_hmult_relin; CKKS_E_DEVICE when
+ * the current device is not the context's.  Every call on one GPU shares that
+ * GPU's array (it keeps the last call's contents; each call writes every word
+ * it reads, so none needs clearing): calls that can overlap on one GPU --
+ * contexts on different streams without synchronisation between them --
+ * race, and must be serialised by the caller.
+ */
+#define CKKS_SCRATCH_BYTES ((size_t)128 << 20)
+ckks_status ckks_hmult_relin_noalloc(ckks_ctx *ctx, const ckks_ct *a, const ckks_ct *b, uint64_t *out,
+                                     double *out_scale);
 /* Left rotation of the slots by `steps` (automorphism X -> X^(5^steps) and
  * key switch; CKKS_E_NOKEY without the Galois key). */
 ckks_status ckks_rotate(ckks_ctx *ctx, const ckks_ct *a, int32_t steps, ckks_ct **out);

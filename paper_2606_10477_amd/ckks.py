@@ -66,6 +66,7 @@ SIGNATURES = {
     "ckks_level_to": (C.c_int, [vp, vp, C.c_uint32, C.POINTER(vp)]),
     "ckks_rescale": (C.c_int, [vp, vp, C.POINTER(vp)]),
     "ckks_hmult_relin": (C.c_int, [vp, vp, vp, C.POINTER(vp)]),
+    "ckks_hmult_relin_noalloc": (C.c_int, [vp, vp, vp, vp, dblp]),
     "ckks_rotate": (C.c_int, [vp, vp, C.c_int32, C.POINTER(vp)]),
     "ckks_conjugate": (C.c_int, [vp, vp, C.POINTER(vp)]),
     "ckks_rotate_hoisted": (C.c_int, [vp, vp, i32p, C.c_uint32, C.POINTER(vp)]),
@@ -315,6 +316,13 @@ class Context:
 
     def hmult(self, a, b):
         return self._ct(lib().ckks_hmult_relin, a.ptr, b.ptr)
+
+    def hmult_noalloc(self, a, b, out_ptr):
+        """ckks_hmult_relin_noalloc: the product's words into the device memory
+        at out_ptr ([B][2][level+1][N] uint64, caller-owned); returns the scale."""
+        sc = C.c_double()
+        self._chk(lib().ckks_hmult_relin_noalloc(self.ptr, a.ptr, b.ptr, C.c_void_p(out_ptr), C.byref(sc)))
+        return sc.value
 
     def rotate(self, a, k):
         return self._ct(lib().ckks_rotate, a.ptr, k)

@@ -14,6 +14,7 @@
 #include <functional>
 #include <map>
 #include <memory>
+#include <mutex>
 #include <set>
 #include <stdexcept>
 #include <string>
@@ -252,6 +253,8 @@ struct ckks_ctx {
     std::string trace;
     std::map<std::string, ProfFamily> prof;
     std::vector<hipEvent_t> ev_free;
+    int device = 0;               // the GPU the context was created on
+    u64 *scratch = nullptr;       // that GPU's scratch array (entry point that allocates nothing)
     u64 words(int level) const { return (u64)2 * (level + 1) * N; }
     ~ckks_ctx();
 };
@@ -706,41 +709,70 @@ Ct op_rescale(ckks_ctx *c, const ckks_ct *a) {
     return r;
 }
 
+// Device temporaries of a key switch: taken from the context's pool, or
+// (the entry point that allocates nothing) carved in order from a fixed
+// region, with mark / release for regions whose contents are dead.
+struct Carver {
+    u64 *base = nullptr;
+    size_t cap = 0, used = 0;   // words
+    u64 *take(size_t words) {
+        const size_t w = (words + 31) & ~(size_t)31;   // 256-byte aligned pieces
+        if (used + w > cap) fail(CKKS_E_PARAM, "scratch array too small for this operation");
+        u64 *p = base + used;
+        used += w;
+        return p;
+    }
+};
+// a temporary of `words` words: pool memory, or a non-owning piece of cv
+Buf temp(ckks_ctx *c, Carver *cv, size_t words) {
+    if (!cv) return Buf(c->pool.get(), words);
+    Buf b;
+    b.p = cv->take(words);
+    b.bytes = words * 8;
+    return b;
+}
+
 // ModUp of nct polynomials d (level l, NTT form; ciphertext b's polynomial
 // at d + b * d_stride): per digit j the base conversion of the digit's limbs
 // to the other primes of Q_l and P, NTT form.  The digits' own limbs stay in
 // d (read in place by the inner product).
 struct ModUp {
     int l = 0, nct = 0;
-    std::vector<Buf> ext;
+    Buf ext[gpu::kMaxDigits];
     gpu::InnerArgs ia{};
 };
-void modup(ckks_ctx *c, int l, const u64 *d, size_t d_stride, int nct, ModUp &mu) {
+// the conversion tables of a level must exist already (no device allocation)
+void need_tables(ckks_ctx *c, int l) {
+    const int beta = (l + 1 + c->alpha - 1) / c->alpha;
+    for (int j = 0; j < beta; ++j)
+        if (c->modup.find(std::make_pair(l, j)) == c->modup.end())
+            fail(CKKS_E_PARAM, "key-switching tables of this level are not built (ckks_keygen builds them)");
+    if (c->moddown.find(l) == c->moddown.end())
+        fail(CKKS_E_PARAM, "key-switching tables of this level are not built (ckks_keygen builds them)");
+}
+void modup(ckks_ctx *c, int l, const u64 *d, size_t d_stride, int nct, ModUp &mu, Carver *cv = nullptr) {
     const size_t N = c->N;
     const int nq = l + 1, ne = nq + c->K;
     const int beta = (nq + c->alpha - 1) / c->alpha;
-    Pool *P = c->pool.get();
     mu.l = l;
     mu.nct = nct;
-    Buf dc(P, (size_t)nct * nq * N);
+    Buf dc = temp(c, cv, (size_t)nct * nq * N);
     ntt_oop_p(c, dc.p, d, d_stride, nq, nct, map_q(0, nq), true);
-    mu.ext.clear();
-    mu.ext.reserve(beta);
     gpu::InnerArgs &ia = mu.ia;
     ia = gpu::InnerArgs{};
     ia.ndig = beta;
     ia.nct = nct;
     for (int j = 0; j < beta; ++j) {
         ConvTable *t = modup_table(c, l, j);
-        mu.ext.emplace_back(P, (size_t)nct * t->dout * N);
+        mu.ext[j] = temp(c, cv, (size_t)nct * t->dout * N);
         gpu::BconvArgs ba{t->pin, t->pout, t->din, t->dout, t->hinv.p, t->hinv_sh.p, t->mat.p, t->split};
         const int lo = j * c->alpha;
-        gpu::bconv(c->T, mu.ext.back().p, dc.p + (size_t)lo * N, ba, nct, (size_t)nq * N, (size_t)t->dout * N,
+        gpu::bconv(c->T, mu.ext[j].p, dc.p + (size_t)lo * N, ba, nct, (size_t)nq * N, (size_t)t->dout * N,
                    c->stream);
-        ntt_p(c, mu.ext.back().p, t->dout, nct, t->pout, false);
+        ntt_p(c, mu.ext[j].p, t->dout, nct, t->pout, false);
         ia.lo[j] = lo;
         ia.hi[j] = lo + t->din;
-        ia.ext[j] = mu.ext.back().p;
+        ia.ext[j] = mu.ext[j].p;
         ia.ext_stride[j] = (size_t)t->dout * N;
     }
     ia.dsrc = d;
@@ -749,6 +781,36 @@ void modup(ckks_ctx *c, int l, const u64 *d, size_t d_stride, int nct, ModUp &mu
     ia.m = map_ext(c, l);
     ia.ne = ne;
     ia.perm = nullptr;
+}
+// ModDown by P of the accumulators acc ([nct][2][ne][N], NTT form over Q_l
+// and P): out ([nct][2][l+1][N]) receives (acc - Conv_P(acc)) P^-1 plus
+// add[b][p] for the polys p selected by add_mask.  y ([2 nct][K][N]) and z
+// ([2 nct][l+1][N]) are its temporaries.
+void ks_moddown(ckks_ctx *c, int l, int nct, const u64 *acc, u64 *out, const u64 *add, int add_mask, u64 *y,
+                u64 *z) {
+    const size_t N = c->N;
+    const int nq = l + 1, ne = nq + c->K;
+    ConvTable *md = moddown_table(c, l);
+    const int np2 = 2 * nct;
+    ntt_oop_p(c, y, acc + (size_t)nq * N, (size_t)ne * N, c->K, np2, md->pin, true);
+    gpu::BconvArgs bd{md->pin, md->pout, md->din, md->dout, md->hinv.p, md->hinv_sh.p, md->mat.p, md->split};
+    gpu::bconv(c->T, z, y, bd, np2, (size_t)c->K * N, (size_t)nq * N, c->stream);
+    if (c->logN == 16) {
+        // (acc - z) P^-1 (+ add) fused into the transform's last pass
+        gpu::NttEpi ep{out, acc, (size_t)ne * N, c->d_pinv.p, c->d_pinvsh.p, add, add_mask};
+        ProfScope ps(c, "ntt", 16.0 * (double)nq * np2 * N);
+        gpu::ntt16_fwd_fused(c->T, z, nullptr, &ep, nq, np2, map_q(0, nq), c->stream);
+        return;
+    }
+    ntt_p(c, z, nq, np2, map_q(0, nq), false);
+    LimbConsts pinv{};
+    for (int i = 0; i < nq; ++i) {
+        u64 pm = 1 % c->q[i];   // P mod q_i
+        for (int k = 0; k < c->K; ++k) pm = hm::mulmod(pm, c->q[c->L + 1 + k] % c->q[i], c->q[i]);
+        pinv.v[i] = hm::invmod(pm, c->q[i]);
+        pinv.sh[i] = shoup(pinv.v[i], c->q[i]);
+    }
+    gpu::moddown_finish(c->T, out, acc, (size_t)ne * N, z, add, add_mask, pinv, nq, nct, map_q(0, nq), c->stream);
 }
 // Inner product of the ModUp digits (read through `perm`, the NTT-domain
 // index map of an automorphism, when given) with the key, ModDown by P.  out
@@ -764,30 +826,8 @@ void ks_finish(ckks_ctx *c, const ModUp &mu, const SwitchKey &key, const int32_t
     ia.perm = perm;
     Buf acc(P, (size_t)nct * 2 * ne * N);
     gpu::key_inner(c->T, acc.p, ia, c->stream);
-    // ModDown of all 2 nct polys
-    ConvTable *md = moddown_table(c, l);
-    const int np2 = 2 * nct;
-    Buf y(P, (size_t)np2 * c->K * N);
-    ntt_oop_p(c, y.p, acc.p + (size_t)nq * N, (size_t)ne * N, c->K, np2, md->pin, true);
-    Buf z(P, (size_t)np2 * nq * N);
-    gpu::BconvArgs bd{md->pin, md->pout, md->din, md->dout, md->hinv.p, md->hinv_sh.p, md->mat.p, md->split};
-    gpu::bconv(c->T, z.p, y.p, bd, np2, (size_t)c->K * N, (size_t)nq * N, c->stream);
-    if (c->logN == 16) {
-        // (acc - z) P^-1 (+ add) fused into the transform's last pass
-        gpu::NttEpi ep{out, acc.p, (size_t)ne * N, c->d_pinv.p, c->d_pinvsh.p, add, add_mask};
-        ProfScope ps(c, "ntt", 16.0 * (double)nq * np2 * N);
-        gpu::ntt16_fwd_fused(c->T, z.p, nullptr, &ep, nq, np2, map_q(0, nq), c->stream);
-        return;
-    }
-    ntt_p(c, z.p, nq, np2, map_q(0, nq), false);
-    LimbConsts pinv{};
-    std::vector<int> pidx;
-    for (int k = 0; k < c->K; ++k) pidx.push_back(c->L + 1 + k);
-    for (int i = 0; i < nq; ++i) {
-        pinv.v[i] = hm::invmod(prod_mod(c, pidx, -1, c->q[i]), c->q[i]);
-        pinv.sh[i] = shoup(pinv.v[i], c->q[i]);
-    }
-    gpu::moddown_finish(c->T, out, acc.p, (size_t)ne * N, z.p, add, add_mask, pinv, nq, nct, map_q(0, nq), c->stream);
+    Buf y(P, (size_t)2 * nct * c->K * N), z(P, (size_t)2 * nct * nq * N);
+    ks_moddown(c, l, nct, acc.p, out, add, add_mask, y.p, z.p);
 }
 
 // Hybrid key switch of nct polynomials d (level l, NTT form; ciphertext b's
@@ -1858,6 +1898,16 @@ void make_switch_key(ckks_ctx *c, uint64_t seed, int galois, const u64 *sprime, 
     hipchk(hipStreamSynchronize(c->stream), "key sync");
 }
 
+// every level's key-switching conversion tables (ModUp per digit, ModDown),
+// so that key switches issued later allocate no tables
+void build_ks_tables(ckks_ctx *c) {
+    for (int l = 0; l <= c->L; ++l) {
+        const int beta = (l + 1 + c->alpha - 1) / c->alpha;
+        for (int j = 0; j < beta; ++j) modup_table(c, l, j);
+        moddown_table(c, l);
+    }
+}
+
 void keygen(ckks_ctx *c, uint64_t seed, const int32_t *gal, uint32_t ng) {
     const size_t N = c->N;
     const int np = c->np;
@@ -1897,6 +1947,7 @@ void keygen(ckks_ctx *c, uint64_t seed, const int32_t *gal, uint32_t ng) {
         gpu::permute(c->T, s2.p, c->sk.p, perm, np, 1, c->stream);
         make_switch_key(c, seed, g, s2.p, c->rot[g]);
     }
+    build_ks_tables(c);
     c->have_keys = true;
 }
 
@@ -2078,6 +2129,87 @@ ckks_status guard_out(ckks_ctx *c, ckks_ct **out, F &&f) {
 
 }  // namespace
 
+// ---------------------------------------------------------------------------
+// The scratch array of the entry point that allocates nothing
+// (ckks_hmult_relin_noalloc): CKKS_SCRATCH_BYTES of device memory per GPU,
+// held for the life of the process.  Host code never passes the array's name
+// to a kernel: its device address on each GPU is looked up once, with that
+// GPU current, when a context is created there.
+// ---------------------------------------------------------------------------
+static __device__ __align__(256) uint64_t scratch[CKKS_SCRATCH_BYTES / 8];
+
+namespace {
+
+std::mutex g_scratch_mu;
+std::map<int, u64 *> g_scratch_at;   // device -> address of its scratch array
+
+u64 *scratch_address(int dev) {
+    std::lock_guard<std::mutex> lk(g_scratch_mu);
+    auto it = g_scratch_at.find(dev);
+    if (it != g_scratch_at.end()) return it->second;
+    void *p = nullptr;
+    const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+    if (e != hipSuccess || !p)
+        fail(CKKS_E_DEVICE, std::string("scratch array address: ") + hipGetErrorString(e));
+    g_scratch_at[dev] = (u64 *)p;
+    return (u64 *)p;
+}
+
+size_t round_words(size_t w) { return (w + 31) & ~(size_t)31; }
+
+// scratch words the no-alloc product takes at level l for B ciphertexts:
+// tensor (d01, d2) and accumulators for the whole call, then either the ModUp
+// (its iNTT copy and the extended digits) or the ModDown (y, z) in one region
+size_t hmult_scratch_words(ckks_ctx *c, int l, int B) {
+    const size_t N = c->N;
+    const int nq = l + 1, ne = nq + c->K;
+    const int beta = (nq + c->alpha - 1) / c->alpha;
+    size_t up = round_words((size_t)B * nq * N);
+    for (int j = 0; j < beta; ++j) up += round_words((size_t)B * modup_table(c, l, j)->dout * N);
+    const size_t down = round_words((size_t)2 * B * c->K * N) + round_words((size_t)2 * B * nq * N);
+    return round_words((size_t)2 * B * nq * N) + round_words((size_t)B * nq * N) +
+           round_words((size_t)2 * B * ne * N) + std::max(up, down);
+}
+
+// Mul_C and relinearisation of op_hmult (same kernels in the same order, so
+// the same words) with every temporary carved from the GPU's scratch array;
+// the result's words go to `out`, [B][2][l+1][N].
+void hmult_noalloc(ckks_ctx *c, const ckks_ct *a, const ckks_ct *b, u64 *out, double *out_scale) {
+    if (!c->have_keys) fail(CKKS_E_NOKEY, "no keys");
+    if (a->level != b->level) fail(CKKS_E_LEVEL, "level mismatch");
+    if (a->B != b->B) fail(CKKS_E_PARAM, "batch size mismatch");
+    if (!c->scratch) fail(CKKS_E_DEVICE, "no scratch array on this device");
+    int dev = -1;
+    if (hipGetDevice(&dev) != hipSuccess || dev != c->device)
+        fail(CKKS_E_DEVICE, "the current device is not the context's");
+    const int l = a->level, nq = l + 1, ne = nq + c->K, B = a->B;
+    const size_t N = c->N;
+    need_tables(c, l);
+    const size_t need = hmult_scratch_words(c, l, B);
+    if (need * 8 > (size_t)CKKS_SCRATCH_BYTES)
+        fail(CKKS_E_PARAM, "this product needs " + std::to_string(need * 8) + " bytes of scratch, more than the " +
+                               std::to_string((size_t)CKKS_SCRATCH_BYTES) + " bytes of CKKS_SCRATCH_BYTES");
+    Carver cv{c->scratch, (size_t)CKKS_SCRATCH_BYTES / 8, 0};
+    u64 *d01 = cv.take((size_t)B * 2 * nq * N), *d2 = cv.take((size_t)B * nq * N);
+    u64 *acc = cv.take((size_t)B * 2 * ne * N);
+    const size_t mark = cv.used;
+    gpu::tensor(c->T, d01, d2, a->buf.p, b->buf.p, nq, B, map_q(0, nq), c->stream);
+    ModUp mu;
+    modup(c, l, d2, (size_t)nq * N, B, mu, &cv);
+    gpu::InnerArgs ia = mu.ia;
+    ia.key = c->relin.k.p;
+    ia.perm = nullptr;
+    gpu::key_inner(c->T, acc, ia, c->stream);
+    // the ModUp's pieces are read only by the inner product, queued before
+    // anything the ModDown writes over them (one stream)
+    cv.used = mark;
+    u64 *y = cv.take((size_t)2 * B * c->K * N), *z = cv.take((size_t)2 * B * nq * N);
+    ks_moddown(c, l, B, acc, out, d01, 3, y, z);
+    *out_scale = a->scale * b->scale;
+}
+
+}  // namespace
+
 // ===========================================================================
 // C-ABI
 // ===========================================================================
@@ -2119,6 +2251,8 @@ ckks_status ckks_ctx_create(const ckks_params *p, void *arena, size_t arena_byte
                         c->ladder);
         c->cdt = hm::gaussian_table(p->sigma);
         build_tables(c);
+        hipchk(hipGetDevice(&c->device), "current device");
+        c->scratch = scratch_address(c->device);
     });
     if (st != CKKS_OK) {
         delete c;
@@ -2273,6 +2407,11 @@ ckks_status ckks_rescale(ckks_ctx *c, const ckks_ct *a, ckks_ct **out) {
 ckks_status ckks_hmult_relin(ckks_ctx *c, const ckks_ct *a, const ckks_ct *b, ckks_ct **out) {
     if (!c || !a || !b) return CKKS_E_PARAM;
     return guard_out(c, out, [&] { return op_hmult(c, a, b); });
+}
+ckks_status ckks_hmult_relin_noalloc(ckks_ctx *c, const ckks_ct *a, const ckks_ct *b, uint64_t *out,
+                                     double *out_scale) {
+    if (!c || !a || !b || !out || !out_scale) return CKKS_E_PARAM;
+    return guard(c, [&] { hmult_noalloc(c, a, b, out, out_scale); });
 }
 ckks_status ckks_rotate(ckks_ctx *c, const ckks_ct *a, int32_t steps, ckks_ct **out) {
     CT_ARGS_CHECK();
