@@ -253,6 +253,7 @@ struct ckks_ctx {
     std::string trace;
     std::map<std::string, ProfFamily> prof;
     std::vector<hipEvent_t> ev_free;
+    int sum_terms = 0;            // products a 128-bit accumulator may add: T (q_max - 1)^2 < 2^127
     int device = 0;               // the GPU the context was created on
     u64 *scratch = nullptr;       // that GPU's scratch array (entry point that allocates nothing)
     u64 words(int level) const { return (u64)2 * (level + 1) * N; }
@@ -1620,8 +1621,13 @@ Ct op_lt(ckks_ctx *c, const ckks_ct *x, const LtStage &st) {
         Pool *Pl = c->pool.get();
         Buf A(Pl, (size_t)B * 2 * ne * N), E(Pl, (size_t)B * 2 * nq * N);
         const u64 *g0 = gis.size() > nrot ? inner.p + nrot * gstride : nullptr;
-        for (size_t j0 = 0; j0 < jobs.size(); j0 += gpu::kMaxJobs) {
-            const int nj = (int)std::min<size_t>(gpu::kMaxJobs, jobs.size() - j0);
+        // the summing inner product adds njob * ndig products of words below
+        // the primes in 128 bits before one reduction: at most
+        // c->sum_terms terms per launch (their sum stays below 2^127)
+        if (mu.ia.ndig > c->sum_terms) fail(CKKS_E_PARAM, "too many digits for a summed inner product");
+        const size_t per = (size_t)std::max(1, std::min(gpu::kMaxJobs, c->sum_terms / mu.ia.ndig));
+        for (size_t j0 = 0; j0 < jobs.size(); j0 += per) {
+            const int nj = (int)std::min<size_t>(per, jobs.size() - j0);
             gpu::KsJobs kj{};
             gpu::FinishJobs fj{};
             kj.njob = nj;
@@ -2250,6 +2256,14 @@ ckks_status ckks_ctx_create(const ckks_params *p, void *arena, size_t arena_byte
         hm::prime_chain(c->logN, c->L, c->K, (int)p->log_scale, (int)p->q0_bits, (int)p->p_bits, c->shape, c->q,
                         c->ladder);
         c->cdt = hm::gaussian_table(p->sigma);
+        {
+            u64 qmax = 0;
+            for (u64 v : c->q) qmax = std::max(qmax, v);
+            const long double m = (long double)(qmax - 1);
+            const long double t = std::ldexp(1.0L, 127) / (m * m);
+            c->sum_terms = (int)std::min<long double>(gpu::kMaxSumTerms, std::floor(t));
+            if (c->sum_terms < 1) fail(CKKS_E_PARAM, "primes too large for 128-bit accumulation");
+        }
         build_tables(c);
         hipchk(hipGetDevice(&c->device), "current device");
         c->scratch = scratch_address(c->device);

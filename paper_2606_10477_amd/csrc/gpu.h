@@ -222,6 +222,11 @@ void pt_mac_giants(const Tables &T, uint64_t *out, size_t gstride, const GiantAr
 // [njob][B][2][ne][N].  Each key word is loaded once per job and used for the
 // job's B inputs.
 constexpr int kMaxJobs = 32;
+// terms a summing inner product (key_inner_jobs_sum) may add in 128 bits
+// before reducing, at most: the host allows T terms per launch with
+// T (q_max - 1)^2 < 2^127 (128 for primes below 2^60, 32 below 2^61) and
+// splits longer job lists into launches of at most T / ndig jobs
+constexpr int kMaxSumTerms = 128;
 struct KsJobs {
     int njob, B;
     int ct0[kMaxJobs];

@@ -2,14 +2,15 @@
 benchmark's roofline line.
 
 Inputs: four `rocprofv3 --pmc ... --output-format csv -o run` directories:
-FETCH_SIZE and WRITE_SIZE of a benchmark run, and of the plain copy in
-hbm_copy.py (512 MiB).  The copy's counters against its known byte count give
-one scale per counter; the NTT dispatches' scaled counters, divided by the
-limbs they transform, give HBM bytes per limb of one transform (both passes).
-The record carries the SHA-256 of kernels.hip: the benchmark reports the
-figure only while the kernels are unchanged.
+FETCH_SIZE and WRITE_SIZE of a benchmark run, and of a plain device copy of
+known size (the `copy` command below, 512 MiB).  The copy's counters against
+its byte count give one scale per counter; the NTT dispatches' scaled
+counters, divided by the limbs they transform, give HBM bytes per limb of one
+transform (both passes).  The record carries the SHA-256 of kernels.hip: the
+benchmark reports the figure only while the kernels are unchanged.
 
-    python -m paper_2606_10477_amd.traffic_record FETCH_DIR WRITE_DIR COPY_FETCH_DIR COPY_WRITE_DIR [--out PATH]
+    python -m paper_2606_10477_amd.traffic_record copy [--mib 512] [--reps 5]
+    python -m paper_2606_10477_amd.traffic_record record FETCH_DIR WRITE_DIR COPY_FETCH_DIR COPY_WRITE_DIR [--out PATH]
 """
 import argparse
 import csv
@@ -61,7 +62,33 @@ def ntt_bytes(fetch_dir, write_dir, fs, ws):
     return tot, limbs
 
 
+def copy_run(mib, reps):
+    """The calibration copy: `reps` device-to-device copies of `mib` MiB."""
+    import torch
+    torch.cuda.set_device(0)
+    n = mib << 20
+    src = torch.empty(n, dtype=torch.uint8, device="cuda")
+    src.fill_(1)
+    dst = torch.empty_like(src)
+    torch.cuda.synchronize()
+    for _ in range(reps):
+        dst.copy_(src)
+    torch.cuda.synchronize()
+    print(json.dumps({"bytes_read_per_copy": n, "bytes_written_per_copy": n, "copies": reps}), flush=True)
+
+
 def main(argv=None):
+    import sys
+    argv = list(sys.argv[1:] if argv is None else argv)
+    if argv and argv[0] == "copy":
+        cp = argparse.ArgumentParser()
+        cp.add_argument("--mib", type=int, default=512)
+        cp.add_argument("--reps", type=int, default=5)
+        c = cp.parse_args(argv[1:])
+        copy_run(c.mib, c.reps)
+        return
+    if argv and argv[0] == "record":
+        argv = argv[1:]
     ap = argparse.ArgumentParser()
     ap.add_argument("fetch_dir")
     ap.add_argument("write_dir")
