@@ -109,6 +109,31 @@ ckks_status ckks_ctx_primes(const ckks_ctx *ctx, uint64_t *primes, double *ladde
 ckks_status ckks_set_stream(ckks_ctx *ctx, void *hip_stream);
 /* Block until all work queued on the context's stream has finished. */
 ckks_status ckks_sync(ckks_ctx *ctx);
+/* Non-blocking: *done = 1 when every operation queued on the context's stream
+ * has completed on the device, 0 while work is pending. */
+ckks_status ckks_stream_done(ckks_ctx *ctx, int *done);
+
+/*
+ * Device memory as the context sees it, for admission control (a serving
+ * loop admits work while its working set fits):
+ *   device_free, device_total  the GPU's free and total bytes (hipMemGetInfo);
+ *   pool_cached   bytes of free blocks the context's pool holds for reuse
+ *                 (available to this context without a new allocation);
+ *   pool_in_use   bytes of the pool's blocks held by live buffers (ciphertexts,
+ *                 keys, tables, temporaries of operations being issued);
+ *   pool_peak     the high-water mark of pool_in_use since the last reset:
+ *                 the working set of the operations issued meanwhile;
+ *   arena_left    bytes not yet handed out of a caller arena (0 without one).
+ * ct_bytes (host, L+1 entries, may be NULL) receives the size of one
+ * ciphertext at each level, 16 (l+1) N bytes.  reset_peak != 0 restarts the
+ * high-water mark at the current pool_in_use (after the figures are read).
+ */
+typedef struct {
+    size_t device_free, device_total;
+    size_t pool_cached, pool_in_use, pool_peak;
+    size_t arena_left;
+} ckks_mem_stats;
+ckks_status ckks_mem_info(ckks_ctx *ctx, ckks_mem_stats *out, uint64_t *ct_bytes, int reset_peak);
 
 /*
  * Keys from the seeded SHAKE-256 sampler: secret, public key, relinearisation
@@ -299,13 +324,23 @@ typedef struct {
     int32_t pre_bts;    /* 1: bootstrap x before the Chebyshev step (the
                            paper's Pre-BTS indicator c = 1); 0: only when x
                            lacks the levels for it */
-    int64_t bts_bound;  /* message bound for bootstrapping y (0: 16 ceil(1/sqrt(a))) */
+    int64_t bts_bound;  /* message bound for bootstrapping y (0: 16 ceil(sqrt(B/a))) */
+    double B;           /* pre-normalisation constant (§2.3, the scaling of
+                           PP-STAT): Alg. 1 runs on u = x/B in [a/B, b/B] and
+                           its result is scaled back by 1/sqrt(B), so the
+                           output approximates 1/sqrt(x); 0 or 1: none */
 } ckks_invsqrt_opts;
 
 /*
  * CryptoInvSqrt (paper Alg. 1): y0 = Chebyshev interpolant of degree `degree`
  * of 1/sqrt on [a, b]; ct_x = x/2; `iters` Newton steps; bootstrapping of y
- * per the policy in opts.  Pre-BTS (the paper's c = 1): with opts.pre_bts,
+ * per the policy in opts.  With pre-normalisation (opts.B > 1, §2.3):
+ * y0 = interpolant of 1/sqrt(u) on [a/B, b/B] at u = x/B (the division by B
+ * folded into the affine map's Mul_P, so the scaling takes the one level the
+ * paper counts for it), ct_x = Mul_P(x, 1/(2B)), and the scale-back by
+ * 1/sqrt(B) folded into the last Newton step (its constant 1.5/sqrt(B) and
+ * the exact scale change of its x operand) or, with no Newton step, into the
+ * coefficients: no extra level.  Pre-BTS (the paper's c = 1): with opts.pre_bts,
  * or if x has fewer than depth(degree) + 1 levels or fewer than 3, x is
  * bootstrapped first (bound 16 ceil(b)); otherwise x is never bootstrapped.  The last Newton step takes x/2 directly from the
  * input (limbs dropped, halving as an exact scale change, no rescale), so the

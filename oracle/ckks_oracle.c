@@ -1746,7 +1746,8 @@ fail:
 /*   tmp_a = y dropped to c-1, Mul_P 1.5 at s_c = (scale(w) q_{c-1}) /       */
 /*   scale(y), rescaled, so that it lands exactly on scale(w).               */
 /* ------------------------------------------------------------------------ */
-orc_ct *orc_newton_step_ex(orc_ctx *c, const orc_ct *y, const orc_ct *ctx_half, int raw_x) {
+/* with the constant c15 of tmp_a (1.5 in the step of §2.2) */
+static orc_ct *newton_step(orc_ctx *c, const orc_ct *y, const orc_ct *ctx_half, int raw_x, double c15) {
     int lc = y->level < ctx_half->level ? y->level : ctx_half->level;
     if (lc < 2) { set_err("level"); return NULL; }
     orc_ct *xa = raw_x ? orc_drop_level(c, ctx_half, lc) : orc_level_to(c, ctx_half, lc);
@@ -1758,13 +1759,16 @@ orc_ct *orc_newton_step_ex(orc_ctx *c, const orc_ct *y, const orc_ct *ctx_half, 
     orc_ct_free(u); orc_ct_free(v);
     orc_ct *yd = orc_drop_level(c, y, lc - 1);
     double sc = (w->scale * (double)c->q[lc - 1]) / yd->scale;
-    orc_ct *tm = orc_mul_const(c, yd, 1.5, sc);
+    orc_ct *tm = orc_mul_const(c, yd, c15, sc);
     orc_ct_free(yd);
     orc_ct *ta = orc_rescale(c, tm);
     orc_ct_free(tm);
     orc_ct *r = orc_sub(c, ta, w);
     orc_ct_free(ta); orc_ct_free(w);
     return r;
+}
+orc_ct *orc_newton_step_ex(orc_ctx *c, const orc_ct *y, const orc_ct *ctx_half, int raw_x) {
+    return newton_step(c, y, ctx_half, raw_x, 1.5);
 }
 orc_ct *orc_newton_step(orc_ctx *c, const orc_ct *y, const orc_ct *ctx_half) {
     return orc_newton_step_ex(c, y, ctx_half, 0);
@@ -2296,15 +2300,32 @@ orc_ct *orc_bootstrap(orc_ctx *c, const orc_ct *a, int64_t M) {
  * input ciphertext: its limbs are dropped to the step's level and the
  * halving is the exact scale change scale(x) -> 2 scale(x), with no rescale,
  * so x keeps the precision of its own scale.
+ * Pre-normalisation by B > 0 (§2.3; B = 0 means 1): the method runs on
+ * u = x/B over [a/B, b/B] and the result is scaled back by k = 1/sqrt(B)
+ * (the paper's "scale back by sqrt(B)" read as the division the mathematics
+ * needs):
+ *   - the Chebyshev coefficients interpolate 1/sqrt on [a/B, b/B]; the
+ *     affine map is formed from [a, b] on x, which is the same map on u,
+ *     so the division by B costs no Mul_P of its own;
+ *   - ct_x = Mul_P(x, 0.5/B);
+ *   - the last Newton step takes u/2 from the input as the scale change
+ *     scale(x) -> 2 B sqrt(B) scale(x) (x operand k u / 2) with the constant
+ *     1.5 k, so it yields k y';  with no Newton step the coefficients are
+ *     multiplied by k instead.
+ *   - the message bound of y's bootstrap is 16 ceil(1/sqrt(a/B)).
  */
 orc_ct *orc_invsqrt(orc_ctx *c, const orc_ct *x, int d, int iters, double a, double b, int literal,
-                    int64_t bts_bound, int pre_bts) {
+                    int64_t bts_bound, int pre_bts, double B) {
+    if (!(B >= 0) || !isfinite(B)) { set_err("bad pre-normalisation constant"); return NULL; }
+    const double Bn = B > 0 ? B : 1.0, an = a / Bn, bn = b / Bn, kappa = 1.0 / sqrt(Bn);
     double *cf = malloc(sizeof(double) * (d + 1));
-    if (d < 1 || iters < 0 || orc_cheb_coeffs_invsqrt(d, a, b, cf) != 0) {
+    if (d < 1 || iters < 0 || !(a > 0) || !(b > a) || orc_cheb_coeffs_invsqrt(d, an, bn, cf) != 0) {
         free(cf); set_err("bad degree / iterations / interval"); return NULL;
     }
+    if (iters == 0)
+        for (int k = 0; k <= d; k++) cf[k] *= kappa;
     orc_ct *xb = NULL;
-    const int64_t My = bts_bound > 0 ? bts_bound : 16 * (int64_t)ceil(1.0 / sqrt(a));
+    const int64_t My = bts_bound > 0 ? bts_bound : 16 * (int64_t)ceil(1.0 / sqrt(an));
     if (pre_bts || x->level < cheb_depth(d) + 1 || x->level < 3) {
         if (!c->bts) {
             if (pre_bts || x->level < 2) { free(cf); set_err("level"); return NULL; }
@@ -2314,7 +2335,7 @@ orc_ct *orc_invsqrt(orc_ctx *c, const orc_ct *x, int d, int iters, double a, dou
             x = xb;
         }
     }
-    orc_ct *cx = mul_const_down(c, x, 0.5);
+    orc_ct *cx = mul_const_down(c, x, 0.5 / Bn);
     orc_ct *y = orc_cheb_eval(c, x, cf, d, a, b);
     free(cf);
     if (!cx || !y) { orc_ct_free(cx); orc_ct_free(y); orc_ct_free(xb); return NULL; }
@@ -2335,8 +2356,8 @@ orc_ct *orc_invsqrt(orc_ctx *c, const orc_ct *x, int d, int iters, double a, dou
         orc_ct *yn;
         if (i == iters - 1) {
             orc_ct *xr = ct_copy(c, x);
-            xr->scale = x->scale * 2.0;
-            yn = orc_newton_step_ex(c, y, xr, 1);
+            xr->scale = x->scale * (2.0 * Bn * sqrt(Bn));
+            yn = newton_step(c, y, xr, 1, 1.5 * kappa);
             orc_ct_free(xr);
         } else {
             yn = orc_newton_step(c, y, cx);

@@ -90,7 +90,8 @@ def lib():
         "orc_cheb_eval": (vp, [vp, vp, dblp, C.c_int, C.c_double, C.c_double]),
         "orc_newton_step": (vp, [vp, vp, vp]),
         "orc_newton_step_ex": (vp, [vp, vp, vp, C.c_int]),
-        "orc_invsqrt": (vp, [vp, vp, C.c_int, C.c_int, C.c_double, C.c_double, C.c_int, C.c_int64, C.c_int]),
+        "orc_invsqrt": (vp, [vp, vp, C.c_int, C.c_int, C.c_double, C.c_double, C.c_int, C.c_int64, C.c_int,
+                             C.c_double]),
         "orc_bootstrap": (vp, [vp, vp, C.c_int64]),
         "orc_ctx_create_bts": (vp, [C.c_int, C.c_int, C.c_int, C.c_int, C.c_int, C.c_int, C.c_int, C.c_int,
                                     C.c_int, C.c_double, C.c_int, C.c_int, C.c_int]),
@@ -360,9 +361,9 @@ class Context:
     def newton_step(self, y, cx, raw_x=False):
         return Ct(self, lib().orc_newton_step_ex(self.ptr, y.ptr, cx.ptr, int(raw_x)))
 
-    def invsqrt(self, x, degree, iters, a, b, literal=False, bts_bound=0, pre_bts=False):
+    def invsqrt(self, x, degree, iters, a, b, literal=False, bts_bound=0, pre_bts=False, B=0.0):
         return Ct(self, lib().orc_invsqrt(self.ptr, x.ptr, degree, iters, a, b, int(literal), int(bts_bound),
-                                          int(pre_bts)))
+                                          int(pre_bts), float(B)))
 
     # -- bootstrapping -------------------------------------------------------
     def bts_config(self, K=25.0, r=4, degree=31):

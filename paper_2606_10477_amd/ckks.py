@@ -33,7 +33,12 @@ class Params(C.Structure):
 
 class InvsqrtOpts(C.Structure):
     _fields_ = [("a", C.c_double), ("b", C.c_double), ("literal", C.c_int32), ("pre_bts", C.c_int32),
-                ("bts_bound", C.c_int64)]
+                ("bts_bound", C.c_int64), ("B", C.c_double)]
+
+
+class MemStats(C.Structure):
+    _fields_ = [("device_free", C.c_size_t), ("device_total", C.c_size_t), ("pool_cached", C.c_size_t),
+                ("pool_in_use", C.c_size_t), ("pool_peak", C.c_size_t), ("arena_left", C.c_size_t)]
 
 
 # name -> (restype, argtypes): every symbol of include/ckks.h
@@ -44,6 +49,8 @@ SIGNATURES = {
     "ckks_ctx_primes": (C.c_int, [vp, u64p, dblp]),
     "ckks_set_stream": (C.c_int, [vp, vp]),
     "ckks_sync": (C.c_int, [vp]),
+    "ckks_stream_done": (C.c_int, [vp, C.POINTER(C.c_int)]),
+    "ckks_mem_info": (C.c_int, [vp, C.POINTER(MemStats), u64p, C.c_int]),
     "ckks_keygen": (C.c_int, [vp, C.c_uint64, i32p, C.c_uint32]),
     "ckks_galois_rotation": (C.c_int32, [vp, C.c_int32]),
     "ckks_encrypt": (C.c_int, [vp, dblp, C.c_uint32, C.c_uint32, C.c_double, C.c_uint64, C.POINTER(vp)]),
@@ -258,6 +265,21 @@ class Context:
     def sync(self):
         self._chk(lib().ckks_sync(self.ptr))
 
+    def stream_done(self):
+        """True when every operation queued on the context's stream has finished."""
+        d = C.c_int()
+        self._chk(lib().ckks_stream_done(self.ptr, C.byref(d)))
+        return bool(d.value)
+
+    def mem_info(self, reset_peak=False):
+        """ckks_mem_info as a dict (bytes), with "ct_bytes" per level."""
+        st = MemStats()
+        cb = np.zeros(self.L + 1, dtype=np.uint64)
+        self._chk(lib().ckks_mem_info(self.ptr, C.byref(st), _p(cb, u64p), int(reset_peak)))
+        d = {k: int(getattr(st, k)) for k, _ in MemStats._fields_}
+        d["ct_bytes"] = [int(v) for v in cb]
+        return d
+
     def keygen(self, seed, galois=()):
         g = np.array(list(galois), dtype=np.int32)
         self._chk(lib().ckks_keygen(self.ptr, seed, _p(g, i32p) if len(g) else None, len(g)))
@@ -376,12 +398,13 @@ class Context:
     def mul_monomial(self, a, k):
         return self._ct(lib().ckks_mul_monomial, a.ptr, int(k))
 
-    def invsqrt(self, x, degree, iters, a=2.0 ** -10, b=1.0, literal=False, bts_bound=0, pre_bts=False):
-        o = InvsqrtOpts(a, b, int(literal), int(pre_bts), int(bts_bound))
+    def invsqrt(self, x, degree, iters, a=2.0 ** -10, b=1.0, literal=False, bts_bound=0, pre_bts=False, B=0.0):
+        o = InvsqrtOpts(a, b, int(literal), int(pre_bts), int(bts_bound), float(B))
         return self._ct(lib().ckks_invsqrt_ex, x.ptr, degree, iters, C.byref(o))
 
-    def invsqrt_batch(self, xs, degree, iters, a=2.0 ** -10, b=1.0, literal=False, bts_bound=0, pre_bts=False):
-        o = InvsqrtOpts(a, b, int(literal), int(pre_bts), int(bts_bound))
+    def invsqrt_batch(self, xs, degree, iters, a=2.0 ** -10, b=1.0, literal=False, bts_bound=0, pre_bts=False,
+                      B=0.0):
+        o = InvsqrtOpts(a, b, int(literal), int(pre_bts), int(bts_bound), float(B))
         arr = (vp * len(xs))(*[x.ptr for x in xs])
         outs = (vp * len(xs))()
         self._chk(lib().ckks_invsqrt_batch(self.ptr, arr, len(xs), degree, iters, C.byref(o), outs))
@@ -410,10 +433,11 @@ class Context:
         self._chk(lib().ckks_profile_read(self.ptr, family.encode(), C.byref(n), C.byref(ms), C.byref(by)))
         return n.value, ms.value, by.value
 
-    def invsqrt_graph(self, x, degree, iters, a=2.0 ** -10, b=1.0, literal=False, bts_bound=0, pre_bts=False):
+    def invsqrt_graph(self, x, degree, iters, a=2.0 ** -10, b=1.0, literal=False, bts_bound=0, pre_bts=False,
+                      B=0.0):
         """Capture the chain for inputs shaped like x (level, scale, batch);
         returns an InvsqrtGraph whose run(x) replays it."""
-        o = InvsqrtOpts(a, b, int(literal), int(pre_bts), int(bts_bound))
+        o = InvsqrtOpts(a, b, int(literal), int(pre_bts), int(bts_bound), float(B))
         out = vp()
         self._chk(lib().ckks_invsqrt_graph_create(self.ptr, x.ptr, degree, iters, C.byref(o), C.byref(out)))
         return InvsqrtGraph(self, out.value)

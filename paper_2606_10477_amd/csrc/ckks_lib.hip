@@ -71,6 +71,7 @@ public:
             void *p = it->second.back();
             it->second.pop_back();
             cached_ -= it->first;
+            note_use(it->first);
             if (it->second.empty()) free_.erase(it);
             if (capturing_) captured_.insert(p);
             return p;
@@ -90,9 +91,18 @@ public:
             }
         }
         size_[p] = cls;
+        held_ += cls;
+        note_use(cls);
         if (capturing_) captured_.insert(p);
         return p;
     }
+    // memory accounting (host side: a block is in use from get to put; work
+    // queued on the stream keeps using it in stream order after put)
+    size_t cached() const { return cached_; }
+    size_t in_use() const { return in_use_; }
+    size_t peak() const { return peak_; }
+    void reset_peak() { peak_ = in_use_; }
+    size_t arena_left() const { return base_ ? cap_ - used_ : 0; }
     // HIP graph capture: every block handed out while capturing is recorded;
     // at the end those blocks belong to the graph (its nodes address them on
     // every replay) and are not handed out again until release_graph.
@@ -113,6 +123,7 @@ public:
             if (f == v.end()) continue;
             v.erase(f);
             cached_ -= sz;
+            note_use(sz);   // held by the graph from now on
             if (v.empty()) free_.erase(it);
         }
         captured_.clear();
@@ -125,6 +136,7 @@ public:
             const size_t sz = size_.at(p);
             free_[sz].push_back(p);
             cached_ += sz;
+            in_use_ -= sz;
         }
     }
     void put(void *p) {
@@ -133,6 +145,7 @@ public:
         const size_t sz = size_.at(p);
         free_[sz].push_back(p);
         cached_ += sz;
+        in_use_ -= sz;
         if (!base_ && cached_ > kCacheLimit) trim();
     }
     // free every cached block (blocks still queued for use by earlier work on
@@ -143,6 +156,7 @@ public:
             for (void *p : kv.second) {
                 size_.erase(p);
                 (void)hipFree(p);
+                held_ -= kv.first;
             }
         free_.clear();
         cached_ = 0;
@@ -153,8 +167,12 @@ private:
     // through tens of GB of distinct block sizes; trimming below that would
     // free and re-allocate (with device synchronisation) on every step
     static constexpr size_t kCacheLimit = (size_t)192 << 30;
+    void note_use(size_t sz) {
+        in_use_ += sz;
+        if (in_use_ > peak_) peak_ = in_use_;
+    }
     char *base_;
-    size_t cap_, used_, cached_ = 0;
+    size_t cap_, used_, cached_ = 0, held_ = 0, in_use_ = 0, peak_ = 0;
     std::map<size_t, std::vector<void *>> free_;   // block size -> free blocks
     std::map<void *, size_t> size_;                // every block -> its size
     bool capturing_ = false;
@@ -1463,10 +1481,12 @@ Ct op_cheb(ckks_ctx *c, const ckks_ct *x, const std::vector<double> &cf, double 
     return cheb_tree(c, pb, cf, m, bb);
 }
 
-// One Newton step y' = 1.5 y - (x/2 * y) * y^2 at c = min(l_x, l_y).  With
-// raw_x the x operand is only limb-dropped (it keeps its own, larger scale);
-// 1.5 y is encoded to land exactly on the scale of the product term.
-Ct op_newton(ckks_ctx *c, const ckks_ct *y, const ckks_ct *half_x, bool raw_x) {
+// One Newton step y' = c15 y - (x/2 * y) * y^2 at c = min(l_x, l_y) (c15 =
+// 1.5: the step of §2.2; the last step of a pre-normalised chain passes
+// 1.5 / sqrt(B) with x/2 declared as x sqrt(B) / (2B)).  With raw_x the x
+// operand is only limb-dropped (it keeps its own, larger scale); c15 y is
+// encoded to land exactly on the scale of the product term.
+Ct op_newton(ckks_ctx *c, const ckks_ct *y, const ckks_ct *half_x, bool raw_x, double c15 = 1.5) {
     const int lc = std::min(y->level, half_x->level);
     if (lc < 2) fail(CKKS_E_LEVEL, "Newton step needs 2 levels");
     Ct xa = raw_x ? op_drop(c, half_x, lc) : op_level_to(c, half_x, lc);
@@ -1480,7 +1500,7 @@ Ct op_newton(ckks_ctx *c, const ckks_ct *y, const ckks_ct *half_x, bool raw_x) {
     u.reset();
     v.reset();
     double sc = (w->scale * (double)c->q[lc - 1]) / y->scale;
-    Ct tm = op_lincomb(c, {y}, {1.5}, {sc}, lc - 1);   // tmp_alpha = 1.5 y (limbs to lc-1) on scale(w)
+    Ct tm = op_lincomb(c, {y}, {c15}, {sc}, lc - 1);   // tmp_alpha = 1.5 y (limbs to lc-1) on scale(w)
     Ct ta = op_rescale(c, tm.get());
     return op_addsub(c, ta.get(), w.get(), true);
 }
@@ -1828,7 +1848,10 @@ std::vector<int> bts_rotations(const ckks_ctx *c) {
 Ct op_invsqrt(ckks_ctx *c, const ckks_ct *x0, int degree, int iters, const ckks_invsqrt_opts &o) {
     if (degree < 1 || iters < 0) fail(CKKS_E_PARAM, "bad degree / iterations");
     if (!(o.a > 0) || !(o.b > o.a)) fail(CKKS_E_PARAM, "bad interval");
-    const int64_t My = o.bts_bound > 0 ? o.bts_bound : 16 * (int64_t)std::ceil(1.0 / std::sqrt(o.a));
+    if (!(o.B >= 0) || !std::isfinite(o.B)) fail(CKKS_E_PARAM, "bad pre-normalisation constant");
+    // pre-normalisation: u = x / Bn on [an, bn]; output scaled by kappa
+    const double Bn = o.B > 0 ? o.B : 1.0, an = o.a / Bn, bn = o.b / Bn, kappa = 1.0 / std::sqrt(Bn);
+    const int64_t My = o.bts_bound > 0 ? o.bts_bound : 16 * (int64_t)std::ceil(1.0 / std::sqrt(an));
     const ckks_ct *x = x0;
     Ct xb;
     if (o.pre_bts || x->level < cheb_depth(degree) + 1 || x->level < 3) {
@@ -1841,9 +1864,11 @@ Ct op_invsqrt(ckks_ctx *c, const ckks_ct *x0, int degree, int iters, const ckks_
         }
     }
     std::vector<double> cf(degree + 1);
-    hm::cheb_invsqrt(degree, o.a, o.b, cf.data());
-    Ct cx = op_mul_const_down(c, x, 0.5);
-    Ct y = op_cheb(c, x, cf, o.a, o.b);
+    hm::cheb_invsqrt(degree, an, bn, cf.data());
+    if (iters == 0)
+        for (double &v : cf) v *= kappa;   // no Newton step to carry the scale-back
+    Ct cx = op_mul_const_down(c, x, 0.5 / Bn);
+    Ct y = op_cheb(c, x, cf, o.a, o.b);   // affine map from [a, b]: t(x) = t(u) on [an, bn]
     if (o.literal) y = op_bootstrap(c, y.get(), My);
     for (int i = 0; i < iters; ++i) {
         if (y->level < 2) {
@@ -1851,10 +1876,13 @@ Ct op_invsqrt(ckks_ctx *c, const ckks_ct *x0, int degree, int iters, const ckks_
             y = op_bootstrap(c, y.get(), My);
         }
         if (i == iters - 1) {
-            // last step: x/2 straight from the input (exact halving of the scale)
+            // last step: u/2 = x/(2B) straight from the input as an exact
+            // change of scale, with the scale-back kappa = 1/sqrt(B) folded
+            // in: the x operand declared as kappa x / (2B), the constant
+            // 1.5 kappa
             Ct xr = ct_copy(c, x);
-            xr->scale = x->scale * 2.0;
-            y = op_newton(c, y.get(), xr.get(), true);
+            xr->scale = x->scale * (2.0 * Bn * std::sqrt(Bn));
+            y = op_newton(c, y.get(), xr.get(), true, 1.5 * kappa);
         } else {
             y = op_newton(c, y.get(), cx.get(), false);
         }
@@ -2297,6 +2325,33 @@ ckks_status ckks_set_stream(ckks_ctx *c, void *s) {
     return CKKS_OK;
 }
 
+ckks_status ckks_mem_info(ckks_ctx *c, ckks_mem_stats *out, uint64_t *ct_bytes, int reset_peak) {
+    if (!c || !out) return CKKS_E_PARAM;
+    return guard(c, [&] {
+        size_t fr = 0, tot = 0;
+        hipchk(hipMemGetInfo(&fr, &tot), "device memory info");
+        out->device_free = fr;
+        out->device_total = tot;
+        out->pool_cached = c->pool->cached();
+        out->pool_in_use = c->pool->in_use();
+        out->pool_peak = c->pool->peak();
+        out->arena_left = c->pool->arena_left();
+        if (ct_bytes)
+            for (int l = 0; l <= c->L; ++l) ct_bytes[l] = c->words(l) * 8;
+        if (reset_peak) c->pool->reset_peak();
+    });
+}
+
+ckks_status ckks_stream_done(ckks_ctx *c, int *done) {
+    if (!c || !done) return CKKS_E_PARAM;
+    return guard(c, [&] {
+        const hipError_t e = hipStreamQuery(c->stream);
+        if (e == hipSuccess) *done = 1;
+        else if (e == hipErrorNotReady) *done = 0;
+        else hipchk(e, "stream query");
+    });
+}
+
 ckks_status ckks_sync(ckks_ctx *c) {
     if (!c) return CKKS_E_PARAM;
     return guard(c, [&] { hipchk(hipStreamSynchronize(c->stream), "sync"); });
@@ -2504,6 +2559,7 @@ static ckks_invsqrt_opts default_opts() {
     o.literal = 0;
     o.pre_bts = 0;
     o.bts_bound = 0;
+    o.B = 0.0;
     return o;
 }
 ckks_status ckks_invsqrt(ckks_ctx *c, const ckks_ct *x, uint32_t degree, uint32_t iters, ckks_ct **out) {

@@ -5,6 +5,12 @@ the 4- and 8-word variants are still the fastest).  Results are identical
 under every schedule; only the time changes.
 
     python -m paper_2606_10477_amd.ntt_tune [--limbs 1,2,4,...] [--json PATH]
+
+With --calls K it only issues K forward and K inverse transforms at each
+size under the library's schedule, untimed, for a counter profiler to
+attribute per dispatch (each dispatch's grid gives its limb count):
+
+    python -m paper_2606_10477_amd.ntt_tune --limbs 1,8,43,96 --calls 20
 """
 import argparse
 import json
@@ -45,6 +51,20 @@ def scan(ctx, sizes, nprimes):
     return rows
 
 
+def issue(ctx, sizes, nprimes, calls):
+    """`calls` forward and inverse transforms at each size (default schedule)."""
+    import numpy as np
+    import torch
+    for n in sizes:
+        idx = np.array([(7 * i) % nprimes for i in range(n)], dtype=np.uint32)
+        x = torch.randint(0, 1 << 30, (n, 1 << 16), dtype=torch.int64, device="cuda")
+        for _ in range(calls):
+            ctx.ntt_device(x.data_ptr(), n, idx, inverse=False)
+            ctx.ntt_device(x.data_ptr(), n, idx, inverse=True)
+        ctx.sync()
+        print(json.dumps({"limbs": n, "calls": calls}), flush=True)
+
+
 def choose(rows, tol=0.01):
     """Bounds (r4_max, r8_max): every call size up to r4_max is fastest (fwd +
     inv) with 4 words per thread, up to r8_max with 4 or 8.  A variant within
@@ -74,11 +94,16 @@ def main(argv=None):
     ap = argparse.ArgumentParser()
     ap.add_argument("--limbs", default=",".join(str(s) for s in SIZES))
     ap.add_argument("--json", default=None)
+    ap.add_argument("--calls", type=int, default=0, help="only issue this many calls per size (for profilers)")
     a = ap.parse_args(argv)
     import torch
     from . import ckks
     torch.cuda.set_device(0)
     ctx = ckks.Context.from_set("p16b", bootstrapping=False)
+    if a.calls:
+        issue(ctx, [int(s) for s in a.limbs.split(",")], ctx.np_, a.calls)
+        ctx.close()
+        return
     rows = scan(ctx, [int(s) for s in a.limbs.split(",")], ctx.np_)
     r4, r8, best = choose(rows)
     res = {"r4_max_limbs": r4, "r8_max_limbs": r8, "fastest_words_per_thread": best, "rows": rows}

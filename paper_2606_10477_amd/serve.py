@@ -2,17 +2,29 @@
 
 Requests arrive over time; each carries 1..32 ciphertexts at one input level
 and an MRE target, which the tuning table maps to a (degree, Pre-BTS
-indicator c, iterations) setting.  The scheduler admits arrived requests while
-their estimated device working set fits the memory budget, groups the
-admitted ciphertexts of all requests by (level, degree, c, iterations) and
-runs the oldest group as one batched launch sequence (up to `max_batch`
-ciphertexts), bootstrapping keys resident in HBM.  Requests that arrive
-while a batch is on the GPU are admitted at the next scheduling round, so work
-from different requests shares launches.  Every ciphertext's result is the same
-alone and in the mix: batch members never interact.
+indicator c, iterations) setting.  The server runs on one or more lanes: a
+lane is a library context (the same parameter set and keys) on a HIP stream
+of its own, all streams at the default priority.  A group -- admitted
+ciphertexts that share (level, degree, c, iterations), up to `max_batch`,
+oldest request first -- is issued on an idle lane as one batched launch
+sequence and runs on the device while the host keeps scheduling: requests
+that arrive meanwhile are admitted and their groups start on another lane,
+so work from different requests overlaps on the GPU.  Completion is polled
+without blocking (ckks_stream_done); a request's latency runs from its
+arrival to the device completion of its last group (device events on the
+lane's stream).
 
-The baseline ("one at a time") serves requests strictly in arrival order, each
-request's ciphertexts in one batched call, with no sharing across requests.
+Admission follows the library's own memory figures (ckks_mem_info): a
+request is admitted while its estimated working set, together with that of
+admitted requests not yet issued, fits the GPU's free memory plus the lanes'
+cached pool blocks, less a reserve.  The working set per ciphertext and
+level starts from a multiple of the ciphertext's size and is replaced by the
+measured pool high-water mark of issued groups.
+
+Every ciphertext's result is the same alone and in the mix: batch members
+never interact and every lane computes the same words.  The baseline ("one
+at a time") serves requests strictly in arrival order on one lane, each
+request's ciphertexts in one batched call, synchronously.
 """
 import os
 import time
@@ -34,6 +46,7 @@ class Request:
     outs: dict = field(default_factory=dict)
     admitted: float = None
     done: float = None
+    issued: int = 0         # ciphertexts handed to groups so far
 
 
 def lookup(table, level, target):
@@ -56,88 +69,171 @@ def lookup(table, level, target):
     return ent["degree"], ent.get("c", 0), ent["iters"]
 
 
-class Server:
-    def __init__(self, ctx, table, max_batch=64, mem_budget=None, ct_factor=24, lo=2.0 ** -10, hi=1.0):
+class Lane:
+    """A context on a stream of its own.  With a torch stream, device events
+    time each group's completion; without one (tests), the host clock at the
+    poll that sees it finished does."""
+
+    def __init__(self, ctx, stream=None):
         self.ctx = ctx
+        self.stream = stream
+        self.group = None          # (key, [(request, ct index)], outs, end event, issue time)
+        self.t0 = None
+
+    def start_clock(self):
+        if self.stream is not None:
+            import torch
+            self.t0 = torch.cuda.Event(enable_timing=True)
+            self.t0.record(self.stream)
+
+    def issue(self, key, work, lo, hi, now):
+        cts = [r.cts[k] for r, k in work]
+        outs = self.ctx.invsqrt_batch(cts, key[1], key[3], a=lo, b=hi, pre_bts=bool(key[2]))
+        end = None
+        if self.stream is not None:
+            import torch
+            end = torch.cuda.Event(enable_timing=True)
+            end.record(self.stream)
+        self.group = (key, work, outs, end, now)
+
+    def finished(self):
+        return self.group is not None and self.ctx.stream_done()
+
+    def done_time(self, now):
+        end = self.group[3]
+        if end is None or self.t0 is None:
+            return now
+        return self.t0.elapsed_time(end) / 1e3
+
+
+class Server:
+    def __init__(self, lanes, table, max_batch=64, reserve_bytes=1 << 30, ct_factor=24, lo=2.0 ** -10, hi=1.0):
+        self.lanes = [ln if isinstance(ln, Lane) else Lane(ln) for ln in (lanes if isinstance(lanes, list)
+                                                                           else [lanes])]
         self.table = table
         self.max_batch = max_batch
         self.lo, self.hi = lo, hi
-        self.ct_factor = ct_factor       # working-set multiple of one input ciphertext
-        if mem_budget is None:
-            import torch
-            free, _ = torch.cuda.mem_get_info()
-            mem_budget = int(0.7 * free)
-        self.mem_budget = mem_budget
-        self.in_use = 0
-        self.queue = []                   # arrived, not admitted
-        self.active = []                  # admitted, not finished
+        self.reserve = reserve_bytes
+        self.ct_factor = ct_factor       # first working-set estimate: a multiple of one input ciphertext
+        self.ct_bytes = self.lanes[0].ctx.mem_info()["ct_bytes"]
+        self.ws = {}                     # level -> measured working set per ciphertext (bytes)
+        self.queue = []                  # arrived, not admitted
+        self.active = []                 # admitted, not finished
         self.log = []
+        self.max_in_flight = 0
+        self.last_finished = 0
 
-    def est_bytes(self, req):
-        return len(req.cts) * 2 * (req.level + 1) * self.ctx.N * 8 * self.ct_factor
+    def est_bytes(self, req, n=None):
+        n = len(req.cts) if n is None else n
+        per = self.ws.get(req.level, self.ct_factor * self.ct_bytes[req.level])
+        return n * per
+
+    def available(self):
+        info = [ln.ctx.mem_info() for ln in self.lanes]
+        return info[0]["device_free"] + sum(i["pool_cached"] for i in info) - self.reserve
 
     def submit(self, req):
         req.degree, req.c, req.iters = lookup(self.table, req.level, req.target)
         self.queue.append(req)
 
     def _admit(self, now):
+        if not self.queue:
+            return
+        pending = sum(self.est_bytes(r, len(r.cts) - r.issued) for r in self.active)
+        room = self.available() - pending
         still = []
         for r in self.queue:
             need = self.est_bytes(r)
-            if self.in_use + need <= self.mem_budget or not self.active:
-                self.in_use += need
+            if need <= room or not self.active:
+                room -= need
                 r.admitted = now
                 self.active.append(r)
             else:
                 still.append(r)
         self.queue = still
 
-    def step(self, clock):
-        """One scheduling round: admit, pick the oldest group, run it."""
-        self._admit(clock())
-        if not self.active:
-            return 0
-        oldest = min(self.active, key=lambda r: r.arrival)
-        key = (oldest.level, oldest.degree, oldest.c, oldest.iters)
-        work = []                          # (request, ct index)
-        for r in sorted(self.active, key=lambda r: r.arrival):
+    def _next_group(self):
+        """The oldest admitted request with ciphertexts not yet issued sets
+        the group key; its and later requests' ciphertexts of the same key
+        fill the group up to max_batch."""
+        cand = [r for r in sorted(self.active, key=lambda r: r.arrival) if r.issued < len(r.cts)]
+        if not cand:
+            return None, []
+        key = (cand[0].level, cand[0].degree, cand[0].c, cand[0].iters)
+        work = []
+        for r in cand:
             if (r.level, r.degree, r.c, r.iters) != key:
                 continue
-            for k in range(len(r.cts)):
-                if k not in r.outs and len(work) < self.max_batch:
-                    work.append((r, k))
-        cts = [r.cts[k] for r, k in work]
-        outs = self.ctx.invsqrt_batch(cts, key[1], key[3], a=self.lo, b=self.hi, pre_bts=bool(key[2]))
-        self.ctx.sync()
-        t = clock()
+            while r.issued < len(r.cts) and len(work) < self.max_batch:
+                work.append((r, r.issued))
+                r.issued += 1
+        return key, work
+
+    def _finish(self, lane, now):
+        key, work, outs, _, _ = lane.group
+        t = lane.done_time(now)
         for (r, k), y in zip(work, outs):
             r.outs[k] = y
         finished = [r for r in self.active if len(r.outs) == len(r.cts)]
         for r in finished:
             r.done = t
-            self.in_use -= self.est_bytes(r)
             self.active.remove(r)
-        self.log.append({"t": t, "group": key, "batch": len(cts), "finished": [r.rid for r in finished]})
-        return len(cts)
+        self.log.append({"t": t, "group": key, "batch": len(work), "lane": self.lanes.index(lane),
+                         "finished": [r.rid for r in finished]})
+        lane.group = None
+
+    def step(self, clock):
+        """One scheduling round: collect finished groups, admit arrivals by
+        memory, issue a group on every idle lane.  Returns the number of
+        ciphertexts issued (last_finished: the number collected)."""
+        moved = 0
+        self.last_finished = 0
+        for ln in self.lanes:
+            if ln.finished():
+                self.last_finished += len(ln.group[1])
+                self._finish(ln, clock())
+        self._admit(clock())
+        for ln in self.lanes:
+            if ln.group is not None:
+                continue
+            key, work = self._next_group()
+            if not work:
+                break
+            before = ln.ctx.mem_info(reset_peak=True)["pool_in_use"]
+            ln.issue(key, work, self.lo, self.hi, clock())
+            peak = ln.ctx.mem_info()["pool_peak"]
+            # working set of the group's temporaries per ciphertext (its outputs stay allocated too)
+            per = max(0, peak - before) / len(work)
+            self.ws[key[0]] = max(self.ws.get(key[0], 0), per)
+            moved += len(work)
+        self.max_in_flight = max(self.max_in_flight, sum(1 for ln in self.lanes if ln.group is not None))
+        return moved
+
+    def busy(self):
+        return bool(self.queue or self.active or any(ln.group is not None for ln in self.lanes))
 
 
-def run_continuous(ctx, table, requests, max_batch=64, mem_budget=None):
+def run_continuous(lanes, table, requests, max_batch=64, reserve_bytes=1 << 30, poll_s=2e-4):
     """Serve `requests` (arrival times relative to start) with continuous
-    batching; returns the server (requests carry admitted/done times)."""
-    srv = Server(ctx, table, max_batch=max_batch, mem_budget=mem_budget)
+    batching on `lanes` (contexts, or Lane objects with their streams);
+    returns the server (requests carry admitted/done times)."""
+    srv = Server(lanes, table, max_batch=max_batch, reserve_bytes=reserve_bytes)
     pending = sorted(requests, key=lambda r: r.arrival)
+    for ln in srv.lanes:
+        ln.start_clock()
     t0 = time.perf_counter()
     clock = lambda: time.perf_counter() - t0
     i = 0
-    while i < len(pending) or srv.queue or srv.active:
+    while i < len(pending) or srv.busy():
         now = clock()
         while i < len(pending) and pending[i].arrival <= now:
             srv.submit(pending[i])
             i += 1
-        if not srv.queue and not srv.active:
-            time.sleep(max(0.0, pending[i].arrival - clock()))
+        if srv.step(clock) or srv.last_finished:
             continue
-        srv.step(clock)
+        # nothing issued or finished: wait for the next arrival or poll again
+        nxt = pending[i].arrival - clock() if i < len(pending) else poll_s
+        time.sleep(max(0.0, min(poll_s, nxt)) if srv.busy() else max(0.0, nxt))
     return srv
 
 
@@ -172,18 +268,33 @@ DEFAULT_TABLE = {"8": {"1e-06": {"degree": 31, "c": 0, "iters": 3}, "1e-07": {"d
                        "3.1e-08": {"degree": 31, "c": 0, "iters": 3}}}
 
 
+def make_lanes(n, keys_seed=9, params="p16b"):
+    """n contexts of one parameter set with the same keys (the same seed),
+    each on a torch stream of its own at the default priority."""
+    import torch
+
+    from . import ckks
+    lanes = []
+    for _ in range(n):
+        s = torch.cuda.Stream()
+        ctx = ckks.Context.from_set(params, stream=s.cuda_stream)
+        ctx.keygen(keys_seed, ctx.bts_galois())
+        lanes.append(Lane(ctx, s))
+    return lanes
+
+
 def main(argv=None):
     """Serving sweep at N = 2^16 on the bootstrapping parameter set (relin,
     rotation and conjugation keys resident): Poisson arrivals at each rate,
     request sizes Geometric(0.25) truncated to [1, 32], levels in [5, 8] and
-    MRE targets drawn per request; continuous batching versus one request at a
-    time."""
+    MRE targets drawn per request; continuous batching on several lanes
+    versus one request at a time."""
     import argparse
     import json
 
     import torch
 
-    from . import ckks, inputs
+    from . import inputs
 
     ap = argparse.ArgumentParser()
     ap.add_argument("--rates", default="10,40,160")
@@ -193,6 +304,7 @@ def main(argv=None):
                     help="tuning JSON from paper_2606_10477_amd.tune")
     ap.add_argument("--max-batch", type=int, default=16,
                     help="ciphertexts per launch sequence (bootstrapping throughput saturates near 8-16)")
+    ap.add_argument("--lanes", type=int, default=2, help="contexts on streams of their own")
     ap.add_argument("--out", default=None)
     args = ap.parse_args(argv)
     table = DEFAULT_TABLE
@@ -200,12 +312,12 @@ def main(argv=None):
         with open(args.table) as f:
             table = json.load(f)["table"]
     torch.cuda.set_device(0)
-    ctx = ckks.Context.from_set("p16b")
-    ctx.keygen(9, ctx.bts_galois())
+    lanes = make_lanes(args.lanes)
+    ctx = lanes[0].ctx
     levels = [int(v) for v in args.levels.split(",")]
     out = {"workload": "CryptoInvSqrt serving at N=2^16 with bootstrapping keys resident, Poisson arrivals, "
                        f"sizes Geometric(0.25) in [1,32], levels {levels}, targets 1e-6/1e-7/3.1e-8",
-           "table": args.table, "runs": []}
+           "table": args.table, "lanes": args.lanes, "runs": []}
     for rate in [float(v) for v in args.rates.split(",")]:
         n = args.requests
         arr = inputs.poisson_arrivals(n, rate, 40)
@@ -220,14 +332,16 @@ def main(argv=None):
         ctx.sync()
         res = {}
         # every mode runs twice on the same ciphertexts; the first pass warms
-        # the device memory pool and is not reported
+        # the device memory pools and is not reported
         for mode in ("continuous", "one_at_a_time"):
             for rep in range(2):
                 reqs = [Request(k, float(arr[k]), cts[k], lv[k], tg[k]) for k in range(n)]
                 if mode == "continuous":
-                    srv = run_continuous(ctx, table, reqs, max_batch=args.max_batch)
+                    srv = run_continuous(lanes, table, reqs, max_batch=args.max_batch)
                     s = summarize(reqs)
                     s["mean_batch"] = float(np.mean([e["batch"] for e in srv.log]))
+                    s["max_groups_in_flight"] = srv.max_in_flight
+                    s["working_set_per_ct_mib"] = {str(k): round(v / 2 ** 20, 1) for k, v in sorted(srv.ws.items())}
                 else:
                     run_one_at_a_time(ctx, table, reqs)
                     s = summarize(reqs)
@@ -241,7 +355,8 @@ def main(argv=None):
     if args.out:
         with open(args.out, "w") as f:
             json.dump(out, f)
-    ctx.close()
+    for ln in lanes:
+        ln.ctx.close()
 
 
 if __name__ == "__main__":

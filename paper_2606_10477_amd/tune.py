@@ -37,9 +37,12 @@ def run(levels, degrees, iters, targets, lo, hi, batch, reps, fixed, tuner_seed=
     bts = params == "bts"
     ctx = ckks.Context.from_set("p16b" if bts else "p16")   # plain set: 27 levels, no bootstrapping
     ctx.keygen(tuner_seed, ctx.bts_galois() if bts else [])      # the tuner's own keys, not a client's
+    Bpre = 0.0
     if domain == "paper":
-        # the paper's own workload (§5.1): linspace over [0.001, 100], pre-normalised by B = 100
-        x = np.linspace(0.001, 100.0, ctx.n) / 100.0
+        # the paper's own workload (§5.1): linspace over [0.001, 100] encrypted as it is, pre-normalised
+        # by B = 100 inside the chain (§2.3) and scaled back by 1/sqrt(B)
+        x = inputs.linspace_input(ctx.n, lo, hi)
+        Bpre = 100.0
     else:
         x = inputs.log_uniform(ctx.n, lo, hi, 11)
     cts = {l: ctx.encrypt(x, l, 2.0 ** 50, 12 + l) for l in levels}
@@ -47,7 +50,7 @@ def run(levels, degrees, iters, targets, lo, hi, batch, reps, fixed, tuner_seed=
         # Alg. 3's cases with l_BTS = 0, l_afterBTS = l_max = the chain's top computation level
         cases = tuner.level_cases(0, ctx.l_after, ctx.l_after)
         cs = {l: cases.get(l, [0]) or [0] for l in levels}
-        bound = 16 * int(math.ceil(1.0 / math.sqrt(lo)))
+        bound = 16 * int(math.ceil(1.0 / math.sqrt(lo / (Bpre or 1.0))))
         prof_levels = list(range(0, ctx.l_after + 1))
     else:
         cs = {l: [0] for l in levels}      # no bootstrapping: x is never bootstrapped
@@ -60,7 +63,8 @@ def run(levels, degrees, iters, targets, lo, hi, batch, reps, fixed, tuner_seed=
         bt = costs.get(("bootstrap", tuner.BTS_ANY_LEVEL))
         print(f"profiled {len(costs)} unit costs" + (f" (bootstrap {bt * 1e3:.1f} ms)" if bt else ""),
               file=sys.stderr, flush=True)
-    rows = tuner.sweep(ctx, x, cts, degrees, iters, lo, hi, batch=batch, reps=reps, costs=costs, cs_by_level=cs)
+    rows = tuner.sweep(ctx, x, cts, degrees, iters, lo, hi, batch=batch, reps=reps, costs=costs, cs_by_level=cs,
+                       B=Bpre)
     table = {}
     for l in levels:
         for tgt in targets:
@@ -82,10 +86,11 @@ def run(levels, degrees, iters, targets, lo, hi, batch, reps, fixed, tuner_seed=
     ok = [r for r in rows if r.get("ok")]
     err = [abs(r["t_pred"] - r["t"]) / r["t"] for r in ok]
     report = {
-        "params": ("N=2^16, log2 QP 1556: q0 60-bit, 10 x 40-bit, 13 x 52-bit, 7 x 60-bit special, dnum 3, h 192; "
-                   "l_BTS 0, l_afterBTS = l_max 8") if bts else
+        "params": ("p16b: N=2^16, log2 QP 1544: q0 60-bit, 11 x 40-bit, 12 x 52-bit, 7 x 60-bit special, dnum 3, "
+                   "h 192; l_BTS 0, l_afterBTS = l_max 8") if bts else
                   "N=2^16, q0 60-bit + 27 x 40-bit, 7 x 60-bit special, dnum 3, h 192; no bootstrapping",
-        "input": (f"x = linspace(0.001, 100, N/2) / 100 (B = 100), interval [{lo}, {hi}], encrypted at scale 2^50"
+        "input": (f"x = linspace({lo}, {hi}, N/2) encrypted at scale 2^50, pre-normalised by B = 100 in the chain "
+                  f"(Chebyshev on [{lo / 100}, {hi / 100}]), scaled back by 1/sqrt(B)"
                   if domain == "paper" else f"x log-uniform in [{lo}, {hi}], encrypted at scale 2^50"),
         "fixed": list(fixed),
         "batch": batch, "grid": {"degrees": degrees, "iters": iters, "levels": levels, "c": cs},
@@ -111,14 +116,14 @@ def main(argv=None):
     ap.add_argument("--batch", type=int, default=1)
     ap.add_argument("--reps", type=int, default=3)
     ap.add_argument("--domain", choices=["logu", "paper"], default="logu",
-                    help="logu: x log-uniform in [2^-10, 1]; paper: linspace(0.001, 100) / 100 on [1e-5, 1]")
+                    help="logu: x log-uniform in [2^-10, 1]; paper: linspace(0.001, 100) with B = 100 in the chain")
     ap.add_argument("--fixed", default="31,3", help="fixed (degree, iterations) the tuned choice is compared with")
     ap.add_argument("--params", choices=["bts", "plain"], default="bts",
                     help="bts: the bootstrapping set (levels 3-8); plain: 27 levels, no bootstrapping "
                          "(use e.g. --levels 13,17,21,27)")
     args = ap.parse_args(argv)
     ints = lambda s: [int(v) for v in s.split(",")]
-    lo, hi = (1e-5, 1.0) if args.domain == "paper" else (2.0 ** -10, 1.0)
+    lo, hi = (0.001, 100.0) if args.domain == "paper" else (2.0 ** -10, 1.0)
     rep = run(ints(args.levels), ints(args.degrees), ints(args.iters),
               [float(v) for v in args.targets.split(",")], lo, hi, args.batch, args.reps, tuple(ints(args.fixed)),
               domain=args.domain, params=args.params)

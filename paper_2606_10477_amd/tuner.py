@@ -215,30 +215,31 @@ def predict(trace, costs, base_batch=1):
 # --------------------------------------------------------------------------
 # Sweep and selection (one MI355X, encrypted runs with the tuner's own keys)
 # --------------------------------------------------------------------------
-def sweep(ctx, x, ct_by_level, degrees, iters, lo, hi, batch=1, reps=3, costs=None, cs_by_level=None):
+def sweep(ctx, x, ct_by_level, degrees, iters, lo, hi, batch=1, reps=3, costs=None, cs_by_level=None, B=0.0):
     """For each input level, Pre-BTS indicator c (cs_by_level[level], default
     [0]) and (degree, iterations): MRE of the decrypted result against FP64
     1/sqrt(x), measured time (median of `reps`, all `batch` ciphertexts), the
     operation trace (bootstraps counted) and the predicted time.  Settings
-    that do not fit the levels are recorded with ok=False."""
+    that do not fit the levels are recorded with ok=False.  B > 1: the
+    chain pre-normalises x by B homomorphically (x in [lo, hi])."""
     ref = 1.0 / np.sqrt(x)
     rows = []
     for lvl, ct in ct_by_level.items():
         for c in (cs_by_level or {}).get(lvl, [0]):
             for d in degrees:
                 for it in iters:
-                    rows.append(_measure(ctx, ct, lvl, c, d, it, lo, hi, batch, reps, costs, ref))
+                    rows.append(_measure(ctx, ct, lvl, c, d, it, lo, hi, batch, reps, costs, ref, B))
     return rows
 
 
-def _measure(ctx, ct, lvl, c, d, it, lo, hi, batch, reps, costs, ref):
+def _measure(ctx, ct, lvl, c, d, it, lo, hi, batch, reps, costs, ref, B=0.0):
     from .ckks import CkksError
     cts = [ct] * batch
 
     def run():
         if batch == 1:
-            return ctx.invsqrt(ct, d, it, a=lo, b=hi, pre_bts=bool(c))
-        return ctx.invsqrt_batch(cts, d, it, a=lo, b=hi, pre_bts=bool(c))[0]
+            return ctx.invsqrt(ct, d, it, a=lo, b=hi, pre_bts=bool(c), B=B)
+        return ctx.invsqrt_batch(cts, d, it, a=lo, b=hi, pre_bts=bool(c), B=B)[0]
 
     row = {"level": lvl, "d": d, "i": it, "c": c}
     try:

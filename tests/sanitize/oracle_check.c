@@ -31,7 +31,7 @@ int orc_rotate_hoisted(orc_ctx *c, const orc_ct *a, const int *steps, int n, orc
 int orc_cheb_coeffs_invsqrt(int d, double a, double b, double *out);
 orc_ct *orc_cheb_eval(orc_ctx *c, const orc_ct *x, const double *cf, int d, double a, double b);
 orc_ct *orc_invsqrt(orc_ctx *c, const orc_ct *x, int d, int iters, double a, double b, int literal, int64_t bts_bound,
-                    int pre_bts);
+                    int pre_bts, double B);
 int orc_bts_config(orc_ctx *c, double Kp, int r, int deg);
 int orc_bts_rotations(orc_ctx *c, int32_t *out, int max);
 orc_ct *orc_bootstrap(orc_ctx *c, const orc_ct *a, int64_t M);
@@ -76,12 +76,13 @@ int main(void) {
     double cf[32];
     orc_cheb_coeffs_invsqrt(31, ldexp(1.0, -8), 1.0, cf);
     orc_ct *y = orc_cheb_eval(c, a, cf, 31, ldexp(1.0, -8), 1.0);
-    orc_ct *z = orc_invsqrt(c, a, 15, 2, ldexp(1.0, -8), 1.0, 0, 0, 0);
-    if (!s || !d || !h || !p || !r || !m || !ro || !cj || !y || !z) return 5;
+    orc_ct *z = orc_invsqrt(c, a, 15, 2, ldexp(1.0, -8), 1.0, 0, 0, 0, 0.0);
+    orc_ct *zb = orc_invsqrt(c, a, 14, 1, ldexp(1.0, -8), 1.0, 0, 0, 0, 100.0);
+    if (!s || !d || !h || !p || !r || !m || !ro || !cj || !y || !z || !zb) return 5;
     printf("plain: cheb(31) max rel err %.3g, invsqrt(15,2) max rel err %.3g\n", max_rel(c, y, inv, n),
            max_rel(c, z, inv, n));
     fflush(stdout);
-    orc_ct *all[] = {a, s, d, h, p, r, m, ro, cj, y, z, hs[0], hs[1], hs[2]};
+    orc_ct *all[] = {a, s, d, h, p, r, m, ro, cj, y, z, zb, hs[0], hs[1], hs[2]};
     for (unsigned i = 0; i < sizeof(all) / sizeof(all[0]); i++) orc_ct_free(all[i]);
     orc_ctx_free(c);
 
@@ -97,8 +98,8 @@ int main(void) {
     if (orc_keygen(b, 9, bg, nr + 1)) return 8;
     free(bg);
     orc_ct *bx = orc_encrypt(b, x, n, 5, ldexp(1.0, 50), 5);
-    orc_ct *bl = orc_invsqrt(b, bx, 15, 3, ldexp(1.0, -8), 1.0, 1, 0, 0);
-    orc_ct *bp = orc_invsqrt(b, bx, 7, 2, ldexp(1.0, -8), 1.0, 0, 0, 1);
+    orc_ct *bl = orc_invsqrt(b, bx, 15, 3, ldexp(1.0, -8), 1.0, 1, 0, 0, 0.0);
+    orc_ct *bp = orc_invsqrt(b, bx, 7, 2, ldexp(1.0, -8), 1.0, 0, 0, 1, 0.0);
     orc_ct *bb = orc_bootstrap(b, bx, 16);
     if (!bx || !bl || !bp || !bb) {
         printf("bootstrapping step failed: %d %d %d %d: %s\n", !bx, !bl, !bp, !bb, orc_last_error());

@@ -142,6 +142,24 @@ def test_invsqrt_with_bootstrapping_bit_exact(pair, degree, iters, level, litera
         assert mre < 1e-7
 
 
+@pytest.mark.parametrize("degree,iters", [(14, 3), (30, 2)])
+def test_invsqrt_prenormalised_paper_domain_bit_exact(pair, degree, iters):
+    """The paper's domain and pre-normalisation (§2.3, §4.3: linspace over
+    [0.001, 100], B = 100, degrees 2^d_e - 2) from the top level with lazy
+    bootstrapping: GPU words equal the oracle's; accuracy against 1/sqrt(x)."""
+    g, o = pair
+    A, Bv = 0.001, 100.0
+    x = np.linspace(A, Bv, g.n)
+    gc, oc = g.encrypt(x, 8, 2.0 ** 50, 74), o.encrypt(x, 8, 2.0 ** 50, 74)
+    gy = g.invsqrt(gc, degree, iters, A, Bv, B=100.0)
+    oy = o.invsqrt(oc, degree, iters, A, Bv, B=100.0)
+    same(gy, oy)
+    ref = 1 / np.sqrt(x)
+    mre = np.mean(np.abs(g.decrypt(gy).real - ref) / ref)
+    print(f"N=2^10 paper domain ({degree},{iters}) B=100: MRE {mre:.3g}", flush=True)
+    assert mre < 1e-2
+
+
 @pytest.fixture(scope="module")
 def full():
     ck = _ck()

@@ -172,8 +172,19 @@ def test_moments_batched_bit_exact_vs_oracle(small):
 
 
 def test_serving_alone_equals_in_the_mix(small):
-    from paper_2606_10477_amd import serve
+    """Continuous batching on two lanes (contexts with the same keys, each on
+    a stream of its own): groups of different requests run on the device at
+    the same time, and every result equals the request run alone."""
+    import torch
+    from paper_2606_10477_amd import ckks, serve
     g, _ = small
+    gal = [g.galois_rot(1 << k) for k in range(11)]
+    lanes = []
+    for _ in range(2):
+        st = torch.cuda.Stream()
+        lc = ckks.Context(**SMALL, stream=st.cuda_stream)
+        lc.keygen(5, gal)
+        lanes.append(serve.Lane(lc, st))
     table = {"12": {"1e-06": {"degree": 15, "iters": 2}, "3.1e-08": {"degree": 15, "iters": 3}},
              "16": {"1e-06": {"degree": 7, "iters": 3}, "3.1e-08": {"degree": 31, "iters": 3}}}
     sizes = [3, 1, 4, 2, 2]
@@ -184,12 +195,22 @@ def test_serving_alone_equals_in_the_mix(small):
         X = np.stack([inputs.log_uniform(g.n, 2 ** -10, 1.0, 300 + 10 * k + j) for j in range(sizes[k])])
         cts = g.encrypt_batch(X, levels[k], 2.0 ** 45, 500 + 10 * k)
         reqs.append(serve.Request(k, 0.0, cts, levels[k], targets[k]))
-    srv = serve.run_continuous(g, table, reqs, max_batch=16)
+    g.sync()
+    srv = serve.run_continuous(lanes, table, reqs, max_batch=16, reserve_bytes=0)
     assert any(e["batch"] > max(sizes) for e in srv.log)   # requests shared a launch sequence
+    assert srv.max_in_flight == 2                          # two groups on the device at once
+    assert {e["lane"] for e in srv.log} == {0, 1}
+    for ln in lanes:
+        ln.ctx.sync()
     for r in reqs:
+        assert r.done is not None and r.done >= r.arrival
         alone = g.invsqrt_batch(r.cts, r.degree, r.iters)
         for k, y in enumerate(alone):
             assert np.array_equal(r.outs[k].words(), y.words())
+    for r in reqs:
+        r.outs = {}
+    for ln in lanes:
+        ln.ctx.close()
 
 
 def test_znorm_full_size_accuracy():

@@ -525,3 +525,29 @@ def test_invsqrt_small_ring_matches_plain_chain(oracle_mod, p12):
     assert abs(mre_plain - 2.7e-5) < 0.1e-5
     assert abs(mre - mre_plain) < 0.02 * mre_plain
     assert np.max(np.abs(z - plain) / ref) < 1e-6
+
+
+def test_invsqrt_prenormalised_matches_plain_chain(oracle_mod, p12):
+    """Pre-normalisation (§2.3; B = 100 and the domain [0.001, 100] of the
+    paper's experiments): the chain runs on u = x/B and is scaled back by
+    1/sqrt(B), so the result follows the FP64 chain on u times 1/sqrt(B) (the
+    Chebyshev interpolant on [a/B, b/B] evaluated at u, then the Newton
+    iteration of §2.2 with u), within CKKS noise; the levels are those of
+    the chain without B (the division by B shares the affine map's level and
+    the scale-back costs none).  With B = 1 (or 0) the words are those of
+    the chain without pre-normalisation."""
+    A, Bv, Bn = 0.001, 100.0, 100.0
+    x = inputs.linspace_input(p12.n, A, Bv)
+    ct = p12.encrypt(x, 13, 2.0 ** 50, 13)
+    u = x / Bn
+    ref = 1 / np.sqrt(x)
+    for d, it in ((14, 2), (14, 0), (30, 1)):
+        cf = oracle_mod.cheb_coeffs_invsqrt(d, A / Bn, Bv / Bn)
+        y = p12.invsqrt(ct, d, it, A, Bv, B=Bn)
+        assert y.level == 13 - 1 - d.bit_length() - 2 * it
+        want = _plain_chain(u, cf, A / Bn, Bv / Bn, it)[-1] / np.sqrt(Bn)
+        z = p12.decrypt(y).real
+        assert np.max(np.abs(z - want) / ref) < 1e-5
+    base = p12.invsqrt(ct, 15, 2, A, Bv)
+    for b1 in (0.0, 1.0):
+        assert np.array_equal(p12.invsqrt(ct, 15, 2, A, Bv, B=b1).words(), base.words())

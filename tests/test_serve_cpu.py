@@ -10,17 +10,31 @@ class FakeCt:
 
 
 class FakeCtx:
+    """Stands in for a library context: records launches, finishes them at
+    once (or when told), reports memory figures."""
     N = 1 << 12
 
-    def __init__(self):
+    def __init__(self, free=1 << 40, immediate=True):
         self.calls = []
+        self.free = free
+        self.immediate = immediate
+        self.pending = False
+        self.in_use = 0
 
     def invsqrt_batch(self, cts, degree, iters, a=None, b=None, pre_bts=False):
         self.calls.append((len(cts), degree, iters) + ((1,) if pre_bts else ()))
+        self.pending = not self.immediate
         return [FakeCt(("y", c.tag, degree, iters)) for c in cts]
 
+    def stream_done(self):
+        return not self.pending
+
+    def mem_info(self, reset_peak=False):
+        return {"device_free": self.free, "pool_cached": 0, "pool_in_use": self.in_use, "pool_peak": self.in_use,
+                "ct_bytes": [2 * (l + 1) * self.N * 8 for l in range(32)]}
+
     def sync(self):
-        pass
+        self.pending = False
 
 
 TABLE = {"13": {"1e-06": {"degree": 15, "iters": 2}, "1e-07": {"degree": 31, "iters": 2},
@@ -48,7 +62,7 @@ def test_lookup_exact_and_fallback():
 
 def test_groups_share_one_batch_and_results_are_attributed():
     ctx = FakeCtx()
-    srv = serve.Server(ctx, TABLE, max_batch=64, mem_budget=1 << 40)
+    srv = serve.Server(ctx, TABLE, max_batch=64, reserve_bytes=0)
     for r in [mk(0, 0.0, 3, 13, 3.1e-8), mk(1, 0.0, 5, 13, 3.1e-8), mk(2, 0.0, 2, 17, 1e-6)]:
         srv.submit(r)
     reqs = list(srv.queue)
@@ -57,6 +71,7 @@ def test_groups_share_one_batch_and_results_are_attributed():
     assert ctx.calls[-1] == (8, 31, 3)
     assert srv.step(clock) == 2
     assert ctx.calls[-1] == (2, 7, 3)
+    assert srv.step(clock) == 0 and not srv.busy()   # the last group collected
     for r in reqs:
         assert r.done == 1.0 and len(r.outs) == len(r.cts)
         for k, y in r.outs.items():
@@ -65,7 +80,7 @@ def test_groups_share_one_batch_and_results_are_attributed():
 
 def test_pre_bts_setting_is_its_own_group():
     ctx = FakeCtx()
-    srv = serve.Server(ctx, TABLE, max_batch=64, mem_budget=1 << 40)
+    srv = serve.Server(ctx, TABLE, max_batch=64, reserve_bytes=0)
     for r in [mk(0, 0.0, 2, 20, 1e-6), mk(1, 0.5, 3, 13, 1e-6)]:
         srv.submit(r)
     clock = lambda: 1.0
@@ -73,11 +88,13 @@ def test_pre_bts_setting_is_its_own_group():
     assert ctx.calls[-1] == (2, 15, 3, 1)      # bootstraps x first
     assert srv.step(clock) == 3
     assert ctx.calls[-1] == (3, 15, 2)
+    srv.step(clock)
+    assert not srv.busy()
 
 
 def test_max_batch_splits_and_request_completes_when_all_parts_done():
     ctx = FakeCtx()
-    srv = serve.Server(ctx, TABLE, max_batch=4, mem_budget=1 << 40)
+    srv = serve.Server(ctx, TABLE, max_batch=4, reserve_bytes=0)
     r = mk(0, 0.0, 10, 13, 1e-6)
     srv.submit(r)
     sizes = []
@@ -86,25 +103,52 @@ def test_max_batch_splits_and_request_completes_when_all_parts_done():
     def clock():
         t[0] += 1
         return t[0]
-    while srv.queue or srv.active:
+    while srv.busy():
         sizes.append(srv.step(clock))
-    assert sizes == [4, 4, 2]
+    # each round collects the finished group and issues the next one
+    assert sizes == [4, 4, 2, 0]
+    assert [e["batch"] for e in srv.log] == [4, 4, 2]
     assert r.done is not None and sorted(r.outs) == list(range(10))
 
 
-def test_admission_by_memory_budget():
-    ctx = FakeCtx()
-    one = 2 * 14 * FakeCtx.N * 8 * 24       # estimate of one ciphertext at level 13
-    srv = serve.Server(ctx, TABLE, max_batch=64, mem_budget=3 * one)
+def test_admission_by_the_librarys_free_memory():
+    one = 2 * 14 * FakeCtx.N * 8 * 24       # first estimate for one ciphertext at level 13
+    ctx = FakeCtx(free=3 * one, immediate=False)
+    srv = serve.Server(ctx, TABLE, max_batch=64, reserve_bytes=0)
     a, b = mk(0, 0.0, 2, 13, 3.1e-8), mk(1, 0.1, 2, 13, 3.1e-8)
     srv.submit(a)
     srv.submit(b)
     srv._admit(0.0)
     assert srv.active == [a] and srv.queue == [b]   # b must wait for memory
-    srv.step(lambda: 1.0)
-    assert a.done == 1.0
-    srv.step(lambda: 2.0)                           # b admitted once a's memory is released
-    assert b.done == 2.0
+    assert srv.step(lambda: 1.0) == 2               # a issued, still running
+    assert a.done is None and srv.queue == [b]
+    ctx.sync()                                      # a's group completes ...
+    ctx.free = 10 * one                             # ... and its memory is free again
+    srv.step(lambda: 2.0)
+    assert a.done == 2.0 and b.admitted == 2.0      # b admitted once the memory is there
+    ctx.sync()
+    srv.step(lambda: 3.0)
+    assert b.done == 3.0
+
+
+def test_two_lanes_overlap_groups():
+    """A request arriving while another's group runs on lane 0 starts on
+    lane 1 before lane 0 finishes; each lane's results go to its requests."""
+    l0, l1 = FakeCtx(immediate=False), FakeCtx(immediate=False)
+    srv = serve.Server([l0, l1], TABLE, max_batch=64, reserve_bytes=0)
+    a, b = mk(0, 0.0, 3, 13, 3.1e-8), mk(1, 0.1, 2, 17, 1e-6)
+    srv.submit(a)
+    assert srv.step(lambda: 0.0) == 3 and l0.calls == [(3, 31, 3)]
+    srv.submit(b)
+    assert srv.step(lambda: 0.2) == 2 and l1.calls == [(2, 7, 3)]   # lane 0 is still busy
+    assert srv.max_in_flight == 2 and a.done is None and b.done is None
+    l1.sync()
+    srv.step(lambda: 0.3)
+    assert b.done == 0.3 and a.done is None
+    l0.sync()
+    srv.step(lambda: 0.5)
+    assert a.done == 0.5 and not srv.busy()
+    assert {k: y.tag for k, y in a.outs.items()} == {k: ("y", (0, k), 31, 3) for k in range(3)}
 
 
 def test_summary():
