@@ -395,11 +395,25 @@ ckks_status ckks_ntt_device(ckks_ctx *ctx, uint64_t *data, uint32_t n_limbs,
  * `r4_max_limbs` limbs in total runs with 4 words per thread, one of at most
  * `r8_max_limbs` limbs with 8, larger calls with 16: fewer words per thread
  * give more, shorter waves (better for small calls), more words fewer LDS
- * exchanges (better for large ones).  -1 restores the library's default for
- * that bound; values below -1 give CKKS_E_PARAM.  Takes effect for launches
- * issued after the call.
+ * exchanges (better for large ones).  A 4-word call of at most `s4_max_limbs`
+ * limbs puts 4 sub-transforms of 256 points in each workgroup instead of 16
+ * (four times as many workgroups for calls too small to fill the chip).  -1
+ * restores the library's default for that bound; values below -1 give
+ * CKKS_E_PARAM.  Takes effect for launches issued after the call.
  */
-ckks_status ckks_ntt_schedule(ckks_ctx *ctx, int32_t r4_max_limbs, int32_t r8_max_limbs);
+ckks_status ckks_ntt_schedule(ckks_ctx *ctx, int32_t r4_max_limbs, int32_t r8_max_limbs,
+                              int32_t s4_max_limbs);
+
+/*
+ * Arithmetic of the N = 2^16 transforms (a tuning knob; results are identical
+ * either way): limbs whose prime is below 2^fp64_max_bits run their
+ * butterflies in binary64 (an error-free product and a rounded quotient by
+ * FMA, exact for primes below 2^42), the others on 64-bit integers.
+ * fp64_max_bits = 0: integers for every prime; -1: the default (42); values
+ * above 42 or below -1 give CKKS_E_PARAM.  Takes effect for launches issued
+ * after the call; a transform's two passes must run under one setting.
+ */
+ckks_status ckks_ntt_arith(ckks_ctx *ctx, int32_t fp64_max_bits);
 
 /*
  * Opt-in timing of kernel families on the context's stream (HIP events

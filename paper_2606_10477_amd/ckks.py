@@ -93,7 +93,8 @@ SIGNATURES = {
     "ckks_invsqrt_batch": (C.c_int, [vp, C.POINTER(vp), C.c_uint32, C.c_uint32, C.c_uint32,
                                      C.POINTER(InvsqrtOpts), C.POINTER(vp)]),
     "ckks_ntt_device": (C.c_int, [vp, C.c_void_p, C.c_uint32, u32p, C.c_int]),
-    "ckks_ntt_schedule": (C.c_int, [vp, C.c_int32, C.c_int32]),
+    "ckks_ntt_schedule": (C.c_int, [vp, C.c_int32, C.c_int32, C.c_int32]),
+    "ckks_ntt_arith": (C.c_int, [vp, C.c_int32]),
     "ckks_invsqrt_graph_create": (C.c_int, [vp, vp, C.c_uint32, C.c_uint32, C.POINTER(InvsqrtOpts),
                                             C.POINTER(vp)]),
     "ckks_invsqrt_graph_run": (C.c_int, [vp, vp, vp, C.POINTER(vp)]),
@@ -452,9 +453,14 @@ class Context:
         self._chk(lib().ckks_ct_unpack(self.ptr, batch.ptr, outs))
         return [Ciphertext(self, outs[i]) for i in range(B)]
 
-    def ntt_schedule(self, r4_max_limbs, r8_max_limbs):
-        """Words per thread of the N = 2^16 transforms by call size."""
-        self._chk(lib().ckks_ntt_schedule(self.ptr, int(r4_max_limbs), int(r8_max_limbs)))
+    def ntt_schedule(self, r4_max_limbs, r8_max_limbs, s4_max_limbs=-1):
+        """Words per thread (and, for 4 words, sub-transforms per workgroup)
+        of the N = 2^16 transforms by call size."""
+        self._chk(lib().ckks_ntt_schedule(self.ptr, int(r4_max_limbs), int(r8_max_limbs), int(s4_max_limbs)))
+
+    def ntt_arith(self, fp64_max_bits):
+        """Primes below 2^fp64_max_bits transform in binary64 (0: none, -1: default)."""
+        self._chk(lib().ckks_ntt_arith(self.ptr, int(fp64_max_bits)))
 
     def ntt_device(self, ptr, n_limbs, prime_idx, inverse=False):
         pi = np.ascontiguousarray(prime_idx, dtype=np.uint32)

@@ -229,6 +229,12 @@ struct BtsPlan;
 // calls of at most this many limbs in total use 4 / 8 words per thread.
 constexpr int kNttR4Max = 32;
 constexpr int kNttR8Max = 32;
+// 4-word calls of at most this many limbs put 4 sub-transforms in a workgroup
+constexpr int kNttS4Max = 32;
+// N = 2^16 transforms of primes below 2^kNttFpBits run their butterflies in
+// binary64 (exact: the bounds are in kernels.hip); larger primes on 64-bit
+// integers.  The largest value the binary64 path accepts.
+constexpr int kNttFpBits = 42;
 
 struct ckks_ctx {
     ckks_params prm;
@@ -243,6 +249,7 @@ struct ckks_ctx {
     std::unique_ptr<Pool> pool;
     gpu::Tables T;
     Buf d_primes, d_fw, d_fwsh, d_iw, d_iwsh, d_ninv, d_ninvsh;
+    Buf d_fwd, d_fwqd, d_iwd, d_iwqd, d_pd;   // binary64 twiddles and prime constants
     Buf d_rsinv, d_rsinvsh;       // [L+1][L+1]: (q_l)^-1 mod q_i and Shoup quotient, for rescale from level l
     Buf d_pinv, d_pinvsh;         // [L+1]: P^-1 mod q_i and Shoup quotient (ModDown)
     Buf d_pqinv, d_pqinvsh;       // [L+1][L+1]: (P q_l)^-1 mod q_i (ModDown merged with the rescale from l)
@@ -407,6 +414,8 @@ void build_tables(ckks_ctx *c) {
     std::vector<u64> fw((size_t)np * N), fwsh((size_t)np * N), iw((size_t)np * N), iwsh((size_t)np * N);
     std::vector<u64> ninv(np), ninvsh(np);
     std::vector<u64> pw(N);
+    std::vector<double> fwd((size_t)np * N), fwqd((size_t)np * N), iwd((size_t)np * N), iwqd((size_t)np * N);
+    std::vector<double> pd((size_t)np * 4);
     for (int i = 0; i < np; ++i) {
         const u64 q = c->q[i];
         int n = 64 - __builtin_clzll(q);
@@ -430,6 +439,17 @@ void build_tables(ckks_ctx *c) {
         }
         ninv[i] = hm::invmod((u64)N, q);
         ninvsh[i] = shoup(ninv[i], q);
+        const double qd = (double)q;
+        for (int k = 0; k < N; ++k) {
+            fwd[(size_t)i * N + k] = (double)fw[(size_t)i * N + k];
+            fwqd[(size_t)i * N + k] = (double)fw[(size_t)i * N + k] / qd;
+            iwd[(size_t)i * N + k] = (double)iw[(size_t)i * N + k];
+            iwqd[(size_t)i * N + k] = (double)iw[(size_t)i * N + k] / qd;
+        }
+        pd[(size_t)i * 4 + 0] = qd;
+        pd[(size_t)i * 4 + 1] = 1.0 / qd;
+        pd[(size_t)i * 4 + 2] = (double)ninv[i];
+        pd[(size_t)i * 4 + 3] = (double)ninv[i] / qd;
     }
     Pool *P = c->pool.get();
     c->d_primes = Buf(P, (np * sizeof(gpu::DevPrime) + 7) / 8);
@@ -446,6 +466,18 @@ void build_tables(ckks_ctx *c) {
     upload(c->d_iwsh, iwsh.data(), iwsh.size() * 8, c->stream);
     upload(c->d_ninv, ninv.data(), np * 8, c->stream);
     upload(c->d_ninvsh, ninvsh.data(), np * 8, c->stream);
+    if (c->logN == 16) {
+        c->d_fwd = Buf(P, (size_t)np * N);
+        c->d_fwqd = Buf(P, (size_t)np * N);
+        c->d_iwd = Buf(P, (size_t)np * N);
+        c->d_iwqd = Buf(P, (size_t)np * N);
+        upload(c->d_fwd, fwd.data(), fwd.size() * 8, c->stream);
+        upload(c->d_fwqd, fwqd.data(), fwqd.size() * 8, c->stream);
+        upload(c->d_iwd, iwd.data(), iwd.size() * 8, c->stream);
+        upload(c->d_iwqd, iwqd.data(), iwqd.size() * 8, c->stream);
+    }
+    c->d_pd = Buf(P, (size_t)np * 4);
+    upload(c->d_pd, pd.data(), pd.size() * 8, c->stream);
     {
         const int L1 = c->L + 1;
         std::vector<u64> rs((size_t)L1 * L1, 0), rssh((size_t)L1 * L1, 0);
@@ -488,9 +520,16 @@ void build_tables(ckks_ctx *c) {
     c->T.iw_sh = c->d_iwsh.p;
     c->T.ninv = c->d_ninv.p;
     c->T.ninv_sh = c->d_ninvsh.p;
+    c->T.fw_d = (const double *)c->d_fwd.p;
+    c->T.fwq_d = (const double *)c->d_fwqd.p;
+    c->T.iw_d = (const double *)c->d_iwd.p;
+    c->T.iwq_d = (const double *)c->d_iwqd.p;
+    c->T.pd = (const double *)c->d_pd.p;
+    c->T.fp_bits = c->logN == 16 ? kNttFpBits : 0;
     c->T.logN = c->logN;
     c->T.ntt_r4_max = kNttR4Max;
     c->T.ntt_r8_max = kNttR8Max;
+    c->T.ntt_s4_max = kNttS4Max;
 }
 
 // product of primes (indices idx, skipping `skip`) modulo m
@@ -2689,11 +2728,19 @@ ckks_status ckks_ntt_device(ckks_ctx *c, uint64_t *data, uint32_t n_limbs, const
     });
 }
 
-ckks_status ckks_ntt_schedule(ckks_ctx *c, int32_t r4_max_limbs, int32_t r8_max_limbs) {
-    if (!c || r4_max_limbs < -1 || r8_max_limbs < -1) return CKKS_E_PARAM;
+ckks_status ckks_ntt_schedule(ckks_ctx *c, int32_t r4_max_limbs, int32_t r8_max_limbs, int32_t s4_max_limbs) {
+    if (!c || r4_max_limbs < -1 || r8_max_limbs < -1 || s4_max_limbs < -1) return CKKS_E_PARAM;
     return guard(c, [&] {
         c->T.ntt_r4_max = r4_max_limbs < 0 ? kNttR4Max : r4_max_limbs;
         c->T.ntt_r8_max = r8_max_limbs < 0 ? kNttR8Max : r8_max_limbs;
+        c->T.ntt_s4_max = s4_max_limbs < 0 ? kNttS4Max : s4_max_limbs;
+    });
+}
+
+ckks_status ckks_ntt_arith(ckks_ctx *c, int32_t fp64_max_bits) {
+    if (!c || fp64_max_bits < -1 || fp64_max_bits > kNttFpBits) return CKKS_E_PARAM;
+    return guard(c, [&] {
+        c->T.fp_bits = c->logN != 16 ? 0 : fp64_max_bits < 0 ? kNttFpBits : fp64_max_bits;
     });
 }
 

@@ -31,10 +31,16 @@ struct Tables {
     const DevPrime *primes;   // [np]
     const uint64_t *fw, *fw_sh, *iw, *iw_sh;
     const uint64_t *ninv, *ninv_sh;   // [np]
+    // binary64 forms for the N = 2^16 transforms of primes below 2^fp_bits:
+    // twiddles w and w / q ([np][N]), per prime {q, 1/q, N^-1, N^-1 / q}
+    const double *fw_d, *fwq_d, *iw_d, *iwq_d;
+    const double *pd;         // [np][4]
+    int fp_bits;              // 0: every prime on the integer path
     int logN;
     // N = 2^16 transforms: calls of at most ntt_r4_max (ntt_r8_max) limbs in
-    // total use 4 (8) words per thread, larger ones 16
-    int ntt_r4_max, ntt_r8_max;
+    // total use 4 (8) words per thread, larger ones 16; 4-word calls of at
+    // most ntt_s4_max limbs put 4 sub-transforms in a block instead of 16
+    int ntt_r4_max, ntt_r8_max, ntt_s4_max;
 };
 
 // Forward N = 2^16 NTT with a fused source and epilogue (rescale / ModRaise):

@@ -251,6 +251,76 @@ DEV u64 mul_shoup_lazy4(u64 a, u64 w, u64 wsh, u64 q) {
 // corrected by 4q, D = U - V + 4q < 8q into the product.
 constexpr u64 kSmallPrime = 1ull << 57;
 
+// Binary64 butterflies for primes q < 2^42 (T.fp_bits).  A residue is held as
+// an integer-valued double (exact below 2^53).  The product r = V w mod q
+// (up to a multiple of q) with the twiddle w < q and wq = fl(w / q):
+//   h = fl(V w), l = V w - h exactly (one FMA: the error-free product),
+//   k = nearest integer to V wq (FMA against 1.5 2^52, exact rounding for
+//       |V wq| < 2^51), r = fma(-k, q, h) + l.
+// For |V| <= 2^50: |V wq - V w / q| <= |V| 2^-54 <= 1/16, so |r| <= 0.57 q;
+// h - k q = r - l with |l| <= 2^(49+42-53) and |r| < q is below 2^53, so the
+// FMA is exact, and r (an integer below 2^53) is exact.  Forward (CT)
+// butterflies U + r, U - r from [0, q) grow by at most 0.57 q per stage:
+// below 10 q < 2^46 after all 16 stages, no reduction needed.  Inverse (GS)
+// butterflies U + V, (U - V) w double the bound per stage: below 2^8 q <
+// 2^50 after a pass of 8; the second pass re-centres its input first.
+constexpr double kRound = 6755399441055744.0;   // 1.5 * 2^52
+DEV double fp_mulmod(double v, double w, double wq, double q) {
+    const double h = v * w;
+    const double l = __fma_rn(v, w, -h);
+    const double k = __fma_rn(v, wq, kRound) - kRound;
+    return __fma_rn(-k, q, h) + l;
+}
+// x - q round(x / q): the representative in about [-q/2, q/2] (|x| < 2^51)
+DEV double fp_centre(double x, double q, double qinv) {
+    const double k = __fma_rn(x, qinv, kRound) - kRound;
+    return __fma_rn(-k, q, x);
+}
+// canonical residue in [0, q) as a word
+DEV u64 fp_canon(double x, double q, double qinv) {
+    double r = fp_centre(x, q, qinv);
+    r = r < 0.0 ? r + q : r;
+    return (u64)r;
+}
+DEV double fp_bits(u64 w) { return __longlong_as_double((long long)w); }
+DEV u64 fp_word(double x) { return (u64)__double_as_longlong(x); }
+DEV bool fp_prime(const Tables &T, u64 q) { return T.fp_bits > 0 && q < (1ull << T.fp_bits); }
+
+// binary64 forward butterflies on v[0..15], 4 stages (pairing as fwd16)
+__device__ __forceinline__ void fwd16_fp(double v[16], const double *W, const double *Wq, int s0, int hi_part,
+                                         double q) {
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+        const int h = 8 >> j;
+#pragma unroll
+        for (int m = 0; m < 16; ++m) {
+            if (m & h) continue;
+            const int wi = (1 << (s0 + j)) + (hi_part << j) + (m >> (4 - j));
+            const double U = v[m];
+            const double r = fp_mulmod(v[m + h], W[wi], Wq[wi], q);
+            v[m] = U + r;
+            v[m + h] = U - r;
+        }
+    }
+}
+// binary64 inverse butterflies on v[0..15], 4 stages (pairing as inv16)
+__device__ __forceinline__ void inv16_fp(double v[16], const double *W, const double *Wq, int logN, int lt0,
+                                         int hi_part, double q) {
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+        const int h = 1 << j;
+#pragma unroll
+        for (int m = 0; m < 16; ++m) {
+            if (m & h) continue;
+            const int lt = lt0 + j;
+            const int wi = (1 << (logN - lt - 1)) + (hi_part << (3 - j)) + (m >> (j + 1));
+            const double U = v[m], V = v[m + h];
+            v[m] = U + V;
+            v[m + h] = fp_mulmod(U - V, W[wi], Wq[wi], q);
+        }
+    }
+}
+
 // forward butterflies (CT) on v[0..15] for 4 stages; element m pairs with
 // m + h (h = 8, 4, 2, 1); twiddle index for stage j (0..3): base_j + (m >> (4 - j))
 template <bool SMALL>
@@ -333,6 +403,24 @@ __global__ void __launch_bounds__(256) k_ntt16_rows_fwd(u64 *dst, const u64 *src
 #pragma unroll
         for (int mm = 0; mm < 16; ++mm) v[mm] = L(v[mm]);
     }
+    if (fp_prime(T, q)) {
+        // binary64 butterflies; the pass's output words hold the doubles' bits
+        const double qd = T.pd[4 * pi];
+        const double *Wd = T.fw_d + ((size_t)pi << 16), *Wq = T.fwq_d + ((size_t)pi << 16);
+        double f[16];
+#pragma unroll
+        for (int mm = 0; mm < 16; ++mm) f[mm] = (double)v[mm];
+        fwd16_fp(f, Wd, Wq, 0, 0, qd);
+#pragma unroll
+        for (int mm = 0; mm < 16; ++mm) tile[(y + 16 * mm) * kPad + x] = fp_word(f[mm]);
+        __syncthreads();
+#pragma unroll
+        for (int mm = 0; mm < 16; ++mm) f[mm] = fp_bits(tile[(16 * y + mm) * kPad + x]);
+        fwd16_fp(f, Wd, Wq, 4, y, qd);
+#pragma unroll
+        for (int mm = 0; mm < 16; ++mm) out[((16 * y + mm) << 8) + c0 + x] = fp_word(f[mm]);
+        return;
+    }
     const bool small = q < kSmallPrime;
     if (small) fwd16<true>(v, W, Ws, 0, 0, q);
     else fwd16<false>(v, W, Ws, 0, 0, q);
@@ -362,11 +450,28 @@ __global__ void __launch_bounds__(256) k_ntt16_blocks_fwd(u64 *data, int nlimb, 
     const int blk0 = blockIdx.x * 16;   // global index of the first 256-block
     const int x = threadIdx.x & 15, y = threadIdx.x >> 4;
     u64 v[16];
+    const bool fp = fp_prime(T, q), small = q < kSmallPrime;
+    if (fp) {
+        // binary64 (the rows pass left doubles' bits), canonical words at the end
+        const double qd = T.pd[4 * pi], qi = T.pd[4 * pi + 1];
+        const double *Wd = T.fw_d + ((size_t)pi << 16), *Wq = T.fwq_d + ((size_t)pi << 16);
+        double f[16];
+#pragma unroll
+        for (int mm = 0; mm < 16; ++mm) f[mm] = fp_bits(d[(y << 8) + x + 16 * mm]);
+        fwd16_fp(f, Wd, Wq, 8, blk0 + y, qd);
+#pragma unroll
+        for (int mm = 0; mm < 16; ++mm) tile[(y * 16 + mm) * kPad + x] = fp_word(f[mm]);
+        __syncthreads();
+#pragma unroll
+        for (int mm = 0; mm < 16; ++mm) f[mm] = fp_bits(tile[(y * 16 + x) * kPad + mm]);
+        fwd16_fp(f, Wd, Wq, 12, (blk0 + y) * 16 + x, qd);
+#pragma unroll
+        for (int mm = 0; mm < 16; ++mm) v[mm] = fp_canon(f[mm], qd, qi);
+    } else {
     // phase 1: block y, words x + 16 m; stages 8..11 (distances 128..16)
 #pragma unroll
     for (int mm = 0; mm < 16; ++mm) v[mm] = d[(y << 8) + x + 16 * mm];
     // twiddle 2^s + (J >> (16 - s)), J = 256 (blk0 + y) + x + 16 m: hi_part = blk0 + y
-    const bool small = q < kSmallPrime;
     if (small) fwd16<true>(v, W, Ws, 8, blk0 + y, q);
     else fwd16<false>(v, W, Ws, 8, blk0 + y, q);
 #pragma unroll
@@ -385,6 +490,7 @@ __global__ void __launch_bounds__(256) k_ntt16_blocks_fwd(u64 *data, int nlimb, 
         const u64 inv64 = T.primes[pi].mu2_hi;
 #pragma unroll
         for (int mm = 0; mm < 16; ++mm) v[mm] = reduce_any(v[mm], inv64, q);
+    }
     }
     __syncthreads();
 #pragma unroll
@@ -425,6 +531,25 @@ __global__ void __launch_bounds__(256) k_ntt16_blocks_inv(u64 *dst, const u64 *s
 #pragma unroll
     for (int mm = 0; mm < 16; ++mm) tile[(y * 16 + mm) * kPad + x] = s_in[(y << 8) + x + 16 * mm];
     __syncthreads();
+    if (fp_prime(T, q)) {
+        // binary64; the pass's output words hold the doubles' bits
+        const double qd = T.pd[4 * pi];
+        const double *Wd = T.iw_d + ((size_t)pi << 16), *Wq = T.iwq_d + ((size_t)pi << 16);
+        double f[16];
+#pragma unroll
+        for (int mm = 0; mm < 16; ++mm) f[mm] = (double)tile[(y * 16 + x) * kPad + mm];
+        inv16_fp(f, Wd, Wq, 16, 0, (blk0 + y) * 16 + x, qd);
+        __syncthreads();
+#pragma unroll
+        for (int mm = 0; mm < 16; ++mm) tile[(y * 16 + x) * kPad + mm] = fp_word(f[mm]);
+        __syncthreads();
+#pragma unroll
+        for (int mm = 0; mm < 16; ++mm) f[mm] = fp_bits(tile[(y * 16 + mm) * kPad + x]);
+        inv16_fp(f, Wd, Wq, 16, 4, blk0 + y, qd);
+#pragma unroll
+        for (int mm = 0; mm < 16; ++mm) d[(y << 8) + x + 16 * mm] = fp_word(f[mm]);
+        return;
+    }
     // phase A: block y, words 16 x + m; half-distances 1..8.  Group index of
     // word J for distance t: J >> (lt + 1), J = 256 (blk0 + y) + 16 x + m
 #pragma unroll
@@ -453,6 +578,25 @@ __global__ void __launch_bounds__(256) k_ntt16_rows_inv(u64 *data, int nlimb, in
     const int c0 = blockIdx.x * 16;
     const int x = threadIdx.x & 15, y = threadIdx.x >> 4;
     u64 v[16];
+    if (fp_prime(T, q)) {
+        // binary64 from the first pass's doubles, re-centred first; canonical words out
+        const double qd = T.pd[4 * pi], qi = T.pd[4 * pi + 1], nd = T.pd[4 * pi + 2], ndq = T.pd[4 * pi + 3];
+        const double *Wd = T.iw_d + ((size_t)pi << 16), *Wq = T.iwq_d + ((size_t)pi << 16);
+        double f[16];
+#pragma unroll
+        for (int mm = 0; mm < 16; ++mm) f[mm] = fp_centre(fp_bits(d[((16 * y + mm) << 8) + c0 + x]), qd, qi);
+        inv16_fp(f, Wd, Wq, 16, 8, y, qd);
+#pragma unroll
+        for (int mm = 0; mm < 16; ++mm) tile[(16 * y + mm) * kPad + x] = fp_word(f[mm]);
+        __syncthreads();
+#pragma unroll
+        for (int mm = 0; mm < 16; ++mm) f[mm] = fp_bits(tile[(y + 16 * mm) * kPad + x]);
+        inv16_fp(f, Wd, Wq, 16, 12, 0, qd);
+#pragma unroll
+        for (int mm = 0; mm < 16; ++mm)
+            d[((y + 16 * mm) << 8) + c0 + x] = fp_canon(fp_mulmod(f[mm], nd, ndq, qd), qd, qi);
+        return;
+    }
     // phase A: rows k = 16 y + m (row distances 1..8 = global 256..2048)
 #pragma unroll
     for (int mm = 0; mm < 16; ++mm) v[mm] = d[((16 * y + mm) << 8) + c0 + x];
@@ -470,12 +614,15 @@ __global__ void __launch_bounds__(256) k_ntt16_rows_inv(u64 *data, int nlimb, in
 }
 
 // ---------------------------------------------------------------------------
-// N = 2^16 passes with R = 4 or 8 words per thread.  Same two passes and same
-// 4096-word tiles as above (16 independent 256-point sub-transforms, "lanes":
-// 16 columns of the 256 x 256 view, or 16 blocks of 256 words), but each
-// sub-transform is shared by 256 / R threads, so a tile takes 4096 / R
-// threads and every wave carries a shorter chain of dependent work: more waves
-// in flight when a call covers few limbs.  Phase p holds the r = log2(R) bits
+// N = 2^16 passes with R = 4 or 8 words per thread.  Same two passes as above,
+// on tiles of S independent 256-point sub-transforms ("lanes": S columns of
+// the 256 x 256 view, or S blocks of 256 words; S = 16 or 4), each shared by
+// 256 / R threads, so a tile takes S 256 / R threads and every wave carries a
+// shorter chain of dependent work: more waves in flight when a call covers few
+// limbs, and with S = 4 four times as many blocks spread over the CUs.  Tiles
+// are ordered so that 8 consecutive ones run on one XCD (workgroups go to the
+// XCDs round robin): the rows pass's narrow column tiles then share their
+// cache lines in one L2.  Phase p holds the r = log2(R) bits
 // [lo, lo + r) of the 8-bit index k within the sub-transform in registers (the
 // thread supplies the other 8 - r bits) and runs the stages of the phase's
 // bits; phases exchange through LDS.  Forward passes take the bits from the
@@ -487,10 +634,11 @@ __global__ void __launch_bounds__(256) k_ntt16_rows_inv(u64 *data, int nlimb, in
 template <int R> struct Geo {
     static constexpr int r = R == 4 ? 2 : 3;
     static constexpr int T = 256 / R;         // threads per sub-transform
-    static constexpr int NT = 16 * T;         // threads per block
     static constexpr int NPH = (8 + r - 1) / r;
     static constexpr int tb = 8 - r;          // thread bits of k
 };
+// tile of block bx among nt tiles (nt a multiple of 8): consecutive tiles on one XCD
+__device__ __forceinline__ int xcd_tile(int bx, int nt) { return (bx & 7) * (nt >> 3) + (bx >> 3); }
 // register bits [lo, lo + r) of phase p; stage bits [s_lo, s_hi)
 template <int R> __device__ constexpr int fwd_lo(int p) {
     return 8 - Geo<R>::r * (p + 1) > 0 ? 8 - Geo<R>::r * (p + 1) : 0;
@@ -502,10 +650,11 @@ template <int R> __device__ constexpr int inv_lo(int p) {
 template <int R> __device__ __forceinline__ int k_of(int u, int m, int lo) {
     return ((u >> lo) << (lo + Geo<R>::r)) | (m << lo) | (u & ((1 << lo) - 1));
 }
-// LDS address of (lane, k): rows view [k][lane] with pitch 17, blocks view
-// [lane][k >> 4][k & 15] with pitch 17 per 16 words
-template <bool ROWS> __device__ __forceinline__ int lds_at(int lane, int k) {
-    return ROWS ? k * kPad + lane : (lane * 16 + (k >> 4)) * kPad + (k & 15);
+// LDS address of (lane, k): rows view [k][lane] with pitch S + 1, blocks
+// view [lane][k >> 4][k & 15] with pitch 17 per 16 words (256 (S + 1) words
+// hold either)
+template <bool ROWS, int S> __device__ __forceinline__ int lds_at(int lane, int k) {
+    return ROWS ? k * (S + 1) + lane : (lane * 16 + (k >> 4)) * kPad + (k & 15);
 }
 
 // forward butterflies of stage bit b (global stage s) on registers pairing
@@ -554,9 +703,72 @@ __device__ __forceinline__ void inv_stage(u64 *v, int u, int lo, int b, int blkg
     }
 }
 
+// binary64 twins of fwd_stage / inv_stage (the bounds of fwd16_fp / inv16_fp)
+template <int R, bool ROWS>
+__device__ __forceinline__ void fwd_stage_fp(double *v, int u, int lo, int b, int blkg, const double *W,
+                                             const double *Wq, double q) {
+    const int j = b - lo;
+#pragma unroll
+    for (int m = 0; m < R; ++m) {
+        if (m & (1 << j)) continue;
+        const int k = k_of<R>(u, m, lo);
+        const int wi = ROWS ? (1 << (7 - b)) + (k >> (b + 1))
+                            : (1 << (15 - b)) + (blkg << (7 - b)) + (k >> (b + 1));
+        const int h = 1 << j;
+        const double U = v[m];
+        const double r = fp_mulmod(v[m + h], W[wi], Wq[wi], q);
+        v[m] = U + r;
+        v[m + h] = U - r;
+    }
+}
+template <int R, bool ROWS>
+__device__ __forceinline__ void inv_stage_fp(double *v, int u, int lo, int b, int blkg, const double *W,
+                                             const double *Wq, double q) {
+    const int j = b - lo;
+#pragma unroll
+    for (int m = 0; m < R; ++m) {
+        if (m & (1 << j)) continue;
+        const int k = k_of<R>(u, m, lo);
+        const int wi = ROWS ? (1 << (7 - b)) + (k >> (b + 1))
+                            : (1 << (15 - b)) + (blkg << (7 - b)) + (k >> (b + 1));
+        const int h = 1 << j;
+        const double U = v[m], V = v[m + h];
+        v[m] = U + V;
+        v[m + h] = fp_mulmod(U - V, W[wi], Wq[wi], q);
+    }
+}
+// binary64 twin of pass_phases (LDS exchanges carry the doubles' bits)
+template <int R, int S, bool ROWS, bool FWD>
+__device__ __forceinline__ void pass_phases_fp(double *v, u64 *tile, int lane, int u, int blkg, const double *W,
+                                               const double *Wq, double q) {
+    constexpr int r = Geo<R>::r, NPH = Geo<R>::NPH;
+#pragma unroll
+    for (int p = 0; p < NPH; ++p) {
+        const int lo = FWD ? fwd_lo<R>(p) : inv_lo<R>(p);
+        if (p > 0) {
+            __syncthreads();
+#pragma unroll
+            for (int m = 0; m < R; ++m) v[m] = fp_bits(tile[lds_at<ROWS, S>(lane, k_of<R>(u, m, lo))]);
+        }
+        if (FWD) {
+            const int b_hi = 8 - r * p - 1, b_lo = lo;
+#pragma unroll
+            for (int b = b_hi; b >= b_lo; --b) fwd_stage_fp<R, ROWS>(v, u, lo, b, blkg, W, Wq, q);
+        } else {
+            const int b_lo = r * p, b_hi = (r * (p + 1) < 8 ? r * (p + 1) : 8) - 1;
+#pragma unroll
+            for (int b = b_lo; b <= b_hi; ++b) inv_stage_fp<R, ROWS>(v, u, lo, b, blkg, W, Wq, q);
+        }
+        if (p + 1 < NPH) {
+#pragma unroll
+            for (int m = 0; m < R; ++m) tile[lds_at<ROWS, S>(lane, k_of<R>(u, m, lo))] = fp_word(v[m]);
+        }
+    }
+}
+
 // all phases of one pass on registers v (loaded for phase 0 by the caller);
 // leaves the registers holding the last phase's words
-template <int R, bool ROWS, bool FWD, bool SMALL>
+template <int R, int S, bool ROWS, bool FWD, bool SMALL>
 __device__ __forceinline__ void pass_phases(u64 *v, u64 *tile, int lane, int u, int blkg, const u64 *W,
                                             const u64 *Ws, u64 q) {
     constexpr int r = Geo<R>::r, NPH = Geo<R>::NPH;
@@ -566,7 +778,7 @@ __device__ __forceinline__ void pass_phases(u64 *v, u64 *tile, int lane, int u, 
         if (p > 0) {
             __syncthreads();   // the previous phase's words are all in LDS
 #pragma unroll
-            for (int m = 0; m < R; ++m) v[m] = tile[lds_at<ROWS>(lane, k_of<R>(u, m, lo))];
+            for (int m = 0; m < R; ++m) v[m] = tile[lds_at<ROWS, S>(lane, k_of<R>(u, m, lo))];
         }
         if (FWD) {
             const int b_hi = 8 - r * p - 1, b_lo = lo;   // stage bits, high to low
@@ -580,24 +792,25 @@ __device__ __forceinline__ void pass_phases(u64 *v, u64 *tile, int lane, int u, 
         if (p + 1 < NPH) {
             // each thread writes back exactly the words it read in this phase
 #pragma unroll
-            for (int m = 0; m < R; ++m) tile[lds_at<ROWS>(lane, k_of<R>(u, m, lo))] = v[m];
+            for (int m = 0; m < R; ++m) tile[lds_at<ROWS, S>(lane, k_of<R>(u, m, lo))] = v[m];
         }
     }
 }
 
 // forward rows pass (stages 0..7): src -> dst
-template <int R, bool LIFT>
-__global__ void __launch_bounds__(Geo<R>::NT) k_nttr_rows_fwd(u64 *dst, const u64 *src, size_t src_stride, int nlimb,
-                                                               int npoly, LimbMap m, Tables T, NttLift lf) {
-    __shared__ u64 tile[256 * kPad];
+template <int R, int S, bool LIFT>
+__global__ void __launch_bounds__(S * Geo<R>::T) k_nttr_rows_fwd(u64 *dst, const u64 *src, size_t src_stride,
+                                                                  int nlimb, int npoly, LimbMap m, Tables T,
+                                                                  NttLift lf) {
+    __shared__ u64 tile[256 * (S + 1)];
     NTT16_INDEX(nlimb, npoly)
     const int pi = m.p[lidx];
     const u64 q = T.primes[pi].q;
     const u64 *W = T.fw + ((size_t)pi << 16), *Ws = T.fw_sh + ((size_t)pi << 16);
     const u64 *in = LIFT ? lf.t + (size_t)pidx * lf.t_stride : src + (size_t)pidx * src_stride + ((size_t)lidx << 16);
     u64 *out = dst + row_off;
-    const int c0 = blockIdx.x * 16;
-    const int lane = threadIdx.x & 15, u = threadIdx.x >> 4;
+    const int c0 = xcd_tile(blockIdx.x, gridDim.x) * S;
+    const int lane = threadIdx.x % S, u = threadIdx.x / S;
     constexpr int lo0 = fwd_lo<R>(0), loL = fwd_lo<R>(Geo<R>::NPH - 1);
     u64 v[R];
 #pragma unroll
@@ -607,40 +820,56 @@ __global__ void __launch_bounds__(Geo<R>::NT) k_nttr_rows_fwd(u64 *dst, const u6
 #pragma unroll
         for (int mm = 0; mm < R; ++mm) v[mm] = L(v[mm]);
     }
-    if (q < kSmallPrime) pass_phases<R, true, true, true>(v, tile, lane, u, 0, W, Ws, q);
-    else pass_phases<R, true, true, false>(v, tile, lane, u, 0, W, Ws, q);
+    if (fp_prime(T, q)) {
+        double f[R];
+#pragma unroll
+        for (int mm = 0; mm < R; ++mm) f[mm] = (double)v[mm];
+        pass_phases_fp<R, S, true, true>(f, tile, lane, u, 0, T.fw_d + ((size_t)pi << 16),
+                                         T.fwq_d + ((size_t)pi << 16), T.pd[4 * pi]);
+#pragma unroll
+        for (int mm = 0; mm < R; ++mm) out[(k_of<R>(u, mm, loL) << 8) + c0 + lane] = fp_word(f[mm]);
+        return;
+    }
+    if (q < kSmallPrime) pass_phases<R, S, true, true, true>(v, tile, lane, u, 0, W, Ws, q);
+    else pass_phases<R, S, true, true, false>(v, tile, lane, u, 0, W, Ws, q);
 #pragma unroll
     for (int mm = 0; mm < R; ++mm) out[(k_of<R>(u, mm, loL) << 8) + c0 + lane] = v[mm];
 }
 // forward blocks pass (stages 8..15), in place, output reduced to [0, q)
-template <int R, bool EPI>
-__global__ void __launch_bounds__(Geo<R>::NT) k_nttr_blocks_fwd(u64 *data, int nlimb, int npoly, LimbMap m,
-                                                                 Tables T, NttEpi ep) {
-    __shared__ u64 tile[256 * kPad];
+template <int R, int S, bool EPI>
+__global__ void __launch_bounds__(S * Geo<R>::T) k_nttr_blocks_fwd(u64 *data, int nlimb, int npoly, LimbMap m,
+                                                                    Tables T, NttEpi ep) {
+    __shared__ u64 tile[256 * (S + 1)];
     NTT16_INDEX(nlimb, npoly)
     const int pi = m.p[lidx];
     const u64 q = T.primes[pi].q;
     const u64 *W = T.fw + ((size_t)pi << 16), *Ws = T.fw_sh + ((size_t)pi << 16);
-    u64 *d = data + row_off + ((size_t)blockIdx.x << 12);
+    const int tl = xcd_tile(blockIdx.x, gridDim.x);
+    const size_t off = (size_t)tl * S * 256;
+    u64 *d = data + row_off + off;
     const int lane = threadIdx.x / Geo<R>::T, u = threadIdx.x % Geo<R>::T;
-    const int blkg = blockIdx.x * 16 + lane;
+    const int blkg = tl * S + lane;
     constexpr int lo0 = fwd_lo<R>(0), loL = fwd_lo<R>(Geo<R>::NPH - 1);
     u64 v[R];
+    if (fp_prime(T, q)) {
+        const double qd = T.pd[4 * pi], qi = T.pd[4 * pi + 1];
+        double f[R];
 #pragma unroll
-    for (int mm = 0; mm < R; ++mm) v[mm] = d[(lane << 8) + k_of<R>(u, mm, lo0)];
-    if (q < kSmallPrime) {
-        pass_phases<R, false, true, true>(v, tile, lane, u, blkg, W, Ws, q);
-        const u64 inv64 = T.primes[pi].mu2_hi;
+        for (int mm = 0; mm < R; ++mm) f[mm] = fp_bits(d[(lane << 8) + k_of<R>(u, mm, lo0)]);
+        pass_phases_fp<R, S, false, true>(f, tile, lane, u, blkg, T.fw_d + ((size_t)pi << 16),
+                                          T.fwq_d + ((size_t)pi << 16), qd);
 #pragma unroll
-        for (int mm = 0; mm < R; ++mm) v[mm] = reduce_any(v[mm], inv64, q);
+        for (int mm = 0; mm < R; ++mm) v[mm] = fp_canon(f[mm], qd, qi);
     } else {
-        pass_phases<R, false, true, false>(v, tile, lane, u, blkg, W, Ws, q);
+#pragma unroll
+        for (int mm = 0; mm < R; ++mm) v[mm] = d[(lane << 8) + k_of<R>(u, mm, lo0)];
+        if (q < kSmallPrime) pass_phases<R, S, false, true, true>(v, tile, lane, u, blkg, W, Ws, q);
+        else pass_phases<R, S, false, true, false>(v, tile, lane, u, blkg, W, Ws, q);
         const u64 inv64 = T.primes[pi].mu2_hi;
 #pragma unroll
         for (int mm = 0; mm < R; ++mm) v[mm] = reduce_any(v[mm], inv64, q);
     }
     if (EPI) {
-        const size_t off = ((size_t)blockIdx.x << 12);
         const u64 *cc = ep.c + (size_t)pidx * ep.c_stride + ((size_t)lidx << 16) + off;
         u64 *o = ep.out + row_off + off;
         const u64 iv = ep.inv[lidx], ivs = ep.inv_sh[lidx];
@@ -658,58 +887,95 @@ __global__ void __launch_bounds__(Geo<R>::NT) k_nttr_blocks_fwd(u64 *data, int n
     }
 }
 // inverse blocks pass (half-distances 1..128): src -> dst
-template <int R>
-__global__ void __launch_bounds__(Geo<R>::NT) k_nttr_blocks_inv(u64 *dst, const u64 *src, size_t src_stride,
-                                                                 int nlimb, int npoly, LimbMap m, Tables T) {
-    __shared__ u64 tile[256 * kPad];
+template <int R, int S>
+__global__ void __launch_bounds__(S * Geo<R>::T) k_nttr_blocks_inv(u64 *dst, const u64 *src, size_t src_stride,
+                                                                    int nlimb, int npoly, LimbMap m, Tables T) {
+    __shared__ u64 tile[256 * (S + 1)];
     NTT16_INDEX(nlimb, npoly)
     const int pi = m.p[lidx];
     const u64 q = T.primes[pi].q;
     const u64 *W = T.iw + ((size_t)pi << 16), *Ws = T.iw_sh + ((size_t)pi << 16);
-    const u64 *s_in = src + (size_t)pidx * src_stride + ((size_t)lidx << 16) + ((size_t)blockIdx.x << 12);
-    u64 *d = dst + row_off + ((size_t)blockIdx.x << 12);
+    const int tl = xcd_tile(blockIdx.x, gridDim.x);
+    const size_t off = (size_t)tl * S * 256;
+    const u64 *s_in = src + (size_t)pidx * src_stride + ((size_t)lidx << 16) + off;
+    u64 *d = dst + row_off + off;
     const int lane = threadIdx.x / Geo<R>::T, u = threadIdx.x % Geo<R>::T;
-    const int blkg = blockIdx.x * 16 + lane;
+    const int blkg = tl * S + lane;
     constexpr int lo0 = inv_lo<R>(0), loL = inv_lo<R>(Geo<R>::NPH - 1);
     u64 v[R];
 #pragma unroll
     for (int mm = 0; mm < R; ++mm) v[mm] = s_in[(lane << 8) + k_of<R>(u, mm, lo0)];
-    pass_phases<R, false, false, true>(v, tile, lane, u, blkg, W, Ws, q);   // inverse: one path for all primes
+    if (fp_prime(T, q)) {
+        double f[R];
+#pragma unroll
+        for (int mm = 0; mm < R; ++mm) f[mm] = (double)v[mm];
+        pass_phases_fp<R, S, false, false>(f, tile, lane, u, blkg, T.iw_d + ((size_t)pi << 16),
+                                           T.iwq_d + ((size_t)pi << 16), T.pd[4 * pi]);
+#pragma unroll
+        for (int mm = 0; mm < R; ++mm) d[(lane << 8) + k_of<R>(u, mm, loL)] = fp_word(f[mm]);
+        return;
+    }
+    pass_phases<R, S, false, false, true>(v, tile, lane, u, blkg, W, Ws, q);   // inverse: one path for all primes
 #pragma unroll
     for (int mm = 0; mm < R; ++mm) d[(lane << 8) + k_of<R>(u, mm, loL)] = v[mm];
 }
 // inverse rows pass (half-distances 256..32768), in place, times N^-1
-template <int R>
-__global__ void __launch_bounds__(Geo<R>::NT) k_nttr_rows_inv(u64 *data, int nlimb, int npoly, LimbMap m, Tables T) {
-    __shared__ u64 tile[256 * kPad];
+template <int R, int S>
+__global__ void __launch_bounds__(S * Geo<R>::T) k_nttr_rows_inv(u64 *data, int nlimb, int npoly, LimbMap m,
+                                                                  Tables T) {
+    __shared__ u64 tile[256 * (S + 1)];
     NTT16_INDEX(nlimb, npoly)
     const int pi = m.p[lidx];
     const u64 q = T.primes[pi].q;
     const u64 *W = T.iw + ((size_t)pi << 16), *Ws = T.iw_sh + ((size_t)pi << 16);
     u64 *d = data + row_off;
-    const int c0 = blockIdx.x * 16;
-    const int lane = threadIdx.x & 15, u = threadIdx.x >> 4;
+    const int c0 = xcd_tile(blockIdx.x, gridDim.x) * S;
+    const int lane = threadIdx.x % S, u = threadIdx.x / S;
     constexpr int lo0 = inv_lo<R>(0), loL = inv_lo<R>(Geo<R>::NPH - 1);
     u64 v[R];
+    if (fp_prime(T, q)) {
+        const double qd = T.pd[4 * pi], qi = T.pd[4 * pi + 1], nd = T.pd[4 * pi + 2], ndq = T.pd[4 * pi + 3];
+        double f[R];
+#pragma unroll
+        for (int mm = 0; mm < R; ++mm) f[mm] = fp_centre(fp_bits(d[(k_of<R>(u, mm, lo0) << 8) + c0 + lane]), qd, qi);
+        pass_phases_fp<R, S, true, false>(f, tile, lane, u, 0, T.iw_d + ((size_t)pi << 16),
+                                          T.iwq_d + ((size_t)pi << 16), qd);
+#pragma unroll
+        for (int mm = 0; mm < R; ++mm)
+            d[(k_of<R>(u, mm, loL) << 8) + c0 + lane] = fp_canon(fp_mulmod(f[mm], nd, ndq, qd), qd, qi);
+        return;
+    }
 #pragma unroll
     for (int mm = 0; mm < R; ++mm) v[mm] = d[(k_of<R>(u, mm, lo0) << 8) + c0 + lane];
-    pass_phases<R, true, false, true>(v, tile, lane, u, 0, W, Ws, q);   // inverse: one path for all primes
+    pass_phases<R, S, true, false, true>(v, tile, lane, u, 0, W, Ws, q);   // inverse: one path for all primes
     const u64 ni = T.ninv[pi], nis = T.ninv_sh[pi];
 #pragma unroll
     for (int mm = 0; mm < R; ++mm) d[(k_of<R>(u, mm, loL) << 8) + c0 + lane] = mul_shoup(v[mm], ni, nis, q);
 }
 
-template <int R>
+template <int R, int S>
 static void launch_nttr(const Tables &T, uint64_t *dst, const uint64_t *src, size_t src_poly_stride, int nlimb,
                         int npoly, const LimbMap &m, bool inverse, hipStream_t s) {
-    dim3 grid(16, nlimb * npoly), block(Geo<R>::NT);
+    dim3 grid(256 / S, nlimb * npoly), block(S * Geo<R>::T);
     if (!inverse) {
-        k_nttr_rows_fwd<R, false><<<grid, block, 0, s>>>(dst, src, src_poly_stride, nlimb, npoly, m, T, NttLift{});
-        k_nttr_blocks_fwd<R, false><<<grid, block, 0, s>>>(dst, nlimb, npoly, m, T, NttEpi{});
+        k_nttr_rows_fwd<R, S, false><<<grid, block, 0, s>>>(dst, src, src_poly_stride, nlimb, npoly, m, T, NttLift{});
+        k_nttr_blocks_fwd<R, S, false><<<grid, block, 0, s>>>(dst, nlimb, npoly, m, T, NttEpi{});
     } else {
-        hipLaunchKernelGGL(k_nttr_blocks_inv<R>, grid, block, 0, s, dst, src, src_poly_stride, nlimb, npoly, m, T);
-        hipLaunchKernelGGL(k_nttr_rows_inv<R>, grid, block, 0, s, dst, nlimb, npoly, m, T);
+        hipLaunchKernelGGL((k_nttr_blocks_inv<R, S>), grid, block, 0, s, dst, src, src_poly_stride, nlimb, npoly, m, T);
+        hipLaunchKernelGGL((k_nttr_rows_inv<R, S>), grid, block, 0, s, dst, nlimb, npoly, m, T);
     }
+}
+template <int R, int S>
+static void launch_nttr_fused(const Tables &T, uint64_t *work, const NttLift *lift, const NttEpi *epi, int nlimb,
+                              int npoly, const LimbMap &m, hipStream_t s) {
+    const NttLift lf = lift ? *lift : NttLift{};
+    const NttEpi ep = epi ? *epi : NttEpi{};
+    const size_t stride = (size_t)nlimb << 16;
+    dim3 grid(256 / S, nlimb * npoly), block(S * Geo<R>::T);
+    if (lift) k_nttr_rows_fwd<R, S, true><<<grid, block, 0, s>>>(work, work, stride, nlimb, npoly, m, T, lf);
+    else k_nttr_rows_fwd<R, S, false><<<grid, block, 0, s>>>(work, work, stride, nlimb, npoly, m, T, lf);
+    if (epi) k_nttr_blocks_fwd<R, S, true><<<grid, block, 0, s>>>(work, nlimb, npoly, m, T, ep);
+    else k_nttr_blocks_fwd<R, S, false><<<grid, block, 0, s>>>(work, nlimb, npoly, m, T, ep);
 }
 
 void ntt16_fwd_fused(const Tables &T, uint64_t *work, const NttLift *lift, const NttEpi *epi, int nlimb, int npoly,
@@ -719,23 +985,16 @@ void ntt16_fwd_fused(const Tables &T, uint64_t *work, const NttLift *lift, const
     const NttLift lf = lift ? *lift : NttLift{};
     const NttEpi ep = epi ? *epi : NttEpi{};
     const size_t stride = (size_t)nlimb << 16;
-    dim3 grid(16, total);
-    if (total <= T.ntt_r4_max || total <= T.ntt_r8_max) {
-        const bool r4 = total <= T.ntt_r4_max;
-        dim3 block(r4 ? Geo<4>::NT : Geo<8>::NT);
-        if (r4) {
-            if (lift) k_nttr_rows_fwd<4, true><<<grid, block, 0, s>>>(work, work, stride, nlimb, npoly, m, T, lf);
-            else k_nttr_rows_fwd<4, false><<<grid, block, 0, s>>>(work, work, stride, nlimb, npoly, m, T, lf);
-            if (epi) k_nttr_blocks_fwd<4, true><<<grid, block, 0, s>>>(work, nlimb, npoly, m, T, ep);
-            else k_nttr_blocks_fwd<4, false><<<grid, block, 0, s>>>(work, nlimb, npoly, m, T, ep);
-        } else {
-            if (lift) k_nttr_rows_fwd<8, true><<<grid, block, 0, s>>>(work, work, stride, nlimb, npoly, m, T, lf);
-            else k_nttr_rows_fwd<8, false><<<grid, block, 0, s>>>(work, work, stride, nlimb, npoly, m, T, lf);
-            if (epi) k_nttr_blocks_fwd<8, true><<<grid, block, 0, s>>>(work, nlimb, npoly, m, T, ep);
-            else k_nttr_blocks_fwd<8, false><<<grid, block, 0, s>>>(work, nlimb, npoly, m, T, ep);
-        }
+    if (total <= T.ntt_r4_max) {
+        if (total <= T.ntt_s4_max) launch_nttr_fused<4, 4>(T, work, lift, epi, nlimb, npoly, m, s);
+        else launch_nttr_fused<4, 16>(T, work, lift, epi, nlimb, npoly, m, s);
         return;
     }
+    if (total <= T.ntt_r8_max) {
+        launch_nttr_fused<8, 16>(T, work, lift, epi, nlimb, npoly, m, s);
+        return;
+    }
+    dim3 grid(16, total);
     if (lift) k_ntt16_rows_fwd<true><<<grid, dim3(256), 0, s>>>(work, work, stride, nlimb, npoly, m, T, lf);
     else k_ntt16_rows_fwd<false><<<grid, dim3(256), 0, s>>>(work, work, stride, nlimb, npoly, m, T, lf);
     if (epi) k_ntt16_blocks_fwd<true><<<grid, dim3(256), 0, s>>>(work, nlimb, npoly, m, T, ep);
@@ -752,11 +1011,12 @@ void ntt_oop(const Tables &T, uint64_t *dst, const uint64_t *src, size_t src_pol
         // words per thread from the call's size (tunable per context): short
         // per-wave chains for small calls, fewer LDS exchanges for large ones
         if (total <= T.ntt_r4_max) {
-            launch_nttr<4>(T, dst, src, src_poly_stride, nlimb, npoly, m, inverse, s);
+            if (total <= T.ntt_s4_max) launch_nttr<4, 4>(T, dst, src, src_poly_stride, nlimb, npoly, m, inverse, s);
+            else launch_nttr<4, 16>(T, dst, src, src_poly_stride, nlimb, npoly, m, inverse, s);
             return;
         }
         if (total <= T.ntt_r8_max) {
-            launch_nttr<8>(T, dst, src, src_poly_stride, nlimb, npoly, m, inverse, s);
+            launch_nttr<8, 16>(T, dst, src, src_poly_stride, nlimb, npoly, m, inverse, s);
             return;
         }
         dim3 grid(16, total);

@@ -1,7 +1,8 @@
 """Tuner of the N = 2^16 transform schedule: times forward and inverse NTT
-calls of several sizes with 4, 8 and 16 words per thread on this GPU and picks
-the limb-count bounds for ckks_ntt_schedule (the largest call sizes at which
-the 4- and 8-word variants are still the fastest).  Results are identical
+calls of several sizes with 4 (4 or 16 sub-transforms per workgroup), 8 and
+16 words per thread on this GPU and picks the limb-count bounds for
+ckks_ntt_schedule (the largest call sizes at which the smaller variants are
+still the fastest).  Results are identical
 under every schedule; only the time changes.
 
     python -m paper_2606_10477_amd.ntt_tune [--limbs 1,2,4,...] [--json PATH]
@@ -18,7 +19,7 @@ import time
 
 SIZES = (1, 2, 3, 4, 6, 8, 10, 12, 16, 20, 24, 28, 32, 40, 48, 64, 96)
 BIG = 1 << 20
-VARIANTS = ((4, (BIG, BIG)), (8, (0, BIG)), (16, (0, 0)))
+VARIANTS = (("4s4", (BIG, BIG, BIG)), (4, (BIG, BIG, 0)), (8, (0, BIG, 0)), (16, (0, 0, 0)))
 
 
 def time_calls(ctx, x, n, idx, inverse, reps):
@@ -47,7 +48,7 @@ def scan(ctx, sizes, nprimes):
             row[f"inv_R{R}_us"] = 1e6 * time_calls(ctx, x, n, idx, True, reps)
         rows.append(row)
         print(json.dumps({k: round(v, 1) if isinstance(v, float) else v for k, v in row.items()}), flush=True)
-    ctx.ntt_schedule(-1, -1)
+    ctx.ntt_schedule(-1, -1, -1)
     return rows
 
 
@@ -66,28 +67,31 @@ def issue(ctx, sizes, nprimes, calls):
 
 
 def choose(rows, tol=0.01):
-    """Bounds (r4_max, r8_max): every call size up to r4_max is fastest (fwd +
-    inv) with 4 words per thread, up to r8_max with 4 or 8.  A variant within
-    `tol` (relative) of the fastest counts as fastest, preferring fewer words
-    per thread, so that timing noise at near-ties does not end a run early."""
+    """Bounds (r4_max, r8_max, s4_max): every call size up to s4_max is fastest
+    (fwd + inv) with 4 words per thread and 4 sub-transforms per workgroup, up
+    to r4_max with 4 words, up to r8_max with 4 or 8.  A variant within `tol`
+    (relative) of the fastest counts as fastest, preferring the smaller
+    workgroups, so that timing noise at near-ties does not end a run early."""
+    rank = {R: k for k, (R, _) in enumerate(VARIANTS)}
     best = []
     for r in rows:
         t = {R: r[f"fwd_R{R}_us"] + r[f"inv_R{R}_us"] for R, _ in VARIANTS}
         tmin = min(t.values())
-        best.append((r["limbs"], min(R for R in t if t[R] <= tmin * (1 + tol))))
-    r4 = 0
-    for n, R in best:
-        if R != 4:
-            break
-        r4 = n
-    r8 = r4
-    for n, R in best:
-        if n <= r4:
-            continue
-        if R != 8:
-            break
-        r8 = n
-    return r4, r8, best
+        best.append((r["limbs"], min((R for R in t if t[R] <= tmin * (1 + tol)), key=rank.get)))
+
+    def run_of(allowed, start):
+        b = start
+        for n, R in best:
+            if n <= start:
+                continue
+            if R not in allowed:
+                break
+            b = n
+        return b
+    s4 = run_of({"4s4"}, 0)
+    r4 = run_of({"4s4", 4}, s4)
+    r8 = run_of({8}, r4)
+    return r4, r8, s4, best
 
 
 def main(argv=None):
@@ -105,9 +109,9 @@ def main(argv=None):
         ctx.close()
         return
     rows = scan(ctx, [int(s) for s in a.limbs.split(",")], ctx.np_)
-    r4, r8, best = choose(rows)
-    res = {"r4_max_limbs": r4, "r8_max_limbs": r8, "fastest_words_per_thread": best, "rows": rows}
-    print(json.dumps({"r4_max_limbs": r4, "r8_max_limbs": r8, "fastest_words_per_thread": best}), flush=True)
+    r4, r8, s4, best = choose(rows)
+    res = {"r4_max_limbs": r4, "r8_max_limbs": r8, "s4_max_limbs": s4, "fastest_variant": best, "rows": rows}
+    print(json.dumps({k: v for k, v in res.items() if k != "rows"}), flush=True)
     if a.json:
         with open(a.json, "w") as f:
             json.dump(res, f, indent=1)

@@ -99,15 +99,19 @@ def test_ntt_bit_exact(pair12, pair16, which):
         assert np.array_equal(got2[i], o.intt(int(i), host[i])), f"inverse limb {i}"
 
 
-@pytest.mark.parametrize("words_per_thread", [4, 8, 16])
-def test_ntt16_schedules_bit_exact(pair16, words_per_thread):
-    """Every N = 2^16 transform variant (4, 8 or 16 words per thread) against
-    the oracle's negacyclic NTT, on single limbs, a ragged count and all limbs
-    of the chain (60-bit and 40-bit primes), including all-(q-1) limbs."""
+@pytest.mark.parametrize("words_per_thread", ["4s4", 4, 8, 16])
+@pytest.mark.parametrize("fp64", [True, False])
+def test_ntt16_schedules_bit_exact(pair16, words_per_thread, fp64):
+    """Every N = 2^16 transform variant (4 words per thread with 4 or 16
+    sub-transforms per workgroup, 8 or 16 words per thread; the
+    40-bit primes' butterflies in binary64 or on integers) against the
+    oracle's negacyclic NTT, on single limbs, a ragged count and all limbs of
+    the chain (60-bit and 40-bit primes), including all-(q-1) limbs."""
     import torch
     g, o = pair16
     big = 1 << 20
-    g.ntt_schedule(*{4: (big, big), 8: (0, big), 16: (0, 0)}[words_per_thread])
+    g.ntt_schedule(*{"4s4": (big, big, big), 4: (big, big, 0), 8: (0, big, 0), 16: (0, 0, 0)}[words_per_thread])
+    g.ntt_arith(-1 if fp64 else 0)
     try:
         for n in (1, 3, g.np_):
             idx = np.array([(5 * i + 1) % g.np_ for i in range(n)], dtype=np.uint32)
@@ -126,7 +130,8 @@ def test_ntt16_schedules_bit_exact(pair16, words_per_thread):
             for i in range(n):
                 assert np.array_equal(got2[i], o.intt(int(idx[i]), host[i])), f"inverse {n} limbs, limb {i}"
     finally:
-        g.ntt_schedule(-1, -1)
+        g.ntt_schedule(-1, -1, -1)
+        g.ntt_arith(-1)
 
 
 def test_encrypt_decrypt_parity(pair12):
