@@ -2326,17 +2326,29 @@ orc_ct *orc_invsqrt(orc_ctx *c, const orc_ct *x, int d, int iters, double a, dou
         for (int k = 0; k <= d; k++) cf[k] *= kappa;
     orc_ct *xb = NULL;
     const int64_t My = bts_bound > 0 ? bts_bound : 16 * (int64_t)ceil(1.0 / sqrt(an));
+    /* the ciphertext the chain reads holds x / s: s = 1, or s = B once x has
+       been pre-normalised by a homomorphic product with 1/B ahead of a
+       Pre-BTS, so that the bootstrap sees a message bounded by b/B */
+    double s = 1.0;
     if (pre_bts || x->level < cheb_depth(d) + 1 || x->level < 3) {
         if (!c->bts) {
             if (pre_bts || x->level < 2) { free(cf); set_err("level"); return NULL; }
         } else {
-            xb = orc_bootstrap(c, x, 16 * (int64_t)ceil(b));
+            orc_ct *xn = NULL;
+            if (Bn > 1.0) {
+                xn = orc_mul_const_down(c, x, 1.0 / Bn);
+                if (!xn) { free(cf); return NULL; }
+                x = xn;
+                s = Bn;
+            }
+            xb = orc_bootstrap(c, x, 16 * (int64_t)ceil(b / s));
+            orc_ct_free(xn);
             if (!xb) { free(cf); return NULL; }
             x = xb;
         }
     }
-    orc_ct *cx = mul_const_down(c, x, 0.5 / Bn);
-    orc_ct *y = orc_cheb_eval(c, x, cf, d, a, b);
+    orc_ct *cx = mul_const_down(c, x, 0.5 * s / Bn);
+    orc_ct *y = orc_cheb_eval(c, x, cf, d, a / s, b / s);
     free(cf);
     if (!cx || !y) { orc_ct_free(cx); orc_ct_free(y); orc_ct_free(xb); return NULL; }
     if (literal) {
@@ -2356,7 +2368,7 @@ orc_ct *orc_invsqrt(orc_ctx *c, const orc_ct *x, int d, int iters, double a, dou
         orc_ct *yn;
         if (i == iters - 1) {
             orc_ct *xr = ct_copy(c, x);
-            xr->scale = x->scale * (2.0 * Bn * sqrt(Bn));
+            xr->scale = x->scale * (2.0 * (Bn / s) * sqrt(Bn));
             yn = newton_step(c, y, xr, 1, 1.5 * kappa);
             orc_ct_free(xr);
         } else {

@@ -109,6 +109,13 @@ SIGNATURES = {
 }
 
 
+def library_sha256():
+    """SHA-256 of the built library file (what a tuning table was measured with)."""
+    import hashlib
+    with open(LIB_PATH, "rb") as f:
+        return hashlib.sha256(f.read()).hexdigest()
+
+
 def lib():
     global _lib
     if _lib is not None:

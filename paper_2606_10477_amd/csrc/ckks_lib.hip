@@ -1893,12 +1893,22 @@ Ct op_invsqrt(ckks_ctx *c, const ckks_ct *x0, int degree, int iters, const ckks_
     const int64_t My = o.bts_bound > 0 ? o.bts_bound : 16 * (int64_t)std::ceil(1.0 / std::sqrt(an));
     const ckks_ct *x = x0;
     Ct xb;
+    // x holds (input) / sx: sx = B once the input has been divided by B ahead
+    // of a Pre-BTS (the bootstrap then sees a message bounded by b/B, which the
+    // input scale leaves room for where b itself would not), else 1
+    double sx = 1.0;
     if (o.pre_bts || x->level < cheb_depth(degree) + 1 || x->level < 3) {
         if (!c->bts) {
             if (o.pre_bts) fail(CKKS_E_NOKEY, "Pre-BTS needs bootstrapping");
             if (x->level < 2) fail(CKKS_E_LEVEL, "input needs at least 2 levels");
         } else {
-            xb = op_bootstrap(c, x, 16 * (int64_t)std::ceil(o.b));
+            Ct xn;
+            if (Bn > 1.0) {
+                xn = op_mul_const_down(c, x, 1.0 / Bn);
+                x = xn.get();
+                sx = Bn;
+            }
+            xb = op_bootstrap(c, x, 16 * (int64_t)std::ceil(o.b / sx));
             x = xb.get();
         }
     }
@@ -1906,8 +1916,9 @@ Ct op_invsqrt(ckks_ctx *c, const ckks_ct *x0, int degree, int iters, const ckks_
     hm::cheb_invsqrt(degree, an, bn, cf.data());
     if (iters == 0)
         for (double &v : cf) v *= kappa;   // no Newton step to carry the scale-back
-    Ct cx = op_mul_const_down(c, x, 0.5 / Bn);
-    Ct y = op_cheb(c, x, cf, o.a, o.b);   // affine map from [a, b]: t(x) = t(u) on [an, bn]
+    Ct cx = op_mul_const_down(c, x, 0.5 * sx / Bn);
+    // affine map from [a/sx, b/sx] (the interval of what x holds): t(x) = t(u) on [an, bn]
+    Ct y = op_cheb(c, x, cf, o.a / sx, o.b / sx);
     if (o.literal) y = op_bootstrap(c, y.get(), My);
     for (int i = 0; i < iters; ++i) {
         if (y->level < 2) {
@@ -1920,7 +1931,7 @@ Ct op_invsqrt(ckks_ctx *c, const ckks_ct *x0, int degree, int iters, const ckks_
             // in: the x operand declared as kappa x / (2B), the constant
             // 1.5 kappa
             Ct xr = ct_copy(c, x);
-            xr->scale = x->scale * (2.0 * Bn * std::sqrt(Bn));
+            xr->scale = x->scale * (2.0 * (Bn / sx) * std::sqrt(Bn));
             y = op_newton(c, y.get(), xr.get(), true, 1.5 * kappa);
         } else {
             y = op_newton(c, y.get(), cx.get(), false);

@@ -22,6 +22,12 @@ def load(name):
     return sets[name]
 
 
+def set_sha256(name):
+    """SHA-256 of the set's canonical JSON: the key a tuning table is valid for."""
+    import hashlib
+    return hashlib.sha256(json.dumps(load(name), sort_keys=True, separators=(",", ":")).encode()).hexdigest()
+
+
 def context_kwargs(name):
     """Keyword arguments of ckks.Context for the set `name`."""
     s = load(name)

@@ -291,10 +291,11 @@ def main(argv=None):
     versus one request at a time."""
     import argparse
     import json
+    import sys
 
     import torch
 
-    from . import inputs
+    from . import inputs, tuner
 
     ap = argparse.ArgumentParser()
     ap.add_argument("--rates", default="10,40,160")
@@ -307,17 +308,24 @@ def main(argv=None):
     ap.add_argument("--lanes", type=int, default=2, help="contexts on streams of their own")
     ap.add_argument("--out", default=None)
     args = ap.parse_args(argv)
-    table = DEFAULT_TABLE
+    torch.cuda.set_device(0)
+    table, key_note = DEFAULT_TABLE, "no table: the fixed (31, 0, 3) for every request"
     if args.table and os.path.exists(args.table):
         with open(args.table) as f:
-            table = json.load(f)["table"]
-    torch.cuda.set_device(0)
+            rep = json.load(f)
+        table = rep["table"]
+        problem = tuner.check_table_key(rep.get("key"), tuner.table_key("p16b"))
+        if problem and problem[0] == "error":
+            raise SystemExit(problem[1])
+        key_note = problem[1] if problem else "table key matches this GPU, parameter set and library"
+        if problem:
+            print(key_note, file=sys.stderr, flush=True)
     lanes = make_lanes(args.lanes)
     ctx = lanes[0].ctx
     levels = [int(v) for v in args.levels.split(",")]
     out = {"workload": "CryptoInvSqrt serving at N=2^16 with bootstrapping keys resident, Poisson arrivals, "
                        f"sizes Geometric(0.25) in [1,32], levels {levels}, targets 1e-6/1e-7/3.1e-8",
-           "table": args.table, "lanes": args.lanes, "runs": []}
+           "table": args.table, "table_key": key_note, "lanes": args.lanes, "runs": []}
     for rate in [float(v) for v in args.rates.split(",")]:
         n = args.requests
         arr = inputs.poisson_arrivals(n, rate, 40)

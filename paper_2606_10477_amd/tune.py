@@ -37,6 +37,7 @@ def run(levels, degrees, iters, targets, lo, hi, batch, reps, fixed, tuner_seed=
     bts = params == "bts"
     ctx = ckks.Context.from_set("p16b" if bts else "p16")   # plain set: 27 levels, no bootstrapping
     ctx.keygen(tuner_seed, ctx.bts_galois() if bts else [])      # the tuner's own keys, not a client's
+    key = tuner.table_key("p16b" if bts else "p16")
     Bpre = 0.0
     if domain == "paper":
         # the paper's own workload (§5.1): linspace over [0.001, 100] encrypted as it is, pre-normalised
@@ -79,13 +80,18 @@ def run(levels, degrees, iters, targets, lo, hi, batch, reps, fixed, tuner_seed=
         best = tuner.select(rows, targets[-1], l)
         fr = fixed_rows[l]
         if best and fr:
+            # a speed-up only where the fixed setting meets the target too; otherwise the tuned
+            # setting is the fastest one that does, and the fixed one is reported as failing
+            meets = fr["m"] <= targets[-1]
             speedup[str(l)] = {"fixed": [fixed[0], 0, fixed[1]], "fixed_t": fr["t"], "fixed_mre": fr["m"],
+                               "fixed_meets_target": meets,
                                "tuned": [best["d"], best["c"], best["i"]], "tuned_t": best["t"],
-                               "tuned_mre": best["m"], "speedup": fr["t"] / best["t"]}
+                               "tuned_mre": best["m"], "speedup": fr["t"] / best["t"] if meets else None}
     D, R = tuner.alg3_from_rows(rows)
     ok = [r for r in rows if r.get("ok")]
     err = [abs(r["t_pred"] - r["t"]) / r["t"] for r in ok]
     report = {
+        "key": key,
         "params": ("p16b: N=2^16, log2 QP 1544: q0 60-bit, 11 x 40-bit, 12 x 52-bit, 7 x 60-bit special, dnum 3, "
                    "h 192; l_BTS 0, l_afterBTS = l_max 8") if bts else
                   "N=2^16, q0 60-bit + 27 x 40-bit, 7 x 60-bit special, dnum 3, h 192; no bootstrapping",

@@ -222,13 +222,17 @@ def sweep(ctx, x, ct_by_level, degrees, iters, lo, hi, batch=1, reps=3, costs=No
     operation trace (bootstraps counted) and the predicted time.  Settings
     that do not fit the levels are recorded with ok=False.  B > 1: the
     chain pre-normalises x by B homomorphically (x in [lo, hi])."""
+    import sys
     ref = 1.0 / np.sqrt(x)
     rows = []
+    t0 = time.perf_counter()
     for lvl, ct in ct_by_level.items():
         for c in (cs_by_level or {}).get(lvl, [0]):
             for d in degrees:
                 for it in iters:
                     rows.append(_measure(ctx, ct, lvl, c, d, it, lo, hi, batch, reps, costs, ref, B))
+            print(f"swept level {lvl}, c = {c}: {len(rows)} settings, {time.perf_counter() - t0:.1f} s",
+                  file=sys.stderr, flush=True)
     return rows
 
 
@@ -334,3 +338,32 @@ def alg3_from_rows(rows, delta=1.0, theta=1.0, key="t"):
         I, m, t = get_opt_iter(M, T, delta)
         D.setdefault(lvl, []).append({"d": d, "c": c, "i": I, "m": m, "t": t})
     return D, optimize_params(D, theta)
+
+
+def table_key(params_name):
+    """What a tuning table is valid for: the GPU, the parameter set (name and
+    hash of its definition) and the library build it was measured with."""
+    import torch
+
+    from . import ckks, params
+    return {"gpu": torch.cuda.get_device_name(0), "params": params_name,
+            "params_sha256": params.set_sha256(params_name), "library_sha256": ckks.library_sha256()}
+
+
+def check_table_key(stored, current):
+    """Problems of using a table keyed `stored` where the key is `current`:
+    ("error", msg) for another parameter set (the table's levels and
+    iteration counts belong to another chain), ("warn", msg) for another GPU
+    or library build (the choices stay valid, their times may not), or None."""
+    if stored is None:
+        return ("warn", "tuning table has no key (GPU, parameter set, library)")
+    for k in ("params", "params_sha256"):
+        if stored.get(k) != current.get(k):
+            return ("error", f"tuning table is for parameter set {stored.get('params')} "
+                             f"({str(stored.get('params_sha256'))[:12]}), not {current.get('params')} "
+                             f"({str(current.get('params_sha256'))[:12]})")
+    diff = [k for k in ("gpu", "library_sha256") if stored.get(k) != current.get(k)]
+    if diff:
+        return ("warn", "tuning table was measured with another " + " and ".join(diff) + "; re-tune for its times")
+    return None
+

@@ -142,21 +142,25 @@ def test_invsqrt_with_bootstrapping_bit_exact(pair, degree, iters, level, litera
         assert mre < 1e-7
 
 
-@pytest.mark.parametrize("degree,iters", [(14, 3), (30, 2)])
-def test_invsqrt_prenormalised_paper_domain_bit_exact(pair, degree, iters):
+@pytest.mark.parametrize("degree,iters,level,pre", [(14, 3, 8, False), (30, 2, 8, False), (14, 3, 8, True),
+                                                    (30, 2, 4, False)])
+def test_invsqrt_prenormalised_paper_domain_bit_exact(pair, degree, iters, level, pre):
     """The paper's domain and pre-normalisation (§2.3, §4.3: linspace over
-    [0.001, 100], B = 100, degrees 2^d_e - 2) from the top level with lazy
-    bootstrapping: GPU words equal the oracle's; accuracy against 1/sqrt(x)."""
+    [0.001, 100], B = 100, degrees 2^d_e - 2) with lazy bootstrapping, from
+    the top level, with Pre-BTS asked for, and from level 4 where degree 30
+    forces it (x divided by B before the bootstrap): GPU words equal the
+    oracle's; accuracy against 1/sqrt(x)."""
     g, o = pair
     A, Bv = 0.001, 100.0
     x = np.linspace(A, Bv, g.n)
-    gc, oc = g.encrypt(x, 8, 2.0 ** 50, 74), o.encrypt(x, 8, 2.0 ** 50, 74)
-    gy = g.invsqrt(gc, degree, iters, A, Bv, B=100.0)
-    oy = o.invsqrt(oc, degree, iters, A, Bv, B=100.0)
+    gc, oc = g.encrypt(x, level, 2.0 ** 50, 74), o.encrypt(x, level, 2.0 ** 50, 74)
+    gy = g.invsqrt(gc, degree, iters, A, Bv, pre_bts=pre, B=100.0)
+    oy = o.invsqrt(oc, degree, iters, A, Bv, pre_bts=pre, B=100.0)
     same(gy, oy)
     ref = 1 / np.sqrt(x)
     mre = np.mean(np.abs(g.decrypt(gy).real - ref) / ref)
-    print(f"N=2^10 paper domain ({degree},{iters}) B=100: MRE {mre:.3g}", flush=True)
+    print(f"N=2^10 paper domain ({degree},{iters}) from level {level}, Pre-BTS {pre}, B=100: MRE {mre:.3g}",
+          flush=True)
     assert mre < 1e-2
 
 

@@ -246,6 +246,38 @@ def test_invsqrt_pre_bts_branch(oracle_mod, o10):
         assert np.mean(np.abs(z - ref) / ref) > floor / 4
 
 
+def test_invsqrt_pre_bts_prenormalised(oracle_mod, o10):
+    """Pre-BTS in the paper's domain (x in [0.001, 100], B = 100): x itself
+    cannot be bootstrapped at scale 2^50 (its bound exceeds the room the
+    60-bit q0 leaves above the scale), so the chain first divides by B (one
+    level) and bootstraps u = x/B with bound 16; the Chebyshev step then runs
+    on [a/B, b/B] directly and the Newton steps on u~, scaled back by
+    1/sqrt(B).  The result is the FP64 chain on u~ (the decrypted bootstrap of
+    u, computed separately through the same public operations) times
+    1/sqrt(B), up to the chain's noise; against 1/sqrt(x) it carries the
+    approximation's own error plus u~'s relative error halved.  Asked for at level 8 and forced at level 4
+    (degree 30 needs 5 + 1 levels)."""
+    o = o10
+    A, Bv, Bn = 0.001, 100.0, 100.0
+    x = np.linspace(A, Bv, o.n)
+    ref = 1 / np.sqrt(x)
+    for level, ask, d, it in ((8, True, 14, 3), (4, False, 30, 2)):
+        ct = o.encrypt(x, level, 2.0 ** 50, 60 + level)
+        y = o.invsqrt(ct, d, it, A, Bv, pre_bts=ask, B=Bn)
+        ut = o.decrypt(o.bootstrap(o.mul_const_down(ct, 1.0 / Bn), 16)).real
+        cf = oracle_mod.cheb_coeffs_invsqrt(d, A / Bn, Bv / Bn)
+        want = _plain_chain(ut, cf, A / Bn, Bv / Bn, it) / np.sqrt(Bn)
+        z = o.decrypt(y).real
+        assert np.max(np.abs(z - want) / ref) < 1e-5
+        floor = np.mean(np.abs(ut - x / Bn) / (x / Bn)) / 2
+        plain = _plain_chain(x / Bn, cf, A / Bn, Bv / Bn, it) / np.sqrt(Bn)   # the approximation's own error
+        m, m_plain = np.mean(np.abs(z - ref) / ref), np.mean(np.abs(plain - ref) / ref)
+        assert floor / 4 < m < m_plain + 4 * floor + 1e-5
+    # without B the input's bound (100) does not fit the bootstrap at this scale
+    with pytest.raises(oracle_mod.OracleError):
+        o.invsqrt(o.encrypt(x, 8, 2.0 ** 50, 68), 14, 3, A, Bv, pre_bts=True)
+
+
 def _bitrev_idx(n):
     b = n.bit_length() - 1
     return np.array([int(format(i, '0%db' % b)[::-1], 2) for i in range(n)])

@@ -147,3 +147,18 @@ def test_moment_reference_matches_scipy():
     assert np.allclose(r, [stats.pearsonr(data[0], data[1])[0], stats.pearsonr(data[2], data[3])[0]], rtol=1e-10)
     # the generator's shapes: skewness 2/sqrt(k) > 0.6, correlated odd columns
     assert sk[0] > 0.5 and sk[2] > 0.5 and abs(r[0]) > 0.05
+
+
+def test_table_key_check():
+    """A table is refused for another parameter set and only flagged for
+    another GPU or library build."""
+    from paper_2606_10477_amd import params
+    cur = {"gpu": "g", "params": "p16b", "params_sha256": params.set_sha256("p16b"), "library_sha256": "L"}
+    assert tuner.check_table_key(dict(cur), cur) is None
+    assert tuner.check_table_key(None, cur)[0] == "warn"
+    assert tuner.check_table_key(dict(cur, gpu="h"), cur)[0] == "warn"
+    assert tuner.check_table_key(dict(cur, library_sha256="M"), cur)[0] == "warn"
+    other = dict(cur, params="p16", params_sha256=params.set_sha256("p16"))
+    assert tuner.check_table_key(other, cur)[0] == "error"
+    assert params.set_sha256("p16b") != params.set_sha256("p16")
+    assert tuner.check_table_key(dict(cur, params_sha256="x"), cur)[0] == "error"
