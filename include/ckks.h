@@ -9,8 +9,8 @@
  * Mul_C, BTS, levels).  The scheme is RNS-CKKS with hybrid key switching; the
  * paper describes none of its internals, so every convention (prime chain,
  * NTT ordering, sampler, scale management, evaluation trees) is fixed by this
- * library's design document and reproduced bit for bit by an independent CPU
- * oracle.
+ * library, stated at the calls below, and reproduced bit for bit by an
+ * independent CPU oracle.
  *
  * Conventions shared by every call:
  *  - A context owns the parameters, the per-prime tables, the keys and the
