@@ -406,9 +406,11 @@ ckks_status ckks_ntt_schedule(ckks_ctx *ctx, int32_t r4_max_limbs, int32_t r8_ma
 
 /*
  * Arithmetic of the N = 2^16 transforms (a tuning knob; results are identical
- * either way): limbs whose prime is below 2^fp64_max_bits run their
- * butterflies in binary64 (an error-free product and a rounded quotient by
- * FMA, exact for primes below 2^42), the others on 64-bit integers.
+ * either way): in the 4- and 8-words-per-thread forms (see ckks_ntt_schedule),
+ * limbs whose prime is below 2^fp64_max_bits run their butterflies in binary64
+ * (an error-free product and a rounded quotient by FMA, exact for primes below
+ * 2^42), the others on 64-bit integers; the 16-word form keeps every prime on
+ * 64-bit integers.
  * fp64_max_bits = 0: integers for every prime; -1: the default (42); values
  * above 42 or below -1 give CKKS_E_PARAM.  Takes effect for launches issued
  * after the call; a transform's two passes must run under one setting.

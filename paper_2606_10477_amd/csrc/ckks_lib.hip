@@ -227,10 +227,10 @@ struct BtsPlan;
 
 // Default N = 2^16 transform schedule (ckks_ntt_schedule overrides it):
 // calls of at most this many limbs in total use 4 / 8 words per thread.
-constexpr int kNttR4Max = 32;
-constexpr int kNttR8Max = 32;
+constexpr int kNttR4Max = 128;
+constexpr int kNttR8Max = 128;
 // 4-word calls of at most this many limbs put 4 sub-transforms in a workgroup
-constexpr int kNttS4Max = 32;
+constexpr int kNttS4Max = 128;
 // N = 2^16 transforms of primes below 2^kNttFpBits run their butterflies in
 // binary64 (exact: the bounds are in kernels.hip); larger primes on 64-bit
 // integers.  The largest value the binary64 path accepts.

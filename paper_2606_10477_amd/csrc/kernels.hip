@@ -251,7 +251,9 @@ DEV u64 mul_shoup_lazy4(u64 a, u64 w, u64 wsh, u64 q) {
 // corrected by 4q, D = U - V + 4q < 8q into the product.
 constexpr u64 kSmallPrime = 1ull << 57;
 
-// Binary64 butterflies for primes q < 2^42 (T.fp_bits).  A residue is held as
+// Binary64 butterflies for primes q < 2^42 (T.fp_bits), in the 4- and 8-word
+// forms (k_nttr_*); the 16-word kernels keep every prime on the integer path,
+// whose registers already set their occupancy.  A residue is held as
 // an integer-valued double (exact below 2^53).  The product r = V w mod q
 // (up to a multiple of q) with the twiddle w < q and wq = fl(w / q):
 //   h = fl(V w), l = V w - h exactly (one FMA: the error-free product),
@@ -285,41 +287,6 @@ DEV u64 fp_canon(double x, double q, double qinv) {
 DEV double fp_bits(u64 w) { return __longlong_as_double((long long)w); }
 DEV u64 fp_word(double x) { return (u64)__double_as_longlong(x); }
 DEV bool fp_prime(const Tables &T, u64 q) { return T.fp_bits > 0 && q < (1ull << T.fp_bits); }
-
-// binary64 forward butterflies on v[0..15], 4 stages (pairing as fwd16)
-__device__ __forceinline__ void fwd16_fp(double v[16], const double *W, const double *Wq, int s0, int hi_part,
-                                         double q) {
-#pragma unroll
-    for (int j = 0; j < 4; ++j) {
-        const int h = 8 >> j;
-#pragma unroll
-        for (int m = 0; m < 16; ++m) {
-            if (m & h) continue;
-            const int wi = (1 << (s0 + j)) + (hi_part << j) + (m >> (4 - j));
-            const double U = v[m];
-            const double r = fp_mulmod(v[m + h], W[wi], Wq[wi], q);
-            v[m] = U + r;
-            v[m + h] = U - r;
-        }
-    }
-}
-// binary64 inverse butterflies on v[0..15], 4 stages (pairing as inv16)
-__device__ __forceinline__ void inv16_fp(double v[16], const double *W, const double *Wq, int logN, int lt0,
-                                         int hi_part, double q) {
-#pragma unroll
-    for (int j = 0; j < 4; ++j) {
-        const int h = 1 << j;
-#pragma unroll
-        for (int m = 0; m < 16; ++m) {
-            if (m & h) continue;
-            const int lt = lt0 + j;
-            const int wi = (1 << (logN - lt - 1)) + (hi_part << (3 - j)) + (m >> (j + 1));
-            const double U = v[m], V = v[m + h];
-            v[m] = U + V;
-            v[m + h] = fp_mulmod(U - V, W[wi], Wq[wi], q);
-        }
-    }
-}
 
 // forward butterflies (CT) on v[0..15] for 4 stages; element m pairs with
 // m + h (h = 8, 4, 2, 1); twiddle index for stage j (0..3): base_j + (m >> (4 - j))
@@ -403,24 +370,6 @@ __global__ void __launch_bounds__(256) k_ntt16_rows_fwd(u64 *dst, const u64 *src
 #pragma unroll
         for (int mm = 0; mm < 16; ++mm) v[mm] = L(v[mm]);
     }
-    if (fp_prime(T, q)) {
-        // binary64 butterflies; the pass's output words hold the doubles' bits
-        const double qd = T.pd[4 * pi];
-        const double *Wd = T.fw_d + ((size_t)pi << 16), *Wq = T.fwq_d + ((size_t)pi << 16);
-        double f[16];
-#pragma unroll
-        for (int mm = 0; mm < 16; ++mm) f[mm] = (double)v[mm];
-        fwd16_fp(f, Wd, Wq, 0, 0, qd);
-#pragma unroll
-        for (int mm = 0; mm < 16; ++mm) tile[(y + 16 * mm) * kPad + x] = fp_word(f[mm]);
-        __syncthreads();
-#pragma unroll
-        for (int mm = 0; mm < 16; ++mm) f[mm] = fp_bits(tile[(16 * y + mm) * kPad + x]);
-        fwd16_fp(f, Wd, Wq, 4, y, qd);
-#pragma unroll
-        for (int mm = 0; mm < 16; ++mm) out[((16 * y + mm) << 8) + c0 + x] = fp_word(f[mm]);
-        return;
-    }
     const bool small = q < kSmallPrime;
     if (small) fwd16<true>(v, W, Ws, 0, 0, q);
     else fwd16<false>(v, W, Ws, 0, 0, q);
@@ -450,28 +399,11 @@ __global__ void __launch_bounds__(256) k_ntt16_blocks_fwd(u64 *data, int nlimb, 
     const int blk0 = blockIdx.x * 16;   // global index of the first 256-block
     const int x = threadIdx.x & 15, y = threadIdx.x >> 4;
     u64 v[16];
-    const bool fp = fp_prime(T, q), small = q < kSmallPrime;
-    if (fp) {
-        // binary64 (the rows pass left doubles' bits), canonical words at the end
-        const double qd = T.pd[4 * pi], qi = T.pd[4 * pi + 1];
-        const double *Wd = T.fw_d + ((size_t)pi << 16), *Wq = T.fwq_d + ((size_t)pi << 16);
-        double f[16];
-#pragma unroll
-        for (int mm = 0; mm < 16; ++mm) f[mm] = fp_bits(d[(y << 8) + x + 16 * mm]);
-        fwd16_fp(f, Wd, Wq, 8, blk0 + y, qd);
-#pragma unroll
-        for (int mm = 0; mm < 16; ++mm) tile[(y * 16 + mm) * kPad + x] = fp_word(f[mm]);
-        __syncthreads();
-#pragma unroll
-        for (int mm = 0; mm < 16; ++mm) f[mm] = fp_bits(tile[(y * 16 + x) * kPad + mm]);
-        fwd16_fp(f, Wd, Wq, 12, (blk0 + y) * 16 + x, qd);
-#pragma unroll
-        for (int mm = 0; mm < 16; ++mm) v[mm] = fp_canon(f[mm], qd, qi);
-    } else {
     // phase 1: block y, words x + 16 m; stages 8..11 (distances 128..16)
 #pragma unroll
     for (int mm = 0; mm < 16; ++mm) v[mm] = d[(y << 8) + x + 16 * mm];
     // twiddle 2^s + (J >> (16 - s)), J = 256 (blk0 + y) + x + 16 m: hi_part = blk0 + y
+    const bool small = q < kSmallPrime;
     if (small) fwd16<true>(v, W, Ws, 8, blk0 + y, q);
     else fwd16<false>(v, W, Ws, 8, blk0 + y, q);
 #pragma unroll
@@ -490,7 +422,6 @@ __global__ void __launch_bounds__(256) k_ntt16_blocks_fwd(u64 *data, int nlimb, 
         const u64 inv64 = T.primes[pi].mu2_hi;
 #pragma unroll
         for (int mm = 0; mm < 16; ++mm) v[mm] = reduce_any(v[mm], inv64, q);
-    }
     }
     __syncthreads();
 #pragma unroll
@@ -531,25 +462,6 @@ __global__ void __launch_bounds__(256) k_ntt16_blocks_inv(u64 *dst, const u64 *s
 #pragma unroll
     for (int mm = 0; mm < 16; ++mm) tile[(y * 16 + mm) * kPad + x] = s_in[(y << 8) + x + 16 * mm];
     __syncthreads();
-    if (fp_prime(T, q)) {
-        // binary64; the pass's output words hold the doubles' bits
-        const double qd = T.pd[4 * pi];
-        const double *Wd = T.iw_d + ((size_t)pi << 16), *Wq = T.iwq_d + ((size_t)pi << 16);
-        double f[16];
-#pragma unroll
-        for (int mm = 0; mm < 16; ++mm) f[mm] = (double)tile[(y * 16 + x) * kPad + mm];
-        inv16_fp(f, Wd, Wq, 16, 0, (blk0 + y) * 16 + x, qd);
-        __syncthreads();
-#pragma unroll
-        for (int mm = 0; mm < 16; ++mm) tile[(y * 16 + x) * kPad + mm] = fp_word(f[mm]);
-        __syncthreads();
-#pragma unroll
-        for (int mm = 0; mm < 16; ++mm) f[mm] = fp_bits(tile[(y * 16 + mm) * kPad + x]);
-        inv16_fp(f, Wd, Wq, 16, 4, blk0 + y, qd);
-#pragma unroll
-        for (int mm = 0; mm < 16; ++mm) d[(y << 8) + x + 16 * mm] = fp_word(f[mm]);
-        return;
-    }
     // phase A: block y, words 16 x + m; half-distances 1..8.  Group index of
     // word J for distance t: J >> (lt + 1), J = 256 (blk0 + y) + 16 x + m
 #pragma unroll
@@ -578,25 +490,6 @@ __global__ void __launch_bounds__(256) k_ntt16_rows_inv(u64 *data, int nlimb, in
     const int c0 = blockIdx.x * 16;
     const int x = threadIdx.x & 15, y = threadIdx.x >> 4;
     u64 v[16];
-    if (fp_prime(T, q)) {
-        // binary64 from the first pass's doubles, re-centred first; canonical words out
-        const double qd = T.pd[4 * pi], qi = T.pd[4 * pi + 1], nd = T.pd[4 * pi + 2], ndq = T.pd[4 * pi + 3];
-        const double *Wd = T.iw_d + ((size_t)pi << 16), *Wq = T.iwq_d + ((size_t)pi << 16);
-        double f[16];
-#pragma unroll
-        for (int mm = 0; mm < 16; ++mm) f[mm] = fp_centre(fp_bits(d[((16 * y + mm) << 8) + c0 + x]), qd, qi);
-        inv16_fp(f, Wd, Wq, 16, 8, y, qd);
-#pragma unroll
-        for (int mm = 0; mm < 16; ++mm) tile[(16 * y + mm) * kPad + x] = fp_word(f[mm]);
-        __syncthreads();
-#pragma unroll
-        for (int mm = 0; mm < 16; ++mm) f[mm] = fp_bits(tile[(y + 16 * mm) * kPad + x]);
-        inv16_fp(f, Wd, Wq, 16, 12, 0, qd);
-#pragma unroll
-        for (int mm = 0; mm < 16; ++mm)
-            d[((y + 16 * mm) << 8) + c0 + x] = fp_canon(fp_mulmod(f[mm], nd, ndq, qd), qd, qi);
-        return;
-    }
     // phase A: rows k = 16 y + m (row distances 1..8 = global 256..2048)
 #pragma unroll
     for (int mm = 0; mm < 16; ++mm) v[mm] = d[((16 * y + mm) << 8) + c0 + x];
@@ -703,7 +596,7 @@ __device__ __forceinline__ void inv_stage(u64 *v, int u, int lo, int b, int blkg
     }
 }
 
-// binary64 twins of fwd_stage / inv_stage (the bounds of fwd16_fp / inv16_fp)
+// binary64 twins of fwd_stage / inv_stage (bounds as stated with fp_mulmod)
 template <int R, bool ROWS>
 __device__ __forceinline__ void fwd_stage_fp(double *v, int u, int lo, int b, int blkg, const double *W,
                                              const double *Wq, double q) {
@@ -1969,7 +1862,8 @@ void pt_mac(const Tables &T, uint64_t *out, const MacArgs &a, int nlimb, int npo
 
 // one thread per (member, limb, word): both polys of every baby in registers
 // (NB is a template parameter so that the arrays stay in registers), then one
-// accumulation per giant
+// accumulation per giant; the next giant's plaintext words are loaded while
+// the current giant's products are summed
 template <int NB>
 __global__ void __launch_bounds__(256) k_pt_mac_giants(u64 *out, size_t gstride, GiantArgs a, int logN, int nlimb,
                                                        size_t total, LimbMap m, Tables T) {
@@ -1988,15 +1882,23 @@ __global__ void __launch_bounds__(256) k_pt_mac_giants(u64 *out, size_t gstride,
             x0[b] = a.x[b][base];
             x1[b] = a.x[b][base + per];
         }
+        u64 wn[NB];
+#pragma unroll
+        for (int b = 0; b < NB; ++b) wn[b] = a.pt[0][b] ? a.pt[0][b][rem] : 0;
         for (int k = 0; k < a.ng; ++k) {
+            u64 w[NB];
+#pragma unroll
+            for (int b = 0; b < NB; ++b) w[b] = wn[b];
+            if (k + 1 < a.ng) {
+#pragma unroll
+                for (int b = 0; b < NB; ++b) wn[b] = a.pt[k + 1][b] ? a.pt[k + 1][b][rem] : 0;
+            }
             u64 h0 = 0, l0 = 0, h1 = 0, l1 = 0;
 #pragma unroll
             for (int b = 0; b < NB; ++b) {
-                const u64 *p = a.pt[k][b];
-                if (p) {
-                    const u64 w = p[rem];
-                    mac128(h0, l0, w, x0[b]);
-                    mac128(h1, l1, w, x1[b]);
+                if (a.pt[k][b]) {
+                    mac128(h0, l0, w[b], x0[b]);
+                    mac128(h1, l1, w[b], x1[b]);
                 }
             }
             u64 *o = out + k * gstride + base;

@@ -7,6 +7,11 @@ under every schedule; only the time changes.
 
     python -m paper_2606_10477_amd.ntt_tune [--limbs 1,2,4,...] [--json PATH]
 
+With --chain it times the benchmarked chain (bootstrapping set, degree 31,
+3 Newton steps, one ciphertext) under the listed schedules instead:
+
+    python -m paper_2606_10477_amd.ntt_tune --chain "s32:32,32,32;s128:128,128,128"
+
 With --calls K it only issues K forward and K inverse transforms at each
 size under the library's schedule, untimed, for a counter profiler to
 attribute per dispatch (each dispatch's grid gives its limb count):
@@ -94,15 +99,61 @@ def choose(rows, tol=0.01):
     return r4, r8, s4, best
 
 
+def chain_times(schedules, reps=3, runs=10):
+    """The benchmarked chain (bootstrapping set, degree 31, 3 Newton steps,
+    one ciphertext from the top level) under each (name, (r4, r8, s4))
+    schedule: the best of `reps` means over `runs` calls, in ms; the result
+    words are checked equal across schedules."""
+    import numpy as np
+    from . import ckks, inputs
+    ctx = ckks.Context.from_set("p16b")
+    ctx.keygen(9, ctx.bts_galois())
+    x = inputs.log_uniform(ctx.n, 2.0 ** -10, 1.0, 1)
+    ct = ctx.encrypt(x, ctx.l_after, 2.0 ** 50, 3)
+    out, ref = [], None
+    for name, sc in schedules:
+        ctx.ntt_schedule(*sc)
+        w = ctx.invsqrt(ct, 31, 3, 2.0 ** -10, 1.0).words()
+        if ref is None:
+            ref = w
+        if not np.array_equal(w, ref):
+            raise RuntimeError(f"schedule {name} changed the result words")
+        best = float("inf")
+        for _ in range(reps):
+            ctx.sync()
+            t0 = time.perf_counter()
+            for _ in range(runs):
+                ctx.invsqrt(ct, 31, 3, 2.0 ** -10, 1.0)
+            ctx.sync()
+            best = min(best, (time.perf_counter() - t0) / runs)
+        out.append({"schedule": name, "bounds": list(sc), "ms": 1e3 * best})
+        print(json.dumps(out[-1]), flush=True)
+    ctx.ntt_schedule(-1, -1, -1)
+    ctx.close()
+    return out
+
+
 def main(argv=None):
     ap = argparse.ArgumentParser()
     ap.add_argument("--limbs", default=",".join(str(s) for s in SIZES))
     ap.add_argument("--json", default=None)
     ap.add_argument("--calls", type=int, default=0, help="only issue this many calls per size (for profilers)")
+    ap.add_argument("--chain", default=None,
+                    help="time the benchmarked chain under schedules 'name:r4,r8,s4;...' instead of scanning")
     a = ap.parse_args(argv)
     import torch
     from . import ckks
     torch.cuda.set_device(0)
+    if a.chain:
+        sch = []
+        for item in a.chain.split(";"):
+            name, b = item.split(":")
+            sch.append((name, tuple(int(v) for v in b.split(","))))
+        res = chain_times(sch)
+        if a.json:
+            with open(a.json, "w") as f:
+                json.dump(res, f, indent=1)
+        return
     ctx = ckks.Context.from_set("p16b", bootstrapping=False)
     if a.calls:
         issue(ctx, [int(s) for s in a.limbs.split(",")], ctx.np_, a.calls)

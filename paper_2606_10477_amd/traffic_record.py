@@ -126,35 +126,37 @@ def _short(name):
     return name.split("(", 1)[0].replace("void ", "").strip()
 
 
-def _dispatches(d):
+def _dispatches(d, every=False):
     """{dispatch id: (kernel, limbs, {counter: value})} of the NTT dispatches
-    of one counter run."""
+    of one counter run (every=True: of every kernel, limbs 0)."""
     out = {}
     for r in _rows(d):
         name = r["Kernel_Name"]
-        if not _is_ntt16(name):
+        if not (every or _is_ntt16(name)):
             continue
         k = int(r["Dispatch_Id"])
-        e = out.setdefault(k, (_short(name), _limbs(name, r["Grid_Size"]), {}))
+        e = out.setdefault(k, (_short(name), _limbs(name, r["Grid_Size"]) if _is_ntt16(name) and not every else 0,
+                               {}))
         e[2][r["Counter_Name"]] = e[2].get(r["Counter_Name"], 0.0) + float(r["Counter_Value"])
     return out
 
 
-def _trace_durations(d):
-    """{(kernel, limbs): [duration us]} of the NTT dispatches of a kernel trace."""
+def _trace_durations(d, every=False):
+    """{(kernel, limbs): [duration us]} of the NTT dispatches of a kernel trace
+    (every=True: of every kernel, limbs 0)."""
     out = {}
     with open(os.path.join(d, "run_kernel_trace.csv")) as f:
         for r in csv.DictReader(f):
             name = r["Kernel_Name"]
-            if not _is_ntt16(name):
+            if not (every or _is_ntt16(name)):
                 continue
             g = int(r["Grid_Size_X"]) * int(r["Grid_Size_Y"]) * int(r["Grid_Size_Z"])
-            key = (_short(name), _limbs(name, g))
+            key = (_short(name), 0 if every else _limbs(name, g))
             out.setdefault(key, []).append((int(r["End_Timestamp"]) - int(r["Start_Timestamp"])) / 1e3)
     return out
 
 
-def counter_table(trace_dir, sq_dirs, fetch_dir, write_dir, fs, ws):
+def counter_table(trace_dir, sq_dirs, fetch_dir, write_dir, fs, ws, every=False):
     """Per (kernel, limbs): mean duration from the trace, mean counters over
     the counter runs' dispatches, and the derived figures (per dispatch):
       hbm_GBps   = (FETCH_SIZE fs + WRITE_SIZE ws) KiB / duration,
@@ -167,10 +169,10 @@ def counter_table(trace_dir, sq_dirs, fetch_dir, write_dir, fs, ws):
                    64-lane instruction on 16 lanes),
       cu_busy    = 100 SQ_BUSY_CU_CYCLES / (CU_NUM cycles) (cycles, summed over CUs),
       wait       = 100 SQ_WAIT_ANY / SQ_WAVE_CYCLES (share of wave time stalled)."""
-    dur = _trace_durations(trace_dir)
+    dur = _trace_durations(trace_dir, every)
     acc = {}
     for d in list(sq_dirs) + [fetch_dir, write_dir]:
-        for name, limbs, cnt in _dispatches(d).values():
+        for name, limbs, cnt in _dispatches(d, every).values():
             a = acc.setdefault((name, limbs), {})
             for c, v in cnt.items():
                 a.setdefault(c, []).append(v)
@@ -182,7 +184,9 @@ def counter_table(trace_dir, sq_dirs, fetch_dir, write_dir, fs, ws):
              "us": sum(t) / len(t) if t else None}
         if "FETCH_SIZE" in m and "WRITE_SIZE" in m:
             b = (m["FETCH_SIZE"] * fs + m["WRITE_SIZE"] * ws) * 1024.0
-            r["hbm_bytes_per_limb"] = b / key[1]
+            r["hbm_bytes"] = b
+            if key[1]:
+                r["hbm_bytes_per_limb"] = b / key[1]
             if r["us"]:
                 r["hbm_GBps"] = b / r["us"] / 1e3
         if r["us"]:
@@ -198,7 +202,7 @@ def counter_table(trace_dir, sq_dirs, fetch_dir, write_dir, fs, ws):
         for c in ("SQ_INSTS_VALU", "SQ_INSTS_VALU_INT64", "SQ_INSTS_VALU_INT32", "SQ_INSTS_VALU_FMA_F64",
                   "SQ_INSTS_LDS", "SQ_INSTS_SALU", "SQ_LDS_BANK_CONFLICT", "SQ_ACTIVE_INST_LDS"):
             if c in m:
-                r[c.replace("SQ_", "").lower() + "_per_limb"] = m[c] / key[1]
+                r[c.replace("SQ_", "").lower() + "_per_limb"] = m[c] / (key[1] or 1)
         rows.append(r)
     return rows
 
@@ -234,10 +238,12 @@ def main(argv=None):
         cp.add_argument("sq_dirs", nargs="+")
         cp.add_argument("--copy-mib", type=int, default=512)
         cp.add_argument("--json", default=None)
+        cp.add_argument("--every-kernel", action="store_true",
+                        help="every kernel, grouped by name (per-dispatch figures averaged)")
         c = cp.parse_args(argv[1:])
         nb = c.copy_mib << 20
         rows = counter_table(c.trace_dir, c.sq_dirs, c.fetch_dir, c.write_dir,
-                             _copy_scale(c.copy_fetch_dir, nb), _copy_scale(c.copy_write_dir, nb))
+                             _copy_scale(c.copy_fetch_dir, nb), _copy_scale(c.copy_write_dir, nb), c.every_kernel)
         if c.json:
             with open(c.json, "w") as f:
                 json.dump(rows, f, indent=1)
