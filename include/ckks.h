@@ -148,7 +148,10 @@ int32_t ckks_galois_rotation(const ckks_ctx *ctx, int32_t steps);
 /*
  * Public-key encryption of n <= N/2 real slot values (the rest are zero) at
  * `level`, encoded at `scale` (quad-precision canonical embedding, rounded to
- * nearest).  Randomness from SHAKE-256 on `seed`.
+ * nearest): the Enc(., l) of Alg. 3, which encrypts its input vector at the
+ * level under test.  Randomness from SHAKE-256 on `seed`.  Errors:
+ * CKKS_E_NOKEY before ckks_keygen, CKKS_E_PARAM for n > N/2, CKKS_E_LEVEL for
+ * level > L, CKKS_E_RANGE when a scaled value does not fit the encoding.
  */
 ckks_status ckks_encrypt(ckks_ctx *ctx, const double *x, uint32_t n, uint32_t level,
                          double scale, uint64_t seed, ckks_ct **out);
@@ -159,7 +162,9 @@ ckks_status ckks_encrypt(ckks_ctx *ctx, const double *x, uint32_t n, uint32_t le
 ckks_status ckks_encrypt_batch(ckks_ctx *ctx, const double *x, uint32_t n_ct, uint32_t n, uint32_t level,
                                double scale, uint64_t seed0, ckks_ct **outs);
 /* Decrypt with the context's secret key and decode N/2 slots (real parts to
- * `re`, imaginary parts to `im`; `im` may be NULL). */
+ * `re`, imaginary parts to `im`; `im` may be NULL): the Dec of Alg. 2, whose
+ * output the MRE of §4.2 is measured on.  `re` / `im` are host arrays of N/2
+ * doubles.  Errors: CKKS_E_NOKEY before ckks_keygen. */
 ckks_status ckks_decrypt(ckks_ctx *ctx, const ckks_ct *ct, double *re, double *im);
 
 /* Ciphertext transfer: host words [B][2][level+1][N] (fully reduced) <->
