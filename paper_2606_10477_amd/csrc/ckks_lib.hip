@@ -655,6 +655,19 @@ u64 *poly(const ckks_ctx *c, const ckks_ct *ct, int p, int b = 0) {
     return ct->buf.p + ((size_t)b * 2 + p) * (ct->level + 1) * c->N;
 }
 
+// a view of a's words under another scale, owning nothing: for temporaries
+// of one operation whose source outlives them (never handed to a caller)
+Ct ct_borrow(const ckks_ct *a, double scale) {
+    Ct v(new ckks_ct);
+    v->level = a->level;
+    v->scale = scale;
+    v->B = a->B;
+    v->buf.pool = nullptr;
+    v->buf.p = a->buf.p;
+    v->buf.bytes = a->buf.bytes;
+    return v;
+}
+
 Ct ct_copy(ckks_ctx *c, const ckks_ct *a) {
     trace_op(c, "copy", a->level, a->B);
     Ct r = ct_new(c, a->level, a->scale, a->B);
@@ -1501,7 +1514,7 @@ Ct op_cheb(ckks_ctx *c, const ckks_ct *x, const std::vector<double> &cf, double 
     if (d < 1) fail(CKKS_E_PARAM, "degree must be >= 1");
     Ct t;
     if (a == -1.0 && b == 1.0) {
-        t = ct_copy(c, x);
+        t = ct_borrow(x, x->scale);   // x outlives the evaluation
     } else {
         if (x->level < 1) fail(CKKS_E_LEVEL, "no level for the affine map");
         double al = 2.0 / (b - a);
@@ -1930,8 +1943,7 @@ Ct op_invsqrt(ckks_ctx *c, const ckks_ct *x0, int degree, int iters, const ckks_
             // change of scale, with the scale-back kappa = 1/sqrt(B) folded
             // in: the x operand declared as kappa x / (2B), the constant
             // 1.5 kappa
-            Ct xr = ct_copy(c, x);
-            xr->scale = x->scale * (2.0 * (Bn / sx) * std::sqrt(Bn));
+            Ct xr = ct_borrow(x, x->scale * (2.0 * (Bn / sx) * std::sqrt(Bn)));
             y = op_newton(c, y.get(), xr.get(), true, 1.5 * kappa);
         } else {
             y = op_newton(c, y.get(), cx.get(), false);

@@ -1558,8 +1558,12 @@ __global__ void k_key_inner_jobs(u64 *acc, InnerArgs a, KsJobs J, int logN, size
         const size_t j = i & (N - 1);
         const int pi = a.m.p[e];
         const DevPrime P = T.primes[pi];
+        // the next job's permutation word is loaded while the current job's
+        // digits (read at the permuted index) are being gathered
+        size_t jxn = J.perm[0] ? (size_t)J.perm[0][j] : j;
         for (int t = 0; t < J.njob; ++t) {
-            const size_t jx = J.perm[t] ? (size_t)J.perm[t][j] : j;
+            const size_t jx = jxn;
+            if (t + 1 < J.njob) jxn = J.perm[t + 1] ? (size_t)J.perm[t + 1][j] : j;
             const u64 *key = J.key[t];
             for (int b = 0; b < J.B; ++b) {
                 const size_t ct = (size_t)(J.ct0[t] + b);
@@ -1599,8 +1603,10 @@ __global__ void k_key_inner_jobs_sum(u64 *acc, InnerArgs a, KsJobs J, int accumu
         const DevPrime P = T.primes[pi];
         for (int b = 0; b < J.B; ++b) {
             u64 h0 = 0, l0 = 0, h1 = 0, l1 = 0;   // < 2^127 for up to 128 terms of < 2^120
+            size_t jxn = J.perm[0] ? (size_t)J.perm[0][j] : j;   // one job ahead, as above
             for (int t = 0; t < J.njob; ++t) {
-                const size_t jx = J.perm[t] ? (size_t)J.perm[t][j] : j;
+                const size_t jx = jxn;
+                if (t + 1 < J.njob) jxn = J.perm[t + 1] ? (size_t)J.perm[t + 1][j] : j;
                 const u64 *key = J.key[t];
                 const size_t ct = (size_t)(J.ct0[t] + b);
                 for (int d = 0; d < a.ndig; ++d) {
