@@ -15,6 +15,11 @@ processes (keys shared copy-on-write), for an all-core throughput; with
 compete with GPU timing.  Prints one JSON line.
 
     python -m oracle.chain_timer --level 8 --degree 31 --iters 3 --procs 16
+
+With --per-op it times the chain's single operations on one core instead
+(products at three levels, a rotation, a rescale, each bootstrapping step):
+
+    python -m oracle.chain_timer --per-op
 """
 import argparse
 import hashlib
@@ -53,6 +58,33 @@ def one(o, O, inputs, args, i):
     return {"seconds": dt, "mre": mre, "level": y.level, "scale": float(y.scale).hex(), "sha256": sha}
 
 
+def per_op(o, inputs):
+    """Single-core seconds of the chain's operations on the same set: the
+    product with relinearisation and rescale at the top, middle and bottom
+    computation levels, a rotation, a rescale, and each bootstrapping step."""
+    x = inputs.log_uniform(o.n, LO, HI, 1)
+    out = {}
+
+    def tm(name, f):
+        t0 = time.perf_counter()
+        r = f()
+        out[name] = time.perf_counter() - t0
+        return r
+    top = o.encrypt(x, o.l_after, 2.0 ** 50, 3)
+    for lv in (o.l_after, 4, 1):
+        c = o.level_to(top, lv) if lv != o.l_after else top
+        tm(f"mult_relin_rescale@{lv}", lambda c=c: o.mult_rs(c, c))
+    tm(f"rotate@{o.l_after}", lambda: o.rotate(top, 1))
+    tm(f"rescale@{o.l_after}", lambda: o.rescale(o.mul_int(top, 3)))
+    y0 = o.invsqrt(top, 31, 0, LO, HI)
+    r = tm("mod_raise", lambda: o.mod_raise(o.drop_level(y0, 0)))
+    y = tm("coeff_to_slot", lambda: o.coeff_to_slot(r))
+    e = tm("eval_mod", lambda: o.eval_mod(o.add(y, o.conjugate(y))))
+    tm("slot_to_coeff", lambda: o.slot_to_coeff(e))
+    tm("bootstrap", lambda: o.bootstrap(y0, 512))
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--level", type=int, default=8)
@@ -60,6 +92,7 @@ def main():
     ap.add_argument("--iters", type=int, default=3)
     ap.add_argument("--procs", type=int, default=1, help="processes of the all-core phase (1: skip it)")
     ap.add_argument("--wait-go", action="store_true", help="start the all-core phase on a line from stdin")
+    ap.add_argument("--per-op", action="store_true", help="time the chain's single operations instead")
     args = ap.parse_args()
     from oracle import oracle as O
     from paper_2606_10477_amd import inputs
@@ -67,6 +100,10 @@ def main():
     o = O.Context.from_set("p16b")
     o.keygen(9, o.bts_galois())
     t_setup = time.perf_counter() - t0
+    if args.per_op:
+        print(json.dumps({"per_op_seconds": per_op(o, inputs), "setup_seconds": t_setup, "cores": 1,
+                          "cpu_model": cpu_model(), "nproc": os.cpu_count()}), flush=True)
+        return
     res = one(o, O, inputs, args, 0)
     res.update({"setup_seconds": t_setup, "cores": 1, "cpu_model": cpu_model(), "nproc": os.cpu_count(),
                 "affinity": len(os.sched_getaffinity(0))})

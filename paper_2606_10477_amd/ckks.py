@@ -10,7 +10,8 @@ import os
 import numpy as np
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
-LIB_PATH = os.path.join(_HERE, "libckks_hip.so")
+# CKKS_LIB selects another build of this library (for comparing builds)
+LIB_PATH = os.environ.get("CKKS_LIB") or os.path.join(_HERE, "libckks_hip.so")
 _lib = None
 
 vp = C.c_void_p

@@ -543,18 +543,11 @@ template <int R> __device__ constexpr int inv_lo(int p) {
 template <int R> __device__ __forceinline__ int k_of(int u, int m, int lo) {
     return ((u >> lo) << (lo + Geo<R>::r)) | (m << lo) | (u & ((1 << lo) - 1));
 }
-// LDS address of (lane, k), laid out so that no 16 lanes of a wave (the 128
-// bytes the LDS serves per cycle) hit one bank twice in any phase: rows view
-// [k][lane] with pitch S + 1 for S = 16, and for S = 4 four words per row with
-// the rows permuted by k ^ ((k >> 2) & 3) (the phases whose consecutive
-// threads step k by 4 then land on distinct banks); blocks view [lane][k'] with
-// k' = k ^ ((k >> sh) & 15), sh = 2 for R = 4 and 3 for R = 8 (all phases'
-// 16-lane groups then spread over the 16 eight-byte bank pairs).  256 (S + 1)
-// words hold either.
-template <bool ROWS, int S, int R> __device__ __forceinline__ int lds_at(int lane, int k) {
-    if (ROWS) return S == 4 ? 4 * (k ^ ((k >> 2) & 3)) + lane : k * (S + 1) + lane;
-    constexpr int sh = R == 8 ? 3 : 2;
-    return lane * 256 + (k ^ ((k >> sh) & 15));
+// LDS address of (lane, k): rows view [k][lane] with pitch S + 1, blocks
+// view [lane][k >> 4][k & 15] with pitch 17 per 16 words (256 (S + 1) words
+// hold either)
+template <bool ROWS, int S> __device__ __forceinline__ int lds_at(int lane, int k) {
+    return ROWS ? k * (S + 1) + lane : (lane * 16 + (k >> 4)) * kPad + (k & 15);
 }
 
 // forward butterflies of stage bit b (global stage s) on registers pairing
@@ -648,7 +641,7 @@ __device__ __forceinline__ void pass_phases_fp(double *v, u64 *tile, int lane, i
         if (p > 0) {
             __syncthreads();
 #pragma unroll
-            for (int m = 0; m < R; ++m) v[m] = fp_bits(tile[lds_at<ROWS, S, R>(lane, k_of<R>(u, m, lo))]);
+            for (int m = 0; m < R; ++m) v[m] = fp_bits(tile[lds_at<ROWS, S>(lane, k_of<R>(u, m, lo))]);
         }
         if (FWD) {
             const int b_hi = 8 - r * p - 1, b_lo = lo;
@@ -661,7 +654,7 @@ __device__ __forceinline__ void pass_phases_fp(double *v, u64 *tile, int lane, i
         }
         if (p + 1 < NPH) {
 #pragma unroll
-            for (int m = 0; m < R; ++m) tile[lds_at<ROWS, S, R>(lane, k_of<R>(u, m, lo))] = fp_word(v[m]);
+            for (int m = 0; m < R; ++m) tile[lds_at<ROWS, S>(lane, k_of<R>(u, m, lo))] = fp_word(v[m]);
         }
     }
 }
@@ -678,7 +671,7 @@ __device__ __forceinline__ void pass_phases(u64 *v, u64 *tile, int lane, int u, 
         if (p > 0) {
             __syncthreads();   // the previous phase's words are all in LDS
 #pragma unroll
-            for (int m = 0; m < R; ++m) v[m] = tile[lds_at<ROWS, S, R>(lane, k_of<R>(u, m, lo))];
+            for (int m = 0; m < R; ++m) v[m] = tile[lds_at<ROWS, S>(lane, k_of<R>(u, m, lo))];
         }
         if (FWD) {
             const int b_hi = 8 - r * p - 1, b_lo = lo;   // stage bits, high to low
@@ -692,7 +685,7 @@ __device__ __forceinline__ void pass_phases(u64 *v, u64 *tile, int lane, int u, 
         if (p + 1 < NPH) {
             // each thread writes back exactly the words it read in this phase
 #pragma unroll
-            for (int m = 0; m < R; ++m) tile[lds_at<ROWS, S, R>(lane, k_of<R>(u, m, lo))] = v[m];
+            for (int m = 0; m < R; ++m) tile[lds_at<ROWS, S>(lane, k_of<R>(u, m, lo))] = v[m];
         }
     }
 }
