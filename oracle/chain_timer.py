@@ -69,6 +69,7 @@ def per_op(o, inputs):
         t0 = time.perf_counter()
         r = f()
         out[name] = time.perf_counter() - t0
+        print(f"{name}: {out[name]:.3f} s", file=sys.stderr, flush=True)
         return r
     top = o.encrypt(x, o.l_after, 2.0 ** 50, 3)
     for lv in (o.l_after, 4, 1):
