@@ -403,8 +403,10 @@ ckks_status ckks_ntt_device(ckks_ctx *ctx, uint64_t *data, uint32_t n_limbs,
  * exchanges (better for large ones).  A 4-word call of at most `s4_max_limbs`
  * limbs puts 4 sub-transforms of 256 points in each workgroup instead of 16
  * (four times as many workgroups for calls too small to fill the chip).  -1
- * restores the library's default for that bound; values below -1 give
- * CKKS_E_PARAM.  Takes effect for launches issued after the call.
+ * restores the library's default for that bound (128 limbs for each: 4 words
+ * and 4 sub-transforms per workgroup up to 128 limbs, 16 words above); values
+ * below -1 give CKKS_E_PARAM.  Takes effect for launches issued after the
+ * call.
  */
 ckks_status ckks_ntt_schedule(ckks_ctx *ctx, int32_t r4_max_limbs, int32_t r8_max_limbs,
                               int32_t s4_max_limbs);

@@ -11,7 +11,6 @@ Every column (or column pair) goes through the same launches: ciphertext j of
 every column forms one batch, as in znorm.py.  Each result sits in every slot
 of one ciphertext per column (pair).
 """
-import math
 
 from .znorm import _log2_exact, mul_pow2_down, rotate_and_sum
 
