@@ -44,6 +44,7 @@ class Request:
     iters: int = 0
     c: int = 0
     outs: dict = field(default_factory=dict)
+    run_level: int = None   # the level the ciphertexts are dropped to before the chain (route())
     admitted: float = None
     done: float = None
     issued: int = 0         # ciphertexts handed to groups so far
@@ -69,6 +70,38 @@ def lookup(table, level, target):
     return ent["degree"], ent.get("c", 0), ent["iters"]
 
 
+def _entry_time(table, level, target):
+    """Measured (else predicted) seconds of the table's own entry for
+    (level, target), or None when the level has no such entry."""
+    ent = table.get(str(level), {}).get(f"{target:.3g}")
+    if not ent:
+        return None
+    return ent.get("t_meas", ent.get("t_pred"))
+
+
+def route(table, level, target, tol=0.02):
+    """(run level, degree, c, iters) of a request: its tuned setting, run at
+    the lowest tuned level not above `level` whose own table entry for
+    `target` is the same setting at no more than (1 + tol) times the
+    measured time of the entry it came from (dropping limbs from a
+    ciphertext costs no level budget the setting needs: the table says the
+    lower level reaches the target as fast).  Requests that meet at one run
+    level and setting share launches.  The choice depends only on the table
+    and the request, so a request's result is the same alone or in a mix.
+    Tables without times (no t_meas / t_pred) route nothing."""
+    d, c, i = lookup(table, level, target)
+    t = _entry_time(table, level, target)
+    if t is None:
+        return level, d, c, i
+    for low in sorted(int(k) for k in table):
+        if low >= level:
+            break
+        tl = _entry_time(table, low, target)
+        if tl is not None and tl <= t * (1.0 + tol) and lookup(table, low, target) == (d, c, i):
+            return low, d, c, i
+    return level, d, c, i
+
+
 class Lane:
     """A context on a stream of its own.  With a torch stream, device events
     time each group's completion; without one (tests), the host clock at the
@@ -87,7 +120,7 @@ class Lane:
             self.t0.record(self.stream)
 
     def issue(self, key, work, lo, hi, now):
-        cts = [r.cts[k] for r, k in work]
+        cts = [r.cts[k] if r.cts[k].level == key[0] else self.ctx.drop_level(r.cts[k], key[0]) for r, k in work]
         outs = self.ctx.invsqrt_batch(cts, key[1], key[3], a=lo, b=hi, pre_bts=bool(key[2]))
         end = None
         if self.stream is not None:
@@ -125,7 +158,8 @@ class Server:
 
     def est_bytes(self, req, n=None):
         n = len(req.cts) if n is None else n
-        per = self.ws.get(req.level, self.ct_factor * self.ct_bytes[req.level])
+        lv = req.run_level if req.run_level is not None else req.level
+        per = self.ws.get(lv, self.ct_factor * self.ct_bytes[lv])
         return n * per
 
     def available(self):
@@ -133,7 +167,7 @@ class Server:
         return info[0]["device_free"] + sum(i["pool_cached"] for i in info) - self.reserve
 
     def submit(self, req):
-        req.degree, req.c, req.iters = lookup(self.table, req.level, req.target)
+        req.run_level, req.degree, req.c, req.iters = route(self.table, req.level, req.target)
         self.queue.append(req)
 
     def _admit(self, now):
@@ -159,10 +193,10 @@ class Server:
         cand = [r for r in sorted(self.active, key=lambda r: r.arrival) if r.issued < len(r.cts)]
         if not cand:
             return None, []
-        key = (cand[0].level, cand[0].degree, cand[0].c, cand[0].iters)
+        key = (cand[0].run_level, cand[0].degree, cand[0].c, cand[0].iters)
         work = []
         for r in cand:
-            if (r.level, r.degree, r.c, r.iters) != key:
+            if (r.run_level, r.degree, r.c, r.iters) != key:
                 continue
             while r.issued < len(r.cts) and len(work) < self.max_batch:
                 work.append((r, r.issued))
@@ -243,12 +277,13 @@ def run_one_at_a_time(ctx, table, requests, lo=2.0 ** -10, hi=1.0):
     t0 = time.perf_counter()
     clock = lambda: time.perf_counter() - t0
     for r in sorted(requests, key=lambda r: r.arrival):
-        r.degree, r.c, r.iters = lookup(table, r.level, r.target)
+        r.run_level, r.degree, r.c, r.iters = route(table, r.level, r.target)
         wait = r.arrival - clock()
         if wait > 0:
             time.sleep(wait)
         r.admitted = clock()
-        outs = ctx.invsqrt_batch(r.cts, r.degree, r.iters, a=lo, b=hi, pre_bts=bool(r.c))
+        cts = [c if c.level == r.run_level else ctx.drop_level(c, r.run_level) for c in r.cts]
+        outs = ctx.invsqrt_batch(cts, r.degree, r.iters, a=lo, b=hi, pre_bts=bool(r.c))
         ctx.sync()
         r.outs = dict(enumerate(outs))
         r.done = clock()

@@ -5,8 +5,9 @@ from paper_2606_10477_amd import serve
 
 
 class FakeCt:
-    def __init__(self, tag):
+    def __init__(self, tag, level=None):
         self.tag = tag
+        self.level = level
 
 
 class FakeCtx:
@@ -16,13 +17,20 @@ class FakeCtx:
 
     def __init__(self, free=1 << 40, immediate=True):
         self.calls = []
+        self.drops = []
+        self.levels = []
         self.free = free
         self.immediate = immediate
         self.pending = False
         self.in_use = 0
 
+    def drop_level(self, ct, level):
+        self.drops.append((ct.tag, ct.level, level))
+        return FakeCt(ct.tag, level)
+
     def invsqrt_batch(self, cts, degree, iters, a=None, b=None, pre_bts=False):
         self.calls.append((len(cts), degree, iters) + ((1,) if pre_bts else ()))
+        self.levels.append(sorted({c.level for c in cts}))
         self.pending = not self.immediate
         return [FakeCt(("y", c.tag, degree, iters)) for c in cts]
 
@@ -45,7 +53,7 @@ TABLE = {"13": {"1e-06": {"degree": 15, "iters": 2}, "1e-07": {"degree": 31, "it
 
 
 def mk(rid, t, n, level, target):
-    return serve.Request(rid, t, [FakeCt((rid, k)) for k in range(n)], level, target)
+    return serve.Request(rid, t, [FakeCt((rid, k), level) for k in range(n)], level, target)
 
 
 def test_lookup_exact_and_fallback():
@@ -157,3 +165,40 @@ def test_summary():
         r.done = r.arrival + 0.5 + 0.1 * i
     s = serve.summarize(rs)
     assert s["ciphertexts"] == 8 and s["p50_latency_s"] == pytest.approx(0.65)
+
+
+TIMED = {"6": {"3.1e-08": {"degree": 31, "c": 0, "iters": 4, "t_meas": 0.034}},
+         "7": {"1e-06": {"degree": 15, "c": 0, "iters": 4, "t_meas": 0.0177},
+               "3.1e-08": {"degree": 31, "c": 0, "iters": 3, "t_meas": 0.0183}},
+         "8": {"1e-06": {"degree": 15, "c": 0, "iters": 4, "t_meas": 0.0176},
+               "3.1e-08": {"degree": 31, "c": 0, "iters": 3, "t_meas": 0.0183}}}
+
+
+def test_route_to_the_lowest_level_with_the_same_setting_and_time():
+    assert serve.route(TIMED, 8, 3.1e-8) == (7, 31, 0, 3)      # same setting, same measured time at 7
+    assert serve.route(TIMED, 8, 1e-6) == (7, 15, 0, 4)        # 17.7 ms within 2 % of 17.6 ms
+    assert serve.route(TIMED, 8, 1e-6, tol=0.0) == (8, 15, 0, 4)
+    assert serve.route(TIMED, 7, 3.1e-8) == (7, 31, 0, 3)      # level 6 has another setting
+    assert serve.route(TIMED, 6, 3.1e-8) == (6, 31, 0, 4)
+    assert serve.route(TABLE, 17, 1e-6) == (17, 7, 0, 3)       # no times: nothing routed
+
+
+def test_routed_requests_share_a_group_at_the_run_level():
+    ctx = FakeCtx()
+    srv = serve.Server(ctx, TIMED, max_batch=64, reserve_bytes=0)
+    a, b = mk(0, 0.0, 2, 8, 3.1e-8), mk(1, 0.0, 3, 7, 3.1e-8)
+    srv.submit(a)
+    srv.submit(b)
+    assert (a.run_level, b.run_level) == (7, 7)
+    assert srv.step(lambda: 1.0) == 5                           # one launch sequence for both
+    assert ctx.calls == [(5, 31, 3)] and ctx.levels == [[7]]
+    assert sorted(d[0] for d in ctx.drops) == [(0, 0), (0, 1)]  # only the level-8 inputs were dropped
+    srv.step(lambda: 2.0)
+    assert a.done and b.done and not srv.busy()
+
+
+def test_one_at_a_time_routes_like_the_server():
+    ctx = FakeCtx()
+    r = mk(0, 0.0, 2, 8, 3.1e-8)
+    serve.run_one_at_a_time(ctx, TIMED, [r])
+    assert r.run_level == 7 and ctx.levels == [[7]] and len(r.outs) == 2
