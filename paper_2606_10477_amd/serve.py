@@ -290,6 +290,33 @@ def run_one_at_a_time(ctx, table, requests, lo=2.0 ** -10, hi=1.0):
     return requests
 
 
+def run_fixed_single(ctx, requests, degree=31, iters=3, lo=2.0 ** -10, hi=1.0):
+    """The plain fixed-configuration single-ciphertext form: every ciphertext
+    of every request in arrival order through CryptoInvSqrt (degree, iters)
+    with lazy bootstrapping, one ciphertext per call, from its own level."""
+    t0 = time.perf_counter()
+    clock = lambda: time.perf_counter() - t0
+    for r in sorted(requests, key=lambda r: r.arrival):
+        r.run_level, r.degree, r.c, r.iters = r.level, degree, 0, iters
+        wait = r.arrival - clock()
+        if wait > 0:
+            time.sleep(wait)
+        r.admitted = clock()
+        r.outs = {k: ctx.invsqrt(c, degree, iters, a=lo, b=hi) for k, c in enumerate(r.cts)}
+        ctx.sync()
+        r.done = clock()
+    return requests
+
+
+def fixed_meets_target(table_rows, level, target, degree=31, iters=3):
+    """Whether the tuning rows' measured MRE of (degree, 0, iters) at `level`
+    meets `target` (None when the rows do not hold that setting)."""
+    for row in table_rows or []:
+        if row.get("ok") and row["level"] == level and row["d"] == degree and row["i"] == iters and row["c"] == 0:
+            return row["m"] <= target
+    return None
+
+
 def summarize(requests):
     lat = np.array([r.done - r.arrival for r in requests])
     n_ct = sum(len(r.cts) for r in requests)
@@ -323,7 +350,8 @@ def main(argv=None):
     rotation and conjugation keys resident): Poisson arrivals at each rate,
     request sizes Geometric(0.25) truncated to [1, 32], levels in [5, 8] and
     MRE targets drawn per request; continuous batching on several lanes
-    versus one request at a time."""
+    versus one request at a time (tuned settings), and versus the plain
+    fixed configuration (31, 3) one ciphertext per call."""
     import argparse
     import json
     import sys
@@ -344,11 +372,11 @@ def main(argv=None):
     ap.add_argument("--out", default=None)
     args = ap.parse_args(argv)
     torch.cuda.set_device(0)
-    table, key_note = DEFAULT_TABLE, "no table: the fixed (31, 0, 3) for every request"
+    table, key_note, rows = DEFAULT_TABLE, "no table: the fixed (31, 0, 3) for every request", None
     if args.table and os.path.exists(args.table):
         with open(args.table) as f:
             rep = json.load(f)
-        table = rep["table"]
+        table, rows = rep["table"], rep.get("rows")
         problem = tuner.check_table_key(rep.get("key"), tuner.table_key("p16b"))
         if problem and problem[0] == "error":
             raise SystemExit(problem[1])
@@ -376,7 +404,7 @@ def main(argv=None):
         res = {}
         # every mode runs twice on the same ciphertexts; the first pass warms
         # the device memory pools and is not reported
-        for mode in ("continuous", "one_at_a_time"):
+        for mode in ("continuous", "one_at_a_time", "fixed_single"):
             for rep in range(2):
                 reqs = [Request(k, float(arr[k]), cts[k], lv[k], tg[k]) for k in range(n)]
                 if mode == "continuous":
@@ -385,14 +413,22 @@ def main(argv=None):
                     s["mean_batch"] = float(np.mean([e["batch"] for e in srv.log]))
                     s["max_groups_in_flight"] = srv.max_in_flight
                     s["working_set_per_ct_mib"] = {str(k): round(v / 2 ** 20, 1) for k, v in sorted(srv.ws.items())}
-                else:
+                elif mode == "one_at_a_time":
                     run_one_at_a_time(ctx, table, reqs)
                     s = summarize(reqs)
+                else:
+                    run_fixed_single(ctx, reqs)
+                    s = summarize(reqs)
+                    meets = [fixed_meets_target(rows, r.level, r.target) for r in reqs]
+                    s["requests_meeting_target"] = (sum(1 for m in meets if m) if all(m is not None for m in meets)
+                                                    else None)
                 del reqs
             res[mode] = s
         del cts
         res["rate_per_s"] = rate
         res["throughput_gain"] = res["continuous"]["ciphertexts_per_s"] / res["one_at_a_time"]["ciphertexts_per_s"]
+        res["gain_vs_fixed_single"] = (res["continuous"]["ciphertexts_per_s"]
+                                       / res["fixed_single"]["ciphertexts_per_s"])
         out["runs"].append(res)
         print(json.dumps(res), flush=True)
     if args.out:

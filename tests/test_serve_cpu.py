@@ -202,3 +202,21 @@ def test_one_at_a_time_routes_like_the_server():
     r = mk(0, 0.0, 2, 8, 3.1e-8)
     serve.run_one_at_a_time(ctx, TIMED, [r])
     assert r.run_level == 7 and ctx.levels == [[7]] and len(r.outs) == 2
+
+
+class FakeSingleCtx(FakeCtx):
+    def invsqrt(self, ct, degree, iters, a=None, b=None):
+        self.calls.append((1, degree, iters))
+        return FakeCt(("y", ct.tag, degree, iters), ct.level)
+
+
+def test_fixed_single_baseline_and_target_check():
+    ctx = FakeSingleCtx()
+    rs = [mk(0, 0.0, 2, 8, 3.1e-8), mk(1, 0.0, 1, 5, 1e-6)]
+    serve.run_fixed_single(ctx, rs)
+    assert ctx.calls == [(1, 31, 3)] * 3 and all(len(r.outs) == len(r.cts) for r in rs)
+    rows = [{"ok": True, "level": 8, "d": 31, "i": 3, "c": 0, "m": 1.1e-8},
+            {"ok": True, "level": 5, "d": 31, "i": 3, "c": 0, "m": 4.9e-3}]
+    assert serve.fixed_meets_target(rows, 8, 3.1e-8) is True
+    assert serve.fixed_meets_target(rows, 5, 1e-6) is False
+    assert serve.fixed_meets_target(rows, 6, 1e-6) is None
