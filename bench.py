@@ -267,6 +267,9 @@ def main():
     cg = copy_gbps(torch)
     roof["copy_GBps"] = round(cg, 1)          # measured practical ceiling (512 MiB device copy)
     roof["frac_of_copy"] = round(achieved / cg, 4) if cg > 0 else None
+    if roof["traffic"] is not None and ms > 0:
+        # measured HBM bytes (counter record) at the same launch times: what the passes really move
+        roof["traffic_GBps"] = round(roof["traffic"] * n / (ms / 1e3) / 1e9, 1)
     # algorithmic bytes per ciphertext of each family (the NTT's 16 N per limb;
     # the key switch's input, key once per batch and output), over the profiled pass
     others = {k: {"calls": v[0], "gpu_ms": round(v[1], 3),
