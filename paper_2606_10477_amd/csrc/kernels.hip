@@ -596,6 +596,22 @@ __device__ __forceinline__ void inv_stage(u64 *v, int u, int lo, int b, int blkg
     }
 }
 
+// The exchange between two phases: in the rows view the threads of one
+// sub-transform are spread over the workgroup's waves (a workgroup barrier);
+// in the blocks view a sub-transform's 256 / R <= 64 threads are one wave or
+// half of one, so its LDS words are written and read by that wave alone and
+// the wave's own order suffices (the wavefront-scope fences keep the
+// compiler from moving the reads above the writes).
+template <bool ROWS> __device__ __forceinline__ void phase_sync() {
+    if (ROWS) {
+        __syncthreads();
+    } else {
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+        __builtin_amdgcn_wave_barrier();
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+    }
+}
+
 // binary64 twins of fwd_stage / inv_stage (bounds as stated with fp_mulmod)
 template <int R, bool ROWS>
 __device__ __forceinline__ void fwd_stage_fp(double *v, int u, int lo, int b, int blkg, const double *W,
@@ -639,7 +655,7 @@ __device__ __forceinline__ void pass_phases_fp(double *v, u64 *tile, int lane, i
     for (int p = 0; p < NPH; ++p) {
         const int lo = FWD ? fwd_lo<R>(p) : inv_lo<R>(p);
         if (p > 0) {
-            __syncthreads();
+            phase_sync<ROWS>();
 #pragma unroll
             for (int m = 0; m < R; ++m) v[m] = fp_bits(tile[lds_at<ROWS, S>(lane, k_of<R>(u, m, lo))]);
         }
@@ -669,7 +685,7 @@ __device__ __forceinline__ void pass_phases(u64 *v, u64 *tile, int lane, int u, 
     for (int p = 0; p < NPH; ++p) {
         const int lo = FWD ? fwd_lo<R>(p) : inv_lo<R>(p);
         if (p > 0) {
-            __syncthreads();   // the previous phase's words are all in LDS
+            phase_sync<ROWS>();   // the previous phase's words are all in LDS
 #pragma unroll
             for (int m = 0; m < R; ++m) v[m] = tile[lds_at<ROWS, S>(lane, k_of<R>(u, m, lo))];
         }
