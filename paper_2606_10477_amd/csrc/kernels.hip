@@ -349,6 +349,15 @@ __device__ __forceinline__ void inv16(u64 v[16], const u64 *W, const u64 *Ws, in
     const uint32_t pidx = y_ - lidx * (uint32_t)(npoly);                      \
     const size_t row_off = ((size_t)pidx * (uint32_t)(nlimb) + lidx) << 16;
 
+// The 16-word blocks passes keep each 256-word block's words among its own 16
+// threads (a quarter wave), so their LDS exchanges need only the wave's own
+// order (fences at wavefront scope), not a workgroup barrier.
+__device__ __forceinline__ void ntt16_block_sync() {
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
 template <bool LIFT>
 __global__ void __launch_bounds__(256) k_ntt16_rows_fwd(u64 *dst, const u64 *src, size_t src_stride, int nlimb,
                                                          int npoly, LimbMap m, Tables T, NttLift lf) {
@@ -408,7 +417,7 @@ __global__ void __launch_bounds__(256) k_ntt16_blocks_fwd(u64 *data, int nlimb, 
     else fwd16<false>(v, W, Ws, 8, blk0 + y, q);
 #pragma unroll
     for (int mm = 0; mm < 16; ++mm) tile[(y * 16 + mm) * kPad + x] = v[mm];   // [block y][row mm][col x]
-    __syncthreads();
+    ntt16_block_sync();
     // phase 2: block y, words 16 x + m; stages 12..15 (distances 8..1)
 #pragma unroll
     for (int mm = 0; mm < 16; ++mm) v[mm] = tile[(y * 16 + x) * kPad + mm];
@@ -423,10 +432,10 @@ __global__ void __launch_bounds__(256) k_ntt16_blocks_fwd(u64 *data, int nlimb, 
 #pragma unroll
         for (int mm = 0; mm < 16; ++mm) v[mm] = reduce_any(v[mm], inv64, q);
     }
-    __syncthreads();
+    ntt16_block_sync();
 #pragma unroll
     for (int mm = 0; mm < 16; ++mm) tile[(y * 16 + x) * kPad + mm] = v[mm];
-    __syncthreads();
+    ntt16_block_sync();
     if (EPI) {
         const size_t off = ((size_t)blockIdx.x << 12);
         const u64 *cc = ep.c + (size_t)pidx * ep.c_stride + ((size_t)lidx << 16) + off;
@@ -461,7 +470,7 @@ __global__ void __launch_bounds__(256) k_ntt16_blocks_inv(u64 *dst, const u64 *s
     u64 v[16];
 #pragma unroll
     for (int mm = 0; mm < 16; ++mm) tile[(y * 16 + mm) * kPad + x] = s_in[(y << 8) + x + 16 * mm];
-    __syncthreads();
+    ntt16_block_sync();
     // phase A: block y, words 16 x + m; half-distances 1..8.  Group index of
     // word J for distance t: J >> (lt + 1), J = 256 (blk0 + y) + 16 x + m
 #pragma unroll
@@ -469,7 +478,7 @@ __global__ void __launch_bounds__(256) k_ntt16_blocks_inv(u64 *dst, const u64 *s
     inv16(v, W, Ws, 16, 0, (blk0 + y) * 16 + x, q);
 #pragma unroll
     for (int mm = 0; mm < 16; ++mm) tile[(y * 16 + x) * kPad + mm] = v[mm];
-    __syncthreads();
+    ntt16_block_sync();
     // phase B: block y, words x + 16 m; half-distances 16..128
 #pragma unroll
     for (int mm = 0; mm < 16; ++mm) v[mm] = tile[(y * 16 + mm) * kPad + x];
