@@ -23,6 +23,9 @@ import time
 
 import numpy as np
 
+# --params choice -> parameter set: the benchmark's bootstrapping set (8 computation levels after
+# bootstrapping, dnum 3), the bootstrapping set with 11 (dnum 6), the plain 27-level set
+SETS = {"bts": "p16b", "bts11": "p16c", "plain": "p16"}
 
 
 def run(levels, degrees, iters, targets, lo, hi, batch, reps, fixed, tuner_seed=777, quiet=False, domain="logu",
@@ -31,13 +34,15 @@ def run(levels, degrees, iters, targets, lo, hi, batch, reps, fixed, tuner_seed=
 
     import torch
     from . import ckks, inputs, tuner
+    from . import params as P
 
     torch.cuda.set_device(0)
     t_start = time.perf_counter()
-    bts = params == "bts"
-    ctx = ckks.Context.from_set("p16b" if bts else "p16")   # plain set: 27 levels, no bootstrapping
+    set_name = SETS[params]
+    bts = "bts" in P.load(set_name)
+    ctx = ckks.Context.from_set(set_name)
     ctx.keygen(tuner_seed, ctx.bts_galois() if bts else [])      # the tuner's own keys, not a client's
-    key = tuner.table_key("p16b" if bts else "p16")
+    key = tuner.table_key(set_name)
     Bpre = 0.0
     if domain == "paper":
         # the paper's own workload (§5.1): linspace over [0.001, 100] encrypted as it is, pre-normalised
@@ -92,9 +97,7 @@ def run(levels, degrees, iters, targets, lo, hi, batch, reps, fixed, tuner_seed=
     err = [abs(r["t_pred"] - r["t"]) / r["t"] for r in ok]
     report = {
         "key": key,
-        "params": ("p16b: N=2^16, log2 QP 1544: q0 60-bit, 11 x 40-bit, 12 x 52-bit, 7 x 60-bit special, dnum 3, "
-                   "h 192; l_BTS 0, l_afterBTS = l_max 8") if bts else
-                  "N=2^16, q0 60-bit + 27 x 40-bit, 7 x 60-bit special, dnum 3, h 192; no bootstrapping",
+        "params": f"{set_name}: " + P.load(set_name)["about"],
         "input": (f"x = linspace({lo}, {hi}, N/2) encrypted at scale 2^50, pre-normalised by B = 100 in the chain "
                   f"(Chebyshev on [{lo / 100}, {hi / 100}]), scaled back by 1/sqrt(B)"
                   if domain == "paper" else f"x log-uniform in [{lo}, {hi}], encrypted at scale 2^50"),
@@ -124,9 +127,10 @@ def main(argv=None):
     ap.add_argument("--domain", choices=["logu", "paper"], default="logu",
                     help="logu: x log-uniform in [2^-10, 1]; paper: linspace(0.001, 100) with B = 100 in the chain")
     ap.add_argument("--fixed", default="31,3", help="fixed (degree, iterations) the tuned choice is compared with")
-    ap.add_argument("--params", choices=["bts", "plain"], default="bts",
-                    help="bts: the bootstrapping set (levels 3-8); plain: 27 levels, no bootstrapping "
-                         "(use e.g. --levels 13,17,21,27)")
+    ap.add_argument("--params", choices=sorted(SETS), default="bts",
+                    help="bts: the bootstrapping set (levels 3-8); bts11: the bootstrapping set with 11 "
+                         "computation levels (use e.g. --levels 3,5,7,9,11); plain: 27 levels, no "
+                         "bootstrapping (use e.g. --levels 13,17,21,27)")
     args = ap.parse_args(argv)
     ints = lambda s: [int(v) for v in s.split(",")]
     lo, hi = (0.001, 100.0) if args.domain == "paper" else (2.0 ** -10, 1.0)

@@ -3,9 +3,11 @@ calls that runs on either side (the oracle's Context or the GPU library's):
 both expose the same operations under the same names.  The recipe holds no
 arithmetic; it only names the calls and their order.
 
-Workload (the benchmark's): the N = 2^16 bootstrapping set "p16b", keys from
-seed 9 with the bootstrapping rotations, x = log-uniform in [2^-10, 1] from
-input seed 1, encrypted at the top level 8 with scale 2^50 and seed 3.
+Workload (the benchmark's): an N = 2^16 bootstrapping set ("p16b", the
+benchmark's, or "p16c", 11 computation levels), keys from seed 9 with the
+bootstrapping rotations, x = log-uniform in [2^-10, 1] from input seed 1,
+encrypted at the set's top computation level (l_afterBTS: 8 or 11) with scale
+2^50 and seed 3.
 Steps (paper §2.1 bootstrapping, Alg. 1):
   enc      the input ciphertext
   cheb     the Chebyshev initial value y0 (degree 31; invsqrt with 0 steps)
@@ -25,7 +27,7 @@ import numpy as np
 
 LO, HI = 2.0 ** -10, 1.0
 KEY_SEED, INPUT_SEED, ENC_SEED = 9, 1, 3
-LEVEL, IN_SCALE = 8, 2.0 ** 50
+IN_SCALE = 2.0 ** 50
 DEGREE, ITERS, BTS_BOUND = 31, 3, 512
 STEPS = ("enc", "cheb", "raise", "cts", "conj", "re", "im", "evm_re", "evm_im", "stc", "bts", "invsqrt")
 N_SAMPLES = 48
@@ -56,7 +58,7 @@ def run(ctx, x, only=None, on_step=None):
             if on_step:
                 on_step(name, out[name])
 
-    enc = ctx.encrypt(x, LEVEL, IN_SCALE, ENC_SEED)
+    enc = ctx.encrypt(x, ctx.l_after, IN_SCALE, ENC_SEED)
     rec("enc", enc)
     if want & {"cheb", "raise", "cts", "conj", "re", "im", "evm_re", "evm_im", "stc", "bts"}:
         y0 = ctx.invsqrt(enc, DEGREE, 0, LO, HI)

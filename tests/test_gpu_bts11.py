@@ -1,0 +1,76 @@
+"""The bootstrapping set with 11 computation levels after bootstrapping
+("p16c"; paper §2.1 quotes l_afterBTS of 11 to 12 at log2 QP ~ 1555): the
+same bootstrap as the benchmark's set (3 CoeffToSlot and 9 EvalMod levels on
+52-bit primes, 3 SlotToCoeff levels on 40-bit primes) under 11 computation
+levels, paid for by a smaller special modulus: digits of 5 primes (dnum 6),
+5 special 60-bit primes, log2 QP ~ 1544.  Through the C-ABI at N = 2^16:
+the chain's primes equal the oracle's, the bootstrap ends on level 11 with
+the benchmark set's accuracy, and CryptoInvSqrt meets the MRE target from the
+top level.  Word-for-word parity of every bootstrap step on this set is in
+test_gpu_fullsize_parity.py.
+"""
+import numpy as np
+import pytest
+
+from paper_2606_10477_amd import inputs
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def full11():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_2606_10477_amd import ckks
+    g = ckks.Context.from_set("p16c")
+    g.keygen(11, g.bts_galois())
+    yield g
+    g.close()
+
+
+def test_chain_primes_and_budget(full11, oracle_mod):
+    g = full11
+    o = oracle_mod.Context.from_set("p16c", bootstrapping=False)
+    assert np.array_equal(g.primes, o.primes) and np.array_equal(g.ladder, o.ladder)
+    bits = [int(p).bit_length() for p in g.primes]
+    assert g.l_after == 11 and g.L == 26 and len(bits) == 32
+    assert bits[0] == 60 and all(40 <= b <= 41 for b in bits[1:15])
+    assert all(52 <= b <= 53 for b in bits[15:27]) and all(b == 60 for b in bits[27:])
+    logp = [np.log2(float(p)) for p in g.primes]
+    digits = [sum(logp[i:i + 5]) for i in range(0, 27, 5)]
+    assert len(digits) == 6 and max(digits) < sum(logp[27:])   # P exceeds every digit
+    assert 1540 < sum(logp) < 1560
+
+
+def test_bootstrap_accuracy(full11):
+    """Same bootstrap as the benchmark's set, so the same accuracy: mean
+    relative error about 2.9e-4 on 1/sqrt(x) values with message bound 512."""
+    g = full11
+    x = inputs.log_uniform(g.n, 2.0 ** -10, 1.0, 9)
+    y = 1 / np.sqrt(x)
+    c = g.encrypt(y, 0, g.ladder[0], 74)
+    b = g.bootstrap(c, 512)
+    rel = np.abs(g.decrypt(b).real - y) / y
+    print(f"N=2^16 11-level set, BTS bound 512: level {b.level}, mean rel err {np.mean(rel):.3g}, "
+          f"max {np.max(rel):.3g}", flush=True)
+    assert b.level == 11 and np.mean(rel) < 4e-4
+
+
+@pytest.mark.parametrize("degree,iters,max_bts", [(31, 3, 1), (63, 2, 1)])
+def test_invsqrt_from_the_top_level(full11, degree, iters, max_bts):
+    g = full11
+    lo, hi = 2.0 ** -10, 1.0
+    x = inputs.log_uniform(g.n, lo, hi, 10)
+    c = g.encrypt(x, 11, 2.0 ** 50, 75)
+    g.trace(True)
+    y = g.invsqrt(c, degree, iters, lo, hi)
+    tr = g.trace_read()
+    g.trace(False)
+    ref = 1 / np.sqrt(x)
+    mre = np.mean(np.abs(g.decrypt(y).real - ref) / ref)
+    n_bts = sum(1 for op in tr if op[0] == "bootstrap")
+    print(f"N=2^16 11-level set ({degree},{iters}) from level 11: {n_bts} bootstrap(s), output level {y.level}, "
+          f"MRE {mre:.3g}", flush=True)
+    assert n_bts <= max_bts
+    assert mre <= 3.1e-8

@@ -1,11 +1,12 @@
 """Word-for-word parity of the benchmarked workload at full size (N = 2^16,
-the bootstrapping set "p16b"; paper §2.1 bootstrapping and Alg. 1), through
-the C-ABI, against digests the oracle wrote (tests/golden/
-fullsize_chain_p16b.json, by make_fullsize_golden.py, which calls only the
-oracle): after the encryption, the Chebyshev step, ModRaise, CoeffToSlot,
-the conjugation and the real/imaginary split, both EvalMods, SlotToCoeff,
-the whole bootstrap and the whole CryptoInvSqrt (31, 3) chain, the GPU's
-level, scale and SHA-256 of all words must equal the oracle's.  The GPU runs
+the benchmark's bootstrapping set "p16b" and the set with 11 computation
+levels "p16c"; paper §2.1 bootstrapping and Alg. 1), through the C-ABI,
+against digests the oracle wrote (tests/golden/fullsize_chain_<set>.json, by
+make_fullsize_golden.py, which calls only the oracle): after the
+encryption, the Chebyshev step, ModRaise, CoeffToSlot, the conjugation and
+the real/imaginary split, both EvalMods, SlotToCoeff, the whole bootstrap and
+the whole CryptoInvSqrt (31, 3) chain, the GPU's level, scale and SHA-256 of
+all words must equal the oracle's.  The GPU runs
 in the benchmark's launch configuration (one ciphertext, the library's
 default schedules).
 """
@@ -23,32 +24,32 @@ import fullsize_chain as F  # noqa: E402
 from paper_2606_10477_amd import inputs  # noqa: E402
 
 pytestmark = pytest.mark.gpu
-GOLDEN = os.path.join(HERE, "golden", "fullsize_chain_p16b.json")
 
 
-def test_fullsize_chain_words_equal_the_oracle():
+@pytest.mark.parametrize("name", ["p16b", "p16c"])
+def test_fullsize_chain_words_equal_the_oracle(name):
     import torch
     if not torch.cuda.is_available():
         pytest.skip("no GPU")
     from paper_2606_10477_amd import ckks
-    with open(GOLDEN) as f:
+    with open(os.path.join(HERE, "golden", f"fullsize_chain_{name}.json")) as f:
         want = json.load(f)["steps"]
-    g = ckks.Context.from_set("p16b")
+    g = ckks.Context.from_set(name)
     try:
         g.keygen(F.KEY_SEED, g.bts_galois())
         x = inputs.log_uniform(g.n, F.LO, F.HI, F.INPUT_SEED)
         bad = []
 
-        def check(name, d):
-            w = want[name]
+        def check(step, d):
+            w = want[step]
             ok = (d["level"], d["scale"], d["sha256"]) == (w["level"], w["scale"], w["sha256"])
             diff = [s for s, t in zip(d["samples"], w["samples"]) if s != t]
-            print(f"{name}: level {d['level']} {'equal' if ok else 'DIFFERENT'}"
+            print(f"{step}: level {d['level']} {'equal' if ok else 'DIFFERENT'}"
                   + ("" if ok else f" (level {w['level']}, scale {w['scale']} vs {d['scale']}, "
                                    f"{len(diff)} of {len(d['samples'])} sampled words differ, e.g. {diff[:3]})"),
                   flush=True)
             if not ok:
-                bad.append(name)
+                bad.append(step)
 
         got = F.run(g, x, on_step=check)
         assert set(got) == set(want)
