@@ -11,7 +11,10 @@ measured live with HIP events on the library's stream, the MRE of the result
 against FP64, the same chain batched (ciphertexts/s at --extra-batch), the
 CPU oracle timed on a bounded sample (one ciphertext on one core, then one
 ciphertext per process on all cores after the GPU work), and whether the
-GPU's result words equal the oracle's.
+GPU's result words equal the oracle's.  Beside it ("tuned_11_levels"): the
+tuned form on the bootstrapping set with 11 computation levels ("p16c", dnum
+6), the (degree, c, iterations) its committed tuning table picks for
+3.1e-8 at the top level, one ciphertext per step and batched, with its MRE.
 """
 import argparse
 import hashlib
@@ -46,6 +49,8 @@ def parse():
                     help="replays of the one-ciphertext chain captured as a HIP graph, against as many eager runs "
                          "(0: skip)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-tuned-11", dest="tuned_11", action="store_false",
+                    help="skip the tuned form on the 11-level set")
     ap.add_argument("--cpu-limit", type=int, default=480,
                     help="seconds after the start the CPU baseline may run until")
     ap.add_argument("--cpu-procs", type=int, default=0,
@@ -138,6 +143,82 @@ def ntt_traffic(alg_bytes_per_launch):
     if rec.get("kernels_hip_sha256") != traffic_record.kernels_sha256():
         return None
     return round(rec["ratio_to_algorithmic"] * alg_bytes_per_launch)
+
+
+def tuned_11_levels(args, ckks, inputs):
+    """The tuned configuration on the 11-level set, timed like the fixed one
+    (inputs resident, `steps` steps after a warm-up; then --extra-batch per
+    step).  None when the tuning table is absent."""
+    path = os.path.join(ROOT, "paper_2606_10477_amd", "tuning_mi355x_bts11.json")
+    if not os.path.exists(path):
+        return None
+    with open(path) as f:
+        rep = json.load(f)
+    top = max(int(l) for l in rep["table"])
+    pick = rep["table"][str(top)].get("3.1e-08")
+    if pick is None:
+        return None
+    d, c, it = pick["degree"], pick["c"], pick["iters"]
+    ctx = ckks.Context.from_set("p16c")
+    try:
+        ctx.keygen(9, ctx.bts_galois() if (pick["bts"] or c) else [])
+        nmax = max(1, args.extra_batch)
+        xs = [inputs.log_uniform(ctx.n, LO, HI, 1 + i) for i in range(nmax)]
+        cts = ctx.encrypt_batch(np.stack(xs), top, 2.0 ** 50, 3)
+
+        def step(B):
+            if B == 1:
+                return [ctx.invsqrt(cts[0], d, it, a=LO, b=HI, pre_bts=bool(c))]
+            return ctx.invsqrt_batch(cts[:B], d, it, a=LO, b=HI, pre_bts=bool(c))
+
+        for _ in range(max(1, args.warmup)):
+            step(1)
+        ctx.sync()
+        ctx.trace(True)
+        out = step(1)
+        n_bts = sum(1 for op in ctx.trace_read() if op[0] == "bootstrap")
+        ctx.trace(False)
+        ctx.sync()
+        t0 = time.perf_counter()
+        for _ in range(args.steps):
+            out = step(1)
+        ctx.sync()
+        dt = time.perf_counter() - t0
+        ref = 1 / np.sqrt(xs[0])
+        mre = float(np.mean(np.abs(ctx.decrypt(out[0]).real - ref) / ref))
+        lat = []
+        for _ in range(args.latency_runs):
+            t1 = time.perf_counter()
+            o1 = step(1)
+            ctx.sync()
+            lat.append(1e3 * (time.perf_counter() - t1))
+            del o1
+        res = {"params": "p16c: " + ckks_params_about("p16c"), "input_level": top,
+               "degree": d, "c": c, "iters": it, "bootstraps_per_ct": n_bts, "mre": mre,
+               "ciphertexts_per_s": round(args.steps / dt, 3), "ms_per_step": round(dt * 1e3 / args.steps, 3),
+               "latency": {"runs": len(lat), "p50_ms": round(float(np.percentile(lat, 50)), 3),
+                           "p99_ms": round(float(np.percentile(lat, 99)), 3)} if lat else None,
+               "table": os.path.basename(path)}
+        if args.extra_batch > 1:
+            step(args.extra_batch)
+            ctx.sync()
+            t1 = time.perf_counter()
+            for _ in range(args.steps):
+                ob = step(args.extra_batch)
+                del ob
+            ctx.sync()
+            dtb = time.perf_counter() - t1
+            res["batched"] = {"batch": args.extra_batch,
+                              "ciphertexts_per_s": round(args.extra_batch * args.steps / dtb, 3),
+                              "ms_per_step": round(dtb * 1e3 / args.steps, 3)}
+        return res
+    finally:
+        ctx.close()
+
+
+def ckks_params_about(name):
+    from paper_2606_10477_amd import params
+    return params.load(name)["about"]
 
 
 def main():
@@ -306,6 +387,12 @@ def main():
         "kernel_families": others,
     }
     ctx.close()
+    if args.tuned_11:
+        res["tuned_11_levels"] = tuned_11_levels(args, ckks, inputs)
+        if res["tuned_11_levels"]:
+            t = res["tuned_11_levels"]
+            t["speedup_vs_fixed_c1"] = round(t["ciphertexts_per_s"] / res["value"], 3)
+        print("tuned 11-level form done", file=sys.stderr, flush=True)
     if cpu_proc is not None:
         print("waiting for the CPU baseline (oracle, one ciphertext)", file=sys.stderr, flush=True)
         left = max(10.0, args.cpu_limit - (time.perf_counter() - t_start))

@@ -13,6 +13,7 @@
 #include <cstring>
 #include <functional>
 #include <map>
+#include <tuple>
 #include <memory>
 #include <mutex>
 #include <set>
@@ -279,6 +280,10 @@ struct ckks_ctx {
     std::map<std::string, ProfFamily> prof;
     std::vector<hipEvent_t> ev_free;
     int sum_terms = 0;            // products a 128-bit accumulator may add: T (q_max - 1)^2 < 2^127
+    // Chebyshev coefficients of 1/sqrt by (degree, interval): the quad-precision
+    // interpolation takes O(d^2) cosines (about 1 ms of host time at degree 31,
+    // 17 ms at 127), which would otherwise precede every chain's first launch
+    std::map<std::tuple<int, double, double>, std::vector<double>> cheb_cf;
     int device = 0;               // the GPU the context was created on
     u64 *scratch = nullptr;       // that GPU's scratch array (entry point that allocates nothing)
     u64 words(int level) const { return (u64)2 * (level + 1) * N; }
@@ -1893,6 +1898,21 @@ std::vector<int> bts_rotations(const ckks_ctx *c) {
     return out;
 }
 
+// The context's Chebyshev coefficients of 1/sqrt on [a, b] at degree d (the
+// interpolation of the host's own quad-precision routine, computed on the
+// first request and kept; at most 64 intervals are kept, then the cache starts
+// over).
+static std::vector<double> cheb_coeffs_invsqrt(ckks_ctx *c, int d, double a, double b) {
+    const auto key = std::make_tuple(d, a, b);
+    auto it = c->cheb_cf.find(key);
+    if (it != c->cheb_cf.end()) return it->second;
+    std::vector<double> cf(d + 1);
+    hm::cheb_invsqrt(d, a, b, cf.data());
+    if (c->cheb_cf.size() >= 64) c->cheb_cf.clear();
+    c->cheb_cf.emplace(key, cf);
+    return cf;
+}
+
 // CryptoInvSqrt with the bootstrapping policy: Pre-BTS of x (paper's c = 1)
 // when asked for (opts.pre_bts) or when x cannot carry the Chebyshev step or
 // ct_x; otherwise x is never bootstrapped.  Lazy bootstrapping of y before a Newton step that lacks 2
@@ -1925,8 +1945,7 @@ Ct op_invsqrt(ckks_ctx *c, const ckks_ct *x0, int degree, int iters, const ckks_
             x = xb.get();
         }
     }
-    std::vector<double> cf(degree + 1);
-    hm::cheb_invsqrt(degree, an, bn, cf.data());
+    std::vector<double> cf = cheb_coeffs_invsqrt(c, degree, an, bn);
     if (iters == 0)
         for (double &v : cf) v *= kappa;   // no Newton step to carry the scale-back
     Ct cx = op_mul_const_down(c, x, 0.5 * sx / Bn);

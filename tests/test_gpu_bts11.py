@@ -57,8 +57,13 @@ def test_bootstrap_accuracy(full11):
     assert b.level == 11 and np.mean(rel) < 4e-4
 
 
-@pytest.mark.parametrize("degree,iters,max_bts", [(31, 3, 1), (63, 2, 1)])
-def test_invsqrt_from_the_top_level(full11, degree, iters, max_bts):
+@pytest.mark.parametrize("degree,iters,target", [(31, 3, 1e-6), (31, 4, 3.1e-8)])
+def test_invsqrt_from_the_top_level(full11, degree, iters, target):
+    """From level 11 the degree-31 start y0 sits at 5; Newton steps at 5 and
+    3 bring it to 1, where the lazy policy bootstraps it to 11.  With 3 steps
+    only the last one follows the bootstrap and its error (~3e-4 relative)
+    is squared once: MRE ~ 4e-7.  A fourth step squares it again and meets
+    3.1e-8, still with one bootstrap."""
     g = full11
     lo, hi = 2.0 ** -10, 1.0
     x = inputs.log_uniform(g.n, lo, hi, 10)
@@ -72,5 +77,5 @@ def test_invsqrt_from_the_top_level(full11, degree, iters, max_bts):
     n_bts = sum(1 for op in tr if op[0] == "bootstrap")
     print(f"N=2^16 11-level set ({degree},{iters}) from level 11: {n_bts} bootstrap(s), output level {y.level}, "
           f"MRE {mre:.3g}", flush=True)
-    assert n_bts <= max_bts
-    assert mre <= 3.1e-8
+    assert n_bts == 1
+    assert mre <= target
