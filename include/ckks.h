@@ -425,6 +425,26 @@ ckks_status ckks_ntt_schedule(ckks_ctx *ctx, int32_t r4_max_limbs, int32_t r8_ma
 ckks_status ckks_ntt_arith(ckks_ctx *ctx, int32_t fp64_max_bits);
 
 /*
+ * Measurement aid for the choice of word size (not a step of the method): the
+ * rate of forward NTT butterflies (U + w V, U - w V with the lazy reductions
+ * of the transforms) held in registers, with no memory traffic, in one of
+ * three word forms:
+ *   form 0: 64-bit words, odd q < 2^61 (the transforms' integer path);
+ *   form 1: binary64 residues, odd q < 2^42 (their binary64 path);
+ *   form 2: 32-bit words, odd q < 2^30 (a 30-bit-prime design; no
+ *           operation of this library uses it).
+ * 2048 x 256 threads each apply `rounds` rounds (1..2^20) of an 8-point
+ * transform held in registers (3 stages of 4 butterflies);
+ * `launches` launches (1..1000) after one warm-up launch are timed with HIP
+ * events on the context's stream.  *butterflies_per_s receives the rate.
+ * Uses a 4 MiB buffer from the context's pool; synchronises the stream.
+ * Bad arguments (q out of its form's range, even, or counts out of range)
+ * give CKKS_E_PARAM.
+ */
+ckks_status ckks_butterfly_rate(ckks_ctx *ctx, int32_t form, uint64_t q, uint32_t rounds, uint32_t launches,
+                                double *butterflies_per_s);
+
+/*
  * Opt-in timing of kernel families on the context's stream (HIP events
  * recorded around each call; enabling clears previous records).  Families:
  *   "ntt"       every forward/inverse NTT call of the hot path; algorithmic

@@ -96,6 +96,7 @@ SIGNATURES = {
     "ckks_ntt_device": (C.c_int, [vp, C.c_void_p, C.c_uint32, u32p, C.c_int]),
     "ckks_ntt_schedule": (C.c_int, [vp, C.c_int32, C.c_int32, C.c_int32]),
     "ckks_ntt_arith": (C.c_int, [vp, C.c_int32]),
+    "ckks_butterfly_rate": (C.c_int, [vp, C.c_int32, C.c_uint64, C.c_uint32, C.c_uint32, dblp]),
     "ckks_invsqrt_graph_create": (C.c_int, [vp, vp, C.c_uint32, C.c_uint32, C.POINTER(InvsqrtOpts),
                                             C.POINTER(vp)]),
     "ckks_invsqrt_graph_run": (C.c_int, [vp, vp, vp, C.POINTER(vp)]),
@@ -469,6 +470,14 @@ class Context:
     def ntt_arith(self, fp64_max_bits):
         """Primes below 2^fp64_max_bits transform in binary64 (0: none, -1: default)."""
         self._chk(lib().ckks_ntt_arith(self.ptr, int(fp64_max_bits)))
+
+    def butterfly_rate(self, form, q, rounds=128, launches=20):
+        """Forward NTT butterflies per second in registers (a word-size
+        measurement): form 0 = 64-bit words (q < 2^61), 1 = binary64
+        (q < 2^42), 2 = 32-bit words (q < 2^30)."""
+        r = C.c_double()
+        self._chk(lib().ckks_butterfly_rate(self.ptr, int(form), int(q), int(rounds), int(launches), C.byref(r)))
+        return r.value
 
     def ntt_device(self, ptr, n_limbs, prime_idx, inverse=False):
         pi = np.ascontiguousarray(prime_idx, dtype=np.uint32)

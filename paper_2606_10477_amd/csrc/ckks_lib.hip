@@ -2786,6 +2786,41 @@ ckks_status ckks_ntt_arith(ckks_ctx *c, int32_t fp64_max_bits) {
     });
 }
 
+ckks_status ckks_butterfly_rate(ckks_ctx *c, int32_t form, uint64_t q, uint32_t rounds, uint32_t launches,
+                                double *butterflies_per_s) {
+    if (!c || !butterflies_per_s || form < 0 || form > 2 || rounds < 1 || rounds > (1u << 20) || launches < 1 ||
+        launches > 1000 || !(q & 1) || q < 3)
+        return CKKS_E_PARAM;
+    const uint64_t qmax = form == 0 ? (1ull << 61) : form == 1 ? (1ull << 42) : (1ull << 30);
+    if (q >= qmax) return CKKS_E_PARAM;
+    return guard(c, [&] {
+        const size_t threads = (size_t)2048 * 256;   // 8 workgroups of 256 per compute unit
+        const u64 w = (q / 3) | 1;                   // any residue: the rate does not depend on it
+        const u64 wsh = form == 2 ? (u64)(((unsigned __int128)w << 32) / q)
+                                  : (u64)(((unsigned __int128)w << 64) / q);
+        const u64 inv64 = (u64)((((unsigned __int128)1) << 64) / q);
+        const double wd = (double)w, wq = (double)w / (double)q, qinv = 1.0 / (double)q;
+        Buf io(c->pool.get(), threads);
+        std::vector<u64> h(threads);
+        for (size_t i = 0; i < threads; ++i) h[i] = (i * 0x9e3779b97f4a7c15ull) >> 3;
+        hipchk(hipMemcpyAsync(io.p, h.data(), threads * 8, hipMemcpyHostToDevice, c->stream), "copy");
+        gpu::butterfly_rate(form, io.p, threads, (int)rounds, q, w, wsh, inv64, wd, wq, qinv, c->stream);   // warm-up
+        hipEvent_t e0, e1;
+        hipchk(hipEventCreate(&e0), "event");
+        hipchk(hipEventCreate(&e1), "event");
+        hipchk(hipEventRecord(e0, c->stream), "event");
+        for (uint32_t k = 0; k < launches; ++k)
+            gpu::butterfly_rate(form, io.p, threads, (int)rounds, q, w, wsh, inv64, wd, wq, qinv, c->stream);
+        hipchk(hipEventRecord(e1, c->stream), "event");
+        hipchk(hipEventSynchronize(e1), "sync");
+        float ms = 0.f;
+        hipchk(hipEventElapsedTime(&ms, e0, e1), "event");
+        (void)hipEventDestroy(e0);
+        (void)hipEventDestroy(e1);
+        *butterflies_per_s = (double)threads * rounds * 12.0 * launches / (ms * 1e-3);
+    });
+}
+
 ckks_status ckks_profile_enable(ckks_ctx *c, int on) {
     if (!c) return CKKS_E_PARAM;
     return guard(c, [&] {

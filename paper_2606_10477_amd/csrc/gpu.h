@@ -291,5 +291,9 @@ void lincomb_multi(const Tables &T, uint64_t *out, const CombMultiArgs &a, int n
 // decryption: m = c0 + c1 * s
 void decrypt_combine(const Tables &T, uint64_t *m, const uint64_t *c0, const uint64_t *c1, const uint64_t *sk,
                      int nlimb, const LimbMap &m_, hipStream_t s);
+// butterfly-rate probe: `threads` (a multiple of 256) threads, `rounds` rounds
+// of 12 forward butterflies each; form 0 = 64-bit words, 1 = binary64, 2 = 32-bit
+void butterfly_rate(int form, uint64_t *io, size_t threads, int rounds, uint64_t q, uint64_t w, uint64_t wsh,
+                    uint64_t inv64, double wd, double wq, double qinv, hipStream_t s);
 
 }  // namespace gpu

@@ -2118,4 +2118,113 @@ void decrypt_combine(const Tables &T, uint64_t *mo, const uint64_t *c0, const ui
     hipLaunchKernelGGL(k_decrypt, grid_for(total), dim3(256), 0, s, mo, c0, c1, sk, T.logN, total, m_, T);
 }
 
+// ---------------------------------------------------------------------------
+// Butterfly-rate probe (a measurement aid for the choice of word size, not a
+// step of the method).  Each thread holds 8 residues and applies `rounds`
+// rounds of an 8-point forward transform (3 stages of 4 Cooley-Tukey
+// butterflies U + w V, U - w V, distances 4, 2, 1) in registers, with no
+// memory traffic in between, in one of three word forms, each lazily reduced
+// as the transforms reduce it:
+//   form 0: 64-bit words, q < 2^61: Shoup product from 32-bit multiplies,
+//           U brought into [0, 4q) first when q >= 2^57, otherwise every
+//           value reduced once per 5 rounds (15 stages; a 16-stage transform
+//           reduces once) (the integer path);
+//   form 1: binary64 residues, q < 2^42: the error-free product with a
+//           rounded quotient, re-centred every 2 rounds (6 stages; a pass
+//           of 8 stages is re-centred once) (the binary64 path);
+//   form 2: 32-bit words, q < 2^30: Shoup product with a 32-bit quotient,
+//           U brought into [0, 2q) first (no transform here uses it).
+// ---------------------------------------------------------------------------
+template <int FORM, int H, class T, class F>
+__device__ __forceinline__ void probe_stage(T *v, F bfly) {
+#pragma unroll
+    for (int m = 0; m < 8; ++m)
+        if (!(m & H)) bfly(v[m], v[m + H]);
+}
+template <int FORM>
+__global__ void __launch_bounds__(256) k_butterfly_rate(u64 *io, int rounds, u64 q, u64 w, u64 wsh, u64 inv64,
+                                                       double wd, double wq, double qinv) {
+    const size_t t = (size_t)blockIdx.x * 256 + threadIdx.x;
+    if (FORM == 0) {
+        u64 v[8];
+#pragma unroll
+        for (int m = 0; m < 8; ++m) v[m] = (io[t] + 977 * m) % q;
+        const u64 q4 = 4 * q;
+        const bool small = q < kSmallPrime;
+        auto bf = [&](u64 &a, u64 &b) {
+            const u64 U = small ? a : (a >= q4 ? a - q4 : a);
+            const u64 V = mul_shoup_lazy4(b, w, wsh, q);
+            a = U + V;
+            b = U - V + q4;
+        };
+        for (int r = 0; r < rounds; ++r) {
+            probe_stage<0, 4>(v, bf);
+            probe_stage<0, 2>(v, bf);
+            probe_stage<0, 1>(v, bf);
+            if (small && r % 5 == 4) {
+#pragma unroll
+                for (int m = 0; m < 8; ++m) v[m] = reduce_any(v[m], inv64, q);
+            }
+        }
+        u64 acc = 0;
+#pragma unroll
+        for (int m = 0; m < 8; ++m) acc ^= v[m];
+        io[t] = acc;
+    } else if (FORM == 1) {
+        double v[8];
+        const double qd = (double)q;
+#pragma unroll
+        for (int m = 0; m < 8; ++m) v[m] = (double)((io[t] + 977 * m) % q);
+        auto bf = [&](double &a, double &b) {
+            const double U = a;
+            const double rr = fp_mulmod(b, wd, wq, qd);
+            a = U + rr;
+            b = U - rr;
+        };
+        for (int r = 0; r < rounds; ++r) {
+            probe_stage<1, 4>(v, bf);
+            probe_stage<1, 2>(v, bf);
+            probe_stage<1, 1>(v, bf);
+            if (r & 1) {
+#pragma unroll
+                for (int m = 0; m < 8; ++m) v[m] = fp_centre(v[m], qd, qinv);
+            }
+        }
+        u64 acc = 0;
+#pragma unroll
+        for (int m = 0; m < 8; ++m) acc ^= fp_canon(v[m], qd, qinv);
+        io[t] = acc;
+    } else {
+        uint32_t v[8];
+        const uint32_t q32 = (uint32_t)q, w32 = (uint32_t)w, ws32 = (uint32_t)wsh, q2 = 2 * q32;
+#pragma unroll
+        for (int m = 0; m < 8; ++m) v[m] = (uint32_t)((io[t] + 977 * m) % q);
+        auto bf = [&](uint32_t &a, uint32_t &b) {
+            const uint32_t U = a >= q2 ? a - q2 : a;
+            const uint32_t V = b * w32 - __umulhi(b, ws32) * q32;   // [0, 2q)
+            a = U + V;
+            b = U - V + q2;
+        };
+        for (int r = 0; r < rounds; ++r) {
+            probe_stage<2, 4>(v, bf);
+            probe_stage<2, 2>(v, bf);
+            probe_stage<2, 1>(v, bf);
+        }
+        u64 acc = 0;
+#pragma unroll
+        for (int m = 0; m < 8; ++m) acc ^= v[m];
+        io[t] = acc;
+    }
+}
+void butterfly_rate(int form, u64 *io, size_t threads, int rounds, u64 q, u64 w, u64 wsh, u64 inv64, double wd,
+                    double wq, double qinv, hipStream_t s) {
+    const dim3 grid((unsigned)(threads / 256));
+    if (form == 0)
+        hipLaunchKernelGGL(k_butterfly_rate<0>, grid, dim3(256), 0, s, io, rounds, q, w, wsh, inv64, wd, wq, qinv);
+    else if (form == 1)
+        hipLaunchKernelGGL(k_butterfly_rate<1>, grid, dim3(256), 0, s, io, rounds, q, w, wsh, inv64, wd, wq, qinv);
+    else
+        hipLaunchKernelGGL(k_butterfly_rate<2>, grid, dim3(256), 0, s, io, rounds, q, w, wsh, inv64, wd, wq, qinv);
+}
+
 }  // namespace gpu

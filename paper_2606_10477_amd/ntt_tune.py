@@ -17,9 +17,26 @@ size under the library's schedule, untimed, for a counter profiler to
 attribute per dispatch (each dispatch's grid gives its limb count):
 
     python -m paper_2606_10477_amd.ntt_tune --limbs 1,8,43,96 --calls 20
+
+With --word-size it measures the butterfly rate of each word form in
+registers (ckks_butterfly_rate): 64-bit words on the chain's 60- and 52-bit
+primes, binary64 on its 40-bit primes, and 32-bit words on a 30-bit prime
+= 1 mod 2N (the alternative design), and states each form's modulus bits
+transformed per second and per byte of HBM traffic:
+
+    python -m paper_2606_10477_amd.ntt_tune --word-size [--json PATH]
+
+From a counter run of the same command (rocprofv3 --pmc ... -o run, the SQ
+instruction counters), VALU wave instructions per butterfly of each form and
+the rate they allow at the VALU peak (256 CUs x 2.4 GHz, one wave
+instruction per CU per cycle):
+
+    python -m paper_2606_10477_amd.ntt_tune --word-size-counters PMC_DIR --json WORD_SIZE.json
 """
 import argparse
+import csv
 import json
+import os
 import time
 
 SIZES = (1, 2, 3, 4, 6, 8, 10, 12, 16, 20, 24, 28, 32, 40, 48, 64, 96)
@@ -133,6 +150,90 @@ def chain_times(schedules, reps=3, runs=10):
     return out
 
 
+def _is_prime(n):
+    """Deterministic Miller-Rabin for n < 3.3e24 (the first 12 prime bases)."""
+    if n < 2:
+        return False
+    small = (2, 3, 5, 7, 11, 13, 17, 19, 23, 29, 31, 37)
+    for p in small:
+        if n % p == 0:
+            return n == p
+    d, r = n - 1, 0
+    while d % 2 == 0:
+        d, r = d // 2, r + 1
+    for a in small:
+        x = pow(a, d, n)
+        if x in (1, n - 1):
+            continue
+        for _ in range(r - 1):
+            x = x * x % n
+            if x == n - 1:
+                break
+        else:
+            return False
+    return True
+
+
+def prime_below(bits, two_n):
+    """The largest prime q < 2^bits with q = 1 mod two_n."""
+    q = ((1 << bits) - 1) // two_n * two_n + 1
+    while q >= (1 << bits) or not _is_prime(q):
+        q -= two_n
+    return q
+
+
+WS_THREADS, WS_ROUNDS, WS_LAUNCHES = 2048 * 256, 128, 20
+VALU_WAVE_INSTR_PER_S = 256 * 2.4e9
+
+
+def word_size_counters(pmc_dir, cases, rounds=WS_ROUNDS, launches=WS_LAUNCHES, threads=WS_THREADS):
+    """Per case of word_size(): counters per butterfly, averaged over the timed
+    dispatches (each case issues one warm-up and `launches` timed dispatches,
+    in case order)."""
+    by = {}
+    with open(os.path.join(pmc_dir, "run_counter_collection.csv")) as f:
+        for r in csv.DictReader(f):
+            if "k_butterfly_rate" not in r["Kernel_Name"]:
+                continue
+            c = by.setdefault(int(r["Dispatch_Id"]), {})
+            c[r["Counter_Name"]] = c.get(r["Counter_Name"], 0.0) + float(r["Counter_Value"])
+    ids = sorted(by)
+    if len(ids) != len(cases) * (launches + 1):
+        raise SystemExit(f"expected {len(cases) * (launches + 1)} probe dispatches, found {len(ids)}")
+    per = threads * rounds * 12       # butterflies per dispatch: 3 stages of 4 per round
+    out = []
+    for i, case in enumerate(cases):
+        grp = ids[i * (launches + 1) + 1:(i + 1) * (launches + 1)]
+        mean = {k: sum(by[d].get(k, 0.0) for d in grp) / len(grp) for k in by[grp[0]]}
+        row = dict(case)
+        row.update({f"{k}_per_butterfly": v * 64 / per for k, v in sorted(mean.items()) if k.startswith("SQ_INSTS")})
+        ipb = mean.get("SQ_INSTS_VALU", 0.0) * 64 / per
+        if ipb > 0:
+            row["valu_bound_butterflies_per_s"] = VALU_WAVE_INSTR_PER_S * 64 / ipb
+            row["valu_issue_pct"] = 100 * case["butterflies_per_s"] / row["valu_bound_butterflies_per_s"]
+        out.append(row)
+    return out
+
+
+def word_size(ctx, rounds=WS_ROUNDS, launches=WS_LAUNCHES):
+    """Butterflies per second of each word form on primes of the chain (and a
+    30-bit prime), with the modulus bits they carry per second and per byte
+    moved (a word read and written once per pass)."""
+    primes = [int(p) for p in ctx.primes]
+    cases = [("u64", 0, max(primes)), ("u64", 0, max(p for p in primes if p.bit_length() <= 53)),
+             ("binary64", 1, max(p for p in primes if p.bit_length() <= 42)),
+             ("u32", 2, prime_below(30, 2 * ctx.N))]
+    out = []
+    for name, form, q in cases:
+        rate = ctx.butterfly_rate(form, q, rounds, launches)
+        bits = q.bit_length()
+        word = 4 if form == 2 else 8
+        out.append({"form": name, "q_bits": bits, "q": q, "butterflies_per_s": rate,
+                    "modulus_bits_per_s": rate * bits, "modulus_bits_per_word_byte": bits / word})
+        print(json.dumps(out[-1]), flush=True)
+    return out
+
+
 def main(argv=None):
     ap = argparse.ArgumentParser()
     ap.add_argument("--limbs", default=",".join(str(s) for s in SIZES))
@@ -140,7 +241,16 @@ def main(argv=None):
     ap.add_argument("--calls", type=int, default=0, help="only issue this many calls per size (for profilers)")
     ap.add_argument("--chain", default=None,
                     help="time the benchmarked chain under schedules 'name:r4,r8,s4;...' instead of scanning")
+    ap.add_argument("--word-size", action="store_true", help="butterfly rates of the word forms instead of scanning")
+    ap.add_argument("--word-size-counters", default=None,
+                    help="counter directory of a --word-size run: instructions per butterfly (reads --json)")
     a = ap.parse_args(argv)
+    if a.word_size_counters:
+        with open(a.json) as f:
+            cases = json.load(f)
+        for row in word_size_counters(a.word_size_counters, cases):
+            print(json.dumps(row), flush=True)
+        return
     import torch
     from . import ckks
     torch.cuda.set_device(0)
@@ -155,6 +265,13 @@ def main(argv=None):
                 json.dump(res, f, indent=1)
         return
     ctx = ckks.Context.from_set("p16b", bootstrapping=False)
+    if a.word_size:
+        res = word_size(ctx)
+        if a.json:
+            with open(a.json, "w") as f:
+                json.dump(res, f, indent=1)
+        ctx.close()
+        return
     if a.calls:
         issue(ctx, [int(s) for s in a.limbs.split(",")], ctx.np_, a.calls)
         ctx.close()

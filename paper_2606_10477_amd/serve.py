@@ -346,10 +346,10 @@ def make_lanes(n, keys_seed=9, params="p16b"):
 
 
 def main(argv=None):
-    """Serving sweep at N = 2^16 on the bootstrapping parameter set (relin,
+    """Serving sweep at N = 2^16 on a bootstrapping parameter set (relin,
     rotation and conjugation keys resident): Poisson arrivals at each rate,
-    request sizes Geometric(0.25) truncated to [1, 32], levels in [5, 8] and
-    MRE targets drawn per request; continuous batching on several lanes
+    request sizes Geometric(0.25) truncated to [1, 32], levels in [5, 8] (in
+    [5, 11] on the 11-level set) and MRE targets drawn per request; continuous batching on several lanes
     versus one request at a time (tuned settings), and versus the plain
     fixed configuration (31, 3) one ciphertext per call."""
     import argparse
@@ -363,30 +363,39 @@ def main(argv=None):
     ap = argparse.ArgumentParser()
     ap.add_argument("--rates", default="10,40,160")
     ap.add_argument("--requests", type=int, default=48)
-    ap.add_argument("--levels", default="5,6,7,8", help="input levels (those the tuning table can serve)")
-    ap.add_argument("--table", default=os.path.join(os.path.dirname(os.path.abspath(__file__)), "tuning_mi355x_bts.json"),
-                    help="tuning JSON from paper_2606_10477_amd.tune")
+    ap.add_argument("--params", choices=["p16b", "p16c"], default="p16b",
+                    help="bootstrapping set: p16b (8 computation levels, dnum 3) or p16c (11, dnum 6)")
+    ap.add_argument("--levels", default=None,
+                    help="input levels (those the tuning table can serve; default 5-8 on p16b, 5-11 on p16c)")
+    ap.add_argument("--table", default=None,
+                    help="tuning JSON from paper_2606_10477_amd.tune (default: the committed table of the set)")
     ap.add_argument("--max-batch", type=int, default=16,
                     help="ciphertexts per launch sequence (bootstrapping throughput saturates near 8-16)")
     ap.add_argument("--lanes", type=int, default=2, help="contexts on streams of their own")
     ap.add_argument("--out", default=None)
     args = ap.parse_args(argv)
+    here = os.path.dirname(os.path.abspath(__file__))
+    if args.table is None:
+        args.table = os.path.join(here, {"p16b": "tuning_mi355x_bts.json", "p16c": "tuning_mi355x_bts11.json"}[args.params])
+    if args.levels is None:
+        args.levels = {"p16b": "5,6,7,8", "p16c": "5,6,7,8,9,10,11"}[args.params]
     torch.cuda.set_device(0)
     table, key_note, rows = DEFAULT_TABLE, "no table: the fixed (31, 0, 3) for every request", None
     if args.table and os.path.exists(args.table):
         with open(args.table) as f:
             rep = json.load(f)
         table, rows = rep["table"], rep.get("rows")
-        problem = tuner.check_table_key(rep.get("key"), tuner.table_key("p16b"))
+        problem = tuner.check_table_key(rep.get("key"), tuner.table_key(args.params))
         if problem and problem[0] == "error":
             raise SystemExit(problem[1])
         key_note = problem[1] if problem else "table key matches this GPU, parameter set and library"
         if problem:
             print(key_note, file=sys.stderr, flush=True)
-    lanes = make_lanes(args.lanes)
+    lanes = make_lanes(args.lanes, params=args.params)
     ctx = lanes[0].ctx
     levels = [int(v) for v in args.levels.split(",")]
-    out = {"workload": "CryptoInvSqrt serving at N=2^16 with bootstrapping keys resident, Poisson arrivals, "
+    out = {"workload": f"CryptoInvSqrt serving at N=2^16 (set {args.params}) with bootstrapping keys resident, "
+                       "Poisson arrivals, "
                        f"sizes Geometric(0.25) in [1,32], levels {levels}, targets 1e-6/1e-7/3.1e-8",
            "table": args.table, "table_key": key_note, "lanes": args.lanes, "runs": []}
     for rate in [float(v) for v in args.rates.split(",")]:
