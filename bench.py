@@ -193,7 +193,24 @@ def tuned_11_levels(args, ckks, inputs):
             ctx.sync()
             lat.append(1e3 * (time.perf_counter() - t1))
             del o1
-        res = {"params": "p16c: " + ckks_params_about("p16c"), "input_level": top,
+        graph = None
+        if args.graph_runs > 0:
+            # the chain without a bootstrap is short (a few hundred launches): replayed as one HIP
+            # graph, against eager runs, with the replay's words checked against eager's
+            ref_words = step(1)[0].words()
+            gr = ctx.invsqrt_graph(cts[0], d, it, a=LO, b=HI, pre_bts=bool(c))
+            same = bool(np.array_equal(gr.run(cts[0]).words(), ref_words))
+            ctx.sync()
+            t1 = time.perf_counter()
+            for _ in range(args.graph_runs):
+                o1 = gr.run(cts[0])
+                del o1
+            ctx.sync()
+            tg = (time.perf_counter() - t1) / args.graph_runs
+            same = same and bool(np.array_equal(gr.run(cts[0]).words(), ref_words))
+            gr.close()
+            graph = {"runs": args.graph_runs, "replay_ms": round(tg * 1e3, 3), "replay_equals_eager": same}
+        res = {"params": "p16c: " + ckks_params_about("p16c"), "input_level": top, "graph": graph,
                "degree": d, "c": c, "iters": it, "bootstraps_per_ct": n_bts, "mre": mre,
                "ciphertexts_per_s": round(args.steps / dt, 3), "ms_per_step": round(dt * 1e3 / args.steps, 3),
                "latency": {"runs": len(lat), "p50_ms": round(float(np.percentile(lat, 50)), 3),

@@ -433,8 +433,9 @@ ckks_status ckks_ntt_arith(ckks_ctx *ctx, int32_t fp64_max_bits);
  *   form 1: binary64 residues, odd q < 2^42 (their binary64 path);
  *   form 2: 32-bit words, odd q < 2^30 (a 30-bit-prime design; no
  *           operation of this library uses it).
- * 2048 x 256 threads each apply `rounds` rounds (1..2^20) of an 8-point
- * transform held in registers (3 stages of 4 butterflies);
+ * 2048 x 256 threads each apply `rounds` rounds (1..4096: at most about 20 ms
+ * per launch) of an 8-point transform held in registers (3 stages of 4
+ * butterflies);
  * `launches` launches (1..1000) after one warm-up launch are timed with HIP
  * events on the context's stream.  *butterflies_per_s receives the rate.
  * Uses a 4 MiB buffer from the context's pool; synchronises the stream.

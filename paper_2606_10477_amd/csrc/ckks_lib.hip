@@ -2788,7 +2788,7 @@ ckks_status ckks_ntt_arith(ckks_ctx *c, int32_t fp64_max_bits) {
 
 ckks_status ckks_butterfly_rate(ckks_ctx *c, int32_t form, uint64_t q, uint32_t rounds, uint32_t launches,
                                 double *butterflies_per_s) {
-    if (!c || !butterflies_per_s || form < 0 || form > 2 || rounds < 1 || rounds > (1u << 20) || launches < 1 ||
+    if (!c || !butterflies_per_s || form < 0 || form > 2 || rounds < 1 || rounds > 4096 || launches < 1 ||
         launches > 1000 || !(q & 1) || q < 3)
         return CKKS_E_PARAM;
     const uint64_t qmax = form == 0 ? (1ull << 61) : form == 1 ? (1ull << 42) : (1ull << 30);
