@@ -308,3 +308,23 @@ def test_slot_to_coeff_is_the_packing(o8):
     want[br + n] = wi
     want *= 2.0 ** 5 / (2 * np.pi)
     assert np.max(np.abs(m - want)) < 1e-6
+
+
+@pytest.mark.parametrize("name,l_after,digit,K", [("p16b", 8, 8, 7), ("p16c", 11, 5, 5)])
+def test_full_size_bootstrapping_sets_budget(oracle_mod, name, l_after, digit, K):
+    """The N = 2^16 bootstrapping sets (§2.1: log2 QP ~ 1555 for 128-bit
+    security, l_afterBTS 11 to 12 in the paper's HEaaN set): prime sizes by
+    role, every prime = 1 mod 2N and distinct, the special modulus above every
+    digit of hybrid key switching, and the total modulus within 1540..1560 bits."""
+    o = oracle_mod.Context.from_set(name, bootstrapping=False)
+    ps = [int(p) for p in o.primes]
+    L = l_after + 15
+    assert o.l_after == l_after and o.L == L and len(ps) == L + 1 + K
+    bits = [p.bit_length() for p in ps]
+    assert bits[0] == 60 and all(40 <= b <= 41 for b in bits[1:l_after + 4])
+    assert all(52 <= b <= 53 for b in bits[l_after + 4:L + 1]) and all(b == 60 for b in bits[L + 1:])
+    assert len(set(ps)) == len(ps) and all(p % (2 * o.N) == 1 for p in ps)
+    logp = [np.log2(float(p)) for p in ps]
+    digits = [sum(logp[i:min(i + digit, L + 1)]) for i in range(0, L + 1, digit)]
+    assert o.dnum == len(digits) and max(digits) < sum(logp[L + 1:])
+    assert 1540 < sum(logp) < 1560
