@@ -12,7 +12,9 @@ CryptoInvSqrt (31, 3) ends at 3 (one Newton step at 2, bootstrap to 8, steps
 at 7 and 5).  On p16c (11 computation levels, the same bootstrap): y0 at 5,
 ModRaise to 26, CoeffToSlot to 23, EvalMod to 14, SlotToCoeff to 11;
 CryptoInvSqrt (31, 3) ends at 9 (Newton steps at 5 and 3 down to 1, bootstrap
-to 11, the last step at 11).
+to 11, the last step at 11).  The tuned step (63, 2): on p16c y0 at 4 and
+two Newton steps down to 0, no bootstrap; on p16b y0 at 1, bootstrap to 8,
+steps at 7 and 5, ending at 3.
 """
 import json
 import os
@@ -26,9 +28,9 @@ import make_fullsize_golden as M  # noqa: E402
 
 LEVELS = {
     "p16b": {"enc": 8, "cheb": 2, "raise": 23, "cts": 20, "conj": 20, "re": 20, "im": 20,
-             "evm_re": 11, "evm_im": 11, "stc": 8, "bts": 8, "invsqrt": 3},
+             "evm_re": 11, "evm_im": 11, "stc": 8, "bts": 8, "invsqrt": 3, "invsqrt_tuned": 3},
     "p16c": {"enc": 11, "cheb": 5, "raise": 26, "cts": 23, "conj": 23, "re": 23, "im": 23,
-             "evm_re": 14, "evm_im": 14, "stc": 11, "bts": 11, "invsqrt": 9},
+             "evm_re": 14, "evm_im": 14, "stc": 11, "bts": 11, "invsqrt": 9, "invsqrt_tuned": 0},
 }
 
 

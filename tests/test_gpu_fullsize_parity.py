@@ -4,9 +4,10 @@ levels "p16c"; paper §2.1 bootstrapping and Alg. 1), through the C-ABI,
 against digests the oracle wrote (tests/golden/fullsize_chain_<set>.json, by
 make_fullsize_golden.py, which calls only the oracle): after the
 encryption, the Chebyshev step, ModRaise, CoeffToSlot, the conjugation and
-the real/imaginary split, both EvalMods, SlotToCoeff, the whole bootstrap and
-the whole CryptoInvSqrt (31, 3) chain, the GPU's level, scale and SHA-256 of
-all words must equal the oracle's.  The GPU runs
+the real/imaginary split, both EvalMods, SlotToCoeff, the whole bootstrap,
+the whole CryptoInvSqrt (31, 3) chain and the tuned (63, 2) chain (no
+bootstrap from p16c's top level), the GPU's level, scale and SHA-256 of all
+words must equal the oracle's.  The GPU runs
 in the benchmark's launch configuration (one ciphertext, the library's
 default schedules).
 """
