@@ -22,6 +22,11 @@ Steps (paper §2.1 bootstrapping, Alg. 1):
   invsqrt  CryptoInvSqrt (31, 3) of enc: the benchmark's step
   invsqrt_tuned  CryptoInvSqrt (63, 2) of enc: the tuned pick for 3.1e-8 at
            the 11-level set's top level (no bootstrap there; one on p16b)
+  invsqrt_pre    CryptoInvSqrt (31, 3) of enc with Pre-BTS (the paper's c = 1:
+           x bootstrapped before the Chebyshev step)
+  invsqrt_paper  the paper's domain: x = linspace(0.001, 100, N/2) encrypted
+           as it is at the top level (scale 2^50, seed 5), pre-normalised by
+           B = 100 in the chain, CryptoInvSqrt (126, 3) on [0.001, 100]
 """
 import hashlib
 
@@ -32,8 +37,9 @@ KEY_SEED, INPUT_SEED, ENC_SEED = 9, 1, 3
 IN_SCALE = 2.0 ** 50
 DEGREE, ITERS, BTS_BOUND = 31, 3, 512
 TUNED_DEGREE, TUNED_ITERS = 63, 2
+PAPER_LO, PAPER_HI, PAPER_B, PAPER_DEGREE, PAPER_ITERS, PAPER_SEED = 0.001, 100.0, 100.0, 126, 3, 5
 STEPS = ("enc", "cheb", "raise", "cts", "conj", "re", "im", "evm_re", "evm_im", "stc", "bts", "invsqrt",
-         "invsqrt_tuned")
+         "invsqrt_tuned", "invsqrt_pre", "invsqrt_paper")
 N_SAMPLES = 48
 
 
@@ -49,10 +55,11 @@ def digest(ct):
             "samples": [[p, l, t, str(int(w[p, l, t]))] for p, l, t in pos]}
 
 
-def run(ctx, x, only=None, on_step=None):
+def run(ctx, x, only=None, on_step=None, x_paper=None):
     """Run the steps on `ctx` (keys already generated) and return
     {step: digest}.  `only` limits the run to a subset of STEPS (their
-    prerequisites are computed as needed)."""
+    prerequisites are computed as needed); x_paper is the paper-domain input
+    (invsqrt_paper is skipped without it)."""
     want = set(STEPS if only is None else only)
     out = {}
 
@@ -94,4 +101,9 @@ def run(ctx, x, only=None, on_step=None):
         rec("invsqrt", ctx.invsqrt(enc, DEGREE, ITERS, LO, HI))
     if "invsqrt_tuned" in want:
         rec("invsqrt_tuned", ctx.invsqrt(enc, TUNED_DEGREE, TUNED_ITERS, LO, HI))
+    if "invsqrt_pre" in want:
+        rec("invsqrt_pre", ctx.invsqrt(enc, DEGREE, ITERS, LO, HI, pre_bts=True))
+    if "invsqrt_paper" in want and x_paper is not None:
+        xp = ctx.encrypt(x_paper, ctx.l_after, IN_SCALE, PAPER_SEED)
+        rec("invsqrt_paper", ctx.invsqrt(xp, PAPER_DEGREE, PAPER_ITERS, PAPER_LO, PAPER_HI, B=PAPER_B))
     return out

@@ -47,7 +47,9 @@ def main(name="p16b"):
     o.keygen(F.KEY_SEED, o.bts_galois())
     x = inputs.log_uniform(o.n, F.LO, F.HI, F.INPUT_SEED)
     print(f"set-up {time.time() - t0:.0f} s", flush=True)
-    steps = F.run(o, x, on_step=lambda n, d: print(f"{n}: level {d['level']} ({time.time() - t0:.0f} s)", flush=True))
+    xp = inputs.linspace_input(o.n, F.PAPER_LO, F.PAPER_HI)
+    steps = F.run(o, x, x_paper=xp,
+                  on_step=lambda n, d: print(f"{n}: level {d['level']} ({time.time() - t0:.0f} s)", flush=True))
     rec = {"about": f"oracle digests of the benchmarked workload's steps at N = 2^16 on set {name} "
                     "(fullsize_chain.py); written by make_fullsize_golden.py",
            "sources_sha256": source_digest(name), "steps": steps}

@@ -14,7 +14,12 @@ ModRaise to 26, CoeffToSlot to 23, EvalMod to 14, SlotToCoeff to 11;
 CryptoInvSqrt (31, 3) ends at 9 (Newton steps at 5 and 3 down to 1, bootstrap
 to 11, the last step at 11).  The tuned step (63, 2): on p16c y0 at 4 and
 two Newton steps down to 0, no bootstrap; on p16b y0 at 1, bootstrap to 8,
-steps at 7 and 5, ending at 3.
+steps at 7 and 5, ending at 3.  With Pre-BTS x is bootstrapped to the top
+level first, and the levels are those of the plain (31, 3) chain (3 / 9).
+The paper's domain (126, 3) with B = 100: the affine map and degree 126 take
+8 levels, so on p16b y0 is at 0, bootstrapped to 8, steps at 7, 5 and 3 end
+at 1; on p16c y0 at 3, one step to 1, bootstrap to 11, steps at 10 and 8 end
+at 6.
 """
 import json
 import os
@@ -28,9 +33,11 @@ import make_fullsize_golden as M  # noqa: E402
 
 LEVELS = {
     "p16b": {"enc": 8, "cheb": 2, "raise": 23, "cts": 20, "conj": 20, "re": 20, "im": 20,
-             "evm_re": 11, "evm_im": 11, "stc": 8, "bts": 8, "invsqrt": 3, "invsqrt_tuned": 3},
+             "evm_re": 11, "evm_im": 11, "stc": 8, "bts": 8, "invsqrt": 3, "invsqrt_tuned": 3,
+             "invsqrt_pre": 3, "invsqrt_paper": 1},
     "p16c": {"enc": 11, "cheb": 5, "raise": 26, "cts": 23, "conj": 23, "re": 23, "im": 23,
-             "evm_re": 14, "evm_im": 14, "stc": 11, "bts": 11, "invsqrt": 9, "invsqrt_tuned": 0},
+             "evm_re": 14, "evm_im": 14, "stc": 11, "bts": 11, "invsqrt": 9, "invsqrt_tuned": 0,
+             "invsqrt_pre": 9, "invsqrt_paper": 6},
 }
 
 

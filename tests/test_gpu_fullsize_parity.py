@@ -5,9 +5,10 @@ against digests the oracle wrote (tests/golden/fullsize_chain_<set>.json, by
 make_fullsize_golden.py, which calls only the oracle): after the
 encryption, the Chebyshev step, ModRaise, CoeffToSlot, the conjugation and
 the real/imaginary split, both EvalMods, SlotToCoeff, the whole bootstrap,
-the whole CryptoInvSqrt (31, 3) chain and the tuned (63, 2) chain (no
-bootstrap from p16c's top level), the GPU's level, scale and SHA-256 of all
-words must equal the oracle's.  The GPU runs
+the whole CryptoInvSqrt (31, 3) chain, the tuned (63, 2) chain (no
+bootstrap from p16c's top level), the (31, 3) chain with Pre-BTS (c = 1) and
+the paper's domain (linspace(0.001, 100), B = 100, degree 126, 3 steps), the
+GPU's level, scale and SHA-256 of all words must equal the oracle's.  The GPU runs
 in the benchmark's launch configuration (one ciphertext, the library's
 default schedules).
 """
@@ -52,7 +53,7 @@ def test_fullsize_chain_words_equal_the_oracle(name):
             if not ok:
                 bad.append(step)
 
-        got = F.run(g, x, on_step=check)
+        got = F.run(g, x, on_step=check, x_paper=inputs.linspace_input(g.n, F.PAPER_LO, F.PAPER_HI))
         assert set(got) == set(want)
         assert not bad, f"steps whose words differ from the oracle's: {bad}"
     finally:
