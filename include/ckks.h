@@ -461,8 +461,10 @@ ckks_status ckks_profile_enable(ckks_ctx *ctx, int on);
  * Opt-in operation trace for the cost model (enabling clears it): one text
  * line "op level B" per primitive executed (op in hmult, rescale, rotate,
  * rotate_hoisted, mul_scalar, mul_plain, add, sub, add_const, drop, copy,
- * mod_raise, bootstrap), in execution order; a bootstrap is one line (its
- * internal operations are not listed).
+ * mod_raise, bootstrap, lincomb, lincomb_term), in execution order; a
+ * bootstrap is one line (its internal operations are not listed).  A fused
+ * linear combination (the Chebyshev baby-step sums) is one "lincomb" line for
+ * the launch and one "lincomb_term" line for each further term or sum.
  * ckks_trace_read copies at most cap-1 bytes plus a terminating zero and
  * returns the size needed (including the zero).
  */

@@ -1181,8 +1181,8 @@ Ct op_lincomb(ckks_ctx *c, const std::vector<const ckks_ct *> &xs, const std::ve
             if (t > 0 && !scales_match(scale, x->scale * sc[t])) fail(CKKS_E_SCALE, "scale mismatch");
             const double kd = std::rint(v[t] * sc[t]);
             if (!(std::fabs(kd) < 4.0e18)) fail(CKKS_E_RANGE, "constant out of range");
-            trace_op(c, "mul_scalar", level, B);
-            if (t > 0) trace_op(c, "add", level, B);
+            // one launch per chunk: its first term opens it, every further term adds one read
+            trace_op(c, t == t0 ? "lincomb" : "lincomb_term", level, B);
             const int n = ca.nterm++;
             ca.x[n] = x->buf.p;
             ca.member_stride[n] = (size_t)2 * (x->level + 1) * N;
@@ -1417,11 +1417,10 @@ bool baby_sums_together(ckks_ctx *c, PowerBasis &pb, const std::vector<std::vect
         }
     }
     ma.c.nterm = (int)terms.size();
+    // one launch: the first term of the first sum opens it; every further term adds one read
+    // (the terms are read once for all sums) and every further sum one write
     for (size_t t = 0; t < n; ++t)
-        for (size_t u = 0; u < terms.size(); ++u) {
-            trace_op(c, "mul_scalar", lmin, B);
-            if (u > 0) trace_op(c, "add", lmin, B);
-        }
+        for (size_t u = 0; u < terms.size(); ++u) trace_op(c, t == 0 && u == 0 ? "lincomb" : "lincomb_term", lmin, B);
     Ct acc = ct_new(c, lmin, scale, (int)n * B);
     gpu::lincomb_multi(c->T, acc->buf.p, ma, lmin + 1, B, map_q(0, lmin + 1), c->stream);
     std::shared_ptr<ckks_ct> rs(op_rescale(c, acc.get()).release());

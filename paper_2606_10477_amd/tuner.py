@@ -104,7 +104,8 @@ def mre(values, ref):
 # --------------------------------------------------------------------------
 # Cost model
 # --------------------------------------------------------------------------
-OPS = ("hmult", "rescale", "rotate", "mul_scalar", "add", "sub", "add_const", "drop", "copy", "bootstrap")
+OPS = ("hmult", "rescale", "rotate", "mul_scalar", "add", "sub", "add_const", "drop", "copy", "bootstrap",
+       "lincomb", "lincomb_term")
 BTS_ANY_LEVEL = -1     # a bootstrap costs the same from any input level (it starts at level 0)
 
 
@@ -174,6 +175,20 @@ def profile_unit_costs(ctx, levels, batch=1, reps=5, rot_step=None, bts_bound=No
                 ctx.sync()
                 ts.append((time.perf_counter() - t0) / PIPELINE)
             costs[(op, lvl)] = float(np.median(ts))
+    derive_lincomb_costs(costs)
+    return costs
+
+
+def derive_lincomb_costs(costs):
+    """A fused linear combination (one kernel) is traced as one "lincomb" line
+    for its launch and one "lincomb_term" line per further term or sum: the
+    launch costs what an integer multiply costs at that level and batch (one
+    read, one write), each further term what an addition adds to it (one more
+    read)."""
+    for (op, lvl), v in list(costs.items()):
+        if op == "mul_scalar" and ("add", lvl) in costs:
+            costs[("lincomb", lvl)] = v
+            costs[("lincomb_term", lvl)] = max(0.0, costs[("add", lvl)] - v)
     return costs
 
 

@@ -75,6 +75,19 @@ def test_predict_sums_unit_costs():
     assert missing == {("rotate", 3)}
 
 
+def test_predict_fused_linear_combination():
+    """A fused linear combination of T terms is one launch: it costs one
+    integer multiply plus (T - 1) times what an addition adds to it, not T
+    multiplies and T - 1 additions."""
+    costs = tuner.derive_lincomb_costs({("mul_scalar", 4): 8.0, ("add", 4): 9.0, ("mul_scalar", 5): 8.5})
+    assert costs[("lincomb", 4)] == 8.0 and costs[("lincomb_term", 4)] == 1.0
+    assert ("lincomb", 5) not in costs                  # no addition profiled at that level
+    trace = [("lincomb", 4, 1)] + [("lincomb_term", 4, 1)] * 7
+    assert tuner.predict(trace, costs)[0] == pytest.approx(8.0 + 7 * 1.0)
+    # an addition profiled faster than the multiply: further terms cost nothing, never less
+    assert tuner.derive_lincomb_costs({("mul_scalar", 2): 8.0, ("add", 2): 7.0})[("lincomb_term", 2)] == 0.0
+
+
 def test_predict_batched_products():
     """An op on m x the base batch costs the profiled m-fold batch
     (interpolated between the profiled multiples, extended past the last)."""
