@@ -1,7 +1,8 @@
 """Provision the degree-versus-iterations table on this GPU (paper §4.2, Alg. 2 and 3).
 
-Runs the encrypted inverse square root with the tuner's own keys on the
-bootstrapping parameter set over a grid of Chebyshev degrees x Newton
+Runs the encrypted inverse square root with the tuner's own keys on a
+parameter set (--params: the bootstrapping set with 8 computation levels, the
+one with 11, or the plain 27-level set) over a grid of Chebyshev degrees x Newton
 iterations x Pre-BTS indicator (the cases Alg. 3 allows per input level),
 measures the MRE against FP64 and the time of each setting, profiles the unit
 cost of every primitive at every level and of a bootstrap, predicts each
@@ -14,6 +15,7 @@ timing every setting against predicting it from unit costs, with the
 prediction's regret per pick).
 
     python -m paper_2606_10477_amd.tune --out tuning.json
+    python -m paper_2606_10477_amd.tune --params bts11 --levels 3,4,5,6,7,8,9,10,11 --out tuning11.json
 """
 import argparse
 import json
